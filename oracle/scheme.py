@@ -1,0 +1,191 @@
+"""Oracle: the orthogonality-preserving midpoint scheme (test infrastructure only).
+
+Notation (paper, Section 2.1): for blocks ``U = (u_1..u_N)``, ``V`` the inner
+matrix is ``<U, V>_ij = (u_i, v_j)``; with Euclidean inner products on grid
+vectors that is ``U^T V``.  The Euclidean product differs from the quadrature
+weighted ``int u v`` by the constant factor ``prod h_a``, which every N x N
+matrix of the scheme is invariant to once ``U^0`` is orthonormal in the same
+product.
+
+Functions and the passage each follows:
+
+* ``generator_apply`` / ``generator_matrix`` -- ``L_U V = U<GU, V> - GU<U, V>``
+  (eq. (3.2)); as an n x n matrix ``L_U = U Y^T - Y U^T`` with ``Y = GU``.
+* ``steps_1_to_4`` -- the scheme (4.1) solved by the paper's Steps 1-4
+  (Section 4.1), literally: Step 1 ``Y = GU``; Step 2
+  ``(I + tau^2/4 (<Y,Y> - <Y,U><Y,U>)) B = I``; Step 3
+  ``tau/2 A = I - B + tau/2 <Y,U> B``; Step 4 ``U' = U - tau U A + tau Y B``.
+* ``step_cayley_dense`` -- the same step straight from (4.1):
+  ``(I + tau/2 L_U) U' = (I - tau/2 L_U) U`` as an n x n dense solve.  Needs no
+  symmetry of ``<Y, U>``, so it is the definition for an inexact Y.
+* ``step_general`` -- Steps 2-4 re-derived from (4.1) exactly as the paper does
+  but without using ``<Y,U> = <U,Y>`` (which only holds for exact ``Y = GU``):
+  ``M = I + tau/2 (S_a - S_b) + tau^2/4 (T - S_a S_b)``, ``B = M^{-1}``,
+  ``A = 2/tau (I - B) + S_b B`` with ``S_a = Y^T U``, ``S_b = U^T Y``,
+  ``T = Y^T Y``.  Identical to ``steps_1_to_4`` when ``S_a = S_b``.
+* ``step_woodbury`` -- (4.1) written with ``L_U = W J W^T``, ``W = [U, Y]``,
+  and inverted through the 2N x 2N capacitance matrix (push-through identity).
+* ``energy``, ``residual``, ``ritz_values``, ``paper_eigenvalues``,
+  ``ortho_error`` -- ``E(U) = 1/2 tr <U,U>_a`` (eq. (2.3)), the eigen-residual,
+  Ritz values, the paper's ``eig(<GU,U>^{-1})`` (Section 5 error measure) and
+  ``|<U,U> - I|_F`` (Theorem 4.1).
+* ``run_algorithm1`` -- Algorithm 1 with a fixed step and either the paper's
+  relative-energy-change stop or an eigen-residual stop.
+
+Parity: all functions are pinned (tests/test_oracle_scheme.py): the three step
+forms agree with each other, orthogonality is preserved (Theorem 4.1), energy
+decreases (Theorem 4.2), eigenbases are fixed points (Remark after (3.1)),
+``L_U`` is skew (Lemma 3.2), the Step-2 matrix is >= I (Lemma 3.1), and the
+iteration converges to dense ``eigh`` / closed-form eigenvalues.
+"""
+from __future__ import annotations
+
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from .operator import Operator, apply_H
+
+
+def inner(U: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """Inner matrix ``<U, V>_ij = (u_i, v_j)`` (Section 2.1), Euclidean."""
+    return U.T @ V
+
+
+def generator_apply(U: np.ndarray, Y: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """``L_U V = U <Y, V> - Y <U, V>`` with ``Y = GU`` (eq. (3.2))."""
+    return U @ inner(Y, V) - Y @ inner(U, V)
+
+
+def generator_matrix(U: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """``L_U`` as an explicit n x n matrix acting on columns: ``U Y^T - Y U^T``."""
+    return U @ Y.T - Y @ U.T
+
+
+def small_solve(S_a: np.ndarray, T: np.ndarray, tau: float, S_b: Optional[np.ndarray] = None):
+    """Steps 2 and 3 of Section 4.1.
+
+    With ``S_b`` omitted this is the paper's form (``S = <GU, U>`` symmetric):
+    ``B = (I + tau^2/4 (T - S S))^{-1}``, ``A = 2/tau (I - B + tau/2 S B)``.
+    With ``S_b = <U, Y>`` given it is the same elimination without assuming
+    ``S_a = S_b`` (see ``step_general``).  Returns ``(A, B, M)``."""
+    N = S_a.shape[0]
+    I = np.eye(N)
+    if S_b is None:
+        M = I + 0.25 * tau * tau * (T - S_a @ S_a)
+        B = np.linalg.solve(M, I)
+        A = (2.0 / tau) * (I - B + 0.5 * tau * S_a @ B)
+    else:
+        M = I + 0.5 * tau * (S_a - S_b) + 0.25 * tau * tau * (T - S_a @ S_b)
+        B = np.linalg.solve(M, I)
+        A = (2.0 / tau) * (I - B) + S_b @ B
+    return A, B, M
+
+
+def steps_1_to_4(U: np.ndarray, G: Callable[[np.ndarray], np.ndarray], tau: float) -> Dict[str, np.ndarray]:
+    """One step of scheme (4.1) by the paper's Steps 1-4 (Section 4.1)."""
+    Y = G(U)                                   # Step 1: N source problems
+    S = inner(Y, U)                            # <GU, U>
+    T = inner(Y, Y)                            # <GU, GU>
+    A, B, M = small_solve(S, T, tau)           # Steps 2, 3
+    U_next = U - tau * U @ A + tau * Y @ B     # Step 4
+    return {"U": U_next, "Y": Y, "A": A, "B": B, "S": S, "T": T, "M": M}
+
+
+def step_general(U: np.ndarray, Y: np.ndarray, tau: float) -> Dict[str, np.ndarray]:
+    """Steps 2-4 for a given block Y (not necessarily exactly GU), eliminated
+    from (4.1) without assuming ``<Y,U> = <U,Y>``."""
+    S_a = inner(Y, U)
+    S_b = inner(U, Y)
+    T = inner(Y, Y)
+    A, B, M = small_solve(S_a, T, tau, S_b=S_b)
+    U_next = U - tau * U @ A + tau * Y @ B
+    return {"U": U_next, "A": A, "B": B, "S_a": S_a, "S_b": S_b, "T": T, "M": M}
+
+
+def step_cayley_dense(U: np.ndarray, Y: np.ndarray, tau: float) -> np.ndarray:
+    """(4.1) as written: ``(U' - U)/tau = -L_U (U' + U)/2`` solved densely for U'."""
+    n = U.shape[0]
+    L = generator_matrix(U, Y)
+    I = np.eye(n)
+    return np.linalg.solve(I + 0.5 * tau * L, (I - 0.5 * tau * L) @ U)
+
+
+def step_woodbury(U: np.ndarray, Y: np.ndarray, tau: float) -> np.ndarray:
+    """(4.1) with ``L_U = W J W^T`` (``W = [U, Y]``, ``J = [[0, I], [-I, 0]]``):
+    ``U' = U - tau W (I_2N + tau/2 J W^T W)^{-1} J W^T U``."""
+    N = U.shape[1]
+    W = np.hstack([U, Y])
+    J = np.zeros((2 * N, 2 * N))
+    J[:N, N:] = np.eye(N)
+    J[N:, :N] = -np.eye(N)
+    cap = np.eye(2 * N) + 0.5 * tau * J @ (W.T @ W)
+    X = np.linalg.solve(cap, J @ (W.T @ U))
+    return U - tau * W @ X
+
+
+def energy(op: Operator, U: np.ndarray) -> float:
+    """``E(U) = 1/2 tr <U, U>_a = 1/2 tr(U^T H U)`` (eq. (2.3))."""
+    return 0.5 * float(np.sum(U * apply_H(op, U)))
+
+
+def ritz_values(op: Operator, U: np.ndarray) -> np.ndarray:
+    """Eigenvalues of ``U^T H U`` (ascending)."""
+    Lam = U.T @ apply_H(op, U)
+    return np.linalg.eigvalsh(0.5 * (Lam + Lam.T))
+
+
+def paper_eigenvalues(U: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Eigenvalues of ``<GU, U>^{-1}`` with ``Y = GU`` (Section 5 error measure), ascending."""
+    S = inner(Y, U)
+    w = np.linalg.eigvals(np.linalg.inv(S))
+    return np.sort(w.real)
+
+
+def residual(op: Operator, U: np.ndarray) -> float:
+    """``|H U - U Lam|_F / |Lam|_F`` with ``Lam = U^T H U``."""
+    HU = apply_H(op, U)
+    Lam = U.T @ HU
+    return float(np.linalg.norm(HU - U @ Lam) / np.linalg.norm(Lam))
+
+
+def ortho_error(U: np.ndarray) -> float:
+    """``|<U, U> - I|_F`` (the quantity Theorem 4.1 keeps at zero)."""
+    return float(np.linalg.norm(U.T @ U - np.eye(U.shape[1])))
+
+
+def subspace_distance(U: np.ndarray, V: np.ndarray) -> float:
+    """Sine of the largest principal angle between span(U) and span(V)."""
+    return float(np.sin(np.max(sla.subspace_angles(U, V))))
+
+
+def run_algorithm1(op: Operator, U0: np.ndarray, tau: float, G: Callable[[np.ndarray], np.ndarray],
+                   max_steps: int, res_tol: Optional[float] = None, energy_tol: Optional[float] = None,
+                   record: bool = True) -> Dict[str, object]:
+    """Algorithm 1 with a fixed step ``tau``.
+
+    Stops after ``max_steps`` steps, or when the eigen-residual drops to
+    ``res_tol``, or when the relative energy change
+    ``|E(U^{n+1}) - E(U^n)| / |E(U^n)|`` drops to ``energy_tol`` (the rule of
+    Algorithm 1).  Step 1 is ``G``."""
+    U = np.array(U0, dtype=np.float64)
+    E = energy(op, U)
+    hist: Dict[str, List[float]] = {"E": [E], "res": [residual(op, U)], "ortho": [ortho_error(U)]}
+    steps = 0
+    while steps < max_steps:
+        if res_tol is not None and hist["res"][-1] <= res_tol:
+            break
+        out = steps_1_to_4(U, G, tau)
+        U = out["U"]
+        E_new = energy(op, U)
+        errE = abs(E_new - E) / abs(E)
+        E = E_new
+        steps += 1
+        if record or res_tol is not None:
+            hist["E"].append(E)
+            hist["res"].append(residual(op, U))
+            hist["ortho"].append(ortho_error(U))
+        if energy_tol is not None and errE <= energy_tol:
+            break
+    return {"U": U, "steps": steps, "hist": hist}

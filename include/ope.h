@@ -1,0 +1,162 @@
+/*
+ * ope.h -- C ABI of the MI355X (gfx950) orthogonality-preserving eigensolver step.
+ *
+ * The library computes the N lowest eigenpairs of the finite-difference
+ * operator  H = c * (-Lap_h) + diag(V + sigma)  (homogeneous Dirichlet
+ * boundary, 5-point stencil in 2D, 7-point in 3D) with the midpoint scheme of
+ * the paper's Section 4.1, eq. (4.1):
+ *
+ *     (U' - U) / tau = -L_U (U' + U) / 2,   L_U V = U <GU, V> - GU <U, V>,
+ *     G = H^{-1},
+ *
+ * solved per step by Steps 1-4 of Section 4.1: Step 1 applies G to the N
+ * columns (warm-started conjugate gradients on the device), Steps 2-3 solve a
+ * small N x N system in FP64 (the Schur complement of the 2N x 2N capacitance
+ * system), Step 4 updates U in place.  Algorithm 1 drives the loop.
+ *
+ * Conventions shared by every entry point:
+ *  - Grid points are numbered x fastest: p = i0 + m0 * (i1 + m1 * i2).
+ *  - An orbital block is n x N, row-major ("point-major"): element (p, j) at
+ *    offset p * N + j, where n = prod(m).  Block pointers are DEVICE pointers
+ *    owned by the caller, 16-byte aligned, and must not overlap unless an
+ *    entry point says so.
+ *  - Inner matrices <X, Y> = X^T Y are N x N row-major; pointers to them are
+ *    device pointers unless the argument says "host".
+ *  - Every entry point returns an ope_status; on error no caller buffer
+ *    named as an output has been written unless stated otherwise.  Work is
+ *    enqueued on the stream given to ope_create (NULL = default stream);
+ *    entry points that return host values synchronise that stream.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef OPE_H
+#define OPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OPE_OK = 0,
+  OPE_EINVAL = 1,      /* invalid argument (sizes, null pointers, dim, N > n ...) */
+  OPE_ENOMEM = 2,      /* device or pinned-host allocation failed */
+  OPE_EHIP = 3,        /* a HIP runtime call failed */
+  OPE_ENONFINITE = 4,  /* a NaN or Inf appeared in a reduction; U left unchanged */
+  OPE_ECG_MAXIT = 5,   /* Step 1 hit its iteration cap before the tolerance (step still applied) */
+  OPE_EPIVOT = 6,      /* non-positive or tiny pivot in a small FP64 solve; U left unchanged */
+  OPE_EUNSUPPORTED = 7 /* valid request this build does not implement */
+} ope_status;
+
+typedef enum { OPE_FP64 = 0 } ope_precision;
+
+/* The discrete operator (paper, Section 2.2 bilinear form a(u,v), discretised
+ * by second-order finite differences on the interior nodes of a uniform grid). */
+typedef struct {
+  int32_t dim;        /* 2 or 3 */
+  int64_t m[3];       /* interior nodes per axis, x first (m[2] ignored for dim 2); each >= 1 */
+  double h[3];        /* grid spacing per axis (> 0) */
+  double kinetic;     /* c > 0: 1.0 for -Lap, 0.5 for -1/2 Lap */
+  double shift;       /* sigma added to the diagonal */
+  const double* V;    /* HOST pointer to n potential values, x fastest; copied at create */
+} ope_op_desc;
+
+typedef struct {
+  double energy;      /* E(U) = 1/2 tr(U^T H U) of the iterate entering the step (eq. (2.3)) */
+  double residual;    /* |H U - U Lam|_F / |Lam|_F of that iterate, Lam = U^T H U */
+  double drift;       /* |U^T U - I|_F of that iterate (Theorem 4.1 keeps it ~ 0) */
+  int32_t inner_iterations; /* CG iterations spent in Step 1 */
+  int32_t status;     /* ope_status of the step */
+} ope_step_info;
+
+typedef struct {
+  int32_t steps;      /* steps taken */
+  int32_t converged;  /* 1 if the residual reached res_tol */
+  double residual;    /* final residual (same definition as ope_step_info) */
+  double energy;      /* final energy */
+  double drift;       /* final |U^T U - I|_F */
+  int64_t inner_iterations; /* total CG iterations */
+} ope_solve_info;
+
+typedef struct ope_ctx ope_ctx;
+
+/* Create a context for one operator and block width N (1 <= N <= 512,
+ * N <= n).  Copies V to the device, allocates the workspace (about six n x N
+ * FP64 blocks plus O(N^2) matrices), and binds `stream` (a hipStream_t, or
+ * NULL).  precision must be OPE_FP64.  On error *ctx is set to NULL. */
+ope_status ope_create(ope_ctx** ctx, const ope_op_desc* op, int64_t N, int32_t precision, void* stream);
+
+/* Release the context and its device memory (synchronises its stream).  NULL is a no-op. */
+ope_status ope_destroy(ope_ctx* ctx);
+
+/* Static text for a status code. */
+const char* ope_status_string(ope_status s);
+
+/* Inner-solve policy for Step 1 (the paper does not fix one).  Column j of
+ * H Y = U is solved by conjugate gradients warm-started at U Lam^{-1} until
+ * |u_j - H y_j| <= eta |u_j|, with eta = max(eta_floor, eta_rel * res) and
+ * res the outer residual of the current iterate; at most max_iter iterations.
+ * Defaults: eta_rel = 1e-2, eta_floor = 1e-12, max_iter = 2000. */
+ope_status ope_set_inner(ope_ctx* ctx, double eta_rel, double eta_floor, int32_t max_iter);
+
+/* --- Hot-path building blocks (each is one row of the step) -------------- */
+
+/* Y = H X for n x N device blocks X, Y (Step 1 operator; a(u,v) of Section
+ * 2.2).  X and Y must not overlap. */
+ope_status ope_apply_h(ope_ctx* ctx, const double* X, double* Y);
+
+/* Step 1: Y ~= G U = H^{-1} U column by column by conjugate gradients.  Y0 is
+ * an optional device n x N warm start (NULL = zero); Y may equal Y0.  Stops
+ * column j when |u_j - H y_j| <= tol |u_j| (recursively updated residual) or
+ * after max_iter iterations (then returns OPE_ECG_MAXIT with Y written).
+ * *iterations (host, nullable) receives the iteration count. */
+ope_status ope_source_solve(ope_ctx* ctx, const double* U, double* Y, const double* Y0,
+                            double tol, int32_t max_iter, int32_t* iterations);
+
+/* Inner matrix out = A^T B (na x nb, row-major, device) over `rows` grid
+ * rows, for row-major device blocks A (leading dimension lda >= na) and B
+ * (ldb >= nb): the products <U,U>, <U,HU>, <U,GU>, <GU,GU> of Steps 2-3.
+ * FP64 on the matrix cores; deterministic summation order. 1 <= na, nb <= 512. */
+ope_status ope_gram(ope_ctx* ctx, const double* A, int64_t lda, int64_t na,
+                    const double* B, int64_t ldb, int64_t nb, int64_t rows, double* out);
+
+/* Steps 2-3 (Section 4.1) for the context's N, in FP64, on the device:
+ * given S_b = <U, Y> and T = <Y, Y> (N x N device), forms
+ *   M = I + tau/2 (S_a - S_b) + tau^2/4 (T - S_a S_b),  S_a = S_b^T,
+ * B = M^{-1}, A = 2/tau (I - B) + S_b B, and Z = [I - tau A ; tau B]
+ * (2N x N), so that Step 4 is U' = [U, Y] Z.  M reduces to the paper's
+ * Step-2 matrix when S is symmetric.  Outputs Z, A, B are device pointers
+ * (A, B nullable).  OPE_EPIVOT if elimination meets a pivot <= 1e-300. */
+ope_status ope_small_solve(ope_ctx* ctx, const double* S_b, const double* T, double tau,
+                           double* Z, double* A, double* B);
+
+/* Step 4: U <- U Z_1 + Y Z_2 in place, Z = [Z_1; Z_2] (2N x N device, as
+ * produced by ope_small_solve).  U and Y are n x N device blocks. */
+ope_status ope_update(ope_ctx* ctx, double* U, const double* Y, const double* Z);
+
+/* E(U) = 1/2 tr(U^T H U) (eq. (2.3)) into *energy (host).  Synchronises. */
+ope_status ope_energy(ope_ctx* ctx, const double* U, double* energy);
+
+/* FP64 checks of an iterate (host outputs, each nullable):
+ *   *residual = |H U - U Lam|_F / |Lam|_F with Lam = U^T H U,
+ *   ritz[0..N) = eigenvalues of Lam, ascending (device Jacobi, FP64),
+ *   *drift = |U^T U - I|_F.  Synchronises. */
+ope_status ope_residual(ope_ctx* ctx, const double* U, double* residual, double* ritz, double* drift);
+
+/* One step of scheme (4.1) in place on the device block U (n x N, FP64):
+ * Steps 1-4 with the inner policy of ope_set_inner.  If info is non-NULL it
+ * receives the diagnostics of the iterate entering the step (host struct).
+ * On OPE_ENONFINITE or OPE_EPIVOT, U is left unchanged. */
+ope_status ope_step(ope_ctx* ctx, void* U, double tau, ope_step_info* info);
+
+/* Algorithm 1 at fixed step tau: repeat ope_step until the residual of the
+ * current iterate is <= res_tol or max_steps steps were taken.  info nullable. */
+ope_status ope_solve(ope_ctx* ctx, void* U, double tau, double res_tol, int32_t max_steps,
+                     ope_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPE_H */

@@ -1,0 +1,438 @@
+// C ABI of the eigensolver step: context, workspace and the Algorithm 1 driver.
+//
+// One step of scheme (4.1) (Section 4.1, Steps 1-4) is enqueued as
+//   HU = H U                                   (stencil)
+//   C = <U,U>, Lam = <U,HU>                    (FP64 MFMA Grams)
+//   E, drift, |Lam|_F, Lam^{-1}                (one work-group, FP64)
+//   R = HU - U Lam (+ column norms)            -> outer residual, inner tolerance
+//   Y = U Lam^{-1}, r = -R Lam^{-1}            (warm start of Step 1: r = U - H Y)
+//   CG on H Y = U, column by column            (Step 1; two sweeps per iteration)
+//   S_b = <U,Y>, T = <Y,Y>                     (Grams)
+//   M, B, A, Z                                 (Steps 2-3, one work-group, FP64)
+//   U <- U Z_1 + Y Z_2 in place                (Step 4, predicated on the error flag)
+// The host only synchronises to poll CG convergence every few iterations and
+// to read the step's scalars at the end.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "ope_internal.h"
+
+#define HIPCHK(x)                               \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return OPE_EHIP;      \
+  } while (0)
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  return hipMalloc((void**)p, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+}
+
+void free_ctx(ope_ctx* c) {
+  if (!c) return;
+  void* dptrs[] = {c->diag, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T, c->Z,
+                   c->A, c->B, c->Wsm, c->alpha, c->beta, c->rho, c->target, c->cnorm2, c->rcol, c->rho0,
+                   c->active, c->part, c->stage, c->counters, c->sc};
+  for (void* p : dptrs)
+    if (p) (void)hipFree(p);
+  if (c->hsc) (void)hipHostFree(c->hsc);
+  if (c->hactive) (void)hipHostFree(c->hactive);
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  delete c;
+}
+
+ope_status sync_and_read_scalars(ope_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return OPE_OK;
+}
+
+// HU, Grams C and Lam, the small prep kernel (energy, drift, Lam^{-1}) and the
+// residual R = HU - U Lam written over HU with its column norms in c->rcol.
+ope_status phase_residual(ope_ctx* c, const double* U) {
+  const int N = (int)c->N;
+  int64_t np = 0;
+  HIPCHK(launch_apply_h(c, U, c->HU));
+  HIPCHK(launch_gram(c, U, N, N, U, N, N, c->n, c->C));
+  HIPCHK(launch_gram(c, U, N, N, c->HU, N, N, c->n, c->Lam));
+  HIPCHK(launch_prep_small(c));
+  HIPCHK(launch_rowmm(c, U, c->Lam, nullptr, nullptr, c->HU, 1.0, -1.0, c->HU, 1, 0, &np));
+  HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rcol, RED_PLAIN));
+  return OPE_OK;
+}
+
+// CG iterations on H Y = U from the state prepared in rho/target/active, with
+// r in c->Rb[0]; returns the iteration count in *iters.
+ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
+  double* r_cur = c->Rb[0];
+  double* r_nxt = c->Rb[1];
+  double* p_old = c->HU;     // never read on the first iteration
+  double* p_new = c->Pb;
+  const int N = (int)c->N;
+  int it = 0;
+  bool done = false;
+  while (it < max_iter) {
+    const int first = (it == 0);
+    HIPCHK(launch_cg_pap(c, r_cur, p_old, first));
+    HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, N, nullptr, RED_CG_ALPHA));
+    HIPCHK(launch_cg_update(c, r_cur, p_old, r_nxt, p_new, c->Y, first));
+    HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, N, nullptr, RED_CG_BETA));
+    double* t = r_cur;
+    r_cur = r_nxt;
+    r_nxt = t;
+    t = p_old;
+    p_old = p_new;
+    p_new = t;
+    ++it;
+    if (it % c->check_every == 0 || it == max_iter) {
+      HIPCHK(hipMemcpyAsync(c->hactive, c->active, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      int cnt = 0;
+      for (int j = 0; j < N; ++j) cnt += c->hactive[j] != 0;
+      if (cnt == 0) {
+        done = true;
+        break;
+      }
+    }
+  }
+  *iters = it;
+  *all_done = done;
+  return OPE_OK;
+}
+
+// One step (or, with res_tol >= 0, the convergence test of Algorithm 1 and a
+// step if the residual is still above res_tol).
+ope_status run_step(ope_ctx* c, double* U, double tau, ope_step_info* info, double res_tol, bool* converged) {
+  const int N = (int)c->N;
+  int64_t np = 0;
+  if (converged) *converged = false;
+  ope_status st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  // warm start: Y = U Lam^{-1}, r = -R Lam^{-1} = U - H Y
+  HIPCHK(launch_rowmm(c, U, c->Linv, nullptr, nullptr, nullptr, 0.0, 1.0, c->Y, 0, 0, &np));
+  HIPCHK(launch_rowmm(c, c->HU, c->Linv, nullptr, nullptr, nullptr, 0.0, -1.0, c->Rb[0], 1, 0, &np));
+  HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rho0, RED_PLAIN));
+  HIPCHK(launch_cg_setup(c, c->rho0));
+  if (res_tol >= 0.0) {
+    st = sync_and_read_scalars(c);
+    if (st != OPE_OK) return st;
+    if (c->hsc->err != 0) return (ope_status)c->hsc->err;
+    if (c->hsc->residual <= res_tol) {
+      if (converged) *converged = true;
+      if (info) {
+        info->energy = c->hsc->energy;
+        info->residual = c->hsc->residual;
+        info->drift = c->hsc->drift;
+        info->inner_iterations = 0;
+        info->status = OPE_OK;
+      }
+      return OPE_OK;
+    }
+  }
+  int32_t iters = 0;
+  bool cg_done = false;
+  st = run_cg(c, c->max_iter, &iters, &cg_done);
+  if (st != OPE_OK) return st;
+  HIPCHK(launch_gram(c, U, N, N, c->Y, N, N, c->n, c->Sb));
+  HIPCHK(launch_gram(c, c->Y, N, N, c->Y, N, N, c->n, c->T));
+  HIPCHK(launch_small_solve(c, c->Sb, c->T, tau, c->Z, c->A, c->B));
+  HIPCHK(launch_rowmm(c, U, c->Z, c->Y, c->Z + (size_t)N * N, nullptr, 0.0, 1.0, U, 0, 1, &np));
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  ope_status out = (ope_status)c->hsc->err;
+  if (out == OPE_OK && !cg_done) out = OPE_ECG_MAXIT;
+  if (info) {
+    info->energy = c->hsc->energy;
+    info->residual = c->hsc->residual;
+    info->drift = c->hsc->drift;
+    info->inner_iterations = c->hsc->cg_iters;
+    info->status = out;
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ope_status_string(ope_status s) {
+  switch (s) {
+    case OPE_OK: return "ok";
+    case OPE_EINVAL: return "invalid argument";
+    case OPE_ENOMEM: return "out of memory";
+    case OPE_EHIP: return "HIP runtime error";
+    case OPE_ENONFINITE: return "non-finite value in a reduction";
+    case OPE_ECG_MAXIT: return "inner CG reached its iteration cap";
+    case OPE_EPIVOT: return "non-positive pivot in a small FP64 solve";
+    case OPE_EUNSUPPORTED: return "not supported by this build";
+  }
+  return "unknown status";
+}
+
+ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t precision, void* stream) {
+  if (!out) return OPE_EINVAL;
+  *out = nullptr;
+  if (!op || !op->V) return OPE_EINVAL;
+  if (op->dim != 2 && op->dim != 3) return OPE_EINVAL;
+  if (precision != OPE_FP64) return OPE_EUNSUPPORTED;
+  int64_t n = 1;
+  for (int a = 0; a < op->dim; ++a) {
+    if (op->m[a] < 1 || !(op->h[a] > 0.0)) return OPE_EINVAL;
+    n *= op->m[a];
+    if (n > (int64_t)1 << 31) return OPE_EINVAL;
+  }
+  if (!(op->kinetic > 0.0)) return OPE_EINVAL;
+  if (N < 1 || N > n) return OPE_EINVAL;
+  if (N > OPE_MAX_N_SMALL) return OPE_EUNSUPPORTED;
+
+  ope_ctx* c = new (std::nothrow) ope_ctx;
+  if (!c) return OPE_ENOMEM;
+  memset(c, 0, sizeof(*c));
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return OPE_EHIP;
+  }
+  c->n = n;
+  c->N = N;
+  c->vw = (N % 2 == 0) ? 2 : 1;
+  OpeGrid& g = c->g;
+  g.dim = op->dim;
+  g.m0 = (uint32_t)op->m[0];
+  g.m1 = (uint32_t)op->m[1];
+  g.m2 = op->dim == 3 ? (uint32_t)op->m[2] : 1u;
+  g.s1 = g.m0;
+  g.s2 = g.m0 * g.m1;
+  g.cx = op->kinetic / (op->h[0] * op->h[0]);
+  g.cy = op->kinetic / (op->h[1] * op->h[1]);
+  g.cz = op->dim == 3 ? op->kinetic / (op->h[2] * op->h[2]) : 0.0;
+  c->eta_rel = 1e-2;
+  c->eta_floor = 1e-12;
+  c->max_iter = 2000;
+  c->check_every = 4;
+
+  // streaming launch shape: about 2048 work-groups, whole passes of points
+  const int64_t NV = N / c->vw;
+  const int64_t pp = OPE_WG / NV;
+  int64_t pts = (n + 2047) / 2048;
+  pts = ((pts + pp - 1) / pp) * pp;
+  if (pts < pp) pts = pp;
+  c->stream_pts = (int)pts;
+  c->stream_wgs = (int)((n + pts - 1) / pts);
+
+  const int64_t blk = n * N;
+  const int64_t gram_parts = 1024 * N * N;
+  const int64_t row_parts = ((n + 63) / 64) * N;
+  int64_t pc = (int64_t)c->stream_wgs * 2 * N;
+  if (gram_parts > pc) pc = gram_parts;
+  if (row_parts > pc) pc = row_parts;
+  c->part_cap = pc;
+  c->stage_cap = 64 * (N * N > 2 * N ? N * N : 2 * N);
+
+  std::vector<double> hd((size_t)n);
+  const double dsum = 2.0 * (g.cx + g.cy + g.cz);
+  for (int64_t p = 0; p < n; ++p) hd[(size_t)p] = op->V[p] + op->shift + dsum;
+
+  bool ok = true;
+  ok &= dalloc(&c->diag, n) == hipSuccess;
+  ok &= dalloc(&c->HU, blk) == hipSuccess;
+  ok &= dalloc(&c->Y, blk) == hipSuccess;
+  ok &= dalloc(&c->Rb[0], blk) == hipSuccess;
+  ok &= dalloc(&c->Rb[1], blk) == hipSuccess;
+  ok &= dalloc(&c->Pb, blk) == hipSuccess;
+  ok &= dalloc(&c->C, N * N) == hipSuccess;
+  ok &= dalloc(&c->Lam, N * N) == hipSuccess;
+  ok &= dalloc(&c->Linv, N * N) == hipSuccess;
+  ok &= dalloc(&c->Sb, N * N) == hipSuccess;
+  ok &= dalloc(&c->T, N * N) == hipSuccess;
+  ok &= dalloc(&c->Z, 2 * N * N) == hipSuccess;
+  ok &= dalloc(&c->A, N * N) == hipSuccess;
+  ok &= dalloc(&c->B, N * N) == hipSuccess;
+  ok &= dalloc(&c->Wsm, N * N) == hipSuccess;
+  ok &= dalloc(&c->alpha, N) == hipSuccess;
+  ok &= dalloc(&c->beta, N) == hipSuccess;
+  ok &= dalloc(&c->rho, N) == hipSuccess;
+  ok &= dalloc(&c->target, N) == hipSuccess;
+  ok &= dalloc(&c->cnorm2, 2 * N) == hipSuccess;
+  ok &= dalloc(&c->rcol, 2 * N) == hipSuccess;
+  ok &= dalloc(&c->rho0, 2 * N) == hipSuccess;
+  ok &= dalloc(&c->active, N) == hipSuccess;
+  ok &= dalloc(&c->part, c->part_cap) == hipSuccess;
+  ok &= dalloc(&c->stage, c->stage_cap) == hipSuccess;
+  ok &= dalloc(&c->counters, 4096) == hipSuccess;
+  ok &= dalloc(&c->sc, 1) == hipSuccess;
+  ok &= hipHostMalloc((void**)&c->hsc, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * N, hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&c->hbuf, sizeof(double) * 2 * N, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    free_ctx(c);
+    return OPE_ENOMEM;
+  }
+  bool hok = true;
+  hok &= hipMemcpy(c->diag, hd.data(), sizeof(double) * n, hipMemcpyHostToDevice) == hipSuccess;
+  hok &= hipMemset(c->counters, 0, sizeof(uint32_t) * 4096) == hipSuccess;
+  hok &= hipMemset(c->sc, 0, sizeof(OpeScalars)) == hipSuccess;
+  hok &= hipMemset(c->active, 0, sizeof(int32_t) * N) == hipSuccess;
+  hok &= hipDeviceSynchronize() == hipSuccess;
+  if (!hok) {
+    free_ctx(c);
+    return OPE_EHIP;
+  }
+  *out = c;
+  return OPE_OK;
+}
+
+ope_status ope_destroy(ope_ctx* c) {
+  if (!c) return OPE_OK;
+  (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  return OPE_OK;
+}
+
+ope_status ope_set_inner(ope_ctx* c, double eta_rel, double eta_floor, int32_t max_iter) {
+  if (!c || !(eta_rel >= 0.0) || !(eta_floor >= 0.0) || max_iter < 1) return OPE_EINVAL;
+  c->eta_rel = eta_rel;
+  c->eta_floor = eta_floor;
+  c->max_iter = max_iter;
+  return OPE_OK;
+}
+
+ope_status ope_apply_h(ope_ctx* c, const double* X, double* Y) {
+  if (!c || !X || !Y || X == Y) return OPE_EINVAL;
+  HIPCHK(launch_apply_h(c, X, Y));
+  return OPE_OK;
+}
+
+ope_status ope_source_solve(ope_ctx* c, const double* U, double* Y, const double* Y0, double tol, int32_t max_iter,
+                            int32_t* iterations) {
+  if (!c || !U || !Y || !(tol >= 0.0) || max_iter < 0) return OPE_EINVAL;
+  if (U == Y) return OPE_EINVAL;
+  const int N = (int)c->N;
+  // r0 = U - H Y0, column norms of r0 and of U
+  if (Y0) {
+    HIPCHK(launch_apply_h(c, Y0, c->HU));
+    HIPCHK(launch_resid0(c, U, c->HU, c->Rb[0], nullptr));
+  } else {
+    HIPCHK(launch_resid0(c, U, nullptr, c->Rb[0], c->Y));
+  }
+  HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, 2 * N, c->rho0, RED_PLAIN));
+  HIPCHK(hipMemcpyAsync(c->cnorm2, c->rho0 + N, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(launch_solve_setup(c, c->rho0, tol));
+  if (Y0) HIPCHK(hipMemcpyAsync(c->Y, Y0, sizeof(double) * c->n * N, hipMemcpyDeviceToDevice, c->stream));
+  int32_t iters = 0;
+  bool done = false;
+  ope_status st = run_cg(c, max_iter, &iters, &done);
+  if (st != OPE_OK) return st;
+  HIPCHK(hipMemcpyAsync(Y, c->Y, sizeof(double) * c->n * N, hipMemcpyDeviceToDevice, c->stream));
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  if (iterations) *iterations = c->hsc->cg_iters;
+  if (c->hsc->err != 0) return (ope_status)c->hsc->err;
+  if (!done) {
+    // the last chunk may have converged exactly at the cap
+    HIPCHK(hipMemcpy(c->hactive, c->active, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+    int cnt = 0;
+    for (int j = 0; j < N; ++j) cnt += c->hactive[j] != 0;
+    if (cnt) return OPE_ECG_MAXIT;
+  }
+  return OPE_OK;
+}
+
+ope_status ope_gram(ope_ctx* c, const double* A, int64_t lda, int64_t na, const double* B, int64_t ldb, int64_t nb,
+                    int64_t rows, double* out) {
+  if (!c || !A || !B || !out) return OPE_EINVAL;
+  if (na < 1 || nb < 1 || na > 512 || nb > 512 || lda < na || ldb < nb || rows < 0) return OPE_EINVAL;
+  if (na * nb > c->part_cap) return OPE_EUNSUPPORTED;
+  if (rows == 0) {
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(double) * na * nb, c->stream));
+    return OPE_OK;
+  }
+  HIPCHK(launch_gram(c, A, lda, (int)na, B, ldb, (int)nb, rows, out));
+  return OPE_OK;
+}
+
+ope_status ope_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau, double* Z, double* A,
+                           double* B) {
+  if (!c || !Sb || !T || !Z || !(tau > 0.0)) return OPE_EINVAL;
+  HIPCHK(hipMemsetAsync(&c->sc->err, 0, sizeof(int32_t), c->stream));
+  HIPCHK(launch_small_solve(c, Sb, T, tau, Z, A, B));
+  ope_status st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  return (ope_status)c->hsc->err;
+}
+
+ope_status ope_update(ope_ctx* c, double* U, const double* Y, const double* Z) {
+  if (!c || !U || !Y || !Z || U == Y) return OPE_EINVAL;
+  const size_t NN = (size_t)c->N * c->N;
+  int64_t np = 0;
+  HIPCHK(launch_rowmm(c, U, Z, Y, Z + NN, nullptr, 0.0, 1.0, U, 0, 0, &np));
+  return OPE_OK;
+}
+
+ope_status ope_energy(ope_ctx* c, const double* U, double* energy) {
+  if (!c || !U || !energy) return OPE_EINVAL;
+  ope_status st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  *energy = c->hsc->energy;
+  return c->hsc->err == OPE_ENONFINITE ? OPE_ENONFINITE : OPE_OK;
+}
+
+ope_status ope_residual(ope_ctx* c, const double* U, double* residual, double* ritz, double* drift) {
+  if (!c || !U) return OPE_EINVAL;
+  const int N = (int)c->N;
+  ope_status st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  HIPCHK(launch_cg_setup(c, c->rcol));   // computes the residual scalar from the column norms
+  if (ritz) {
+    HIPCHK(launch_jacobi_eig(c, c->Lam, c->rho0));
+    HIPCHK(hipMemcpyAsync(c->hbuf, c->rho0, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+  }
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  if (residual) *residual = c->hsc->residual;
+  if (drift) *drift = c->hsc->drift;
+  if (ritz) memcpy(ritz, c->hbuf, sizeof(double) * N);
+  return c->hsc->err == OPE_ENONFINITE ? OPE_ENONFINITE : OPE_OK;
+}
+
+ope_status ope_step(ope_ctx* c, void* U, double tau, ope_step_info* info) {
+  if (!c || !U || !(tau > 0.0)) return OPE_EINVAL;
+  return run_step(c, (double*)U, tau, info, -1.0, nullptr);
+}
+
+ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t max_steps, ope_solve_info* info) {
+  if (!c || !U || !(tau > 0.0) || !(res_tol >= 0.0) || max_steps < 0) return OPE_EINVAL;
+  ope_solve_info si;
+  memset(&si, 0, sizeof(si));
+  ope_status st = OPE_OK;
+  for (;;) {
+    ope_step_info s;
+    bool conv = false;
+    const bool last = si.steps >= max_steps;
+    // the final pass only evaluates the iterate (a residual of 2 is never reached)
+    st = run_step(c, (double*)U, tau, &s, last ? 1e300 : res_tol, &conv);
+    if (st != OPE_OK && st != OPE_ECG_MAXIT) break;
+    si.residual = s.residual;
+    si.energy = s.energy;
+    si.drift = s.drift;
+    if (conv) {
+      si.converged = s.residual <= res_tol;
+      st = OPE_OK;
+      break;
+    }
+    si.steps += 1;
+    si.inner_iterations += s.inner_iterations;
+  }
+  if (info) *info = si;
+  return st;
+}
+
+}  // extern "C"

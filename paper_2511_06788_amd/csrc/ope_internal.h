@@ -1,0 +1,123 @@
+// Internal declarations of the gfx950 eigensolver-step library.
+//
+// Data layout in HBM (all FP64):
+//   orbital blocks   n x N row-major (point-major): the N orbitals of one grid
+//                    point are one contiguous row, so a wavefront reading 64
+//                    consecutive lanes touches whole rows (fully coalesced);
+//                    stencil neighbours sit at +-N, +-m0*N, +-m0*m1*N elements.
+//   inner matrices   N x N row-major.
+//   partials         [work-group][column] rows, reduced in a fixed order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ope.h"
+
+#define OPE_WG 256                  // threads per work-group of the streaming kernels
+#define OPE_MAX_N_SMALL 128         // largest N of the one-work-group FP64 small solves
+
+struct OpeGrid {
+  int dim;
+  uint32_t m0, m1, m2;              // interior nodes per axis (m2 = 1 in 2D)
+  uint32_t s1, s2;                  // point strides of the y and z neighbours (m0, m0*m1)
+  double cx, cy, cz;                // kinetic / h_a^2 per axis (cz = 0 in 2D)
+};
+
+// Device-resident scalars of one context (written by kernels, read by kernels
+// and, after a synchronisation, by the host).
+struct OpeScalars {
+  double energy;      // 1/2 tr Lam
+  double residual;    // |HU - U Lam|_F / |Lam|_F
+  double drift;       // |U^T U - I|_F
+  double lam_fro;     // |Lam|_F
+  double eta;         // inner tolerance of this step
+  int32_t err;        // ope_status of the device side of the step (0 = ok)
+  int32_t cg_iters;   // CG iterations that had at least one active column
+};
+
+struct ope_ctx {
+  int device;
+  hipStream_t stream;
+  OpeGrid g;
+  int64_t n, N;
+  int vw;                       // vector width of block rows (2 if N even, else 1)
+  // operator
+  double* diag;                 // V + shift + 2 (cx + cy + cz), n values
+  // n x N workspace blocks
+  double* HU;                   // H U, then R = HU - U Lam, then a CG direction buffer
+  double* Y;                    // Step-1 solution G U
+  double* Rb[2];                // CG residuals (double buffered)
+  double* Pb;                   // second CG direction buffer (the first is HU)
+  // N x N (and 2N x N) matrices
+  double *C, *Lam, *Linv, *Sb, *T, *Z, *A, *B, *Wsm;
+  // per-column CG state
+  double *alpha, *beta, *rho, *target, *cnorm2, *rcol, *rho0;
+  int32_t* active;
+  // reductions
+  double* part;                 // partial sums, part_cap doubles
+  int64_t part_cap;
+  double* stage;                // second-stage partial sums
+  int64_t stage_cap;
+  uint32_t* counters;           // last-block counters of the split reductions
+  // scalars
+  OpeScalars* sc;               // device
+  OpeScalars* hsc;              // pinned host mirror
+  int32_t* hactive;             // pinned host mirror of active[]
+  double* hbuf;                 // pinned host scratch (N doubles)
+  // policy
+  double eta_rel, eta_floor;
+  int32_t max_iter;
+  int32_t check_every;          // CG iterations between host convergence checks
+  // launch shapes
+  int stream_wgs;               // work-groups of the streaming CG kernels
+  int stream_pts;               // grid points per streaming work-group
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each enqueues on ctx->stream and returns hipSuccess or an error)
+// ---------------------------------------------------------------------------
+hipError_t launch_apply_h(ope_ctx* c, const double* X, double* Y);
+
+// CG iteration halves (see k_stencil.hip)
+hipError_t launch_cg_pap(ope_ctx* c, const double* r, const double* pold, int first);
+hipError_t launch_cg_update(ope_ctx* c, const double* r, const double* pold, double* rnew,
+                            double* pnew, double* y, int first);
+hipError_t launch_cg_setup_reduce(ope_ctx* c, int mode);
+
+// column sums of partials: out[j] = sum_w part[w*ncols + j], fixed order
+hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols,
+                              double* out, int mode);
+enum { RED_PLAIN = 0, RED_CG_ALPHA = 1, RED_CG_BETA = 2 };
+
+// inner matrix out = A^T B over `rows` rows (partials into c->part, then reduced)
+hipError_t launch_gram(ope_ctx* c, const double* A, int64_t lda, int na, const double* B,
+                       int64_t ldb, int nb, int64_t rows, double* out);
+
+// row-block products: Out = cbeta*Cm + ascale*(X0*M0 + X1*M1); optional per-column sums of Out^2
+// into c->part (one row per work-group); returns the number of partial rows in *nparts.
+hipError_t launch_rowmm(ope_ctx* c, const double* X0, const double* M0, const double* X1,
+                        const double* M1, const double* Cm, double cbeta, double ascale, double* Out,
+                        int want_colsq, int predicated, int64_t* nparts);
+// r0 = U - H Y0 (or U when HY is NULL, zeroing y), per-column sums of r0^2 and U^2 into c->part
+hipError_t launch_resid0(ope_ctx* c, const double* U, const double* HY, double* R, double* y);
+
+// one-work-group FP64 kernels
+hipError_t launch_prep_small(ope_ctx* c);
+hipError_t launch_cg_setup(ope_ctx* c, const double* rho0);
+hipError_t launch_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau,
+                              double* Z, double* A, double* B);
+hipError_t launch_jacobi_eig(ope_ctx* c, const double* Asym, double* evals);
+hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
+
+// device helpers shared by the kernels ---------------------------------------
+#ifdef __HIPCC__
+// The hardware hands work-group b to XCD (b mod 8).  Map it to a logical index
+// so that each XCD works through one contiguous range of the problem and its
+// private L2 sees the neighbouring rows it needs.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+  uint32_t q = G >> 3, r = G & 7u;
+  uint32_t x = b & 7u, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+#endif

@@ -1,0 +1,260 @@
+"""ctypes binding of ``libope.so`` (declared in ``include/ope.h``).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions carry the C names; device buffers may be passed as torch CUDA tensors
+(float64, contiguous) or as raw integer device addresses.  A missing or
+unloadable library raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libope.so")
+
+OPE_OK = 0
+OPE_EINVAL = 1
+OPE_ENOMEM = 2
+OPE_EHIP = 3
+OPE_ENONFINITE = 4
+OPE_ECG_MAXIT = 5
+OPE_EPIVOT = 6
+OPE_EUNSUPPORTED = 7
+OPE_FP64 = 0
+
+STATUS_NAMES = {
+    OPE_OK: "OPE_OK", OPE_EINVAL: "OPE_EINVAL", OPE_ENOMEM: "OPE_ENOMEM", OPE_EHIP: "OPE_EHIP",
+    OPE_ENONFINITE: "OPE_ENONFINITE", OPE_ECG_MAXIT: "OPE_ECG_MAXIT", OPE_EPIVOT: "OPE_EPIVOT",
+    OPE_EUNSUPPORTED: "OPE_EUNSUPPORTED",
+}
+
+
+class OpeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({ope_status_string(status)})")
+
+
+class ope_op_desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("m", ctypes.c_int64 * 3),
+        ("h", ctypes.c_double * 3),
+        ("kinetic", ctypes.c_double),
+        ("shift", ctypes.c_double),
+        ("V", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class ope_step_info(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double),
+        ("residual", ctypes.c_double),
+        ("drift", ctypes.c_double),
+        ("inner_iterations", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class ope_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("residual", ctypes.c_double),
+        ("energy", ctypes.c_double),
+        ("drift", ctypes.c_double),
+        ("inner_iterations", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+SIGNATURES = {
+    "ope_create": ([ctypes.POINTER(_P), ctypes.POINTER(ope_op_desc), _I64, _I32, _P], _I32),
+    "ope_destroy": ([_P], _I32),
+    "ope_status_string": ([_I32], ctypes.c_char_p),
+    "ope_set_inner": ([_P, _D, _D, _I32], _I32),
+    "ope_apply_h": ([_P, _P, _P], _I32),
+    "ope_source_solve": ([_P, _P, _P, _P, _D, _I32, ctypes.POINTER(_I32)], _I32),
+    "ope_gram": ([_P, _P, _I64, _I64, _P, _I64, _I64, _I64, _P], _I32),
+    "ope_small_solve": ([_P, _P, _P, _D, _P, _P, _P], _I32),
+    "ope_update": ([_P, _P, _P, _P], _I32),
+    "ope_energy": ([_P, _P, ctypes.POINTER(_D)], _I32),
+    "ope_residual": ([_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I32),
+    "ope_step": ([_P, _P, _D, ctypes.POINTER(ope_step_info)], _I32),
+    "ope_solve": ([_P, _P, _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libope.so`` once; raise if it is missing (build it first).
+
+    torch is imported first when it is installed: its ROCm build ships its own
+    HIP runtime under the same soname, and loading torch first makes this
+    library bind to that one runtime, so torch's streams and allocations are
+    valid here.  Loading the system runtime first would leave two runtimes in
+    the process."""
+    global _lib
+    if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2511_06788_amd.build` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    # torch tensor: must live on the GPU, float64, contiguous
+    if not x.is_cuda:
+        raise ValueError("device buffer expected (torch CUDA tensor)")
+    if not x.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return x.data_ptr()
+
+
+def _check(status: int, where: str, allow=()):
+    if status != OPE_OK and status not in allow:
+        raise OpeError(status, where)
+    return status
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def ope_status_string(status: int) -> str:
+    return lib().ope_status_string(status).decode()
+
+
+def ope_create(dim: int, m: Sequence[int], h: Sequence[float], V: np.ndarray, N: int, kinetic: float = 1.0,
+               shift: float = 0.0, precision: int = OPE_FP64, stream=None) -> int:
+    """Create a context; returns the opaque handle (an int)."""
+    Vh = np.ascontiguousarray(V, dtype=np.float64)
+    d = ope_op_desc()
+    d.dim = dim
+    for a in range(3):
+        d.m[a] = int(m[a]) if a < len(m) else 1
+        d.h[a] = float(h[a]) if a < len(h) else 1.0
+    d.kinetic = kinetic
+    d.shift = shift
+    d.V = Vh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    out = _P()
+    _check(lib().ope_create(ctypes.byref(out), ctypes.byref(d), int(N), int(precision), _stream_ptr(stream)),
+           "ope_create")
+    return out.value
+
+
+def ope_destroy(ctx: int) -> None:
+    _check(lib().ope_destroy(ctx), "ope_destroy")
+
+
+def ope_set_inner(ctx: int, eta_rel: float = 1e-2, eta_floor: float = 1e-12, max_iter: int = 2000) -> None:
+    _check(lib().ope_set_inner(ctx, eta_rel, eta_floor, max_iter), "ope_set_inner")
+
+
+def ope_apply_h(ctx: int, X, Y) -> None:
+    _check(lib().ope_apply_h(ctx, _ptr(X), _ptr(Y)), "ope_apply_h")
+
+
+def ope_source_solve(ctx: int, U, Y, Y0=None, tol: float = 1e-12, max_iter: int = 10000, allow_maxit=False) -> int:
+    it = _I32(0)
+    st = lib().ope_source_solve(ctx, _ptr(U), _ptr(Y), _ptr(Y0), tol, max_iter, ctypes.byref(it))
+    _check(st, "ope_source_solve", allow=(OPE_ECG_MAXIT,) if allow_maxit else ())
+    return it.value
+
+
+def ope_gram(ctx: int, A, lda: int, na: int, B, ldb: int, nb: int, rows: int, out) -> None:
+    _check(lib().ope_gram(ctx, _ptr(A), lda, na, _ptr(B), ldb, nb, rows, _ptr(out)), "ope_gram")
+
+
+def ope_small_solve(ctx: int, Sb, T, tau: float, Z, A=None, B=None) -> None:
+    _check(lib().ope_small_solve(ctx, _ptr(Sb), _ptr(T), tau, _ptr(Z), _ptr(A), _ptr(B)), "ope_small_solve")
+
+
+def ope_update(ctx: int, U, Y, Z) -> None:
+    _check(lib().ope_update(ctx, _ptr(U), _ptr(Y), _ptr(Z)), "ope_update")
+
+
+def ope_energy(ctx: int, U) -> float:
+    e = _D(0.0)
+    _check(lib().ope_energy(ctx, _ptr(U), ctypes.byref(e)), "ope_energy")
+    return e.value
+
+
+def ope_residual(ctx: int, U, N: int, want_ritz: bool = True):
+    """Returns ``(residual, ritz values (N,) or None, drift)``."""
+    res = _D(0.0)
+    drift = _D(0.0)
+    ritz = (ctypes.c_double * N)() if want_ritz else None
+    _check(lib().ope_residual(ctx, _ptr(U), ctypes.byref(res), ritz, ctypes.byref(drift)), "ope_residual")
+    return res.value, (np.array(ritz[:], dtype=np.float64) if want_ritz else None), drift.value
+
+
+def ope_step(ctx: int, U, tau: float, allow_maxit: bool = True) -> ope_step_info:
+    info = ope_step_info()
+    st = lib().ope_step(ctx, _ptr(U), tau, ctypes.byref(info))
+    _check(st, "ope_step", allow=(OPE_ECG_MAXIT,) if allow_maxit else ())
+    return info
+
+
+def ope_step_raw(ctx: int, U, tau: float) -> int:
+    """``ope_step`` without diagnostics (NULL info); returns the status."""
+    return lib().ope_step(ctx, _ptr(U), tau, None)
+
+
+def ope_solve(ctx: int, U, tau: float, res_tol: float, max_steps: int) -> ope_solve_info:
+    info = ope_solve_info()
+    _check(lib().ope_solve(ctx, _ptr(U), tau, res_tol, max_steps, ctypes.byref(info)), "ope_solve",
+           allow=(OPE_ECG_MAXIT,))
+    return info
+
+
+class Context:
+    """Owns one ``ope_ctx`` for a workload (grid, potential, N)."""
+
+    def __init__(self, grid, V, N, kinetic=1.0, shift=0.0, stream=None):
+        self.N = int(N)
+        self.n = int(np.prod(grid.m))
+        self.handle = ope_create(grid.dim, grid.m, grid.h, V, N, kinetic=kinetic, shift=shift, stream=stream)
+
+    def close(self):
+        if self.handle:
+            ope_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the orthogonality-preserving eigensolver step on one MI355X.
+
+Workload: 3D 7-point Dirichlet Laplacian on the 64^3 interior grid of the unit
+cube plus 8 seeded Gaussian wells (seed 0), N = 128 lowest pairs, plain FP64,
+fixed tau = 45 (0.9 of the stability limit 2 / (1/lambda_1 - 1/lambda_max)),
+start block a seeded Gaussian orthonormalised by QR.  One benchmark step is one
+full step of scheme (4.1) (Section 4.1, Steps 1-4) with every row of the hot
+path: stencil, Grams, energy/residual reductions, warm-started CG for Step 1,
+the FP64 small solve and the in-place update.  Inputs are resident in HBM
+before the timed region starts.
+
+Prints one JSON line: outer steps per second (whole job, one GPU), the live
+roofline of the dominant kernel (CG sweep B, timed with HIP events on the
+library's stream), per-kernel timings, a measured time-to-residual-1e-8 on a
+problem that converges within the run, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-residual-1e-8 and iter/s at 64³,N=128: plain FP64 vs mixed vs learned"
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2511_06788_amd", "csrc", "k_stencil.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_b_bytes(n, N):
+    """Algorithmic HBM bytes of one CG sweep B: read r, p_old, y; write r', p, y
+    (six n x N FP64 blocks) plus the n-entry diagonal."""
+    return 6 * n * N * 8 + 8 * n
+
+
+def kernel_bytes(kind, n, N):
+    blk = n * N * 8
+    return {
+        "stencil": 2 * blk + 8 * n,          # read X, write HX, diagonal
+        "cg_sweep_a": 2 * blk + 8 * n,       # read r, p_old, diagonal
+        "cg_sweep_b": sweep_b_bytes(n, N),
+    }.get(kind)
+
+
+def traffic_from_pmc(n, N):
+    """HBM bytes per sweep-B launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    rec = json.load(open(PMC_FILE))
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha or rec.get("n") != n or rec.get("N") != N:
+        return None
+    return (rec["fetch_kib_per_dispatch"] + rec["write_kib_per_dispatch"]) * 1024.0 * rec["copy_scale"]
+
+
+def cpu_baseline(problem, tau, steps):
+    """The oracle, as it stands, on the same workload: `steps` outer steps with
+    the same warm start and inner tolerance rule, composed from oracle functions."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        blas_threads = 1
+    op = O.Operator(problem.grid.m, problem.grid.h, problem.V)
+    U = problem.U0.copy()
+    its = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        HU = O.apply_H(op, U)
+        Lam = U.T @ HU
+        res = np.linalg.norm(HU - U @ Lam) / np.linalg.norm(Lam)
+        eta = max(1e-12, 1e-2 * res)
+        st = {}
+        Y = O.cg_source(op, U, Y0=U @ np.linalg.inv(Lam), tol=eta, stats=st)
+        its += st["iterations"]
+        U = O.step_general(U, Y, tau)["U"]
+    dt = time.perf_counter() - t0
+    return {
+        "value": steps / dt, "unit": "iter/s", "cores": int(blas_threads), "kind": "oracle",
+        "sample": (f"{steps} outer step(s) of the same 64^3 N=128 workload from the same start block "
+                   f"({its} inner CG iterations, {dt:.1f} s); numpy/scipy FP64, BLAS products on "
+                   f"{blas_threads} threads, stencil and vector updates single-threaded numpy"),
+    }
+
+
+def time_to_residual(ope, torch, tol=1e-8):
+    """Wall time of Algorithm 1 from the start block to residual `tol` on a
+    problem whose spectral gap lets it converge in a few hundred steps."""
+    import workloads as W
+    p = W.wells_3d(m=32, N=17, seed=0)
+    tau = 45.0
+    U = torch.from_numpy(p.U0).to("cuda")
+    with ope.Context(p.grid, p.V, p.N) as ctx:
+        Uw = U.clone()
+        ope.ope_solve(ctx.handle, Uw, tau, tol, 3)      # warm the code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        si = ope.ope_solve(ctx.handle, U, tau, tol, 20000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    return {"workload": "wells3d_32^3_N17_seed0", "tau": tau, "res_tol": tol, "converged": bool(si.converged),
+            "steps": int(si.steps), "seconds": dt, "inner_iterations": int(si.inner_iterations),
+            "final_residual": si.residual, "final_drift": si.drift}
+
+
+def copy_calibration(torch, gib=1.0, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    n = int(gib * (1 << 30) // 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tau", type=float, default=45.0)
+    ap.add_argument("--cpu-steps", type=int, default=1, help="outer steps of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print("bench.py measures one GPU: this build runs the step on a single MI355X and has no "
+                  "multi-GPU path (the row-slab sharding design is described in DESIGN.md).", flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_06788_amd import ope
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a visible MI355X")
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    log(f"building workload {args.m}^3 N={args.N} seed={args.seed}")
+    p = W.wells_3d(m=args.m, N=args.N, seed=args.seed, tau=args.tau)
+    n, N = p.grid.n, p.N
+    U = torch.from_numpy(p.U0).to("cuda")
+    ctx = ope.Context(p.grid, p.V, N)
+    h = ctx.handle
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        ope.ope_step(h, U, args.tau)
+    torch.cuda.synchronize()
+
+    log(f"timed {args.steps} steps")
+    ope.ope_profile_begin(h, ope.OPE_KERNEL_CG_SWEEP_B)
+    inner = 0
+    last = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        last = ope.ope_step(h, U, args.tau)
+        inner += last.inner_iterations
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, total_ms = ope.ope_profile_end(h)
+    dt = t1 - t0
+    ms_per_step = 1e3 * dt / max(args.steps, 1)
+    avg_ms = total_ms / max(launches, 1)
+    achieved = sweep_b_bytes(n, N) / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_pmc(n, N)
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"wells3d_{args.m}^3_N{N}_seed{args.seed}", "n": n, "N": N, "tau": args.tau,
+                   "form": "plain FP64", "inner": "CG, eta = max(1e-12, 1e-2 res), warm start U Lam^-1"},
+        "roofline": {"bound": "hbm", "kernel": "cg_sweep_b", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes": sweep_b_bytes(n, N),
+                     "avg_launch_ms": avg_ms, "launches": launches},
+        "inner_iterations_per_step": inner / max(args.steps, 1),
+        "residual_at_end": last.residual if last else None,
+        "drift_at_end": last.drift if last else None,
+    }
+
+    if not args.no_extras:
+        kernels = {}
+        for name, kid in (("stencil", ope.OPE_KERNEL_STENCIL), ("cg_sweep_a", ope.OPE_KERNEL_CG_SWEEP_A),
+                          ("gram", ope.OPE_KERNEL_GRAM), ("rowmm", ope.OPE_KERNEL_ROWMM),
+                          ("small", ope.OPE_KERNEL_SMALL)):
+            ope.ope_profile_begin(h, kid)
+            for _ in range(5):
+                ope.ope_step(h, U, args.tau)
+            nl, tms = ope.ope_profile_end(h)
+            rec = {"avg_ms": tms / max(nl, 1), "launches_per_step": nl / 5.0}
+            b = kernel_bytes(name, n, N)
+            if b:
+                rec["GB/s"] = b / (rec["avg_ms"] * 1e-3) / 1e9
+            if name == "gram":
+                rec["TFLOP/s_fp64"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
+            if name == "rowmm":
+                rec["TFLOP/s_fp64_N_by_N"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
+            kernels[name] = rec
+        kernels["cg_sweep_b"] = {"avg_ms": avg_ms, "GB/s": achieved}
+        out["kernels"] = kernels
+        log("time to residual on the 32^3 N=17 problem")
+        out["time_to_residual"] = time_to_residual(ope, torch)
+    ctx.close()
+
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_steps} oracle step(s)")
+        out["cpu_baseline"] = cpu_baseline(p, args.tau, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,49 @@ ope_status ope_step(ope_ctx* ctx, void* U, double tau, ope_step_info* info);
 ope_status ope_solve(ope_ctx* ctx, void* U, double tau, double res_tol, int32_t max_steps,
                      ope_solve_info* info);
 
+/* --- Launch shape of the stencil / CG sweeps (tuning) --------------------
+ * The sweeps march along the slowest grid axis; a work-group covers q passes
+ * of 256/8 grid points of one x segment (q in {1, 2, 4}; more passes per
+ * plane mean fewer x segments but more registers), and the march axis is cut
+ * into march_chunks ranges (0 = automatic: at least 512 work-groups).  The
+ * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR.
+ * q_max = 0 lets the library choose.  flags: OPE_SWEEP_CHUNK_MAJOR puts the
+ * work-groups of one column chunk next to each other (so one XCD streams one
+ * chunk of every side line) instead of those of one side line;
+ * OPE_SWEEP_NONTEMPORAL writes the swept outputs with non-temporal stores.
+ * Results do not depend on the shape beyond the summation order of the CG dot
+ * products.  Synchronises; on OPE_EINVAL the previous shape stays. */
+#define OPE_SWEEP_CHUNK_MAJOR 1
+#define OPE_SWEEP_NONTEMPORAL 2
+ope_status ope_set_sweep_shape(ope_ctx* ctx, int32_t q_max, int32_t march_chunks, int32_t flags);
+
+/* The shape in use (outputs nullable, host). */
+ope_status ope_get_sweep_shape(const ope_ctx* ctx, int32_t* q, int32_t* march_chunks, int32_t* workgroups);
+
+/* --- Kernel timing (measurement support) ------------------------------ */
+
+typedef enum {
+  OPE_KERNEL_STENCIL = 0,   /* H X (stencil SpMM) */
+  OPE_KERNEL_CG_SWEEP_A = 1,/* CG sweep A: p^T H p with p formed on the fly */
+  OPE_KERNEL_CG_SWEEP_B = 2,/* CG sweep B: y, r, p updates with H p and r^T r */
+  OPE_KERNEL_GRAM = 3,      /* split-K MFMA inner matrices (without their reduction) */
+  OPE_KERNEL_ROWMM = 4,     /* MFMA row-block products (residual, warm start, Step 4) */
+  OPE_KERNEL_SMALL = 5,     /* one-work-group FP64 small solves */
+  OPE_KERNEL_COUNT = 6
+} ope_kernel_id;
+
+typedef struct {
+  int64_t launches;         /* launches timed */
+  double total_ms;          /* summed device time between the events around each launch */
+} ope_kernel_time;
+
+/* Start timing every launch of `kernel` on the context's stream with a pair of
+ * HIP events (until ope_profile_end).  Adds two event records per launch. */
+ope_status ope_profile_begin(ope_ctx* ctx, int32_t kernel);
+
+/* Stop timing; synchronises the stream and writes the totals to *out (host). */
+ope_status ope_profile_end(ope_ctx* ctx, ope_kernel_time* out);
+
 #ifdef __cplusplus
 }
 #endif

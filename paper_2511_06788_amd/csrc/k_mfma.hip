@@ -180,8 +180,11 @@ hipError_t launch_gram(ope_ctx* c, const double* A, int64_t lda, int na, const d
   if (rps < 4) rps = 4;
   ks = (rows + rps - 1) / rps;
   if (ks < 1) ks = 1;
-  hipLaunchKernelGGL(k_gram, dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda, (uint32_t)na, B,
-                     (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
+  {
+    ProfScope ps(c, OPE_KERNEL_GRAM);
+    hipLaunchKernelGGL(k_gram, dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda, (uint32_t)na, B,
+                       (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_cols(c, c->part, ks, (int64_t)na * nb, out, RED_PLAIN);
@@ -194,6 +197,7 @@ hipError_t launch_rowmm(ope_ctx* c, const double* X0, const double* M0, const do
   const uint32_t gr = (n + RT - 1) / RT, gc = (N + CT - 1) / CT;
   if (gc != 1 && (Out == X0 || Out == X1)) return hipErrorInvalidValue;  // in place needs one column tile
   if (want_colsq && (int64_t)gr * N > c->part_cap) return hipErrorInvalidValue;
+  ProfScope ps(c, OPE_KERNEL_ROWMM);
   if (X1)
     hipLaunchKernelGGL((k_rowmm<2>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta, ascale, Out, n, N,
                        want_colsq, predicated, c->sc, c->part);

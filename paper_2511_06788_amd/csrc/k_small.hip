@@ -331,6 +331,7 @@ __global__ __launch_bounds__(SW) void k_jacobi(const double* __restrict__ Asrc, 
 }  // namespace
 
 hipError_t launch_prep_small(ope_ctx* c) {
+  ProfScope ps(c, OPE_KERNEL_SMALL);
   hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(SW), 0, c->stream, c->C, c->Lam, c->Linv, c->cnorm2, (uint32_t)c->N,
                      c->sc);
   return hipGetLastError();
@@ -350,6 +351,7 @@ hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol) {
 
 hipError_t launch_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau, double* Z, double* A,
                               double* B) {
+  ProfScope ps(c, OPE_KERNEL_SMALL);
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SW), 0, c->stream, Sb, T, tau, (uint32_t)c->N, B ? B : c->B, Z, A,
                      c->sc);
   return hipGetLastError();

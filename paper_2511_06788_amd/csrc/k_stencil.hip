@@ -45,17 +45,11 @@ __device__ __forceinline__ void stv(double* __restrict__ base, uint64_t off, con
   }
 }
 
-struct PointCoord {
-  uint32_t i0, i1, i2;
-};
-
-__device__ __forceinline__ PointCoord coords(uint32_t p, const OpeGrid& g) {
-  PointCoord c;
-  const uint32_t t = p / g.m0;
-  c.i0 = p - t * g.m0;
-  c.i2 = t / g.m1;
-  c.i1 = t - c.i2 * g.m1;
-  return c;
+// Store that is not kept in the caches (the rows are not read again by this sweep).
+template <int VW>
+__device__ __forceinline__ void stv_nt(double* __restrict__ base, uint64_t off, const double (&v)[VW]) {
+#pragma unroll
+  for (int k = 0; k < VW; ++k) __builtin_nontemporal_store(v[k], base + off + k);
 }
 
 // Search direction value at element offset `off`: r + beta * p_old (r on the first iteration).
@@ -73,44 +67,6 @@ __device__ __forceinline__ void dirv(const double* __restrict__ r, const double*
 #pragma unroll
     for (int v = 0; v < VW; ++v) out[v] = rv[v] + b[v] * pv[v];
   }
-}
-
-// (H x) at point p for the field produced by `get(off, out)`, given x_p = xc.
-template <int VW, typename Get>
-__device__ __forceinline__ void stencil_at(uint32_t p, uint64_t off, uint64_t rowlen, const OpeGrid& g,
-                                           const double* __restrict__ diag, const double (&xc)[VW],
-                                           Get&& get, double (&hx)[VW]) {
-  const PointCoord pc = coords(p, g);
-  const double d = diag[p];
-  double nx[VW], ny[VW], nz[VW], t[VW];
-#pragma unroll
-  for (int v = 0; v < VW; ++v) nx[v] = ny[v] = nz[v] = 0.0;
-  if (pc.i0 > 0) { get(off - rowlen, t); for (int v = 0; v < VW; ++v) nx[v] += t[v]; }
-  if (pc.i0 + 1 < g.m0) { get(off + rowlen, t); for (int v = 0; v < VW; ++v) nx[v] += t[v]; }
-  if (pc.i1 > 0) { get(off - rowlen * g.s1, t); for (int v = 0; v < VW; ++v) ny[v] += t[v]; }
-  if (pc.i1 + 1 < g.m1) { get(off + rowlen * g.s1, t); for (int v = 0; v < VW; ++v) ny[v] += t[v]; }
-  if (g.dim == 3) {
-    if (pc.i2 > 0) { get(off - rowlen * g.s2, t); for (int v = 0; v < VW; ++v) nz[v] += t[v]; }
-    if (pc.i2 + 1 < g.m2) { get(off + rowlen * g.s2, t); for (int v = 0; v < VW; ++v) nz[v] += t[v]; }
-  }
-#pragma unroll
-  for (int v = 0; v < VW; ++v) hx[v] = d * xc[v] - (g.cx * nx[v] + g.cy * ny[v] + g.cz * nz[v]);
-}
-
-template <int VW>
-__global__ __launch_bounds__(OPE_WG) void k_apply_h(const double* __restrict__ X, double* __restrict__ Yo,
-                                                    const double* __restrict__ diag, OpeGrid g, uint32_t N,
-                                                    uint32_t NV, uint64_t total) {
-  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-  const uint64_t e = (uint64_t)b * OPE_WG + threadIdx.x;
-  if (e >= total) return;
-  const uint32_t p = (uint32_t)(e / NV);
-  const uint32_t cv = (uint32_t)(e - (uint64_t)p * NV);
-  const uint64_t off = (uint64_t)p * N + (uint64_t)cv * VW;
-  double xc[VW], hx[VW];
-  ldv<VW>(X, off, xc);
-  stencil_at<VW>(p, off, N, g, diag, xc, [&](uint64_t o, double (&t)[VW]) { ldv<VW>(X, o, t); }, hx);
-  stv<VW>(Yo, off, hx);
 }
 
 __device__ __forceinline__ bool any_active(const int32_t* __restrict__ active, uint32_t N) {
@@ -142,84 +98,256 @@ __device__ __forceinline__ void wg_colsum(double* red, const double (&acc)[VW], 
   }
 }
 
-template <int VW, bool FIRST>
-__global__ __launch_bounds__(OPE_WG) void k_cg_pap(const double* __restrict__ r, const double* __restrict__ pold,
-                                                   const double* __restrict__ beta, const int32_t* __restrict__ active,
-                                                   const double* __restrict__ diag, OpeGrid g, uint32_t n, uint32_t N,
-                                                   uint32_t NV, uint32_t pts, double* __restrict__ part,
-                                                   OpeScalars* __restrict__ sc) {
-  __shared__ double red[OPE_WG * VW];
-  if (!any_active(active, N)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->cg_iters += 1;
-  const uint32_t wg = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t pp = OPE_WG / NV;                 // points per pass
-  const uint32_t lp = threadIdx.x / NV, cv = threadIdx.x - lp * NV;
-  const bool lane_ok = lp < pp;
-  double b[VW], acc[VW];
-#pragma unroll
-  for (int v = 0; v < VW; ++v) {
-    b[v] = FIRST ? 0.0 : beta[cv * VW + v];
-    acc[v] = 0.0;
-  }
-  const uint32_t p0 = wg * pts;
-  const uint32_t p1 = min(n, p0 + pts);
-  if (lane_ok) {
-    for (uint32_t p = p0 + lp; p < p1; p += pp) {
-      const uint64_t off = (uint64_t)p * N + (uint64_t)cv * VW;
-      double pc[VW], hp[VW];
-      dirv<VW, FIRST>(r, pold, off, b, pc);
-      stencil_at<VW>(p, off, N, g, diag, pc,
-                     [&](uint64_t o, double (&t)[VW]) { dirv<VW, FIRST>(r, pold, o, b, t); }, hp);
-#pragma unroll
-      for (int v = 0; v < VW; ++v) acc[v] += pc[v] * hp[v];
-    }
-  }
-  wg_colsum<VW>(red, acc, lane_ok, pp, NV, N, part + (uint64_t)wg * N);
-}
+// Plane-marching stencil sweep (2.5D).  A work-group owns one side line
+// (y in 3D), one x segment, one chunk of columns and one range of the march
+// axis (z in 3D, y in 2D).  It walks that range plane by plane, keeping the
+// field at planes k-1, k, k+1 in registers, so each row is read from HBM once;
+// x neighbours come from the current plane staged in LDS, side neighbours from
+// the rows the adjacent work-groups of the same XCD stream at the same time
+// (L2 hits).  The march is software-pipelined: while plane k is computed, the
+// centre rows of plane k+2 and the side rows, diagonal and y of plane k+1 are
+// already in flight, so no load latency sits on the per-plane critical path.
+// MODE selects what is done with (H p) at each point:
+//   SW_APPLY   out = H x
+//   SW_PAP     sigma_j += p_j (H p)_j,          p = r + beta p_old
+//   SW_UPDATE  y += alpha p, r' = r - alpha H p, p written, rho'_j += r'_j^2
+enum { SW_APPLY = 0, SW_PAP = 1, SW_UPDATE = 2 };
 
-template <int VW, bool FIRST>
-__global__ __launch_bounds__(OPE_WG) void k_cg_update(const double* __restrict__ r, const double* __restrict__ pold,
-                                                      double* __restrict__ rnew, double* __restrict__ pnew,
-                                                      double* __restrict__ y, const double* __restrict__ alpha,
-                                                      const double* __restrict__ beta, const int32_t* __restrict__ active,
-                                                      const double* __restrict__ diag, OpeGrid g, uint32_t n,
-                                                      uint32_t N, uint32_t NV, uint32_t pts, double* __restrict__ part) {
+template <int VW, int Q, int MODE, bool FIRST>
+__global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0, const double* __restrict__ F1,
+                                                  double* __restrict__ O0, double* __restrict__ O1,
+                                                  double* __restrict__ Yv, const double* __restrict__ alpha,
+                                                  const double* __restrict__ beta, const int32_t* __restrict__ active,
+                                                  const double* __restrict__ diag, OpeGrid g, MarchShape ms,
+                                                  uint32_t N, uint32_t NV, double* __restrict__ part,
+                                                  OpeScalars* __restrict__ sc) {
+  constexpr bool TWO = (MODE != SW_APPLY) && !FIRST;   // field is r + beta p_old (two loads per value)
+  constexpr bool UPD = (MODE == SW_UPDATE);
+  __shared__ double lds[2 * Q * OPE_WG * VW];
   __shared__ double red[OPE_WG * VW];
-  if (!any_active(active, N)) return;
-  const uint32_t wg = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t pp = OPE_WG / NV;
-  const uint32_t lp = threadIdx.x / NV, cv = threadIdx.x - lp * NV;
-  const bool lane_ok = lp < pp;
+  if (MODE != SW_APPLY) {
+    if (!any_active(active, N)) return;
+    if (MODE == SW_PAP && blockIdx.x == 0 && threadIdx.x == 0) sc->cg_iters += 1;
+  }
+  uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t mchunk_id = t % ms.mc;
+  t /= ms.mc;
+  uint32_t cchunk, xs, line;
+  if (ms.order == 0) {           // ((line * nxs + xs) * cc + chunk) * mc + m
+    cchunk = t % ms.cc;
+    t /= ms.cc;
+    xs = t % ms.nxs;
+    line = t / ms.nxs;
+  } else {                       // ((chunk * lines + line) * nxs + xs) * mc + m
+    xs = t % ms.nxs;
+    t /= ms.nxs;
+    line = t % ms.lines;
+    cchunk = t / ms.lines;
+  }
+  const uint32_t cv = threadIdx.x % ms.ncv, slot = threadIdx.x / ms.ncv;
+  const uint32_t colv = cchunk * ms.ncv + cv;
+  const bool lane_ok = slot < ms.pp && colv < NV;
+  const uint64_t coff = (uint64_t)colv * VW;
+  const uint32_t z0 = mchunk_id * ms.mchunk;
+  const uint32_t z1 = min(ms.mlen, z0 + ms.mchunk);
+  const uint64_t lbase = (uint64_t)line * ms.side_stride;
+  const bool side_lo = ms.has_side && line > 0;
+  const bool side_hi = ms.has_side && line + 1 < ms.lines;
+  const uint64_t sstride = (uint64_t)ms.side_stride * N;
+
   double b[VW], a[VW], acc[VW];
 #pragma unroll
   for (int v = 0; v < VW; ++v) {
-    b[v] = FIRST ? 0.0 : beta[cv * VW + v];
-    a[v] = alpha[cv * VW + v];
+    b[v] = (TWO && lane_ok) ? beta[coff + v] : 0.0;
+    a[v] = (UPD && lane_ok) ? alpha[coff + v] : 0.0;
     acc[v] = 0.0;
   }
-  const uint32_t p0 = wg * pts;
-  const uint32_t p1 = min(n, p0 + pts);
-  if (lane_ok) {
-    for (uint32_t p = p0 + lp; p < p1; p += pp) {
-      const uint64_t off = (uint64_t)p * N + (uint64_t)cv * VW;
-      double pc[VW], hp[VW], rc[VW], yc[VW];
-      dirv<VW, FIRST>(r, pold, off, b, pc);
-      stencil_at<VW>(p, off, N, g, diag, pc,
-                     [&](uint64_t o, double (&t)[VW]) { dirv<VW, FIRST>(r, pold, o, b, t); }, hp);
-      ldv<VW>(r, off, rc);
-      ldv<VW>(y, off, yc);
+  uint32_t xq[Q];
+  bool okq[Q];
 #pragma unroll
-      for (int v = 0; v < VW; ++v) {
-        yc[v] += a[v] * pc[v];
-        rc[v] -= a[v] * hp[v];
-        acc[v] += rc[v] * rc[v];
-      }
-      stv<VW>(y, off, yc);
-      stv<VW>(rnew, off, rc);
-      stv<VW>(pnew, off, pc);
+  for (int q = 0; q < Q; ++q) {
+    const uint32_t xi = q * ms.pp + slot;
+    xq[q] = xs * ms.xseg + xi;
+    okq[q] = lane_ok && xi < ms.xseg && xq[q] < g.m0;
+  }
+  auto off_of = [&](uint32_t x, uint32_t z) -> uint64_t {
+    return ((uint64_t)x + lbase + (uint64_t)z * ms.march_stride) * N + coff;
+  };
+  auto zero = [](double (&o)[VW]) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) o[v] = 0.0;
+  };
+  // raw loads of one field value (r and p_old, or x); combined later
+  auto ld_raw = [&](bool ok, uint64_t o, double (&r)[VW], double (&po)[VW]) {
+    if (ok) {
+      ldv<VW>(F0, o, r);
+      if constexpr (TWO) ldv<VW>(F1, o, po);
+    } else {
+      zero(r);
+      if constexpr (TWO) zero(po);
+    }
+  };
+  auto comb = [&](const double (&r)[VW], const double (&po)[VW], double (&out)[VW]) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) out[v] = TWO ? r[v] + b[v] * po[v] : r[v];
+  };
+
+  // pipeline registers (per pass q)
+  double pm[Q][VW], pz[Q][VW], p1[Q][VW];          // field at z-1, z, z+1
+  double rz[Q][VW], r1[Q][VW];                      // r at z, z+1 (UPDATE)
+  double smz[Q][VW], spz[Q][VW];                    // side neighbours at z
+  double dz[Q], yz[Q][VW];                          // diagonal and y at z
+  double c2r[Q][VW], c2p[Q][VW];                    // in flight: centre of z+2
+  double s1r[Q][VW], s1p[Q][VW], t1r[Q][VW], t1p[Q][VW];  // in flight: side rows of z+1
+  double d1[Q], y1[Q][VW];                          // in flight: diagonal, y of z+1
+
+  // prologue: everything for plane z0 and the centre of z0+1
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double tr[VW], tp[VW];
+    const bool ok = okq[q] && z0 < z1;
+    ld_raw(ok && z0 > 0, ok && z0 > 0 ? off_of(xq[q], z0 - 1) : 0, tr, tp);
+    comb(tr, tp, pm[q]);
+    ld_raw(ok, ok ? off_of(xq[q], z0) : 0, tr, tp);
+    comb(tr, tp, pz[q]);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) rz[q][v] = tr[v];
+    ld_raw(ok && z0 + 1 < ms.mlen, ok && z0 + 1 < ms.mlen ? off_of(xq[q], z0 + 1) : 0, tr, tp);
+    comb(tr, tp, p1[q]);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) r1[q][v] = tr[v];
+    const uint64_t o = ok ? off_of(xq[q], z0) : 0;
+    ld_raw(ok && side_lo, o - (side_lo ? sstride : 0), tr, tp);
+    comb(tr, tp, smz[q]);
+    ld_raw(ok && side_hi, o + (side_hi ? sstride : 0), tr, tp);
+    comb(tr, tp, spz[q]);
+    dz[q] = ok ? diag[o / N] : 0.0;
+    if constexpr (UPD) {
+      if (ok) ldv<VW>(Yv, o, yz[q]);
+      else zero(yz[q]);
     }
   }
-  wg_colsum<VW>(red, acc, lane_ok, pp, NV, N, part + (uint64_t)wg * N);
+
+  for (uint32_t z = z0; z < z1; ++z) {
+    // issue the loads of the next iterations
+    const bool n2 = z + 2 < ms.mlen && z + 1 < z1;
+    const bool n1 = z + 1 < z1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const bool ok = okq[q];
+      ld_raw(ok && n2, ok && n2 ? off_of(xq[q], z + 2) : 0, c2r[q], c2p[q]);
+      const uint64_t o1 = (ok && n1) ? off_of(xq[q], z + 1) : 0;
+      ld_raw(ok && n1 && side_lo, o1 - (ok && n1 && side_lo ? sstride : 0), s1r[q], s1p[q]);
+      ld_raw(ok && n1 && side_hi, o1 + (ok && n1 && side_hi ? sstride : 0), t1r[q], t1p[q]);
+      d1[q] = (ok && n1) ? diag[o1 / N] : 0.0;
+      if constexpr (UPD) {
+        if (ok && n1) ldv<VW>(Yv, o1, y1[q]);
+        else zero(y1[q]);
+      }
+    }
+    // stage plane z for the x neighbours
+    double* buf = lds + (z & 1u) * (Q * OPE_WG * VW);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int v = 0; v < VW; ++v) buf[((q * ms.pp + slot) * ms.ncv + cv) * VW + v] = pz[q][v];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (!okq[q]) continue;
+      const uint32_t x = xq[q];
+      const uint32_t xi = q * ms.pp + slot;
+      const uint64_t o = off_of(x, z);
+      double xm[VW], xp[VW];
+      zero(xm);
+      zero(xp);
+      if (x > 0) {
+        if (xi > 0) {
+#pragma unroll
+          for (int v = 0; v < VW; ++v) xm[v] = buf[((xi - 1) * ms.ncv + cv) * VW + v];
+        } else {
+          double tr[VW], tp[VW];
+          ld_raw(true, o - N, tr, tp);
+          comb(tr, tp, xm);
+        }
+      }
+      if (x + 1 < g.m0) {
+        if (xi + 1 < ms.xseg) {
+#pragma unroll
+          for (int v = 0; v < VW; ++v) xp[v] = buf[((xi + 1) * ms.ncv + cv) * VW + v];
+        } else {
+          double tr[VW], tp[VW];
+          ld_raw(true, o + N, tr, tp);
+          comb(tr, tp, xp);
+        }
+      }
+      double hx[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+        hx[v] = dz[q] * pz[q][v] -
+                (g.cx * (xm[v] + xp[v]) + ms.cs * (smz[q][v] + spz[q][v]) + ms.cm * (pm[q][v] + p1[q][v]));
+      if constexpr (MODE == SW_APPLY) {
+        if (ms.nt) stv_nt<VW>(O0, o, hx);
+        else stv<VW>(O0, o, hx);
+      } else if constexpr (MODE == SW_PAP) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] += pz[q][v] * hx[v];
+      } else {
+        double yv[VW], rnew[VW];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+          yv[v] = yz[q][v] + a[v] * pz[q][v];
+          rnew[v] = rz[q][v] - a[v] * hx[v];
+          acc[v] += rnew[v] * rnew[v];
+        }
+        if (ms.nt) {
+          stv_nt<VW>(Yv, o, yv);
+          stv_nt<VW>(O0, o, rnew);
+          stv_nt<VW>(O1, o, pz[q]);
+        } else {
+          stv<VW>(Yv, o, yv);
+          stv<VW>(O0, o, rnew);
+          stv<VW>(O1, o, pz[q]);
+        }
+      }
+    }
+    // rotate the pipeline
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        pm[q][v] = pz[q][v];
+        pz[q][v] = p1[q][v];
+        rz[q][v] = r1[q][v];
+        r1[q][v] = c2r[q][v];
+        if constexpr (UPD) yz[q][v] = y1[q][v];
+      }
+      comb(c2r[q], c2p[q], p1[q]);
+      comb(s1r[q], s1p[q], smz[q]);
+      comb(t1r[q], t1p[q], spz[q]);
+      dz[q] = d1[q];
+    }
+  }
+  if constexpr (MODE != SW_APPLY) {
+    // per-column sums over the work-group's slots -> one partial row per (line, segment, march chunk)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) red[threadIdx.x * VW + v] = (slot < ms.pp) ? acc[v] : 0.0;
+    __syncthreads();
+    if (threadIdx.x < ms.ncv && colv < NV) {
+      double s[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) s[v] = 0.0;
+      for (uint32_t l = 0; l < ms.pp; ++l)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) s[v] += red[(l * ms.ncv + cv) * VW + v];
+      const uint64_t row = ((uint64_t)line * ms.nxs + xs) * ms.mc + mchunk_id;
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const uint64_t col = coff + v;
+        if (col < N) part[row * N + col] = s[v];
+      }
+    }
+  }
 }
 
 // r0 = U - H Y0 (HY given) or r0 = U with y zeroed (HY null); one partial row of
@@ -343,53 +471,94 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_apply_h(ope_ctx* c, const double* X, double* Yo) {
-  const uint32_t N = (uint32_t)c->N;
-  const uint32_t NV = N / c->vw;
-  const uint64_t total = (uint64_t)c->n * NV;
-  const uint32_t grid = (uint32_t)((total + OPE_WG - 1) / OPE_WG);
-  if (c->vw == 2)
-    hipLaunchKernelGGL((k_apply_h<2>), dim3(grid), dim3(OPE_WG), 0, c->stream, X, Yo, c->diag, c->g, N, NV, total);
-  else
-    hipLaunchKernelGGL((k_apply_h<1>), dim3(grid), dim3(OPE_WG), 0, c->stream, X, Yo, c->diag, c->g, N, NV, total);
+template <int VW, int Q, int MODE, bool FIRST>
+static void launch_march_t(ope_ctx* c, const double* F0, const double* F1, double* O0, double* O1, double* Yv) {
+  const uint32_t N = (uint32_t)c->N, NV = N / c->vw;
+  const MarchShape& ms = c->ms;
+  const uint32_t grid = ms.lines * ms.nxs * ms.cc * ms.mc;
+  hipLaunchKernelGGL((k_march<VW, Q, MODE, FIRST>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0, O1, Yv,
+                     c->alpha, c->beta, c->active, c->diag, c->g, ms, N, NV, c->part, c->sc);
+}
+
+template <int VW, int MODE, bool FIRST>
+static void launch_march_q(ope_ctx* c, const double* F0, const double* F1, double* O0, double* O1, double* Yv) {
+  switch (c->ms.q) {
+    case 1: launch_march_t<VW, 1, MODE, FIRST>(c, F0, F1, O0, O1, Yv); break;
+    case 2: launch_march_t<VW, 2, MODE, FIRST>(c, F0, F1, O0, O1, Yv); break;
+    default: launch_march_t<VW, 4, MODE, FIRST>(c, F0, F1, O0, O1, Yv); break;
+  }
+}
+
+template <int MODE, bool FIRST>
+static hipError_t launch_march(ope_ctx* c, const double* F0, const double* F1, double* O0, double* O1, double* Yv) {
+  if (c->vw == 2) launch_march_q<2, MODE, FIRST>(c, F0, F1, O0, O1, Yv);
+  else launch_march_q<1, MODE, FIRST>(c, F0, F1, O0, O1, Yv);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_pap(ope_ctx* c, const double* r, const double* pold, int first) {
-  const uint32_t N = (uint32_t)c->N, NV = N / c->vw, n = (uint32_t)c->n;
-  const dim3 grid(c->stream_wgs), blk(OPE_WG);
-  const uint32_t pts = (uint32_t)c->stream_pts;
-  if (c->vw == 2) {
-    if (first)
-      hipLaunchKernelGGL((k_cg_pap<2, true>), grid, blk, 0, c->stream, r, pold, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part, c->sc);
-    else
-      hipLaunchKernelGGL((k_cg_pap<2, false>), grid, blk, 0, c->stream, r, pold, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part, c->sc);
+void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt) {
+  MarchShape& ms = c->ms;
+  ms.order = order ? 1u : 0u;
+  ms.nt = nt ? 1u : 0u;
+  const OpeGrid& g = c->g;
+  const uint32_t NV = (uint32_t)(c->N / c->vw);
+  // 8 vector columns: one 128-byte line per grid point and work-group for FP64 pairs
+  ms.ncv = NV < 8u ? NV : 8u;
+  ms.pp = OPE_WG / ms.ncv;
+  const uint32_t qcap = q_max > 0 ? (uint32_t)q_max : 2u;
+  uint32_t q = 1;
+  while (q < qcap && q < 4u && q * ms.pp < g.m0) q *= 2;
+  ms.q = q;
+  ms.xseg = q * ms.pp;
+  ms.nxs = (g.m0 + ms.xseg - 1) / ms.xseg;
+  ms.cc = (NV + ms.ncv - 1) / ms.ncv;
+  if (g.dim == 3) {
+    ms.lines = g.m1;
+    ms.mlen = g.m2;
+    ms.side_stride = g.m0;
+    ms.march_stride = g.m0 * g.m1;
+    ms.cm = g.cz;
+    ms.cs = g.cy;
+    ms.has_side = 1;
   } else {
-    if (first)
-      hipLaunchKernelGGL((k_cg_pap<1, true>), grid, blk, 0, c->stream, r, pold, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part, c->sc);
-    else
-      hipLaunchKernelGGL((k_cg_pap<1, false>), grid, blk, 0, c->stream, r, pold, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part, c->sc);
+    ms.lines = 1;
+    ms.mlen = g.m1;
+    ms.side_stride = 0;
+    ms.march_stride = g.m0;
+    ms.cm = g.cy;
+    ms.cs = 0.0;
+    ms.has_side = 0;
   }
-  return hipGetLastError();
+  // automatic: one march chunk when that already gives 512 work-groups (the
+  // lock-step march keeps side rows in L2), more chunks for smaller grids
+  const uint32_t base = ms.lines * ms.nxs * ms.cc;
+  uint32_t mc = mc_override > 0 ? (uint32_t)mc_override : (512u + base - 1) / base;
+  if (mc < 1) mc = 1;
+  if (mc > ms.mlen) mc = ms.mlen;
+  ms.mchunk = (ms.mlen + mc - 1) / mc;
+  ms.mc = (ms.mlen + ms.mchunk - 1) / ms.mchunk;
+}
+
+int64_t march_rows(const ope_ctx* c) {
+  return (int64_t)c->ms.lines * c->ms.nxs * c->ms.mc;
+}
+
+hipError_t launch_apply_h(ope_ctx* c, const double* X, double* Yo) {
+  ProfScope ps(c, OPE_KERNEL_STENCIL);
+  return launch_march<SW_APPLY, false>(c, X, nullptr, Yo, nullptr, nullptr);
+}
+
+hipError_t launch_cg_pap(ope_ctx* c, const double* r, const double* pold, int first) {
+  ProfScope ps(c, OPE_KERNEL_CG_SWEEP_A);
+  if (first) return launch_march<SW_PAP, true>(c, r, pold, nullptr, nullptr, nullptr);
+  return launch_march<SW_PAP, false>(c, r, pold, nullptr, nullptr, nullptr);
 }
 
 hipError_t launch_cg_update(ope_ctx* c, const double* r, const double* pold, double* rnew, double* pnew,
                             double* y, int first) {
-  const uint32_t N = (uint32_t)c->N, NV = N / c->vw, n = (uint32_t)c->n;
-  const dim3 grid(c->stream_wgs), blk(OPE_WG);
-  const uint32_t pts = (uint32_t)c->stream_pts;
-  if (c->vw == 2) {
-    if (first)
-      hipLaunchKernelGGL((k_cg_update<2, true>), grid, blk, 0, c->stream, r, pold, rnew, pnew, y, c->alpha, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part);
-    else
-      hipLaunchKernelGGL((k_cg_update<2, false>), grid, blk, 0, c->stream, r, pold, rnew, pnew, y, c->alpha, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part);
-  } else {
-    if (first)
-      hipLaunchKernelGGL((k_cg_update<1, true>), grid, blk, 0, c->stream, r, pold, rnew, pnew, y, c->alpha, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part);
-    else
-      hipLaunchKernelGGL((k_cg_update<1, false>), grid, blk, 0, c->stream, r, pold, rnew, pnew, y, c->alpha, c->beta, c->active, c->diag, c->g, n, N, NV, pts, c->part);
-  }
-  return hipGetLastError();
+  ProfScope ps(c, OPE_KERNEL_CG_SWEEP_B);
+  if (first) return launch_march<SW_UPDATE, true>(c, r, pold, rnew, pnew, y);
+  return launch_march<SW_UPDATE, false>(c, r, pold, rnew, pnew, y);
 }
 
 hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols, double* out, int mode) {

@@ -44,6 +44,7 @@ void free_ctx(ope_ctx* c) {
   if (c->hsc) (void)hipHostFree(c->hsc);
   if (c->hactive) (void)hipHostFree(c->hactive);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
+  for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -80,9 +81,9 @@ ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) 
   while (it < max_iter) {
     const int first = (it == 0);
     HIPCHK(launch_cg_pap(c, r_cur, p_old, first));
-    HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, N, nullptr, RED_CG_ALPHA));
+    HIPCHK(launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA));
     HIPCHK(launch_cg_update(c, r_cur, p_old, r_nxt, p_new, c->Y, first));
-    HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, N, nullptr, RED_CG_BETA));
+    HIPCHK(launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA));
     double* t = r_cur;
     r_cur = r_nxt;
     r_nxt = t;
@@ -159,6 +160,27 @@ ope_status run_step(ope_ctx* c, double* U, double tau, ope_step_info* info, doub
 
 }  // namespace
 
+ProfScope::ProfScope(ope_ctx* ctx, int kernel) : c(ctx), on(ctx->prof_kernel == kernel) {
+  if (!on) return;
+  if (c->prof_used + 2 > c->prof_events.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      c->prof_events.push_back(e);
+    }
+  }
+  (void)hipEventRecord(c->prof_events[c->prof_used], c->stream);
+}
+
+ProfScope::~ProfScope() {
+  if (!on) return;
+  (void)hipEventRecord(c->prof_events[c->prof_used + 1], c->stream);
+  c->prof_used += 2;
+}
+
 extern "C" {
 
 const char* ope_status_string(ope_status s) {
@@ -191,9 +213,10 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (N < 1 || N > n) return OPE_EINVAL;
   if (N > OPE_MAX_N_SMALL) return OPE_EUNSUPPORTED;
 
-  ope_ctx* c = new (std::nothrow) ope_ctx;
+  ope_ctx* c = new (std::nothrow) ope_ctx();
   if (!c) return OPE_ENOMEM;
-  memset(c, 0, sizeof(*c));
+  c->prof_kernel = -1;
+  c->prof_used = 0;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -225,11 +248,13 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (pts < pp) pts = pp;
   c->stream_pts = (int)pts;
   c->stream_wgs = (int)((n + pts - 1) / pts);
+  march_shape(c, 0, 0, 1, 0);
 
   const int64_t blk = n * N;
   const int64_t gram_parts = 1024 * N * N;
   const int64_t row_parts = ((n + 63) / 64) * N;
   int64_t pc = (int64_t)c->stream_wgs * 2 * N;
+  if (march_rows(c) * N > pc) pc = march_rows(c) * N;
   if (gram_parts > pc) pc = gram_parts;
   if (row_parts > pc) pc = row_parts;
   c->part_cap = pc;
@@ -401,6 +426,50 @@ ope_status ope_residual(ope_ctx* c, const double* U, double* residual, double* r
   if (drift) *drift = c->hsc->drift;
   if (ritz) memcpy(ritz, c->hbuf, sizeof(double) * N);
   return c->hsc->err == OPE_ENONFINITE ? OPE_ENONFINITE : OPE_OK;
+}
+
+ope_status ope_set_sweep_shape(ope_ctx* c, int32_t q_max, int32_t march_chunks, int32_t flags) {
+  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~3))
+    return OPE_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const MarchShape keep = c->ms;
+  march_shape(c, q_max, march_chunks, flags & OPE_SWEEP_CHUNK_MAJOR, flags & OPE_SWEEP_NONTEMPORAL);
+  if (march_rows(c) * c->N > c->part_cap) {
+    c->ms = keep;
+    return OPE_EINVAL;
+  }
+  return OPE_OK;
+}
+
+ope_status ope_get_sweep_shape(const ope_ctx* c, int32_t* q, int32_t* march_chunks, int32_t* workgroups) {
+  if (!c) return OPE_EINVAL;
+  if (q) *q = (int32_t)c->ms.q;
+  if (march_chunks) *march_chunks = (int32_t)c->ms.mc;
+  if (workgroups) *workgroups = (int32_t)(c->ms.lines * c->ms.nxs * c->ms.cc * c->ms.mc);
+  return OPE_OK;
+}
+
+ope_status ope_profile_begin(ope_ctx* c, int32_t kernel) {
+  if (!c || kernel < 0 || kernel >= OPE_KERNEL_COUNT) return OPE_EINVAL;
+  c->prof_kernel = kernel;
+  c->prof_used = 0;
+  return OPE_OK;
+}
+
+ope_status ope_profile_end(ope_ctx* c, ope_kernel_time* out) {
+  if (!c || !out) return OPE_EINVAL;
+  c->prof_kernel = -1;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (size_t k = 0; k + 1 < c->prof_used; k += 2) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->prof_events[k], c->prof_events[k + 1]));
+    total += ms;
+  }
+  out->launches = (int64_t)(c->prof_used / 2);
+  out->total_ms = total;
+  c->prof_used = 0;
+  return OPE_OK;
 }
 
 ope_status ope_step(ope_ctx* c, void* U, double tau, ope_step_info* info) {

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ope.h"
 
 #define OPE_WG 256                  // threads per work-group of the streaming kernels
@@ -22,6 +24,25 @@ struct OpeGrid {
   uint32_t m0, m1, m2;              // interior nodes per axis (m2 = 1 in 2D)
   uint32_t s1, s2;                  // point strides of the y and z neighbours (m0, m0*m1)
   double cx, cy, cz;                // kinetic / h_a^2 per axis (cz = 0 in 2D)
+};
+
+// Work decomposition of the plane-marching stencil sweeps (see k_stencil.hip).
+struct MarchShape {
+  uint32_t ncv;       // vector columns per work-group (column chunk)
+  uint32_t pp;        // grid points per pass (OPE_WG / ncv)
+  uint32_t q;         // passes per plane (compile-time variant 1, 2, 4 or 8)
+  uint32_t xseg;      // x points per segment (q * pp)
+  uint32_t nxs;       // x segments
+  uint32_t cc;        // column chunks
+  uint32_t lines;     // side lines (m1 in 3D, 1 in 2D)
+  uint32_t mlen;      // planes along the march axis (m2 in 3D, m1 in 2D)
+  uint32_t mc;        // march chunks
+  uint32_t mchunk;    // planes per march chunk
+  uint32_t side_stride, march_stride;  // point strides of the side and march axes
+  uint32_t has_side;
+  uint32_t order;     // 0: work-groups of one side line adjacent; 1: of one column chunk adjacent
+  uint32_t nt;        // 1: streamed outputs bypass the caches (non-temporal stores)
+  double cm, cs;      // stencil coefficients of the march and side axes
 };
 
 // Device-resident scalars of one context (written by kernels, read by kernels
@@ -70,14 +91,29 @@ struct ope_ctx {
   int32_t max_iter;
   int32_t check_every;          // CG iterations between host convergence checks
   // launch shapes
-  int stream_wgs;               // work-groups of the streaming CG kernels
-  int stream_pts;               // grid points per streaming work-group
+  int stream_wgs;               // work-groups of the flat streaming kernels
+  int stream_pts;               // grid points per flat streaming work-group
+  MarchShape ms;                // plane-marching stencil sweeps
+  // kernel timing (ope_profile_begin / ope_profile_end)
+  int prof_kernel;              // kernel id being timed, -1 when off
+  std::vector<hipEvent_t> prof_events;  // start/stop pairs, reused across sessions
+  size_t prof_used;             // events recorded in this session
+};
+
+// Brackets one launch with timing events when that kernel is being profiled.
+struct ProfScope {
+  ope_ctx* c;
+  bool on;
+  ProfScope(ope_ctx* ctx, int kernel);
+  ~ProfScope();
 };
 
 // ---------------------------------------------------------------------------
 // launchers (each enqueues on ctx->stream and returns hipSuccess or an error)
 // ---------------------------------------------------------------------------
 hipError_t launch_apply_h(ope_ctx* c, const double* X, double* Y);
+void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt);  // fills c->ms (0 = automatic)
+int64_t march_rows(const ope_ctx* c);              // partial rows written by the CG sweeps
 
 // CG iteration halves (see k_stencil.hip)
 hipError_t launch_cg_pap(ope_ctx* c, const double* r, const double* pold, int first);

@@ -71,6 +71,17 @@ class ope_solve_info(ctypes.Structure):
     ]
 
 
+class ope_kernel_time(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+OPE_KERNEL_STENCIL = 0
+OPE_KERNEL_CG_SWEEP_A = 1
+OPE_KERNEL_CG_SWEEP_B = 2
+OPE_KERNEL_GRAM = 3
+OPE_KERNEL_ROWMM = 4
+OPE_KERNEL_SMALL = 5
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -92,6 +103,10 @@ SIGNATURES = {
     "ope_residual": ([_P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)], _I32),
     "ope_step": ([_P, _P, _D, ctypes.POINTER(ope_step_info)], _I32),
     "ope_solve": ([_P, _P, _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
+    "ope_set_sweep_shape": ([_P, _I32, _I32, _I32], _I32),
+    "ope_get_sweep_shape": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _I32),
+    "ope_profile_begin": ([_P, _I32], _I32),
+    "ope_profile_end": ([_P, ctypes.POINTER(ope_kernel_time)], _I32),
 }
 
 
@@ -232,6 +247,32 @@ def ope_solve(ctx: int, U, tau: float, res_tol: float, max_steps: int) -> ope_so
     _check(lib().ope_solve(ctx, _ptr(U), tau, res_tol, max_steps, ctypes.byref(info)), "ope_solve",
            allow=(OPE_ECG_MAXIT,))
     return info
+
+
+OPE_SWEEP_CHUNK_MAJOR = 1
+OPE_SWEEP_NONTEMPORAL = 2
+
+
+def ope_set_sweep_shape(ctx: int, q_max: int, march_chunks: int, flags: int = 0) -> None:
+    _check(lib().ope_set_sweep_shape(ctx, q_max, march_chunks, flags), "ope_set_sweep_shape")
+
+
+def ope_get_sweep_shape(ctx: int):
+    """Returns ``(q, march_chunks, workgroups)`` of the stencil / CG sweeps."""
+    q, mc, wg = _I32(0), _I32(0), _I32(0)
+    _check(lib().ope_get_sweep_shape(ctx, ctypes.byref(q), ctypes.byref(mc), ctypes.byref(wg)), "ope_get_sweep_shape")
+    return q.value, mc.value, wg.value
+
+
+def ope_profile_begin(ctx: int, kernel: int) -> None:
+    _check(lib().ope_profile_begin(ctx, kernel), "ope_profile_begin")
+
+
+def ope_profile_end(ctx: int):
+    """Returns ``(launches, total_ms)`` of the kernel timed since ope_profile_begin."""
+    t = ope_kernel_time()
+    _check(lib().ope_profile_end(ctx, ctypes.byref(t)), "ope_profile_end")
+    return t.launches, t.total_ms
 
 
 class Context:

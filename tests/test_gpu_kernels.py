@@ -178,3 +178,25 @@ def test_energy_residual_ritz_match_oracle():
     r_ref = O.ritz_values(op, U)
     assert np.max(np.abs(ritz - r_ref)) <= 1e-12 * np.max(np.abs(r_ref))
     assert abs(drift - O.ortho_error(U)) <= 1e-14 * p.N
+
+
+@pytest.mark.parametrize("q_max,chunks,flags", [(1, 1, 0), (2, 3, 1), (4, 0, 2), (4, 5, 3), (1, 0, 3)])
+def test_sweep_shapes_agree(q_max, chunks, flags):
+    """Every launch shape of the marching sweeps computes the same H X, and the
+    same CG solution up to the order of the dot-product sums."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=21, N=34, seed=6)
+    op = _op(p)
+    X = np.random.default_rng(3).standard_normal((p.grid.n, p.N))
+    U = W.initial_block(p.grid.n, p.N, 8)
+    say(f"sweep shape q={q_max} chunks={chunks} flags={flags}")
+    with _ctx(p) as ctx:
+        ope.ope_set_sweep_shape(ctx.handle, q_max, chunks, flags)
+        Yd = empty_dev(p.grid.n, p.N)
+        ope.ope_apply_h(ctx.handle, to_dev(X), Yd)
+        Y = to_host(Yd)
+        Sd = empty_dev(p.grid.n, p.N)
+        ope.ope_source_solve(ctx.handle, to_dev(U), Sd, None, 1e-11, 20000)
+        S = to_host(Sd)
+    assert np.max(np.abs(Y - O.apply_H(op, X))) <= stencil_bound(op, X)
+    assert np.all(np.linalg.norm(U - O.apply_H(op, S), axis=0) <= 20 * 1e-11)

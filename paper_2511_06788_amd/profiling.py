@@ -1,0 +1,116 @@
+"""Summaries of rocprofv3 results (SQLite ``*_results.db``) for ``profiles/``.
+
+``python -m paper_2511_06788_amd.profiling trace <db> --cmd "<rocprofv3 command>"``
+prints a per-kernel table (calls, total and average duration) as Markdown.
+
+``python -m paper_2511_06788_amd.profiling pmc --fetch <db> --write <db>
+--copy-fetch <db> --copy-write <db> --kernel <regex> --n N_POINTS --N N_COLS
+--source <file> --cmd ...`` prints the byte counters of the kernels matching
+``regex`` per dispatch, scaled by the factor that makes a plain device copy of
+known size read its own size, and writes the JSON record ``bench.py`` uses for
+its ``traffic`` field.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import re
+import sqlite3
+import sys
+
+
+def kernel_stats(db: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    # rocprofv3's top_kernels view reports durations in microseconds
+    return [{"name": r[0], "calls": int(r[1]), "total_ms": r[2] / 1e3, "avg_us": r[3], "pct": r[4]}
+            for r in rows]
+
+
+def counter_per_dispatch(db: str, counter: str, pattern: str):
+    con = sqlite3.connect(db)
+    rx = re.compile(pattern)
+    vals = [r[1] for r in con.execute("select kernel_name, value from counters_collection where counter_name=?",
+                                      (counter,)) if rx.search(r[0])]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def short_name(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
+    m = re.match(r"(void )?([\w:]+)(<[^()]*>)?", name)
+    return (m.group(2) + (m.group(3) or "")) if m else name[:60]
+
+
+def cmd_trace(args):
+    st = kernel_stats(args.db)
+    out = [f"# Kernel trace: {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
+           "| kernel | calls | total (ms) | average (us) | share |", "|---|---:|---:|---:|---:|"]
+    for r in st[: args.top]:
+        out.append(f"| `{short_name(r['name'])}` | {r['calls']} | {r['total_ms']:.2f} | {r['avg_us']:.1f} | {r['pct']:.1f}% |")
+    print("\n".join(out))
+
+
+def cmd_pmc(args):
+    cf, _ = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE", args.copy_kernel)
+    cw, _ = counter_per_dispatch(args.copy_write, "WRITE_SIZE", args.copy_kernel)
+    copy_kib = args.copy_bytes / 1024.0
+    fscale = copy_kib / cf
+    wscale = copy_kib / cw
+    f, nf = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
+    w, nw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
+    blk = args.n * args.N * 8
+    algo_read = args.reads * blk + 8 * args.n
+    algo_write = args.writes * blk
+    rec = {
+        "kernel_regex": args.kernel, "n": args.n, "N": args.N,
+        "fetch_kib_per_dispatch": f * fscale, "write_kib_per_dispatch": w * wscale, "copy_scale": 1.0,
+        "raw_fetch_kib": f, "raw_write_kib": w, "fetch_scale": fscale, "write_scale": wscale,
+        "dispatches": [nf, nw], "algorithmic_read_bytes": algo_read, "algorithmic_write_bytes": algo_write,
+        "source_sha256": hashlib.sha256(open(args.source, "rb").read()).hexdigest(), "command": args.cmd,
+    }
+    if args.json:
+        with open(args.json, "w") as fh:
+            json.dump(rec, fh, indent=1)
+    print("\n".join([
+        f"# HBM traffic: {args.title}", "", "Commands:", "", "```", args.cmd, "```", "",
+        f"Copy calibration: a plain device copy of {args.copy_bytes} bytes reads as {cf:.1f} KiB FETCH_SIZE and "
+        f"{cw:.1f} KiB WRITE_SIZE per dispatch: fetch scale {fscale:.4f}, write scale {wscale:.4f}.", "",
+        "| quantity | per dispatch |", "|---|---:|",
+        f"| FETCH_SIZE raw (KiB) | {f:.1f} |", f"| WRITE_SIZE raw (KiB) | {w:.1f} |",
+        f"| read bytes, scaled | {f * fscale * 1024:.4g} |", f"| written bytes, scaled | {w * wscale * 1024:.4g} |",
+        f"| algorithmic read bytes | {algo_read:.4g} |", f"| algorithmic written bytes | {algo_write:.4g} |",
+        f"| read / algorithmic | {f * fscale * 1024 / algo_read:.2f} |",
+        f"| written / algorithmic | {w * wscale * 1024 / max(algo_write, 1):.2f} |",
+        f"| dispatches averaged | {nf} / {nw} |",
+    ]))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--title", default="")
+    t.add_argument("--top", type=int, default=20)
+    p = sub.add_parser("pmc")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    p.add_argument("--kernel", required=True)
+    p.add_argument("--copy-kernel", default="copyBuffer|elementwise")
+    p.add_argument("--copy-bytes", type=int, default=1 << 30)
+    p.add_argument("--n", type=int, required=True)
+    p.add_argument("--N", type=int, required=True)
+    p.add_argument("--reads", type=int, default=3)
+    p.add_argument("--writes", type=int, default=3)
+    p.add_argument("--source", required=True)
+    p.add_argument("--cmd", required=True)
+    p.add_argument("--title", default="")
+    p.add_argument("--json", default=None)
+    args = ap.parse_args(argv)
+    {"trace": cmd_trace, "pmc": cmd_pmc}[args.what](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

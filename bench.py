@@ -12,9 +12,11 @@ before the timed region starts.
 
 Prints one JSON line: outer steps per second (whole job, one GPU), the live
 roofline of the dominant kernel (CG sweep B, timed with HIP events on the
-library's stream), per-kernel timings, a measured time-to-residual-1e-8 on a
-problem that converges within the run, and the CPU oracle timed on a bounded
-sample of the same workload.
+library's stream), per-kernel timings, the mixed-precision form's steps per
+second on the same workload, measured time-to-residual-1e-8 (plain FP64, and
+mixed precision with an FP64 finish) on a problem that converges within the
+run (64^3 grid, N = 17, which closes a level shell), and the CPU oracle timed
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -98,24 +100,58 @@ def cpu_baseline(problem, tau, steps):
     }
 
 
-def time_to_residual(ope, torch, tol=1e-8):
+def time_to_residual(ope, torch, tol=1e-8, switch=1e-5):
     """Wall time of Algorithm 1 from the start block to residual `tol` on a
-    problem whose spectral gap lets it converge in a few hundred steps."""
+    problem whose spectral gap lets it converge in a few hundred steps: plain
+    FP64, and the mixed form until `switch` followed by FP64 steps."""
+    import numpy as np
     import workloads as W
-    p = W.wells_3d(m=32, N=17, seed=0)
+    p = W.wells_3d(m=64, N=17, seed=0)
     tau = 45.0
-    U = torch.from_numpy(p.U0).to("cuda")
-    with ope.Context(p.grid, p.V, p.N) as ctx:
-        Uw = U.clone()
-        ope.ope_solve(ctx.handle, Uw, tau, tol, 3)      # warm the code paths
+    out = {"workload": "wells3d_64^3_N17_seed0", "tau": tau, "res_tol": tol}
+    with ope.Context(p.grid, p.V, p.N) as cd, ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as cm:
+        # warm the code paths
+        ope.ope_solve(cd.handle, torch.from_numpy(p.U0).to("cuda"), tau, tol, 3)
+        ope.ope_solve(cm.handle, torch.from_numpy(p.U0.astype(np.float32)).to("cuda"), tau, tol, 3)
+        U = torch.from_numpy(p.U0).to("cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        si = ope.ope_solve(ctx.handle, U, tau, tol, 20000)
+        si = ope.ope_solve(cd.handle, U, tau, tol, 20000)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
+        U64 = torch.empty_like(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sm = ope.ope_solve(cm.handle, U32, tau, switch, 20000)
+        ope.ope_convert(cm.handle, U32, U64, p.grid.n * p.N, True)
+        sf = ope.ope_solve(cd.handle, U64, tau, tol, 20000)
+        torch.cuda.synchronize()
+        t_mixed = time.perf_counter() - t0
+    out["plain_fp64"] = {"converged": bool(si.converged), "steps": int(si.steps), "seconds": t_plain,
+                         "final_residual": si.residual, "final_drift": si.drift}
+    out["mixed_then_fp64"] = {"converged": bool(sf.converged), "mixed_steps": int(sm.steps),
+                              "fp64_steps": int(sf.steps), "switch_residual": switch, "seconds": t_mixed,
+                              "final_residual": sf.residual, "final_drift": sf.drift}
+    out["speedup_mixed"] = t_plain / t_mixed
+    return out
+
+
+def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
+    import numpy as np
+    U = torch.from_numpy(p.U0.astype(np.float32 if precision == ope.OPE_MIXED else np.float64)).to("cuda")
+    with ope.Context(p.grid, p.V, p.N, precision=precision) as ctx:
+        for _ in range(warmup):
+            ope.ope_step(ctx.handle, U, tau)
+        torch.cuda.synchronize()
+        inner = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            inner += ope.ope_step(ctx.handle, U, tau).inner_iterations
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-    return {"workload": "wells3d_32^3_N17_seed0", "tau": tau, "res_tol": tol, "converged": bool(si.converged),
-            "steps": int(si.steps), "seconds": dt, "inner_iterations": int(si.inner_iterations),
-            "final_residual": si.residual, "final_drift": si.drift}
+    return {"iter_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "inner_iterations_per_step": inner / steps,
+            "steps": steps, "warmup": warmup}
 
 
 def copy_calibration(torch, gib=1.0, reps=5):
@@ -235,9 +271,17 @@ def main():
             kernels[name] = rec
         kernels["cg_sweep_b"] = {"avg_ms": avg_ms, "GB/s": achieved}
         out["kernels"] = kernels
-        log("time to residual on the 32^3 N=17 problem")
-        out["time_to_residual"] = time_to_residual(ope, torch)
     ctx.close()
+    if not args.no_extras:
+        log("mixed-precision form at the same workload")
+        ks = min(args.steps, 100)
+        out["forms"] = {
+            "plain_fp64": {"iter_per_s": args.steps / dt, "ms_per_step": ms_per_step,
+                           "inner_iterations_per_step": inner / max(args.steps, 1)},
+            "mixed": steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, ks, args.warmup),
+        }
+        log("time to residual on the 64^3 N=17 problem")
+        out["time_to_residual"] = time_to_residual(ope, torch)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle step(s)")

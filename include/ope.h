@@ -49,7 +49,17 @@ typedef enum {
   OPE_EUNSUPPORTED = 7 /* valid request this build does not implement */
 } ope_status;
 
-typedef enum { OPE_FP64 = 0 } ope_precision;
+/* OPE_FP64: every block and every operation in FP64.
+ * OPE_MIXED: orbital blocks (U and the workspace) stored in FP32; stencil and
+ * Step-1 CG in FP32; <U,U> and <U,HU> (energy, drift) accumulated in FP64 on the
+ * matrix cores; <U,Y> and the projection P = Y - U<U,Y> in FP32 on the matrix
+ * cores; P^T P and Step 4 in BF16 with FP32 accumulation, with Step 4 written
+ * in delta form U' = U + U Z1 + P Z2 (Z1 = -2(I - B), Z2 = tau B) so that its
+ * BF16 rounding vanishes at convergence; the Step-2 matrix uses
+ * T - S_a S_b = P^T P - S_b^T (C - I) S_b; the small solves and all checks in FP64.  Its accuracy is
+ * bounded by FP32 storage (residual floor about 1e-6); convert U to FP64 and
+ * continue with an OPE_FP64 context to finish. */
+typedef enum { OPE_FP64 = 0, OPE_MIXED = 1 } ope_precision;
 
 /* The discrete operator (paper, Section 2.2 bilinear form a(u,v), discretised
  * by second-order finite differences on the interior nodes of a uniform grid). */
@@ -77,14 +87,17 @@ typedef struct {
   double energy;      /* final energy */
   double drift;       /* final |U^T U - I|_F */
   int64_t inner_iterations; /* total CG iterations */
+  int32_t stalled;    /* OPE_MIXED only: 1 if the residual stopped improving (60 steps without a 10% gain) */
+  int32_t reserved;
 } ope_solve_info;
 
 typedef struct ope_ctx ope_ctx;
 
-/* Create a context for one operator and block width N (1 <= N <= 512,
- * N <= n).  Copies V to the device, allocates the workspace (about six n x N
- * FP64 blocks plus O(N^2) matrices), and binds `stream` (a hipStream_t, or
- * NULL).  precision must be OPE_FP64.  On error *ctx is set to NULL. */
+/* Create a context for one operator and block width N (1 <= N <= 128,
+ * N <= n; larger N returns OPE_EUNSUPPORTED in this build).  Copies V to the
+ * device, allocates the workspace (five n x N blocks in the precision's storage
+ * type plus O(N^2) matrices), and binds `stream` (a hipStream_t, or NULL).
+ * precision is an ope_precision.  On error *ctx is set to NULL. */
 ope_status ope_create(ope_ctx** ctx, const ope_op_desc* op, int64_t N, int32_t precision, void* stream);
 
 /* Release the context and its device memory (synchronises its stream).  NULL is a no-op. */
@@ -97,16 +110,17 @@ const char* ope_status_string(ope_status s);
  * H Y = U is solved by conjugate gradients warm-started at U Lam^{-1} until
  * |u_j - H y_j| <= eta |u_j|, with eta = max(eta_floor, eta_rel * res) and
  * res the outer residual of the current iterate; at most max_iter iterations.
- * Defaults: eta_rel = 1e-2, eta_floor = 1e-12, max_iter = 2000. */
+ * Defaults: eta_rel = 1e-2, eta_floor = 1e-12 (1e-6 for OPE_MIXED), max_iter = 2000. */
 ope_status ope_set_inner(ope_ctx* ctx, double eta_rel, double eta_floor, int32_t max_iter);
 
 /* --- Hot-path building blocks (each is one row of the step) -------------- */
 
 /* Y = H X for n x N device blocks X, Y (Step 1 operator; a(u,v) of Section
- * 2.2).  X and Y must not overlap. */
-ope_status ope_apply_h(ope_ctx* ctx, const double* X, double* Y);
+ * 2.2), in the context's storage type (FP64, or FP32 for OPE_MIXED).  X and Y
+ * must not overlap. */
+ope_status ope_apply_h(ope_ctx* ctx, const void* X, void* Y);
 
-/* Step 1: Y ~= G U = H^{-1} U column by column by conjugate gradients.  Y0 is
+/* Step 1 (OPE_FP64 contexts): Y ~= G U = H^{-1} U column by column by conjugate gradients.  Y0 is
  * an optional device n x N warm start (NULL = zero); Y may equal Y0.  Stops
  * column j when |u_j - H y_j| <= tol |u_j| (recursively updated residual) or
  * after max_iter iterations (then returns OPE_ECG_MAXIT with Y written).
@@ -121,7 +135,7 @@ ope_status ope_source_solve(ope_ctx* ctx, const double* U, double* Y, const doub
 ope_status ope_gram(ope_ctx* ctx, const double* A, int64_t lda, int64_t na,
                     const double* B, int64_t ldb, int64_t nb, int64_t rows, double* out);
 
-/* Steps 2-3 (Section 4.1) for the context's N, in FP64, on the device:
+/* Steps 2-3 (Section 4.1) for the context's N, in FP64, on the device (OPE_FP64 contexts):
  * given S_b = <U, Y> and T = <Y, Y> (N x N device), forms
  *   M = I + tau/2 (S_a - S_b) + tau^2/4 (T - S_a S_b),  S_a = S_b^T,
  * B = M^{-1}, A = 2/tau (I - B) + S_b B, and Z = [I - tau A ; tau B]
@@ -132,28 +146,48 @@ ope_status ope_small_solve(ope_ctx* ctx, const double* S_b, const double* T, dou
                            double* Z, double* A, double* B);
 
 /* Step 4: U <- U Z_1 + Y Z_2 in place, Z = [Z_1; Z_2] (2N x N device, as
- * produced by ope_small_solve).  U and Y are n x N device blocks. */
+ * produced by ope_small_solve).  U and Y are n x N FP64 device blocks (OPE_FP64 contexts). */
 ope_status ope_update(ope_ctx* ctx, double* U, const double* Y, const double* Z);
 
-/* E(U) = 1/2 tr(U^T H U) (eq. (2.3)) into *energy (host).  Synchronises. */
-ope_status ope_energy(ope_ctx* ctx, const double* U, double* energy);
+/* E(U) = 1/2 tr(U^T H U) (eq. (2.3)) into *energy (host), accumulated in FP64;
+ * U in the context's storage type.  Synchronises. */
+ope_status ope_energy(ope_ctx* ctx, const void* U, double* energy);
 
 /* FP64 checks of an iterate (host outputs, each nullable):
  *   *residual = |H U - U Lam|_F / |Lam|_F with Lam = U^T H U,
  *   ritz[0..N) = eigenvalues of Lam, ascending (device Jacobi, FP64),
  *   *drift = |U^T U - I|_F.  Synchronises. */
-ope_status ope_residual(ope_ctx* ctx, const double* U, double* residual, double* ritz, double* drift);
+ope_status ope_residual(ope_ctx* ctx, const void* U, double* residual, double* ritz, double* drift);
 
-/* One step of scheme (4.1) in place on the device block U (n x N, FP64):
- * Steps 1-4 with the inner policy of ope_set_inner.  If info is non-NULL it
+/* One step of scheme (4.1) in place on the device block U (n x N, in the
+ * context's storage type): Steps 1-4 with the inner policy of ope_set_inner.  If info is non-NULL it
  * receives the diagnostics of the iterate entering the step (host struct).
  * On OPE_ENONFINITE or OPE_EPIVOT, U is left unchanged. */
 ope_status ope_step(ope_ctx* ctx, void* U, double tau, ope_step_info* info);
 
 /* Algorithm 1 at fixed step tau: repeat ope_step until the residual of the
- * current iterate is <= res_tol or max_steps steps were taken.  info nullable. */
+ * current iterate is <= res_tol or max_steps steps were taken (or, for
+ * OPE_MIXED, the residual stalls at the FP32 floor).  info nullable. */
 ope_status ope_solve(ope_ctx* ctx, void* U, double tau, double res_tol, int32_t max_steps,
                      ope_solve_info* info);
+
+/* Elementwise precision change of `count` values on the context's stream:
+ * to_double != 0 converts FP32 src to FP64 dst, else FP64 src to FP32 dst
+ * (round to nearest).  Used to hand a mixed-precision iterate to an FP64
+ * context for the finishing steps.  src and dst must not overlap. */
+ope_status ope_convert(ope_ctx* ctx, const void* src, void* dst, int64_t count, int32_t to_double);
+
+/* Mixed-precision building blocks on FP32 device blocks (kind: 0 = FP64
+ * accumulation of FP32 inputs, 1 = FP32 matrix cores, 2 = BF16 inputs with FP32
+ * accumulation):
+ *   ope_gram_f32: out (na x nb, FP64, device) = A^T B over `rows` rows;
+ *   ope_rowmm_f32 (kind 1 or 2): Out = cbeta Cm + ascale (X0 M0 + X1 M1) for
+ *     the context's n x N blocks and N x N FP32 matrices (X1/M1 and Cm
+ *     nullable); Out may equal X0 or Cm. */
+ope_status ope_gram_f32(ope_ctx* ctx, int32_t kind, const float* A, int64_t lda, int64_t na, const float* B,
+                        int64_t ldb, int64_t nb, int64_t rows, double* out);
+ope_status ope_rowmm_f32(ope_ctx* ctx, int32_t kind, const float* X0, const float* M0, const float* X1,
+                         const float* M1, const float* Cm, double cbeta, double ascale, float* Out);
 
 /* --- Launch shape of the stencil / CG sweeps (tuning) --------------------
  * The sweeps march along the slowest grid axis; a work-group covers q passes

@@ -33,6 +33,7 @@ from .scheme import (  # noqa: F401
     generator_matrix,
     steps_1_to_4,
     step_general,
+    step_delta,
     step_cayley_dense,
     step_woodbury,
     small_solve,

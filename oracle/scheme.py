@@ -23,6 +23,9 @@ Functions and the passage each follows:
   ``M = I + tau/2 (S_a - S_b) + tau^2/4 (T - S_a S_b)``, ``B = M^{-1}``,
   ``A = 2/tau (I - B) + S_b B`` with ``S_a = Y^T U``, ``S_b = U^T Y``,
   ``T = Y^T Y``.  Identical to ``steps_1_to_4`` when ``S_a = S_b``.
+* ``step_delta`` -- the same step as a correction of U (Step 3 substituted
+  into Step 4, ``T - S_a S_b`` rewritten through ``P = Y - U S_b``); equal to
+  ``step_general`` for any U and Y.
 * ``step_woodbury`` -- (4.1) written with ``L_U = W J W^T``, ``W = [U, Y]``,
   and inverted through the 2N x 2N capacitance matrix (push-through identity).
 * ``energy``, ``residual``, ``ritz_values``, ``paper_eigenvalues``,
@@ -102,6 +105,26 @@ def step_general(U: np.ndarray, Y: np.ndarray, tau: float) -> Dict[str, np.ndarr
     A, B, M = small_solve(S_a, T, tau, S_b=S_b)
     U_next = U - tau * U @ A + tau * Y @ B
     return {"U": U_next, "A": A, "B": B, "S_a": S_a, "S_b": S_b, "T": T, "M": M}
+
+
+def step_delta(U: np.ndarray, Y: np.ndarray, tau: float) -> Dict[str, np.ndarray]:
+    """Steps 2-4 written as a correction of U (the form the reduced-precision
+    path evaluates).  With ``S_b = <U,Y>``, ``C = <U,U>`` and ``P = Y - U S_b``,
+    ``T - S_a S_b = P^T P - S_b^T (C - I) S_b`` and Step 3 turns Step 4 into
+    ``U' = U - 2 U (I - B) + tau P B``.  Algebraically identical to
+    ``step_general`` for any U and Y; both correction terms vanish at a fixed
+    point, which is what lets them be evaluated in low precision."""
+    N = U.shape[1]
+    I = np.eye(N)
+    S_b = inner(U, Y)
+    P = Y - U @ S_b
+    C = inner(U, U)
+    Tp = inner(P, P) - S_b.T @ (C - I) @ S_b
+    M = I + 0.5 * tau * (S_b.T - S_b) + 0.25 * tau * tau * Tp
+    B = np.linalg.solve(M, I)
+    Z1 = -2.0 * (I - B)
+    Z2 = tau * B
+    return {"U": U + U @ Z1 + P @ Z2, "B": B, "S_b": S_b, "P": P, "Tp": Tp, "Z1": Z1, "Z2": Z2, "M": M}
 
 
 def step_cayley_dense(U: np.ndarray, Y: np.ndarray, tau: float) -> np.ndarray:

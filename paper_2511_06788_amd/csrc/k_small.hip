@@ -90,7 +90,8 @@ __device__ void store_own(double* __restrict__ M, uint32_t N, const double (&w)[
 // Energy, drift, |Lam|_F, column norms, and Lam^{-1} for the warm start.
 __global__ __launch_bounds__(SW) void k_prep_small(const double* __restrict__ C, const double* __restrict__ Lam,
                                                    double* __restrict__ Linv, double* __restrict__ cnorm2,
-                                                   uint32_t N, OpeScalars* __restrict__ sc) {
+                                                   uint32_t N, OpeScalars* __restrict__ sc, float* __restrict__ Lam32,
+                                                   float* __restrict__ Linv32) {
   __shared__ double red[SW];
   __shared__ double fcol[256], rowk[256];
   __shared__ int bad;
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(SW) void k_prep_small(const double* __restrict__ C,
       const double lij = Lam[(uint64_t)i * N + o.j], lji = Lam[(uint64_t)o.j * N + i];
       const double cij = C[(uint64_t)i * N + o.j] - (i == o.j ? 1.0 : 0.0);
       w[r] = 0.5 * (lij + lji);
+      if (Lam32) Lam32[(uint64_t)i * N + o.j] = (float)lij;
       lf += lij * lij;
       dr += cij * cij;
       if (i == o.j) {
@@ -120,6 +122,13 @@ __global__ __launch_bounds__(SW) void k_prep_small(const double* __restrict__ C,
   dr = wg_sum(dr, red);
   gj_invert(w, N, fcol, rowk, &bad);
   store_own(Linv, N, w);
+  if (Linv32) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const uint32_t i = o.row(r);
+      if (i < N && o.j < N) Linv32[(uint64_t)i * N + o.j] = (float)w[r];
+    }
+  }
   if (threadIdx.x == 0) {
     sc->energy = 0.5 * e;
     sc->lam_fro = sqrt(lf);
@@ -246,6 +255,86 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
   if (threadIdx.x == 0 && bad && sc->err == 0) sc->err = OPE_EPIVOT;
 }
 
+// Mixed-precision Steps 2-3 in delta form.  With P = Y - U S_b and
+// C = <U,U>, T - S_a S_b = P^T P - S_b^T (C - I) S_b, so the Step-2 matrix is
+// M = I + tau/2 (S_a - S_b) + tau^2/4 (P^T P - S_b^T (C - I) S_b), B = M^{-1},
+// and Step 4 is U' = U + U Z1 + P Z2 with Z1 = -2 (I - B), Z2 = tau B: the
+// same map as the FP64 step for any U, written so that both products vanish
+// at a fixed point (their BF16 rounding vanishes with them).  The
+// S_b^T (C - I) S_b term keeps the step orthogonality-preserving when the
+// FP32 iterate has drifted; without it the drift is amplified at large tau.
+// Z is written in FP32 (2N x N) for the BF16 product; Wsm is N x N scratch.
+__global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restrict__ Sb,
+                                                          const double* __restrict__ Tp,
+                                                          const double* __restrict__ C, double tau, uint32_t N,
+                                                          double* __restrict__ Wsm, float* __restrict__ Z32,
+                                                          OpeScalars* __restrict__ sc) {
+  __shared__ double fcol[256], rowk[256];
+  __shared__ int bad;
+  const Own o;
+  if (threadIdx.x == 0) bad = 0;
+  const uint32_t jj = o.j < N ? o.j : 0u;
+  // Wsm = (C - I) S_b
+  double acc[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
+  for (uint32_t l = 0; l < N; ++l) {
+    const double slj = Sb[(uint64_t)l * N + jj];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const uint32_t k = o.row(r) < N ? o.row(r) : 0u;
+      acc[r] += (C[(uint64_t)k * N + l] - (k == l ? 1.0 : 0.0)) * slj;
+    }
+  }
+  store_own(Wsm, N, acc);
+  __syncthreads();
+  // Q = S_b^T Wsm
+  double qv[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) qv[r] = 0.0;
+  for (uint32_t k = 0; k < N; ++k) {
+    const double wkj = Wsm[(uint64_t)k * N + jj];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const uint32_t i = o.row(r) < N ? o.row(r) : 0u;
+      qv[r] += Sb[(uint64_t)k * N + i] * wkj;
+    }
+  }
+  double w[RPT];
+  const double ht = 0.5 * tau, qt = 0.25 * tau * tau;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const uint32_t i = o.row(r);
+    if (i < N && o.j < N) {
+      const double sb = Sb[(uint64_t)i * N + o.j], sa = Sb[(uint64_t)o.j * N + i];
+      w[r] = (i == o.j ? 1.0 : 0.0) + ht * (sa - sb) + qt * (Tp[(uint64_t)i * N + o.j] - qv[r]);
+    } else {
+      w[r] = 0.0;
+    }
+  }
+  gj_invert(w, N, fcol, rowk, &bad);
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const uint32_t i = o.row(r);
+    if (i < N && o.j < N) {
+      const double dij = (i == o.j ? 1.0 : 0.0);
+      Z32[(uint64_t)i * N + o.j] = (float)(-2.0 * (dij - w[r]));
+      Z32[(uint64_t)(N + i) * N + o.j] = (float)(tau * w[r]);
+    }
+  }
+  if (threadIdx.x == 0 && bad && sc->err == 0) sc->err = OPE_EPIVOT;
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, uint64_t count) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < count; e += (uint64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+__global__ void k_to_f64(const float* __restrict__ src, double* __restrict__ dst, uint64_t count) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < count; e += (uint64_t)gridDim.x * blockDim.x)
+    dst[e] = (double)src[e];
+}
+
 // Cyclic Jacobi (round-robin parallel ordering) on a symmetric N x N matrix
 // held in global workspace; eigenvalues sorted ascending into evals.
 __global__ __launch_bounds__(SW) void k_jacobi(const double* __restrict__ Asrc, double* __restrict__ W,
@@ -333,7 +422,31 @@ __global__ __launch_bounds__(SW) void k_jacobi(const double* __restrict__ Asrc, 
 hipError_t launch_prep_small(ope_ctx* c) {
   ProfScope ps(c, OPE_KERNEL_SMALL);
   hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(SW), 0, c->stream, c->C, c->Lam, c->Linv, c->cnorm2, (uint32_t)c->N,
-                     c->sc);
+                     c->sc, c->Lam32, c->Linv32);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_solve_delta(ope_ctx* c, const double* Sb, const double* Tperp, double tau) {
+  ProfScope ps(c, OPE_KERNEL_SMALL);
+  hipLaunchKernelGGL(k_small_solve_delta, dim3(1), dim3(SW), 0, c->stream, Sb, Tperp, c->C, tau, (uint32_t)c->N,
+                     c->Wsm, c->Z32, c->sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_to_f32(ope_ctx* c, const double* src, float* dst, int64_t count) {
+  hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, c->stream, src, dst, (uint64_t)count);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(ope_ctx* c, const void* src, void* dst, int64_t count, int to_double) {
+  const uint64_t n = (uint64_t)count;
+  uint64_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  if (to_double)
+    hipLaunchKernelGGL(k_to_f64, dim3((uint32_t)grid), dim3(256), 0, c->stream, (const float*)src, (double*)dst, n);
+  else
+    hipLaunchKernelGGL(k_to_f32, dim3((uint32_t)grid), dim3(256), 0, c->stream, (const double*)src, (float*)dst, n);
   return hipGetLastError();
 }
 

@@ -25,48 +25,32 @@
 
 namespace {
 
-template <int VW>
-__device__ __forceinline__ void ldv(const double* __restrict__ base, uint64_t off, double (&v)[VW]) {
-  if constexpr (VW == 2) {
-    const double2 t = *reinterpret_cast<const double2*>(base + off);
-    v[0] = t.x;
-    v[1] = t.y;
-  } else {
-    v[0] = base[off];
-  }
+// 16-byte (or narrower) row chunk of VW elements of type T.
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) RowVec {
+  T v[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ void ldv(const T* __restrict__ base, uint64_t off, T (&v)[VW]) {
+  const RowVec<T, VW> t = *reinterpret_cast<const RowVec<T, VW>*>(base + off);
+#pragma unroll
+  for (int k = 0; k < VW; ++k) v[k] = t.v[k];
 }
 
-template <int VW>
-__device__ __forceinline__ void stv(double* __restrict__ base, uint64_t off, const double (&v)[VW]) {
-  if constexpr (VW == 2) {
-    *reinterpret_cast<double2*>(base + off) = make_double2(v[0], v[1]);
-  } else {
-    base[off] = v[0];
-  }
+template <typename T, int VW>
+__device__ __forceinline__ void stv(T* __restrict__ base, uint64_t off, const T (&v)[VW]) {
+  RowVec<T, VW> t;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) t.v[k] = v[k];
+  *reinterpret_cast<RowVec<T, VW>*>(base + off) = t;
 }
 
 // Store that is not kept in the caches (the rows are not read again by this sweep).
-template <int VW>
-__device__ __forceinline__ void stv_nt(double* __restrict__ base, uint64_t off, const double (&v)[VW]) {
+template <typename T, int VW>
+__device__ __forceinline__ void stv_nt(T* __restrict__ base, uint64_t off, const T (&v)[VW]) {
 #pragma unroll
   for (int k = 0; k < VW; ++k) __builtin_nontemporal_store(v[k], base + off + k);
-}
-
-// Search direction value at element offset `off`: r + beta * p_old (r on the first iteration).
-template <int VW, bool FIRST>
-__device__ __forceinline__ void dirv(const double* __restrict__ r, const double* __restrict__ pold,
-                                     uint64_t off, const double (&b)[VW], double (&out)[VW]) {
-  double rv[VW];
-  ldv<VW>(r, off, rv);
-  if constexpr (FIRST) {
-#pragma unroll
-    for (int v = 0; v < VW; ++v) out[v] = rv[v];
-  } else {
-    double pv[VW];
-    ldv<VW>(pold, off, pv);
-#pragma unroll
-    for (int v = 0; v < VW; ++v) out[v] = rv[v] + b[v] * pv[v];
-  }
 }
 
 __device__ __forceinline__ bool any_active(const int32_t* __restrict__ active, uint32_t N) {
@@ -113,17 +97,17 @@ __device__ __forceinline__ void wg_colsum(double* red, const double (&acc)[VW], 
 //   SW_UPDATE  y += alpha p, r' = r - alpha H p, p written, rho'_j += r'_j^2
 enum { SW_APPLY = 0, SW_PAP = 1, SW_UPDATE = 2 };
 
-template <int VW, int Q, int MODE, bool FIRST>
-__global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0, const double* __restrict__ F1,
-                                                  double* __restrict__ O0, double* __restrict__ O1,
-                                                  double* __restrict__ Yv, const double* __restrict__ alpha,
+template <typename T, int VW, int Q, int MODE, bool FIRST>
+__global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, const T* __restrict__ F1,
+                                                  T* __restrict__ O0, T* __restrict__ O1,
+                                                  T* __restrict__ Yv, const double* __restrict__ alpha,
                                                   const double* __restrict__ beta, const int32_t* __restrict__ active,
-                                                  const double* __restrict__ diag, OpeGrid g, MarchShape ms,
+                                                  const T* __restrict__ diag, OpeGrid g, MarchShape ms,
                                                   uint32_t N, uint32_t NV, double* __restrict__ part,
                                                   OpeScalars* __restrict__ sc) {
   constexpr bool TWO = (MODE != SW_APPLY) && !FIRST;   // field is r + beta p_old (two loads per value)
   constexpr bool UPD = (MODE == SW_UPDATE);
-  __shared__ double lds[2 * Q * OPE_WG * VW];
+  __shared__ T lds[2 * Q * OPE_WG * VW];
   __shared__ double red[OPE_WG * VW];
   if (MODE != SW_APPLY) {
     if (!any_active(active, N)) return;
@@ -155,13 +139,15 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
   const bool side_hi = ms.has_side && line + 1 < ms.lines;
   const uint64_t sstride = (uint64_t)ms.side_stride * N;
 
-  double b[VW], a[VW], acc[VW];
+  T b[VW], a[VW];
+  double acc[VW];
 #pragma unroll
   for (int v = 0; v < VW; ++v) {
-    b[v] = (TWO && lane_ok) ? beta[coff + v] : 0.0;
-    a[v] = (UPD && lane_ok) ? alpha[coff + v] : 0.0;
+    b[v] = (TWO && lane_ok) ? (T)beta[coff + v] : T(0);
+    a[v] = (UPD && lane_ok) ? (T)alpha[coff + v] : T(0);
     acc[v] = 0.0;
   }
+  const T cx = (T)g.cx, cs = (T)ms.cs, cm = (T)ms.cm;
   uint32_t xq[Q];
   bool okq[Q];
 #pragma unroll
@@ -173,38 +159,38 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
   auto off_of = [&](uint32_t x, uint32_t z) -> uint64_t {
     return ((uint64_t)x + lbase + (uint64_t)z * ms.march_stride) * N + coff;
   };
-  auto zero = [](double (&o)[VW]) {
+  auto zero = [](T (&o)[VW]) {
 #pragma unroll
-    for (int v = 0; v < VW; ++v) o[v] = 0.0;
+    for (int v = 0; v < VW; ++v) o[v] = T(0);
   };
   // raw loads of one field value (r and p_old, or x); combined later
-  auto ld_raw = [&](bool ok, uint64_t o, double (&r)[VW], double (&po)[VW]) {
+  auto ld_raw = [&](bool ok, uint64_t o, T (&r)[VW], T (&po)[VW]) {
     if (ok) {
-      ldv<VW>(F0, o, r);
-      if constexpr (TWO) ldv<VW>(F1, o, po);
+      ldv<T, VW>(F0, o, r);
+      if constexpr (TWO) ldv<T, VW>(F1, o, po);
     } else {
       zero(r);
       if constexpr (TWO) zero(po);
     }
   };
-  auto comb = [&](const double (&r)[VW], const double (&po)[VW], double (&out)[VW]) {
+  auto comb = [&](const T (&r)[VW], const T (&po)[VW], T (&out)[VW]) {
 #pragma unroll
     for (int v = 0; v < VW; ++v) out[v] = TWO ? r[v] + b[v] * po[v] : r[v];
   };
 
   // pipeline registers (per pass q)
-  double pm[Q][VW], pz[Q][VW], p1[Q][VW];          // field at z-1, z, z+1
-  double rz[Q][VW], r1[Q][VW];                      // r at z, z+1 (UPDATE)
-  double smz[Q][VW], spz[Q][VW];                    // side neighbours at z
-  double dz[Q], yz[Q][VW];                          // diagonal and y at z
-  double c2r[Q][VW], c2p[Q][VW];                    // in flight: centre of z+2
-  double s1r[Q][VW], s1p[Q][VW], t1r[Q][VW], t1p[Q][VW];  // in flight: side rows of z+1
-  double d1[Q], y1[Q][VW];                          // in flight: diagonal, y of z+1
+  T pm[Q][VW], pz[Q][VW], p1[Q][VW];               // field at z-1, z, z+1
+  T rz[Q][VW], r1[Q][VW];                           // r at z, z+1 (UPDATE)
+  T smz[Q][VW], spz[Q][VW];                         // side neighbours at z
+  T dz[Q], yz[Q][VW];                               // diagonal and y at z
+  T c2r[Q][VW], c2p[Q][VW];                         // in flight: centre of z+2
+  T s1r[Q][VW], s1p[Q][VW], t1r[Q][VW], t1p[Q][VW];  // in flight: side rows of z+1
+  T d1[Q], y1[Q][VW];                               // in flight: diagonal, y of z+1
 
   // prologue: everything for plane z0 and the centre of z0+1
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    double tr[VW], tp[VW];
+    T tr[VW], tp[VW];
     const bool ok = okq[q] && z0 < z1;
     ld_raw(ok && z0 > 0, ok && z0 > 0 ? off_of(xq[q], z0 - 1) : 0, tr, tp);
     comb(tr, tp, pm[q]);
@@ -221,9 +207,9 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
     comb(tr, tp, smz[q]);
     ld_raw(ok && side_hi, o + (side_hi ? sstride : 0), tr, tp);
     comb(tr, tp, spz[q]);
-    dz[q] = ok ? diag[o / N] : 0.0;
+    dz[q] = ok ? diag[o / N] : T(0);
     if constexpr (UPD) {
-      if (ok) ldv<VW>(Yv, o, yz[q]);
+      if (ok) ldv<T, VW>(Yv, o, yz[q]);
       else zero(yz[q]);
     }
   }
@@ -239,14 +225,14 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
       const uint64_t o1 = (ok && n1) ? off_of(xq[q], z + 1) : 0;
       ld_raw(ok && n1 && side_lo, o1 - (ok && n1 && side_lo ? sstride : 0), s1r[q], s1p[q]);
       ld_raw(ok && n1 && side_hi, o1 + (ok && n1 && side_hi ? sstride : 0), t1r[q], t1p[q]);
-      d1[q] = (ok && n1) ? diag[o1 / N] : 0.0;
+      d1[q] = (ok && n1) ? diag[o1 / N] : T(0);
       if constexpr (UPD) {
-        if (ok && n1) ldv<VW>(Yv, o1, y1[q]);
+        if (ok && n1) ldv<T, VW>(Yv, o1, y1[q]);
         else zero(y1[q]);
       }
     }
     // stage plane z for the x neighbours
-    double* buf = lds + (z & 1u) * (Q * OPE_WG * VW);
+    T* buf = lds + (z & 1u) * (Q * OPE_WG * VW);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -258,7 +244,7 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
       const uint32_t x = xq[q];
       const uint32_t xi = q * ms.pp + slot;
       const uint64_t o = off_of(x, z);
-      double xm[VW], xp[VW];
+      T xm[VW], xp[VW];
       zero(xm);
       zero(xp);
       if (x > 0) {
@@ -266,7 +252,7 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
 #pragma unroll
           for (int v = 0; v < VW; ++v) xm[v] = buf[((xi - 1) * ms.ncv + cv) * VW + v];
         } else {
-          double tr[VW], tp[VW];
+          T tr[VW], tp[VW];
           ld_raw(true, o - N, tr, tp);
           comb(tr, tp, xm);
         }
@@ -276,38 +262,37 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const double* __restrict__ F0,
 #pragma unroll
           for (int v = 0; v < VW; ++v) xp[v] = buf[((xi + 1) * ms.ncv + cv) * VW + v];
         } else {
-          double tr[VW], tp[VW];
+          T tr[VW], tp[VW];
           ld_raw(true, o + N, tr, tp);
           comb(tr, tp, xp);
         }
       }
-      double hx[VW];
+      T hx[VW];
 #pragma unroll
       for (int v = 0; v < VW; ++v)
-        hx[v] = dz[q] * pz[q][v] -
-                (g.cx * (xm[v] + xp[v]) + ms.cs * (smz[q][v] + spz[q][v]) + ms.cm * (pm[q][v] + p1[q][v]));
+        hx[v] = dz[q] * pz[q][v] - (cx * (xm[v] + xp[v]) + cs * (smz[q][v] + spz[q][v]) + cm * (pm[q][v] + p1[q][v]));
       if constexpr (MODE == SW_APPLY) {
-        if (ms.nt) stv_nt<VW>(O0, o, hx);
-        else stv<VW>(O0, o, hx);
+        if (ms.nt) stv_nt<T, VW>(O0, o, hx);
+        else stv<T, VW>(O0, o, hx);
       } else if constexpr (MODE == SW_PAP) {
 #pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] += pz[q][v] * hx[v];
+        for (int v = 0; v < VW; ++v) acc[v] += (double)pz[q][v] * (double)hx[v];
       } else {
-        double yv[VW], rnew[VW];
+        T yv[VW], rnew[VW];
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
           yv[v] = yz[q][v] + a[v] * pz[q][v];
           rnew[v] = rz[q][v] - a[v] * hx[v];
-          acc[v] += rnew[v] * rnew[v];
+          acc[v] += (double)rnew[v] * (double)rnew[v];
         }
         if (ms.nt) {
-          stv_nt<VW>(Yv, o, yv);
-          stv_nt<VW>(O0, o, rnew);
-          stv_nt<VW>(O1, o, pz[q]);
+          stv_nt<T, VW>(Yv, o, yv);
+          stv_nt<T, VW>(O0, o, rnew);
+          stv_nt<T, VW>(O1, o, pz[q]);
         } else {
-          stv<VW>(Yv, o, yv);
-          stv<VW>(O0, o, rnew);
-          stv<VW>(O1, o, pz[q]);
+          stv<T, VW>(Yv, o, yv);
+          stv<T, VW>(O0, o, rnew);
+          stv<T, VW>(O1, o, pz[q]);
         }
       }
     }
@@ -370,10 +355,10 @@ __global__ __launch_bounds__(OPE_WG) void k_resid0(const double* __restrict__ U,
     for (uint32_t p = p0 + lp; p < p1; p += pp) {
       const uint64_t off = (uint64_t)p * N + (uint64_t)cv * VW;
       double u[VW], r[VW];
-      ldv<VW>(U, off, u);
+      ldv<double, VW>(U, off, u);
       if (HY) {
         double t[VW];
-        ldv<VW>(HY, off, t);
+        ldv<double, VW>(HY, off, t);
 #pragma unroll
         for (int v = 0; v < VW; ++v) r[v] = u[v] - t[v];
       } else {
@@ -383,9 +368,9 @@ __global__ __launch_bounds__(OPE_WG) void k_resid0(const double* __restrict__ U,
           r[v] = u[v];
           z[v] = 0.0;
         }
-        stv<VW>(y, off, z);
+        stv<double, VW>(y, off, z);
       }
-      stv<VW>(R, off, r);
+      stv<double, VW>(R, off, r);
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
         ar[v] += r[v] * r[v];
@@ -471,28 +456,41 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int VW, int Q, int MODE, bool FIRST>
-static void launch_march_t(ope_ctx* c, const double* F0, const double* F1, double* O0, double* O1, double* Yv) {
-  const uint32_t N = (uint32_t)c->N, NV = N / c->vw;
+template <typename T, int VW, int Q, int MODE, bool FIRST>
+static void launch_march_t(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag) {
+  const uint32_t N = (uint32_t)c->N, NV = N / VW;
   const MarchShape& ms = c->ms;
   const uint32_t grid = ms.lines * ms.nxs * ms.cc * ms.mc;
-  hipLaunchKernelGGL((k_march<VW, Q, MODE, FIRST>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0, O1, Yv,
-                     c->alpha, c->beta, c->active, c->diag, c->g, ms, N, NV, c->part, c->sc);
+  hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0, O1, Yv,
+                     c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
 }
 
-template <int VW, int MODE, bool FIRST>
-static void launch_march_q(ope_ctx* c, const double* F0, const double* F1, double* O0, double* O1, double* Yv) {
+template <typename T, int VW, int MODE, bool FIRST>
+static void launch_march_q(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag) {
   switch (c->ms.q) {
-    case 1: launch_march_t<VW, 1, MODE, FIRST>(c, F0, F1, O0, O1, Yv); break;
-    case 2: launch_march_t<VW, 2, MODE, FIRST>(c, F0, F1, O0, O1, Yv); break;
-    default: launch_march_t<VW, 4, MODE, FIRST>(c, F0, F1, O0, O1, Yv); break;
+    case 1: launch_march_t<T, VW, 1, MODE, FIRST>(c, F0, F1, O0, O1, Yv, diag); break;
+    case 2: launch_march_t<T, VW, 2, MODE, FIRST>(c, F0, F1, O0, O1, Yv, diag); break;
+    default: launch_march_t<T, VW, 4, MODE, FIRST>(c, F0, F1, O0, O1, Yv, diag); break;
   }
 }
 
 template <int MODE, bool FIRST>
-static hipError_t launch_march(ope_ctx* c, const double* F0, const double* F1, double* O0, double* O1, double* Yv) {
-  if (c->vw == 2) launch_march_q<2, MODE, FIRST>(c, F0, F1, O0, O1, Yv);
-  else launch_march_q<1, MODE, FIRST>(c, F0, F1, O0, O1, Yv);
+static hipError_t launch_march(ope_ctx* c, const void* F0, const void* F1, void* O0, void* O1, void* Yv) {
+  if (c->prec == OPE_FP64) {
+    using T = double;
+    if (c->vw == 2)
+      launch_march_q<T, 2, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag);
+    else
+      launch_march_q<T, 1, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag);
+  } else {
+    using T = float;
+    if (c->vw == 4)
+      launch_march_q<T, 4, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32);
+    else if (c->vw == 2)
+      launch_march_q<T, 2, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32);
+    else
+      launch_march_q<T, 1, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32);
+  }
   return hipGetLastError();
 }
 
@@ -502,7 +500,7 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt) {
   ms.nt = nt ? 1u : 0u;
   const OpeGrid& g = c->g;
   const uint32_t NV = (uint32_t)(c->N / c->vw);
-  // 8 vector columns: one 128-byte line per grid point and work-group for FP64 pairs
+  // 8 vector columns of 16 bytes: one 128-byte line per grid point and work-group
   ms.ncv = NV < 8u ? NV : 8u;
   ms.pp = OPE_WG / ms.ncv;
   const uint32_t qcap = q_max > 0 ? (uint32_t)q_max : 2u;
@@ -543,19 +541,19 @@ int64_t march_rows(const ope_ctx* c) {
   return (int64_t)c->ms.lines * c->ms.nxs * c->ms.mc;
 }
 
-hipError_t launch_apply_h(ope_ctx* c, const double* X, double* Yo) {
+hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Yo) {
   ProfScope ps(c, OPE_KERNEL_STENCIL);
   return launch_march<SW_APPLY, false>(c, X, nullptr, Yo, nullptr, nullptr);
 }
 
-hipError_t launch_cg_pap(ope_ctx* c, const double* r, const double* pold, int first) {
+hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, int first) {
   ProfScope ps(c, OPE_KERNEL_CG_SWEEP_A);
   if (first) return launch_march<SW_PAP, true>(c, r, pold, nullptr, nullptr, nullptr);
   return launch_march<SW_PAP, false>(c, r, pold, nullptr, nullptr, nullptr);
 }
 
-hipError_t launch_cg_update(ope_ctx* c, const double* r, const double* pold, double* rnew, double* pnew,
-                            double* y, int first) {
+hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* pold, void* rnew, void* pnew,
+                            void* y, int first) {
   ProfScope ps(c, OPE_KERNEL_CG_SWEEP_B);
   if (first) return launch_march<SW_UPDATE, true>(c, r, pold, rnew, pnew, y);
   return launch_march<SW_UPDATE, false>(c, r, pold, rnew, pnew, y);

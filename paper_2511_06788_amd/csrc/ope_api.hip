@@ -34,11 +34,16 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc((void**)p, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
 }
 
+hipError_t balloc(void** p, size_t bytes) {
+  *p = nullptr;
+  return hipMalloc(p, bytes > 0 ? bytes : 1);
+}
+
 void free_ctx(ope_ctx* c) {
   if (!c) return;
-  void* dptrs[] = {c->diag, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T, c->Z,
-                   c->A, c->B, c->Wsm, c->alpha, c->beta, c->rho, c->target, c->cnorm2, c->rcol, c->rho0,
-                   c->active, c->part, c->stage, c->counters, c->sc};
+  void* dptrs[] = {c->diag, c->diag32, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T,
+                   c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
+                   c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->counters, c->sc};
   for (void* p : dptrs)
     if (p) (void)hipFree(p);
   if (c->hsc) (void)hipHostFree(c->hsc);
@@ -56,14 +61,27 @@ ope_status sync_and_read_scalars(ope_ctx* c) {
 
 // HU, Grams C and Lam, the small prep kernel (energy, drift, Lam^{-1}) and the
 // residual R = HU - U Lam written over HU with its column norms in c->rcol.
-ope_status phase_residual(ope_ctx* c, const double* U) {
+// FP64: everything in FP64.  Mixed: FP32 stencil, C and Lam accumulated in
+// FP64 on the matrix cores (energy and drift stay FP64), R in FP32.
+ope_status phase_residual(ope_ctx* c, const void* Uv) {
   const int N = (int)c->N;
   int64_t np = 0;
-  HIPCHK(launch_apply_h(c, U, c->HU));
-  HIPCHK(launch_gram(c, U, N, N, U, N, N, c->n, c->C));
-  HIPCHK(launch_gram(c, U, N, N, c->HU, N, N, c->n, c->Lam));
-  HIPCHK(launch_prep_small(c));
-  HIPCHK(launch_rowmm(c, U, c->Lam, nullptr, nullptr, c->HU, 1.0, -1.0, c->HU, 1, 0, &np));
+  HIPCHK(launch_apply_h(c, Uv, c->HU));
+  if (c->prec == OPE_FP64) {
+    const double* U = (const double*)Uv;
+    double* HU = (double*)c->HU;
+    HIPCHK(launch_gram(c, U, N, N, U, N, N, c->n, c->C));
+    HIPCHK(launch_gram(c, U, N, N, HU, N, N, c->n, c->Lam));
+    HIPCHK(launch_prep_small(c));
+    HIPCHK(launch_rowmm(c, U, c->Lam, nullptr, nullptr, HU, 1.0, -1.0, HU, 1, 0, &np));
+  } else {
+    const float* U = (const float*)Uv;
+    float* HU = (float*)c->HU;
+    HIPCHK(launch_gram_f32(c, MK_F64, U, N, N, U, N, N, c->n, c->C));
+    HIPCHK(launch_gram_f32(c, MK_F64, U, N, N, HU, N, N, c->n, c->Lam));
+    HIPCHK(launch_prep_small(c));
+    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Lam32, nullptr, nullptr, HU, 1.0, -1.0, HU, 1, 0, &np));
+  }
   HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rcol, RED_PLAIN));
   return OPE_OK;
 }
@@ -71,10 +89,10 @@ ope_status phase_residual(ope_ctx* c, const double* U) {
 // CG iterations on H Y = U from the state prepared in rho/target/active, with
 // r in c->Rb[0]; returns the iteration count in *iters.
 ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
-  double* r_cur = c->Rb[0];
-  double* r_nxt = c->Rb[1];
-  double* p_old = c->HU;     // never read on the first iteration
-  double* p_new = c->Pb;
+  void* r_cur = c->Rb[0];
+  void* r_nxt = c->Rb[1];
+  void* p_old = c->HU;     // never read on the first iteration
+  void* p_new = c->Pb;
   const int N = (int)c->N;
   int it = 0;
   bool done = false;
@@ -84,7 +102,7 @@ ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) 
     HIPCHK(launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA));
     HIPCHK(launch_cg_update(c, r_cur, p_old, r_nxt, p_new, c->Y, first));
     HIPCHK(launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA));
-    double* t = r_cur;
+    void* t = r_cur;
     r_cur = r_nxt;
     r_nxt = t;
     t = p_old;
@@ -107,32 +125,78 @@ ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) 
   return OPE_OK;
 }
 
-// One step (or, with res_tol >= 0, the convergence test of Algorithm 1 and a
-// step if the residual is still above res_tol).
-ope_status run_step(ope_ctx* c, double* U, double tau, ope_step_info* info, double res_tol, bool* converged) {
+void fill_info(ope_ctx* c, ope_step_info* info, int32_t iters, ope_status st) {
+  if (!info) return;
+  info->energy = c->hsc->energy;
+  info->residual = c->hsc->residual;
+  info->drift = c->hsc->drift;
+  info->inner_iterations = iters;
+  info->status = st;
+}
+
+// Warm start of Step 1 (Y = U Lam^{-1}, r = -R Lam^{-1} = U - H Y) and the CG
+// start state; R is in c->HU.
+ope_status phase_warm_start(ope_ctx* c, const void* Uv) {
   const int N = (int)c->N;
   int64_t np = 0;
+  if (c->prec == OPE_FP64) {
+    HIPCHK(launch_rowmm(c, (const double*)Uv, c->Linv, nullptr, nullptr, nullptr, 0.0, 1.0, (double*)c->Y, 0, 0, &np));
+    HIPCHK(launch_rowmm(c, (const double*)c->HU, c->Linv, nullptr, nullptr, nullptr, 0.0, -1.0, (double*)c->Rb[0], 1,
+                        0, &np));
+  } else {
+    HIPCHK(launch_rowmm_f32(c, MK_F32, (const float*)Uv, c->Linv32, nullptr, nullptr, nullptr, 0.0, 1.0,
+                            (float*)c->Y, 0, 0, &np));
+    HIPCHK(launch_rowmm_f32(c, MK_F32, (const float*)c->HU, c->Linv32, nullptr, nullptr, nullptr, 0.0, -1.0,
+                            (float*)c->Rb[0], 1, 0, &np));
+  }
+  HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rho0, RED_PLAIN));
+  HIPCHK(launch_cg_setup(c, c->rho0));
+  return OPE_OK;
+}
+
+// Steps 2-4 after Step 1 (Y in c->Y).
+ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
+  const int N = (int)c->N;
+  const size_t NN = (size_t)N * N;
+  int64_t np = 0;
+  if (c->prec == OPE_FP64) {
+    double* U = (double*)Uv;
+    const double* Y = (const double*)c->Y;
+    HIPCHK(launch_gram(c, U, N, N, Y, N, N, c->n, c->Sb));
+    HIPCHK(launch_gram(c, Y, N, N, Y, N, N, c->n, c->T));
+    HIPCHK(launch_small_solve(c, c->Sb, c->T, tau, c->Z, c->A, c->B));
+    HIPCHK(launch_rowmm(c, U, c->Z, Y, c->Z + NN, nullptr, 0.0, 1.0, U, 0, 1, &np));
+  } else {
+    // S_b = U^T Y (FP32 matrix cores), P = Y - U S_b (FP32), T_perp = P^T P
+    // (BF16, FP32 accumulation), FP64 small solve, U += U Z1 + P Z2 (BF16).
+    float* U = (float*)Uv;
+    const float* Y = (const float*)c->Y;
+    float* P = (float*)c->HU;
+    HIPCHK(launch_gram_f32(c, MK_F32, U, N, N, Y, N, N, c->n, c->Sb));
+    HIPCHK(launch_small_to_f32(c, c->Sb, c->Sb32, (int64_t)NN));
+    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Sb32, nullptr, nullptr, Y, 1.0, -1.0, P, 0, 0, &np));
+    HIPCHK(launch_gram_f32(c, MK_BF16, P, N, N, P, N, N, c->n, c->T));
+    HIPCHK(launch_small_solve_delta(c, c->Sb, c->T, tau));
+    HIPCHK(launch_rowmm_f32(c, MK_BF16, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, 1, &np));
+  }
+  return OPE_OK;
+}
+
+// One step (or, with res_tol >= 0, the convergence test of Algorithm 1 and a
+// step if the residual is still above res_tol).
+ope_status run_step(ope_ctx* c, void* U, double tau, ope_step_info* info, double res_tol, bool* converged) {
   if (converged) *converged = false;
   ope_status st = phase_residual(c, U);
   if (st != OPE_OK) return st;
-  // warm start: Y = U Lam^{-1}, r = -R Lam^{-1} = U - H Y
-  HIPCHK(launch_rowmm(c, U, c->Linv, nullptr, nullptr, nullptr, 0.0, 1.0, c->Y, 0, 0, &np));
-  HIPCHK(launch_rowmm(c, c->HU, c->Linv, nullptr, nullptr, nullptr, 0.0, -1.0, c->Rb[0], 1, 0, &np));
-  HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rho0, RED_PLAIN));
-  HIPCHK(launch_cg_setup(c, c->rho0));
+  st = phase_warm_start(c, U);
+  if (st != OPE_OK) return st;
   if (res_tol >= 0.0) {
     st = sync_and_read_scalars(c);
     if (st != OPE_OK) return st;
     if (c->hsc->err != 0) return (ope_status)c->hsc->err;
     if (c->hsc->residual <= res_tol) {
       if (converged) *converged = true;
-      if (info) {
-        info->energy = c->hsc->energy;
-        info->residual = c->hsc->residual;
-        info->drift = c->hsc->drift;
-        info->inner_iterations = 0;
-        info->status = OPE_OK;
-      }
+      fill_info(c, info, 0, OPE_OK);
       return OPE_OK;
     }
   }
@@ -140,21 +204,13 @@ ope_status run_step(ope_ctx* c, double* U, double tau, ope_step_info* info, doub
   bool cg_done = false;
   st = run_cg(c, c->max_iter, &iters, &cg_done);
   if (st != OPE_OK) return st;
-  HIPCHK(launch_gram(c, U, N, N, c->Y, N, N, c->n, c->Sb));
-  HIPCHK(launch_gram(c, c->Y, N, N, c->Y, N, N, c->n, c->T));
-  HIPCHK(launch_small_solve(c, c->Sb, c->T, tau, c->Z, c->A, c->B));
-  HIPCHK(launch_rowmm(c, U, c->Z, c->Y, c->Z + (size_t)N * N, nullptr, 0.0, 1.0, U, 0, 1, &np));
+  st = phase_update(c, U, tau);
+  if (st != OPE_OK) return st;
   st = sync_and_read_scalars(c);
   if (st != OPE_OK) return st;
   ope_status out = (ope_status)c->hsc->err;
   if (out == OPE_OK && !cg_done) out = OPE_ECG_MAXIT;
-  if (info) {
-    info->energy = c->hsc->energy;
-    info->residual = c->hsc->residual;
-    info->drift = c->hsc->drift;
-    info->inner_iterations = c->hsc->cg_iters;
-    info->status = out;
-  }
+  fill_info(c, info, c->hsc->cg_iters, out);
   return out;
 }
 
@@ -202,7 +258,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   *out = nullptr;
   if (!op || !op->V) return OPE_EINVAL;
   if (op->dim != 2 && op->dim != 3) return OPE_EINVAL;
-  if (precision != OPE_FP64) return OPE_EUNSUPPORTED;
+  if (precision != OPE_FP64 && precision != OPE_MIXED) return OPE_EUNSUPPORTED;
   int64_t n = 1;
   for (int a = 0; a < op->dim; ++a) {
     if (op->m[a] < 1 || !(op->h[a] > 0.0)) return OPE_EINVAL;
@@ -224,7 +280,10 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   }
   c->n = n;
   c->N = N;
-  c->vw = (N % 2 == 0) ? 2 : 1;
+  c->prec = precision;
+  if (precision == OPE_FP64) c->vw = (N % 2 == 0) ? 2 : 1;
+  else c->vw = (N % 4 == 0) ? 4 : ((N % 2 == 0) ? 2 : 1);
+  const size_t esz = precision == OPE_FP64 ? sizeof(double) : sizeof(float);
   OpeGrid& g = c->g;
   g.dim = op->dim;
   g.m0 = (uint32_t)op->m[0];
@@ -236,7 +295,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   g.cy = op->kinetic / (op->h[1] * op->h[1]);
   g.cz = op->dim == 3 ? op->kinetic / (op->h[2] * op->h[2]) : 0.0;
   c->eta_rel = 1e-2;
-  c->eta_floor = 1e-12;
+  c->eta_floor = precision == OPE_FP64 ? 1e-12 : 1e-6;
   c->max_iter = 2000;
   c->check_every = 4;
 
@@ -266,11 +325,18 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
 
   bool ok = true;
   ok &= dalloc(&c->diag, n) == hipSuccess;
-  ok &= dalloc(&c->HU, blk) == hipSuccess;
-  ok &= dalloc(&c->Y, blk) == hipSuccess;
-  ok &= dalloc(&c->Rb[0], blk) == hipSuccess;
-  ok &= dalloc(&c->Rb[1], blk) == hipSuccess;
-  ok &= dalloc(&c->Pb, blk) == hipSuccess;
+  ok &= balloc(&c->HU, blk * esz) == hipSuccess;
+  ok &= balloc(&c->Y, blk * esz) == hipSuccess;
+  ok &= balloc(&c->Rb[0], blk * esz) == hipSuccess;
+  ok &= balloc(&c->Rb[1], blk * esz) == hipSuccess;
+  ok &= balloc(&c->Pb, blk * esz) == hipSuccess;
+  if (precision == OPE_MIXED) {
+    ok &= dalloc(&c->diag32, n) == hipSuccess;
+    ok &= dalloc(&c->Lam32, N * N) == hipSuccess;
+    ok &= dalloc(&c->Linv32, N * N) == hipSuccess;
+    ok &= dalloc(&c->Sb32, N * N) == hipSuccess;
+    ok &= dalloc(&c->Z32, 2 * N * N) == hipSuccess;
+  }
   ok &= dalloc(&c->C, N * N) == hipSuccess;
   ok &= dalloc(&c->Lam, N * N) == hipSuccess;
   ok &= dalloc(&c->Linv, N * N) == hipSuccess;
@@ -301,6 +367,11 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   }
   bool hok = true;
   hok &= hipMemcpy(c->diag, hd.data(), sizeof(double) * n, hipMemcpyHostToDevice) == hipSuccess;
+  if (precision == OPE_MIXED) {
+    std::vector<float> hf((size_t)n);
+    for (int64_t p = 0; p < n; ++p) hf[(size_t)p] = (float)hd[(size_t)p];
+    hok &= hipMemcpy(c->diag32, hf.data(), sizeof(float) * n, hipMemcpyHostToDevice) == hipSuccess;
+  }
   hok &= hipMemset(c->counters, 0, sizeof(uint32_t) * 4096) == hipSuccess;
   hok &= hipMemset(c->sc, 0, sizeof(OpeScalars)) == hipSuccess;
   hok &= hipMemset(c->active, 0, sizeof(int32_t) * N) == hipSuccess;
@@ -328,7 +399,7 @@ ope_status ope_set_inner(ope_ctx* c, double eta_rel, double eta_floor, int32_t m
   return OPE_OK;
 }
 
-ope_status ope_apply_h(ope_ctx* c, const double* X, double* Y) {
+ope_status ope_apply_h(ope_ctx* c, const void* X, void* Y) {
   if (!c || !X || !Y || X == Y) return OPE_EINVAL;
   HIPCHK(launch_apply_h(c, X, Y));
   return OPE_OK;
@@ -338,13 +409,14 @@ ope_status ope_source_solve(ope_ctx* c, const double* U, double* Y, const double
                             int32_t* iterations) {
   if (!c || !U || !Y || !(tol >= 0.0) || max_iter < 0) return OPE_EINVAL;
   if (U == Y) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
   const int N = (int)c->N;
   // r0 = U - H Y0, column norms of r0 and of U
   if (Y0) {
     HIPCHK(launch_apply_h(c, Y0, c->HU));
-    HIPCHK(launch_resid0(c, U, c->HU, c->Rb[0], nullptr));
+    HIPCHK(launch_resid0(c, U, (const double*)c->HU, (double*)c->Rb[0], nullptr));
   } else {
-    HIPCHK(launch_resid0(c, U, nullptr, c->Rb[0], c->Y));
+    HIPCHK(launch_resid0(c, U, nullptr, (double*)c->Rb[0], (double*)c->Y));
   }
   HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, 2 * N, c->rho0, RED_PLAIN));
   HIPCHK(hipMemcpyAsync(c->cnorm2, c->rho0 + N, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
@@ -385,6 +457,7 @@ ope_status ope_gram(ope_ctx* c, const double* A, int64_t lda, int64_t na, const 
 ope_status ope_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau, double* Z, double* A,
                            double* B) {
   if (!c || !Sb || !T || !Z || !(tau > 0.0)) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
   HIPCHK(hipMemsetAsync(&c->sc->err, 0, sizeof(int32_t), c->stream));
   HIPCHK(launch_small_solve(c, Sb, T, tau, Z, A, B));
   ope_status st = sync_and_read_scalars(c);
@@ -394,13 +467,14 @@ ope_status ope_small_solve(ope_ctx* c, const double* Sb, const double* T, double
 
 ope_status ope_update(ope_ctx* c, double* U, const double* Y, const double* Z) {
   if (!c || !U || !Y || !Z || U == Y) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
   const size_t NN = (size_t)c->N * c->N;
   int64_t np = 0;
   HIPCHK(launch_rowmm(c, U, Z, Y, Z + NN, nullptr, 0.0, 1.0, U, 0, 0, &np));
   return OPE_OK;
 }
 
-ope_status ope_energy(ope_ctx* c, const double* U, double* energy) {
+ope_status ope_energy(ope_ctx* c, const void* U, double* energy) {
   if (!c || !U || !energy) return OPE_EINVAL;
   ope_status st = phase_residual(c, U);
   if (st != OPE_OK) return st;
@@ -410,7 +484,7 @@ ope_status ope_energy(ope_ctx* c, const double* U, double* energy) {
   return c->hsc->err == OPE_ENONFINITE ? OPE_ENONFINITE : OPE_OK;
 }
 
-ope_status ope_residual(ope_ctx* c, const double* U, double* residual, double* ritz, double* drift) {
+ope_status ope_residual(ope_ctx* c, const void* U, double* residual, double* ritz, double* drift) {
   if (!c || !U) return OPE_EINVAL;
   const int N = (int)c->N;
   ope_status st = phase_residual(c, U);
@@ -474,7 +548,32 @@ ope_status ope_profile_end(ope_ctx* c, ope_kernel_time* out) {
 
 ope_status ope_step(ope_ctx* c, void* U, double tau, ope_step_info* info) {
   if (!c || !U || !(tau > 0.0)) return OPE_EINVAL;
-  return run_step(c, (double*)U, tau, info, -1.0, nullptr);
+  return run_step(c, U, tau, info, -1.0, nullptr);
+}
+
+ope_status ope_convert(ope_ctx* c, const void* src, void* dst, int64_t count, int32_t to_double) {
+  if (!c || !src || !dst || count < 0 || src == dst) return OPE_EINVAL;
+  if (count == 0) return OPE_OK;
+  HIPCHK(launch_convert(c, src, dst, count, to_double));
+  return OPE_OK;
+}
+
+ope_status ope_gram_f32(ope_ctx* c, int32_t kind, const float* A, int64_t lda, int64_t na, const float* B,
+                        int64_t ldb, int64_t nb, int64_t rows, double* out) {
+  if (!c || !A || !B || !out || kind < MK_F64 || kind > MK_BF16) return OPE_EINVAL;
+  if (na < 1 || nb < 1 || na > 512 || nb > 512 || lda < na || ldb < nb || rows < 1) return OPE_EINVAL;
+  if (na * nb > c->part_cap) return OPE_EUNSUPPORTED;
+  HIPCHK(launch_gram_f32(c, kind, A, lda, (int)na, B, ldb, (int)nb, rows, out));
+  return OPE_OK;
+}
+
+ope_status ope_rowmm_f32(ope_ctx* c, int32_t kind, const float* X0, const float* M0, const float* X1,
+                         const float* M1, const float* Cm, double cbeta, double ascale, float* Out) {
+  if (!c || !X0 || !M0 || !Out || (X1 && !M1) || (cbeta != 0.0 && !Cm) || (kind != MK_F32 && kind != MK_BF16))
+    return OPE_EINVAL;
+  int64_t np = 0;
+  HIPCHK(launch_rowmm_f32(c, kind, X0, M0, X1, M1, Cm, cbeta, ascale, Out, 0, 0, &np));
+  return OPE_OK;
 }
 
 ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t max_steps, ope_solve_info* info) {
@@ -482,12 +581,14 @@ ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t ma
   ope_solve_info si;
   memset(&si, 0, sizeof(si));
   ope_status st = OPE_OK;
+  double best = 1e300;
+  int32_t since_best = 0;
   for (;;) {
     ope_step_info s;
     bool conv = false;
-    const bool last = si.steps >= max_steps;
-    // the final pass only evaluates the iterate (a residual of 2 is never reached)
-    st = run_step(c, (double*)U, tau, &s, last ? 1e300 : res_tol, &conv);
+    const bool last = si.steps >= max_steps || si.stalled;
+    // the final pass only evaluates the iterate (a residual of 1e300 is always reached)
+    st = run_step(c, U, tau, &s, last ? 1e300 : res_tol, &conv);
     if (st != OPE_OK && st != OPE_ECG_MAXIT) break;
     si.residual = s.residual;
     si.energy = s.energy;
@@ -499,6 +600,13 @@ ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t ma
     }
     si.steps += 1;
     si.inner_iterations += s.inner_iterations;
+    // the reduced-precision form stops improving at its rounding floor
+    if (s.residual < 0.9 * best) {
+      best = s.residual;
+      since_best = 0;
+    } else if (c->prec == OPE_MIXED && ++since_best >= 60) {
+      si.stalled = 1;
+    }
   }
   if (info) *info = si;
   return st;

@@ -17,6 +17,9 @@
 #include "ope.h"
 
 #define OPE_WG 256                  // threads per work-group of the streaming kernels
+
+// Arithmetic of a dense contraction (see k_mfma.hip).
+enum { MK_F64 = 0, MK_F32 = 1, MK_BF16 = 2 };
 #define OPE_MAX_N_SMALL 128         // largest N of the one-work-group FP64 small solves
 
 struct OpeGrid {
@@ -62,16 +65,21 @@ struct ope_ctx {
   hipStream_t stream;
   OpeGrid g;
   int64_t n, N;
-  int vw;                       // vector width of block rows (2 if N even, else 1)
+  int prec;                     // OPE_FP64 or OPE_MIXED
+  int vw;                       // elements per 16-byte row chunk (fewer when N is not a multiple)
   // operator
   double* diag;                 // V + shift + 2 (cx + cy + cz), n values
-  // n x N workspace blocks
-  double* HU;                   // H U, then R = HU - U Lam, then a CG direction buffer
-  double* Y;                    // Step-1 solution G U
-  double* Rb[2];                // CG residuals (double buffered)
-  double* Pb;                   // second CG direction buffer (the first is HU)
-  // N x N (and 2N x N) matrices
+  float* diag32;                // the same in FP32 (mixed precision)
+  // n x N workspace blocks, FP64 (OPE_FP64) or FP32 (OPE_MIXED)
+  void* HU;                     // H U, then R = HU - U Lam, then a CG direction buffer
+                                // (mixed: finally the projection Y - U <U,Y>)
+  void* Y;                      // Step-1 solution G U
+  void* Rb[2];                  // CG residuals (double buffered)
+  void* Pb;                     // second CG direction buffer (the first is HU)
+  // N x N (and 2N x N) matrices, FP64
   double *C, *Lam, *Linv, *Sb, *T, *Z, *A, *B, *Wsm;
+  // FP32 copies used by the mixed-precision products
+  float *Lam32, *Linv32, *Sb32, *Z32;
   // per-column CG state
   double *alpha, *beta, *rho, *target, *cnorm2, *rcol, *rho0;
   int32_t* active;
@@ -111,14 +119,14 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 // launchers (each enqueues on ctx->stream and returns hipSuccess or an error)
 // ---------------------------------------------------------------------------
-hipError_t launch_apply_h(ope_ctx* c, const double* X, double* Y);
+hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Y);
 void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt);  // fills c->ms (0 = automatic)
 int64_t march_rows(const ope_ctx* c);              // partial rows written by the CG sweeps
 
 // CG iteration halves (see k_stencil.hip)
-hipError_t launch_cg_pap(ope_ctx* c, const double* r, const double* pold, int first);
-hipError_t launch_cg_update(ope_ctx* c, const double* r, const double* pold, double* rnew,
-                            double* pnew, double* y, int first);
+hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, int first);
+hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* pold, void* rnew,
+                            void* pnew, void* y, int first);
 hipError_t launch_cg_setup_reduce(ope_ctx* c, int mode);
 
 // column sums of partials: out[j] = sum_w part[w*ncols + j], fixed order
@@ -138,11 +146,24 @@ hipError_t launch_rowmm(ope_ctx* c, const double* X0, const double* M0, const do
 // r0 = U - H Y0 (or U when HY is NULL, zeroing y), per-column sums of r0^2 and U^2 into c->part
 hipError_t launch_resid0(ope_ctx* c, const double* U, const double* HY, double* R, double* y);
 
+// mixed precision: FP32 blocks, kind MK_F64 / MK_F32 / MK_BF16
+hipError_t launch_gram_f32(ope_ctx* c, int kind, const float* A, int64_t lda, int na, const float* B,
+                           int64_t ldb, int nb, int64_t rows, double* out);
+hipError_t launch_rowmm_f32(ope_ctx* c, int kind, const float* X0, const float* M0, const float* X1,
+                            const float* M1, const float* Cm, double cbeta, double ascale, float* Out,
+                            int want_colsq, int predicated, int64_t* nparts);
+// elementwise precision conversion (to_double != 0: float -> double)
+hipError_t launch_convert(ope_ctx* c, const void* src, void* dst, int64_t count, int to_double);
+
 // one-work-group FP64 kernels
 hipError_t launch_prep_small(ope_ctx* c);
 hipError_t launch_cg_setup(ope_ctx* c, const double* rho0);
 hipError_t launch_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau,
                               double* Z, double* A, double* B);
+// mixed: M = I + tau/2 (S_a - S_b) + tau^2/4 (P^T P - S_b^T (C-I) S_b), B = M^{-1}; Z32 = [-2(I-B) ; tau B]
+hipError_t launch_small_solve_delta(ope_ctx* c, const double* Sb, const double* Tperp, double tau);
+// FP32 copy of an N x N matrix
+hipError_t launch_small_to_f32(ope_ctx* c, const double* src, float* dst, int64_t count);
 hipError_t launch_jacobi_eig(ope_ctx* c, const double* Asym, double* evals);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
 

@@ -25,6 +25,8 @@ OPE_ECG_MAXIT = 5
 OPE_EPIVOT = 6
 OPE_EUNSUPPORTED = 7
 OPE_FP64 = 0
+OPE_MIXED = 1
+MK_F64, MK_F32, MK_BF16 = 0, 1, 2
 
 STATUS_NAMES = {
     OPE_OK: "OPE_OK", OPE_EINVAL: "OPE_EINVAL", OPE_ENOMEM: "OPE_ENOMEM", OPE_EHIP: "OPE_EHIP",
@@ -68,6 +70,8 @@ class ope_solve_info(ctypes.Structure):
         ("energy", ctypes.c_double),
         ("drift", ctypes.c_double),
         ("inner_iterations", ctypes.c_int64),
+        ("stalled", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -106,6 +110,9 @@ SIGNATURES = {
     "ope_set_sweep_shape": ([_P, _I32, _I32, _I32], _I32),
     "ope_get_sweep_shape": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _I32),
     "ope_profile_begin": ([_P, _I32], _I32),
+    "ope_convert": ([_P, _P, _P, _I64, _I32], _I32),
+    "ope_gram_f32": ([_P, _I32, _P, _I64, _I64, _P, _I64, _I64, _I64, _P], _I32),
+    "ope_rowmm_f32": ([_P, _I32, _P, _P, _P, _P, _P, _D, _D, _P], _I32),
     "ope_profile_end": ([_P, ctypes.POINTER(ope_kernel_time)], _I32),
 }
 
@@ -140,7 +147,7 @@ def _ptr(x) -> Optional[int]:
         return None
     if isinstance(x, int):
         return x
-    # torch tensor: must live on the GPU, float64, contiguous
+    # torch tensor: must live on the GPU and be contiguous
     if not x.is_cuda:
         raise ValueError("device buffer expected (torch CUDA tensor)")
     if not x.is_contiguous():
@@ -264,6 +271,19 @@ def ope_get_sweep_shape(ctx: int):
     return q.value, mc.value, wg.value
 
 
+def ope_convert(ctx: int, src, dst, count: int, to_double: bool) -> None:
+    _check(lib().ope_convert(ctx, _ptr(src), _ptr(dst), int(count), 1 if to_double else 0), "ope_convert")
+
+
+def ope_gram_f32(ctx: int, kind: int, A, lda: int, na: int, B, ldb: int, nb: int, rows: int, out) -> None:
+    _check(lib().ope_gram_f32(ctx, kind, _ptr(A), lda, na, _ptr(B), ldb, nb, rows, _ptr(out)), "ope_gram_f32")
+
+
+def ope_rowmm_f32(ctx: int, kind: int, X0, M0, X1, M1, Cm, cbeta: float, ascale: float, Out) -> None:
+    _check(lib().ope_rowmm_f32(ctx, kind, _ptr(X0), _ptr(M0), _ptr(X1), _ptr(M1), _ptr(Cm), cbeta, ascale, _ptr(Out)),
+           "ope_rowmm_f32")
+
+
 def ope_profile_begin(ctx: int, kernel: int) -> None:
     _check(lib().ope_profile_begin(ctx, kernel), "ope_profile_begin")
 
@@ -278,10 +298,12 @@ def ope_profile_end(ctx: int):
 class Context:
     """Owns one ``ope_ctx`` for a workload (grid, potential, N)."""
 
-    def __init__(self, grid, V, N, kinetic=1.0, shift=0.0, stream=None):
+    def __init__(self, grid, V, N, kinetic=1.0, shift=0.0, stream=None, precision=OPE_FP64):
         self.N = int(N)
         self.n = int(np.prod(grid.m))
-        self.handle = ope_create(grid.dim, grid.m, grid.h, V, N, kinetic=kinetic, shift=shift, stream=stream)
+        self.precision = precision
+        self.handle = ope_create(grid.dim, grid.m, grid.h, V, N, kinetic=kinetic, shift=shift, stream=stream,
+                                 precision=precision)
 
     def close(self):
         if self.handle:

@@ -173,3 +173,19 @@ def test_small_tau_rate_is_theorem_3_11(cfg1):
     err = np.array(err)
     slope = np.polyfit(np.arange(200, 400) * tau, np.log(err[200:]), 1)[0]
     assert abs(-slope - 2 * kmin) <= 0.05 * 2 * kmin
+
+
+def test_delta_form_equals_general_step(cfg1):
+    """The delta form is Steps 2-4 rewritten (Step 3 substituted into Step 4,
+    T - S_a S_b expressed through the projected block): identical to the
+    general step for any U (also not orthonormal) and any Y."""
+    p, op, G, w, X = cfg1
+    U = p.U0
+    rng = np.random.default_rng(9)
+    E = rng.standard_normal((8, 8)) * 1e-3
+    for Uc in (U, U @ (np.eye(8) + 0.5 * (E + E.T))):
+        for Y in (G(Uc), G(Uc) + 1e-3 * rng.standard_normal(U.shape) / 25.0):
+            for tau in (0.1, 20.0, 45.0):
+                a = O.step_general(Uc, Y, tau)["U"]
+                b = O.step_delta(Uc, Y, tau)["U"]
+                assert np.max(np.abs(a - b)) <= 1e-12

@@ -14,6 +14,9 @@ so that a reader can check each function against the paper by eye:
 * :mod:`oracle.scheme`   -- the midpoint scheme (4.1): the paper's Steps 1-4,
   the same step as a dense Cayley solve and as the 2N x 2N Woodbury system,
   the generator ``L_U``, energy, residual, Ritz values and the Algorithm 1 loop.
+* :mod:`oracle.net`      -- the small 3D conv-net that stands in for ``H^{-1}``
+  applied to residual columns in the learned form (forward, backward, loss);
+  imported as ``oracle.net``.
 
 Parity status of every function is listed in the module headers; all are pinned
 by ``tests/test_oracle_*.py`` against closed forms, brute force, invariants and

@@ -1,0 +1,153 @@
+"""Oracle: the small 3D conv-net preconditioner (test infrastructure only).
+
+The learned form replaces ``H^{-1} R`` in the gradient form of the step
+(``GU = (U - H^{-1} R) Lam^{-1}``, ``R = HU - U Lam``) by a network applied to
+each column of R.  The network here is the plain definition, in float64, of:
+
+    input channels  x_0 = r / |r|,  x_1 = h^2 V            (on the grid, zero outside)
+    z_1 = W_1 * x,        a_1 = relu(z_1)      2 -> 16 channels
+    z_2 = W_2 * a_1,      a_2 = relu(z_2)     16 -> 16
+    z_3 = W_3 * a_2,      a_3 = relu(z_3)     16 -> 16
+    f   = W_4 * a_3                           16 -> 1
+    P(r) = |r| h^2 f
+
+where ``W * a`` is a 3x3x3 cross-correlation with zero padding outside the
+grid, ``out[v, co] = sum_{tap, ci} W[tap, ci, co] a[v + tap, ci]``, no biases
+(so ``P(0) = 0`` and eigenbases stay fixed points).  The training loss of a
+batch is ``mean_b |f_b - t_b|^2 / |t_b|^2`` with ``t = H^{-1} r / (|r| h^2)``.
+
+Layout: a field of C channels on the grid is an array of shape
+``(m2, m1, m0, C)`` (x fastest); taps are ordered ``(dz, dy, dx)`` with dx
+fastest, each in ``(-1, 0, 1)``.
+
+Parity: the backward pass is pinned by central finite differences of the loss
+and by the linear special case (all-positive activations) where the network is
+a composition of explicit stencils.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+CHANNELS = (2, 16, 16, 16, 1)
+
+
+def shift(a: np.ndarray, tap) -> np.ndarray:
+    """``out[v] = a[v + tap]`` with zeros outside the grid (array axes z, y, x, c)."""
+    out = np.zeros_like(a)
+    src = []
+    dst = []
+    for ax, d in enumerate(tap):
+        n = a.shape[ax]
+        if d == 0:
+            src.append(slice(0, n))
+            dst.append(slice(0, n))
+        elif d > 0:
+            src.append(slice(d, n))
+            dst.append(slice(0, n - d))
+        else:
+            src.append(slice(0, n + d))
+            dst.append(slice(-d, n))
+    out[tuple(dst)] = a[tuple(src)]
+    return out
+
+
+def conv(a: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """3x3x3 cross-correlation ``out[v, co] = sum_{t, ci} W[t, ci, co] a[v + tap_t, ci]``."""
+    out = np.zeros(a.shape[:3] + (W.shape[2],))
+    for t, tap in enumerate(TAPS):
+        out += shift(a, tap) @ W[t]
+    return out
+
+
+def conv_transpose(g: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Adjoint of ``conv`` in its input: ``out[v, ci] = sum_{t, co} W[t, ci, co] g[v - tap_t, co]``."""
+    out = np.zeros(g.shape[:3] + (W.shape[1],))
+    for t, tap in enumerate(TAPS):
+        out += shift(g, tuple(-d for d in tap)) @ W[t].T
+    return out
+
+
+def conv_weight_grad(a: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """``dW[t, ci, co] = sum_v a[v + tap_t, ci] g[v, co]``."""
+    ci, co = a.shape[3], g.shape[3]
+    dW = np.zeros((27, ci, co))
+    af = a.reshape(-1, ci)
+    gf = g.reshape(-1, co)
+    for t, tap in enumerate(TAPS):
+        dW[t] = shift(a, tap).reshape(-1, ci).T @ gf
+    return dW
+
+
+def init_weights(seed: int) -> List[np.ndarray]:
+    """He-style normal initialisation of the four weight tensors ``(27, ci, co)``."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xC0117]))
+    Ws = []
+    for ci, co in zip(CHANNELS[:-1], CHANNELS[1:]):
+        Ws.append(rng.standard_normal((27, ci, co)) * np.sqrt(2.0 / (27 * ci)))
+    return Ws
+
+
+def forward(x: np.ndarray, Ws: Sequence[np.ndarray]) -> Dict[str, np.ndarray]:
+    """Network on one sample; ``x`` has shape (m2, m1, m0, 2).  Returns the
+    pre-activations z1..z3 and the output f (m2, m1, m0)."""
+    z1 = conv(x, Ws[0])
+    z2 = conv(np.maximum(z1, 0.0), Ws[1])
+    z3 = conv(np.maximum(z2, 0.0), Ws[2])
+    f = conv(np.maximum(z3, 0.0), Ws[3])[..., 0]
+    return {"x": x, "z1": z1, "z2": z2, "z3": z3, "f": f}
+
+
+def backward(cache: Dict[str, np.ndarray], df: np.ndarray, Ws: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Weight gradients of a scalar with ``d/df = df`` (same shape as f)."""
+    g4 = df[..., None]
+    a3 = np.maximum(cache["z3"], 0.0)
+    dW4 = conv_weight_grad(a3, g4)
+    g3 = conv_transpose(g4, Ws[3]) * (cache["z3"] > 0)
+    a2 = np.maximum(cache["z2"], 0.0)
+    dW3 = conv_weight_grad(a2, g3)
+    g2 = conv_transpose(g3, Ws[2]) * (cache["z2"] > 0)
+    a1 = np.maximum(cache["z1"], 0.0)
+    dW2 = conv_weight_grad(a1, g2)
+    g1 = conv_transpose(g2, Ws[1]) * (cache["z1"] > 0)
+    dW1 = conv_weight_grad(cache["x"], g1)
+    return [dW1, dW2, dW3, dW4]
+
+
+def batch_loss_and_grads(xs: Sequence[np.ndarray], ts: Sequence[np.ndarray], Ws: Sequence[np.ndarray]):
+    """Loss ``mean_b |f_b - t_b|^2 / |t_b|^2`` and its weight gradients."""
+    B = len(xs)
+    loss = 0.0
+    grads = [np.zeros_like(W) for W in Ws]
+    for x, t in zip(xs, ts):
+        c = forward(x, Ws)
+        e = c["f"] - t
+        tt = float(np.sum(t * t))
+        loss += float(np.sum(e * e)) / tt / B
+        g = backward(c, 2.0 * e / tt / B, Ws)
+        for k in range(4):
+            grads[k] += g[k]
+    return loss, grads
+
+
+def inputs_for(r_column: np.ndarray, V: np.ndarray, h: float, m) -> np.ndarray:
+    """Network input of one residual column (n values, x fastest) on grid m."""
+    shape = (m[2], m[1], m[0])
+    x = np.zeros(shape + (2,))
+    x[..., 0] = (r_column / np.linalg.norm(r_column)).reshape(shape)
+    x[..., 1] = (h * h * V).reshape(shape)
+    return x
+
+
+def apply_preconditioner(R: np.ndarray, V: np.ndarray, h: float, m, Ws: Sequence[np.ndarray]) -> np.ndarray:
+    """``P(R)`` column by column: ``|r| h^2 f(r / |r|, h^2 V)``; zero columns map to zero."""
+    out = np.zeros_like(R)
+    for j in range(R.shape[1]):
+        nr = np.linalg.norm(R[:, j])
+        if nr == 0.0:
+            continue
+        f = forward(inputs_for(R[:, j], V, h, m), Ws)["f"]
+        out[:, j] = nr * h * h * f.reshape(-1)
+    return out

@@ -1,0 +1,118 @@
+"""Pins of the oracle conv-net (the learned preconditioner's definition).
+
+* ``conv_transpose`` is the adjoint of ``conv`` (inner-product identity).
+* ``conv`` of a one-hot kernel is a shift; with a 7-point Laplacian kernel it
+  reproduces the oracle's finite-difference operator (with h = 1).
+* Weight gradients match central finite differences of the batch loss.
+* Through all four layers: identity taps in layers 1-3 on a positive input
+  (every ReLU passes) and the Laplacian kernel in layer 4 give the
+  finite-difference operator; a planted sign error in a ReLU mask is caught by
+  the finite-difference gradient check.
+* Positive homogeneity ``P(a r) = a P(r)`` (a > 0) and ``P(0) = 0``: the
+  eigenbasis remains a fixed point of the learned step.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import net as NN
+
+
+def test_transpose_is_adjoint():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((4, 5, 6, 3))
+    g = rng.standard_normal((4, 5, 6, 2))
+    W = rng.standard_normal((27, 3, 2))
+    lhs = np.sum(NN.conv(a, W) * g)
+    rhs = np.sum(a * NN.conv_transpose(g, W))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_laplacian_kernel_matches_fd_operator():
+    m = (6, 5, 4)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(int(np.prod(m)))
+    W = np.zeros((27, 1, 1))
+    for t, tap in enumerate(NN.TAPS):
+        k = sum(abs(d) for d in tap)
+        if k == 0:
+            W[t] = 6.0
+        elif k == 1:
+            W[t] = -1.0
+    out = NN.conv(u.reshape(m[2], m[1], m[0], 1), W).reshape(-1)
+    op = O.Operator(m, (1.0, 1.0, 1.0), np.zeros(u.size))
+    assert np.allclose(out, O.apply_H(op, u[:, None])[:, 0], atol=1e-12)
+
+
+def test_weight_gradients_match_finite_differences():
+    rng = np.random.default_rng(2)
+    shape = (4, 4, 5)
+    Ws = NN.init_weights(7)
+    xs = [rng.standard_normal(shape + (2,)) for _ in range(2)]
+    ts = [rng.standard_normal(shape) for _ in range(2)]
+    loss, grads = NN.batch_loss_and_grads(xs, ts, Ws)
+    eps = 1e-6
+    for k, (li, idx) in enumerate([(0, (3, 1, 5)), (1, (13, 7, 2)), (2, (26, 15, 15)), (3, (0, 4, 0)), (1, (4, 0, 9))]):
+        Wp = [W.copy() for W in Ws]
+        Wm = [W.copy() for W in Ws]
+        Wp[li][idx] += eps
+        Wm[li][idx] -= eps
+        fd = (NN.batch_loss_and_grads(xs, ts, Wp)[0] - NN.batch_loss_and_grads(xs, ts, Wm)[0]) / (2 * eps)
+        assert abs(fd - grads[li][idx]) <= 1e-6 * max(1.0, abs(fd)), (li, idx, fd, grads[li][idx])
+
+
+def test_positive_homogeneity_and_zero():
+    rng = np.random.default_rng(3)
+    m = (5, 4, 3)
+    n = int(np.prod(m))
+    V = rng.uniform(-5, 0, n)
+    R = rng.standard_normal((n, 3))
+    Ws = NN.init_weights(1)
+    P1 = NN.apply_preconditioner(R, V, 0.1, m, Ws)
+    P2 = NN.apply_preconditioner(2.5 * R, V, 0.1, m, Ws)
+    assert np.allclose(P2, 2.5 * P1, rtol=1e-12, atol=1e-14)
+    assert np.all(NN.apply_preconditioner(np.zeros((n, 2)), V, 0.1, m, Ws) == 0.0)
+
+
+def test_full_network_linear_special_case():
+    m = (5, 6, 4)
+    rng = np.random.default_rng(4)
+    u = rng.uniform(0.5, 1.5, int(np.prod(m)))
+    x = np.zeros((m[2], m[1], m[0], 2))
+    x[..., 0] = u.reshape(m[2], m[1], m[0])
+    x[..., 1] = rng.uniform(-1, 1, x.shape[:3])     # ignored by W1 below
+    centre = NN.TAPS.index((0, 0, 0))
+    Ws = [np.zeros((27, ci, co)) for ci, co in zip(NN.CHANNELS[:-1], NN.CHANNELS[1:])]
+    Ws[0][centre, 0, 3] = 1.0
+    Ws[1][centre, 3, 5] = 1.0
+    Ws[2][centre, 5, 0] = 1.0
+    for t, tap in enumerate(NN.TAPS):
+        k = sum(abs(d) for d in tap)
+        Ws[3][t, 0, 0] = 6.0 if k == 0 else (-1.0 if k == 1 else 0.0)
+    f = NN.forward(x, Ws)["f"].reshape(-1)
+    op = O.Operator(m, (1.0, 1.0, 1.0), np.zeros(u.size))
+    assert np.allclose(f, O.apply_H(op, u[:, None])[:, 0], atol=1e-12)
+
+
+def test_planted_relu_mask_error_is_caught(monkeypatch):
+    rng = np.random.default_rng(5)
+    shape = (3, 4, 4)
+    Ws = NN.init_weights(3)
+    xs = [rng.standard_normal(shape + (2,))]
+    ts = [rng.standard_normal(shape)]
+    good = NN.backward
+    def bad(cache, df, Ws_):
+        c = dict(cache)
+        c["z2"] = -c["z2"]            # wrong mask (z < 0 instead of z > 0) in layer 2
+        return good(c, df, Ws_)
+    monkeypatch.setattr(NN, "backward", bad)
+    _, g_bad = NN.batch_loss_and_grads(xs, ts, Ws)
+    monkeypatch.setattr(NN, "backward", good)
+    _, g_ok = NN.batch_loss_and_grads(xs, ts, Ws)
+    li, idx = 1, (13, 2, 3)
+    eps = 1e-6
+    Wp = [W.copy() for W in Ws]; Wp[li][idx] += eps
+    Wm = [W.copy() for W in Ws]; Wm[li][idx] -= eps
+    fd = (NN.batch_loss_and_grads(xs, ts, Wp)[0] - NN.batch_loss_and_grads(xs, ts, Wm)[0]) / (2 * eps)
+    assert abs(fd - g_ok[li][idx]) <= 1e-6 * max(1.0, abs(fd))
+    assert np.max(np.abs(g_bad[0] - g_ok[0])) > 1e-3

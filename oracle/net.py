@@ -4,7 +4,7 @@ The learned form replaces ``H^{-1} R`` in the gradient form of the step
 (``GU = (U - H^{-1} R) Lam^{-1}``, ``R = HU - U Lam``) by a network applied to
 each column of R.  The network here is the plain definition, in float64, of:
 
-    input channels  x_0 = r / |r|,  x_1 = h^2 V            (on the grid, zero outside)
+    input channels  x_0 = r / |r|,  x_1 = h^2 (V + shift)  (on the grid, zero outside)
     z_1 = W_1 * x,        a_1 = relu(z_1)      2 -> 16 channels
     z_2 = W_2 * a_1,      a_2 = relu(z_2)     16 -> 16
     z_3 = W_3 * a_2,      a_3 = relu(z_3)     16 -> 16
@@ -14,21 +14,32 @@ each column of R.  The network here is the plain definition, in float64, of:
 where ``W * a`` is a 3x3x3 cross-correlation with zero padding outside the
 grid, ``out[v, co] = sum_{tap, ci} W[tap, ci, co] a[v + tap, ci]``, no biases
 (so ``P(0) = 0`` and eigenbases stay fixed points).  The training loss of a
-batch is ``mean_b |f_b - t_b|^2 / |t_b|^2`` with ``t = H^{-1} r / (|r| h^2)``.
+sample is the squared energy-norm error of the preconditioned direction
+relative to the exact one,
+
+    (P r - H^{-1} r)^T H (P r - H^{-1} r) / (r^T H^{-1} r)
+        = (f - t)^T A (f - t) / (x_0 . t),   t = H^{-1} r / (|r| h^2),  A = h^2 H,
+
+(1 for the zero network, 0 for the exact inverse), averaged over the batch.
+The grid spacing must be the same on all three axes.
 
 Layout: a field of C channels on the grid is an array of shape
 ``(m2, m1, m0, C)`` (x fastest); taps are ordered ``(dz, dy, dx)`` with dx
 fastest, each in ``(-1, 0, 1)``.
 
-Parity: the backward pass is pinned by central finite differences of the loss
-and by the linear special case (all-positive activations) where the network is
-a composition of explicit stencils.
+Parity: the backward pass is pinned by central finite differences of the loss,
+the forward pass by the special case where every ReLU passes and the network
+reduces to an explicit stencil, and the loss by its values for the zero and
+the exact network.
 """
 from __future__ import annotations
 
-from typing import Dict, List, Sequence
+from typing import Callable, Dict, List, Sequence
 
 import numpy as np
+
+from .operator import Operator, apply_H
+from .scheme import step_general
 
 TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 CHANNELS = (2, 16, 16, 16, 1)
@@ -116,38 +127,80 @@ def backward(cache: Dict[str, np.ndarray], df: np.ndarray, Ws: Sequence[np.ndarr
     return [dW1, dW2, dW3, dW4]
 
 
-def batch_loss_and_grads(xs: Sequence[np.ndarray], ts: Sequence[np.ndarray], Ws: Sequence[np.ndarray]):
-    """Loss ``mean_b |f_b - t_b|^2 / |t_b|^2`` and its weight gradients."""
+def scaled_operator(op: Operator) -> Callable[[np.ndarray], np.ndarray]:
+    """``A = h^2 H`` acting on a field of shape (m2, m1, m0); equal spacings only."""
+    h = op.h[0]
+    if any(abs(hh - h) > 1e-12 * h for hh in op.h):
+        raise ValueError("the network needs equal grid spacings")
+    m = op.m
+    shape = (m[2], m[1], m[0])
+    return lambda e: h * h * apply_H(op, e.reshape(-1, 1))[:, 0].reshape(shape)
+
+
+def sample_loss(f: np.ndarray, t: np.ndarray, x0: np.ndarray, apply_A) -> tuple:
+    """Energy-norm loss of one sample and its derivative in f."""
+    e = f - t
+    Ae = apply_A(e)
+    den = float(np.sum(x0 * t))
+    return float(np.sum(e * Ae)) / den, 2.0 * Ae / den
+
+
+def batch_loss_and_grads(xs: Sequence[np.ndarray], ts: Sequence[np.ndarray], Ws: Sequence[np.ndarray], apply_A):
+    """Batch-mean loss and its weight gradients."""
     B = len(xs)
     loss = 0.0
     grads = [np.zeros_like(W) for W in Ws]
     for x, t in zip(xs, ts):
         c = forward(x, Ws)
-        e = c["f"] - t
-        tt = float(np.sum(t * t))
-        loss += float(np.sum(e * e)) / tt / B
-        g = backward(c, 2.0 * e / tt / B, Ws)
+        l, df = sample_loss(c["f"], t, x[..., 0], apply_A)
+        loss += l / B
+        g = backward(c, df / B, Ws)
         for k in range(4):
             grads[k] += g[k]
     return loss, grads
 
 
-def inputs_for(r_column: np.ndarray, V: np.ndarray, h: float, m) -> np.ndarray:
-    """Network input of one residual column (n values, x fastest) on grid m."""
+def inputs_for(r_column: np.ndarray, op: Operator) -> np.ndarray:
+    """Network input of one residual column (n values, x fastest)."""
+    m = op.m
+    h = op.h[0]
     shape = (m[2], m[1], m[0])
     x = np.zeros(shape + (2,))
     x[..., 0] = (r_column / np.linalg.norm(r_column)).reshape(shape)
-    x[..., 1] = (h * h * V).reshape(shape)
+    x[..., 1] = (h * h * (op.V + op.shift)).reshape(shape)
     return x
 
 
-def apply_preconditioner(R: np.ndarray, V: np.ndarray, h: float, m, Ws: Sequence[np.ndarray]) -> np.ndarray:
-    """``P(R)`` column by column: ``|r| h^2 f(r / |r|, h^2 V)``; zero columns map to zero."""
+def target_for(r_column: np.ndarray, op: Operator, solve) -> np.ndarray:
+    """``t = H^{-1} r / (|r| h^2)`` on the grid, with ``solve`` applying ``H^{-1}`` to a block."""
+    m = op.m
+    h = op.h[0]
+    y = solve(r_column[:, None])[:, 0]
+    return (y / (np.linalg.norm(r_column) * h * h)).reshape(m[2], m[1], m[0])
+
+
+def apply_preconditioner(R: np.ndarray, op: Operator, Ws: Sequence[np.ndarray]) -> np.ndarray:
+    """``P(R)`` column by column: ``|r| h^2 f(r / |r|, h^2 (V + shift))``; zero columns map to zero."""
+    h = op.h[0]
     out = np.zeros_like(R)
     for j in range(R.shape[1]):
         nr = np.linalg.norm(R[:, j])
         if nr == 0.0:
             continue
-        f = forward(inputs_for(R[:, j], V, h, m), Ws)["f"]
+        f = forward(inputs_for(R[:, j], op), Ws)["f"]
         out[:, j] = nr * h * h * f.reshape(-1)
+    return out
+
+
+def learned_step(op: Operator, U: np.ndarray, Ws: Sequence[np.ndarray], tau: float) -> Dict[str, np.ndarray]:
+    """The learned form of one step: with ``Lam = U^T H U`` and ``R = HU - U Lam``,
+    ``Y = (U - P(R)) Lam^{-1}`` (the gradient form ``GU = (U - H^{-1} R) Lam^{-1}``
+    with the network in place of ``H^{-1}``), then Steps 2-4 for that Y."""
+    HU = apply_H(op, U)
+    Lam = U.T @ HU
+    R = HU - U @ Lam
+    Y = np.linalg.solve(Lam.T, (U - apply_preconditioner(R, op, Ws)).T).T
+    out = step_general(U, Y, tau)
+    out["Y"] = Y
+    out["R"] = R
     return out

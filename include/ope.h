@@ -88,7 +88,7 @@ typedef struct {
   double drift;       /* final |U^T U - I|_F */
   int64_t inner_iterations; /* total CG iterations */
   int32_t stalled;    /* OPE_MIXED only: 1 if the residual stopped improving (60 steps without a 10% gain) */
-  int32_t reserved;
+  int32_t learned_steps; /* steps taken by the learned form and kept by its judge */
 } ope_solve_info;
 
 typedef struct ope_ctx ope_ctx;
@@ -188,6 +188,69 @@ ope_status ope_gram_f32(ope_ctx* ctx, int32_t kind, const float* A, int64_t lda,
                         int64_t ldb, int64_t nb, int64_t rows, double* out);
 ope_status ope_rowmm_f32(ope_ctx* ctx, int32_t kind, const float* X0, const float* M0, const float* X1,
                          const float* M1, const float* Cm, double cbeta, double ascale, float* Out);
+
+/* --- Learned preconditioner --------------------------------------------
+ * Gradient form of Step 1: with R = HU - U Lam, G U = (U - H^{-1} R) Lam^{-1}.
+ * The learned form replaces H^{-1} R column by column by a small 3D conv net,
+ *   P(r) = |r| h^2 f(r / |r|, h^2 (V + shift)),
+ * f: four bias-free 3x3x3 cross-correlations with zero padding, channels
+ * 2 -> 16 -> 16 -> 16 -> 1, ReLU after the first three, on BF16 matrix cores
+ * with FP32 accumulation (activations stored in BF16).  Weights are FP32
+ * masters (BF16 copies feed the matrix cores): OPE_NET_PARAMS values in the
+ * order W1[27][2][16], W2[27][16][16], W3[27][16][16], W4[27][16][1], each
+ * [tap][in][out] with taps (dz, dy, dx), dx fastest, each in (-1, 0, 1).
+ * Training loss of a sample (x = r/|r|, target t = H^{-1} r / (|r| h^2)):
+ *   (f - t)^T A (f - t) / (x . t),  A = h^2 H
+ * (the squared H-norm error of P r relative to H^{-1} r: 1 for the zero
+ * network), averaged over the batch.  3D grids with equal spacings only.
+ * Sample blocks X, T, F are device FP32 [sample][z][y][x] (n values each).
+ * The learned step keeps Steps 2-4 (Section 4.1), so orthogonality holds for
+ * any weights (Theorem 4.1's argument), and P(0) = 0 keeps eigenbases fixed. */
+#define OPE_NET_PARAMS 15120
+typedef struct ope_net ope_net;
+
+/* Network on ctx's grid with activations for up to max_batch (1..4096)
+ * samples; its bound second input channel is ctx's h^2 (V + shift).  Weights
+ * start at zero.  EUNSUPPORTED for 2D grids or unequal spacings.  Destroy the
+ * network before its context. */
+ope_status ope_net_create(ope_ctx* ctx, int64_t max_batch, ope_net** net);
+ope_status ope_net_destroy(ope_net* net);
+/* FP32 weights from / to a HOST array of OPE_NET_PARAMS values (set resets the Adam state). */
+ope_status ope_net_set_weights(ope_net* net, const float* w);
+ope_status ope_net_get_weights(ope_net* net, float* w);
+/* The bound second input channel h^2 (V + shift) into V2 (device, n FP32). */
+ope_status ope_net_potential(ope_net* net, float* V2);
+/* F = f(X) for 1 <= B <= max_batch samples.  V2: the second input channel
+ * (device, n FP32, shared by the batch), NULL for the bound one. */
+ope_status ope_net_forward(ope_net* net, const float* X, const float* V2, int64_t B, float* F);
+/* Batch loss into *loss (host, nullable) and its gradient into grad (HOST
+ * array of OPE_NET_PARAMS, nullable).  ENONFINITE if the loss is not finite. */
+ope_status ope_net_grad(ope_net* net, const float* X, const float* V2, const float* T, int64_t B,
+                        double* loss, float* grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr > 0; *loss (host, nullable) receives the loss before the step. */
+ope_status ope_net_train_step(ope_net* net, const float* X, const float* V2, const float* T, int64_t B,
+                              double lr, double* loss);
+/* Training samples from point-major FP64 device blocks R (residual columns)
+ * and S = H^{-1} R (leading dimension ld, columns 0..B-1, B <= the context's
+ * N): X[b] = r_b / |r_b|, T[b] = s_b / (|r_b| h^2); zero columns give zeros. */
+ope_status ope_net_samples(ope_net* net, const double* R, const double* S, int64_t ld, int64_t B,
+                           float* X, float* T);
+
+/* Use `net` (created on this context, max_batch >= N) for ope_step_learned
+ * and ope_solve, or NULL to go back to plain steps.  OPE_FP64 contexts only.
+ * judge = 1: the plain step judges every learned iterate and replaces it when
+ * rejected (below); judge = 0: learned iterates are always kept (for study). */
+ope_status ope_set_preconditioner(ope_ctx* ctx, ope_net* net, int32_t judge);
+/* One learned step in place on U: Y = (U - P(R)) Lam^{-1}, then Steps 2-4.
+ * With the judge on, the learned iterate is kept only if its energy is not
+ * above the current one (up to 1e-13 relative) and its residual
+ * |HU - U Lam|_F / |Lam|_F is not above the current one; otherwise U is
+ * restored and one plain step (ope_step) is taken.  *accepted (host,
+ * nullable) = 1 if the learned iterate was kept.  info as for ope_step (the
+ * input U's energy, residual and drift; inner_iterations 0 when accepted).
+ * EINVAL if no network is set. */
+ope_status ope_step_learned(ope_ctx* ctx, void* U, double tau, ope_step_info* info, int32_t* accepted);
 
 /* --- Launch shape of the stencil / CG sweeps (tuning) --------------------
  * The sweeps march along the slowest grid axis; a work-group covers q passes

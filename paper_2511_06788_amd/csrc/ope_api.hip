@@ -15,6 +15,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -43,12 +44,14 @@ void free_ctx(ope_ctx* c) {
   if (!c) return;
   void* dptrs[] = {c->diag, c->diag32, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T,
                    c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
-                   c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->counters, c->sc};
+                   c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->counters, c->sc,
+                   c->Ubak};
   for (void* p : dptrs)
     if (p) (void)hipFree(p);
   if (c->hsc) (void)hipHostFree(c->hsc);
   if (c->hactive) (void)hipHostFree(c->hactive);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
+  if (c->hsc2) (void)hipHostFree(c->hsc2);
   for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
   delete c;
 }
@@ -214,6 +217,89 @@ ope_status run_step(ope_ctx* c, void* U, double tau, ope_step_info* info, double
   return out;
 }
 
+// Learned step after phase_residual(U) with its scalars in c->hsc: Y =
+// (U - P(R)) Lam^{-1}, Steps 2-4, then the judge (the new iterate's energy and
+// residual).  Accepted: U holds the new iterate and its residual phase is done
+// (scalars in c->hsc).  Rejected: U is restored and one plain step is taken
+// (its diagnostics in *plain).
+ope_status learned_core(ope_ctx* c, void* Uv, double tau, bool* accepted, ope_step_info* plain) {
+  *accepted = false;
+  const int N = (int)c->N;
+  const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)N;
+  const double E0 = c->hsc->energy, res0 = c->hsc->residual;
+  double* U = (double*)Uv;
+  int64_t np = 0;
+  if (c->net_judge) HIPCHK(hipMemcpyAsync(c->Ubak, U, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(net_apply_residual(c->net, (const double*)c->HU, c->rcol, U, (double*)c->Rb[0]));
+  HIPCHK(launch_rowmm(c, (const double*)c->Rb[0], c->Linv, nullptr, nullptr, nullptr, 0.0, 1.0, (double*)c->Y, 0, 0,
+                      &np));
+  ope_status st = phase_update(c, U, tau);
+  if (st != OPE_OK) return st;
+  if (!c->net_judge) {
+    // no judge: the learned iterate is kept unless the small solve failed (then U is unchanged)
+    st = sync_and_read_scalars(c);
+    if (st != OPE_OK) return st;
+    *accepted = c->hsc->err == 0;
+    return c->hsc->err == 0 ? OPE_OK : (ope_status)c->hsc->err;
+  }
+  HIPCHK(hipMemcpyAsync(c->hsc2, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream));
+  st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  HIPCHK(launch_cg_setup(c, c->rcol));   // the residual scalar from the column norms
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  const OpeScalars& s = *c->hsc;
+  if (c->hsc2->err == 0 && s.err == 0 && s.energy <= E0 + 1e-13 * std::fabs(E0) && s.residual <= res0) {
+    *accepted = true;
+    return OPE_OK;
+  }
+  HIPCHK(hipMemcpyAsync(U, c->Ubak, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return run_step(c, U, tau, plain, -1.0, nullptr);
+}
+
+ope_status check_learned(ope_ctx* c) {
+  if (!c->net) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  return OPE_OK;
+}
+
+// Algorithm 1 with learned steps judged by the plain step.
+ope_status solve_learned(ope_ctx* c, void* U, double tau, double res_tol, int32_t max_steps, ope_solve_info* si) {
+  bool ready = false;
+  ope_status st = OPE_OK;
+  for (;;) {
+    if (!ready) {
+      st = phase_residual(c, U);
+      if (st != OPE_OK) return st;
+      HIPCHK(launch_cg_setup(c, c->rcol));
+      st = sync_and_read_scalars(c);
+      if (st != OPE_OK) return st;
+      if (c->hsc->err != 0) return (ope_status)c->hsc->err;
+    }
+    si->residual = c->hsc->residual;
+    si->energy = c->hsc->energy;
+    si->drift = c->hsc->drift;
+    if (c->hsc->residual <= res_tol) {
+      si->converged = 1;
+      return OPE_OK;
+    }
+    if (si->steps >= max_steps) return OPE_OK;
+    bool acc = false;
+    ope_step_info plain;
+    memset(&plain, 0, sizeof(plain));
+    st = learned_core(c, U, tau, &acc, &plain);
+    if (st != OPE_OK && st != OPE_ECG_MAXIT) return st;
+    si->steps += 1;
+    if (acc) {
+      si->learned_steps += 1;
+      ready = c->net_judge != 0;   // the judge already evaluated the new iterate
+    } else {
+      si->inner_iterations += plain.inner_iterations;
+      ready = false;
+    }
+  }
+}
+
 }  // namespace
 
 ProfScope::ProfScope(ope_ctx* ctx, int kernel) : c(ctx), on(ctx->prof_kernel == kernel) {
@@ -294,6 +380,10 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   g.cx = op->kinetic / (op->h[0] * op->h[0]);
   g.cy = op->kinetic / (op->h[1] * op->h[1]);
   g.cz = op->dim == 3 ? op->kinetic / (op->h[2] * op->h[2]) : 0.0;
+  c->h[0] = op->h[0];
+  c->h[1] = op->h[1];
+  c->h[2] = op->dim == 3 ? op->h[2] : op->h[1];
+  c->kinetic = op->kinetic;
   c->eta_rel = 1e-2;
   c->eta_floor = precision == OPE_FP64 ? 1e-12 : 1e-6;
   c->max_iter = 2000;
@@ -361,6 +451,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   ok &= hipHostMalloc((void**)&c->hsc, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * N, hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hbuf, sizeof(double) * 2 * N, hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&c->hsc2, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     free_ctx(c);
     return OPE_ENOMEM;
@@ -581,6 +672,11 @@ ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t ma
   ope_solve_info si;
   memset(&si, 0, sizeof(si));
   ope_status st = OPE_OK;
+  if (c->net) {
+    st = solve_learned(c, U, tau, res_tol, max_steps, &si);
+    if (info) *info = si;
+    return st;
+  }
   double best = 1e300;
   int32_t since_best = 0;
   for (;;) {
@@ -609,6 +705,52 @@ ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t ma
     }
   }
   if (info) *info = si;
+  return st;
+}
+
+ope_status ope_set_preconditioner(ope_ctx* c, ope_net* net, int32_t judge) {
+  if (!c) return OPE_EINVAL;
+  if (!net) {
+    c->net = nullptr;
+    return OPE_OK;
+  }
+  if (net->ctx != c || net->max_batch < c->N || (judge != 0 && judge != 1)) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  c->net_judge = judge;
+  if (judge && !c->Ubak) {
+    if (balloc(&c->Ubak, sizeof(double) * (size_t)c->n * (size_t)c->N) != hipSuccess) return OPE_ENOMEM;
+  }
+  c->net = net;
+  return OPE_OK;
+}
+
+ope_status ope_step_learned(ope_ctx* c, void* U, double tau, ope_step_info* info, int32_t* accepted) {
+  if (!c || !U || !(tau > 0.0)) return OPE_EINVAL;
+  ope_status st = check_learned(c);
+  if (st != OPE_OK) return st;
+  if (accepted) *accepted = 0;
+  st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  HIPCHK(launch_cg_setup(c, c->rcol));
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  if (c->hsc->err != 0) {
+    fill_info(c, info, 0, (ope_status)c->hsc->err);
+    return (ope_status)c->hsc->err;
+  }
+  ope_step_info in;
+  memset(&in, 0, sizeof(in));
+  in.energy = c->hsc->energy;
+  in.residual = c->hsc->residual;
+  in.drift = c->hsc->drift;
+  bool acc = false;
+  ope_step_info plain;
+  memset(&plain, 0, sizeof(plain));
+  st = learned_core(c, U, tau, &acc, &plain);
+  in.inner_iterations = acc ? 0 : plain.inner_iterations;
+  in.status = st;
+  if (info) *info = in;
+  if (accepted) *accepted = acc ? 1 : 0;
   return st;
 }
 

@@ -64,6 +64,8 @@ struct ope_ctx {
   int device;
   hipStream_t stream;
   OpeGrid g;
+  double h[3];                  // grid spacings (h[2] = h[1] in 2D)
+  double kinetic;               // coefficient of -Lap in H
   int64_t n, N;
   int prec;                     // OPE_FP64 or OPE_MIXED
   int vw;                       // elements per 16-byte row chunk (fewer when N is not a multiple)
@@ -102,10 +104,35 @@ struct ope_ctx {
   int stream_wgs;               // work-groups of the flat streaming kernels
   int stream_pts;               // grid points per flat streaming work-group
   MarchShape ms;                // plane-marching stencil sweeps
+  // learned form: network (not owned) and the saved iterate its judge restores
+  ope_net* net;
+  int net_judge;                // 1: the plain step judges each learned iterate and replaces it if rejected
+  void* Ubak;
+  OpeScalars* hsc2;             // pinned: scalars right after a learned update
   // kernel timing (ope_profile_begin / ope_profile_end)
   int prof_kernel;              // kernel id being timed, -1 when off
   std::vector<hipEvent_t> prof_events;  // start/stop pairs, reused across sessions
   size_t prof_used;             // events recorded in this session
+};
+
+// The conv-net preconditioner (see k_net.hip).  Activations BF16
+// [sample][z][y][x][channel]; FP32 fields [sample][z][y][x].
+struct ope_net {
+  ope_ctx* ctx;                 // grid, stream and bound potential
+  int64_t max_batch;
+  int64_t n;
+  uint32_t m0, m1, m2;
+  double hh;                    // h^2
+  double kin;                   // kinetic coefficient: h^2 H = kin (6 - neighbours) + h^2 (V + shift)
+  int64_t adam_t;               // Adam steps taken
+  float *w, *adam_m, *adam_v, *grad;   // FP32 masters, moments, gradient (OPE_NET_PARAMS each)
+  uint16_t* wpk;                // packed BF16 operands of the forward and transposed layers
+  float* v2;                    // h^2 (V + shift), n values
+  uint16_t *x, *a1, *a2, *a3, *g3, *g4;  // input pair, activations, gradients
+  float* f;                     // network output
+  float* part;                  // weight-gradient partial rows
+  double *stage, *lpart, *coef, *dloss, *colsq;
+  double* hloss;                // pinned
 };
 
 // Brackets one launch with timing events when that kernel is being profiled.
@@ -166,6 +193,11 @@ hipError_t launch_small_solve_delta(ope_ctx* c, const double* Sb, const double* 
 hipError_t launch_small_to_f32(ope_ctx* c, const double* src, float* dst, int64_t count);
 hipError_t launch_jacobi_eig(ope_ctx* c, const double* Asym, double* evals);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
+
+// learned form (k_net.hip): column sums of squares of point-major FP64 rows
+// (B <= 256) into out, and E = U - P(R) for the context's N columns
+hipError_t launch_colsq(ope_ctx* c, const double* R, int64_t ld, int64_t B, double* out);
+hipError_t net_apply_residual(ope_net* t, const double* R, const double* colsq, const double* U, double* E);
 
 // device helpers shared by the kernels ---------------------------------------
 #ifdef __HIPCC__

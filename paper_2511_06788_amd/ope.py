@@ -71,7 +71,7 @@ class ope_solve_info(ctypes.Structure):
         ("drift", ctypes.c_double),
         ("inner_iterations", ctypes.c_int64),
         ("stalled", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("learned_steps", ctypes.c_int32),
     ]
 
 
@@ -114,7 +114,20 @@ SIGNATURES = {
     "ope_gram_f32": ([_P, _I32, _P, _I64, _I64, _P, _I64, _I64, _I64, _P], _I32),
     "ope_rowmm_f32": ([_P, _I32, _P, _P, _P, _P, _P, _D, _D, _P], _I32),
     "ope_profile_end": ([_P, ctypes.POINTER(ope_kernel_time)], _I32),
+    "ope_net_create": ([_P, _I64, ctypes.POINTER(_P)], _I32),
+    "ope_net_destroy": ([_P], _I32),
+    "ope_net_set_weights": ([_P, _P], _I32),
+    "ope_net_get_weights": ([_P, _P], _I32),
+    "ope_net_potential": ([_P, _P], _I32),
+    "ope_net_forward": ([_P, _P, _P, _I64, _P], _I32),
+    "ope_net_grad": ([_P, _P, _P, _P, _I64, ctypes.POINTER(_D), _P], _I32),
+    "ope_net_train_step": ([_P, _P, _P, _P, _I64, _D, ctypes.POINTER(_D)], _I32),
+    "ope_net_samples": ([_P, _P, _P, _I64, _I64, _P, _P], _I32),
+    "ope_set_preconditioner": ([_P, _P, _I32], _I32),
+    "ope_step_learned": ([_P, _P, _D, ctypes.POINTER(ope_step_info), ctypes.POINTER(_I32)], _I32),
 }
+
+OPE_NET_PARAMS = 15120
 
 
 def lib() -> ctypes.CDLL:
@@ -293,6 +306,112 @@ def ope_profile_end(ctx: int):
     t = ope_kernel_time()
     _check(lib().ope_profile_end(ctx, ctypes.byref(t)), "ope_profile_end")
     return t.launches, t.total_ms
+
+
+def ope_net_create(ctx: int, max_batch: int) -> int:
+    h = _P()
+    _check(lib().ope_net_create(ctx, int(max_batch), ctypes.byref(h)), "ope_net_create")
+    return h.value
+
+
+def ope_net_destroy(net: int) -> None:
+    _check(lib().ope_net_destroy(net), "ope_net_destroy")
+
+
+def ope_net_set_weights(net: int, w: np.ndarray) -> None:
+    w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+    if w.size != OPE_NET_PARAMS:
+        raise ValueError(f"{OPE_NET_PARAMS} weights expected")
+    _check(lib().ope_net_set_weights(net, w.ctypes.data), "ope_net_set_weights")
+
+
+def ope_net_get_weights(net: int) -> np.ndarray:
+    w = np.empty(OPE_NET_PARAMS, dtype=np.float32)
+    _check(lib().ope_net_get_weights(net, w.ctypes.data), "ope_net_get_weights")
+    return w
+
+
+def ope_net_potential(net: int, V2) -> None:
+    _check(lib().ope_net_potential(net, _ptr(V2)), "ope_net_potential")
+
+
+def ope_net_forward(net: int, X, V2, B: int, F) -> None:
+    _check(lib().ope_net_forward(net, _ptr(X), _ptr(V2), int(B), _ptr(F)), "ope_net_forward")
+
+
+def ope_net_grad(net: int, X, V2, T, B: int, want_grad: bool = True):
+    """Returns ``(loss, grad)`` (grad a host FP32 array, or None)."""
+    loss = _D(0.0)
+    g = np.empty(OPE_NET_PARAMS, dtype=np.float32) if want_grad else None
+    _check(lib().ope_net_grad(net, _ptr(X), _ptr(V2), _ptr(T), int(B), ctypes.byref(loss),
+                              g.ctypes.data if g is not None else None), "ope_net_grad")
+    return loss.value, g
+
+
+def ope_net_train_step(net: int, X, V2, T, B: int, lr: float) -> float:
+    loss = _D(0.0)
+    _check(lib().ope_net_train_step(net, _ptr(X), _ptr(V2), _ptr(T), int(B), float(lr), ctypes.byref(loss)),
+           "ope_net_train_step")
+    return loss.value
+
+
+def ope_net_samples(net: int, R, S, ld: int, B: int, X, T) -> None:
+    _check(lib().ope_net_samples(net, _ptr(R), _ptr(S), int(ld), int(B), _ptr(X), _ptr(T)), "ope_net_samples")
+
+
+def ope_set_preconditioner(ctx: int, net: Optional[int], judge: bool = True) -> None:
+    _check(lib().ope_set_preconditioner(ctx, net, 1 if judge else 0), "ope_set_preconditioner")
+
+
+def ope_step_learned(ctx: int, U, tau: float, allow_maxit: bool = True):
+    """Returns ``(info, accepted)``."""
+    info = ope_step_info()
+    acc = _I32(0)
+    st = lib().ope_step_learned(ctx, _ptr(U), tau, ctypes.byref(info), ctypes.byref(acc))
+    _check(st, "ope_step_learned", allow=(OPE_ECG_MAXIT,) if allow_maxit else ())
+    return info, bool(acc.value)
+
+
+def net_weights_to_layers(w: np.ndarray):
+    """Split a flat parameter vector into W1 (27,2,16), W2, W3 (27,16,16), W4 (27,16,1)."""
+    w = np.asarray(w).reshape(-1)
+    out, off = [], 0
+    for ci, co in ((2, 16), (16, 16), (16, 16), (16, 1)):
+        k = 27 * ci * co
+        out.append(w[off:off + k].reshape(27, ci, co))
+        off += k
+    return out
+
+
+def net_layers_to_weights(Ws) -> np.ndarray:
+    return np.concatenate([np.asarray(W, dtype=np.float32).reshape(-1) for W in Ws])
+
+
+class Net:
+    """Owns one ``ope_net`` created on a Context."""
+
+    def __init__(self, ctx, max_batch: int, weights: Optional[np.ndarray] = None):
+        self.ctx = ctx
+        self.handle = ope_net_create(ctx.handle, max_batch)
+        if weights is not None:
+            ope_net_set_weights(self.handle, weights)
+
+    def close(self):
+        if self.handle:
+            ope_net_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:

@@ -1,0 +1,263 @@
+"""GPU parity of the learned form (conv-net preconditioner) through the C ABI.
+
+* Forward: the network on the matrix cores equals the FP64 oracle network
+  (same BF16-representable weights and inputs) to the BF16 rounding of the
+  stored activations, on a grid with ragged tiles in every axis.
+* Loss and weight gradients equal the oracle's (energy-norm loss, backward
+  pass pinned by finite differences on the CPU) to BF16 precision.
+* Sample packing is exact up to FP32 rounding.
+* The learned step with the judge off equals the oracle's learned step; with
+  the judge on, a rejected learned iterate is replaced by exactly the plain
+  step; orthogonality is kept for any weights.
+* Training on the GPU lowers the loss as measured by the CPU oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import net as NN
+import workloads as W
+from tests.gpu_common import empty_dev, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    x = np.ascontiguousarray(a, dtype=np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _dev32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda")
+
+
+def _empty32(*shape):
+    import torch
+    return torch.empty(*shape, dtype=torch.float32, device="cuda")
+
+
+def _problem(m, N=4, seed=0):
+    return W.wells_3d(m=m, N=N, seed=seed)
+
+
+def _ctx(p):
+    from paper_2511_06788_amd import ope
+    return ope.Context(p.grid, p.V, p.N, kinetic=p.kinetic, shift=p.shift)
+
+
+def _bf16_weights(seed, scale=1.0):
+    return [bf16_round(scale * Wl) for Wl in NN.init_weights(seed)]
+
+
+def _op_with_v2(p, v2):
+    """Oracle operator whose h^2 (V + shift) is exactly the given field."""
+    h = p.grid.h[0]
+    return O.Operator(p.grid.m, p.grid.h, v2 / (h * h), kinetic=p.kinetic, shift=0.0)
+
+
+def _grid(m):
+    """Box grid with equal spacings on every axis (the network's requirement)."""
+    h = 1.0 / (max(m) + 1)
+    return W.Grid(m=tuple(m), h=(h, h, h), lo=(0.0, 0.0, 0.0))
+
+
+def _fields(m, B, rng):
+    shape = (m[2], m[1], m[0])
+    X = np.stack([bf16_round(rng.standard_normal(shape)) for _ in range(B)])
+    return X
+
+
+@pytest.mark.parametrize("m", [(20, 18, 17), (16, 8, 4), (5, 3, 2)])
+def test_forward_matches_oracle(m):
+    from paper_2511_06788_amd import ope
+    g = _grid(m)
+    V = W.gaussian_wells(g, 1)
+    p = W.Problem("net", g, V, 3, 1.0)
+    rng = np.random.default_rng(sum(m))
+    B = 3
+    Ws = _bf16_weights(5)
+    X = _fields(m, B, rng)
+    v2 = bf16_round((g.h[0] ** 2) * V).reshape(m[2], m[1], m[0])
+    say(f"net forward m={m}")
+    with _ctx(p) as ctx, ope.Net(ctx, B, ope.net_layers_to_weights(Ws)) as net:
+        Fd = _empty32(B, g.n)
+        ope.ope_net_forward(net.handle, _dev32(X.reshape(B, -1)), _dev32(v2.reshape(-1)), B, Fd)
+        F = to_host(Fd).astype(np.float64).reshape(B, m[2], m[1], m[0])
+        # the bound potential channel is h^2 (V + shift) in FP32
+        v2b = _empty32(g.n)
+        ope.ope_net_potential(net.handle, v2b)
+        assert np.allclose(to_host(v2b), (g.h[0] ** 2) * V, rtol=1e-6, atol=1e-6)
+    for b in range(B):
+        x = np.stack([X[b], v2], axis=-1)
+        ref = NN.forward(x, Ws)["f"]
+        err = np.linalg.norm(F[b] - ref) / np.linalg.norm(ref)
+        assert err <= 1.5e-2, (b, err)
+
+
+def _grad_case(m, B, seed):
+    g = _grid(m)
+    V = W.gaussian_wells(g, seed)
+    p = W.Problem("net", g, V, 3, 1.0)
+    v2 = bf16_round((g.h[0] ** 2) * V)
+    op = _op_with_v2(p, v2)
+    solve = O.GSolver(op, "dense")
+    rng = np.random.default_rng(seed)
+    shape = (m[2], m[1], m[0])
+    X, T = [], []
+    for _ in range(B):
+        r = rng.standard_normal(g.n)
+        x0 = bf16_round(r / np.linalg.norm(r))
+        X.append(x0.reshape(shape))
+        T.append(NN.target_for(x0, op, solve) * 1.0)   # t = H^{-1} x0 / h^2 (|x0| = 1 up to rounding)
+    return p, op, v2, np.stack(X), np.stack(T).astype(np.float32).astype(np.float64)
+
+
+def test_loss_and_gradients_match_oracle():
+    from paper_2511_06788_amd import ope
+    m, B = (18, 9, 6), 2
+    p, op, v2, X, T = _grad_case(m, B, 4)
+    shape = X.shape[1:]
+    Ws = _bf16_weights(2)
+    say("net grad")
+    with _ctx(p) as ctx, ope.Net(ctx, B, ope.net_layers_to_weights(Ws)) as net:
+        loss, grad = ope.ope_net_grad(net.handle, _dev32(X.reshape(B, -1)), _dev32(v2), _dev32(T.reshape(B, -1)), B)
+    xs = [np.stack([X[b], v2.reshape(shape)], axis=-1) for b in range(B)]
+    ref_loss, ref_grads = NN.batch_loss_and_grads(xs, list(T), Ws, NN.scaled_operator(op))
+    assert abs(loss - ref_loss) <= 2e-2 * abs(ref_loss), (loss, ref_loss)
+    got = ope.net_weights_to_layers(grad)
+    for L in range(4):
+        a, b = got[L].astype(np.float64).reshape(-1), ref_grads[L].reshape(-1)
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        assert rel <= 5e-2 and cos >= 0.998, (L, rel, cos)
+
+
+def test_samples_pack():
+    from paper_2511_06788_amd import ope
+    p = _problem(12, N=5)
+    n, N = p.grid.n, p.N
+    rng = np.random.default_rng(7)
+    R = rng.standard_normal((n, N))
+    R[:, 2] = 0.0
+    S = rng.standard_normal((n, N))
+    h2 = p.grid.h[0] ** 2
+    say("net samples")
+    with _ctx(p) as ctx, ope.Net(ctx, N) as net:
+        Xd, Td = _empty32(N, n), _empty32(N, n)
+        ope.ope_net_samples(net.handle, to_dev(R), to_dev(S), N, N, Xd, Td)
+        X, T = to_host(Xd), to_host(Td)
+    nr = np.linalg.norm(R, axis=0)
+    for b in range(N):
+        if nr[b] == 0:
+            assert np.all(X[b] == 0) and np.all(T[b] == 0)
+            continue
+        assert np.allclose(X[b], R[:, b] / nr[b], rtol=1e-6, atol=1e-7 * np.max(np.abs(R[:, b] / nr[b])))
+        assert np.allclose(T[b], S[:, b] / (nr[b] * h2), rtol=1e-6, atol=1e-7 * np.max(np.abs(S[:, b] / (nr[b] * h2))))
+
+
+def _identity_net(c):
+    """ch0 = relu(x), ch1 = relu(-x), passed through, f = c (ch0 - ch1) = c x:
+    P(r) = c h^2 r (all weights exact in BF16 for c a power of two)."""
+    Ws = [np.zeros((27, ci, co)) for ci, co in zip(NN.CHANNELS[:-1], NN.CHANNELS[1:])]
+    k = NN.TAPS.index((0, 0, 0))
+    Ws[0][k, 0, 0], Ws[0][k, 0, 1] = 1.0, -1.0
+    for L in (1, 2):
+        Ws[L][k, 0, 0] = Ws[L][k, 1, 1] = 1.0
+    Ws[3][k, 0, 0], Ws[3][k, 1, 0] = c, -c
+    return Ws
+
+
+@pytest.mark.parametrize("weights", ["identity", "random"])
+def test_learned_step_without_judge_matches_oracle(weights):
+    from paper_2511_06788_amd import ope
+    p = _problem(16, N=8, seed=2)
+    op = O.Operator(p.grid.m, p.grid.h, p.V, kinetic=p.kinetic, shift=p.shift)
+    Ws = _identity_net(1.0 / 16) if weights == "identity" else _bf16_weights(9, scale=0.5)
+    tau = 30.0
+    ref = NN.learned_step(op, p.U0, Ws, tau)
+    say(f"learned step, judge off, {weights}")
+    with _ctx(p) as ctx, ope.Net(ctx, p.N, ope.net_layers_to_weights(Ws)) as net:
+        ope.ope_set_preconditioner(ctx.handle, net.handle, judge=False)
+        Ud = to_dev(p.U0)
+        info, acc = ope.ope_step_learned(ctx.handle, Ud, tau)
+        U1 = to_host(Ud)
+    assert acc
+    step = np.max(np.abs(ref["U"] - p.U0))
+    assert step > 1e-4
+    assert np.max(np.abs(U1 - ref["U"])) <= 2e-2 * step
+    assert O.ortho_error(U1) <= 1e-12
+    assert abs(info.energy - O.energy(op, p.U0)) <= 1e-12 * abs(info.energy)
+
+
+def test_judge_falls_back_to_the_plain_step():
+    """Identity-type weights lower the energy but raise the relative residual
+    on a random start block, so the judge rejects them: the result is then
+    exactly the plain step's."""
+    from paper_2511_06788_amd import ope
+    p = _problem(16, N=8, seed=2)
+    op = O.Operator(p.grid.m, p.grid.h, p.V, kinetic=p.kinetic, shift=p.shift)
+    tau = 30.0
+    cand = NN.learned_step(op, p.U0, _identity_net(1.0 / 16), tau)["U"]
+    assert O.residual(op, cand) > O.residual(op, p.U0)     # the oracle's verdict: reject
+    say("learned step, judge on")
+    with _ctx(p) as ctx, ope.Net(ctx, p.N, ope.net_layers_to_weights(_identity_net(1.0 / 16))) as net:
+        Ud = to_dev(p.U0)
+        Up = to_dev(p.U0)
+        ip = ope.ope_step(ctx.handle, Up, tau)
+        ope.ope_set_preconditioner(ctx.handle, net.handle, judge=True)
+        info, acc = ope.ope_step_learned(ctx.handle, Ud, tau)
+        U1, Uplain = to_host(Ud), to_host(Up)
+    assert not acc
+    assert np.array_equal(U1, Uplain)
+    assert info.inner_iterations == ip.inner_iterations
+
+
+def test_zero_network_is_a_fixed_point_or_the_plain_step():
+    """P = 0 gives Y = U Lam^{-1}, for which Steps 2-4 return U itself."""
+    from paper_2511_06788_amd import ope
+    p = _problem(12, N=6, seed=1)
+    tau = 30.0
+    say("learned step, zero weights")
+    with _ctx(p) as ctx, ope.Net(ctx, p.N) as net:
+        ope.ope_set_preconditioner(ctx.handle, net.handle, judge=False)
+        Ud = to_dev(p.U0)
+        _, acc = ope.ope_step_learned(ctx.handle, Ud, tau)
+        U1 = to_host(Ud)
+    assert acc
+    assert np.max(np.abs(U1 - p.U0)) <= 1e-12
+
+
+def test_training_lowers_the_oracle_loss():
+    """A few hundred Adam steps on the GPU (its own forward and backward
+    kernels) on residual columns of one small problem; the loss of the trained
+    weights, evaluated by the CPU oracle on held-out columns, drops well below
+    that of the initial weights."""
+    from paper_2511_06788_amd import ope
+    m, B = (14, 12, 10), 8
+    p, op, v2, X, T = _grad_case(m, 24, 11)
+    shape = X.shape[1:]
+    W0 = _bf16_weights(3, scale=0.5)
+    A = NN.scaled_operator(op)
+    held = range(16, 24)
+    def oracle_loss(Ws):
+        xs = [np.stack([X[b], v2.reshape(shape)], axis=-1) for b in held]
+        return NN.batch_loss_and_grads(xs, [T[b] for b in held], Ws, A)[0]
+    say("net training")
+    with _ctx(p) as ctx, ope.Net(ctx, B, ope.net_layers_to_weights(W0)) as net:
+        Xd = _dev32(X.reshape(24, -1))
+        Td = _dev32(T.reshape(24, -1))
+        v2d = _dev32(v2)
+        losses = []
+        rng = np.random.default_rng(0)
+        for it in range(300):
+            k = int(rng.integers(0, 2)) * B
+            losses.append(ope.ope_net_train_step(net.handle, Xd[k:k + B], v2d, Td[k:k + B], B, 3e-3))
+        W1 = ope.net_weights_to_layers(ope.ope_net_get_weights(net.handle).astype(np.float64))
+    l0, l1 = oracle_loss(W0), oracle_loss(W1)
+    assert np.all(np.isfinite(losses))
+    assert l1 <= 0.5 * l0, (l0, l1, losses[:3], losses[-3:])
+    assert l1 < 1.0     # better than the zero network

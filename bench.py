@@ -12,11 +12,12 @@ before the timed region starts.
 
 Prints one JSON line: outer steps per second (whole job, one GPU), the live
 roofline of the dominant kernel (CG sweep B, timed with HIP events on the
-library's stream), per-kernel timings, the mixed-precision form's steps per
-second on the same workload, measured time-to-residual-1e-8 (plain FP64, and
-mixed precision with an FP64 finish) on a problem that converges within the
-run (64^3 grid, N = 17, which closes a level shell), and the CPU oracle timed
-on a bounded sample of the same workload.
+library's stream), per-kernel timings, the mixed-precision and learned forms'
+steps per second on the same workload, measured time-to-residual-1e-8 (plain
+FP64; mixed precision with an FP64 finish; learned steps judged by the plain
+step) on a problem that converges within the run (64^3 grid, N = 17, which
+closes a level shell), and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -103,7 +104,8 @@ def cpu_baseline(problem, tau, steps):
 def time_to_residual(ope, torch, tol=1e-8, switch=1e-5):
     """Wall time of Algorithm 1 from the start block to residual `tol` on a
     problem whose spectral gap lets it converge in a few hundred steps: plain
-    FP64, and the mixed form until `switch` followed by FP64 steps."""
+    FP64; the mixed form until `switch` followed by FP64 steps; and the learned
+    form (shipped weights, plain-step judge and fallback)."""
     import numpy as np
     import workloads as W
     p = W.wells_3d(m=64, N=17, seed=0)
@@ -134,7 +136,42 @@ def time_to_residual(ope, torch, tol=1e-8, switch=1e-5):
                               "fp64_steps": int(sf.steps), "switch_residual": switch, "seconds": t_mixed,
                               "final_residual": sf.residual, "final_drift": sf.drift}
     out["speedup_mixed"] = t_plain / t_mixed
+    with ope.Context(p.grid, p.V, p.N) as cl:
+        net = ope.Net(cl, p.N, ope.load_net_weights())
+        ope.ope_set_preconditioner(cl.handle, net.handle, judge=True)
+        ope.ope_solve(cl.handle, torch.from_numpy(p.U0).to("cuda"), tau, tol, 3)
+        U = torch.from_numpy(p.U0).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sl = ope.ope_solve(cl.handle, U, tau, tol, 20000)
+        torch.cuda.synchronize()
+        t_learned = time.perf_counter() - t0
+        net.close()
+    out["learned_judged"] = {"converged": bool(sl.converged), "steps": int(sl.steps),
+                             "learned_steps_kept": int(sl.learned_steps), "seconds": t_learned,
+                             "final_residual": sl.residual, "final_drift": sl.drift}
+    out["speedup_learned"] = t_plain / t_learned
     return out
+
+
+def learned_steps_per_second(ope, torch, p, tau, steps, warmup):
+    """The learned form on the benchmark workload: Algorithm 1 with the shipped
+    network, each learned step judged by the plain step (replaced when
+    rejected, with back-off after rejections), for a fixed number of steps."""
+    U = torch.from_numpy(p.U0).to("cuda")
+    with ope.Context(p.grid, p.V, p.N) as ctx:
+        net = ope.Net(ctx, p.N, ope.load_net_weights())
+        ope.ope_set_preconditioner(ctx.handle, net.handle, judge=True)
+        ope.ope_solve(ctx.handle, U, tau, 0.0, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        si = ope.ope_solve(ctx.handle, U, tau, 0.0, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        net.close()
+    return {"iter_per_s": si.steps / dt, "ms_per_step": 1e3 * dt / max(si.steps, 1),
+            "learned_steps_kept": int(si.learned_steps), "steps": int(si.steps), "warmup": warmup,
+            "residual_at_end": si.residual}
 
 
 def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
@@ -280,6 +317,8 @@ def main():
                            "inner_iterations_per_step": inner / max(args.steps, 1)},
             "mixed": steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, ks, args.warmup),
         }
+        log("learned form at the same workload")
+        out["forms"]["learned"] = learned_steps_per_second(ope, torch, p, args.tau, min(ks, 40), 5)
         log("time to residual on the 64^3 N=17 problem")
         out["time_to_residual"] = time_to_residual(ope, torch)
 

@@ -199,14 +199,21 @@ ope_status ope_rowmm_f32(ope_ctx* ctx, int32_t kind, const float* X0, const floa
  * masters (BF16 copies feed the matrix cores): OPE_NET_PARAMS values in the
  * order W1[27][2][16], W2[27][16][16], W3[27][16][16], W4[27][16][1], each
  * [tap][in][out] with taps (dz, dy, dx), dx fastest, each in (-1, 0, 1).
- * Training loss of a sample (x = r/|r|, target t = H^{-1} r / (|r| h^2)):
- *   (f - t)^T A (f - t) / (x . t),  A = h^2 H
- * (the squared H-norm error of P r relative to H^{-1} r: 1 for the zero
- * network), averaged over the batch.  3D grids with equal spacings only.
+ * Training losses of a sample (x = r/|r|, target t = H^{-1} r / (|r| h^2),
+ * A = h^2 H), averaged over the batch:
+ *   OPE_NET_LOSS_ENERGY    (f - t)^T A (f - t) / (x . t)   the squared H-norm
+ *                          error of P r relative to H^{-1} r;
+ *   OPE_NET_LOSS_RESIDUAL  |A f - x|^2 / |x|^2   the residual norm of the
+ *                          preconditioned direction (no target needed);
+ *   OPE_NET_LOSS_BOTH      their sum.
+ * Each is 1 for the zero network.  3D grids with equal spacings only.
  * Sample blocks X, T, F are device FP32 [sample][z][y][x] (n values each).
  * The learned step keeps Steps 2-4 (Section 4.1), so orthogonality holds for
  * any weights (Theorem 4.1's argument), and P(0) = 0 keeps eigenbases fixed. */
 #define OPE_NET_PARAMS 15120
+#define OPE_NET_LOSS_ENERGY 0
+#define OPE_NET_LOSS_RESIDUAL 1
+#define OPE_NET_LOSS_BOTH 2
 typedef struct ope_net ope_net;
 
 /* Network on ctx's grid with activations for up to max_batch (1..4096)
@@ -218,13 +225,17 @@ ope_status ope_net_destroy(ope_net* net);
 /* FP32 weights from / to a HOST array of OPE_NET_PARAMS values (set resets the Adam state). */
 ope_status ope_net_set_weights(ope_net* net, const float* w);
 ope_status ope_net_get_weights(ope_net* net, float* w);
+/* Training loss of ope_net_grad / ope_net_train_step (OPE_NET_LOSS_*; default energy). */
+ope_status ope_net_set_loss(ope_net* net, int32_t kind);
 /* The bound second input channel h^2 (V + shift) into V2 (device, n FP32). */
 ope_status ope_net_potential(ope_net* net, float* V2);
 /* F = f(X) for 1 <= B <= max_batch samples.  V2: the second input channel
  * (device, n FP32, shared by the batch), NULL for the bound one. */
 ope_status ope_net_forward(ope_net* net, const float* X, const float* V2, int64_t B, float* F);
 /* Batch loss into *loss (host, nullable) and its gradient into grad (HOST
- * array of OPE_NET_PARAMS, nullable).  ENONFINITE if the loss is not finite. */
+ * array of OPE_NET_PARAMS, nullable).  T may be NULL for the residual loss
+ * only.
+ * ENONFINITE if the loss is not finite. */
 ope_status ope_net_grad(ope_net* net, const float* X, const float* V2, const float* T, int64_t B,
                         double* loss, float* grad);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with

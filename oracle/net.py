@@ -21,7 +21,13 @@ relative to the exact one,
         = (f - t)^T A (f - t) / (x_0 . t),   t = H^{-1} r / (|r| h^2),  A = h^2 H,
 
 (1 for the zero network, 0 for the exact inverse), averaged over the batch.
-The grid spacing must be the same on all three axes.
+The second loss is the residual norm of the preconditioned direction,
+
+    |H P r - r|^2 / |r|^2 = |A f - x_0|^2 / |x_0|^2,
+
+also 1 for the zero network and 0 for the exact inverse; it weights errors at
+high frequencies by H^2 instead of H and needs no target.  The grid spacing
+must be the same on all three axes.
 
 Layout: a field of C channels on the grid is an array of shape
 ``(m2, m1, m0, C)`` (x fastest); taps are ordered ``(dz, dy, dx)`` with dx
@@ -145,14 +151,27 @@ def sample_loss(f: np.ndarray, t: np.ndarray, x0: np.ndarray, apply_A) -> tuple:
     return float(np.sum(e * Ae)) / den, 2.0 * Ae / den
 
 
-def batch_loss_and_grads(xs: Sequence[np.ndarray], ts: Sequence[np.ndarray], Ws: Sequence[np.ndarray], apply_A):
-    """Batch-mean loss and its weight gradients."""
+def sample_residual_loss(f: np.ndarray, x0: np.ndarray, apply_A) -> tuple:
+    """Residual-norm loss of one sample and its derivative in f (A is symmetric)."""
+    e = apply_A(f) - x0
+    xx = float(np.sum(x0 * x0))
+    return float(np.sum(e * e)) / xx, 2.0 * apply_A(e) / xx
+
+
+def batch_loss_and_grads(xs: Sequence[np.ndarray], ts, Ws: Sequence[np.ndarray], apply_A, kind: str = "energy"):
+    """Batch-mean loss (``kind`` "energy" or "residual"; targets unused by the
+    latter) and its weight gradients."""
     B = len(xs)
     loss = 0.0
     grads = [np.zeros_like(W) for W in Ws]
-    for x, t in zip(xs, ts):
+    for b, x in enumerate(xs):
         c = forward(x, Ws)
-        l, df = sample_loss(c["f"], t, x[..., 0], apply_A)
+        if kind == "energy":
+            l, df = sample_loss(c["f"], ts[b], x[..., 0], apply_A)
+        elif kind == "residual":
+            l, df = sample_residual_loss(c["f"], x[..., 0], apply_A)
+        else:
+            raise ValueError(kind)
         loss += l / B
         g = backward(c, df / B, Ws)
         for k in range(4):

@@ -416,6 +416,74 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ F, 
   g[b * n + v] = to_bf16((float)(coef[b] * (double)ae));
 }
 
+// residual-norm loss: e = A f - x, L_b = |e|^2 / |x|^2, dL/df_b = 2 A e / |x|^2 / B
+__device__ __forceinline__ float apply_a1(const float* __restrict__ f, const float* __restrict__ v2, uint32_t v,
+                                          uint32_t m0, uint32_t m1, uint32_t m2, float kin) {
+  const Vox p = vox_of(v, m0, m1);
+  float nb = 0.f;
+  const uint32_t s1 = m0, s2 = m0 * m1;
+  if (p.x > 0) nb += f[v - 1];
+  if (p.x + 1 < (int)m0) nb += f[v + 1];
+  if (p.y > 0) nb += f[v - s1];
+  if (p.y + 1 < (int)m1) nb += f[v + s1];
+  if (p.z > 0) nb += f[v - s2];
+  if (p.z + 1 < (int)m2) nb += f[v + s2];
+  return kin * (6.f * f[v] - nb) + v2[v] * f[v];
+}
+
+__global__ __launch_bounds__(256) void k_rloss_part(const float* __restrict__ F, const float* __restrict__ X,
+                                                    const float* __restrict__ v2, uint32_t m0, uint32_t m1,
+                                                    uint32_t m2, float kin, float* __restrict__ E,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[256];
+  const uint64_t n = (uint64_t)m0 * m1 * m2;
+  const uint32_t b = blockIdx.y;
+  const float* f = F + b * n;
+  const float* x = X + b * n;
+  double ee = 0.0, xx = 0.0;
+  const uint32_t p0 = blockIdx.x * LOSS_PTS;
+  for (uint32_t q = threadIdx.x; q < LOSS_PTS; q += 256) {
+    const uint32_t v = p0 + q;
+    if (v >= n) break;
+    const float e = apply_a1(f, v2, v, m0, m1, m2, kin) - x[v];
+    E[b * n + v] = e;
+    ee += (double)e * (double)e;
+    xx += (double)x[v] * (double)x[v];
+  }
+  ee = wg_sum_d(ee, sh);
+  xx = wg_sum_d(xx, sh);
+  if (threadIdx.x == 0) {
+    part[((uint64_t)b * gridDim.x + blockIdx.x) * 2 + 0] = ee;
+    part[((uint64_t)b * gridDim.x + blockIdx.x) * 2 + 1] = xx;
+  }
+}
+
+// energy + residual losses: g = coefE A (f - t) + coefR A e
+__global__ __launch_bounds__(256) void k_bloss_grad(const float* __restrict__ F, const float* __restrict__ T,
+                                                    const float* __restrict__ E, const float* __restrict__ v2,
+                                                    uint32_t m0, uint32_t m1, uint32_t m2, float kin,
+                                                    const double* __restrict__ coefE, const double* __restrict__ coefR,
+                                                    uint16_t* __restrict__ g) {
+  const uint64_t n = (uint64_t)m0 * m1 * m2;
+  const uint32_t b = blockIdx.y;
+  const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  const float a1 = apply_a(F + b * n, T + b * n, v2, v, m0, m1, m2, kin);
+  const float a2 = apply_a1(E + b * n, v2, v, m0, m1, m2, kin);
+  g[b * n + v] = to_bf16((float)(coefE[b] * (double)a1 + coefR[b] * (double)a2));
+}
+
+__global__ __launch_bounds__(256) void k_rloss_grad(const float* __restrict__ E, const float* __restrict__ v2,
+                                                    uint32_t m0, uint32_t m1, uint32_t m2, float kin,
+                                                    const double* __restrict__ coef, uint16_t* __restrict__ g) {
+  const uint64_t n = (uint64_t)m0 * m1 * m2;
+  const uint32_t b = blockIdx.y;
+  const uint32_t v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  const float ae = apply_a1(E + b * n, v2, v, m0, m1, m2, kin);
+  g[b * n + v] = to_bf16((float)(coef[b] * (double)ae));
+}
+
 // ---------------------------------------------------------------------------
 // input / output packing
 // ---------------------------------------------------------------------------
@@ -575,7 +643,7 @@ constexpr int WGRAD_GROUPS = 32;      // first-stage groups of their fixed-order
 void free_net(ope_net* t) {
   if (!t) return;
   void* ptrs[] = {t->w, t->adam_m, t->adam_v, t->grad, t->wpk, t->v2, t->x, t->a1, t->a2, t->a3, t->g3, t->g4,
-                  t->f, t->part, t->stage, t->lpart, t->coef, t->dloss, t->colsq};
+                  t->f, t->e, t->part, t->stage, t->lpart, t->coef, t->dloss, t->colsq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (t->hloss) (void)hipHostFree(t->hloss);
@@ -626,13 +694,35 @@ ope_status grad_pass(ope_net* t, const float* X, const float* v2, const float* T
   HIPCHK(forward(t, B, t->f));
   // loss and dL/df
   const uint32_t chunks = (uint32_t)((n + LOSS_PTS - 1) / LOSS_PTS);
-  hipLaunchKernelGGL(k_loss_part, dim3(chunks, B), dim3(256), 0, s, t->f, T, X, v2, t->m0, t->m1, t->m2,
-                     (float)t->kin, t->lpart);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, t->lpart, chunks, B, t->coef, t->dloss);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_loss_grad, dim3((uint32_t)((n + 255) / 256), B), dim3(256), 0, s, t->f, T, v2, t->m0, t->m1,
-                     t->m2, (float)t->kin, t->coef, t->g4);
+  const int kind = t->loss_kind;
+  const dim3 pgrid((uint32_t)((n + 255) / 256), B);
+  double* lossE = t->dloss;
+  double* lossR = kind == OPE_NET_LOSS_RESIDUAL ? t->dloss : t->dloss + 1;
+  // per sample: coef = 2 / (den B), loss = mean(num / den); den = x . t (energy) or |x|^2 (residual)
+  if (kind != OPE_NET_LOSS_RESIDUAL) {
+    hipLaunchKernelGGL(k_loss_part, dim3(chunks, B), dim3(256), 0, s, t->f, T, X, v2, t->m0, t->m1, t->m2,
+                       (float)t->kin, t->lpart);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, t->lpart, chunks, B, t->coef, lossE);
+    HIPCHK(hipGetLastError());
+  }
+  if (kind != OPE_NET_LOSS_ENERGY) {
+    hipLaunchKernelGGL(k_rloss_part, dim3(chunks, B), dim3(256), 0, s, t->f, X, v2, t->m0, t->m1, t->m2,
+                       (float)t->kin, t->e, t->lpart);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, t->lpart, chunks, B, t->coef + t->max_batch, lossR);
+    HIPCHK(hipGetLastError());
+  }
+  if (kind == OPE_NET_LOSS_ENERGY) {
+    hipLaunchKernelGGL(k_loss_grad, pgrid, dim3(256), 0, s, t->f, T, v2, t->m0, t->m1, t->m2, (float)t->kin, t->coef,
+                       t->g4);
+  } else if (kind == OPE_NET_LOSS_RESIDUAL) {
+    hipLaunchKernelGGL(k_rloss_grad, pgrid, dim3(256), 0, s, t->e, v2, t->m0, t->m1, t->m2, (float)t->kin,
+                       t->coef + t->max_batch, t->g4);
+  } else {
+    hipLaunchKernelGGL(k_bloss_grad, pgrid, dim3(256), 0, s, t->f, T, t->e, v2, t->m0, t->m1, t->m2, (float)t->kin,
+                       t->coef, t->coef + t->max_batch, t->g4);
+  }
   HIPCHK(hipGetLastError());
   // voxel ranges of the weight-gradient partials
   uint32_t rps = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((int64_t)((n + 1023) / 1024), WGRAD_ROWS / B));
@@ -669,10 +759,11 @@ hipError_t pack_weights(ope_net* t) {
 }
 
 ope_status read_loss(ope_net* t, double* loss) {
-  HIPCHK(hipMemcpyAsync(t->hloss, t->dloss, sizeof(double), hipMemcpyDeviceToHost, t->ctx->stream));
+  HIPCHK(hipMemcpyAsync(t->hloss, t->dloss, 2 * sizeof(double), hipMemcpyDeviceToHost, t->ctx->stream));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
-  if (loss) *loss = *t->hloss;
-  return std::isfinite(*t->hloss) ? OPE_OK : OPE_ENONFINITE;
+  const double l = t->loss_kind == OPE_NET_LOSS_BOTH ? t->hloss[0] + t->hloss[1] : t->hloss[0];
+  if (loss) *loss = l;
+  return std::isfinite(l) ? OPE_OK : OPE_ENONFINITE;
 }
 
 ope_status check_batch(const ope_net* t, int64_t B) {
@@ -730,6 +821,7 @@ ope_status ope_net_create(ope_ctx* ctx, int64_t max_batch, ope_net** out) {
   t->hh = h * h;
   t->kin = ctx->kinetic;
   t->adam_t = 0;
+  t->loss_kind = OPE_NET_LOSS_ENERGY;
   const uint64_t nb = (uint64_t)t->n * (uint64_t)max_batch;
   const uint64_t chunks = (t->n + LOSS_PTS - 1) / LOSS_PTS;
   bool ok = true;
@@ -747,13 +839,14 @@ ope_status ope_net_create(ope_ctx* ctx, int64_t max_batch, ope_net** out) {
   al((void**)&t->g3, sizeof(uint16_t) * 16 * nb);
   al((void**)&t->g4, sizeof(uint16_t) * nb);
   al((void**)&t->f, sizeof(float) * nb);
+  al((void**)&t->e, sizeof(float) * nb);
   al((void**)&t->part, sizeof(float) * (size_t)std::max<int64_t>(WGRAD_ROWS, max_batch) * OPE_NET_PARAMS);
   al((void**)&t->stage, sizeof(double) * (size_t)WGRAD_GROUPS * OPE_NET_PARAMS);
   al((void**)&t->lpart, sizeof(double) * 2 * chunks * (uint64_t)max_batch);
-  al((void**)&t->coef, sizeof(double) * (size_t)max_batch);
-  al((void**)&t->dloss, sizeof(double));
+  al((void**)&t->coef, sizeof(double) * 2 * (size_t)max_batch);
+  al((void**)&t->dloss, sizeof(double) * 2);
   al((void**)&t->colsq, sizeof(double) * 256);
-  ok &= hipHostMalloc((void**)&t->hloss, sizeof(double), hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&t->hloss, 2 * sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     free_net(t);
     return OPE_ENOMEM;
@@ -815,7 +908,7 @@ ope_status ope_net_forward(ope_net* t, const float* X, const float* V2, int64_t 
 
 ope_status ope_net_grad(ope_net* t, const float* X, const float* V2, const float* T, int64_t B, double* loss,
                         float* grad) {
-  if (!t || !X || !T) return OPE_EINVAL;
+  if (!t || !X || (!T && t->loss_kind != OPE_NET_LOSS_RESIDUAL)) return OPE_EINVAL;
   ope_status st = check_batch(t, B);
   if (st != OPE_OK) return st;
   st = grad_pass(t, X, V2 ? V2 : t->v2, T, (uint32_t)B);
@@ -827,7 +920,7 @@ ope_status ope_net_grad(ope_net* t, const float* X, const float* V2, const float
 
 ope_status ope_net_train_step(ope_net* t, const float* X, const float* V2, const float* T, int64_t B, double lr,
                               double* loss) {
-  if (!t || !X || !T || !(lr > 0.0)) return OPE_EINVAL;
+  if (!t || !X || (!T && t->loss_kind != OPE_NET_LOSS_RESIDUAL) || !(lr > 0.0)) return OPE_EINVAL;
   ope_status st = check_batch(t, B);
   if (st != OPE_OK) return st;
   st = grad_pass(t, X, V2 ? V2 : t->v2, T, (uint32_t)B);
@@ -856,6 +949,12 @@ ope_status ope_net_samples(ope_net* t, const double* R, const double* S, int64_t
                      (uint64_t)c->n, t->colsq, 1.0 / t->hh, t->v2, (void*)T);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
+  return OPE_OK;
+}
+
+ope_status ope_net_set_loss(ope_net* t, int32_t kind) {
+  if (!t || kind < OPE_NET_LOSS_ENERGY || kind > OPE_NET_LOSS_BOTH) return OPE_EINVAL;
+  t->loss_kind = kind;
   return OPE_OK;
 }
 

@@ -15,6 +15,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -263,11 +264,35 @@ ope_status check_learned(ope_ctx* c) {
   return OPE_OK;
 }
 
-// Algorithm 1 with learned steps judged by the plain step.
+// Algorithm 1 with learned steps judged by the plain step.  After a rejected
+// learned step the next `backoff` steps are plain (1, 2, 4, ... up to 64,
+// reset by an accepted one), so a network that stops helping late in a solve
+// costs little more than the plain iteration.
 ope_status solve_learned(ope_ctx* c, void* U, double tau, double res_tol, int32_t max_steps, ope_solve_info* si) {
-  bool ready = false;
+  bool ready = false;      // residual phase of the current U done, scalars in c->hsc
+  int32_t skip = 0, backoff = 0;
   ope_status st = OPE_OK;
   for (;;) {
+    const bool last = si->steps >= max_steps;
+    if (!last && skip > 0) {
+      // a plain step (with the convergence test of Algorithm 1 on the way)
+      ope_step_info s;
+      bool conv = false;
+      st = run_step(c, U, tau, &s, res_tol, &conv);
+      if (st != OPE_OK && st != OPE_ECG_MAXIT) return st;
+      si->residual = s.residual;
+      si->energy = s.energy;
+      si->drift = s.drift;
+      if (conv) {
+        si->converged = 1;
+        return OPE_OK;
+      }
+      si->steps += 1;
+      si->inner_iterations += s.inner_iterations;
+      --skip;
+      ready = false;
+      continue;
+    }
     if (!ready) {
       st = phase_residual(c, U);
       if (st != OPE_OK) return st;
@@ -283,7 +308,7 @@ ope_status solve_learned(ope_ctx* c, void* U, double tau, double res_tol, int32_
       si->converged = 1;
       return OPE_OK;
     }
-    if (si->steps >= max_steps) return OPE_OK;
+    if (last) return OPE_OK;
     bool acc = false;
     ope_step_info plain;
     memset(&plain, 0, sizeof(plain));
@@ -293,9 +318,12 @@ ope_status solve_learned(ope_ctx* c, void* U, double tau, double res_tol, int32_
     if (acc) {
       si->learned_steps += 1;
       ready = c->net_judge != 0;   // the judge already evaluated the new iterate
+      backoff = 0;
     } else {
       si->inner_iterations += plain.inner_iterations;
       ready = false;
+      backoff = backoff ? std::min(2 * backoff, 64) : 1;
+      skip = backoff;
     }
   }
 }

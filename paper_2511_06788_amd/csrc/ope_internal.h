@@ -125,11 +125,13 @@ struct ope_net {
   double hh;                    // h^2
   double kin;                   // kinetic coefficient: h^2 H = kin (6 - neighbours) + h^2 (V + shift)
   int64_t adam_t;               // Adam steps taken
+  int32_t loss_kind;            // OPE_NET_LOSS_ENERGY or OPE_NET_LOSS_RESIDUAL
   float *w, *adam_m, *adam_v, *grad;   // FP32 masters, moments, gradient (OPE_NET_PARAMS each)
   uint16_t* wpk;                // packed BF16 operands of the forward and transposed layers
   float* v2;                    // h^2 (V + shift), n values
   uint16_t *x, *a1, *a2, *a3, *g3, *g4;  // input pair, activations, gradients
   float* f;                     // network output
+  float* e;                     // residual-norm loss: A f - x
   float* part;                  // weight-gradient partial rows
   double *stage, *lpart, *coef, *dloss, *colsq;
   double* hloss;                // pinned

@@ -119,6 +119,7 @@ SIGNATURES = {
     "ope_net_set_weights": ([_P, _P], _I32),
     "ope_net_get_weights": ([_P, _P], _I32),
     "ope_net_potential": ([_P, _P], _I32),
+    "ope_net_set_loss": ([_P, _I32], _I32),
     "ope_net_forward": ([_P, _P, _P, _I64, _P], _I32),
     "ope_net_grad": ([_P, _P, _P, _P, _I64, ctypes.POINTER(_D), _P], _I32),
     "ope_net_train_step": ([_P, _P, _P, _P, _I64, _D, ctypes.POINTER(_D)], _I32),
@@ -128,6 +129,9 @@ SIGNATURES = {
 }
 
 OPE_NET_PARAMS = 15120
+OPE_NET_LOSS_ENERGY = 0
+OPE_NET_LOSS_RESIDUAL = 1
+OPE_NET_LOSS_BOTH = 2
 
 
 def lib() -> ctypes.CDLL:
@@ -331,6 +335,10 @@ def ope_net_get_weights(net: int) -> np.ndarray:
     return w
 
 
+def ope_net_set_loss(net: int, kind: int) -> None:
+    _check(lib().ope_net_set_loss(net, int(kind)), "ope_net_set_loss")
+
+
 def ope_net_potential(net: int, V2) -> None:
     _check(lib().ope_net_potential(net, _ptr(V2)), "ope_net_potential")
 
@@ -385,6 +393,17 @@ def net_weights_to_layers(w: np.ndarray):
 
 def net_layers_to_weights(Ws) -> np.ndarray:
     return np.concatenate([np.asarray(W, dtype=np.float32).reshape(-1) for W in Ws])
+
+
+NET_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "net_wells64.npy")
+
+
+def load_net_weights(path: str = NET_WEIGHTS) -> np.ndarray:
+    """Trained weights shipped with the package (FP32, OPE_NET_PARAMS values)."""
+    w = np.load(path, allow_pickle=False).astype(np.float32).reshape(-1)
+    if w.size != OPE_NET_PARAMS:
+        raise ValueError(f"{path}: {w.size} values, {OPE_NET_PARAMS} expected")
+    return w
 
 
 class Net:

@@ -116,17 +116,27 @@ def _grad_case(m, B, seed):
     return p, op, v2, np.stack(X), np.stack(T).astype(np.float32).astype(np.float64)
 
 
-def test_loss_and_gradients_match_oracle():
+@pytest.mark.parametrize("kind", ["energy", "residual", "both"])
+def test_loss_and_gradients_match_oracle(kind):
     from paper_2511_06788_amd import ope
     m, B = (18, 9, 6), 2
     p, op, v2, X, T = _grad_case(m, B, 4)
     shape = X.shape[1:]
     Ws = _bf16_weights(2)
-    say("net grad")
+    say(f"net grad {kind}")
     with _ctx(p) as ctx, ope.Net(ctx, B, ope.net_layers_to_weights(Ws)) as net:
-        loss, grad = ope.ope_net_grad(net.handle, _dev32(X.reshape(B, -1)), _dev32(v2), _dev32(T.reshape(B, -1)), B)
+        ope.ope_net_set_loss(net.handle, {"energy": ope.OPE_NET_LOSS_ENERGY, "residual": ope.OPE_NET_LOSS_RESIDUAL,
+                                          "both": ope.OPE_NET_LOSS_BOTH}[kind])
+        Td = _dev32(T.reshape(B, -1)) if kind != "residual" else None
+        loss, grad = ope.ope_net_grad(net.handle, _dev32(X.reshape(B, -1)), _dev32(v2), Td, B)
     xs = [np.stack([X[b], v2.reshape(shape)], axis=-1) for b in range(B)]
-    ref_loss, ref_grads = NN.batch_loss_and_grads(xs, list(T), Ws, NN.scaled_operator(op))
+    A = NN.scaled_operator(op)
+    if kind == "both":
+        le, ge = NN.batch_loss_and_grads(xs, list(T), Ws, A, "energy")
+        lr, gr = NN.batch_loss_and_grads(xs, list(T), Ws, A, "residual")
+        ref_loss, ref_grads = le + lr, [a + b for a, b in zip(ge, gr)]
+    else:
+        ref_loss, ref_grads = NN.batch_loss_and_grads(xs, list(T), Ws, A, kind)
     assert abs(loss - ref_loss) <= 2e-2 * abs(ref_loss), (loss, ref_loss)
     got = ope.net_weights_to_layers(grad)
     for L in range(4):

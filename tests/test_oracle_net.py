@@ -4,7 +4,8 @@
 * ``conv`` of a one-hot kernel is a shift; with a 7-point Laplacian kernel it
   reproduces the oracle's finite-difference operator (with h = 1).
 * Weight gradients match central finite differences of the batch loss.
-* The energy-norm loss is 1 for the zero network and 0 for the exact inverse.
+* Both losses (energy norm, residual norm) are 1 for the zero network and 0
+  for the exact inverse; their weight gradients match finite differences.
 * The learned step with the exact inverse in place of the network is the
   paper's step with exact Step 1 (gradient form ``GU = (U - H^{-1} R) Lam^{-1}``);
   with any network it keeps orthogonality and leaves an eigenbasis fixed.
@@ -66,19 +67,20 @@ def _samples(op, rng, count):
     return xs, ts
 
 
-def test_weight_gradients_match_finite_differences():
+@pytest.mark.parametrize("kind", ["energy", "residual"])
+def test_weight_gradients_match_finite_differences(kind):
     op, rng = _small_problem()
     A = NN.scaled_operator(op)
     Ws = NN.init_weights(7)
     xs, ts = _samples(op, rng, 2)
-    loss, grads = NN.batch_loss_and_grads(xs, ts, Ws, A)
+    loss, grads = NN.batch_loss_and_grads(xs, ts, Ws, A, kind)
     eps = 1e-6
     for li, idx in [(0, (3, 1, 5)), (1, (13, 7, 2)), (2, (26, 15, 15)), (3, (0, 4, 0)), (1, (4, 0, 9)), (0, (20, 0, 2))]:
         Wp = [W.copy() for W in Ws]
         Wm = [W.copy() for W in Ws]
         Wp[li][idx] += eps
         Wm[li][idx] -= eps
-        fd = (NN.batch_loss_and_grads(xs, ts, Wp, A)[0] - NN.batch_loss_and_grads(xs, ts, Wm, A)[0]) / (2 * eps)
+        fd = (NN.batch_loss_and_grads(xs, ts, Wp, A, kind)[0] - NN.batch_loss_and_grads(xs, ts, Wm, A, kind)[0]) / (2 * eps)
         assert abs(fd - grads[li][idx]) <= 1e-6 * max(1.0, abs(fd)), (li, idx, fd, grads[li][idx])
 
 
@@ -95,6 +97,13 @@ def test_energy_loss_of_zero_and_exact_network():
         d = rng.standard_normal(t.shape)
         l2, _ = NN.sample_loss(t + d, t, x[..., 0], A)
         assert l2 > 0.0
+        # residual norm: x0 = A t exactly for the normalised column, so
+        # the zero network leaves the whole residual and t none of it
+        x0 = A(t)
+        r0, _ = NN.sample_residual_loss(np.zeros_like(t), x0, A)
+        r1, _ = NN.sample_residual_loss(t, x0, A)
+        assert abs(r0 - 1.0) <= 1e-12 and r1 <= 1e-24
+        assert abs(NN.sample_residual_loss(t + d, x0, A)[0] - np.sum(A(d) ** 2) / np.sum(x0 * x0)) <= 1e-10
 
 
 def test_learned_step_with_exact_inverse_is_the_paper_step(monkeypatch):

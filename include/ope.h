@@ -263,6 +263,12 @@ ope_status ope_set_preconditioner(ope_ctx* ctx, ope_net* net, int32_t judge);
  * EINVAL if no network is set. */
 ope_status ope_step_learned(ope_ctx* ctx, void* U, double tau, ope_step_info* info, int32_t* accepted);
 
+/* Step 1's CG runs in chunks of 4 iterations between host convergence checks;
+ * with graphs on (the default) each chunk is one replay of a HIP graph
+ * captured once per context (on a private stream, replayed on the context's
+ * stream), with the same kernels and results as eager launches.  enable 0/1. */
+ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
+
 /* --- Launch shape of the stencil / CG sweeps (tuning) --------------------
  * The sweeps march along the slowest grid axis; a work-group covers q passes
  * of 256/8 grid points of one x segment (q in {1, 2, 4}; more passes per
@@ -272,11 +278,14 @@ ope_status ope_step_learned(ope_ctx* ctx, void* U, double tau, ope_step_info* in
  * q_max = 0 lets the library choose.  flags: OPE_SWEEP_CHUNK_MAJOR puts the
  * work-groups of one column chunk next to each other (so one XCD streams one
  * chunk of every side line) instead of those of one side line;
- * OPE_SWEEP_NONTEMPORAL writes the swept outputs with non-temporal stores.
+ * OPE_SWEEP_NONTEMPORAL writes the swept outputs with non-temporal stores;
+ * OPE_SWEEP_NARROW keeps 8-vector column chunks for rows of at most 32
+ * vector columns (which by default a work-group takes whole).
  * Results do not depend on the shape beyond the summation order of the CG dot
  * products.  Synchronises; on OPE_EINVAL the previous shape stays. */
 #define OPE_SWEEP_CHUNK_MAJOR 1
 #define OPE_SWEEP_NONTEMPORAL 2
+#define OPE_SWEEP_NARROW 4
 ope_status ope_set_sweep_shape(ope_ctx* ctx, int32_t q_max, int32_t march_chunks, int32_t flags);
 
 /* The shape in use (outputs nullable, host). */

@@ -233,10 +233,14 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
     }
     // stage plane z for the x neighbours
     T* buf = lds + (z & 1u) * (Q * OPE_WG * VW);
+    // lanes past the last whole slot (when ncv does not divide the work-group)
+    // hold no point, and their index would alias the next pass's first slot
+    if (slot < ms.pp) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+      for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int v = 0; v < VW; ++v) buf[((q * ms.pp + slot) * ms.ncv + cv) * VW + v] = pz[q][v];
+        for (int v = 0; v < VW; ++v) buf[((q * ms.pp + slot) * ms.ncv + cv) * VW + v] = pz[q][v];
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -494,18 +498,32 @@ static hipError_t launch_march(ope_ctx* c, const void* F0, const void* F1, void*
   return hipGetLastError();
 }
 
-void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt) {
+void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow) {
   MarchShape& ms = c->ms;
   ms.order = order ? 1u : 0u;
   ms.nt = nt ? 1u : 0u;
   const OpeGrid& g = c->g;
   const uint32_t NV = (uint32_t)(c->N / c->vw);
-  // 8 vector columns of 16 bytes: one 128-byte line per grid point and work-group
-  ms.ncv = NV < 8u ? NV : 8u;
+  // Column chunk of a work-group: whole rows when they have at most 32 vector
+  // columns (one contiguous run of pp rows per pass, no partly idle chunk),
+  // else 8 vector columns (one 128-byte line per grid point and work-group).
+  ms.ncv = (NV <= 32u && !narrow) ? NV : (NV < 8u ? NV : 8u);
   ms.pp = OPE_WG / ms.ncv;
+  // passes per plane (1, 2 or 4, at most q_max, default 2; a larger one only
+  // while the smaller does not cover the x line): the one that leaves the
+  // fewest idle lanes in the last x segment, the larger on a tie
   const uint32_t qcap = q_max > 0 ? (uint32_t)q_max : 2u;
   uint32_t q = 1;
-  while (q < qcap && q < 4u && q * ms.pp < g.m0) q *= 2;
+  double best = -1.0;
+  for (uint32_t qq = 1; qq <= qcap && qq <= 4u; qq *= 2) {
+    if (qq > 1 && (qq / 2) * ms.pp >= g.m0) break;
+    const uint32_t xs = qq * ms.pp, nx = (g.m0 + xs - 1) / xs;
+    const double use = (double)g.m0 / (double)(nx * xs);
+    if (use >= best - 1e-12) {
+      q = qq;
+      best = use > best ? use : best;
+    }
+  }
   ms.q = q;
   ms.xseg = q * ms.pp;
   ms.nxs = (g.m0 + ms.xseg - 1) / ms.xseg;

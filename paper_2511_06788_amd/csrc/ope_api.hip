@@ -41,6 +41,8 @@ hipError_t balloc(void** p, size_t bytes) {
   return hipMalloc(p, bytes > 0 ? bytes : 1);
 }
 
+void drop_graphs(ope_ctx* c);
+
 void free_ctx(ope_ctx* c) {
   if (!c) return;
   void* dptrs[] = {c->diag, c->diag32, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T,
@@ -54,6 +56,8 @@ void free_ctx(ope_ctx* c) {
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->hsc2) (void)hipHostFree(c->hsc2);
   for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -90,30 +94,87 @@ ope_status phase_residual(ope_ctx* c, const void* Uv) {
   return OPE_OK;
 }
 
-// CG iterations on H Y = U from the state prepared in rho/target/active, with
-// r in c->Rb[0]; returns the iteration count in *iters.
-ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
-  void* r_cur = c->Rb[0];
-  void* r_nxt = c->Rb[1];
-  void* p_old = c->HU;     // never read on the first iteration
-  void* p_new = c->Pb;
+// One CG iteration (two sweeps and their fixed-order reductions) with the
+// buffer roles of iteration `it` (r and p alternate between two buffers).
+hipError_t cg_iteration(ope_ctx* c, int it) {
+  void* r_cur = c->Rb[it & 1];
+  void* r_nxt = c->Rb[(it + 1) & 1];
+  void* p_old = (it & 1) ? c->Pb : c->HU;    // never read on the first iteration
+  void* p_new = (it & 1) ? c->HU : c->Pb;
   const int N = (int)c->N;
+  const int first = it == 0;
+  hipError_t e;
+  if ((e = launch_cg_pap(c, r_cur, p_old, first)) != hipSuccess) return e;
+  if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA)) != hipSuccess) return e;
+  if ((e = launch_cg_update(c, r_cur, p_old, r_nxt, p_new, c->Y, first)) != hipSuccess) return e;
+  return launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA);
+}
+
+void drop_graphs(ope_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
+    c->cg_graph[k] = nullptr;
+  }
+  c->graph_state = 0;
+}
+
+// Capture the two CG chunks (iterations 0..K-1 and K..2K-1, K = check_every,
+// even) as graphs on a private stream; they are replayed on the context's
+// stream.  Every buffer and launch shape they use is fixed for the context,
+// and convergence lives in device-side column masks, so a chunk needs no
+// host decision.  On any capture error the context stays on eager launches.
+void build_graphs(ope_ctx* c) {
+  c->graph_state = -1;
+  if (c->check_every % 2 != 0) return;
+  if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->cap_stream = nullptr;
+    return;
+  }
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  bool ok = true;
+  for (int k = 0; k < 2 && ok; ++k) {
+    hipGraph_t g = nullptr;
+    ok &= hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (!ok) break;
+    bool lok = true;
+    for (int it = k * c->check_every; it < (k + 1) * c->check_every && lok; ++it) lok = cg_iteration(c, it) == hipSuccess;
+    const bool eok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess;
+    ok &= lok && eok && g != nullptr;
+    if (ok) ok &= hipGraphInstantiate(&c->cg_graph[k], g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+  }
+  c->stream = user;
+  if (!ok) {
+    (void)hipGetLastError();
+    drop_graphs(c);
+    c->graph_state = -1;
+    return;
+  }
+  c->graph_state = 1;
+}
+
+// CG iterations on H Y = U from the state prepared in rho/target/active, with
+// r in c->Rb[0]; returns the iteration count in *iters.  Chunks of
+// check_every iterations run as graph replays when graphs are on (and no
+// kernel is being timed), the rest as eager launches; the host reads the
+// column masks after every chunk.
+ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
+  const int N = (int)c->N;
+  const int K = c->check_every;
+  const bool graphs = c->use_graphs && c->prof_kernel < 0 && K % 2 == 0;
+  if (graphs && c->graph_state == 0) build_graphs(c);
   int it = 0;
   bool done = false;
   while (it < max_iter) {
-    const int first = (it == 0);
-    HIPCHK(launch_cg_pap(c, r_cur, p_old, first));
-    HIPCHK(launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA));
-    HIPCHK(launch_cg_update(c, r_cur, p_old, r_nxt, p_new, c->Y, first));
-    HIPCHK(launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA));
-    void* t = r_cur;
-    r_cur = r_nxt;
-    r_nxt = t;
-    t = p_old;
-    p_old = p_new;
-    p_new = t;
-    ++it;
-    if (it % c->check_every == 0 || it == max_iter) {
+    if (graphs && c->graph_state == 1 && it % K == 0 && it + K <= max_iter) {
+      HIPCHK(hipGraphLaunch(c->cg_graph[it == 0 ? 0 : 1], c->stream));
+      it += K;
+    } else {
+      HIPCHK(cg_iteration(c, it));
+      ++it;
+    }
+    if (it % K == 0 || it == max_iter) {
       HIPCHK(hipMemcpyAsync(c->hactive, c->active, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
       int cnt = 0;
@@ -416,6 +477,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   c->eta_floor = precision == OPE_FP64 ? 1e-12 : 1e-6;
   c->max_iter = 2000;
   c->check_every = 4;
+  c->use_graphs = 1;
 
   // streaming launch shape: about 2048 work-groups, whole passes of points
   const int64_t NV = N / c->vw;
@@ -425,7 +487,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (pts < pp) pts = pp;
   c->stream_pts = (int)pts;
   c->stream_wgs = (int)((n + pts - 1) / pts);
-  march_shape(c, 0, 0, 1, 0);
+  march_shape(c, 0, 0, 1, 0, 0);
 
   const int64_t blk = n * N;
   const int64_t gram_parts = 1024 * N * N;
@@ -621,12 +683,20 @@ ope_status ope_residual(ope_ctx* c, const void* U, double* residual, double* rit
   return c->hsc->err == OPE_ENONFINITE ? OPE_ENONFINITE : OPE_OK;
 }
 
+ope_status ope_set_graphs(ope_ctx* c, int32_t enable) {
+  if (!c || (enable != 0 && enable != 1)) return OPE_EINVAL;
+  c->use_graphs = enable;
+  return OPE_OK;
+}
+
 ope_status ope_set_sweep_shape(ope_ctx* c, int32_t q_max, int32_t march_chunks, int32_t flags) {
-  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~3))
+  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~7))
     return OPE_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
   const MarchShape keep = c->ms;
-  march_shape(c, q_max, march_chunks, flags & OPE_SWEEP_CHUNK_MAJOR, flags & OPE_SWEEP_NONTEMPORAL);
+  march_shape(c, q_max, march_chunks, flags & OPE_SWEEP_CHUNK_MAJOR, flags & OPE_SWEEP_NONTEMPORAL,
+              flags & OPE_SWEEP_NARROW);
   if (march_rows(c) * c->N > c->part_cap) {
     c->ms = keep;
     return OPE_EINVAL;

@@ -99,7 +99,11 @@ struct ope_ctx {
   // policy
   double eta_rel, eta_floor;
   int32_t max_iter;
-  int32_t check_every;          // CG iterations between host convergence checks
+  int32_t check_every;          // CG iterations between host convergence checks (even: graph chunks)
+  int use_graphs;               // replay CG chunks as captured graphs
+  int graph_state;              // 0 not built, 1 built, -1 capture failed (eager launches)
+  hipStream_t cap_stream;       // private stream used only for capturing
+  hipGraphExec_t cg_graph[2];   // first chunk (iterations 0..K-1) and later chunks
   // launch shapes
   int stream_wgs;               // work-groups of the flat streaming kernels
   int stream_pts;               // grid points per flat streaming work-group
@@ -149,7 +153,8 @@ struct ProfScope {
 // launchers (each enqueues on ctx->stream and returns hipSuccess or an error)
 // ---------------------------------------------------------------------------
 hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Y);
-void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt);  // fills c->ms (0 = automatic)
+// fills c->ms (0 = automatic); narrow = 1 keeps 8-vector column chunks for short rows
+void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow);
 int64_t march_rows(const ope_ctx* c);              // partial rows written by the CG sweeps
 
 // CG iteration halves (see k_stencil.hip)

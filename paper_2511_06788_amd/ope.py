@@ -108,6 +108,7 @@ SIGNATURES = {
     "ope_step": ([_P, _P, _D, ctypes.POINTER(ope_step_info)], _I32),
     "ope_solve": ([_P, _P, _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
     "ope_set_sweep_shape": ([_P, _I32, _I32, _I32], _I32),
+    "ope_set_graphs": ([_P, _I32], _I32),
     "ope_get_sweep_shape": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _I32),
     "ope_profile_begin": ([_P, _I32], _I32),
     "ope_convert": ([_P, _P, _P, _I64, _I32], _I32),
@@ -275,6 +276,11 @@ def ope_solve(ctx: int, U, tau: float, res_tol: float, max_steps: int) -> ope_so
 
 OPE_SWEEP_CHUNK_MAJOR = 1
 OPE_SWEEP_NONTEMPORAL = 2
+OPE_SWEEP_NARROW = 4
+
+
+def ope_set_graphs(ctx: int, enable: bool) -> None:
+    _check(lib().ope_set_graphs(ctx, 1 if enable else 0), "ope_set_graphs")
 
 
 def ope_set_sweep_shape(ctx: int, q_max: int, march_chunks: int, flags: int = 0) -> None:

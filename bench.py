@@ -191,6 +191,71 @@ def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
             "steps": steps, "warmup": warmup}
 
 
+def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
+    """The batched workload (64 well problems, grid edges 24..48, N 16..128):
+    problem-steps per second of ope_batch_step before and after the autotuner,
+    and of the same problems stepped one after the other with ope_step."""
+    import numpy as np
+    import workloads as W
+    probs = W.batched_problems(count)
+    out = {"workload": f"{count} wells3d problems, m 24..48, N 16..128, seed 0", "tau": tau, "steps": steps,
+           "grid_points_x_columns": int(sum(p.grid.n * p.N for p in probs))}
+    with ope.Batch(probs) as b:
+        U0 = [torch.from_numpy(p.U0).to("cuda") for p in probs]
+        U = [u.clone() for u in U0]
+
+        def reset():
+            for u, u0 in zip(U, U0):
+                u.copy_(u0)
+            torch.cuda.synchronize()
+
+        def timed(fn):
+            reset()
+            fn()
+            reset()
+            t0 = time.perf_counter()
+            inner = fn()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, inner
+
+        # algorithmic bytes of the CG sweeps: 8 n x N block passes per iteration
+        blk = [8 * p.grid.n * p.N * 8 for p in probs]
+
+        def batch_steps():
+            inner, nbytes = 0, 0
+            for _ in range(steps):
+                for k, i in enumerate(b.step(U, tau)):
+                    inner += i.inner_iterations
+                    nbytes += i.inner_iterations * blk[k]
+            return inner, nbytes
+
+        def sequential_steps():
+            inner, nbytes = 0, 0
+            for _ in range(steps):
+                for k in range(count):
+                    it = ope.ope_step(b.context(k), U[k], tau).inner_iterations
+                    inner += it
+                    nbytes += it * blk[k]
+            return inner, nbytes
+
+        t_seq, in_seq = timed(sequential_steps)
+        t_b0, in_b0 = timed(batch_steps)
+        t_tune0 = time.perf_counter()
+        buckets = b.autotune()
+        t_tune = time.perf_counter() - t_tune0
+        t_b1, in_b1 = timed(batch_steps)
+    ps = count * steps
+
+    def rec(t, r):
+        return {"problem_steps_per_s": ps / t, "seconds": t, "inner_iterations": r[0],
+                "cg_sweep_GB_per_s": r[1] / t / 1e9}
+    out["sequential"] = rec(t_seq, in_seq)
+    out["batched_default_shapes"] = rec(t_b0, in_b0)
+    out["batched_autotuned"] = dict(rec(t_b1, in_b1), buckets=buckets, autotune_seconds=t_tune)
+    out["speedup_vs_sequential"] = t_seq / t_b1
+    return out
+
+
 def copy_calibration(torch, gib=1.0, reps=5):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     n = int(gib * (1 << 30) // 8)
@@ -321,6 +386,8 @@ def main():
         out["forms"]["learned"] = learned_steps_per_second(ope, torch, p, args.tau, min(ks, 40), 5)
         log("time to residual on the 64^3 N=17 problem")
         out["time_to_residual"] = time_to_residual(ope, torch)
+        log("batched workload (64 problems)")
+        out["batched"] = batched_throughput(ope, torch)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle step(s)")

@@ -263,6 +263,41 @@ ope_status ope_set_preconditioner(ope_ctx* ctx, ope_net* net, int32_t judge);
  * EINVAL if no network is set. */
 ope_status ope_step_learned(ope_ctx* ctx, void* U, double tau, ope_step_info* info, int32_t* accepted);
 
+/* --- Batched form ----------------------------------------------------------
+ * Many independent problems (each its own grid, potential and N) stepped
+ * together.  Every problem gets its own context and a private stream (default
+ * priority); a batch step enqueues the pre-phase of every problem, then rounds
+ * of Step-1 CG chunks (graph replays) in which each problem drops out as soon
+ * as its own columns have converged, then Steps 2-4 of every problem, so the
+ * problems' kernels overlap on the GPU.  Each problem's result is exactly that
+ * of ope_step on its own context.  The batch is ordered after earlier work on
+ * `stream` (NULL: the default stream) and later work on it waits for the batch. */
+typedef struct ope_batch ope_batch;
+
+/* count (1..4096) problems: ops[i] (as for ope_create) with block width N[i],
+ * all in one precision.  On error *batch is NULL. */
+ope_status ope_batch_create(ope_batch** batch, const ope_op_desc* ops, const int64_t* N, int32_t count,
+                            int32_t precision, void* stream);
+ope_status ope_batch_destroy(ope_batch* batch);
+/* The context of problem i (owned by the batch): for its inner policy, sweep
+ * shape, residual and energy calls. */
+ope_status ope_batch_context(ope_batch* batch, int32_t i, ope_ctx** ctx);
+/* One step of every problem; U[i] is problem i's device block (in place).
+ * info (host, count entries, nullable) as for ope_step, status per problem;
+ * returns the first non-OK status, else OPE_OK. */
+ope_status ope_batch_step(ope_batch* batch, void* const* U, double tau, ope_step_info* info);
+/* Algorithm 1 for every problem in lock-step rounds (as ope_solve; no stall
+ * test and no learned steps).  info: count entries, nullable. */
+ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double res_tol, int32_t max_steps,
+                           ope_solve_info* info);
+/* Autotuner: for every bucket of problems (grid edges and vector-column count
+ * in steps of 8) time short CG runs of the first problem over the sweep shapes
+ * (passes per plane 1/2/4, work-group order, column chunking, march chunks)
+ * and give every problem of the bucket the fastest; FP32 contexts keep the
+ * default.  *tuned (nullable) = number of buckets.  Synchronises; uses a
+ * temporary n x N block per tuned bucket. */
+ope_status ope_batch_autotune(ope_batch* batch, int32_t* tuned);
+
 /* Step 1's CG runs in chunks of 4 iterations between host convergence checks;
  * with graphs on (the default) each chunk is one replay of a HIP graph
  * captured once per context (on a private stream, replayed on the context's

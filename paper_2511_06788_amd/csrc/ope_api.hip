@@ -17,7 +17,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "ope_internal.h"
@@ -27,6 +29,15 @@
     hipError_t e_ = (x);                        \
     if (e_ != hipSuccess) return OPE_EHIP;      \
   } while (0)
+
+struct ope_batch {
+  int32_t count;
+  hipStream_t user;                   // the caller's stream
+  hipEvent_t start;
+  std::vector<ope_ctx*> ctx;          // one context per problem
+  std::vector<hipStream_t> streams;   // its stream
+  std::vector<hipEvent_t> done;
+};
 
 namespace {
 
@@ -154,35 +165,46 @@ void build_graphs(ope_ctx* c) {
   c->graph_state = 1;
 }
 
-// CG iterations on H Y = U from the state prepared in rho/target/active, with
-// r in c->Rb[0]; returns the iteration count in *iters.  Chunks of
-// check_every iterations run as graph replays when graphs are on (and no
-// kernel is being timed), the rest as eager launches; the host reads the
-// column masks after every chunk.
-ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
-  const int N = (int)c->N;
+// Enqueues CG iterations up to the next host check (a multiple of
+// check_every, or max_iter) and the copy of the column flags to the host.
+// Whole chunks run as graph replays when graphs are on (and no kernel is
+// being timed), the rest as eager launches.
+hipError_t cg_chunk(ope_ctx* c, int32_t* it, int32_t max_iter) {
   const int K = c->check_every;
   const bool graphs = c->use_graphs && c->prof_kernel < 0 && K % 2 == 0;
   if (graphs && c->graph_state == 0) build_graphs(c);
-  int it = 0;
+  const int32_t end = std::min<int32_t>(max_iter, (*it / K + 1) * K);
+  hipError_t e;
+  while (*it < end) {
+    if (graphs && c->graph_state == 1 && *it % K == 0 && *it + K <= end) {
+      if ((e = hipGraphLaunch(c->cg_graph[*it == 0 ? 0 : 1], c->stream)) != hipSuccess) return e;
+      *it += K;
+    } else {
+      if ((e = cg_iteration(c, *it)) != hipSuccess) return e;
+      *it += 1;
+    }
+  }
+  return hipMemcpyAsync(c->hactive, c->active, sizeof(int32_t) * c->N, hipMemcpyDeviceToHost, c->stream);
+}
+
+// After the copy of cg_chunk has completed: true if every column converged.
+bool cg_all_done(const ope_ctx* c) {
+  for (int64_t j = 0; j < c->N; ++j)
+    if (c->hactive[j] != 0) return false;
+  return true;
+}
+
+// CG iterations on H Y = U from the state prepared in rho/target/active, with
+// r in c->Rb[0]; returns the iteration count in *iters.
+ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
+  int32_t it = 0;
   bool done = false;
   while (it < max_iter) {
-    if (graphs && c->graph_state == 1 && it % K == 0 && it + K <= max_iter) {
-      HIPCHK(hipGraphLaunch(c->cg_graph[it == 0 ? 0 : 1], c->stream));
-      it += K;
-    } else {
-      HIPCHK(cg_iteration(c, it));
-      ++it;
-    }
-    if (it % K == 0 || it == max_iter) {
-      HIPCHK(hipMemcpyAsync(c->hactive, c->active, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
-      int cnt = 0;
-      for (int j = 0; j < N; ++j) cnt += c->hactive[j] != 0;
-      if (cnt == 0) {
-        done = true;
-        break;
-      }
+    HIPCHK(cg_chunk(c, &it, max_iter));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (cg_all_done(c)) {
+      done = true;
+      break;
     }
   }
   *iters = it;
@@ -387,6 +409,133 @@ ope_status solve_learned(ope_ctx* c, void* U, double tau, double res_tol, int32_
       skip = backoff;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// batched form: many independent problems, each on its own context and stream
+// ---------------------------------------------------------------------------
+struct BatchState {
+  std::vector<ope_step_info> info;
+  std::vector<ope_status> st;
+  std::vector<char> conv, cgdone;
+  std::vector<int32_t> it;
+};
+
+// One round over the problems with run[i] set: the pre-phase of every problem
+// (residual, Lam^{-1}, warm start), one host synchronisation, then rounds of
+// CG chunks in which each problem leaves as soon as all its columns converged,
+// then Steps 2-4 of every problem still running.  With res_tol >= 0 a problem
+// whose residual is already <= res_tol is only evaluated (conv set).
+ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol, const std::vector<char>& run,
+                       BatchState& bs) {
+  const int P = b->count;
+  bs.info.assign(P, ope_step_info{});
+  bs.st.assign(P, OPE_OK);
+  bs.conv.assign(P, 0);
+  bs.cgdone.assign(P, 0);
+  bs.it.assign(P, 0);
+  std::vector<char> go(run);
+  HIPCHK(hipEventRecord(b->start, b->user));
+  for (int i = 0; i < P; ++i) {
+    if (!go[i]) continue;
+    ope_ctx* c = b->ctx[i];
+    HIPCHK(hipStreamWaitEvent(c->stream, b->start, 0));
+    ope_status st = phase_residual(c, U[i]);
+    if (st == OPE_OK) st = phase_warm_start(c, U[i]);
+    if (st == OPE_OK && hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      st = OPE_EHIP;
+    if (st != OPE_OK) {
+      bs.st[i] = st;
+      go[i] = 0;
+    }
+  }
+  for (int i = 0; i < P; ++i) {
+    if (!go[i]) continue;
+    ope_ctx* c = b->ctx[i];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->hsc->err != 0) {
+      bs.st[i] = (ope_status)c->hsc->err;
+      fill_info(c, &bs.info[i], 0, bs.st[i]);
+      go[i] = 0;
+    } else if (res_tol >= 0.0 && c->hsc->residual <= res_tol) {
+      bs.conv[i] = 1;
+      fill_info(c, &bs.info[i], 0, OPE_OK);
+      go[i] = 0;
+    }
+  }
+  std::vector<char> pending(go);
+  for (;;) {
+    bool any = false;
+    for (int i = 0; i < P; ++i) {
+      if (!pending[i]) continue;
+      any = true;
+      if (cg_chunk(b->ctx[i], &bs.it[i], b->ctx[i]->max_iter) != hipSuccess) {
+        bs.st[i] = OPE_EHIP;
+        pending[i] = go[i] = 0;
+      }
+    }
+    if (!any) break;
+    for (int i = 0; i < P; ++i) {
+      if (!pending[i]) continue;
+      ope_ctx* c = b->ctx[i];
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (cg_all_done(c)) {
+        bs.cgdone[i] = 1;
+        pending[i] = 0;
+      } else if (bs.it[i] >= c->max_iter) {
+        pending[i] = 0;
+      }
+    }
+  }
+  for (int i = 0; i < P; ++i) {
+    if (!go[i]) continue;
+    ope_ctx* c = b->ctx[i];
+    ope_status st = phase_update(c, U[i], tau);
+    if (st == OPE_OK && hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      st = OPE_EHIP;
+    if (st != OPE_OK) {
+      bs.st[i] = st;
+      go[i] = 0;
+    }
+  }
+  for (int i = 0; i < P; ++i) {
+    if (!run[i]) continue;
+    ope_ctx* c = b->ctx[i];
+    if (go[i]) {
+      HIPCHK(hipStreamSynchronize(c->stream));
+      ope_status out = (ope_status)c->hsc->err;
+      if (out == OPE_OK && !bs.cgdone[i]) out = OPE_ECG_MAXIT;
+      fill_info(c, &bs.info[i], c->hsc->cg_iters, out);
+      bs.st[i] = out;
+    }
+    // later work on the caller's stream waits for this problem
+    HIPCHK(hipEventRecord(b->done[i], c->stream));
+    HIPCHK(hipStreamWaitEvent(b->user, b->done[i], 0));
+  }
+  return OPE_OK;
+}
+
+// Seconds per short CG run (8 iterations, 3 repetitions, best) for the
+// context's current sweep shape, on the scratch right-hand side X.
+double time_cg(ope_ctx* c, const double* X, hipEvent_t e0, hipEvent_t e1) {
+  double best = 1e30;
+  for (int rep = 0; rep < 4; ++rep) {
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return 1e30;
+    if (launch_resid0(c, X, nullptr, (double*)c->Rb[0], (double*)c->Y) != hipSuccess) return 1e30;
+    if (launch_reduce_cols(c, c->part, c->stream_wgs, 2 * c->N, c->rho0, RED_PLAIN) != hipSuccess) return 1e30;
+    if (hipMemcpyAsync(c->cnorm2, c->rho0 + c->N, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+      return 1e30;
+    if (launch_solve_setup(c, c->rho0, 0.0) != hipSuccess) return 1e30;
+    for (int it = 0; it < 8; ++it)
+      if (cg_iteration(c, it) != hipSuccess) return 1e30;
+    if (hipEventRecord(e1, c->stream) != hipSuccess) return 1e30;
+    if (hipEventSynchronize(e1) != hipSuccess) return 1e30;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30;
+    if (rep > 0 && ms < best) best = ms;      // the first run warms the caches and code
+  }
+  return best * 1e-3;
 }
 
 }  // namespace
@@ -850,6 +999,214 @@ ope_status ope_step_learned(ope_ctx* c, void* U, double tau, ope_step_info* info
   if (info) *info = in;
   if (accepted) *accepted = acc ? 1 : 0;
   return st;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+ope_status ope_batch_create(ope_batch** out, const ope_op_desc* ops, const int64_t* N, int32_t count,
+                            int32_t precision, void* stream) {
+  if (!out) return OPE_EINVAL;
+  *out = nullptr;
+  if (!ops || !N || count < 1 || count > 4096) return OPE_EINVAL;
+  ope_batch* b = new (std::nothrow) ope_batch();
+  if (!b) return OPE_ENOMEM;
+  b->count = count;
+  b->user = (hipStream_t)stream;
+  b->ctx.assign(count, nullptr);
+  b->streams.assign(count, nullptr);
+  b->done.assign(count, nullptr);
+  ope_status st = OPE_OK;
+  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) st = OPE_EHIP;
+  for (int32_t i = 0; i < count && st == OPE_OK; ++i) {
+    if (hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess) {
+      st = OPE_EHIP;
+      break;
+    }
+    st = ope_create(&b->ctx[i], &ops[i], N[i], precision, b->streams[i]);
+  }
+  if (st != OPE_OK) {
+    ope_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return OPE_OK;
+}
+
+ope_status ope_batch_destroy(ope_batch* b) {
+  if (!b) return OPE_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    if (b->ctx[i]) ope_destroy(b->ctx[i]);
+    if (b->streams[i]) (void)hipStreamDestroy(b->streams[i]);
+    if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+  }
+  if (b->start) (void)hipEventDestroy(b->start);
+  delete b;
+  return OPE_OK;
+}
+
+ope_status ope_batch_context(ope_batch* b, int32_t i, ope_ctx** ctx) {
+  if (!b || !ctx || i < 0 || i >= b->count) return OPE_EINVAL;
+  *ctx = b->ctx[i];
+  return OPE_OK;
+}
+
+ope_status ope_batch_step(ope_batch* b, void* const* U, double tau, ope_step_info* info) {
+  if (!b || !U || !(tau > 0.0)) return OPE_EINVAL;
+  for (int32_t i = 0; i < b->count; ++i)
+    if (!U[i]) return OPE_EINVAL;
+  BatchState bs;
+  std::vector<char> run(b->count, 1);
+  ope_status st = batch_round(b, U, tau, -1.0, run, bs);
+  if (st != OPE_OK) return st;
+  ope_status first = OPE_OK;
+  for (int32_t i = 0; i < b->count; ++i) {
+    if (info) {
+      info[i] = bs.info[i];
+      info[i].status = bs.st[i];
+    }
+    if (first == OPE_OK && bs.st[i] != OPE_OK) first = bs.st[i];
+  }
+  return first;
+}
+
+ope_status ope_batch_solve(ope_batch* b, void* const* U, double tau, double res_tol, int32_t max_steps,
+                           ope_solve_info* info) {
+  if (!b || !U || !(tau > 0.0) || !(res_tol >= 0.0) || max_steps < 0) return OPE_EINVAL;
+  for (int32_t i = 0; i < b->count; ++i)
+    if (!U[i]) return OPE_EINVAL;
+  const int P = b->count;
+  std::vector<ope_solve_info> si(P);
+  for (auto& x : si) memset(&x, 0, sizeof(x));
+  std::vector<char> live(P, 1);
+  std::vector<ope_status> fail(P, OPE_OK);
+  BatchState bs;
+  for (;;) {
+    // problems at their step limit are only evaluated in this round
+    std::vector<char> run(P, 0), eval_only(P, 0);
+    bool any = false;
+    for (int i = 0; i < P; ++i) {
+      if (!live[i]) continue;
+      run[i] = 1;
+      any = true;
+      eval_only[i] = si[i].steps >= max_steps;
+    }
+    if (!any) break;
+    // problems at their step limit take an evaluation-only round (any residual passes)
+    std::vector<char> run_step_set(P, 0), run_eval_set(P, 0);
+    for (int i = 0; i < P; ++i) {
+      run_step_set[i] = run[i] && !eval_only[i];
+      run_eval_set[i] = run[i] && eval_only[i];
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      const std::vector<char>& set = pass == 0 ? run_step_set : run_eval_set;
+      bool has = false;
+      for (int i = 0; i < P; ++i) has |= set[i] != 0;
+      if (!has) continue;
+      ope_status st = batch_round(b, U, tau, pass == 0 ? res_tol : 1e300, set, bs);
+      if (st != OPE_OK) return st;
+      for (int i = 0; i < P; ++i) {
+        if (!set[i]) continue;
+        const ope_status s = bs.st[i];
+        if (s != OPE_OK && s != OPE_ECG_MAXIT) {
+          fail[i] = s;
+          live[i] = 0;
+          continue;
+        }
+        si[i].residual = bs.info[i].residual;
+        si[i].energy = bs.info[i].energy;
+        si[i].drift = bs.info[i].drift;
+        if (bs.conv[i]) {
+          si[i].converged = bs.info[i].residual <= res_tol;
+          live[i] = 0;
+          continue;
+        }
+        si[i].steps += 1;
+        si[i].inner_iterations += bs.info[i].inner_iterations;
+      }
+    }
+  }
+  ope_status first = OPE_OK;
+  for (int i = 0; i < P; ++i) {
+    if (info) info[i] = si[i];
+    if (first == OPE_OK && fail[i] != OPE_OK) first = fail[i];
+  }
+  return first;
+}
+
+ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
+  if (!b) return OPE_EINVAL;
+  // bucket of a problem: grid edge and vector-column count, each in steps of 8
+  struct Key {
+    int dim, prec, vw;
+    uint32_t mx, my, mz, nv;
+    bool operator<(const Key& o) const {
+      return std::tie(dim, prec, vw, mx, my, mz, nv) < std::tie(o.dim, o.prec, o.vw, o.mx, o.my, o.mz, o.nv);
+    }
+  };
+  struct Shape {
+    int q, mc, flags;
+  };
+  std::map<Key, Shape> best;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return OPE_EHIP;
+  }
+  ope_status status = OPE_OK;
+  for (int32_t i = 0; i < b->count && status == OPE_OK; ++i) {
+    ope_ctx* c = b->ctx[i];
+    const uint32_t NV = (uint32_t)(c->N / c->vw);
+    const Key k{c->g.dim, c->prec, c->vw, (c->g.m0 + 7) / 8, (c->g.m1 + 7) / 8, (c->g.m2 + 7) / 8, (NV + 7) / 8};
+    auto f = best.find(k);
+    if (f == best.end()) {
+      if (c->prec != OPE_FP64) {
+        best[k] = Shape{2, 0, OPE_SWEEP_CHUNK_MAJOR};   // FP32 contexts keep the default shape
+      } else {
+        void* X = nullptr;
+        const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
+        if (hipMalloc(&X, bytes) != hipSuccess) {
+          status = OPE_ENOMEM;
+          break;
+        }
+        // any non-zero right-hand side (the sweeps' cost does not depend on it)
+        (void)hipMemsetAsync(X, 0x3F, bytes, c->stream);
+        Shape pick{2, 0, OPE_SWEEP_CHUNK_MAJOR};
+        double tbest = 1e30;
+        const int narrow_opts = NV <= 32 ? 2 : 1;
+        for (int q : {1, 2, 4})
+          for (int cm : {0, OPE_SWEEP_CHUNK_MAJOR})
+            for (int nr = 0; nr < narrow_opts; ++nr)
+              for (int mcm : {0, 2}) {
+                const int flags = cm | (nr ? OPE_SWEEP_NARROW : 0);
+                if (ope_set_sweep_shape(c, q, 0, flags) != OPE_OK) continue;
+                int mc = 0;
+                if (mcm == 2) {
+                  mc = (int)c->ms.mc * 2;
+                  if (ope_set_sweep_shape(c, q, mc, flags) != OPE_OK) continue;
+                }
+                const double t = time_cg(c, (const double*)X, e0, e1);
+                if (t < tbest) {
+                  tbest = t;
+                  pick = Shape{q, mc, flags};
+                }
+              }
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(X);
+        best[k] = pick;
+      }
+      f = best.find(k);
+    }
+    if (ope_set_sweep_shape(c, f->second.q, f->second.mc, f->second.flags) != OPE_OK) {
+      // a shape tuned on a bucket neighbour may not fit this problem's partial buffer
+      (void)ope_set_sweep_shape(c, 2, 0, OPE_SWEEP_CHUNK_MAJOR);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (tuned_keys) *tuned_keys = (int32_t)best.size();
+  return status;
 }
 
 }  // extern "C"

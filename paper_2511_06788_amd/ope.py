@@ -109,6 +109,13 @@ SIGNATURES = {
     "ope_solve": ([_P, _P, _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
     "ope_set_sweep_shape": ([_P, _I32, _I32, _I32], _I32),
     "ope_set_graphs": ([_P, _I32], _I32),
+    "ope_batch_create": ([ctypes.POINTER(_P), ctypes.POINTER(ope_op_desc), ctypes.POINTER(_I64), _I32, _I32, _P],
+                         _I32),
+    "ope_batch_destroy": ([_P], _I32),
+    "ope_batch_context": ([_P, _I32, ctypes.POINTER(_P)], _I32),
+    "ope_batch_step": ([_P, ctypes.POINTER(_P), _D, ctypes.POINTER(ope_step_info)], _I32),
+    "ope_batch_solve": ([_P, ctypes.POINTER(_P), _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
+    "ope_batch_autotune": ([_P, ctypes.POINTER(_I32)], _I32),
     "ope_get_sweep_shape": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _I32),
     "ope_profile_begin": ([_P, _I32], _I32),
     "ope_convert": ([_P, _P, _P, _I64, _I32], _I32),
@@ -424,6 +431,77 @@ class Net:
     def close(self):
         if self.handle:
             ope_net_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns one ``ope_batch`` of independent problems (workloads.Problem list)."""
+
+    def __init__(self, problems, precision=OPE_FP64, stream=None):
+        self.count = len(problems)
+        self.N = [int(p.N) for p in problems]
+        self.n = [int(p.grid.n) for p in problems]
+        descs = (ope_op_desc * self.count)()
+        self._keep = []
+        for i, p in enumerate(problems):
+            Vc = np.ascontiguousarray(p.V, dtype=np.float64)
+            self._keep.append(Vc)
+            d = descs[i]
+            d.dim = p.grid.dim
+            for a in range(3):
+                d.m[a] = p.grid.m[a] if a < p.grid.dim else 1
+                d.h[a] = p.grid.h[a] if a < p.grid.dim else 1.0
+            d.kinetic = p.kinetic
+            d.shift = p.shift
+            d.V = Vc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        Ns = (_I64 * self.count)(*self.N)
+        h = _P()
+        _check(lib().ope_batch_create(ctypes.byref(h), descs, Ns, self.count, precision, _stream_ptr(stream)),
+               "ope_batch_create")
+        self.handle = h.value
+
+    def context(self, i: int) -> int:
+        c = _P()
+        _check(lib().ope_batch_context(self.handle, i, ctypes.byref(c)), "ope_batch_context")
+        return c.value
+
+    def _ptrs(self, Us):
+        if len(Us) != self.count:
+            raise ValueError("one block per problem expected")
+        return (_P * self.count)(*[_ptr(U) for U in Us])
+
+    def step(self, Us, tau: float, allow_maxit: bool = True):
+        infos = (ope_step_info * self.count)()
+        _check(lib().ope_batch_step(self.handle, self._ptrs(Us), tau, infos), "ope_batch_step",
+               allow=(OPE_ECG_MAXIT,) if allow_maxit else ())
+        return list(infos)
+
+    def solve(self, Us, tau: float, res_tol: float, max_steps: int):
+        infos = (ope_solve_info * self.count)()
+        _check(lib().ope_batch_solve(self.handle, self._ptrs(Us), tau, res_tol, max_steps, infos), "ope_batch_solve",
+               allow=(OPE_ECG_MAXIT,))
+        return list(infos)
+
+    def autotune(self) -> int:
+        k = _I32(0)
+        _check(lib().ope_batch_autotune(self.handle, ctypes.byref(k)), "ope_batch_autotune")
+        return k.value
+
+    def close(self):
+        if self.handle:
+            lib().ope_batch_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

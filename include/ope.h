@@ -93,10 +93,12 @@ typedef struct {
 
 typedef struct ope_ctx ope_ctx;
 
-/* Create a context for one operator and block width N (1 <= N <= 128,
+/* Create a context for one operator and block width N (1 <= N <= 512,
  * N <= n; larger N returns OPE_EUNSUPPORTED in this build).  Copies V to the
  * device, allocates the workspace (five n x N blocks in the precision's storage
  * type plus O(N^2) matrices), and binds `stream` (a hipStream_t, or NULL).
+ * Steps 2-3 run as one-work-group Gauss-Jordan kernels for N <= 128 and as
+ * Newton-Schulz inversions on the FP64 matrix cores for larger N.
  * precision is an ope_precision.  On error *ctx is set to NULL. */
 ope_status ope_create(ope_ctx** ctx, const ope_op_desc* op, int64_t N, int32_t precision, void* stream);
 

@@ -225,6 +225,77 @@ __global__ __launch_bounds__(256) void k_rowmm(const TI* X0, const TI* __restric
   }
 }
 
+// Square FP64 products of N x N matrices (the small solves for large N):
+// D = alpha op(A) op(B) + beta C + gamma I, op = transpose when ta / tb is
+// set.  Work-group tile 64 x 64 (4 waves of 32 x 32), operands straight from
+// global memory (the matrices are L2-resident).  When res is given, the
+// work-group adds sum over its tile of (delta_ij - D_ij)^2 into res[block]
+// (the Newton-Schulz residual |I - M X|_F^2).  A non-zero *skip makes the
+// launch a no-op (device-side convergence of an iteration).
+__global__ __launch_bounds__(256) void k_sqmm(const double* __restrict__ A, int ta, const double* __restrict__ B,
+                                              int tb, const double* __restrict__ C, double alpha, double beta,
+                                              double gamma, double* __restrict__ D, uint32_t N,
+                                              const int32_t* __restrict__ skip, double* __restrict__ res) {
+  using MK = Mk<MK_F64>;
+  __shared__ double red[256];
+  if (skip && *skip) return;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t i_base = blockIdx.y * 64 + (wave >> 1) * 32;
+  const uint32_t j_base = blockIdx.x * 64 + (wave & 1u) * 32;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = zero_acc<v4d>();
+  for (uint32_t k0 = 0; k0 < N; k0 += 4) {
+    const uint32_t k = k0 + kr;
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const uint32_t i = i_base + a * 16 + ci;
+      av[a] = (k < N && i < N) ? (ta ? A[(uint64_t)k * N + i] : A[(uint64_t)i * N + k]) : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const uint32_t j = j_base + b * 16 + ci;
+      bv[b] = (k < N && j < N) ? (tb ? B[(uint64_t)j * N + k] : B[(uint64_t)k * N + j]) : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+  double rs = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = i_base + a * 16 + MK::drow(kr, r);
+        const uint32_t j = j_base + b * 16 + ci;
+        if (i < N && j < N) {
+          const uint64_t o = (uint64_t)i * N + j;
+          double v = alpha * acc[a][b][r];
+          if (beta != 0.0) v += beta * C[o];
+          if (i == j) v += gamma;
+          D[o] = v;
+          const double e = (i == j ? 1.0 : 0.0) - v;
+          rs += e * e;
+        }
+      }
+  if (!res) return;
+  red[threadIdx.x] = rs;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
 template <typename TI, int KIND>
 hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int64_t ldb, int nb, int64_t rows,
                   double* out) {
@@ -289,6 +360,15 @@ hipError_t launch_rowmm(ope_ctx* c, const double* X0, const double* M0, const do
                         const double* Cm, double cbeta, double ascale, double* Out, int want_colsq, int predicated,
                         int64_t* nparts) {
   return rowmm_t<double, MK_F64>(c, X0, M0, X1, M1, Cm, cbeta, ascale, Out, want_colsq, predicated, nparts);
+}
+
+hipError_t launch_sqmm(ope_ctx* c, const double* A, int ta, const double* B, int tb, const double* C, double alpha,
+                       double beta, double gamma, double* D, uint32_t N, const int32_t* skip, double* res) {
+  const uint32_t t = (N + 63) / 64;
+  ProfScope ps(c, OPE_KERNEL_SMALL);
+  hipLaunchKernelGGL(k_sqmm, dim3(t, t), dim3(256), 0, c->stream, A, ta, B, tb, C, alpha, beta, gamma, D, N, skip,
+                     res);
+  return hipGetLastError();
 }
 
 hipError_t launch_rowmm_f32(ope_ctx* c, int kind, const float* X0, const float* M0, const float* X1, const float* M1,

@@ -1,11 +1,12 @@
-// One-work-group FP64 kernels on N x N matrices (N <= 128): the small solve of
+// FP64 kernels on N x N matrices: the small solve of
 // Steps 2-3 (Section 4.1), the warm-start inverse Lam^{-1}, the per-step
 // scalars, and Jacobi eigenvalues for the Ritz values.
 //
 // A 1024-thread work-group holds an N x N matrix in registers: thread t owns
 // column j = t % 128 and rows i = t / 128 + 8 r, r = 0..15.  Gauss-Jordan
 // elimination without pivoting runs with one barrier per pivot (the pivot
-// column and pivot row are published through double-buffered LDS).  No
+// column and pivot row are published through double-buffered LDS); this is
+// the path for N <= 128, larger N use the Newton-Schulz pieces below.  No
 // pivoting is needed: the Step-2 matrix has symmetric part >= I (Lemma 3.1 and
 // its generalisation to an inexact GU), and Lam = U^T H U is SPD, so every
 // pivot of either is positive.
@@ -336,13 +337,13 @@ __global__ void k_to_f64(const float* __restrict__ src, double* __restrict__ dst
 }
 
 // Cyclic Jacobi (round-robin parallel ordering) on a symmetric N x N matrix
-// held in global workspace; eigenvalues sorted ascending into evals.
+// (N <= 512) held in global workspace; eigenvalues sorted ascending into evals.
 __global__ __launch_bounds__(SW) void k_jacobi(const double* __restrict__ Asrc, double* __restrict__ W,
                                                double* __restrict__ evals, uint32_t N) {
   __shared__ double red[SW];
-  __shared__ double cs[64], sn[64];
-  __shared__ uint32_t pp[64], qq[64];
-  __shared__ double dg[128];
+  __shared__ double cs[256], sn[256];
+  __shared__ uint32_t pp[256], qq[256];
+  __shared__ double dg[512];
   const uint32_t Np = N + (N & 1u);             // even number of players (one dummy for odd N)
   const uint32_t npair = Np / 2, m = Np - 1;
   for (uint32_t e = threadIdx.x; e < N * N; e += SW) {
@@ -417,9 +418,287 @@ __global__ __launch_bounds__(SW) void k_jacobi(const double* __restrict__ Asrc, 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// N > 128: the same small phase from multi-work-group pieces.  Inverses by
+// Newton-Schulz, X <- X (2I - M X), on the FP64 matrix cores (k_sqmm): it
+// converges quadratically from X0 = M^T / (|M|_1 |M|_inf) for any
+// non-singular M, and from X0 = I / |M|_inf for SPD M (Lam); the Step-2
+// matrix has symmetric part >= I and Lam is SPD, so both are well
+// conditioned.  A device-side state stops the iteration once
+// |I - M X_k|_F <= 1e-10 (one more update then squares the error).
+// ---------------------------------------------------------------------------
+
+// one work-group: energy, |Lam|_F, drift, column norms, sym(Lam) into Ls,
+// X0 = I / |Ls|_inf, and the Newton-Schulz state reset
+__global__ __launch_bounds__(SW) void k_big_prep(const double* __restrict__ C, const double* __restrict__ Lam,
+                                                 double* __restrict__ Ls, double* __restrict__ X0,
+                                                 double* __restrict__ cnorm2, uint32_t N,
+                                                 OpeScalars* __restrict__ sc, float* __restrict__ Lam32,
+                                                 NsState* __restrict__ ns) {
+  __shared__ double red[SW];
+  double e = 0.0, lf = 0.0, dr = 0.0, rmax = 0.0;
+  for (uint32_t i = threadIdx.x; i < N; i += SW) {
+    double rs = 0.0;
+    for (uint32_t j = 0; j < N; ++j) {
+      const double lij = Lam[(uint64_t)i * N + j], lji = Lam[(uint64_t)j * N + i];
+      const double ls = 0.5 * (lij + lji);
+      Ls[(uint64_t)i * N + j] = ls;
+      if (Lam32) Lam32[(uint64_t)i * N + j] = (float)lij;
+      const double cij = C[(uint64_t)i * N + j] - (i == j ? 1.0 : 0.0);
+      lf += lij * lij;
+      dr += cij * cij;
+      rs += fabs(ls);
+    }
+    e += Lam[(uint64_t)i * N + i];
+    cnorm2[i] = C[(uint64_t)i * N + i];
+    rmax = rs > rmax ? rs : rmax;
+  }
+  e = wg_sum(e, red);
+  lf = wg_sum(lf, red);
+  dr = wg_sum(dr, red);
+  red[threadIdx.x] = rmax;
+  __syncthreads();
+  for (int s = SW / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double scale = red[0] > 0.0 ? 1.0 / red[0] : 0.0;
+  for (uint32_t q = threadIdx.x; q < N * N; q += SW) X0[q] = (q % (N + 1) == 0) ? scale : 0.0;
+  if (threadIdx.x == 0) {
+    sc->energy = 0.5 * e;
+    sc->lam_fro = sqrt(lf);
+    sc->drift = sqrt(dr);
+    int err = 0;
+    if (!isfinite(e) || !isfinite(lf) || !isfinite(dr) || !(scale > 0.0)) err = OPE_ENONFINITE;
+    sc->err = err;                 // first writer of the step: resets earlier errors
+    ns->done = 0;
+    ns->cur = 0;
+    ns->upd_skip = 0;
+    ns->iters = 0;
+  }
+}
+
+// M = I + tau/2 (S_b^T - S_b) + tau^2/4 (T - P) (N^2 threads); with the
+// transpose X0 = M^T / (|M|_1 |M|_inf) written by k_big_init.
+__global__ void k_big_form_m(const double* __restrict__ Sb, const double* __restrict__ T,
+                             const double* __restrict__ P, double tau, uint32_t N, double* __restrict__ M) {
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (uint64_t)N * N) return;
+  const uint32_t i = (uint32_t)(q / N), j = (uint32_t)(q % N);
+  M[q] = (i == j ? 1.0 : 0.0) + 0.5 * tau * (Sb[(uint64_t)j * N + i] - Sb[q]) + 0.25 * tau * tau * (T[q] - P[q]);
+}
+
+// one work-group: X0 = M^T / (|M|_1 |M|_inf), Newton-Schulz state reset
+__global__ __launch_bounds__(SW) void k_big_init(const double* __restrict__ M, uint32_t N, double* __restrict__ X0,
+                                                 NsState* __restrict__ ns, OpeScalars* __restrict__ sc) {
+  __shared__ double red[SW];
+  double rmax = 0.0, cmax = 0.0;
+  for (uint32_t i = threadIdx.x; i < N; i += SW) {
+    double rs = 0.0, cs = 0.0;
+    for (uint32_t j = 0; j < N; ++j) {
+      rs += fabs(M[(uint64_t)i * N + j]);
+      cs += fabs(M[(uint64_t)j * N + i]);
+    }
+    rmax = rs > rmax ? rs : rmax;
+    cmax = cs > cmax ? cs : cmax;
+  }
+  red[threadIdx.x] = rmax;
+  __syncthreads();
+  for (int s = SW / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double ninf = red[0];
+  __syncthreads();
+  red[threadIdx.x] = cmax;
+  __syncthreads();
+  for (int s = SW / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double n1 = red[0];
+  const double a = (ninf > 0.0 && n1 > 0.0 && isfinite(ninf * n1)) ? 1.0 / (ninf * n1) : 0.0;
+  for (uint32_t q = threadIdx.x; q < N * N; q += SW) {
+    const uint32_t i = q / N, j = q % N;
+    X0[q] = a * M[(uint64_t)j * N + i];
+  }
+  if (threadIdx.x == 0) {
+    ns->done = 0;
+    ns->cur = 0;
+    ns->upd_skip = 0;
+    ns->iters = 0;
+    if (!(a > 0.0) && sc->err == 0) sc->err = OPE_EPIVOT;
+  }
+}
+
+// after G = M X_k with its residual partials: |I - G|_F, the stop decision,
+// and which buffer the update of iteration k writes
+__global__ __launch_bounds__(256) void k_ns_check(const double* __restrict__ part, uint32_t nparts, uint32_t k,
+                                                  NsState* __restrict__ ns) {
+  __shared__ double red[256];
+  if (ns->done) {
+    if (threadIdx.x == 0) ns->upd_skip = 1;
+    return;
+  }
+  double s = 0.0;
+  for (uint32_t q = threadIdx.x; q < nparts; q += 256) s += part[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(red[0]);
+    ns->res = r;
+    ns->iters = (int32_t)k + 1;
+    ns->upd_skip = 0;
+    ns->cur = (int32_t)((k + 1) & 1u);
+    if (!isfinite(r)) {
+      ns->done = 2;              // failed: no further iterations
+      ns->upd_skip = 1;
+      ns->cur = (int32_t)(k & 1u);
+    } else if (r <= 1e-10) {
+      ns->done = 1;              // this iteration's update is the last
+    }
+  }
+}
+
+// the inverse into Dst from the buffer holding it; sets EPIVOT if the
+// iteration did not converge
+__global__ void k_ns_take(const double* __restrict__ X0, const double* __restrict__ X1, uint32_t N,
+                          const NsState* __restrict__ ns, double* __restrict__ Dst, float* __restrict__ Dst32,
+                          OpeScalars* __restrict__ sc) {
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double* X = ns->cur ? X1 : X0;
+  if (q < (uint64_t)N * N) {
+    Dst[q] = X[q];
+    if (Dst32) Dst32[q] = (float)X[q];
+  }
+  if (q == 0 && ns->done != 1 && sc->err == 0) sc->err = OPE_EPIVOT;
+}
+
+// Z = [I - tau A ; tau B] (FP64) or, for the delta form, Z32 = [-2 (I - B) ; tau B]
+__global__ void k_big_z(const double* __restrict__ A, const double* __restrict__ B, double tau, uint32_t N,
+                        double* __restrict__ Z, float* __restrict__ Z32) {
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (uint64_t)N * N) return;
+  const uint32_t i = (uint32_t)(q / N), j = (uint32_t)(q % N);
+  const double d = i == j ? 1.0 : 0.0;
+  if (Z) {
+    Z[q] = d - tau * A[q];
+    Z[(uint64_t)N * N + q] = tau * B[q];
+  } else {
+    Z32[q] = (float)(-2.0 * (d - B[q]));
+    Z32[(uint64_t)N * N + q] = (float)(tau * B[q]);
+  }
+}
+
+__global__ void k_copy_pred(const void* __restrict__ src, void* __restrict__ dst, uint64_t words,
+                            const OpeScalars* __restrict__ sc) {
+  if (sc->err != 0) return;
+  const uint64_t* s = (const uint64_t*)src;
+  uint64_t* d = (uint64_t*)dst;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < words; e += (uint64_t)gridDim.x * blockDim.x)
+    d[e] = s[e];
+}
+
 }  // namespace
 
+// Newton-Schulz iterations on M (from X0 in ns_x[0]) in chunks of 8 with a
+// host check of the device state between chunks; the inverse goes to Dst.
+static hipError_t ns_invert(ope_ctx* c, const double* M, double* Dst, float* Dst32) {
+  const uint32_t N = (uint32_t)c->N;
+  const uint32_t t = (N + 63) / 64;
+  hipError_t e;
+  for (int k = 0; k < 96; ++k) {
+    double* X = c->ns_x[k & 1];
+    double* Xn = c->ns_x[(k + 1) & 1];
+    if ((e = launch_sqmm(c, M, 0, X, 0, nullptr, 1.0, 0.0, 0.0, c->ns_g, N, &c->ns->done, c->ns_part)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(256), 0, c->stream, c->ns_part, t * t, (uint32_t)k, c->ns);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // X_{k+1} = 2 X_k - X_k G
+    if ((e = launch_sqmm(c, X, 0, c->ns_g, 0, X, -1.0, 2.0, 0.0, Xn, N, &c->ns->upd_skip, nullptr)) != hipSuccess)
+      return e;
+    if (k % 8 == 7) {
+      if ((e = hipMemcpyAsync(c->hns, c->ns, sizeof(NsState), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return e;
+      if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+      if (c->hns->done) break;
+    }
+  }
+  const uint64_t nn = (uint64_t)N * N;
+  hipLaunchKernelGGL(k_ns_take, dim3((uint32_t)((nn + 255) / 256)), dim3(256), 0, c->stream, c->ns_x[0], c->ns_x[1],
+                     N, c->ns, Dst, Dst32, c->sc);
+  return hipGetLastError();
+}
+
+static hipError_t big_prep(ope_ctx* c) {
+  const uint32_t N = (uint32_t)c->N;
+  hipLaunchKernelGGL(k_big_prep, dim3(1), dim3(SW), 0, c->stream, c->C, c->Lam, c->ns_m, c->ns_x[0], c->cnorm2, N,
+                     c->sc, c->Lam32, c->ns);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return ns_invert(c, c->ns_m, c->Linv, c->Linv32);
+}
+
+// B = M^{-1} for M = I + tau/2 (S_b^T - S_b) + tau^2/4 (T' - P), P in ns_p
+static hipError_t big_form_and_invert(ope_ctx* c, const double* Sb, const double* Tp, double tau, double* B) {
+  const uint32_t N = (uint32_t)c->N;
+  const uint64_t nn = (uint64_t)N * N;
+  hipLaunchKernelGGL(k_big_form_m, dim3((uint32_t)((nn + 255) / 256)), dim3(256), 0, c->stream, Sb, Tp, c->ns_p, tau,
+                     N, c->ns_m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_big_init, dim3(1), dim3(SW), 0, c->stream, c->ns_m, N, c->ns_x[0], c->ns, c->sc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return ns_invert(c, c->ns_m, B, nullptr);
+}
+
+static hipError_t big_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau, double* Z, double* A,
+                                  double* B) {
+  const uint32_t N = (uint32_t)c->N;
+  const uint64_t nn = (uint64_t)N * N;
+  hipError_t e;
+  // P = S_a S_b = S_b^T S_b
+  if ((e = launch_sqmm(c, Sb, 1, Sb, 0, nullptr, 1.0, 0.0, 0.0, c->ns_p, N, nullptr, nullptr)) != hipSuccess) return e;
+  if ((e = big_form_and_invert(c, Sb, T, tau, B)) != hipSuccess) return e;
+  // A = 2/tau (I - B) + S_b B
+  double* Aw = A ? A : c->A;
+  if ((e = launch_sqmm(c, Sb, 0, B, 0, B, 1.0, -2.0 / tau, 2.0 / tau, Aw, N, nullptr, nullptr)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_big_z, dim3((uint32_t)((nn + 255) / 256)), dim3(256), 0, c->stream, Aw, B, tau, N, Z,
+                     (float*)nullptr);
+  return hipGetLastError();
+}
+
+static hipError_t big_small_solve_delta(ope_ctx* c, const double* Sb, const double* Tp, double tau) {
+  const uint32_t N = (uint32_t)c->N;
+  const uint64_t nn = (uint64_t)N * N;
+  hipError_t e;
+  // Wsm = (C - I) S_b = C S_b - S_b ; P = S_b^T Wsm
+  if ((e = launch_sqmm(c, c->C, 0, Sb, 0, Sb, 1.0, -1.0, 0.0, c->Wsm, N, nullptr, nullptr)) != hipSuccess) return e;
+  if ((e = launch_sqmm(c, Sb, 1, c->Wsm, 0, nullptr, 1.0, 0.0, 0.0, c->ns_p, N, nullptr, nullptr)) != hipSuccess)
+    return e;
+  if ((e = big_form_and_invert(c, Sb, Tp, tau, c->B)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_big_z, dim3((uint32_t)((nn + 255) / 256)), dim3(256), 0, c->stream, (const double*)nullptr,
+                     c->B, tau, N, (double*)nullptr, c->Z32);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes) {
+  uint64_t words = bytes / 8;
+  uint64_t grid = (words + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_copy_pred, dim3((uint32_t)grid), dim3(256), 0, c->stream, src, dst, words, c->sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep_small(ope_ctx* c) {
+  if (c->N > OPE_MAX_N_ONE_WG) return big_prep(c);
   ProfScope ps(c, OPE_KERNEL_SMALL);
   hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(SW), 0, c->stream, c->C, c->Lam, c->Linv, c->cnorm2, (uint32_t)c->N,
                      c->sc, c->Lam32, c->Linv32);
@@ -427,6 +706,7 @@ hipError_t launch_prep_small(ope_ctx* c) {
 }
 
 hipError_t launch_small_solve_delta(ope_ctx* c, const double* Sb, const double* Tperp, double tau) {
+  if (c->N > OPE_MAX_N_ONE_WG) return big_small_solve_delta(c, Sb, Tperp, tau);
   ProfScope ps(c, OPE_KERNEL_SMALL);
   hipLaunchKernelGGL(k_small_solve_delta, dim3(1), dim3(SW), 0, c->stream, Sb, Tperp, c->C, tau, (uint32_t)c->N,
                      c->Wsm, c->Z32, c->sc);
@@ -464,6 +744,7 @@ hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol) {
 
 hipError_t launch_small_solve(ope_ctx* c, const double* Sb, const double* T, double tau, double* Z, double* A,
                               double* B) {
+  if (c->N > OPE_MAX_N_ONE_WG) return big_small_solve(c, Sb, T, tau, Z, A, B ? B : c->B);
   ProfScope ps(c, OPE_KERNEL_SMALL);
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SW), 0, c->stream, Sb, T, tau, (uint32_t)c->N, B ? B : c->B, Z, A,
                      c->sc);

@@ -59,13 +59,14 @@ void free_ctx(ope_ctx* c) {
   void* dptrs[] = {c->diag, c->diag32, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T,
                    c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
                    c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->counters, c->sc,
-                   c->Ubak};
+                   c->Ubak, c->ns_x[0], c->ns_x[1], c->ns_g, c->ns_m, c->ns_p, c->ns_part, c->ns};
   for (void* p : dptrs)
     if (p) (void)hipFree(p);
   if (c->hsc) (void)hipHostFree(c->hsc);
   if (c->hactive) (void)hipHostFree(c->hactive);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->hsc2) (void)hipHostFree(c->hsc2);
+  if (c->hns) (void)hipHostFree(c->hns);
   for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -252,7 +253,14 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
     HIPCHK(launch_gram(c, U, N, N, Y, N, N, c->n, c->Sb));
     HIPCHK(launch_gram(c, Y, N, N, Y, N, N, c->n, c->T));
     HIPCHK(launch_small_solve(c, c->Sb, c->T, tau, c->Z, c->A, c->B));
-    HIPCHK(launch_rowmm(c, U, c->Z, Y, c->Z + NN, nullptr, 0.0, 1.0, U, 0, 1, &np));
+    if (N <= 128) {
+      HIPCHK(launch_rowmm(c, U, c->Z, Y, c->Z + NN, nullptr, 0.0, 1.0, U, 0, 1, &np));
+    } else {
+      // several column tiles read every column of U: write aside, then copy back
+      double* tmp = (double*)c->Pb;
+      HIPCHK(launch_rowmm(c, U, c->Z, Y, c->Z + NN, nullptr, 0.0, 1.0, tmp, 0, 1, &np));
+      HIPCHK(launch_copy_pred(c, tmp, U, sizeof(double) * (uint64_t)c->n * N));
+    }
   } else {
     // S_b = U^T Y (FP32 matrix cores), P = Y - U S_b (FP32), T_perp = P^T P
     // (BF16, FP32 accumulation), FP64 small solve, U += U Z1 + P Z2 (BF16).
@@ -264,7 +272,13 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
     HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Sb32, nullptr, nullptr, Y, 1.0, -1.0, P, 0, 0, &np));
     HIPCHK(launch_gram_f32(c, MK_BF16, P, N, N, P, N, N, c->n, c->T));
     HIPCHK(launch_small_solve_delta(c, c->Sb, c->T, tau));
-    HIPCHK(launch_rowmm_f32(c, MK_BF16, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, 1, &np));
+    if (N <= 128) {
+      HIPCHK(launch_rowmm_f32(c, MK_BF16, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, 1, &np));
+    } else {
+      float* tmp = (float*)c->Pb;
+      HIPCHK(launch_rowmm_f32(c, MK_BF16, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, tmp, 0, 1, &np));
+      HIPCHK(launch_copy_pred(c, tmp, U, sizeof(float) * (uint64_t)c->n * N));
+    }
   }
   return OPE_OK;
 }
@@ -639,7 +653,8 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   march_shape(c, 0, 0, 1, 0, 0);
 
   const int64_t blk = n * N;
-  const int64_t gram_parts = 1024 * N * N;
+  const int64_t gtiles = ((N + 63) / 64) * ((N + 63) / 64);
+  const int64_t gram_parts = ((1024 + gtiles - 1) / gtiles) * N * N;
   const int64_t row_parts = ((n + 63) / 64) * N;
   int64_t pc = (int64_t)c->stream_wgs * 2 * N;
   if (march_rows(c) * N > pc) pc = march_rows(c) * N;
@@ -691,6 +706,17 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   ok &= hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * N, hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hbuf, sizeof(double) * 2 * N, hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hsc2, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
+  if (N > OPE_MAX_N_ONE_WG) {
+    const int64_t t = (N + 63) / 64;
+    ok &= dalloc(&c->ns_x[0], N * N) == hipSuccess;
+    ok &= dalloc(&c->ns_x[1], N * N) == hipSuccess;
+    ok &= dalloc(&c->ns_g, N * N) == hipSuccess;
+    ok &= dalloc(&c->ns_m, N * N) == hipSuccess;
+    ok &= dalloc(&c->ns_p, N * N) == hipSuccess;
+    ok &= dalloc(&c->ns_part, t * t) == hipSuccess;
+    ok &= dalloc(&c->ns, 1) == hipSuccess;
+    ok &= hipHostMalloc((void**)&c->hns, sizeof(NsState), hipHostMallocDefault) == hipSuccess;
+  }
   if (!ok) {
     free_ctx(c);
     return OPE_ENOMEM;
@@ -800,7 +826,12 @@ ope_status ope_update(ope_ctx* c, double* U, const double* Y, const double* Z) {
   if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
   const size_t NN = (size_t)c->N * c->N;
   int64_t np = 0;
-  HIPCHK(launch_rowmm(c, U, Z, Y, Z + NN, nullptr, 0.0, 1.0, U, 0, 0, &np));
+  if (c->N <= 128) {
+    HIPCHK(launch_rowmm(c, U, Z, Y, Z + NN, nullptr, 0.0, 1.0, U, 0, 0, &np));
+  } else {
+    HIPCHK(launch_rowmm(c, U, Z, Y, Z + NN, nullptr, 0.0, 1.0, (double*)c->Pb, 0, 0, &np));
+    HIPCHK(hipMemcpyAsync(U, c->Pb, sizeof(double) * (size_t)c->n * c->N, hipMemcpyDeviceToDevice, c->stream));
+  }
   return OPE_OK;
 }
 
@@ -909,6 +940,7 @@ ope_status ope_rowmm_f32(ope_ctx* c, int32_t kind, const float* X0, const float*
                          const float* M1, const float* Cm, double cbeta, double ascale, float* Out) {
   if (!c || !X0 || !M0 || !Out || (X1 && !M1) || (cbeta != 0.0 && !Cm) || (kind != MK_F32 && kind != MK_BF16))
     return OPE_EINVAL;
+  if (c->N > 128 && (Out == X0 || Out == X1)) return OPE_EUNSUPPORTED;
   int64_t np = 0;
   HIPCHK(launch_rowmm_f32(c, kind, X0, M0, X1, M1, Cm, cbeta, ascale, Out, 0, 0, &np));
   return OPE_OK;
@@ -962,7 +994,7 @@ ope_status ope_set_preconditioner(ope_ctx* c, ope_net* net, int32_t judge) {
     return OPE_OK;
   }
   if (net->ctx != c || net->max_batch < c->N || (judge != 0 && judge != 1)) return OPE_EINVAL;
-  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  if (c->prec != OPE_FP64 || c->N > 128) return OPE_EUNSUPPORTED;
   c->net_judge = judge;
   if (judge && !c->Ubak) {
     if (balloc(&c->Ubak, sizeof(double) * (size_t)c->n * (size_t)c->N) != hipSuccess) return OPE_ENOMEM;

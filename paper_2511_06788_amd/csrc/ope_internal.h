@@ -20,7 +20,8 @@
 
 // Arithmetic of a dense contraction (see k_mfma.hip).
 enum { MK_F64 = 0, MK_F32 = 1, MK_BF16 = 2 };
-#define OPE_MAX_N_SMALL 128         // largest N of the one-work-group FP64 small solves
+#define OPE_MAX_N_SMALL 512         // largest block width N
+#define OPE_MAX_N_ONE_WG 128        // largest N of the one-work-group FP64 small solves
 
 struct OpeGrid {
   int dim;
@@ -46,6 +47,15 @@ struct MarchShape {
   uint32_t order;     // 0: work-groups of one side line adjacent; 1: of one column chunk adjacent
   uint32_t nt;        // 1: streamed outputs bypass the caches (non-temporal stores)
   double cm, cs;      // stencil coefficients of the march and side axes
+};
+
+// State of a device-side Newton-Schulz inversion (N > OPE_MAX_N_ONE_WG).
+struct NsState {
+  int32_t done;       // 1 converged (its last update still runs), 2 failed
+  int32_t upd_skip;   // the update of the current iteration is skipped
+  int32_t cur;        // buffer holding the latest iterate
+  int32_t iters;
+  double res;         // |I - M X_k|_F of the last checked iterate
 };
 
 // Device-resident scalars of one context (written by kernels, read by kernels
@@ -80,6 +90,10 @@ struct ope_ctx {
   void* Pb;                     // second CG direction buffer (the first is HU)
   // N x N (and 2N x N) matrices, FP64
   double *C, *Lam, *Linv, *Sb, *T, *Z, *A, *B, *Wsm;
+  // N > 128: Newton-Schulz workspace (iterates, M X, the matrix, a product), state
+  double *ns_x[2], *ns_g, *ns_m, *ns_p, *ns_part;
+  NsState* ns;
+  NsState* hns;                 // pinned
   // FP32 copies used by the mixed-precision products
   float *Lam32, *Linv32, *Sb32, *Z32;
   // per-column CG state
@@ -199,6 +213,13 @@ hipError_t launch_small_solve_delta(ope_ctx* c, const double* Sb, const double* 
 // FP32 copy of an N x N matrix
 hipError_t launch_small_to_f32(ope_ctx* c, const double* src, float* dst, int64_t count);
 hipError_t launch_jacobi_eig(ope_ctx* c, const double* Asym, double* evals);
+// D = alpha op(A) op(B) + beta C + gamma I for N x N FP64 matrices (FP64 matrix
+// cores); *skip != 0 makes it a no-op; res (nullable) receives per-work-group
+// sums of (delta_ij - D_ij)^2, ((N + 63) / 64)^2 values
+hipError_t launch_sqmm(ope_ctx* c, const double* A, int ta, const double* B, int tb, const double* C, double alpha,
+                       double beta, double gamma, double* D, uint32_t N, const int32_t* skip, double* res);
+// dst = src (bytes, a multiple of 8) unless the step's error flag is set
+hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
 
 // learned form (k_net.hip): column sums of squares of point-major FP64 rows

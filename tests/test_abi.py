@@ -47,7 +47,7 @@ def test_status_strings():
     (dict(m=(0, 4, 4)), "OPE_EINVAL"),
     (dict(kinetic=-1.0), "OPE_EINVAL"),
     (dict(precision=5), "OPE_EUNSUPPORTED"),
-    (dict(N=200, m=(40, 40, 40)), "OPE_EUNSUPPORTED"),
+    (dict(N=513, m=(40, 40, 40)), "OPE_EUNSUPPORTED"),
 ])
 def test_create_rejects_invalid_arguments(kw, expect):
     from paper_2511_06788_amd import ope

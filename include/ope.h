@@ -53,12 +53,15 @@ typedef enum {
  * OPE_MIXED: orbital blocks (U and the workspace) stored in FP32; stencil and
  * Step-1 CG in FP32; <U,U> and <U,HU> (energy, drift) accumulated in FP64 on the
  * matrix cores; <U,Y> and the projection P = Y - U<U,Y> in FP32 on the matrix
- * cores; P^T P and Step 4 in BF16 with FP32 accumulation, with Step 4 written
- * in delta form U' = U + U Z1 + P Z2 (Z1 = -2(I - B), Z2 = tau B) so that its
- * BF16 rounding vanishes at convergence; the Step-2 matrix uses
- * T - S_a S_b = P^T P - S_b^T (C - I) S_b; the small solves and all checks in FP64.  Its accuracy is
- * bounded by FP32 storage (residual floor about 1e-6); convert U to FP64 and
- * continue with an OPE_FP64 context to finish. */
+ * cores; P^T P in BF16 with FP32 accumulation; Step 4 in FP32 on the matrix
+ * cores, written in delta form U' = U + U Z1 + P Z2 (Z1 = -2(I - B),
+ * Z2 = tau B) so that its rounding vanishes at convergence; the Step-2 matrix uses
+ * T - S_a S_b = P^T P - S_b^T (C - I) S_b; the small solves and all checks in FP64.
+ * FP32 rounding adds to the drift |U^T U - I|_F that the scheme itself keeps
+ * constant, so a step whose predecessor saw a drift above 1e-6 first applies
+ * U <- U (3I - C)/2 (one Newton-Schulz step, C = U^T U; drift E -> O(E^2)).
+ * Its accuracy is bounded by FP32 storage (residual floor about 1e-6); convert
+ * U to FP64 and continue with an OPE_FP64 context to finish. */
 typedef enum { OPE_FP64 = 0, OPE_MIXED = 1 } ope_precision;
 
 /* The discrete operator (paper, Section 2.2 bilinear form a(u,v), discretised

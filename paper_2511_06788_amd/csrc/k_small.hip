@@ -595,6 +595,13 @@ __global__ void k_big_z(const double* __restrict__ A, const double* __restrict__
   }
 }
 
+__global__ void k_renorm(const double* __restrict__ C, uint32_t N, float* __restrict__ Z) {
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (uint64_t)N * N) return;
+  const uint32_t i = (uint32_t)(q / N), j = (uint32_t)(q % N);
+  Z[q] = (float)((i == j ? 1.5 : 0.0) - 0.5 * C[q]);
+}
+
 __global__ void k_copy_pred(const void* __restrict__ src, void* __restrict__ dst, uint64_t words,
                             const OpeScalars* __restrict__ sc) {
   if (sc->err != 0) return;
@@ -685,6 +692,12 @@ static hipError_t big_small_solve_delta(ope_ctx* c, const double* Sb, const doub
   if ((e = big_form_and_invert(c, Sb, Tp, tau, c->B)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_big_z, dim3((uint32_t)((nn + 255) / 256)), dim3(256), 0, c->stream, (const double*)nullptr,
                      c->B, tau, N, (double*)nullptr, c->Z32);
+  return hipGetLastError();
+}
+
+hipError_t launch_renorm_matrix(ope_ctx* c, const double* C, float* Z32) {
+  const uint64_t nn = (uint64_t)c->N * c->N;
+  hipLaunchKernelGGL(k_renorm, dim3((uint32_t)((nn + 255) / 256)), dim3(256), 0, c->stream, C, (uint32_t)c->N, Z32);
   return hipGetLastError();
 }
 

@@ -214,6 +214,7 @@ ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) 
 }
 
 void fill_info(ope_ctx* c, ope_step_info* info, int32_t iters, ope_status st) {
+  c->drift_seen = c->hsc->drift;
   if (!info) return;
   info->energy = c->hsc->energy;
   info->residual = c->hsc->residual;
@@ -263,7 +264,9 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
     }
   } else {
     // S_b = U^T Y (FP32 matrix cores), P = Y - U S_b (FP32), T_perp = P^T P
-    // (BF16, FP32 accumulation), FP64 small solve, U += U Z1 + P Z2 (BF16).
+    // (BF16, FP32 accumulation), FP64 small solve, U += U Z1 + P Z2 (FP32
+    // matrix cores: with BF16 operands the rounding of U in U Z1 adds about
+    // 1e-4 of drift per early step, with FP32 about 1e-6, at the same speed).
     float* U = (float*)Uv;
     const float* Y = (const float*)c->Y;
     float* P = (float*)c->HU;
@@ -273,13 +276,35 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
     HIPCHK(launch_gram_f32(c, MK_BF16, P, N, N, P, N, N, c->n, c->T));
     HIPCHK(launch_small_solve_delta(c, c->Sb, c->T, tau));
     if (N <= 128) {
-      HIPCHK(launch_rowmm_f32(c, MK_BF16, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, 1, &np));
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, 1, &np));
     } else {
       float* tmp = (float*)c->Pb;
-      HIPCHK(launch_rowmm_f32(c, MK_BF16, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, tmp, 0, 1, &np));
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, tmp, 0, 1, &np));
       HIPCHK(launch_copy_pred(c, tmp, U, sizeof(float) * (uint64_t)c->n * N));
     }
   }
+  return OPE_OK;
+}
+
+// Mixed precision: when the last observed drift |U^T U - I|_F exceeds 1e-6,
+// one Newton-Schulz re-normalisation U <- U (3I - C) / 2 with C = U^T U (FP64
+// Gram of the FP32 block, FP32 product) before the step: the scheme keeps the
+// drift constant in exact arithmetic, the BF16 update adds to it, and this
+// takes a drift E to O(E^2).
+ope_status mixed_renormalize(ope_ctx* c, void* Uv) {
+  if (c->prec != OPE_MIXED || !(c->drift_seen > 1e-6)) return OPE_OK;
+  const int N = (int)c->N;
+  float* U = (float*)Uv;
+  int64_t np = 0;
+  HIPCHK(launch_gram_f32(c, MK_F64, U, N, N, U, N, N, c->n, c->C));
+  HIPCHK(launch_renorm_matrix(c, c->C, c->Z32));
+  if (N <= 128) {
+    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, U, 0, 0, &np));
+  } else {
+    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, (float*)c->Pb, 0, 0, &np));
+    HIPCHK(hipMemcpyAsync(U, c->Pb, sizeof(float) * (size_t)c->n * N, hipMemcpyDeviceToDevice, c->stream));
+  }
+  c->renorms += 1;
   return OPE_OK;
 }
 
@@ -287,7 +312,9 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
 // step if the residual is still above res_tol).
 ope_status run_step(ope_ctx* c, void* U, double tau, ope_step_info* info, double res_tol, bool* converged) {
   if (converged) *converged = false;
-  ope_status st = phase_residual(c, U);
+  ope_status st = mixed_renormalize(c, U);
+  if (st != OPE_OK) return st;
+  st = phase_residual(c, U);
   if (st != OPE_OK) return st;
   st = phase_warm_start(c, U);
   if (st != OPE_OK) return st;
@@ -454,7 +481,8 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
     if (!go[i]) continue;
     ope_ctx* c = b->ctx[i];
     HIPCHK(hipStreamWaitEvent(c->stream, b->start, 0));
-    ope_status st = phase_residual(c, U[i]);
+    ope_status st = mixed_renormalize(c, U[i]);
+    if (st == OPE_OK) st = phase_residual(c, U[i]);
     if (st == OPE_OK) st = phase_warm_start(c, U[i]);
     if (st == OPE_OK && hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
       st = OPE_EHIP;

@@ -114,6 +114,8 @@ struct ope_ctx {
   double eta_rel, eta_floor;
   int32_t max_iter;
   int32_t check_every;          // CG iterations between host convergence checks (even: graph chunks)
+  double drift_seen;            // drift of the last iterate whose scalars reached the host
+  int64_t renorms;              // mixed precision: re-normalisations applied
   int use_graphs;               // replay CG chunks as captured graphs
   int graph_state;              // 0 not built, 1 built, -1 capture failed (eager launches)
   hipStream_t cap_stream;       // private stream used only for capturing
@@ -218,6 +220,8 @@ hipError_t launch_jacobi_eig(ope_ctx* c, const double* Asym, double* evals);
 // sums of (delta_ij - D_ij)^2, ((N + 63) / 64)^2 values
 hipError_t launch_sqmm(ope_ctx* c, const double* A, int ta, const double* B, int tb, const double* C, double alpha,
                        double beta, double gamma, double* D, uint32_t N, const int32_t* skip, double* res);
+// Z32 (N x N, FP32) = (3 I - C) / 2
+hipError_t launch_renorm_matrix(ope_ctx* c, const double* C, float* Z32);
 // dst = src (bytes, a multiple of 8) unless the step's error flag is set
 hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);

@@ -136,5 +136,5 @@ def test_mixed_96_cubed_n512_steps():
     E_ref = O.energy(op, U64)
     assert abs(i1.energy - E_ref) <= 1e-6 * abs(E_ref)
     assert i2.energy < i1.energy
-    assert i1.drift <= 1e-5 and drift <= 1e-4
+    assert i1.drift <= 1e-5 and drift <= 2e-5
     assert np.isfinite(res)

@@ -5,7 +5,7 @@ products, FP64 small solve and checks) through the C ABI.
   on small-integer data (exactly representable in BF16, sums below 2^24); the
   FP32 stencil is within FP32 rounding of the oracle.
 * One mixed step equals the oracle's step (delta form, FP64, exact Step 1) to
-  the BF16 precision of the update.
+  the precision of the FP32 block and the BF16 P^T P.
 * Converged mixed runs: Ritz values within 1e-6 of the FP64 reference and
   |U^T U - I| < 1e-6; after converting to FP64 and finishing, within 1e-10.
 * At 64^3, N = 128: sampled FP32 stencil and the step's invariants.
@@ -184,5 +184,5 @@ def test_mixed_full_size_invariants():
     c = sum(1.0 / h ** 2 for h in op.h)
     assert np.max(np.abs(HU - ref)) <= 16 * EPS32 * (np.max(np.abs(op.V)) + 4 * c) * np.max(np.abs(U32))
     assert i2.energy < i1.energy and E2 < i2.energy
-    # far from convergence the BF16 update leaves a drift of order 1e-5
-    assert drift <= 1e-4 and i1.drift <= 1e-5
+    # FP32 storage and the FP32 update leave a drift of order 1e-6
+    assert drift <= 1e-5 and i1.drift <= 1e-5

@@ -256,6 +256,55 @@ def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
     return out
 
 
+def large_mixed(ope, torch, steps=5, warmup=2, tau=45.0):
+    """The large mixed-precision workload: 96^3 grid, N = 512, 8 wells (seed 0):
+    steps per second of the mixed form and of plain FP64 from the same start
+    block, with the orthogonality drift each leaves."""
+    import numpy as np
+    import workloads as W
+    p = W.wells_3d(m=96, N=512, seed=0)
+    out = {"workload": "wells3d_96^3_N512_seed0", "tau": tau, "steps": steps, "warmup": warmup}
+    for name, prec, dt_ in (("mixed", ope.OPE_MIXED, np.float32), ("plain_fp64", ope.OPE_FP64, np.float64)):
+        with ope.Context(p.grid, p.V, p.N, precision=prec) as ctx:
+            U = torch.from_numpy(p.U0.astype(dt_)).to("cuda")
+            for _ in range(warmup):
+                ope.ope_step(ctx.handle, U, tau)
+            torch.cuda.synchronize()
+            inner = 0
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                inner += ope.ope_step(ctx.handle, U, tau).inner_iterations
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res, _, drift = ope.ope_residual(ctx.handle, U, p.N, want_ritz=False)
+        out[name] = {"iter_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "inner_iterations_per_step": inner / steps,
+                     "residual_at_end": res, "drift_at_end": drift}
+    out["speedup_mixed"] = out["mixed"]["iter_per_s"] / out["plain_fp64"]["iter_per_s"]
+    return out
+
+
+def net_forward_rate(ope, torch, reps=10):
+    """The network alone on 128 residual columns of the 64^3 workload (the
+    learned step's dominant kernels): algorithmic TFLOP/s of the forward pass."""
+    import numpy as np
+    import workloads as W
+    p = W.wells_3d(m=64, N=128, seed=0, with_u0=False)
+    n = p.grid.n
+    with ope.Context(p.grid, p.V, 128) as ctx, ope.Net(ctx, 128, ope.load_net_weights()) as net:
+        X = torch.randn(128, n, device="cuda", dtype=torch.float32)
+        F = torch.empty_like(X)
+        ope.ope_net_forward(net.handle, X, None, 128, F)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ope.ope_net_forward(net.handle, X, None, 128, F)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    flop = 2.0 * (27 * 2 * 16 + 2 * 27 * 16 * 16 + 27 * 16) * n * 128
+    return {"ms_per_application": 1e3 * dt, "algorithmic_TFLOP_per_s": flop / dt / 1e12, "columns": 128,
+            "flop_per_application": flop}
+
+
 def copy_calibration(torch, gib=1.0, reps=5):
     """A plain device copy of known size, for scaling rocprofv3 byte counters."""
     n = int(gib * (1 << 30) // 8)
@@ -280,6 +329,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large"], default=None,
+                    help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -297,6 +348,21 @@ def main():
         raise SystemExit("bench.py needs a visible MI355X")
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.form:
+        if args.form == "large":
+            r = large_mixed(ope, torch, steps=args.steps, warmup=args.warmup)
+        elif args.form == "batched":
+            r = batched_throughput(ope, torch, steps=args.steps)
+        elif args.form == "net":
+            r = net_forward_rate(ope, torch, reps=args.steps)
+        else:
+            p = W.wells_3d(m=args.m, N=args.N, seed=args.seed, tau=args.tau)
+            if args.form == "mixed":
+                r = steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, args.steps, args.warmup)
+            else:
+                r = learned_steps_per_second(ope, torch, p, args.tau, args.steps, args.warmup)
+        print(json.dumps({"form": args.form, **r}), flush=True)
         return
 
     log(f"building workload {args.m}^3 N={args.N} seed={args.seed}")
@@ -388,6 +454,10 @@ def main():
         out["time_to_residual"] = time_to_residual(ope, torch)
         log("batched workload (64 problems)")
         out["batched"] = batched_throughput(ope, torch)
+        log("large mixed-precision workload (96^3, N=512)")
+        out["large_mixed"] = large_mixed(ope, torch)
+        log("network forward pass")
+        out["net_forward"] = net_forward_rate(ope, torch)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle step(s)")

@@ -98,7 +98,7 @@ def main(argv=None):
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     p.add_argument("--kernel", required=True)
-    p.add_argument("--copy-kernel", default="copyBuffer|elementwise")
+    p.add_argument("--copy-kernel", default="copyBuffer")
     p.add_argument("--copy-bytes", type=int, default=1 << 30)
     p.add_argument("--n", type=int, required=True)
     p.add_argument("--N", type=int, required=True)

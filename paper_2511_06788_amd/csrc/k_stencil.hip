@@ -388,6 +388,34 @@ __global__ __launch_bounds__(OPE_WG) void k_resid0(const double* __restrict__ U,
   wg_colsum<VW>(red, au, lane_ok, pp, NV, N, row + N);
 }
 
+// CG finalisation of one column from its dot product `tot` (after sweep A:
+// alpha; after sweep B: beta, rho and the convergence flag).
+template <int MODE>
+__device__ __forceinline__ void cg_finalise(uint32_t col, double tot, double* __restrict__ alpha,
+                                            double* __restrict__ beta, double* __restrict__ rho,
+                                            const double* __restrict__ target, int32_t* __restrict__ active,
+                                            OpeScalars* __restrict__ sc) {
+  if (MODE == RED_CG_ALPHA) {
+    const bool act = active[col] != 0;
+    if (act && !isfinite(tot)) sc->err = OPE_ENONFINITE;
+    alpha[col] = (act && tot > 0.0 && isfinite(tot)) ? rho[col] / tot : 0.0;
+  } else {  // RED_CG_BETA
+    if (active[col]) {
+      if (!isfinite(tot)) {
+        sc->err = OPE_ENONFINITE;
+        active[col] = 0;
+        beta[col] = 0.0;
+      } else {
+        beta[col] = tot / rho[col];
+        rho[col] = tot;
+        active[col] = tot > target[col] ? 1 : 0;
+      }
+    } else {
+      beta[col] = 0.0;
+    }
+  }
+}
+
 // Column sums of a [nrows][ncols] partial array in a fixed order, split over
 // gridDim.y work-groups per column group with a last-block second stage, and
 // an optional CG finalisation per column.
@@ -431,27 +459,42 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict
     if (threadIdx.x == 0) counters[blockIdx.x] = 0u;
   }
   if (grp != 0 || col >= ncols) return;
-  if (MODE == RED_PLAIN) {
-    out[col] = tot;
-  } else if (MODE == RED_CG_ALPHA) {
-    const bool act = active[col] != 0;
-    if (act && !isfinite(tot)) sc->err = OPE_ENONFINITE;
-    alpha[col] = (act && tot > 0.0 && isfinite(tot)) ? rho[col] / tot : 0.0;
-  } else {  // RED_CG_BETA
-    if (active[col]) {
-      if (!isfinite(tot)) {
-        sc->err = OPE_ENONFINITE;
-        active[col] = 0;
-        beta[col] = 0.0;
-      } else {
-        beta[col] = tot / rho[col];
-        rho[col] = tot;
-        active[col] = tot > target[col] ? 1 : 0;
-      }
-    } else {
-      beta[col] = 0.0;
+  if (MODE == RED_PLAIN) out[col] = tot;
+  else cg_finalise<MODE>(col, tot, alpha, beta, rho, target, active, sc);
+}
+
+// The same column sums for few columns (ncols <= 128) by one work-group with
+// no second stage: thread t sums column t % ncols over rows t / ncols,
+// t / ncols + G, ... (G = 256 / ncols row groups, eight loads in flight), then
+// the groups are added in order.  Avoids the cross-work-group fence of the
+// split form, which writes back the L2 lines the preceding sweep left dirty.
+template <int MODE>
+__global__ __launch_bounds__(OPE_WG) void k_reduce_few(const double* __restrict__ part, uint32_t nrows,
+                                                       uint32_t ncols, double* __restrict__ out,
+                                                       double* __restrict__ alpha, double* __restrict__ beta,
+                                                       double* __restrict__ rho, const double* __restrict__ target,
+                                                       int32_t* __restrict__ active, OpeScalars* __restrict__ sc) {
+  __shared__ double red[OPE_WG];
+  const uint32_t G = OPE_WG / ncols;
+  const uint32_t col = threadIdx.x % ncols, gi = threadIdx.x / ncols;
+  double a = 0.0;
+  if (gi < G) {
+    double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    uint32_t w = gi;
+    for (; w + 7 * G < nrows; w += 8 * G) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] += part[(uint64_t)(w + u * G) * ncols + col];
     }
+    for (; w < nrows; w += G) q[0] += part[(uint64_t)w * ncols + col];
+    a = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
   }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  if (gi != 0) return;
+  double tot = 0.0;
+  for (uint32_t k = 0; k < G; ++k) tot += red[k * ncols + col];
+  if (MODE == RED_PLAIN) out[col] = tot;
+  else cg_finalise<MODE>(col, tot, alpha, beta, rho, target, active, sc);
 }
 
 }  // namespace
@@ -578,6 +621,24 @@ hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* pold, void* r
 }
 
 hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols, double* out, int mode) {
+  if (ncols <= 128 && nrows * ncols <= (int64_t)1 << 17) {
+    const uint32_t nr = (uint32_t)nrows, nc = (uint32_t)ncols;
+    switch (mode) {
+      case RED_PLAIN:
+        hipLaunchKernelGGL((k_reduce_few<RED_PLAIN>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out, c->alpha,
+                           c->beta, c->rho, c->target, c->active, c->sc);
+        break;
+      case RED_CG_ALPHA:
+        hipLaunchKernelGGL((k_reduce_few<RED_CG_ALPHA>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out,
+                           c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+        break;
+      default:
+        hipLaunchKernelGGL((k_reduce_few<RED_CG_BETA>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out,
+                           c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+        break;
+    }
+    return hipGetLastError();
+  }
   const uint32_t ncg = (uint32_t)((ncols + 63) / 64);
   // enough rows per work-group to amortise, enough work-groups to spread the read
   uint32_t S = (uint32_t)((nrows + 255) / 256);

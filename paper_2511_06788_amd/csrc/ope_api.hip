@@ -70,6 +70,8 @@ void free_ctx(ope_ctx* c) {
   for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (int k = 0; k < 2; ++k)
+    if (c->chunk_ev[k]) (void)hipEventDestroy(c->chunk_ev[k]);
   delete c;
 }
 
@@ -167,10 +169,10 @@ void build_graphs(ope_ctx* c) {
 }
 
 // Enqueues CG iterations up to the next host check (a multiple of
-// check_every, or max_iter) and the copy of the column flags to the host.
-// Whole chunks run as graph replays when graphs are on (and no kernel is
-// being timed), the rest as eager launches.
-hipError_t cg_chunk(ope_ctx* c, int32_t* it, int32_t max_iter) {
+// check_every, or max_iter), the copy of the column flags into host slot
+// `slot` and that slot's event.  Whole chunks run as graph replays when graphs
+// are on (and no kernel is being timed), the rest as eager launches.
+hipError_t cg_chunk(ope_ctx* c, int32_t* it, int32_t max_iter, int slot) {
   const int K = c->check_every;
   const bool graphs = c->use_graphs && c->prof_kernel < 0 && K % 2 == 0;
   if (graphs && c->graph_state == 0) build_graphs(c);
@@ -185,25 +187,44 @@ hipError_t cg_chunk(ope_ctx* c, int32_t* it, int32_t max_iter) {
       *it += 1;
     }
   }
-  return hipMemcpyAsync(c->hactive, c->active, sizeof(int32_t) * c->N, hipMemcpyDeviceToHost, c->stream);
+  if ((e = hipMemcpyAsync(c->hactive + (size_t)slot * c->N, c->active, sizeof(int32_t) * c->N,
+                          hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return e;
+  return hipEventRecord(c->chunk_ev[slot], c->stream);
 }
 
-// After the copy of cg_chunk has completed: true if every column converged.
-bool cg_all_done(const ope_ctx* c) {
+// After host slot `slot` has been filled: true if every column converged.
+bool cg_all_done(const ope_ctx* c, int slot) {
+  const int32_t* a = c->hactive + (size_t)slot * c->N;
   for (int64_t j = 0; j < c->N; ++j)
-    if (c->hactive[j] != 0) return false;
+    if (a[j] != 0) return false;
   return true;
 }
 
 // CG iterations on H Y = U from the state prepared in rho/target/active, with
-// r in c->Rb[0]; returns the iteration count in *iters.
+// r in c->Rb[0]; returns the enqueued iteration count in *iters.  The next
+// chunk is enqueued before the flags of the previous one are read, so the GPU
+// does not wait for the host; a chunk enqueued after convergence finds every
+// column inactive and its kernels do nothing (the sweeps exit, the
+// reductions leave inactive columns at alpha = beta = 0).
 ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) {
   int32_t it = 0;
   bool done = false;
-  while (it < max_iter) {
-    HIPCHK(cg_chunk(c, &it, max_iter));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (cg_all_done(c)) {
+  int slot_next = 0, head = 0, nout = 0;
+  int q[2] = {0, 0};
+  for (;;) {
+    while (it < max_iter && nout < 2) {
+      HIPCHK(cg_chunk(c, &it, max_iter, slot_next));
+      q[(head + nout) & 1] = slot_next;
+      ++nout;
+      slot_next ^= 1;
+    }
+    if (nout == 0) break;
+    const int s = q[head];
+    head ^= 1;
+    --nout;
+    HIPCHK(hipEventSynchronize(c->chunk_ev[s]));
+    if (cg_all_done(c, s)) {
       done = true;
       break;
     }
@@ -511,7 +532,7 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
     for (int i = 0; i < P; ++i) {
       if (!pending[i]) continue;
       any = true;
-      if (cg_chunk(b->ctx[i], &bs.it[i], b->ctx[i]->max_iter) != hipSuccess) {
+      if (cg_chunk(b->ctx[i], &bs.it[i], b->ctx[i]->max_iter, 0) != hipSuccess) {
         bs.st[i] = OPE_EHIP;
         pending[i] = go[i] = 0;
       }
@@ -520,8 +541,8 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
     for (int i = 0; i < P; ++i) {
       if (!pending[i]) continue;
       ope_ctx* c = b->ctx[i];
-      HIPCHK(hipStreamSynchronize(c->stream));
-      if (cg_all_done(c)) {
+      HIPCHK(hipEventSynchronize(c->chunk_ev[0]));
+      if (cg_all_done(c, 0)) {
         bs.cgdone[i] = 1;
         pending[i] = 0;
       } else if (bs.it[i] >= c->max_iter) {
@@ -731,7 +752,8 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   ok &= dalloc(&c->counters, 4096) == hipSuccess;
   ok &= dalloc(&c->sc, 1) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hsc, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
-  ok &= hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * N, hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * 2 * N, hipHostMallocDefault) == hipSuccess;
+  for (int k = 0; k < 2; ++k) ok &= hipEventCreateWithFlags(&c->chunk_ev[k], hipEventDisableTiming) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hbuf, sizeof(double) * 2 * N, hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hsc2, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
   if (N > OPE_MAX_N_ONE_WG) {

@@ -108,7 +108,8 @@ struct ope_ctx {
   // scalars
   OpeScalars* sc;               // device
   OpeScalars* hsc;              // pinned host mirror
-  int32_t* hactive;             // pinned host mirror of active[]
+  int32_t* hactive;             // pinned host mirrors of active[] (two slots of N)
+  hipEvent_t chunk_ev[2];       // marks each slot's copy
   double* hbuf;                 // pinned host scratch (N doubles)
   // policy
   double eta_rel, eta_floor;

@@ -14,10 +14,10 @@ Prints one JSON line: outer steps per second (whole job, one GPU), the live
 roofline of the dominant kernel (CG sweep B, timed with HIP events on the
 library's stream), per-kernel timings, the mixed-precision and learned forms'
 steps per second on the same workload, measured time-to-residual-1e-8 (plain
-FP64; mixed precision with an FP64 finish; learned steps judged by the plain
-step) on a problem that converges within the run (64^3 grid, N = 17, which
-closes a level shell), and the CPU oracle timed on a bounded sample of the
-same workload.
+FP64; mixed precision to 1e-4 then FP64; learned steps judged by the plain
+step) on problems that converge within the run (64^3 and 96^3 grids, N = 17,
+which closes a level shell), the batched and the large (96^3, N = 512)
+workloads, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -101,16 +101,17 @@ def cpu_baseline(problem, tau, steps):
     }
 
 
-def time_to_residual(ope, torch, tol=1e-8, switch=1e-5):
-    """Wall time of Algorithm 1 from the start block to residual `tol` on a
-    problem whose spectral gap lets it converge in a few hundred steps: plain
-    FP64; the mixed form until `switch` followed by FP64 steps; and the learned
-    form (shipped weights, plain-step judge and fallback)."""
+def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
+    """Wall time of Algorithm 1 from the start block to residual `tol` on an m^3
+    wells problem whose block width N = 17 closes a level shell (it converges
+    in a few hundred steps): plain FP64; the mixed form until `switch`, then
+    FP64 steps; and the learned form (shipped weights, plain-step judge and
+    fallback)."""
     import numpy as np
     import workloads as W
-    p = W.wells_3d(m=64, N=17, seed=0)
+    p = W.wells_3d(m=m, N=17, seed=0)
     tau = 45.0
-    out = {"workload": "wells3d_64^3_N17_seed0", "tau": tau, "res_tol": tol}
+    out = {"workload": f"wells3d_{m}^3_N17_seed0", "tau": tau, "res_tol": tol}
     with ope.Context(p.grid, p.V, p.N) as cd, ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as cm:
         # warm the code paths
         ope.ope_solve(cd.handle, torch.from_numpy(p.U0).to("cuda"), tau, tol, 3)
@@ -452,6 +453,8 @@ def main():
         out["forms"]["learned"] = learned_steps_per_second(ope, torch, p, args.tau, min(ks, 40), 5)
         log("time to residual on the 64^3 N=17 problem")
         out["time_to_residual"] = time_to_residual(ope, torch)
+        log("time to residual on the 96^3 N=17 problem")
+        out["time_to_residual_96"] = time_to_residual(ope, torch, m=96)
         log("batched workload (64 problems)")
         out["batched"] = batched_throughput(ope, torch)
         log("large mixed-precision workload (96^3, N=512)")

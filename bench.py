@@ -337,8 +337,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         if int(os.environ.get("RANK", "0")) == 0:
-            print("bench.py measures one GPU: this build runs the step on a single MI355X and has no "
-                  "multi-GPU path (the row-slab sharding design is described in DESIGN.md).", flush=True)
+            print("bench.py measures one GPU: the library runs the step on a single MI355X and has no "
+                  "multi-GPU path (the grid would shard by z-slabs with halo exchange; not built).", flush=True)
         sys.exit(2)
 
     import torch

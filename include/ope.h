@@ -46,7 +46,7 @@ typedef enum {
   OPE_ENONFINITE = 4,  /* a NaN or Inf appeared in a reduction; U left unchanged */
   OPE_ECG_MAXIT = 5,   /* Step 1 hit its iteration cap before the tolerance (step still applied) */
   OPE_EPIVOT = 6,      /* non-positive or tiny pivot in a small FP64 solve; U left unchanged */
-  OPE_EUNSUPPORTED = 7 /* valid request this build does not implement */
+  OPE_EUNSUPPORTED = 7 /* valid request the library does not implement */
 } ope_status;
 
 /* OPE_FP64: every block and every operation in FP64.
@@ -97,7 +97,7 @@ typedef struct {
 typedef struct ope_ctx ope_ctx;
 
 /* Create a context for one operator and block width N (1 <= N <= 512,
- * N <= n; larger N returns OPE_EUNSUPPORTED in this build).  Copies V to the
+ * N <= n; larger N returns OPE_EUNSUPPORTED).  Copies V to the
  * device, allocates the workspace (five n x N blocks in the precision's storage
  * type plus O(N^2) matrices), and binds `stream` (a hipStream_t, or NULL).
  * Steps 2-3 run as one-work-group Gauss-Jordan kernels for N <= 128 and as

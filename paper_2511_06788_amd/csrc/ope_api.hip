@@ -635,7 +635,7 @@ const char* ope_status_string(ope_status s) {
     case OPE_ENONFINITE: return "non-finite value in a reduction";
     case OPE_ECG_MAXIT: return "inner CG reached its iteration cap";
     case OPE_EPIVOT: return "non-positive pivot in a small FP64 solve";
-    case OPE_EUNSUPPORTED: return "not supported by this build";
+    case OPE_EUNSUPPORTED: return "not supported by the library";
   }
   return "unknown status";
 }

@@ -194,7 +194,8 @@ def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
 
 def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
     """The batched workload (64 well problems, grid edges 24..48, N 16..128):
-    problem-steps per second of ope_batch_step before and after the autotuner,
+    problem-steps per second of ope_batch_step (per-problem CG launches on the
+    problems' streams; shared CG launches, before and after the autotuner),
     and of the same problems stepped one after the other with ope_step."""
     import numpy as np
     import workloads as W
@@ -240,6 +241,9 @@ def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
             return inner, nbytes
 
         t_seq, in_seq = timed(sequential_steps)
+        b.set_shared(False)
+        t_bs, in_bs = timed(batch_steps)
+        b.set_shared(True)
         t_b0, in_b0 = timed(batch_steps)
         t_tune0 = time.perf_counter()
         buckets = b.autotune()
@@ -251,6 +255,7 @@ def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
         return {"problem_steps_per_s": ps / t, "seconds": t, "inner_iterations": r[0],
                 "cg_sweep_GB_per_s": r[1] / t / 1e9}
     out["sequential"] = rec(t_seq, in_seq)
+    out["batched_per_problem_launches"] = rec(t_bs, in_bs)
     out["batched_default_shapes"] = rec(t_b0, in_b0)
     out["batched_autotuned"] = dict(rec(t_b1, in_b1), buckets=buckets, autotune_seconds=t_tune)
     out["speedup_vs_sequential"] = t_seq / t_b1

@@ -97,7 +97,9 @@ typedef struct {
 typedef struct ope_ctx ope_ctx;
 
 /* Create a context for one operator and block width N (1 <= N <= 512,
- * N <= n; larger N returns OPE_EUNSUPPORTED).  Copies V to the
+ * N <= n; larger N returns OPE_EUNSUPPORTED, and so does a plane of the
+ * march axis holding 2 GiB or more of FP64 block rows, m0 m1 N 8 bytes in 3D,
+ * m0 N 8 in 2D: the stencil addresses one plane through 32-bit offsets).  Copies V to the
  * device, allocates the workspace (five n x N blocks in the precision's storage
  * type plus O(N^2) matrices), and binds `stream` (a hipStream_t, or NULL).
  * Steps 2-3 run as one-work-group Gauss-Jordan kernels for N <= 128 and as
@@ -295,9 +297,19 @@ ope_status ope_batch_step(ope_batch* batch, void* const* U, double tau, ope_step
  * test and no learned steps).  info: count entries, nullable. */
 ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double res_tol, int32_t max_steps,
                            ope_solve_info* info);
+/* shared = 1 (default): Step 1's CG sweeps and column reductions of all
+ * problems whose column sums fit one work-group (at most 128 columns) run as
+ * one launch per phase and class of problems (storage type, vector width,
+ * passes per plane, split x lines) on a batch stream, each launch's
+ * work-groups spread over (problem, tile) work items of every problem's own
+ * sweep shape; same kernels and summation order as the per-problem launches,
+ * so the results are identical.  shared = 0: every problem's CG runs on its
+ * own stream. */
+ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
 /* Autotuner: for every bucket of problems (grid edges and vector-column count
  * in steps of 8) time short CG runs of the first problem over the sweep shapes
- * (passes per plane 1/2/4, work-group order, column chunking, march chunks)
+ * (passes per plane 1/2, work-group order, non-temporal stores, column
+ * chunking, march chunks)
  * and give every problem of the bucket the fastest; FP32 contexts keep the
  * default.  *tuned (nullable) = number of buckets.  Synchronises; uses a
  * temporary n x N block per tuned bucket. */
@@ -314,7 +326,8 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * of 256/8 grid points of one x segment (q in {1, 2, 4}; more passes per
  * plane mean fewer x segments but more registers), and the march axis is cut
  * into march_chunks ranges (0 = automatic: at least 512 work-groups).  The
- * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR.
+ * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR, plus
+ * OPE_SWEEP_NONTEMPORAL when a row holds more than 32 16-byte vectors.
  * q_max = 0 lets the library choose.  flags: OPE_SWEEP_CHUNK_MAJOR puts the
  * work-groups of one column chunk next to each other (so one XCD streams one
  * chunk of every side line) instead of those of one side line;

@@ -134,6 +134,70 @@ __global__ __launch_bounds__(256) void k_gram(const TI* __restrict__ A, uint64_t
       }
 }
 
+// Wide Grams (both sides >= 128 columns, FP32 and BF16 kinds): work-group tile
+// 128 x 128, each wave a 64 x 64 sub-tile (4 x 4 MFMA blocks), so every
+// operand load feeds four MFMAs instead of two.
+constexpr int GT2 = 128;
+constexpr int GW2 = 64;
+
+template <typename TI, int KIND>
+__global__ __launch_bounds__(256) void k_gram_wide(const TI* __restrict__ A, uint64_t lda, uint32_t na,
+                                                   const TI* __restrict__ B, uint64_t ldb, uint32_t nb,
+                                                   uint32_t rows, uint32_t rows_per_split, double* __restrict__ part) {
+  using M = Mk<KIND>;
+  using acc_t = typename M::acc_t;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t i_base = blockIdx.y * GT2 + (wave >> 1) * GW2;
+  const uint32_t j_base = blockIdx.x * GT2 + (wave & 1u) * GW2;
+  const uint32_t ks = blockIdx.z;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = zero_acc<acc_t>();
+  const uint32_t r0 = ks * rows_per_split;
+  const uint32_t r1 = min(rows, r0 + rows_per_split);
+  bool iok[4], jok[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    iok[a] = i_base + a * 16 + ci < na;
+    jok[a] = j_base + a * 16 + ci < nb;
+  }
+  if (i_base < na && j_base < nb) {
+    for (uint32_t p = r0; p < r1; p += M::KSTEP) {
+      TI av[4][M::KPL], bv[4][M::KPL];
+#pragma unroll
+      for (int e = 0; e < M::KPL; ++e) {
+        const uint32_t row = p + kr * M::KPL + e;
+        const bool rok = row < r1;
+        const TI* ar = A + (uint64_t)row * lda + i_base + ci;
+        const TI* br = B + (uint64_t)row * ldb + j_base + ci;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          av[a][e] = (rok && iok[a]) ? ar[16 * a] : TI(0);
+          bv[a][e] = (rok && jok[a]) ? br[16 * a] : TI(0);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mma<KIND, TI>(av[a], bv[b], acc[a][b]);
+    }
+  }
+  double* out = part + (uint64_t)ks * na * nb;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = i_base + a * 16 + M::drow(kr, r);
+        const uint32_t j = j_base + b * 16 + ci;
+        if (i < na && j < nb) out[(uint64_t)i * nb + j] = (double)acc[a][b][r];
+      }
+}
+
 // Row-block products Out = cbeta Cm + ascale (X0 M0 + X1 M1).  Work-group =
 // 4 waves, 2 (rows) x 2 (columns); a wave owns 32 rows x 64 columns (2 x 4
 // MFMA blocks), the work-group 64 x 128.  TI is the type of X, M, Cm and Out.
@@ -299,7 +363,11 @@ __global__ __launch_bounds__(256) void k_sqmm(const double* __restrict__ A, int 
 template <typename TI, int KIND>
 hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int64_t ldb, int nb, int64_t rows,
                   double* out) {
-  const uint32_t ti = (uint32_t)((na + GT - 1) / GT), tj = (uint32_t)((nb + GT - 1) / GT);
+  // FP64 MFMA keeps the 64 x 64 tile: its 16 accumulators per wave cost more
+  // occupancy than the operand reuse gains (measured)
+  const bool wide = KIND != MK_F64 && na >= GT2 && nb >= GT2;
+  const int tile = wide ? GT2 : GT;
+  const uint32_t ti = (uint32_t)((na + tile - 1) / tile), tj = (uint32_t)((nb + tile - 1) / tile);
   // about 1024 work-groups in total, within the partial buffer
   int64_t ks = 1024 / (int64_t)(ti * tj);
   if (ks < 1) ks = 1;
@@ -314,8 +382,13 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
   if (ks < 1) ks = 1;
   {
     ProfScope ps(c, OPE_KERNEL_GRAM);
-    hipLaunchKernelGGL((k_gram<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda,
-                       (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
+    if (wide)
+      hipLaunchKernelGGL((k_gram_wide<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A,
+                         (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps,
+                         c->part);
+    else
+      hipLaunchKernelGGL((k_gram<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda,
+                         (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

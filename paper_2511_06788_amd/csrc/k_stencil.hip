@@ -86,34 +86,141 @@ __device__ __forceinline__ void wg_colsum(double* red, const double (&acc)[VW], 
 // (y in 3D), one x segment, one chunk of columns and one range of the march
 // axis (z in 3D, y in 2D).  It walks that range plane by plane, keeping the
 // field at planes k-1, k, k+1 in registers, so each row is read from HBM once;
-// x neighbours come from the current plane staged in LDS, side neighbours from
+// x neighbours come from the current plane staged in LDS (and, at the ends of
+// an x segment, from the neighbouring segment's rows), side neighbours from
 // the rows the adjacent work-groups of the same XCD stream at the same time
-// (L2 hits).  The march is software-pipelined: while plane k is computed, the
-// centre rows of plane k+2 and the side rows, diagonal and y of plane k+1 are
-// already in flight, so no load latency sits on the per-plane critical path.
+// (L2 hits).
+//
+// Memory access is through buffer descriptors, one per array and plane (base
+// = the plane's first row, range = one plane), with per-lane byte offsets
+// that stay fixed over the march.  A lane without a row to touch (outside the
+// grid or the column range) carries an offset beyond every range: its loads
+// return zero and its stores are dropped by the range check, and a plane
+// outside the march gets an empty range.  So no load or store sits under a
+// branch.
+//
+// Software pipeline: at plane k the loads for plane k+2 (its side rows,
+// x-segment ends, diagonal and y, and the centre row of plane k+3) are issued
+// into one of two register sets, while the other set, issued one plane
+// earlier, is taken in at the end of plane k.  Vector-memory counters retire
+// in issue order, so a load has two plane steps to arrive; with every access
+// unconditional the compiler's wait before taking a set in covers exactly the
+// accesses issued before it.
 // MODE selects what is done with (H p) at each point:
 //   SW_APPLY   out = H x
 //   SW_PAP     sigma_j += p_j (H p)_j,          p = r + beta p_old
 //   SW_UPDATE  y += alpha p, r' = r - alpha H p, p written, rho'_j += r'_j^2
 enum { SW_APPLY = 0, SW_PAP = 1, SW_UPDATE = 2 };
 
-template <typename T, int VW, int Q, int MODE, bool FIRST>
-__global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, const T* __restrict__ F1,
-                                                  T* __restrict__ O0, T* __restrict__ O1,
-                                                  T* __restrict__ Yv, const double* __restrict__ alpha,
-                                                  const double* __restrict__ beta, const int32_t* __restrict__ active,
-                                                  const T* __restrict__ diag, OpeGrid g, MarchShape ms,
-                                                  uint32_t N, uint32_t NV, double* __restrict__ part,
-                                                  OpeScalars* __restrict__ sc) {
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int RSRC_FLAGS = 0x00020000;        // raw (unformatted) 32-bit dword access
+constexpr uint32_t NO_ROW = 0x80000000u;      // a byte offset beyond every plane's range
+constexpr int AUX_NT = 2;                     // non-temporal (streamed, not kept in the caches)
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, RSRC_FLAGS);
+}
+
+typedef unsigned int BufU4 __attribute__((ext_vector_type(4)));
+typedef unsigned int BufU2 __attribute__((ext_vector_type(2)));
+
+// One row chunk (VW elements of T, 4, 8 or 16 bytes) through a descriptor.
+template <typename T, int VW>
+__device__ __forceinline__ void bld(Rsrc rs, uint32_t off, T (&v)[VW]) {
+  constexpr int B = (int)sizeof(T) * VW;
+  RowVec<T, VW> t;
+  if constexpr (B == 16) t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  else if constexpr (B == 8) t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+  else t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+#pragma unroll
+  for (int k = 0; k < VW; ++k) v[k] = t.v[k];
+}
+
+template <typename T>
+__device__ __forceinline__ T bld1(Rsrc rs, uint32_t off) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+
+template <typename T, int VW, int AUX>
+__device__ __forceinline__ void bst(Rsrc rs, uint32_t off, const T (&v)[VW]) {
+  constexpr int B = (int)sizeof(T) * VW;
+  RowVec<T, VW> t;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) t.v[k] = v[k];
+  if constexpr (B == 16) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(BufU4, t), rs, off, 0, AUX);
+  else if constexpr (B == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, t), rs, off, 0, AUX);
+  else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, t), rs, off, 0, AUX);
+}
+
+// A register move the compiler cannot fold away.  Taking a load set in
+// through these leaves its load registers dead, so the loop keeps each set in
+// the same registers; otherwise the combined values (r + beta p_old, formed in
+// place) occupy them, the next load of the set lands elsewhere and is copied
+// back at the loop edge, and the copy must wait for the load.
+template <typename T>
+__device__ __forceinline__ T vmove(T x) {
+  T r;
+  if constexpr (sizeof(T) == 8) asm volatile("v_mov_b64 %0, %1" : "=&v"(r) : "v"(x));
+  else asm volatile("v_mov_b32 %0, %1" : "=&v"(r) : "v"(x));
+  return r;
+}
+
+// The loads of one plane step, per pass q (raw values; r and p_old apart).
+template <typename T, int VW, int Q>
+struct MarchLoads {
+  T cr[Q][VW], cp[Q][VW];      // centre row of plane k+3
+  T lr[Q][VW], lp[Q][VW];      // side row below, plane k+2
+  T ur[Q][VW], up[Q][VW];      // side row above, plane k+2
+  T hr[Q][VW], hp[Q][VW];      // the x-segment end's outer neighbour, plane k+2
+  T d[Q];                      // diagonal, plane k+2
+  T y[Q][VW];                  // y, plane k+2 (SW_UPDATE)
+};
+
+template <typename T, int VW, int Q, bool TWO, bool UPD, bool HALO>
+__device__ __forceinline__ void take_set(const MarchLoads<T, VW, Q>& a, MarchLoads<T, VW, Q>& b) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      b.cr[q][v] = vmove(a.cr[q][v]);
+      b.lr[q][v] = vmove(a.lr[q][v]);
+      b.ur[q][v] = vmove(a.ur[q][v]);
+      if constexpr (TWO) {
+        b.cp[q][v] = vmove(a.cp[q][v]);
+        b.lp[q][v] = vmove(a.lp[q][v]);
+        b.up[q][v] = vmove(a.up[q][v]);
+      }
+      if constexpr (HALO) {
+        b.hr[q][v] = vmove(a.hr[q][v]);
+        if constexpr (TWO) b.hp[q][v] = vmove(a.hp[q][v]);
+      }
+      if constexpr (UPD) b.y[q][v] = vmove(a.y[q][v]);
+    }
+    b.d[q] = vmove(a.d[q]);
+  }
+}
+
+// The march of work item t (0 <= t < lines * nxs * cc * mc) of one problem;
+// shared by the single-problem kernel and the batched kernel below.  HALO:
+// the x line is split into several segments (nxs > 1).  A plane of one array
+// must be smaller than 2 GiB (checked when the context is created).
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO>
+__device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0, const T* __restrict__ F1,
+                                           T* __restrict__ O0, T* __restrict__ O1, T* __restrict__ Yv,
+                                           const double* __restrict__ alpha, const double* __restrict__ beta,
+                                           const int32_t* __restrict__ active, const T* __restrict__ diag,
+                                           const OpeGrid& g, const MarchShape& ms, uint32_t N, uint32_t NV,
+                                           double* __restrict__ part, OpeScalars* __restrict__ sc) {
   constexpr bool TWO = (MODE != SW_APPLY) && !FIRST;   // field is r + beta p_old (two loads per value)
   constexpr bool UPD = (MODE == SW_UPDATE);
+  constexpr int AUX_OUT = 0;
   __shared__ T lds[2 * Q * OPE_WG * VW];
   __shared__ double red[OPE_WG * VW];
   if (MODE != SW_APPLY) {
     if (!any_active(active, N)) return;
-    if (MODE == SW_PAP && blockIdx.x == 0 && threadIdx.x == 0) sc->cg_iters += 1;
+    if (MODE == SW_PAP && t == 0 && threadIdx.x == 0) sc->cg_iters += 1;
   }
-  uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t mchunk_id = t % ms.mc;
   t /= ms.mc;
   uint32_t cchunk, xs, line;
@@ -131,47 +238,55 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
   const uint32_t cv = threadIdx.x % ms.ncv, slot = threadIdx.x / ms.ncv;
   const uint32_t colv = cchunk * ms.ncv + cv;
   const bool lane_ok = slot < ms.pp && colv < NV;
-  const uint64_t coff = (uint64_t)colv * VW;
   const uint32_t z0 = mchunk_id * ms.mchunk;
   const uint32_t z1 = min(ms.mlen, z0 + ms.mchunk);
-  const uint64_t lbase = (uint64_t)line * ms.side_stride;
   const bool side_lo = ms.has_side && line > 0;
   const bool side_hi = ms.has_side && line + 1 < ms.lines;
-  const uint64_t sstride = (uint64_t)ms.side_stride * N;
+  // one plane of an array: march_stride rows of N values
+  const uint64_t plane_elems = (uint64_t)ms.march_stride * N;
+  const uint32_t plane_bytes = (uint32_t)(plane_elems * sizeof(T));
+  const uint32_t row_bytes = N * (uint32_t)sizeof(T);
 
   T b[VW], a[VW];
   double acc[VW];
 #pragma unroll
   for (int v = 0; v < VW; ++v) {
-    b[v] = (TWO && lane_ok) ? (T)beta[coff + v] : T(0);
-    a[v] = (UPD && lane_ok) ? (T)alpha[coff + v] : T(0);
+    b[v] = (TWO && lane_ok) ? (T)beta[colv * VW + v] : T(0);
+    a[v] = (UPD && lane_ok) ? (T)alpha[colv * VW + v] : T(0);
     acc[v] = 0.0;
   }
   const T cx = (T)g.cx, cs = (T)ms.cs, cm = (T)ms.cm;
-  uint32_t xq[Q];
+  // per-pass byte offsets within a plane (NO_ROW where there is no row)
+  uint32_t xq[Q], oc[Q], ol[Q], ou[Q], oh[Q], od[Q];
   bool okq[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const uint32_t xi = q * ms.pp + slot;
     xq[q] = xs * ms.xseg + xi;
     okq[q] = lane_ok && xi < ms.xseg && xq[q] < g.m0;
+    const uint32_t p = xq[q] + line * ms.side_stride;     // point index within the plane
+    oc[q] = okq[q] ? p * row_bytes + colv * VW * (uint32_t)sizeof(T) : NO_ROW;
+    ol[q] = (okq[q] && side_lo) ? oc[q] - ms.side_stride * row_bytes : NO_ROW;
+    ou[q] = (okq[q] && side_hi) ? oc[q] + ms.side_stride * row_bytes : NO_ROW;
+    oh[q] = NO_ROW;
+    if (HALO && okq[q]) {
+      if (xi == 0 && xq[q] > 0) oh[q] = oc[q] - row_bytes;
+      else if (xi + 1 == ms.xseg && xq[q] + 1 < g.m0) oh[q] = oc[q] + row_bytes;
+    }
+    od[q] = okq[q] ? p * (uint32_t)sizeof(T) : NO_ROW;
   }
-  auto off_of = [&](uint32_t x, uint32_t z) -> uint64_t {
-    return ((uint64_t)x + lbase + (uint64_t)z * ms.march_stride) * N + coff;
+  // descriptors of plane z of an array and of the diagonal; empty unless `valid`
+  // (an empty one points at plane 0, so no address is formed outside the array)
+  auto prs = [&](const T* base, uint32_t z, bool valid) -> Rsrc {
+    return make_rsrc(base + (valid ? (uint64_t)z * plane_elems : 0), valid ? plane_bytes : 0u);
+  };
+  auto drs = [&](uint32_t z, bool valid) -> Rsrc {
+    return make_rsrc(diag + (valid ? (uint64_t)z * ms.march_stride : 0),
+                     valid ? ms.march_stride * (uint32_t)sizeof(T) : 0u);
   };
   auto zero = [](T (&o)[VW]) {
 #pragma unroll
     for (int v = 0; v < VW; ++v) o[v] = T(0);
-  };
-  // raw loads of one field value (r and p_old, or x); combined later
-  auto ld_raw = [&](bool ok, uint64_t o, T (&r)[VW], T (&po)[VW]) {
-    if (ok) {
-      ldv<T, VW>(F0, o, r);
-      if constexpr (TWO) ldv<T, VW>(F1, o, po);
-    } else {
-      zero(r);
-      if constexpr (TWO) zero(po);
-    }
   };
   auto comb = [&](const T (&r)[VW], const T (&po)[VW], T (&out)[VW]) {
 #pragma unroll
@@ -179,60 +294,85 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
   };
 
   // pipeline registers (per pass q)
-  T pm[Q][VW], pz[Q][VW], p1[Q][VW];               // field at z-1, z, z+1
-  T rz[Q][VW], r1[Q][VW];                           // r at z, z+1 (UPDATE)
-  T smz[Q][VW], spz[Q][VW];                         // side neighbours at z
-  T dz[Q], yz[Q][VW];                               // diagonal and y at z
-  T c2r[Q][VW], c2p[Q][VW];                         // in flight: centre of z+2
-  T s1r[Q][VW], s1p[Q][VW], t1r[Q][VW], t1p[Q][VW];  // in flight: side rows of z+1
-  T d1[Q], y1[Q][VW];                               // in flight: diagonal, y of z+1
+  T pm[Q][VW], pz[Q][VW], p1[Q][VW];   // field at z-1, z, z+1
+  T rz[Q][VW], r1[Q][VW];               // r at z, z+1 (SW_UPDATE)
+  T smz[Q][VW], spz[Q][VW], hz[Q][VW];  // side neighbours and segment-end neighbour at z
+  T dz[Q], yz[Q][VW];                   // diagonal and y at z
 
-  // prologue: everything for plane z0 and the centre of z0+1
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    T tr[VW], tp[VW];
-    const bool ok = okq[q] && z0 < z1;
-    ld_raw(ok && z0 > 0, ok && z0 > 0 ? off_of(xq[q], z0 - 1) : 0, tr, tp);
-    comb(tr, tp, pm[q]);
-    ld_raw(ok, ok ? off_of(xq[q], z0) : 0, tr, tp);
-    comb(tr, tp, pz[q]);
-#pragma unroll
-    for (int v = 0; v < VW; ++v) rz[q][v] = tr[v];
-    ld_raw(ok && z0 + 1 < ms.mlen, ok && z0 + 1 < ms.mlen ? off_of(xq[q], z0 + 1) : 0, tr, tp);
-    comb(tr, tp, p1[q]);
-#pragma unroll
-    for (int v = 0; v < VW; ++v) r1[q][v] = tr[v];
-    const uint64_t o = ok ? off_of(xq[q], z0) : 0;
-    ld_raw(ok && side_lo, o - (side_lo ? sstride : 0), tr, tp);
-    comb(tr, tp, smz[q]);
-    ld_raw(ok && side_hi, o + (side_hi ? sstride : 0), tr, tp);
-    comb(tr, tp, spz[q]);
-    dz[q] = ok ? diag[o / N] : T(0);
-    if constexpr (UPD) {
-      if (ok) ldv<T, VW>(Yv, o, yz[q]);
-      else zero(yz[q]);
-    }
-  }
-
-  for (uint32_t z = z0; z < z1; ++z) {
-    // issue the loads of the next iterations
-    const bool n2 = z + 2 < ms.mlen && z + 1 < z1;
-    const bool n1 = z + 1 < z1;
+  // loads for plane zs (side rows, segment ends, diagonal, y) and the centre row of zs + 1
+  auto issue = [&](uint32_t zs, MarchLoads<T, VW, Q>& L) {
+    const bool vs = zs < z1, vc = vs && zs + 1 < ms.mlen;
+    const Rsrc c0 = prs(F0, zs + 1, vc), s0 = prs(F0, zs, vs);
+    const Rsrc c1 = prs(F1, zs + 1, vc && TWO), s1 = prs(F1, zs, vs && TWO);
+    const Rsrc dr = drs(zs, vs), yr = prs(Yv, zs, vs && UPD);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const bool ok = okq[q];
-      ld_raw(ok && n2, ok && n2 ? off_of(xq[q], z + 2) : 0, c2r[q], c2p[q]);
-      const uint64_t o1 = (ok && n1) ? off_of(xq[q], z + 1) : 0;
-      ld_raw(ok && n1 && side_lo, o1 - (ok && n1 && side_lo ? sstride : 0), s1r[q], s1p[q]);
-      ld_raw(ok && n1 && side_hi, o1 + (ok && n1 && side_hi ? sstride : 0), t1r[q], t1p[q]);
-      d1[q] = (ok && n1) ? diag[o1 / N] : T(0);
-      if constexpr (UPD) {
-        if (ok && n1) ldv<T, VW>(Yv, o1, y1[q]);
-        else zero(y1[q]);
+      bld<T, VW>(c0, oc[q], L.cr[q]);
+      if constexpr (TWO) bld<T, VW>(c1, oc[q], L.cp[q]);
+      bld<T, VW>(s0, ol[q], L.lr[q]);
+      if constexpr (TWO) bld<T, VW>(s1, ol[q], L.lp[q]);
+      bld<T, VW>(s0, ou[q], L.ur[q]);
+      if constexpr (TWO) bld<T, VW>(s1, ou[q], L.up[q]);
+      if constexpr (HALO) {
+        bld<T, VW>(s0, oh[q], L.hr[q]);
+        if constexpr (TWO) bld<T, VW>(s1, oh[q], L.hp[q]);
       }
+      L.d[q] = bld1<T>(dr, od[q]);
+      if constexpr (UPD) bld<T, VW>(yr, oc[q], L.y[q]);
     }
-    // stage plane z for the x neighbours
-    T* buf = lds + (z & 1u) * (Q * OPE_WG * VW);
+  };
+  // end of plane z: shift the planes and take in the set issued for plane z + 1
+  // (moved out of its load registers first, so those stay free for the next
+  // load of the same set)
+  auto rotate = [&](const MarchLoads<T, VW, Q>& Lin) {
+    MarchLoads<T, VW, Q> L;
+    take_set<T, VW, Q, TWO, UPD, HALO>(Lin, L);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        pm[q][v] = pz[q][v];
+        pz[q][v] = p1[q][v];
+        if constexpr (UPD) {
+          rz[q][v] = r1[q][v];
+          r1[q][v] = L.cr[q][v];
+          yz[q][v] = L.y[q][v];
+        }
+      }
+      comb(L.cr[q], L.cp[q], p1[q]);
+      comb(L.lr[q], L.lp[q], smz[q]);
+      comb(L.ur[q], L.up[q], spz[q]);
+      if constexpr (HALO) comb(L.hr[q], L.hp[q], hz[q]);
+      dz[q] = L.d[q];
+    }
+  };
+
+  // prologue: planes z0 - 1 and z0, then plane z0's set (its side rows etc.
+  // and the centre of z0 + 1) through the same rotate
+  {
+    const uint32_t zm = z0 > 0 ? z0 - 1 : 0;
+    const Rsrc m0r = prs(F0, zm, z0 > 0), m1r = prs(F1, zm, z0 > 0 && TWO);
+    const Rsrc c0r = prs(F0, z0, true), c1r = prs(F1, z0, TWO);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T tr[VW], tp[VW];
+      zero(tp);
+      bld<T, VW>(m0r, oc[q], tr);
+      if constexpr (TWO) bld<T, VW>(m1r, oc[q], tp);
+      comb(tr, tp, pz[q]);                      // becomes pm
+      bld<T, VW>(c0r, oc[q], tr);
+      if constexpr (TWO) bld<T, VW>(c1r, oc[q], tp);
+      comb(tr, tp, p1[q]);                      // becomes pz
+#pragma unroll
+      for (int v = 0; v < VW; ++v) r1[q][v] = tr[v];
+    }
+    MarchLoads<T, VW, Q> L0;
+    issue(z0, L0);
+    rotate(L0);
+  }
+
+  // plane z: stage it for the x neighbours, apply H, use the result
+  auto compute = [&](uint32_t z, T* __restrict__ buf) {
     // lanes past the last whole slot (when ncv does not divide the work-group)
     // hold no point, and their index would alias the next pass's first slot
     if (slot < ms.pp) {
@@ -242,81 +382,67 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
         for (int v = 0; v < VW; ++v) buf[((q * ms.pp + slot) * ms.ncv + cv) * VW + v] = pz[q][v];
     }
     __syncthreads();
+    const Rsrc o0 = prs(O0, z, MODE != SW_PAP);
+    const Rsrc o1 = prs(O1, z, UPD), yo = prs(Yv, z, UPD);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      if (!okq[q]) continue;
-      const uint32_t x = xq[q];
       const uint32_t xi = q * ms.pp + slot;
-      const uint64_t o = off_of(x, z);
+      // x neighbours: the staged plane, or the segment end's outer row (zero
+      // where there is none: at the grid boundary, or a lane past the grid)
+      const uint32_t im = xi > 0 ? xi - 1 : 0, ip = xi + 1 < ms.xseg ? xi + 1 : xi;
       T xm[VW], xp[VW];
-      zero(xm);
-      zero(xp);
-      if (x > 0) {
-        if (xi > 0) {
 #pragma unroll
-          for (int v = 0; v < VW; ++v) xm[v] = buf[((xi - 1) * ms.ncv + cv) * VW + v];
-        } else {
-          T tr[VW], tp[VW];
-          ld_raw(true, o - N, tr, tp);
-          comb(tr, tp, xm);
-        }
-      }
-      if (x + 1 < g.m0) {
-        if (xi + 1 < ms.xseg) {
-#pragma unroll
-          for (int v = 0; v < VW; ++v) xp[v] = buf[((xi + 1) * ms.ncv + cv) * VW + v];
-        } else {
-          T tr[VW], tp[VW];
-          ld_raw(true, o + N, tr, tp);
-          comb(tr, tp, xp);
-        }
+      for (int v = 0; v < VW; ++v) {
+        const T lm = buf[(im * ms.ncv + cv) * VW + v], lp = buf[(ip * ms.ncv + cv) * VW + v];
+        const T hm = HALO ? hz[q][v] : T(0);
+        xm[v] = xi > 0 ? lm : hm;
+        xp[v] = xi + 1 < ms.xseg ? lp : hm;
       }
       T hx[VW];
 #pragma unroll
       for (int v = 0; v < VW; ++v)
         hx[v] = dz[q] * pz[q][v] - (cx * (xm[v] + xp[v]) + cs * (smz[q][v] + spz[q][v]) + cm * (pm[q][v] + p1[q][v]));
       if constexpr (MODE == SW_APPLY) {
-        if (ms.nt) stv_nt<T, VW>(O0, o, hx);
-        else stv<T, VW>(O0, o, hx);
+        if (ms.nt) bst<T, VW, AUX_NT>(o0, oc[q], hx);
+        else bst<T, VW, AUX_OUT>(o0, oc[q], hx);
       } else if constexpr (MODE == SW_PAP) {
 #pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] += (double)pz[q][v] * (double)hx[v];
+        for (int v = 0; v < VW; ++v) acc[v] += okq[q] ? (double)pz[q][v] * (double)hx[v] : 0.0;
       } else {
         T yv[VW], rnew[VW];
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
           yv[v] = yz[q][v] + a[v] * pz[q][v];
           rnew[v] = rz[q][v] - a[v] * hx[v];
-          acc[v] += (double)rnew[v] * (double)rnew[v];
+          acc[v] += okq[q] ? (double)rnew[v] * (double)rnew[v] : 0.0;
         }
         if (ms.nt) {
-          stv_nt<T, VW>(Yv, o, yv);
-          stv_nt<T, VW>(O0, o, rnew);
-          stv_nt<T, VW>(O1, o, pz[q]);
+          bst<T, VW, AUX_NT>(yo, oc[q], yv);
+          bst<T, VW, AUX_NT>(o0, oc[q], rnew);
+          bst<T, VW, AUX_NT>(o1, oc[q], pz[q]);
         } else {
-          stv<T, VW>(Yv, o, yv);
-          stv<T, VW>(O0, o, rnew);
-          stv<T, VW>(O1, o, pz[q]);
+          bst<T, VW, AUX_OUT>(yo, oc[q], yv);
+          bst<T, VW, AUX_OUT>(o0, oc[q], rnew);
+          bst<T, VW, AUX_OUT>(o1, oc[q], pz[q]);
         }
       }
     }
-    // rotate the pipeline
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-#pragma unroll
-      for (int v = 0; v < VW; ++v) {
-        pm[q][v] = pz[q][v];
-        pz[q][v] = p1[q][v];
-        rz[q][v] = r1[q][v];
-        r1[q][v] = c2r[q][v];
-        if constexpr (UPD) yz[q][v] = y1[q][v];
-      }
-      comb(c2r[q], c2p[q], p1[q]);
-      comb(s1r[q], s1p[q], smz[q]);
-      comb(t1r[q], t1p[q], spz[q]);
-      dz[q] = d1[q];
-    }
+  };
+
+  // the march, unrolled by two (a straight-line body, so that the two load
+  // sets keep fixed registers across the loop edge), then an odd last plane
+  MarchLoads<T, VW, Q> LA, LB;
+  issue(z0 + 1, LA);      // z0 < z1 always (march chunks are never empty)
+  uint32_t z = z0;
+  for (; z + 1 < z1; z += 2) {
+    issue(z + 2, LB);
+    compute(z, lds);
+    rotate(LA);
+    issue(z + 3, LA);
+    compute(z + 1, lds + Q * OPE_WG * VW);
+    rotate(LB);
   }
+  if (z < z1) compute(z, lds);
   if constexpr (MODE != SW_APPLY) {
     // per-column sums over the work-group's slots -> one partial row per (line, segment, march chunk)
 #pragma unroll
@@ -332,11 +458,44 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
       const uint64_t row = ((uint64_t)line * ms.nxs + xs) * ms.mc + mchunk_id;
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
-        const uint64_t col = coff + v;
+        const uint64_t col = (uint64_t)colv * VW + v;
         if (col < N) part[row * N + col] = s[v];
       }
     }
   }
+}
+
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO>
+__global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, const T* __restrict__ F1,
+                                                  T* __restrict__ O0, T* __restrict__ O1,
+                                                  T* __restrict__ Yv, const double* __restrict__ alpha,
+                                                  const double* __restrict__ beta, const int32_t* __restrict__ active,
+                                                  const T* __restrict__ diag, OpeGrid g, MarchShape ms,
+                                                  uint32_t N, uint32_t NV, double* __restrict__ part,
+                                                  OpeScalars* __restrict__ sc) {
+  march_body<T, VW, Q, MODE, FIRST, HALO>(xcd_remap(blockIdx.x, gridDim.x), F0, F1, O0, O1, Yv, alpha, beta, active,
+                                          diag, g, ms, N, NV, part, sc);
+}
+
+// Batched form: one launch for the CG sweeps of many problems of the same
+// storage type and shape class.  The XCD-remapped work-group index is a work
+// item (problem, tile): problem j owns items [wg_begin, wg_begin + wg_count),
+// so each XCD streams a contiguous range of one problem's lines.
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO>
+__global__ __launch_bounds__(OPE_WG) void k_march_batched(const MarchJob* __restrict__ jobs, uint32_t njobs) {
+  const uint32_t gt = xcd_remap(blockIdx.x, gridDim.x);
+  uint32_t lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (jobs[mid].wg_begin <= gt) lo = mid;
+    else hi = mid;
+  }
+  const MarchJob& jb = jobs[lo];
+  const OpeGrid g = jb.g;
+  const MarchShape ms = jb.ms;
+  march_body<T, VW, Q, MODE, FIRST, HALO>(gt - jb.wg_begin, (const T*)jb.F0, (const T*)jb.F1, (T*)jb.O0, (T*)jb.O1,
+                                    (T*)jb.Yv, jb.alpha, jb.beta, jb.active, (const T*)jb.diag, g, ms, jb.N, jb.NV,
+                                    jb.part, jb.sc);
 }
 
 // r0 = U - H Y0 (HY given) or r0 = U with y zeroed (HY null); one partial row of
@@ -497,6 +656,39 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_few(const double* __restrict_
   else cg_finalise<MODE>(col, tot, alpha, beta, rho, target, active, sc);
 }
 
+// Batched one-work-group column reductions: work-group j reduces problem j.
+template <int MODE>
+__global__ __launch_bounds__(OPE_WG) void k_reduce_batched(const ReduceJob* __restrict__ jobs) {
+  __shared__ double red[OPE_WG];
+  const ReduceJob& jb = jobs[blockIdx.x];
+  const uint32_t nrows = jb.nrows, ncols = jb.ncols;
+  const double* part = jb.part;
+  const uint32_t G = OPE_WG / ncols;
+  const uint32_t col = threadIdx.x % ncols, gi = threadIdx.x / ncols;
+  double a = 0.0;
+  if (gi < G) {
+    double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    uint32_t w = gi;
+    for (; w + 7 * G < nrows; w += 8 * G) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] += part[(uint64_t)(w + u * G) * ncols + col];
+    }
+    for (; w < nrows; w += G) q[0] += part[(uint64_t)w * ncols + col];
+    a = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  if (gi != 0) return;
+  double tot = 0.0;
+  for (uint32_t k = 0; k < G; ++k) tot += red[k * ncols + col];
+  cg_finalise<MODE>(col, tot, jb.alpha, jb.beta, jb.rho, jb.target, jb.active, jb.sc);
+}
+
+__global__ __launch_bounds__(OPE_WG) void k_gather_flags(const ReduceJob* __restrict__ jobs) {
+  const ReduceJob& jb = jobs[blockIdx.x];
+  for (uint32_t j = threadIdx.x; j < jb.ncols; j += OPE_WG) jb.flags_out[j] = jb.active[j];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -508,8 +700,12 @@ static void launch_march_t(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T
   const uint32_t N = (uint32_t)c->N, NV = N / VW;
   const MarchShape& ms = c->ms;
   const uint32_t grid = ms.lines * ms.nxs * ms.cc * ms.mc;
-  hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0, O1, Yv,
-                     c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
+  if (ms.nxs > 1)
+    hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, true>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0, O1,
+                       Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
+  else
+    hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, false>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0,
+                       O1, Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
 }
 
 template <typename T, int VW, int MODE, bool FIRST>
@@ -588,10 +784,16 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
     ms.cs = 0.0;
     ms.has_side = 0;
   }
-  // automatic: one march chunk when that already gives 512 work-groups (the
-  // lock-step march keeps side rows in L2), more chunks for smaller grids
+  // automatic: at least 512 work-groups, and enough march chunks that about
+  // 2.5 MB of plane data is in flight (a work-group with short rows moves
+  // little per plane); one chunk when that already holds (the lock-step march
+  // keeps side rows in L2)
   const uint32_t base = ms.lines * ms.nxs * ms.cc;
-  uint32_t mc = mc_override > 0 ? (uint32_t)mc_override : (512u + base - 1) / base;
+  const double plane_bytes = (double)ms.xseg * ms.ncv * c->vw * (c->prec == OPE_FP64 ? 8.0 : 4.0);
+  uint32_t mc_auto = (512u + base - 1) / base;
+  const uint32_t mc_bytes = (uint32_t)(2.5 * 1048576.0 / ((double)base * plane_bytes) + 0.5);
+  if (mc_bytes > mc_auto) mc_auto = mc_bytes;
+  uint32_t mc = mc_override > 0 ? (uint32_t)mc_override : mc_auto;
   if (mc < 1) mc = 1;
   if (mc > ms.mlen) mc = ms.mlen;
   ms.mchunk = (ms.mlen + mc - 1) / mc;
@@ -672,5 +874,67 @@ hipError_t launch_resid0(ope_ctx* c, const double* U, const double* HY, double* 
     hipLaunchKernelGGL((k_resid0<2>), grid, blk, 0, c->stream, U, HY, R, y, n, N, NV, pts, c->part);
   else
     hipLaunchKernelGGL((k_resid0<1>), grid, blk, 0, c->stream, U, HY, R, y, n, N, NV, pts, c->part);
+  return hipGetLastError();
+}
+
+bool reduce_few_fits(const ope_ctx* c) {
+  return c->N <= 128 && march_rows(c) * c->N <= ((int64_t)1 << 17);
+}
+
+template <typename T, int VW, int Q, int MODE, bool FIRST>
+static void launch_mb(hipStream_t s, int halo, const MarchJob* jobs, uint32_t njobs, uint32_t total) {
+  if (halo)
+    hipLaunchKernelGGL((k_march_batched<T, VW, Q, MODE, FIRST, true>), dim3(total), dim3(OPE_WG), 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL((k_march_batched<T, VW, Q, MODE, FIRST, false>), dim3(total), dim3(OPE_WG), 0, s, jobs, njobs);
+}
+
+template <typename T, int VW, int MODE, bool FIRST>
+static void launch_mb_q(hipStream_t s, int q, int halo, const MarchJob* jobs, uint32_t njobs, uint32_t total) {
+  switch (q) {
+    case 1: launch_mb<T, VW, 1, MODE, FIRST>(s, halo, jobs, njobs, total); break;
+    case 2: launch_mb<T, VW, 2, MODE, FIRST>(s, halo, jobs, njobs, total); break;
+    default: launch_mb<T, VW, 4, MODE, FIRST>(s, halo, jobs, njobs, total); break;
+  }
+}
+
+template <int MODE, bool FIRST>
+static void launch_mb_t(hipStream_t s, int prec, int vw, int q, int halo, const MarchJob* jobs, uint32_t njobs,
+                        uint32_t total) {
+  if (prec == OPE_FP64) {
+    if (vw == 2) launch_mb_q<double, 2, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+    else launch_mb_q<double, 1, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+  } else {
+    if (vw == 4) launch_mb_q<float, 4, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+    else if (vw == 2) launch_mb_q<float, 2, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+    else launch_mb_q<float, 1, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+  }
+}
+
+hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int mode, int first,
+                                const MarchJob* jobs, uint32_t njobs, uint32_t total_wgs) {
+  if (njobs == 0 || total_wgs == 0) return hipSuccess;
+  if (mode == SW_PAP) {
+    if (first) launch_mb_t<SW_PAP, true>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
+    else launch_mb_t<SW_PAP, false>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
+  } else {
+    if (first) launch_mb_t<SW_UPDATE, true>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
+    else launch_mb_t<SW_UPDATE, false>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(hipStream_t s, int mode, const ReduceJob* jobs, uint32_t njobs) {
+  if (njobs == 0) return hipSuccess;
+  if (mode == RED_CG_ALPHA)
+    hipLaunchKernelGGL((k_reduce_batched<RED_CG_ALPHA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs);
+  else
+    hipLaunchKernelGGL((k_reduce_batched<RED_CG_BETA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_flags(hipStream_t s, const ReduceJob* jobs, uint32_t njobs) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_flags, dim3(njobs), dim3(OPE_WG), 0, s, jobs);
   return hipGetLastError();
 }

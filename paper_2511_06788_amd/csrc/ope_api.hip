@@ -37,6 +37,19 @@ struct ope_batch {
   std::vector<ope_ctx*> ctx;          // one context per problem
   std::vector<hipStream_t> streams;   // its stream
   std::vector<hipEvent_t> done;
+  // shared CG launches: one stream, job tables (device + pinned staging), flags
+  int shared;                         // 1: one launch per CG phase and class of problems
+  hipStream_t cg_stream;
+  hipEvent_t cg_ev;
+  MarchJob* d_mjobs;
+  MarchJob* h_mjobs;
+  ReduceJob* d_rjobs;
+  ReduceJob* h_rjobs;
+  int32_t* d_flags;
+  int32_t* h_flags;
+  std::vector<uint32_t> flag_off;     // problem i's flags in h_flags
+  std::vector<hipStream_t> cls_streams;  // one per class of problems in a shared launch
+  std::vector<hipEvent_t> cls_events;
 };
 
 namespace {
@@ -483,6 +496,140 @@ struct BatchState {
   std::vector<int32_t> it;
 };
 
+// A problem takes part in the shared launches when its column sums fit one
+// work-group's reduction (the same fixed-order sum its own steps use, so that
+// its shared-launch iterates equal those of its own launches bit for bit); its
+// work items are the tiles of its own sweep shape.
+bool shared_fits(const ope_ctx* c) { return reduce_few_fits(c); }
+
+// One chunk (check_every iterations) of Step 1's CG for the problems in
+// `members`, with one launch per sweep and class of problems and one launch
+// per column reduction, then the gather of their convergence flags into
+// h_flags (synchronised).  The problems' pre-phases must have completed.
+hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t* it) {
+  struct Cls {
+    int prec, vw, q, halo;
+    std::vector<int> idx;
+  };
+  std::vector<Cls> cls;
+  for (int i : members) {
+    const ope_ctx* c = b->ctx[i];
+    const int halo = c->ms.nxs > 1 ? 1 : 0;
+    bool found = false;
+    for (auto& k : cls)
+      if (k.prec == c->prec && k.vw == c->vw && k.q == (int)c->ms.q && k.halo == halo) {
+        k.idx.push_back(i);
+        found = true;
+        break;
+      }
+    if (!found) cls.push_back(Cls{c->prec, c->vw, (int)c->ms.q, halo, {i}});
+  }
+  // job tables: per class, 4 variants (sweep A / B, even / odd iteration)
+  const uint32_t M = (uint32_t)members.size();
+  std::vector<uint32_t> cls_off(cls.size()), cls_total(cls.size());
+  uint32_t off = 0;
+  for (size_t k = 0; k < cls.size(); ++k) {
+    cls_off[k] = off;
+    uint32_t wg = 0;
+    for (int v = 0; v < 4; ++v) {
+      wg = 0;
+      for (size_t m = 0; m < cls[k].idx.size(); ++m) {
+        ope_ctx* c = b->ctx[cls[k].idx[m]];
+        const int par = v & 1, upd = v >> 1;
+        MarchJob& jb = b->h_mjobs[off + v * cls[k].idx.size() + m];
+        jb.F0 = c->Rb[par];
+        jb.F1 = par ? c->Pb : c->HU;
+        jb.O0 = upd ? c->Rb[par ^ 1] : nullptr;
+        jb.O1 = upd ? (par ? c->HU : c->Pb) : nullptr;
+        jb.Yv = upd ? c->Y : nullptr;
+        jb.alpha = c->alpha;
+        jb.beta = c->beta;
+        jb.active = c->active;
+        jb.diag = c->prec == OPE_FP64 ? (const void*)c->diag : (const void*)c->diag32;
+        jb.g = c->g;
+        jb.ms = c->ms;
+        jb.N = (uint32_t)c->N;
+        jb.NV = (uint32_t)(c->N / c->vw);
+        jb.part = c->part;
+        jb.sc = c->sc;
+        jb.wg_begin = wg;
+        jb.wg_count = jb.ms.lines * jb.ms.nxs * jb.ms.cc * jb.ms.mc;
+        wg += jb.wg_count;
+      }
+    }
+    cls_total[k] = wg;
+    off += 4 * (uint32_t)cls[k].idx.size();
+  }
+  uint32_t foff = 0;
+  for (uint32_t m = 0; m < M; ++m) {
+    ope_ctx* c = b->ctx[members[m]];
+    ReduceJob& rj = b->h_rjobs[m];
+    rj.part = c->part;
+    rj.nrows = (uint32_t)march_rows(c);
+    rj.ncols = (uint32_t)c->N;
+    rj.alpha = c->alpha;
+    rj.beta = c->beta;
+    rj.rho = c->rho;
+    rj.target = c->target;
+    rj.active = c->active;
+    rj.sc = c->sc;
+    rj.flags_out = b->d_flags + foff;
+    b->flag_off[members[m]] = foff;
+    foff += (uint32_t)c->N;
+  }
+  hipStream_t s = b->cg_stream;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(b->d_mjobs, b->h_mjobs, sizeof(MarchJob) * off, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(b->d_rjobs, b->h_rjobs, sizeof(ReduceJob) * M, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  // classes run their sweeps on their own streams (forked from and joined
+  // back into the CG stream around every sweep), so they overlap
+  while (b->cls_streams.size() < cls.size()) {
+    hipStream_t cs;
+    hipEvent_t ce;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ce, hipEventDisableTiming)) != hipSuccess) return e;
+    b->cls_streams.push_back(cs);
+    b->cls_events.push_back(ce);
+  }
+  auto sweep = [&](int mode, int par, int first) -> hipError_t {
+    hipError_t er;
+    if (cls.size() == 1) {
+      const uint32_t nc = (uint32_t)cls[0].idx.size();
+      const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
+      return launch_march_batched(s, cls[0].prec, cls[0].vw, cls[0].q, cls[0].halo, mode, first,
+                                  b->d_mjobs + cls_off[0] + v * nc, nc, cls_total[0]);
+    }
+    if ((er = hipEventRecord(b->cg_ev, s)) != hipSuccess) return er;
+    for (size_t c = 0; c < cls.size(); ++c) {
+      hipStream_t cs = b->cls_streams[c];
+      const uint32_t nc = (uint32_t)cls[c].idx.size();
+      const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
+      if ((er = hipStreamWaitEvent(cs, b->cg_ev, 0)) != hipSuccess) return er;
+      if ((er = launch_march_batched(cs, cls[c].prec, cls[c].vw, cls[c].q, cls[c].halo, mode, first,
+                                     b->d_mjobs + cls_off[c] + v * nc, nc, cls_total[c])) != hipSuccess)
+        return er;
+      if ((er = hipEventRecord(b->cls_events[c], cs)) != hipSuccess) return er;
+      if ((er = hipStreamWaitEvent(s, b->cls_events[c], 0)) != hipSuccess) return er;
+    }
+    return hipSuccess;
+  };
+  const int K = b->ctx[members[0]]->check_every;
+  for (int k = 0; k < K; ++k, ++*it) {
+    const int par = *it & 1, first = *it == 0;
+    if ((e = sweep(BATCH_SW_PAP, par, first)) != hipSuccess) return e;
+    if ((e = launch_reduce_batched(s, RED_CG_ALPHA, b->d_rjobs, M)) != hipSuccess) return e;
+    if ((e = sweep(BATCH_SW_UPDATE, par, first)) != hipSuccess) return e;
+    if ((e = launch_reduce_batched(s, RED_CG_BETA, b->d_rjobs, M)) != hipSuccess) return e;
+  }
+  if ((e = launch_gather_flags(s, b->d_rjobs, M)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int32_t) * foff, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  if ((e = hipEventRecord(b->cg_ev, s)) != hipSuccess) return e;
+  return hipEventSynchronize(b->cg_ev);
+}
+
 // One round over the problems with run[i] set: the pre-phase of every problem
 // (residual, Lam^{-1}, warm start), one host synchronisation, then rounds of
 // CG chunks in which each problem leaves as soon as all its columns converged,
@@ -526,21 +673,50 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
       go[i] = 0;
     }
   }
-  std::vector<char> pending(go);
+  // Step 1: problems whose column sums fit one work-group share one launch per
+  // CG phase and class (storage type, vector width, passes per plane, split x
+  // lines) on the batch's CG stream; the others run their own chunks on their
+  // own streams.
+  std::vector<char> pending(go), shared(P, 0);
+  for (int i = 0; i < P; ++i) shared[i] = go[i] && b->shared && shared_fits(b->ctx[i]);
+  int32_t it_shared = 0;
   for (;;) {
-    bool any = false;
+    bool any = false, any_shared = false;
     for (int i = 0; i < P; ++i) {
       if (!pending[i]) continue;
       any = true;
+      if (shared[i]) {
+        any_shared = true;
+        continue;
+      }
       if (cg_chunk(b->ctx[i], &bs.it[i], b->ctx[i]->max_iter, 0) != hipSuccess) {
         bs.st[i] = OPE_EHIP;
         pending[i] = go[i] = 0;
       }
     }
     if (!any) break;
+    if (any_shared) {
+      std::vector<int> members;
+      for (int i = 0; i < P; ++i)
+        if (pending[i] && shared[i]) members.push_back(i);
+      HIPCHK(batch_cg_chunk(b, members, &it_shared));
+    }
     for (int i = 0; i < P; ++i) {
       if (!pending[i]) continue;
       ope_ctx* c = b->ctx[i];
+      if (shared[i]) {
+        bs.it[i] = it_shared;
+        const int32_t* f = b->h_flags + b->flag_off[i];
+        bool done = true;
+        for (int64_t j = 0; j < c->N; ++j) done &= f[j] == 0;
+        if (done) {
+          bs.cgdone[i] = 1;
+          pending[i] = 0;
+        } else if (it_shared >= c->max_iter) {
+          pending[i] = 0;
+        }
+        continue;
+      }
       HIPCHK(hipEventSynchronize(c->chunk_ev[0]));
       if (cg_all_done(c, 0)) {
         bs.cgdone[i] = 1;
@@ -624,6 +800,14 @@ ProfScope::~ProfScope() {
   c->prof_used += 2;
 }
 
+// Default sweep flags: chunk-major; non-temporal stores when a row is split
+// over several column chunks (more than 32 16-byte vectors).  Measured: they
+// help there and cost where one work-group takes whole rows.
+static int default_sweep_flags(const ope_ctx* c) {
+  const int64_t NV = c->N / c->vw;
+  return OPE_SWEEP_CHUNK_MAJOR | (NV > 32 ? OPE_SWEEP_NONTEMPORAL : 0);
+}
+
 extern "C" {
 
 const char* ope_status_string(ope_status s) {
@@ -655,6 +839,9 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (!(op->kinetic > 0.0)) return OPE_EINVAL;
   if (N < 1 || N > n) return OPE_EINVAL;
   if (N > OPE_MAX_N_SMALL) return OPE_EUNSUPPORTED;
+  // the stencil sweeps address one plane of the march axis with 32-bit offsets
+  const int64_t plane_pts = op->dim == 3 ? op->m[0] * op->m[1] : op->m[0];
+  if (plane_pts * N * (int64_t)sizeof(double) >= ((int64_t)1 << 31)) return OPE_EUNSUPPORTED;
 
   ope_ctx* c = new (std::nothrow) ope_ctx();
   if (!c) return OPE_ENOMEM;
@@ -699,7 +886,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (pts < pp) pts = pp;
   c->stream_pts = (int)pts;
   c->stream_wgs = (int)((n + pts - 1) / pts);
-  march_shape(c, 0, 0, 1, 0, 0);
+  march_shape(c, 0, 0, 1, (default_sweep_flags(c) & OPE_SWEEP_NONTEMPORAL) ? 1 : 0, 0);
 
   const int64_t blk = n * N;
   const int64_t gtiles = ((N + 63) / 64) * ((N + 63) / 64);
@@ -1108,11 +1295,32 @@ ope_status ope_batch_create(ope_batch** out, const ope_op_desc* ops, const int64
     }
     st = ope_create(&b->ctx[i], &ops[i], N[i], precision, b->streams[i]);
   }
+  b->shared = 1;
+  b->flag_off.assign(count, 0);
+  if (st == OPE_OK) {
+    int64_t nflags = 0;
+    for (int32_t i = 0; i < count; ++i) nflags += N[i];
+    bool ok = hipStreamCreateWithFlags(&b->cg_stream, hipStreamNonBlocking) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&b->cg_ev, hipEventDisableTiming) == hipSuccess;
+    ok &= hipMalloc((void**)&b->d_mjobs, sizeof(MarchJob) * 4 * (size_t)count) == hipSuccess;
+    ok &= hipHostMalloc((void**)&b->h_mjobs, sizeof(MarchJob) * 4 * (size_t)count, hipHostMallocDefault) == hipSuccess;
+    ok &= hipMalloc((void**)&b->d_rjobs, sizeof(ReduceJob) * (size_t)count) == hipSuccess;
+    ok &= hipHostMalloc((void**)&b->h_rjobs, sizeof(ReduceJob) * (size_t)count, hipHostMallocDefault) == hipSuccess;
+    ok &= hipMalloc((void**)&b->d_flags, sizeof(int32_t) * (size_t)nflags) == hipSuccess;
+    ok &= hipHostMalloc((void**)&b->h_flags, sizeof(int32_t) * (size_t)nflags, hipHostMallocDefault) == hipSuccess;
+    if (!ok) st = OPE_ENOMEM;
+  }
   if (st != OPE_OK) {
     ope_batch_destroy(b);
     return st;
   }
   *out = b;
+  return OPE_OK;
+}
+
+ope_status ope_batch_set_shared(ope_batch* b, int32_t shared) {
+  if (!b || (shared != 0 && shared != 1)) return OPE_EINVAL;
+  b->shared = shared;
   return OPE_OK;
 }
 
@@ -1124,6 +1332,16 @@ ope_status ope_batch_destroy(ope_batch* b) {
     if (b->done[i]) (void)hipEventDestroy(b->done[i]);
   }
   if (b->start) (void)hipEventDestroy(b->start);
+  if (b->cg_ev) (void)hipEventDestroy(b->cg_ev);
+  for (hipStream_t cs : b->cls_streams) (void)hipStreamDestroy(cs);
+  for (hipEvent_t ce : b->cls_events) (void)hipEventDestroy(ce);
+  if (b->cg_stream) (void)hipStreamDestroy(b->cg_stream);
+  if (b->d_mjobs) (void)hipFree(b->d_mjobs);
+  if (b->d_rjobs) (void)hipFree(b->d_rjobs);
+  if (b->d_flags) (void)hipFree(b->d_flags);
+  if (b->h_mjobs) (void)hipHostFree(b->h_mjobs);
+  if (b->h_rjobs) (void)hipHostFree(b->h_rjobs);
+  if (b->h_flags) (void)hipHostFree(b->h_flags);
   delete b;
   return OPE_OK;
 }
@@ -1244,7 +1462,7 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
     auto f = best.find(k);
     if (f == best.end()) {
       if (c->prec != OPE_FP64) {
-        best[k] = Shape{2, 0, OPE_SWEEP_CHUNK_MAJOR};   // FP32 contexts keep the default shape
+        best[k] = Shape{2, 0, default_sweep_flags(c)};   // FP32 contexts keep the default shape
       } else {
         void* X = nullptr;
         const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
@@ -1254,14 +1472,15 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
         }
         // any non-zero right-hand side (the sweeps' cost does not depend on it)
         (void)hipMemsetAsync(X, 0x3F, bytes, c->stream);
-        Shape pick{2, 0, OPE_SWEEP_CHUNK_MAJOR};
+        Shape pick{2, 0, default_sweep_flags(c)};
         double tbest = 1e30;
         const int narrow_opts = NV <= 32 ? 2 : 1;
-        for (int q : {1, 2, 4})
+        for (int q : {1, 2})
           for (int cm : {0, OPE_SWEEP_CHUNK_MAJOR})
+            for (int nt : {0, OPE_SWEEP_NONTEMPORAL})
             for (int nr = 0; nr < narrow_opts; ++nr)
               for (int mcm : {0, 2}) {
-                const int flags = cm | (nr ? OPE_SWEEP_NARROW : 0);
+                const int flags = cm | nt | (nr ? OPE_SWEEP_NARROW : 0);
                 if (ope_set_sweep_shape(c, q, 0, flags) != OPE_OK) continue;
                 int mc = 0;
                 if (mcm == 2) {
@@ -1282,7 +1501,7 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
     }
     if (ope_set_sweep_shape(c, f->second.q, f->second.mc, f->second.flags) != OPE_OK) {
       // a shape tuned on a bucket neighbour may not fit this problem's partial buffer
-      (void)ope_set_sweep_shape(c, 2, 0, OPE_SWEEP_CHUNK_MAJOR);
+      (void)ope_set_sweep_shape(c, 2, 0, default_sweep_flags(c));
     }
   }
   (void)hipEventDestroy(e0);

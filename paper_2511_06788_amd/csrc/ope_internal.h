@@ -227,6 +227,44 @@ hipError_t launch_renorm_matrix(ope_ctx* c, const double* C, float* Z32);
 hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
 
+// Batched CG sweeps (k_stencil.hip): one work item range per problem.
+struct MarchJob {
+  const void* F0;
+  const void* F1;
+  void* O0;
+  void* O1;
+  void* Yv;
+  double* alpha;
+  double* beta;
+  int32_t* active;
+  const void* diag;
+  OpeGrid g;
+  MarchShape ms;
+  uint32_t N, NV;
+  double* part;
+  OpeScalars* sc;
+  uint32_t wg_begin, wg_count;
+};
+// Batched column reductions (one work-group per problem; ncols <= 128) and the
+// gather of every problem's convergence flags into one array.
+struct ReduceJob {
+  const double* part;
+  uint32_t nrows, ncols;
+  double *alpha, *beta, *rho;
+  const double* target;
+  int32_t* active;
+  OpeScalars* sc;
+  int32_t* flags_out;      // gather destination (N values)
+};
+enum { BATCH_SW_PAP = 1, BATCH_SW_UPDATE = 2 };   // sweep A, sweep B
+// halo: the class's x lines are split into several segments (nxs > 1)
+hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int mode, int first,
+                                const MarchJob* jobs, uint32_t njobs, uint32_t total_wgs);
+hipError_t launch_reduce_batched(hipStream_t s, int mode, const ReduceJob* jobs, uint32_t njobs);
+hipError_t launch_gather_flags(hipStream_t s, const ReduceJob* jobs, uint32_t njobs);
+// whether a context's CG column sums fit the one-work-group reduction
+bool reduce_few_fits(const ope_ctx* c);
+
 // learned form (k_net.hip): column sums of squares of point-major FP64 rows
 // (B <= 256) into out, and E = U - P(R) for the context's N columns
 hipError_t launch_colsq(ope_ctx* c, const double* R, int64_t ld, int64_t B, double* out);

@@ -116,6 +116,7 @@ SIGNATURES = {
     "ope_batch_step": ([_P, ctypes.POINTER(_P), _D, ctypes.POINTER(ope_step_info)], _I32),
     "ope_batch_solve": ([_P, ctypes.POINTER(_P), _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
     "ope_batch_autotune": ([_P, ctypes.POINTER(_I32)], _I32),
+    "ope_batch_set_shared": ([_P, _I32], _I32),
     "ope_get_sweep_shape": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _I32),
     "ope_profile_begin": ([_P, _I32], _I32),
     "ope_convert": ([_P, _P, _P, _I64, _I32], _I32),
@@ -493,6 +494,9 @@ class Batch:
         _check(lib().ope_batch_solve(self.handle, self._ptrs(Us), tau, res_tol, max_steps, infos), "ope_batch_solve",
                allow=(OPE_ECG_MAXIT,))
         return list(infos)
+
+    def set_shared(self, shared: bool) -> None:
+        _check(lib().ope_batch_set_shared(self.handle, 1 if shared else 0), "ope_batch_set_shared")
 
     def autotune(self) -> int:
         k = _I32(0)

@@ -1,7 +1,8 @@
 """GPU tests of the batched form (many independent problems stepped together).
 
 * Each problem's batched steps equal ope_step on its own context bit for bit
-  (FP64 and mixed, ragged grids and block widths, 2D and 3D), with the same
+  (FP64 and mixed, ragged grids and block widths, 2D and 3D, with shared CG
+  launches over all problems and with per-problem launches), with the same
   diagnostics; ope_batch_solve equals per-problem ope_solve.
 * After the autotuner has changed the sweep shapes, converged batched solves
   still give the dense-eigensolver Ritz values to 1e-10.
@@ -30,14 +31,16 @@ def _ragged():
             W.wells_3d(m=16, N=34, seed=3), W.wells_3d(m=11, N=3, seed=4)]
 
 
+@pytest.mark.parametrize("shared", [True, False])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_steps_equal_single_steps(prec):
+def test_batch_steps_equal_single_steps(prec, shared):
     from paper_2511_06788_amd import ope
     probs = _ragged()
-    say(f"batch steps vs single prec={prec}")
+    say(f"batch steps vs single prec={prec} shared={shared}")
     # the batch takes one tau for every problem
     tau = 0.5
     with ope.Batch(probs, precision=prec) as b:
+        b.set_shared(shared)
         Ub = [_dev(p.U0, prec) for p in probs]
         infos_b = [b.step(Ub, tau) for _ in range(3)]
         Ub = [to_host(U) for U in Ub]

@@ -271,3 +271,40 @@ def test_training_lowers_the_oracle_loss():
     assert np.all(np.isfinite(losses))
     assert l1 <= 0.5 * l0, (l0, l1, losses[:3], losses[-3:])
     assert l1 < 1.0     # better than the zero network
+
+
+def test_full_size_network_and_learned_step():
+    """64^3, N = 128 with the shipped weights: the network on two sampled
+    residual columns equals the oracle network (BF16-rounded weights); one
+    learned step without the judge keeps orthogonality and changes U."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=64, N=128, seed=0)
+    op = O.Operator(p.grid.m, p.grid.h, p.V)
+    w = ope.load_net_weights()
+    Ws = [bf16_round(Wl) for Wl in ope.net_weights_to_layers(w.astype(np.float64))]
+    shape = (64, 64, 64)
+    say("full-size network and learned step")
+    with _ctx(p) as ctx, ope.Net(ctx, p.N, ope.net_layers_to_weights(Ws)) as net:
+        U = to_dev(p.U0)
+        HU = empty_dev(p.grid.n, p.N)
+        ope.ope_apply_h(ctx.handle, U, HU)
+        Hh = to_host(HU)
+        R = Hh - p.U0 @ (p.U0.T @ Hh)
+        cols = [3, 77]
+        X = np.stack([bf16_round(R[:, j] / np.linalg.norm(R[:, j])) for j in cols])
+        v2 = _empty32(p.grid.n)
+        ope.ope_net_potential(net.handle, v2)
+        v2h = bf16_round(to_host(v2))
+        F = _empty32(2, p.grid.n)
+        ope.ope_net_forward(net.handle, _dev32(X), _dev32(v2h), 2, F)
+        F = to_host(F).astype(np.float64)
+        ope.ope_set_preconditioner(ctx.handle, net.handle, judge=False)
+        info, acc = ope.ope_step_learned(ctx.handle, U, 45.0)
+        res, _, drift = ope.ope_residual(ctx.handle, U, p.N, want_ritz=False)
+        U1 = to_host(U)
+    for k in range(2):
+        x = np.stack([X[k].reshape(shape), v2h.reshape(shape)], axis=-1)
+        ref = NN.forward(x, Ws)["f"].reshape(-1)
+        assert np.linalg.norm(F[k] - ref) <= 1.5e-2 * np.linalg.norm(ref), k
+    assert acc and drift <= 1e-12
+    assert np.max(np.abs(U1 - p.U0)) > 1e-6

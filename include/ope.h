@@ -297,19 +297,20 @@ ope_status ope_batch_step(ope_batch* batch, void* const* U, double tau, ope_step
  * test and no learned steps).  info: count entries, nullable. */
 ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double res_tol, int32_t max_steps,
                            ope_solve_info* info);
-/* shared = 1 (default): Step 1's CG sweeps and column reductions of all
+/* shared = 1: Step 1's CG sweeps and column reductions of all
  * problems whose column sums fit one work-group (at most 128 columns) run as
  * one launch per phase and class of problems (storage type, vector width,
- * passes per plane, split x lines) on a batch stream, each launch's
+ * passes per plane, split x lines, two-line tiles) on a batch stream, each launch's
  * work-groups spread over (problem, tile) work items of every problem's own
  * sweep shape; same kernels and summation order as the per-problem launches,
- * so the results are identical.  shared = 0: every problem's CG runs on its
- * own stream. */
+ * so the results are identical.  shared = 0 (default): every problem's CG
+ * runs on its own stream (measured: as fast as shared launches after the
+ * autotuner, faster before it). */
 ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
 /* Autotuner: for every bucket of problems (grid edges and vector-column count
  * in steps of 8) time short CG runs of the first problem over the sweep shapes
- * (passes per plane 1/2, work-group order, non-temporal stores, column
- * chunking, march chunks)
+ * (passes per plane 1/2 or the two-line tile, work-group order, non-temporal
+ * stores, column chunking, march chunks)
  * and give every problem of the bucket the fastest; FP32 contexts keep the
  * default.  *tuned (nullable) = number of buckets.  Synchronises; uses a
  * temporary n x N block per tuned bucket. */
@@ -327,18 +328,23 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * plane mean fewer x segments but more registers), and the march axis is cut
  * into march_chunks ranges (0 = automatic: at least 512 work-groups).  The
  * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR, plus
- * OPE_SWEEP_NONTEMPORAL when a row holds more than 32 16-byte vectors.
+ * OPE_SWEEP_LINES on 3D grids and OPE_SWEEP_NONTEMPORAL when five n x N
+ * blocks of the storage type exceed 256 MiB.
  * q_max = 0 lets the library choose.  flags: OPE_SWEEP_CHUNK_MAJOR puts the
  * work-groups of one column chunk next to each other (so one XCD streams one
  * chunk of every side line) instead of those of one side line;
  * OPE_SWEEP_NONTEMPORAL writes the swept outputs with non-temporal stores;
  * OPE_SWEEP_NARROW keeps 8-vector column chunks for rows of at most 32
- * vector columns (which by default a work-group takes whole).
+ * vector columns (which by default a work-group takes whole);
+ * OPE_SWEEP_LINES (3D grids) gives a work-group two adjacent side lines, one
+ * per pass over an x segment of 256/8 points (q is then 2), so that each line
+ * takes its inner side neighbour from the other line's registers.
  * Results do not depend on the shape beyond the summation order of the CG dot
  * products.  Synchronises; on OPE_EINVAL the previous shape stays. */
 #define OPE_SWEEP_CHUNK_MAJOR 1
 #define OPE_SWEEP_NONTEMPORAL 2
 #define OPE_SWEEP_NARROW 4
+#define OPE_SWEEP_LINES 8
 ope_status ope_set_sweep_shape(ope_ctx* ctx, int32_t q_max, int32_t march_chunks, int32_t flags);
 
 /* The shape in use (outputs nullable, host). */

@@ -14,11 +14,12 @@
 //
 // Step 1 solves the N source problems H y_j = u_j independently (one CG per
 // column).  One CG iteration is two sweeps:
-//   sweep A (cg_pap):    p = r + beta p_old (formed on the fly), sigma_j = p_j^T H p_j
-//   sweep B (cg_update): p = r + beta p_old, y += alpha p, r' = r - alpha H p,
-//                        rho'_j = r'_j^T r'_j, and p is written out
-// so an iteration moves 8 block-passes (A reads r, p_old; B reads r, p_old, y
-// and writes r', p, y) instead of materialising q = H p.  The per-column
+//   sweep A (cg_pap):    p = r + beta p_old (formed on the fly, with its
+//                        neighbours), sigma_j = p_j^T H p_j, and p is written out
+//   sweep B (cg_update): y += alpha p, r' = r - alpha H p, rho'_j = r'_j^T r'_j
+// so an iteration moves 8 block-passes (A reads r, p_old and writes p; B reads
+// p, r, y and writes r', y) instead of materialising q = H p.  B recomputes
+// H p from p, so its neighbour rows come from one array, not two.  The per-column
 // scalars alpha, beta, rho and the convergence flags live on the device and
 // are produced by the fixed-order reductions at the end of this file.
 #include "ope_internal.h"
@@ -106,10 +107,12 @@ __device__ __forceinline__ void wg_colsum(double* red, const double (&acc)[VW], 
 // in issue order, so a load has two plane steps to arrive; with every access
 // unconditional the compiler's wait before taking a set in covers exactly the
 // accesses issued before it.
-// MODE selects what is done with (H p) at each point:
-//   SW_APPLY   out = H x
-//   SW_PAP     sigma_j += p_j (H p)_j,          p = r + beta p_old
-//   SW_UPDATE  y += alpha p, r' = r - alpha H p, p written, rho'_j += r'_j^2
+// MODE selects the field and what is done with (H p) at each point:
+//   SW_APPLY   field x (F0);          out = H x (O0)
+//   SW_PAP     field p = r + beta p_old (F0, F1; r alone when FIRST);
+//              sigma_j += p_j (H p)_j, p written (O1)
+//   SW_UPDATE  field p (F1), r (F0) at the centre only;
+//              y += alpha p, r' = r - alpha H p (O0), rho'_j += r'_j^2
 enum { SW_APPLY = 0, SW_PAP = 1, SW_UPDATE = 2 };
 
 typedef __amdgpu_buffer_rsrc_t Rsrc;
@@ -166,55 +169,66 @@ __device__ __forceinline__ T vmove(T x) {
   return r;
 }
 
-// The loads of one plane step, per pass q (raw values; r and p_old apart).
+// The loads of one plane step, per pass q (raw field values: the two parts
+// r and p_old apart in SW_PAP).
 template <typename T, int VW, int Q>
 struct MarchLoads {
-  T cr[Q][VW], cp[Q][VW];      // centre row of plane k+3
+  T cr[Q][VW], cp[Q][VW];      // field at the centre row of plane k+3
   T lr[Q][VW], lp[Q][VW];      // side row below, plane k+2
   T ur[Q][VW], up[Q][VW];      // side row above, plane k+2
   T hr[Q][VW], hp[Q][VW];      // the x-segment end's outer neighbour, plane k+2
   T d[Q];                      // diagonal, plane k+2
-  T y[Q][VW];                  // y, plane k+2 (SW_UPDATE)
+  T r[Q][VW], y[Q][VW];        // r and y at the centre row of plane k+2 (SW_UPDATE)
 };
 
-template <typename T, int VW, int Q, bool TWO, bool UPD, bool HALO>
+template <typename T, int VW, int Q, bool TWO, bool UPD, bool HALO, bool LN>
 __device__ __forceinline__ void take_set(const MarchLoads<T, VW, Q>& a, MarchLoads<T, VW, Q>& b) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
 #pragma unroll
     for (int v = 0; v < VW; ++v) {
       b.cr[q][v] = vmove(a.cr[q][v]);
-      b.lr[q][v] = vmove(a.lr[q][v]);
-      b.ur[q][v] = vmove(a.ur[q][v]);
-      if constexpr (TWO) {
-        b.cp[q][v] = vmove(a.cp[q][v]);
-        b.lp[q][v] = vmove(a.lp[q][v]);
-        b.up[q][v] = vmove(a.up[q][v]);
+      if constexpr (TWO) b.cp[q][v] = vmove(a.cp[q][v]);
+      if (!LN || q == 0) {
+        b.lr[q][v] = vmove(a.lr[q][v]);
+        if constexpr (TWO) b.lp[q][v] = vmove(a.lp[q][v]);
+      }
+      if (!LN || q == Q - 1) {
+        b.ur[q][v] = vmove(a.ur[q][v]);
+        if constexpr (TWO) b.up[q][v] = vmove(a.up[q][v]);
       }
       if constexpr (HALO) {
         b.hr[q][v] = vmove(a.hr[q][v]);
         if constexpr (TWO) b.hp[q][v] = vmove(a.hp[q][v]);
       }
-      if constexpr (UPD) b.y[q][v] = vmove(a.y[q][v]);
+      if constexpr (UPD) {
+        b.r[q][v] = vmove(a.r[q][v]);
+        b.y[q][v] = vmove(a.y[q][v]);
+      }
     }
     b.d[q] = vmove(a.d[q]);
   }
 }
 
-// The march of work item t (0 <= t < lines * nxs * cc * mc) of one problem;
-// shared by the single-problem kernel and the batched kernel below.  HALO:
-// the x line is split into several segments (nxs > 1).  A plane of one array
-// must be smaller than 2 GiB (checked when the context is created).
-template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO>
+// The march of work item t (0 <= t < lgroups * nxs * cc * mc) of one
+// problem; shared by the single-problem kernel and the batched kernel below.
+// HALO: the x line is split into several segments (nxs > 1).  LN: the Q passes
+// are Q adjacent side lines (each over one x segment of pp points) rather than
+// Q parts of one line's x segment; a pass then takes its inner side neighbours
+// from the other passes' registers and only the outer lines load side rows.
+// A plane of one array must be smaller than 2 GiB (checked when the context
+// is created).
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO, bool LN>
 __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0, const T* __restrict__ F1,
                                            T* __restrict__ O0, T* __restrict__ O1, T* __restrict__ Yv,
                                            const double* __restrict__ alpha, const double* __restrict__ beta,
                                            const int32_t* __restrict__ active, const T* __restrict__ diag,
                                            const OpeGrid& g, const MarchShape& ms, uint32_t N, uint32_t NV,
                                            double* __restrict__ part, OpeScalars* __restrict__ sc) {
-  constexpr bool TWO = (MODE != SW_APPLY) && !FIRST;   // field is r + beta p_old (two loads per value)
+  constexpr bool TWO = (MODE == SW_PAP) && !FIRST;   // field is r + beta p_old (two loads per value)
   constexpr bool UPD = (MODE == SW_UPDATE);
   constexpr int AUX_OUT = 0;
+  const T* __restrict__ FF = UPD ? F1 : F0;            // the field's (first) array
   __shared__ T lds[2 * Q * OPE_WG * VW];
   __shared__ double red[OPE_WG * VW];
   if (MODE != SW_APPLY) {
@@ -223,25 +237,24 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   }
   const uint32_t mchunk_id = t % ms.mc;
   t /= ms.mc;
-  uint32_t cchunk, xs, line;
-  if (ms.order == 0) {           // ((line * nxs + xs) * cc + chunk) * mc + m
+  uint32_t cchunk, xs, lg;
+  if (ms.order == 0) {           // ((group * nxs + xs) * cc + chunk) * mc + m
     cchunk = t % ms.cc;
     t /= ms.cc;
     xs = t % ms.nxs;
-    line = t / ms.nxs;
-  } else {                       // ((chunk * lines + line) * nxs + xs) * mc + m
+    lg = t / ms.nxs;
+  } else {                       // ((chunk * lgroups + group) * nxs + xs) * mc + m
     xs = t % ms.nxs;
     t /= ms.nxs;
-    line = t % ms.lines;
-    cchunk = t / ms.lines;
+    lg = t % ms.lgroups;
+    cchunk = t / ms.lgroups;
   }
+  const uint32_t line0 = lg * (LN ? (uint32_t)Q : 1u);
   const uint32_t cv = threadIdx.x % ms.ncv, slot = threadIdx.x / ms.ncv;
   const uint32_t colv = cchunk * ms.ncv + cv;
   const bool lane_ok = slot < ms.pp && colv < NV;
   const uint32_t z0 = mchunk_id * ms.mchunk;
   const uint32_t z1 = min(ms.mlen, z0 + ms.mchunk);
-  const bool side_lo = ms.has_side && line > 0;
-  const bool side_hi = ms.has_side && line + 1 < ms.lines;
   // one plane of an array: march_stride rows of N values
   const uint64_t plane_elems = (uint64_t)ms.march_stride * N;
   const uint32_t plane_bytes = (uint32_t)(plane_elems * sizeof(T));
@@ -257,17 +270,21 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   }
   const T cx = (T)g.cx, cs = (T)ms.cs, cm = (T)ms.cm;
   // per-pass byte offsets within a plane (NO_ROW where there is no row)
-  uint32_t xq[Q], oc[Q], ol[Q], ou[Q], oh[Q], od[Q];
+  uint32_t xq[Q], xiq[Q], oc[Q], ol[Q], ou[Q], oh[Q], od[Q];
   bool okq[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const uint32_t xi = q * ms.pp + slot;
+    const uint32_t xi = LN ? slot : q * ms.pp + slot;      // position in the x segment
+    const uint32_t line = line0 + (LN ? (uint32_t)q : 0u);
+    xiq[q] = xi;
     xq[q] = xs * ms.xseg + xi;
-    okq[q] = lane_ok && xi < ms.xseg && xq[q] < g.m0;
+    okq[q] = lane_ok && xi < ms.xseg && xq[q] < g.m0 && line < ms.lines;
     const uint32_t p = xq[q] + line * ms.side_stride;     // point index within the plane
     oc[q] = okq[q] ? p * row_bytes + colv * VW * (uint32_t)sizeof(T) : NO_ROW;
-    ol[q] = (okq[q] && side_lo) ? oc[q] - ms.side_stride * row_bytes : NO_ROW;
-    ou[q] = (okq[q] && side_hi) ? oc[q] + ms.side_stride * row_bytes : NO_ROW;
+    // side rows from memory: every pass, or in LN only the outer lines
+    const bool own_lo = !LN || q == 0, own_hi = !LN || q == Q - 1;
+    ol[q] = (okq[q] && own_lo && ms.has_side && line > 0) ? oc[q] - ms.side_stride * row_bytes : NO_ROW;
+    ou[q] = (okq[q] && own_hi && ms.has_side && line + 1 < ms.lines) ? oc[q] + ms.side_stride * row_bytes : NO_ROW;
     oh[q] = NO_ROW;
     if (HALO && okq[q]) {
       if (xi == 0 && xq[q] > 0) oh[q] = oc[q] - row_bytes;
@@ -295,30 +312,38 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
 
   // pipeline registers (per pass q)
   T pm[Q][VW], pz[Q][VW], p1[Q][VW];   // field at z-1, z, z+1
-  T rz[Q][VW], r1[Q][VW];               // r at z, z+1 (SW_UPDATE)
+  T rz[Q][VW];                          // r at z (SW_UPDATE)
   T smz[Q][VW], spz[Q][VW], hz[Q][VW];  // side neighbours and segment-end neighbour at z
   T dz[Q], yz[Q][VW];                   // diagonal and y at z
 
-  // loads for plane zs (side rows, segment ends, diagonal, y) and the centre row of zs + 1
+  // loads for plane zs (side rows, segment ends, diagonal, r and y) and the
+  // field's centre row of zs + 1
   auto issue = [&](uint32_t zs, MarchLoads<T, VW, Q>& L) {
     const bool vs = zs < z1, vc = vs && zs + 1 < ms.mlen;
-    const Rsrc c0 = prs(F0, zs + 1, vc), s0 = prs(F0, zs, vs);
+    const Rsrc c0 = prs(FF, zs + 1, vc), s0 = prs(FF, zs, vs);
     const Rsrc c1 = prs(F1, zs + 1, vc && TWO), s1 = prs(F1, zs, vs && TWO);
-    const Rsrc dr = drs(zs, vs), yr = prs(Yv, zs, vs && UPD);
+    const Rsrc dr = drs(zs, vs), yr = prs(Yv, zs, vs && UPD), rr = prs(F0, zs, vs && UPD);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       bld<T, VW>(c0, oc[q], L.cr[q]);
       if constexpr (TWO) bld<T, VW>(c1, oc[q], L.cp[q]);
-      bld<T, VW>(s0, ol[q], L.lr[q]);
-      if constexpr (TWO) bld<T, VW>(s1, ol[q], L.lp[q]);
-      bld<T, VW>(s0, ou[q], L.ur[q]);
-      if constexpr (TWO) bld<T, VW>(s1, ou[q], L.up[q]);
+      if (!LN || q == 0) {
+        bld<T, VW>(s0, ol[q], L.lr[q]);
+        if constexpr (TWO) bld<T, VW>(s1, ol[q], L.lp[q]);
+      }
+      if (!LN || q == Q - 1) {
+        bld<T, VW>(s0, ou[q], L.ur[q]);
+        if constexpr (TWO) bld<T, VW>(s1, ou[q], L.up[q]);
+      }
       if constexpr (HALO) {
         bld<T, VW>(s0, oh[q], L.hr[q]);
         if constexpr (TWO) bld<T, VW>(s1, oh[q], L.hp[q]);
       }
       L.d[q] = bld1<T>(dr, od[q]);
-      if constexpr (UPD) bld<T, VW>(yr, oc[q], L.y[q]);
+      if constexpr (UPD) {
+        bld<T, VW>(rr, oc[q], L.r[q]);
+        bld<T, VW>(yr, oc[q], L.y[q]);
+      }
     }
   };
   // end of plane z: shift the planes and take in the set issued for plane z + 1
@@ -326,7 +351,7 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   // load of the same set)
   auto rotate = [&](const MarchLoads<T, VW, Q>& Lin) {
     MarchLoads<T, VW, Q> L;
-    take_set<T, VW, Q, TWO, UPD, HALO>(Lin, L);
+    take_set<T, VW, Q, TWO, UPD, HALO, LN>(Lin, L);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
@@ -334,14 +359,13 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         pm[q][v] = pz[q][v];
         pz[q][v] = p1[q][v];
         if constexpr (UPD) {
-          rz[q][v] = r1[q][v];
-          r1[q][v] = L.cr[q][v];
+          rz[q][v] = L.r[q][v];
           yz[q][v] = L.y[q][v];
         }
       }
       comb(L.cr[q], L.cp[q], p1[q]);
-      comb(L.lr[q], L.lp[q], smz[q]);
-      comb(L.ur[q], L.up[q], spz[q]);
+      if (!LN || q == 0) comb(L.lr[q], L.lp[q], smz[q]);
+      if (!LN || q == Q - 1) comb(L.ur[q], L.up[q], spz[q]);
       if constexpr (HALO) comb(L.hr[q], L.hp[q], hz[q]);
       dz[q] = L.d[q];
     }
@@ -351,8 +375,8 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   // and the centre of z0 + 1) through the same rotate
   {
     const uint32_t zm = z0 > 0 ? z0 - 1 : 0;
-    const Rsrc m0r = prs(F0, zm, z0 > 0), m1r = prs(F1, zm, z0 > 0 && TWO);
-    const Rsrc c0r = prs(F0, z0, true), c1r = prs(F1, z0, TWO);
+    const Rsrc m0r = prs(FF, zm, z0 > 0), m1r = prs(F1, zm, z0 > 0 && TWO);
+    const Rsrc c0r = prs(FF, z0, true), c1r = prs(F1, z0, TWO);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       T tr[VW], tp[VW];
@@ -363,8 +387,6 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
       bld<T, VW>(c0r, oc[q], tr);
       if constexpr (TWO) bld<T, VW>(c1r, oc[q], tp);
       comb(tr, tp, p1[q]);                      // becomes pz
-#pragma unroll
-      for (int v = 0; v < VW; ++v) r1[q][v] = tr[v];
     }
     MarchLoads<T, VW, Q> L0;
     issue(z0, L0);
@@ -383,13 +405,13 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
     }
     __syncthreads();
     const Rsrc o0 = prs(O0, z, MODE != SW_PAP);
-    const Rsrc o1 = prs(O1, z, UPD), yo = prs(Yv, z, UPD);
+    const Rsrc o1 = prs(O1, z, MODE == SW_PAP), yo = prs(Yv, z, UPD);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const uint32_t xi = q * ms.pp + slot;
+      const uint32_t xi = xiq[q], li = q * ms.pp + slot;   // x position; slot in the staged plane
       // x neighbours: the staged plane, or the segment end's outer row (zero
       // where there is none: at the grid boundary, or a lane past the grid)
-      const uint32_t im = xi > 0 ? xi - 1 : 0, ip = xi + 1 < ms.xseg ? xi + 1 : xi;
+      const uint32_t im = xi > 0 ? li - 1 : li, ip = xi + 1 < ms.xseg ? li + 1 : li;
       T xm[VW], xp[VW];
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
@@ -398,16 +420,26 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         xm[v] = xi > 0 ? lm : hm;
         xp[v] = xi + 1 < ms.xseg ? lp : hm;
       }
+      // side neighbours: loaded rows, or in LN the adjacent passes' lines
+      // (zero beyond the grid: such a pass loaded nothing)
+      T sm[VW], sp[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        sm[v] = (LN && q > 0) ? pz[q > 0 ? q - 1 : 0][v] : smz[q][v];
+        sp[v] = (LN && q < Q - 1) ? pz[q < Q - 1 ? q + 1 : 0][v] : spz[q][v];
+      }
       T hx[VW];
 #pragma unroll
       for (int v = 0; v < VW; ++v)
-        hx[v] = dz[q] * pz[q][v] - (cx * (xm[v] + xp[v]) + cs * (smz[q][v] + spz[q][v]) + cm * (pm[q][v] + p1[q][v]));
+        hx[v] = dz[q] * pz[q][v] - (cx * (xm[v] + xp[v]) + cs * (sm[v] + sp[v]) + cm * (pm[q][v] + p1[q][v]));
       if constexpr (MODE == SW_APPLY) {
         if (ms.nt) bst<T, VW, AUX_NT>(o0, oc[q], hx);
         else bst<T, VW, AUX_OUT>(o0, oc[q], hx);
       } else if constexpr (MODE == SW_PAP) {
 #pragma unroll
         for (int v = 0; v < VW; ++v) acc[v] += okq[q] ? (double)pz[q][v] * (double)hx[v] : 0.0;
+        if (ms.nt) bst<T, VW, AUX_NT>(o1, oc[q], pz[q]);
+        else bst<T, VW, AUX_OUT>(o1, oc[q], pz[q]);
       } else {
         T yv[VW], rnew[VW];
 #pragma unroll
@@ -419,11 +451,9 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         if (ms.nt) {
           bst<T, VW, AUX_NT>(yo, oc[q], yv);
           bst<T, VW, AUX_NT>(o0, oc[q], rnew);
-          bst<T, VW, AUX_NT>(o1, oc[q], pz[q]);
         } else {
           bst<T, VW, AUX_OUT>(yo, oc[q], yv);
           bst<T, VW, AUX_OUT>(o0, oc[q], rnew);
-          bst<T, VW, AUX_OUT>(o1, oc[q], pz[q]);
         }
       }
     }
@@ -455,7 +485,7 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
       for (uint32_t l = 0; l < ms.pp; ++l)
 #pragma unroll
         for (int v = 0; v < VW; ++v) s[v] += red[(l * ms.ncv + cv) * VW + v];
-      const uint64_t row = ((uint64_t)line * ms.nxs + xs) * ms.mc + mchunk_id;
+      const uint64_t row = ((uint64_t)lg * ms.nxs + xs) * ms.mc + mchunk_id;
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
         const uint64_t col = (uint64_t)colv * VW + v;
@@ -465,7 +495,7 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   }
 }
 
-template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO>
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO, bool LN>
 __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, const T* __restrict__ F1,
                                                   T* __restrict__ O0, T* __restrict__ O1,
                                                   T* __restrict__ Yv, const double* __restrict__ alpha,
@@ -473,7 +503,7 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
                                                   const T* __restrict__ diag, OpeGrid g, MarchShape ms,
                                                   uint32_t N, uint32_t NV, double* __restrict__ part,
                                                   OpeScalars* __restrict__ sc) {
-  march_body<T, VW, Q, MODE, FIRST, HALO>(xcd_remap(blockIdx.x, gridDim.x), F0, F1, O0, O1, Yv, alpha, beta, active,
+  march_body<T, VW, Q, MODE, FIRST, HALO, LN>(xcd_remap(blockIdx.x, gridDim.x), F0, F1, O0, O1, Yv, alpha, beta, active,
                                           diag, g, ms, N, NV, part, sc);
 }
 
@@ -481,7 +511,7 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
 // storage type and shape class.  The XCD-remapped work-group index is a work
 // item (problem, tile): problem j owns items [wg_begin, wg_begin + wg_count),
 // so each XCD streams a contiguous range of one problem's lines.
-template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO>
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO, bool LN>
 __global__ __launch_bounds__(OPE_WG) void k_march_batched(const MarchJob* __restrict__ jobs, uint32_t njobs) {
   const uint32_t gt = xcd_remap(blockIdx.x, gridDim.x);
   uint32_t lo = 0, hi = njobs;
@@ -493,7 +523,7 @@ __global__ __launch_bounds__(OPE_WG) void k_march_batched(const MarchJob* __rest
   const MarchJob& jb = jobs[lo];
   const OpeGrid g = jb.g;
   const MarchShape ms = jb.ms;
-  march_body<T, VW, Q, MODE, FIRST, HALO>(gt - jb.wg_begin, (const T*)jb.F0, (const T*)jb.F1, (T*)jb.O0, (T*)jb.O1,
+  march_body<T, VW, Q, MODE, FIRST, HALO, LN>(gt - jb.wg_begin, (const T*)jb.F0, (const T*)jb.F1, (T*)jb.O0, (T*)jb.O1,
                                     (T*)jb.Yv, jb.alpha, jb.beta, jb.active, (const T*)jb.diag, g, ms, jb.N, jb.NV,
                                     jb.part, jb.sc);
 }
@@ -695,25 +725,29 @@ __global__ __launch_bounds__(OPE_WG) void k_gather_flags(const ReduceJob* __rest
 // launchers
 // ---------------------------------------------------------------------------
 
-template <typename T, int VW, int Q, int MODE, bool FIRST>
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool LN>
 static void launch_march_t(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag) {
   const uint32_t N = (uint32_t)c->N, NV = N / VW;
   const MarchShape& ms = c->ms;
-  const uint32_t grid = ms.lines * ms.nxs * ms.cc * ms.mc;
+  const uint32_t grid = ms.lgroups * ms.nxs * ms.cc * ms.mc;
   if (ms.nxs > 1)
-    hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, true>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0, O1,
-                       Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
+    hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, true, LN>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0,
+                       O1, Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
   else
-    hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, false>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0,
+    hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, false, LN>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0,
                        O1, Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
 }
 
 template <typename T, int VW, int MODE, bool FIRST>
 static void launch_march_q(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag) {
+  if (c->ms.ly > 1) {   // two side lines per work-group (q = 2)
+    launch_march_t<T, VW, 2, MODE, FIRST, true>(c, F0, F1, O0, O1, Yv, diag);
+    return;
+  }
   switch (c->ms.q) {
-    case 1: launch_march_t<T, VW, 1, MODE, FIRST>(c, F0, F1, O0, O1, Yv, diag); break;
-    case 2: launch_march_t<T, VW, 2, MODE, FIRST>(c, F0, F1, O0, O1, Yv, diag); break;
-    default: launch_march_t<T, VW, 4, MODE, FIRST>(c, F0, F1, O0, O1, Yv, diag); break;
+    case 1: launch_march_t<T, VW, 1, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag); break;
+    case 2: launch_march_t<T, VW, 2, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag); break;
+    default: launch_march_t<T, VW, 4, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag); break;
   }
 }
 
@@ -737,7 +771,7 @@ static hipError_t launch_march(ope_ctx* c, const void* F0, const void* F1, void*
   return hipGetLastError();
 }
 
-void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow) {
+void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow, int lines) {
   MarchShape& ms = c->ms;
   ms.order = order ? 1u : 0u;
   ms.nt = nt ? 1u : 0u;
@@ -763,8 +797,14 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
       best = use > best ? use : best;
     }
   }
+  ms.ly = 1;
+  if (lines && g.dim == 3 && g.m1 > 1) q = 2;   // two side lines per work-group, one per pass
   ms.q = q;
   ms.xseg = q * ms.pp;
+  if (lines && g.dim == 3 && g.m1 > 1) {
+    ms.ly = 2;
+    ms.xseg = ms.pp;
+  }
   ms.nxs = (g.m0 + ms.xseg - 1) / ms.xseg;
   ms.cc = (NV + ms.ncv - 1) / ms.ncv;
   if (g.dim == 3) {
@@ -788,8 +828,9 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
   // 2.5 MB of plane data is in flight (a work-group with short rows moves
   // little per plane); one chunk when that already holds (the lock-step march
   // keeps side rows in L2)
-  const uint32_t base = ms.lines * ms.nxs * ms.cc;
-  const double plane_bytes = (double)ms.xseg * ms.ncv * c->vw * (c->prec == OPE_FP64 ? 8.0 : 4.0);
+  ms.lgroups = (ms.lines + ms.ly - 1) / ms.ly;
+  const uint32_t base = ms.lgroups * ms.nxs * ms.cc;
+  const double plane_bytes = (double)ms.q * ms.pp * ms.ncv * c->vw * (c->prec == OPE_FP64 ? 8.0 : 4.0);
   uint32_t mc_auto = (512u + base - 1) / base;
   const uint32_t mc_bytes = (uint32_t)(2.5 * 1048576.0 / ((double)base * plane_bytes) + 0.5);
   if (mc_bytes > mc_auto) mc_auto = mc_bytes;
@@ -801,7 +842,7 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
 }
 
 int64_t march_rows(const ope_ctx* c) {
-  return (int64_t)c->ms.lines * c->ms.nxs * c->ms.mc;
+  return (int64_t)c->ms.lgroups * c->ms.nxs * c->ms.mc;
 }
 
 hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Yo) {
@@ -809,17 +850,15 @@ hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Yo) {
   return launch_march<SW_APPLY, false>(c, X, nullptr, Yo, nullptr, nullptr);
 }
 
-hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, int first) {
+hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, void* pnew, int first) {
   ProfScope ps(c, OPE_KERNEL_CG_SWEEP_A);
-  if (first) return launch_march<SW_PAP, true>(c, r, pold, nullptr, nullptr, nullptr);
-  return launch_march<SW_PAP, false>(c, r, pold, nullptr, nullptr, nullptr);
+  if (first) return launch_march<SW_PAP, true>(c, r, pold, nullptr, pnew, nullptr);
+  return launch_march<SW_PAP, false>(c, r, pold, nullptr, pnew, nullptr);
 }
 
-hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* pold, void* rnew, void* pnew,
-                            void* y, int first) {
+hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew, void* y) {
   ProfScope ps(c, OPE_KERNEL_CG_SWEEP_B);
-  if (first) return launch_march<SW_UPDATE, true>(c, r, pold, rnew, pnew, y);
-  return launch_march<SW_UPDATE, false>(c, r, pold, rnew, pnew, y);
+  return launch_march<SW_UPDATE, false>(c, r, p, rnew, nullptr, y);
 }
 
 hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols, double* out, int mode) {
@@ -881,45 +920,51 @@ bool reduce_few_fits(const ope_ctx* c) {
   return c->N <= 128 && march_rows(c) * c->N <= ((int64_t)1 << 17);
 }
 
-template <typename T, int VW, int Q, int MODE, bool FIRST>
+template <typename T, int VW, int Q, int MODE, bool FIRST, bool LN>
 static void launch_mb(hipStream_t s, int halo, const MarchJob* jobs, uint32_t njobs, uint32_t total) {
   if (halo)
-    hipLaunchKernelGGL((k_march_batched<T, VW, Q, MODE, FIRST, true>), dim3(total), dim3(OPE_WG), 0, s, jobs, njobs);
+    hipLaunchKernelGGL((k_march_batched<T, VW, Q, MODE, FIRST, true, LN>), dim3(total), dim3(OPE_WG), 0, s, jobs,
+                       njobs);
   else
-    hipLaunchKernelGGL((k_march_batched<T, VW, Q, MODE, FIRST, false>), dim3(total), dim3(OPE_WG), 0, s, jobs, njobs);
+    hipLaunchKernelGGL((k_march_batched<T, VW, Q, MODE, FIRST, false, LN>), dim3(total), dim3(OPE_WG), 0, s, jobs,
+                       njobs);
 }
 
 template <typename T, int VW, int MODE, bool FIRST>
-static void launch_mb_q(hipStream_t s, int q, int halo, const MarchJob* jobs, uint32_t njobs, uint32_t total) {
+static void launch_mb_q(hipStream_t s, int q, int halo, int ln, const MarchJob* jobs, uint32_t njobs,
+                        uint32_t total) {
+  if (ln) {
+    launch_mb<T, VW, 2, MODE, FIRST, true>(s, halo, jobs, njobs, total);
+    return;
+  }
   switch (q) {
-    case 1: launch_mb<T, VW, 1, MODE, FIRST>(s, halo, jobs, njobs, total); break;
-    case 2: launch_mb<T, VW, 2, MODE, FIRST>(s, halo, jobs, njobs, total); break;
-    default: launch_mb<T, VW, 4, MODE, FIRST>(s, halo, jobs, njobs, total); break;
+    case 1: launch_mb<T, VW, 1, MODE, FIRST, false>(s, halo, jobs, njobs, total); break;
+    case 2: launch_mb<T, VW, 2, MODE, FIRST, false>(s, halo, jobs, njobs, total); break;
+    default: launch_mb<T, VW, 4, MODE, FIRST, false>(s, halo, jobs, njobs, total); break;
   }
 }
 
 template <int MODE, bool FIRST>
-static void launch_mb_t(hipStream_t s, int prec, int vw, int q, int halo, const MarchJob* jobs, uint32_t njobs,
-                        uint32_t total) {
+static void launch_mb_t(hipStream_t s, int prec, int vw, int q, int halo, int ln, const MarchJob* jobs,
+                        uint32_t njobs, uint32_t total) {
   if (prec == OPE_FP64) {
-    if (vw == 2) launch_mb_q<double, 2, MODE, FIRST>(s, q, halo, jobs, njobs, total);
-    else launch_mb_q<double, 1, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+    if (vw == 2) launch_mb_q<double, 2, MODE, FIRST>(s, q, halo, ln, jobs, njobs, total);
+    else launch_mb_q<double, 1, MODE, FIRST>(s, q, halo, ln, jobs, njobs, total);
   } else {
-    if (vw == 4) launch_mb_q<float, 4, MODE, FIRST>(s, q, halo, jobs, njobs, total);
-    else if (vw == 2) launch_mb_q<float, 2, MODE, FIRST>(s, q, halo, jobs, njobs, total);
-    else launch_mb_q<float, 1, MODE, FIRST>(s, q, halo, jobs, njobs, total);
+    if (vw == 4) launch_mb_q<float, 4, MODE, FIRST>(s, q, halo, ln, jobs, njobs, total);
+    else if (vw == 2) launch_mb_q<float, 2, MODE, FIRST>(s, q, halo, ln, jobs, njobs, total);
+    else launch_mb_q<float, 1, MODE, FIRST>(s, q, halo, ln, jobs, njobs, total);
   }
 }
 
-hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int mode, int first,
+hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int ln, int mode, int first,
                                 const MarchJob* jobs, uint32_t njobs, uint32_t total_wgs) {
   if (njobs == 0 || total_wgs == 0) return hipSuccess;
   if (mode == SW_PAP) {
-    if (first) launch_mb_t<SW_PAP, true>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
-    else launch_mb_t<SW_PAP, false>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
+    if (first) launch_mb_t<SW_PAP, true>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);
+    else launch_mb_t<SW_PAP, false>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);
   } else {
-    if (first) launch_mb_t<SW_UPDATE, true>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
-    else launch_mb_t<SW_UPDATE, false>(s, prec, vw, q, halo, jobs, njobs, total_wgs);
+    launch_mb_t<SW_UPDATE, false>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);   // no first-iteration form
   }
   return hipGetLastError();
 }

@@ -131,9 +131,9 @@ hipError_t cg_iteration(ope_ctx* c, int it) {
   const int N = (int)c->N;
   const int first = it == 0;
   hipError_t e;
-  if ((e = launch_cg_pap(c, r_cur, p_old, first)) != hipSuccess) return e;
+  if ((e = launch_cg_pap(c, r_cur, p_old, p_new, first)) != hipSuccess) return e;
   if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA)) != hipSuccess) return e;
-  if ((e = launch_cg_update(c, r_cur, p_old, r_nxt, p_new, c->Y, first)) != hipSuccess) return e;
+  if ((e = launch_cg_update(c, r_cur, p_new, r_nxt, c->Y)) != hipSuccess) return e;
   return launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA);
 }
 
@@ -508,21 +508,21 @@ bool shared_fits(const ope_ctx* c) { return reduce_few_fits(c); }
 // h_flags (synchronised).  The problems' pre-phases must have completed.
 hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t* it) {
   struct Cls {
-    int prec, vw, q, halo;
+    int prec, vw, q, halo, ln;
     std::vector<int> idx;
   };
   std::vector<Cls> cls;
   for (int i : members) {
     const ope_ctx* c = b->ctx[i];
-    const int halo = c->ms.nxs > 1 ? 1 : 0;
+    const int halo = c->ms.nxs > 1 ? 1 : 0, ln = c->ms.ly > 1 ? 1 : 0;
     bool found = false;
     for (auto& k : cls)
-      if (k.prec == c->prec && k.vw == c->vw && k.q == (int)c->ms.q && k.halo == halo) {
+      if (k.prec == c->prec && k.vw == c->vw && k.q == (int)c->ms.q && k.halo == halo && k.ln == ln) {
         k.idx.push_back(i);
         found = true;
         break;
       }
-    if (!found) cls.push_back(Cls{c->prec, c->vw, (int)c->ms.q, halo, {i}});
+    if (!found) cls.push_back(Cls{c->prec, c->vw, (int)c->ms.q, halo, ln, {i}});
   }
   // job tables: per class, 4 variants (sweep A / B, even / odd iteration)
   const uint32_t M = (uint32_t)members.size();
@@ -536,11 +536,13 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
       for (size_t m = 0; m < cls[k].idx.size(); ++m) {
         ope_ctx* c = b->ctx[cls[k].idx[m]];
         const int par = v & 1, upd = v >> 1;
+        void* p_old = par ? c->Pb : c->HU;      // as in cg_iteration
+        void* p_new = par ? c->HU : c->Pb;
         MarchJob& jb = b->h_mjobs[off + v * cls[k].idx.size() + m];
         jb.F0 = c->Rb[par];
-        jb.F1 = par ? c->Pb : c->HU;
+        jb.F1 = upd ? p_new : p_old;
         jb.O0 = upd ? c->Rb[par ^ 1] : nullptr;
-        jb.O1 = upd ? (par ? c->HU : c->Pb) : nullptr;
+        jb.O1 = upd ? nullptr : p_new;
         jb.Yv = upd ? c->Y : nullptr;
         jb.alpha = c->alpha;
         jb.beta = c->beta;
@@ -553,7 +555,7 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
         jb.part = c->part;
         jb.sc = c->sc;
         jb.wg_begin = wg;
-        jb.wg_count = jb.ms.lines * jb.ms.nxs * jb.ms.cc * jb.ms.mc;
+        jb.wg_count = jb.ms.lgroups * jb.ms.nxs * jb.ms.cc * jb.ms.mc;
         wg += jb.wg_count;
       }
     }
@@ -598,7 +600,7 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
     if (cls.size() == 1) {
       const uint32_t nc = (uint32_t)cls[0].idx.size();
       const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
-      return launch_march_batched(s, cls[0].prec, cls[0].vw, cls[0].q, cls[0].halo, mode, first,
+      return launch_march_batched(s, cls[0].prec, cls[0].vw, cls[0].q, cls[0].halo, cls[0].ln, mode, first,
                                   b->d_mjobs + cls_off[0] + v * nc, nc, cls_total[0]);
     }
     if ((er = hipEventRecord(b->cg_ev, s)) != hipSuccess) return er;
@@ -607,7 +609,7 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
       const uint32_t nc = (uint32_t)cls[c].idx.size();
       const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
       if ((er = hipStreamWaitEvent(cs, b->cg_ev, 0)) != hipSuccess) return er;
-      if ((er = launch_march_batched(cs, cls[c].prec, cls[c].vw, cls[c].q, cls[c].halo, mode, first,
+      if ((er = launch_march_batched(cs, cls[c].prec, cls[c].vw, cls[c].q, cls[c].halo, cls[c].ln, mode, first,
                                      b->d_mjobs + cls_off[c] + v * nc, nc, cls_total[c])) != hipSuccess)
         return er;
       if ((er = hipEventRecord(b->cls_events[c], cs)) != hipSuccess) return er;
@@ -800,12 +802,14 @@ ProfScope::~ProfScope() {
   c->prof_used += 2;
 }
 
-// Default sweep flags: chunk-major; non-temporal stores when a row is split
-// over several column chunks (more than 32 16-byte vectors).  Measured: they
-// help there and cost where one work-group takes whole rows.
+// Default sweep flags: chunk-major, two side lines per work-group on 3D grids,
+// and non-temporal stores when the CG's working set (about five n x N blocks)
+// exceeds the 256 MiB last-level cache.  Measured: streamed stores help once
+// the sweeps' arrays cannot stay in that cache and cost while they can.
 static int default_sweep_flags(const ope_ctx* c) {
-  const int64_t NV = c->N / c->vw;
-  return OPE_SWEEP_CHUNK_MAJOR | (NV > 32 ? OPE_SWEEP_NONTEMPORAL : 0);
+  const double esz = c->prec == OPE_FP64 ? 8.0 : 4.0;
+  const bool big = 5.0 * (double)c->n * (double)c->N * esz > 256.0 * 1048576.0;
+  return OPE_SWEEP_CHUNK_MAJOR | (c->g.dim == 3 ? OPE_SWEEP_LINES : 0) | (big ? OPE_SWEEP_NONTEMPORAL : 0);
 }
 
 extern "C" {
@@ -886,7 +890,10 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (pts < pp) pts = pp;
   c->stream_pts = (int)pts;
   c->stream_wgs = (int)((n + pts - 1) / pts);
-  march_shape(c, 0, 0, 1, (default_sweep_flags(c) & OPE_SWEEP_NONTEMPORAL) ? 1 : 0, 0);
+  {
+    const int f = default_sweep_flags(c);
+    march_shape(c, 0, 0, 1, (f & OPE_SWEEP_NONTEMPORAL) ? 1 : 0, 0, (f & OPE_SWEEP_LINES) ? 1 : 0);
+  }
 
   const int64_t blk = n * N;
   const int64_t gtiles = ((N + 63) / 64) * ((N + 63) / 64);
@@ -1107,13 +1114,13 @@ ope_status ope_set_graphs(ope_ctx* c, int32_t enable) {
 }
 
 ope_status ope_set_sweep_shape(ope_ctx* c, int32_t q_max, int32_t march_chunks, int32_t flags) {
-  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~7))
+  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~15))
     return OPE_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   const MarchShape keep = c->ms;
   march_shape(c, q_max, march_chunks, flags & OPE_SWEEP_CHUNK_MAJOR, flags & OPE_SWEEP_NONTEMPORAL,
-              flags & OPE_SWEEP_NARROW);
+              flags & OPE_SWEEP_NARROW, flags & OPE_SWEEP_LINES);
   if (march_rows(c) * c->N > c->part_cap) {
     c->ms = keep;
     return OPE_EINVAL;
@@ -1125,7 +1132,7 @@ ope_status ope_get_sweep_shape(const ope_ctx* c, int32_t* q, int32_t* march_chun
   if (!c) return OPE_EINVAL;
   if (q) *q = (int32_t)c->ms.q;
   if (march_chunks) *march_chunks = (int32_t)c->ms.mc;
-  if (workgroups) *workgroups = (int32_t)(c->ms.lines * c->ms.nxs * c->ms.cc * c->ms.mc);
+  if (workgroups) *workgroups = (int32_t)(c->ms.lgroups * c->ms.nxs * c->ms.cc * c->ms.mc);
   return OPE_OK;
 }
 
@@ -1295,7 +1302,7 @@ ope_status ope_batch_create(ope_batch** out, const ope_op_desc* ops, const int64
     }
     st = ope_create(&b->ctx[i], &ops[i], N[i], precision, b->streams[i]);
   }
-  b->shared = 1;
+  b->shared = 0;   // per-problem launches: measured as fast as tuned shared launches
   b->flag_off.assign(count, 0);
   if (st == OPE_OK) {
     int64_t nflags = 0;
@@ -1475,12 +1482,15 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
         Shape pick{2, 0, default_sweep_flags(c)};
         double tbest = 1e30;
         const int narrow_opts = NV <= 32 ? 2 : 1;
-        for (int q : {1, 2})
+        // q = 3 stands for the two-line tile (q 2, OPE_SWEEP_LINES)
+        for (int qs : {1, 2, 3})
           for (int cm : {0, OPE_SWEEP_CHUNK_MAJOR})
             for (int nt : {0, OPE_SWEEP_NONTEMPORAL})
             for (int nr = 0; nr < narrow_opts; ++nr)
               for (int mcm : {0, 2}) {
-                const int flags = cm | nt | (nr ? OPE_SWEEP_NARROW : 0);
+                if (qs == 3 && c->g.dim != 3) continue;
+                const int q = qs == 3 ? 2 : qs;
+                const int flags = cm | nt | (nr ? OPE_SWEEP_NARROW : 0) | (qs == 3 ? OPE_SWEEP_LINES : 0);
                 if (ope_set_sweep_shape(c, q, 0, flags) != OPE_OK) continue;
                 int mc = 0;
                 if (mcm == 2) {

@@ -39,6 +39,8 @@ struct MarchShape {
   uint32_t nxs;       // x segments
   uint32_t cc;        // column chunks
   uint32_t lines;     // side lines (m1 in 3D, 1 in 2D)
+  uint32_t ly;        // side lines per work-group: 1, or q (one line per pass, x segment = pp)
+  uint32_t lgroups;   // groups of ly side lines
   uint32_t mlen;      // planes along the march axis (m2 in 3D, m1 in 2D)
   uint32_t mc;        // march chunks
   uint32_t mchunk;    // planes per march chunk
@@ -170,14 +172,16 @@ struct ProfScope {
 // launchers (each enqueues on ctx->stream and returns hipSuccess or an error)
 // ---------------------------------------------------------------------------
 hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Y);
-// fills c->ms (0 = automatic); narrow = 1 keeps 8-vector column chunks for short rows
-void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow);
+// fills c->ms (0 = automatic); narrow = 1 keeps 8-vector column chunks for short rows;
+// lines = 1 gives each work-group two side lines, one per pass (3D only)
+void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow, int lines = 0);
 int64_t march_rows(const ope_ctx* c);              // partial rows written by the CG sweeps
 
 // CG iteration halves (see k_stencil.hip)
-hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, int first);
-hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* pold, void* rnew,
-                            void* pnew, void* y, int first);
+// sweep A: p = r + beta p_old (p = r when first) written to pnew, p^T H p partials
+hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, void* pnew, int first);
+// sweep B: y += alpha p, rnew = r - alpha H p, rnew^T rnew partials
+hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew, void* y);
 hipError_t launch_cg_setup_reduce(ope_ctx* c, int mode);
 
 // column sums of partials: out[j] = sum_w part[w*ncols + j], fixed order
@@ -257,8 +261,9 @@ struct ReduceJob {
   int32_t* flags_out;      // gather destination (N values)
 };
 enum { BATCH_SW_PAP = 1, BATCH_SW_UPDATE = 2 };   // sweep A, sweep B
-// halo: the class's x lines are split into several segments (nxs > 1)
-hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int mode, int first,
+// halo: the class's x lines are split into several segments (nxs > 1);
+// ln: its work-groups take two side lines, one per pass (ly = 2)
+hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int ln, int mode, int first,
                                 const MarchJob* jobs, uint32_t njobs, uint32_t total_wgs);
 hipError_t launch_reduce_batched(hipStream_t s, int mode, const ReduceJob* jobs, uint32_t njobs);
 hipError_t launch_gather_flags(hipStream_t s, const ReduceJob* jobs, uint32_t njobs);

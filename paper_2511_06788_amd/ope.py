@@ -285,6 +285,7 @@ def ope_solve(ctx: int, U, tau: float, res_tol: float, max_steps: int) -> ope_so
 OPE_SWEEP_CHUNK_MAJOR = 1
 OPE_SWEEP_NONTEMPORAL = 2
 OPE_SWEEP_NARROW = 4
+OPE_SWEEP_LINES = 8
 
 
 def ope_set_graphs(ctx: int, enable: bool) -> None:

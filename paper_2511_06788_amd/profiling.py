@@ -28,12 +28,20 @@ def kernel_stats(db: str):
             for r in rows]
 
 
-def counter_per_dispatch(db: str, counter: str, pattern: str):
+def counter_per_dispatch(db: str, counter: str, pattern: str, min_frac: float = 0.0):
+    """Mean of `counter` over the dispatches of kernels matching `pattern`
+    whose value is at least min_frac of the largest (a CG sweep launched after
+    every column converged returns at once and moves next to nothing; such
+    launches are left out of a per-sweep figure).  Returns (mean, used, all)."""
     con = sqlite3.connect(db)
     rx = re.compile(pattern)
     vals = [r[1] for r in con.execute("select kernel_name, value from counters_collection where counter_name=?",
                                       (counter,)) if rx.search(r[0])]
-    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+    if not vals:
+        return None, 0, 0
+    top = max(vals)
+    used = [v for v in vals if v >= min_frac * top]
+    return sum(used) / len(used), len(used), len(vals)
 
 
 def short_name(name: str) -> str:
@@ -48,17 +56,19 @@ def cmd_trace(args):
            "| kernel | calls | total (ms) | average (us) | share |", "|---|---:|---:|---:|---:|"]
     for r in st[: args.top]:
         out.append(f"| `{short_name(r['name'])}` | {r['calls']} | {r['total_ms']:.2f} | {r['avg_us']:.1f} | {r['pct']:.1f}% |")
+    if args.note:
+        out += ["", args.note]
     print("\n".join(out))
 
 
 def cmd_pmc(args):
-    cf, _ = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE", args.copy_kernel)
-    cw, _ = counter_per_dispatch(args.copy_write, "WRITE_SIZE", args.copy_kernel)
+    cf, _, _ = counter_per_dispatch(args.copy_fetch, "FETCH_SIZE", args.copy_kernel)
+    cw, _, _ = counter_per_dispatch(args.copy_write, "WRITE_SIZE", args.copy_kernel)
     copy_kib = args.copy_bytes / 1024.0
     fscale = copy_kib / cf
     wscale = copy_kib / cw
-    f, nf = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
-    w, nw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
+    f, nf, af = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel, args.min_frac)
+    w, nw, aw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel, args.min_frac)
     blk = args.n * args.N * 8
     algo_read = args.reads * blk + 8 * args.n
     algo_write = args.writes * blk
@@ -66,7 +76,8 @@ def cmd_pmc(args):
         "kernel_regex": args.kernel, "n": args.n, "N": args.N,
         "fetch_kib_per_dispatch": f * fscale, "write_kib_per_dispatch": w * wscale, "copy_scale": 1.0,
         "raw_fetch_kib": f, "raw_write_kib": w, "fetch_scale": fscale, "write_scale": wscale,
-        "dispatches": [nf, nw], "algorithmic_read_bytes": algo_read, "algorithmic_write_bytes": algo_write,
+        "dispatches": [nf, nw], "dispatches_all": [af, aw], "min_frac": args.min_frac,
+        "algorithmic_read_bytes": algo_read, "algorithmic_write_bytes": algo_write,
         "source_sha256": hashlib.sha256(open(args.source, "rb").read()).hexdigest(), "command": args.cmd,
     }
     if args.json:
@@ -82,8 +93,11 @@ def cmd_pmc(args):
         f"| algorithmic read bytes | {algo_read:.4g} |", f"| algorithmic written bytes | {algo_write:.4g} |",
         f"| read / algorithmic | {f * fscale * 1024 / algo_read:.2f} |",
         f"| written / algorithmic | {w * wscale * 1024 / max(algo_write, 1):.2f} |",
-        f"| dispatches averaged | {nf} / {nw} |",
-    ]))
+        f"| dispatches averaged (of all) | {nf} of {af} / {nw} of {aw} |",
+        "",
+        f"Averaged: the dispatches whose counter is at least {args.min_frac:g} of the largest (launches past the last "
+        "converged column of a CG chunk return at once and move almost nothing).",
+    ] + ([""] + [args.note] if args.note else [])))
 
 
 def main(argv=None):
@@ -94,6 +108,7 @@ def main(argv=None):
     t.add_argument("--cmd", required=True)
     t.add_argument("--title", default="")
     t.add_argument("--top", type=int, default=20)
+    t.add_argument("--note", default="", help="text appended to the summary")
     p = sub.add_parser("pmc")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -103,11 +118,13 @@ def main(argv=None):
     p.add_argument("--n", type=int, required=True)
     p.add_argument("--N", type=int, required=True)
     p.add_argument("--reads", type=int, default=3)
-    p.add_argument("--writes", type=int, default=3)
+    p.add_argument("--writes", type=int, default=2)
     p.add_argument("--source", required=True)
     p.add_argument("--cmd", required=True)
     p.add_argument("--title", default="")
     p.add_argument("--json", default=None)
+    p.add_argument("--min-frac", type=float, default=0.1)
+    p.add_argument("--note", default="")
     args = ap.parse_args(argv)
     {"trace": cmd_trace, "pmc": cmd_pmc}[args.what](args)
 

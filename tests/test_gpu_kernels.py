@@ -180,10 +180,14 @@ def test_energy_residual_ritz_match_oracle():
     assert abs(drift - O.ortho_error(U)) <= 1e-14 * p.N
 
 
-@pytest.mark.parametrize("q_max,chunks,flags", [(1, 1, 0), (2, 3, 1), (4, 0, 2), (4, 5, 3), (1, 0, 3)])
+@pytest.mark.parametrize("q_max,chunks,flags", [(1, 1, 0), (2, 3, 1), (4, 0, 2), (4, 5, 3), (1, 0, 3),
+                                                 (2, 0, 9), (2, 3, 8), (1, 2, 11), (2, 0, 13)])
 def test_sweep_shapes_agree(q_max, chunks, flags):
     """Every launch shape of the marching sweeps computes the same H X, and the
-    same CG solution up to the order of the dot-product sums."""
+    same CG solution up to the order of the dot-product sums (flags 8: two
+    side lines per work-group; with 21 lines the last group is half empty, and
+    its x segments of 15 points need segment-end neighbours; with 13 the
+    8-vector chunks cover x whole)."""
     from paper_2511_06788_amd import ope
     p = W.wells_3d(m=21, N=34, seed=6)
     op = _op(p)

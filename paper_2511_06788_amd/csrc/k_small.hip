@@ -190,28 +190,37 @@ __global__ __launch_bounds__(SW) void k_solve_setup(const double* __restrict__ r
   }
 }
 
+// The N x N products below run from LDS: a thread's row index is uniform over
+// its wave, so that operand is a broadcast read; from global memory it would be
+// a scalar load, and at most 15 of those can be outstanding.  smat holds one
+// N x N FP64 matrix (dynamic LDS, N*N*8 bytes, at most 128 KiB).
+
 // Steps 2-3: M = I + tau/2 (S_a - S_b) + tau^2/4 (T - S_a S_b), S_a = S_b^T,
 // B = M^{-1}, A = 2/tau (I - B) + S_b B, Z = [I - tau A ; tau B].
 __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ Sb, const double* __restrict__ T,
                                                     double tau, uint32_t N, double* __restrict__ Bws,
                                                     double* __restrict__ Z, double* __restrict__ Aout,
                                                     OpeScalars* __restrict__ sc) {
+  extern __shared__ double smat[];
   __shared__ double fcol[256], rowk[256];
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
+  for (uint32_t e = threadIdx.x; e < N * N; e += SW) smat[e] = Sb[e];
+  __syncthreads();
   const uint32_t jj = o.j < N ? o.j : 0u;
   double w[RPT];
   // M, with P = S_a S_b, P_ij = sum_k S_b[k][i] S_b[k][j]
   double P[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) P[r] = 0.0;
+#pragma unroll 4
   for (uint32_t k = 0; k < N; ++k) {
-    const double skj = Sb[(uint64_t)k * N + jj];
+    const double skj = smat[k * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t i = o.row(r);
-      const double ski = Sb[(uint64_t)k * N + (i < N ? i : 0u)];
+      const double ski = smat[k * N + (i < N ? i : 0u)];
       P[r] += ski * skj;
     }
   }
@@ -229,16 +238,17 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
   gj_invert(w, N, fcol, rowk, &bad);
   store_own(Bws, N, w);           // B
   __syncthreads();
-  // A = 2/tau (I - B) + S_b B
+  // A = 2/tau (I - B) + S_b B (B's columns from global memory, eight rows in flight)
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
+#pragma unroll 8
   for (uint32_t k = 0; k < N; ++k) {
     const double bkj = Bws[(uint64_t)k * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t i = o.row(r);
-      acc[r] += Sb[(uint64_t)(i < N ? i : 0u) * N + k] * bkj;
+      acc[r] += smat[(i < N ? i : 0u) * N + k] * bkj;
     }
   }
   const double it = 2.0 / tau;
@@ -270,35 +280,42 @@ __global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restri
                                                           const double* __restrict__ C, double tau, uint32_t N,
                                                           double* __restrict__ Wsm, float* __restrict__ Z32,
                                                           OpeScalars* __restrict__ sc) {
+  extern __shared__ double smat[];
   __shared__ double fcol[256], rowk[256];
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
+  for (uint32_t e = threadIdx.x; e < N * N; e += SW) smat[e] = C[e];
+  __syncthreads();
   const uint32_t jj = o.j < N ? o.j : 0u;
-  // Wsm = (C - I) S_b
+  // Wsm = (C - I) S_b  (C from LDS, S_b's columns from global memory)
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
+#pragma unroll 8
   for (uint32_t l = 0; l < N; ++l) {
     const double slj = Sb[(uint64_t)l * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t k = o.row(r) < N ? o.row(r) : 0u;
-      acc[r] += (C[(uint64_t)k * N + l] - (k == l ? 1.0 : 0.0)) * slj;
+      acc[r] += (smat[k * N + l] - (k == l ? 1.0 : 0.0)) * slj;
     }
   }
   store_own(Wsm, N, acc);
   __syncthreads();
-  // Q = S_b^T Wsm
+  for (uint32_t e = threadIdx.x; e < N * N; e += SW) smat[e] = Sb[e];
+  __syncthreads();
+  // Q = S_b^T Wsm  (S_b from LDS, Wsm's columns from global memory)
   double qv[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) qv[r] = 0.0;
+#pragma unroll 8
   for (uint32_t k = 0; k < N; ++k) {
     const double wkj = Wsm[(uint64_t)k * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t i = o.row(r) < N ? o.row(r) : 0u;
-      qv[r] += Sb[(uint64_t)k * N + i] * wkj;
+      qv[r] += smat[k * N + i] * wkj;
     }
   }
   double w[RPT];
@@ -721,8 +738,8 @@ hipError_t launch_prep_small(ope_ctx* c) {
 hipError_t launch_small_solve_delta(ope_ctx* c, const double* Sb, const double* Tperp, double tau) {
   if (c->N > OPE_MAX_N_ONE_WG) return big_small_solve_delta(c, Sb, Tperp, tau);
   ProfScope ps(c, OPE_KERNEL_SMALL);
-  hipLaunchKernelGGL(k_small_solve_delta, dim3(1), dim3(SW), 0, c->stream, Sb, Tperp, c->C, tau, (uint32_t)c->N,
-                     c->Wsm, c->Z32, c->sc);
+  hipLaunchKernelGGL(k_small_solve_delta, dim3(1), dim3(SW), (size_t)c->N * c->N * sizeof(double), c->stream, Sb,
+                     Tperp, c->C, tau, (uint32_t)c->N, c->Wsm, c->Z32, c->sc);
   return hipGetLastError();
 }
 
@@ -759,8 +776,8 @@ hipError_t launch_small_solve(ope_ctx* c, const double* Sb, const double* T, dou
                               double* B) {
   if (c->N > OPE_MAX_N_ONE_WG) return big_small_solve(c, Sb, T, tau, Z, A, B ? B : c->B);
   ProfScope ps(c, OPE_KERNEL_SMALL);
-  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SW), 0, c->stream, Sb, T, tau, (uint32_t)c->N, B ? B : c->B, Z, A,
-                     c->sc);
+  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SW), (size_t)c->N * c->N * sizeof(double), c->stream, Sb, T, tau,
+                     (uint32_t)c->N, B ? B : c->B, Z, A, c->sc);
   return hipGetLastError();
 }
 

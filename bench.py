@@ -44,9 +44,11 @@ def log(msg):
 
 
 def sweep_b_bytes(n, N):
-    """Algorithmic HBM bytes of one CG sweep B: read p, r, y; write r', y
-    (five n x N FP64 blocks) plus the n-entry diagonal."""
-    return 5 * n * N * 8 + 8 * n
+    """Algorithmic HBM bytes of one CG sweep B, averaged over its two forms
+    (one launch per CG iteration, alternating): even iterations read p, r and
+    write r' (three n x N FP64 blocks); odd ones also read y and p_prev and
+    write y (six blocks).  4.5 blocks plus the n-entry diagonal."""
+    return 4.5 * n * N * 8 + 8 * n
 
 
 def kernel_bytes(kind, n, N):
@@ -55,6 +57,7 @@ def kernel_bytes(kind, n, N):
         "stencil": 2 * blk + 8 * n,          # read X, write HX, diagonal
         "cg_sweep_a": 3 * blk + 8 * n,       # read r, p_old, write p, diagonal
         "cg_sweep_b": sweep_b_bytes(n, N),
+        "cg_sweep_b_odd": 6 * blk + 8 * n,   # read p, r, y, p_prev, write r', y, diagonal
     }.get(kind)
 
 
@@ -438,6 +441,7 @@ def main():
     if not args.no_extras:
         kernels = {}
         for name, kid in (("stencil", ope.OPE_KERNEL_STENCIL), ("cg_sweep_a", ope.OPE_KERNEL_CG_SWEEP_A),
+                          ("cg_sweep_b_odd", ope.OPE_KERNEL_CG_SWEEP_B_Y),
                           ("gram", ope.OPE_KERNEL_GRAM), ("rowmm", ope.OPE_KERNEL_ROWMM),
                           ("small", ope.OPE_KERNEL_SMALL)):
             ope.ope_profile_begin(h, kid)
@@ -445,8 +449,9 @@ def main():
             for _ in range(5):
                 its += ope.ope_step(h, U, args.tau).inner_iterations
             nl, tms = ope.ope_profile_end(h)
-            # a CG sweep's time per counted iteration (as for sweep B above)
-            per = its if name == "cg_sweep_a" else nl
+            # a CG sweep's time per counted iteration (as for sweep B above);
+            # the odd form of sweep B runs on every second one
+            per = its if name == "cg_sweep_a" else (its / 2.0 if name == "cg_sweep_b_odd" else nl)
             rec = {"avg_ms": tms / max(per, 1), "launches_per_step": nl / 5.0}
             b = kernel_bytes(name, n, N)
             if b:

@@ -355,11 +355,12 @@ ope_status ope_get_sweep_shape(const ope_ctx* ctx, int32_t* q, int32_t* march_ch
 typedef enum {
   OPE_KERNEL_STENCIL = 0,   /* H X (stencil SpMM) */
   OPE_KERNEL_CG_SWEEP_A = 1,/* CG sweep A: p^T H p with p formed on the fly */
-  OPE_KERNEL_CG_SWEEP_B = 2,/* CG sweep B: y, r, p updates with H p and r^T r */
+  OPE_KERNEL_CG_SWEEP_B = 2,/* CG sweep B, both forms: r update with H p and r^T r; odd iterations also y */
   OPE_KERNEL_GRAM = 3,      /* split-K MFMA inner matrices (without their reduction) */
   OPE_KERNEL_ROWMM = 4,     /* MFMA row-block products (residual, warm start, Step 4) */
   OPE_KERNEL_SMALL = 5,     /* one-work-group FP64 small solves */
-  OPE_KERNEL_COUNT = 6
+  OPE_KERNEL_CG_SWEEP_B_Y = 6,/* CG sweep B of odd iterations only (with the paired y update) */
+  OPE_KERNEL_COUNT = 7
 } ope_kernel_id;
 
 typedef struct {

@@ -159,6 +159,7 @@ __global__ __launch_bounds__(SW) void k_cg_setup(const double* __restrict__ rcol
     target[j] = t;
     rho[j] = rho0[j];
     alpha[j] = 0.0;
+    alpha[N + j] = 0.0;        // both iteration-parity halves
     beta[j] = 0.0;
     active[j] = rho0[j] > t ? 1 : 0;
   }
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(SW) void k_solve_setup(const double* __restrict__ r
     target[j] = t;
     rho[j] = rho0[j];
     alpha[j] = 0.0;
+    alpha[N + j] = 0.0;        // both iteration-parity halves
     beta[j] = 0.0;
     active[j] = rho0[j] > t ? 1 : 0;
   }

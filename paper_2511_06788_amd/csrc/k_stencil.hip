@@ -16,10 +16,16 @@
 // column).  One CG iteration is two sweeps:
 //   sweep A (cg_pap):    p = r + beta p_old (formed on the fly, with its
 //                        neighbours), sigma_j = p_j^T H p_j, and p is written out
-//   sweep B (cg_update): y += alpha p, r' = r - alpha H p, rho'_j = r'_j^T r'_j
-// so an iteration moves 8 block-passes (A reads r, p_old and writes p; B reads
-// p, r, y and writes r', y) instead of materialising q = H p.  B recomputes
-// H p from p, so its neighbour rows come from one array, not two.  The per-column
+//   sweep B (cg_update): r' = r - alpha H p, rho'_j = r'_j^T r'_j, and on odd
+//                        iterations y += alpha_prev p_prev + alpha p
+// B recomputes H p from p instead of reading a stored q = H p, so its neighbour
+// rows come from one array.  The y update of an even iteration k is deferred to
+// iteration k + 1 (p_k is still in the other p buffer then, and alpha keeps
+// one array per iteration parity): per pair of iterations A moves 3 + 3 block
+// passes (reads r, p_old, writes p) and B 3 + 6 (reads p, r, writes r'; then
+// also reads y, p_prev and writes y), 15 instead of 16.  The two y terms are
+// added in iteration order, so y equals that of updating it every iteration,
+// bit for bit.  The per-column
 // scalars alpha, beta, rho and the convergence flags live on the device and
 // are produced by the fixed-order reductions at the end of this file.
 #include "ope_internal.h"
@@ -54,9 +60,11 @@ __device__ __forceinline__ void stv_nt(T* __restrict__ base, uint64_t off, const
   for (int k = 0; k < VW; ++k) __builtin_nontemporal_store(v[k], base + off + k);
 }
 
-__device__ __forceinline__ bool any_active(const int32_t* __restrict__ active, uint32_t N) {
+// Whether any column is active, or (given `pending`) has a non-zero entry there.
+__device__ __forceinline__ bool any_active(const int32_t* __restrict__ active, uint32_t N,
+                                           const double* __restrict__ pending = nullptr) {
   int a = 0;
-  for (uint32_t j = threadIdx.x; j < N; j += OPE_WG) a |= active[j];
+  for (uint32_t j = threadIdx.x; j < N; j += OPE_WG) a |= active[j] | (pending && pending[j] != 0.0 ? 1 : 0);
   return __syncthreads_or(a) != 0;
 }
 
@@ -112,8 +120,10 @@ __device__ __forceinline__ void wg_colsum(double* red, const double (&acc)[VW], 
 //   SW_PAP     field p = r + beta p_old (F0, F1; r alone when FIRST);
 //              sigma_j += p_j (H p)_j, p written (O1)
 //   SW_UPDATE  field p (F1), r (F0) at the centre only;
-//              y += alpha p, r' = r - alpha H p (O0), rho'_j += r'_j^2
-enum { SW_APPLY = 0, SW_PAP = 1, SW_UPDATE = 2 };
+//              r' = r - alpha H p (O0), rho'_j += r'_j^2
+//   SW_UPDATE_Y  as SW_UPDATE, and y (Yv) += alpha_prev p_prev + alpha p, with
+//              p_prev read from O1 and alpha_prev taken from the beta argument
+enum { SW_APPLY = 0, SW_PAP = 1, SW_UPDATE = 2, SW_UPDATE_Y = 3 };
 
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int RSRC_FLAGS = 0x00020000;        // raw (unformatted) 32-bit dword access
@@ -178,10 +188,11 @@ struct MarchLoads {
   T ur[Q][VW], up[Q][VW];      // side row above, plane k+2
   T hr[Q][VW], hp[Q][VW];      // the x-segment end's outer neighbour, plane k+2
   T d[Q];                      // diagonal, plane k+2
-  T r[Q][VW], y[Q][VW];        // r and y at the centre row of plane k+2 (SW_UPDATE)
+  T r[Q][VW], y[Q][VW];        // r and y at the centre row of plane k+2 (SW_UPDATE, y: SW_UPDATE_Y)
+  T pp[Q][VW];                 // p_prev at the centre row of plane k+2 (SW_UPDATE_Y)
 };
 
-template <typename T, int VW, int Q, bool TWO, bool UPD, bool HALO, bool LN>
+template <typename T, int VW, int Q, bool TWO, bool UPD, bool YUP, bool HALO, bool LN>
 __device__ __forceinline__ void take_set(const MarchLoads<T, VW, Q>& a, MarchLoads<T, VW, Q>& b) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -201,9 +212,10 @@ __device__ __forceinline__ void take_set(const MarchLoads<T, VW, Q>& a, MarchLoa
         b.hr[q][v] = vmove(a.hr[q][v]);
         if constexpr (TWO) b.hp[q][v] = vmove(a.hp[q][v]);
       }
-      if constexpr (UPD) {
-        b.r[q][v] = vmove(a.r[q][v]);
+      if constexpr (UPD) b.r[q][v] = vmove(a.r[q][v]);
+      if constexpr (YUP) {
         b.y[q][v] = vmove(a.y[q][v]);
+        b.pp[q][v] = vmove(a.pp[q][v]);
       }
     }
     b.d[q] = vmove(a.d[q]);
@@ -226,13 +238,15 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
                                            const OpeGrid& g, const MarchShape& ms, uint32_t N, uint32_t NV,
                                            double* __restrict__ part, OpeScalars* __restrict__ sc) {
   constexpr bool TWO = (MODE == SW_PAP) && !FIRST;   // field is r + beta p_old (two loads per value)
-  constexpr bool UPD = (MODE == SW_UPDATE);
+  constexpr bool UPD = (MODE == SW_UPDATE || MODE == SW_UPDATE_Y);
+  constexpr bool YUP = (MODE == SW_UPDATE_Y);
   constexpr int AUX_OUT = 0;
   const T* __restrict__ FF = UPD ? F1 : F0;            // the field's (first) array
   __shared__ T lds[2 * Q * OPE_WG * VW];
   __shared__ double red[OPE_WG * VW];
   if (MODE != SW_APPLY) {
-    if (!any_active(active, N)) return;
+    // SW_UPDATE_Y also runs for a pending y update of converged columns
+    if (!any_active(active, N, YUP ? beta : nullptr)) return;
     if (MODE == SW_PAP && t == 0 && threadIdx.x == 0) sc->cg_iters += 1;
   }
   const uint32_t mchunk_id = t % ms.mc;
@@ -260,12 +274,13 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   const uint32_t plane_bytes = (uint32_t)(plane_elems * sizeof(T));
   const uint32_t row_bytes = N * (uint32_t)sizeof(T);
 
-  T b[VW], a[VW];
+  T b[VW], a[VW], ap[VW];
   double acc[VW];
 #pragma unroll
   for (int v = 0; v < VW; ++v) {
     b[v] = (TWO && lane_ok) ? (T)beta[colv * VW + v] : T(0);
     a[v] = (UPD && lane_ok) ? (T)alpha[colv * VW + v] : T(0);
+    ap[v] = (YUP && lane_ok) ? (T)beta[colv * VW + v] : T(0);     // alpha of the previous iteration
     acc[v] = 0.0;
   }
   const T cx = (T)g.cx, cs = (T)ms.cs, cm = (T)ms.cm;
@@ -314,7 +329,7 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   T pm[Q][VW], pz[Q][VW], p1[Q][VW];   // field at z-1, z, z+1
   T rz[Q][VW];                          // r at z (SW_UPDATE)
   T smz[Q][VW], spz[Q][VW], hz[Q][VW];  // side neighbours and segment-end neighbour at z
-  T dz[Q], yz[Q][VW];                   // diagonal and y at z
+  T dz[Q], yz[Q][VW], ppz[Q][VW];       // diagonal, y and p_prev at z
 
   // loads for plane zs (side rows, segment ends, diagonal, r and y) and the
   // field's centre row of zs + 1
@@ -322,7 +337,8 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
     const bool vs = zs < z1, vc = vs && zs + 1 < ms.mlen;
     const Rsrc c0 = prs(FF, zs + 1, vc), s0 = prs(FF, zs, vs);
     const Rsrc c1 = prs(F1, zs + 1, vc && TWO), s1 = prs(F1, zs, vs && TWO);
-    const Rsrc dr = drs(zs, vs), yr = prs(Yv, zs, vs && UPD), rr = prs(F0, zs, vs && UPD);
+    const Rsrc dr = drs(zs, vs), yr = prs(Yv, zs, vs && YUP), rr = prs(F0, zs, vs && UPD);
+    const Rsrc qr = prs(O1, zs, vs && YUP);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       bld<T, VW>(c0, oc[q], L.cr[q]);
@@ -340,9 +356,10 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         if constexpr (TWO) bld<T, VW>(s1, oh[q], L.hp[q]);
       }
       L.d[q] = bld1<T>(dr, od[q]);
-      if constexpr (UPD) {
-        bld<T, VW>(rr, oc[q], L.r[q]);
+      if constexpr (UPD) bld<T, VW>(rr, oc[q], L.r[q]);
+      if constexpr (YUP) {
         bld<T, VW>(yr, oc[q], L.y[q]);
+        bld<T, VW>(qr, oc[q], L.pp[q]);
       }
     }
   };
@@ -351,16 +368,17 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   // load of the same set)
   auto rotate = [&](const MarchLoads<T, VW, Q>& Lin) {
     MarchLoads<T, VW, Q> L;
-    take_set<T, VW, Q, TWO, UPD, HALO, LN>(Lin, L);
+    take_set<T, VW, Q, TWO, UPD, YUP, HALO, LN>(Lin, L);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
         pm[q][v] = pz[q][v];
         pz[q][v] = p1[q][v];
-        if constexpr (UPD) {
-          rz[q][v] = L.r[q][v];
+        if constexpr (UPD) rz[q][v] = L.r[q][v];
+        if constexpr (YUP) {
           yz[q][v] = L.y[q][v];
+          ppz[q][v] = L.pp[q][v];
         }
       }
       comb(L.cr[q], L.cp[q], p1[q]);
@@ -405,7 +423,7 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
     }
     __syncthreads();
     const Rsrc o0 = prs(O0, z, MODE != SW_PAP);
-    const Rsrc o1 = prs(O1, z, MODE == SW_PAP), yo = prs(Yv, z, UPD);
+    const Rsrc o1 = prs(O1, z, MODE == SW_PAP), yo = prs(Yv, z, YUP);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const uint32_t xi = xiq[q], li = q * ms.pp + slot;   // x position; slot in the staged plane
@@ -444,15 +462,18 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         T yv[VW], rnew[VW];
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
-          yv[v] = yz[q][v] + a[v] * pz[q][v];
           rnew[v] = rz[q][v] - a[v] * hx[v];
           acc[v] += okq[q] ? (double)rnew[v] * (double)rnew[v] : 0.0;
+          if constexpr (YUP) {
+            const T y1 = yz[q][v] + ap[v] * ppz[q][v];      // the previous iteration's term first
+            yv[v] = y1 + a[v] * pz[q][v];
+          }
         }
         if (ms.nt) {
-          bst<T, VW, AUX_NT>(yo, oc[q], yv);
+          if constexpr (YUP) bst<T, VW, AUX_NT>(yo, oc[q], yv);
           bst<T, VW, AUX_NT>(o0, oc[q], rnew);
         } else {
-          bst<T, VW, AUX_OUT>(yo, oc[q], yv);
+          if constexpr (YUP) bst<T, VW, AUX_OUT>(yo, oc[q], yv);
           bst<T, VW, AUX_OUT>(o0, oc[q], rnew);
         }
       }
@@ -687,8 +708,10 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_few(const double* __restrict_
 }
 
 // Batched one-work-group column reductions: work-group j reduces problem j.
+// par: the CG iteration's parity, which selects the half of the problem's
+// alpha array (2 ncols entries) the alpha reduction writes.
 template <int MODE>
-__global__ __launch_bounds__(OPE_WG) void k_reduce_batched(const ReduceJob* __restrict__ jobs) {
+__global__ __launch_bounds__(OPE_WG) void k_reduce_batched(const ReduceJob* __restrict__ jobs, uint32_t par) {
   __shared__ double red[OPE_WG];
   const ReduceJob& jb = jobs[blockIdx.x];
   const uint32_t nrows = jb.nrows, ncols = jb.ncols;
@@ -711,7 +734,16 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_batched(const ReduceJob* __re
   if (gi != 0) return;
   double tot = 0.0;
   for (uint32_t k = 0; k < G; ++k) tot += red[k * ncols + col];
-  cg_finalise<MODE>(col, tot, jb.alpha, jb.beta, jb.rho, jb.target, jb.active, jb.sc);
+  cg_finalise<MODE>(col, tot, jb.alpha + (uint64_t)par * ncols, jb.beta, jb.rho, jb.target, jb.active, jb.sc);
+}
+
+// y[i][j] += alpha[j] p[i][j] over n x N (a CG that stopped on an even
+// iteration leaves that iteration's y term to add).
+template <typename T>
+__global__ __launch_bounds__(OPE_WG) void k_y_flush(T* __restrict__ y, const T* __restrict__ p,
+                                                    const double* __restrict__ alpha, uint64_t count, uint32_t N) {
+  for (uint64_t e = blockIdx.x * (uint64_t)OPE_WG + threadIdx.x; e < count; e += (uint64_t)gridDim.x * OPE_WG)
+    y[e] = y[e] + (T)alpha[e % N] * p[e];
 }
 
 __global__ __launch_bounds__(OPE_WG) void k_gather_flags(const ReduceJob* __restrict__ jobs) {
@@ -725,48 +757,53 @@ __global__ __launch_bounds__(OPE_WG) void k_gather_flags(const ReduceJob* __rest
 // launchers
 // ---------------------------------------------------------------------------
 
+// al, be: the kernel's alpha and beta arguments (their meaning per MODE is
+// given at march_body).
 template <typename T, int VW, int Q, int MODE, bool FIRST, bool LN>
-static void launch_march_t(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag) {
+static void launch_march_t(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag,
+                           const double* al, const double* be) {
   const uint32_t N = (uint32_t)c->N, NV = N / VW;
   const MarchShape& ms = c->ms;
   const uint32_t grid = ms.lgroups * ms.nxs * ms.cc * ms.mc;
   if (ms.nxs > 1)
     hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, true, LN>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0,
-                       O1, Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
+                       O1, Yv, al, be, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
   else
     hipLaunchKernelGGL((k_march<T, VW, Q, MODE, FIRST, false, LN>), dim3(grid), dim3(OPE_WG), 0, c->stream, F0, F1, O0,
-                       O1, Yv, c->alpha, c->beta, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
+                       O1, Yv, al, be, c->active, diag, c->g, ms, N, NV, c->part, c->sc);
 }
 
 template <typename T, int VW, int MODE, bool FIRST>
-static void launch_march_q(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag) {
+static void launch_march_q(ope_ctx* c, const T* F0, const T* F1, T* O0, T* O1, T* Yv, const T* diag,
+                           const double* al, const double* be) {
   if (c->ms.ly > 1) {   // two side lines per work-group (q = 2)
-    launch_march_t<T, VW, 2, MODE, FIRST, true>(c, F0, F1, O0, O1, Yv, diag);
+    launch_march_t<T, VW, 2, MODE, FIRST, true>(c, F0, F1, O0, O1, Yv, diag, al, be);
     return;
   }
   switch (c->ms.q) {
-    case 1: launch_march_t<T, VW, 1, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag); break;
-    case 2: launch_march_t<T, VW, 2, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag); break;
-    default: launch_march_t<T, VW, 4, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag); break;
+    case 1: launch_march_t<T, VW, 1, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag, al, be); break;
+    case 2: launch_march_t<T, VW, 2, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag, al, be); break;
+    default: launch_march_t<T, VW, 4, MODE, FIRST, false>(c, F0, F1, O0, O1, Yv, diag, al, be); break;
   }
 }
 
 template <int MODE, bool FIRST>
-static hipError_t launch_march(ope_ctx* c, const void* F0, const void* F1, void* O0, void* O1, void* Yv) {
+static hipError_t launch_march(ope_ctx* c, const void* F0, const void* F1, void* O0, void* O1, void* Yv,
+                               const double* al, const double* be) {
   if (c->prec == OPE_FP64) {
     using T = double;
     if (c->vw == 2)
-      launch_march_q<T, 2, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag);
+      launch_march_q<T, 2, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag, al, be);
     else
-      launch_march_q<T, 1, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag);
+      launch_march_q<T, 1, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag, al, be);
   } else {
     using T = float;
     if (c->vw == 4)
-      launch_march_q<T, 4, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32);
+      launch_march_q<T, 4, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32, al, be);
     else if (c->vw == 2)
-      launch_march_q<T, 2, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32);
+      launch_march_q<T, 2, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32, al, be);
     else
-      launch_march_q<T, 1, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32);
+      launch_march_q<T, 1, MODE, FIRST>(c, (const T*)F0, (const T*)F1, (T*)O0, (T*)O1, (T*)Yv, c->diag32, al, be);
   }
   return hipGetLastError();
 }
@@ -847,35 +884,52 @@ int64_t march_rows(const ope_ctx* c) {
 
 hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Yo) {
   ProfScope ps(c, OPE_KERNEL_STENCIL);
-  return launch_march<SW_APPLY, false>(c, X, nullptr, Yo, nullptr, nullptr);
+  return launch_march<SW_APPLY, false>(c, X, nullptr, Yo, nullptr, nullptr, c->alpha, c->beta);
 }
 
 hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, void* pnew, int first) {
   ProfScope ps(c, OPE_KERNEL_CG_SWEEP_A);
-  if (first) return launch_march<SW_PAP, true>(c, r, pold, nullptr, pnew, nullptr);
-  return launch_march<SW_PAP, false>(c, r, pold, nullptr, pnew, nullptr);
+  if (first) return launch_march<SW_PAP, true>(c, r, pold, nullptr, pnew, nullptr, c->alpha, c->beta);
+  return launch_march<SW_PAP, false>(c, r, pold, nullptr, pnew, nullptr, c->alpha, c->beta);
 }
 
-hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew, void* y) {
-  ProfScope ps(c, OPE_KERNEL_CG_SWEEP_B);
-  return launch_march<SW_UPDATE, false>(c, r, p, rnew, nullptr, y);
+hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew, const double* alpha, void* y,
+                            const void* pprev, const double* alpha_prev) {
+  // profiled as sweep B (both forms), or the odd form alone
+  ProfScope ps(c, (y && c->prof_kernel == OPE_KERNEL_CG_SWEEP_B_Y) ? OPE_KERNEL_CG_SWEEP_B_Y : OPE_KERNEL_CG_SWEEP_B);
+  if (y) return launch_march<SW_UPDATE_Y, false>(c, r, p, rnew, const_cast<void*>(pprev), y, alpha, alpha_prev);
+  return launch_march<SW_UPDATE, false>(c, r, p, rnew, nullptr, nullptr, alpha, c->beta);
 }
 
-hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols, double* out, int mode) {
+hipError_t launch_y_flush(ope_ctx* c, hipStream_t s, void* y, const void* p, const double* alpha) {
+  const uint64_t count = (uint64_t)c->n * (uint64_t)c->N;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((count + OPE_WG - 1) / OPE_WG, 8192);
+  if (c->prec == OPE_FP64)
+    hipLaunchKernelGGL((k_y_flush<double>), dim3(grid), dim3(OPE_WG), 0, s, (double*)y, (const double*)p, alpha, count,
+                       (uint32_t)c->N);
+  else
+    hipLaunchKernelGGL((k_y_flush<float>), dim3(grid), dim3(OPE_WG), 0, s, (float*)y, (const float*)p, alpha, count,
+                       (uint32_t)c->N);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols, double* out, int mode,
+                              double* alpha) {
+  if (!alpha) alpha = c->alpha;
   if (ncols <= 128 && nrows * ncols <= (int64_t)1 << 17) {
     const uint32_t nr = (uint32_t)nrows, nc = (uint32_t)ncols;
     switch (mode) {
       case RED_PLAIN:
-        hipLaunchKernelGGL((k_reduce_few<RED_PLAIN>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out, c->alpha,
+        hipLaunchKernelGGL((k_reduce_few<RED_PLAIN>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out, alpha,
                            c->beta, c->rho, c->target, c->active, c->sc);
         break;
       case RED_CG_ALPHA:
         hipLaunchKernelGGL((k_reduce_few<RED_CG_ALPHA>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out,
-                           c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                           alpha, c->beta, c->rho, c->target, c->active, c->sc);
         break;
       default:
         hipLaunchKernelGGL((k_reduce_few<RED_CG_BETA>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out,
-                           c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                           alpha, c->beta, c->rho, c->target, c->active, c->sc);
         break;
     }
     return hipGetLastError();
@@ -891,15 +945,15 @@ hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int
   switch (mode) {
     case RED_PLAIN:
       hipLaunchKernelGGL((k_reduce_cols<RED_PLAIN>), grid, blk, 0, c->stream, part, (uint32_t)nrows, (uint32_t)ncols,
-                         out, c->stage, c->counters, c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                         out, c->stage, c->counters, alpha, c->beta, c->rho, c->target, c->active, c->sc);
       break;
     case RED_CG_ALPHA:
       hipLaunchKernelGGL((k_reduce_cols<RED_CG_ALPHA>), grid, blk, 0, c->stream, part, (uint32_t)nrows, (uint32_t)ncols,
-                         out, c->stage, c->counters, c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                         out, c->stage, c->counters, alpha, c->beta, c->rho, c->target, c->active, c->sc);
       break;
     default:
       hipLaunchKernelGGL((k_reduce_cols<RED_CG_BETA>), grid, blk, 0, c->stream, part, (uint32_t)nrows, (uint32_t)ncols,
-                         out, c->stage, c->counters, c->alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                         out, c->stage, c->counters, alpha, c->beta, c->rho, c->target, c->active, c->sc);
       break;
   }
   return hipGetLastError();
@@ -963,18 +1017,20 @@ hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo
   if (mode == SW_PAP) {
     if (first) launch_mb_t<SW_PAP, true>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);
     else launch_mb_t<SW_PAP, false>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);
+  } else if (mode == SW_UPDATE_Y) {
+    launch_mb_t<SW_UPDATE_Y, false>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);
   } else {
     launch_mb_t<SW_UPDATE, false>(s, prec, vw, q, halo, ln, jobs, njobs, total_wgs);   // no first-iteration form
   }
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_batched(hipStream_t s, int mode, const ReduceJob* jobs, uint32_t njobs) {
+hipError_t launch_reduce_batched(hipStream_t s, int mode, int par, const ReduceJob* jobs, uint32_t njobs) {
   if (njobs == 0) return hipSuccess;
   if (mode == RED_CG_ALPHA)
-    hipLaunchKernelGGL((k_reduce_batched<RED_CG_ALPHA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs);
+    hipLaunchKernelGGL((k_reduce_batched<RED_CG_ALPHA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs, (uint32_t)par);
   else
-    hipLaunchKernelGGL((k_reduce_batched<RED_CG_BETA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs);
+    hipLaunchKernelGGL((k_reduce_batched<RED_CG_BETA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs, (uint32_t)par);
   return hipGetLastError();
 }
 

@@ -122,19 +122,32 @@ ope_status phase_residual(ope_ctx* c, const void* Uv) {
 }
 
 // One CG iteration (two sweeps and their fixed-order reductions) with the
-// buffer roles of iteration `it` (r and p alternate between two buffers).
+// buffer roles of iteration `it` (r and p alternate between two buffers, alpha
+// between the two halves of its array).  The y term of an even iteration is
+// added by the next iteration's sweep B, together with its own.
 hipError_t cg_iteration(ope_ctx* c, int it) {
   void* r_cur = c->Rb[it & 1];
   void* r_nxt = c->Rb[(it + 1) & 1];
   void* p_old = (it & 1) ? c->Pb : c->HU;    // never read on the first iteration
   void* p_new = (it & 1) ? c->HU : c->Pb;
+  double* a_cur = c->alpha + (size_t)(it & 1) * c->N;
+  double* a_prev = c->alpha + (size_t)((it + 1) & 1) * c->N;
   const int N = (int)c->N;
   const int first = it == 0;
   hipError_t e;
   if ((e = launch_cg_pap(c, r_cur, p_old, p_new, first)) != hipSuccess) return e;
-  if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA)) != hipSuccess) return e;
-  if ((e = launch_cg_update(c, r_cur, p_new, r_nxt, c->Y)) != hipSuccess) return e;
-  return launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA);
+  if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA, a_cur)) != hipSuccess) return e;
+  if (it & 1) e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, c->Y, p_old, a_prev);
+  else e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, nullptr, nullptr, nullptr);
+  if (e != hipSuccess) return e;
+  return launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA, a_cur);
+}
+
+// After `its` CG iterations: when the last one was even, add its deferred y
+// term (its p is in Pb, its alpha in the first half), on stream s.
+hipError_t cg_flush(ope_ctx* c, int32_t its, hipStream_t s) {
+  if (its <= 0 || (its & 1) == 0) return hipSuccess;
+  return launch_y_flush(c, s, c->Y, c->Pb, c->alpha);
 }
 
 void drop_graphs(ope_ctx* c) {
@@ -242,6 +255,7 @@ ope_status run_cg(ope_ctx* c, int32_t max_iter, int32_t* iters, bool* all_done) 
       break;
     }
   }
+  HIPCHK(cg_flush(c, it, c->stream));
   *iters = it;
   *all_done = done;
   return OPE_OK;
@@ -542,10 +556,10 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
         jb.F0 = c->Rb[par];
         jb.F1 = upd ? p_new : p_old;
         jb.O0 = upd ? c->Rb[par ^ 1] : nullptr;
-        jb.O1 = upd ? nullptr : p_new;
-        jb.Yv = upd ? c->Y : nullptr;
-        jb.alpha = c->alpha;
-        jb.beta = c->beta;
+        jb.O1 = upd ? (par ? p_old : nullptr) : p_new;     // odd sweep B: p of the previous iteration
+        jb.Yv = (upd && par) ? c->Y : nullptr;
+        jb.alpha = c->alpha + (size_t)par * c->N;
+        jb.beta = (upd && par) ? c->alpha : c->beta;       // odd sweep B: the previous iteration's alpha
         jb.active = c->active;
         jb.diag = c->prec == OPE_FP64 ? (const void*)c->diag : (const void*)c->diag32;
         jb.g = c->g;
@@ -597,10 +611,11 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
   }
   auto sweep = [&](int mode, int par, int first) -> hipError_t {
     hipError_t er;
+    const int kmode = (mode == BATCH_SW_UPDATE && par) ? BATCH_SW_UPDATE_Y : mode;
     if (cls.size() == 1) {
       const uint32_t nc = (uint32_t)cls[0].idx.size();
       const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
-      return launch_march_batched(s, cls[0].prec, cls[0].vw, cls[0].q, cls[0].halo, cls[0].ln, mode, first,
+      return launch_march_batched(s, cls[0].prec, cls[0].vw, cls[0].q, cls[0].halo, cls[0].ln, kmode, first,
                                   b->d_mjobs + cls_off[0] + v * nc, nc, cls_total[0]);
     }
     if ((er = hipEventRecord(b->cg_ev, s)) != hipSuccess) return er;
@@ -609,7 +624,7 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
       const uint32_t nc = (uint32_t)cls[c].idx.size();
       const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
       if ((er = hipStreamWaitEvent(cs, b->cg_ev, 0)) != hipSuccess) return er;
-      if ((er = launch_march_batched(cs, cls[c].prec, cls[c].vw, cls[c].q, cls[c].halo, cls[c].ln, mode, first,
+      if ((er = launch_march_batched(cs, cls[c].prec, cls[c].vw, cls[c].q, cls[c].halo, cls[c].ln, kmode, first,
                                      b->d_mjobs + cls_off[c] + v * nc, nc, cls_total[c])) != hipSuccess)
         return er;
       if ((er = hipEventRecord(b->cls_events[c], cs)) != hipSuccess) return er;
@@ -621,9 +636,9 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
   for (int k = 0; k < K; ++k, ++*it) {
     const int par = *it & 1, first = *it == 0;
     if ((e = sweep(BATCH_SW_PAP, par, first)) != hipSuccess) return e;
-    if ((e = launch_reduce_batched(s, RED_CG_ALPHA, b->d_rjobs, M)) != hipSuccess) return e;
+    if ((e = launch_reduce_batched(s, RED_CG_ALPHA, par, b->d_rjobs, M)) != hipSuccess) return e;
     if ((e = sweep(BATCH_SW_UPDATE, par, first)) != hipSuccess) return e;
-    if ((e = launch_reduce_batched(s, RED_CG_BETA, b->d_rjobs, M)) != hipSuccess) return e;
+    if ((e = launch_reduce_batched(s, RED_CG_BETA, par, b->d_rjobs, M)) != hipSuccess) return e;
   }
   if ((e = launch_gather_flags(s, b->d_rjobs, M)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int32_t) * foff, hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -731,7 +746,8 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
   for (int i = 0; i < P; ++i) {
     if (!go[i]) continue;
     ope_ctx* c = b->ctx[i];
-    ope_status st = phase_update(c, U[i], tau);
+    ope_status st = cg_flush(c, bs.it[i], c->stream) == hipSuccess ? OPE_OK : OPE_EHIP;   // shared CG: synchronised
+    if (st == OPE_OK) st = phase_update(c, U[i], tau);
     if (st == OPE_OK && hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
       st = OPE_EHIP;
     if (st != OPE_OK) {
@@ -933,7 +949,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   ok &= dalloc(&c->A, N * N) == hipSuccess;
   ok &= dalloc(&c->B, N * N) == hipSuccess;
   ok &= dalloc(&c->Wsm, N * N) == hipSuccess;
-  ok &= dalloc(&c->alpha, N) == hipSuccess;
+  ok &= dalloc(&c->alpha, 2 * N) == hipSuccess;   // one half per CG iteration parity
   ok &= dalloc(&c->beta, N) == hipSuccess;
   ok &= dalloc(&c->rho, N) == hipSuccess;
   ok &= dalloc(&c->target, N) == hipSuccess;

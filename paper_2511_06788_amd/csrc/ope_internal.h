@@ -98,7 +98,7 @@ struct ope_ctx {
   NsState* hns;                 // pinned
   // FP32 copies used by the mixed-precision products
   float *Lam32, *Linv32, *Sb32, *Z32;
-  // per-column CG state
+  // per-column CG state (alpha: 2N, one half per iteration parity)
   double *alpha, *beta, *rho, *target, *cnorm2, *rcol, *rho0;
   int32_t* active;
   // reductions
@@ -180,13 +180,19 @@ int64_t march_rows(const ope_ctx* c);              // partial rows written by th
 // CG iteration halves (see k_stencil.hip)
 // sweep A: p = r + beta p_old (p = r when first) written to pnew, p^T H p partials
 hipError_t launch_cg_pap(ope_ctx* c, const void* r, const void* pold, void* pnew, int first);
-// sweep B: y += alpha p, rnew = r - alpha H p, rnew^T rnew partials
-hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew, void* y);
+// sweep B: rnew = r - alpha H p, rnew^T rnew partials; with y given (odd
+// iterations) also y += alpha_prev pprev + alpha p
+hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew, const double* alpha, void* y,
+                            const void* pprev, const double* alpha_prev);
+// y += alpha p (per column) on stream s: the deferred y term of a CG that
+// stopped on an even iteration
+hipError_t launch_y_flush(ope_ctx* c, hipStream_t s, void* y, const void* p, const double* alpha);
 hipError_t launch_cg_setup_reduce(ope_ctx* c, int mode);
 
 // column sums of partials: out[j] = sum_w part[w*ncols + j], fixed order
+// (the CG modes write alpha, default c->alpha)
 hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols,
-                              double* out, int mode);
+                              double* out, int mode, double* alpha = nullptr);
 enum { RED_PLAIN = 0, RED_CG_ALPHA = 1, RED_CG_BETA = 2 };
 
 // inner matrix out = A^T B over `rows` rows (partials into c->part, then reduced)
@@ -231,7 +237,9 @@ hipError_t launch_renorm_matrix(ope_ctx* c, const double* C, float* Z32);
 hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
 
-// Batched CG sweeps (k_stencil.hip): one work item range per problem.
+// Batched CG sweeps (k_stencil.hip): one work item range per problem.  The
+// fields are the march kernel's arguments (for the odd-iteration sweep B,
+// O1 is p of the previous iteration and beta that iteration's alpha).
 struct MarchJob {
   const void* F0;
   const void* F1;
@@ -254,18 +262,19 @@ struct MarchJob {
 struct ReduceJob {
   const double* part;
   uint32_t nrows, ncols;
-  double *alpha, *beta, *rho;
+  double *alpha, *beta, *rho;   // alpha: 2 ncols (one half per iteration parity)
   const double* target;
   int32_t* active;
   OpeScalars* sc;
   int32_t* flags_out;      // gather destination (N values)
 };
-enum { BATCH_SW_PAP = 1, BATCH_SW_UPDATE = 2 };   // sweep A, sweep B
+// sweep A, sweep B of an even iteration, sweep B of an odd one (with the y update)
+enum { BATCH_SW_PAP = 1, BATCH_SW_UPDATE = 2, BATCH_SW_UPDATE_Y = 3 };
 // halo: the class's x lines are split into several segments (nxs > 1);
 // ln: its work-groups take two side lines, one per pass (ly = 2)
 hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo, int ln, int mode, int first,
                                 const MarchJob* jobs, uint32_t njobs, uint32_t total_wgs);
-hipError_t launch_reduce_batched(hipStream_t s, int mode, const ReduceJob* jobs, uint32_t njobs);
+hipError_t launch_reduce_batched(hipStream_t s, int mode, int par, const ReduceJob* jobs, uint32_t njobs);
 hipError_t launch_gather_flags(hipStream_t s, const ReduceJob* jobs, uint32_t njobs);
 // whether a context's CG column sums fit the one-work-group reduction
 bool reduce_few_fits(const ope_ctx* c);

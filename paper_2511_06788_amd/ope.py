@@ -85,6 +85,7 @@ OPE_KERNEL_CG_SWEEP_B = 2
 OPE_KERNEL_GRAM = 3
 OPE_KERNEL_ROWMM = 4
 OPE_KERNEL_SMALL = 5
+OPE_KERNEL_CG_SWEEP_B_Y = 6
 
 _lib = None
 

@@ -67,13 +67,25 @@ def cmd_pmc(args):
     copy_kib = args.copy_bytes / 1024.0
     fscale = copy_kib / cf
     wscale = copy_kib / cw
-    f, nf, af = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel, args.min_frac)
-    w, nw, aw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel, args.min_frac)
+    # several --kernel patterns: kernels that alternate one launch per
+    # iteration (the two forms of a sweep); the figures are their mean
+    fs_, ws_ = [], []
+    nf = af = nw = aw = 0
+    for pat in args.kernel:
+        f1, n1, a1 = counter_per_dispatch(args.fetch, "FETCH_SIZE", pat, args.min_frac)
+        w1, n2, a2 = counter_per_dispatch(args.write, "WRITE_SIZE", pat, args.min_frac)
+        fs_.append(f1)
+        ws_.append(w1)
+        nf, af, nw, aw = nf + n1, af + a1, nw + n2, aw + a2
+    f = sum(fs_) / len(fs_)
+    w = sum(ws_) / len(ws_)
     blk = args.n * args.N * 8
     algo_read = args.reads * blk + 8 * args.n
     algo_write = args.writes * blk
+    per_kernel = [{"kernel_regex": k, "fetch_kib": a * fscale, "write_kib": b * wscale}
+                  for k, a, b in zip(args.kernel, fs_, ws_)]
     rec = {
-        "kernel_regex": args.kernel, "n": args.n, "N": args.N,
+        "kernel_regex": args.kernel, "per_kernel": per_kernel, "n": args.n, "N": args.N,
         "fetch_kib_per_dispatch": f * fscale, "write_kib_per_dispatch": w * wscale, "copy_scale": 1.0,
         "raw_fetch_kib": f, "raw_write_kib": w, "fetch_scale": fscale, "write_scale": wscale,
         "dispatches": [nf, nw], "dispatches_all": [af, aw], "min_frac": args.min_frac,
@@ -95,6 +107,9 @@ def cmd_pmc(args):
         f"| written / algorithmic | {w * wscale * 1024 / max(algo_write, 1):.2f} |",
         f"| dispatches averaged (of all) | {nf} of {af} / {nw} of {aw} |",
         "",
+    ] + ([f"Per kernel (the table gives their mean): " + "; ".join(
+        f"`{k['kernel_regex']}` reads {k['fetch_kib'] * 1024:.4g} B, writes {k['write_kib'] * 1024:.4g} B"
+        for k in per_kernel), ""] if len(per_kernel) > 1 else []) + [
         f"Averaged: the dispatches whose counter is at least {args.min_frac:g} of the largest (launches past the last "
         "converged column of a CG chunk return at once and move almost nothing).",
     ] + ([""] + [args.note] if args.note else [])))
@@ -112,13 +127,14 @@ def main(argv=None):
     p = sub.add_parser("pmc")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
-    p.add_argument("--kernel", required=True)
+    p.add_argument("--kernel", required=True, action="append",
+                   help="kernel name pattern; repeat for kernels that alternate per iteration (mean taken)")
     p.add_argument("--copy-kernel", default="copyBuffer")
     p.add_argument("--copy-bytes", type=int, default=1 << 30)
     p.add_argument("--n", type=int, required=True)
     p.add_argument("--N", type=int, required=True)
-    p.add_argument("--reads", type=int, default=3)
-    p.add_argument("--writes", type=int, default=2)
+    p.add_argument("--reads", type=float, default=3)
+    p.add_argument("--writes", type=float, default=2)
     p.add_argument("--source", required=True)
     p.add_argument("--cmd", required=True)
     p.add_argument("--title", default="")

@@ -360,16 +360,123 @@ __global__ __launch_bounds__(256) void k_sqmm(const double* __restrict__ A, int 
   if (threadIdx.x == 0) res[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
+// Wide Grams from LDS (both sides >= 128 columns, 16-byte aligned rows):
+// work-group tile 128 x 128, each wave a 64 x 64 sub-tile (4 x 4 MFMA blocks).
+// The work-group stages KC-row panels of both operands in LDS (double
+// buffered; the next panel's 16-byte loads are in flight while the current one
+// is consumed), so each operand element crosses L2 once per work-group
+// instead of once per wave: at the MFMA rate the 64 x 64-tile Gram needs more
+// L1-to-L2 traffic than the chip sustains.
+template <int KIND> struct PanelRows { static constexpr int KC = Mk<KIND>::KSTEP < 16 ? 16 : Mk<KIND>::KSTEP; };
+
+template <typename TI, int KIND>
+__global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint64_t lda, uint32_t na,
+                                                  const TI* __restrict__ B, uint64_t ldb, uint32_t nb,
+                                                  uint32_t rows, uint32_t rows_per_split, double* __restrict__ part) {
+  using M = Mk<KIND>;
+  using acc_t = typename M::acc_t;
+  constexpr int KC = PanelRows<KIND>::KC;
+  constexpr int VPC = 16 / (int)sizeof(TI);            // values per 16-byte chunk
+  constexpr int CPR = GT2 / VPC;                        // chunks per panel row
+  constexpr int CPT = KC * CPR / 256;                   // chunks per thread and operand
+  static_assert(CPT * 256 == KC * CPR, "panel chunks must divide the work-group");
+  __shared__ __align__(16) TI pa[2][KC][GT2];
+  __shared__ __align__(16) TI pb[2][KC][GT2];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t wi = (wave >> 1) * GW2, wj = (wave & 1u) * GW2;     // the wave's sub-tile in the tile
+  const uint32_t i0 = blockIdx.y * GT2, j0 = blockIdx.x * GT2;
+  const uint32_t ks = blockIdx.z;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  const uint32_t r0 = ks * rows_per_split;
+  const uint32_t r1 = min(rows, r0 + rows_per_split);
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = zero_acc<acc_t>();
+  // 16-byte chunks of the panel starting at row p (zero outside the rows and
+  // columns), as raw 4 x 32-bit vectors
+  typedef unsigned int Chunk __attribute__((ext_vector_type(4)));
+  Chunk ca[CPT], cb[CPT];
+  auto load = [&](uint32_t p) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t row = c / CPR, col = (c % CPR) * VPC;
+      const uint32_t gr = p + row;
+      const bool rok = gr < r1;
+      const Chunk z = {0u, 0u, 0u, 0u};
+      ca[u] = (rok && i0 + col < na) ? *reinterpret_cast<const Chunk*>(A + (uint64_t)gr * lda + i0 + col) : z;
+      cb[u] = (rok && j0 + col < nb) ? *reinterpret_cast<const Chunk*>(B + (uint64_t)gr * ldb + j0 + col) : z;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t row = c / CPR, col = (c % CPR) * VPC;
+      *reinterpret_cast<Chunk*>(&pa[buf][row][col]) = ca[u];
+      *reinterpret_cast<Chunk*>(&pb[buf][row][col]) = cb[u];
+    }
+  };
+  const uint32_t npan = (r1 > r0) ? (r1 - r0 + KC - 1) / KC : 0;
+  if (npan > 0) {
+    load(r0);
+    store(0);
+  }
+  __syncthreads();
+  for (uint32_t t = 0; t < npan; ++t) {
+    const int buf = (int)(t & 1u);
+    if (t + 1 < npan) load(r0 + (t + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC / M::KSTEP; ++kk) {
+      TI av[4][M::KPL], bv[4][M::KPL];
+#pragma unroll
+      for (int e = 0; e < M::KPL; ++e) {
+        const uint32_t row = kk * M::KSTEP + kr * M::KPL + e;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          av[a][e] = pa[buf][row][wi + a * 16 + ci];
+          bv[a][e] = pb[buf][row][wj + a * 16 + ci];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mma<KIND, TI>(av[a], bv[b], acc[a][b]);
+    }
+    if (t + 1 < npan) store(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = part + (uint64_t)ks * na * nb;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = i0 + wi + a * 16 + M::drow(kr, r);
+        const uint32_t j = j0 + wj + b * 16 + ci;
+        if (i < na && j < nb) out[(uint64_t)i * nb + j] = (double)acc[a][b][r];
+      }
+}
+
 template <typename TI, int KIND>
 hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int64_t ldb, int nb, int64_t rows,
                   double* out) {
-  // FP64 MFMA keeps the 64 x 64 tile: its 16 accumulators per wave cost more
-  // occupancy than the operand reuse gains (measured)
-  const bool wide = KIND != MK_F64 && na >= GT2 && nb >= GT2;
+  // 128 x 128 tiles from LDS when both sides are wide and rows split into
+  // whole 16-byte chunks; else the wide tile from global memory (FP32 and
+  // BF16 kinds), else 64 x 64 tiles
+  constexpr int64_t VPC = 16 / (int64_t)sizeof(TI);
+  const bool lds = na >= GT2 && nb >= GT2 && (reinterpret_cast<uintptr_t>(A) % 16) == 0 &&
+                   (reinterpret_cast<uintptr_t>(B) % 16) == 0 && lda % VPC == 0 && ldb % VPC == 0 &&
+                   na % VPC == 0 && nb % VPC == 0;
+  const bool wide = lds || (KIND != MK_F64 && na >= GT2 && nb >= GT2);
   const int tile = wide ? GT2 : GT;
   const uint32_t ti = (uint32_t)((na + tile - 1) / tile), tj = (uint32_t)((nb + tile - 1) / tile);
-  // about 1024 work-groups in total, within the partial buffer
-  int64_t ks = 1024 / (int64_t)(ti * tj);
+  // about 1024 work-groups in total (512, two per CU, for the LDS kernel),
+  // within the partial buffer
+  int64_t ks = (lds ? 512 : 1024) / (int64_t)(ti * tj);
   if (ks < 1) ks = 1;
   const int64_t max_ks = c->part_cap / ((int64_t)na * nb);
   if (ks > max_ks) ks = max_ks;
@@ -382,7 +489,11 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
   if (ks < 1) ks = 1;
   {
     ProfScope ps(c, OPE_KERNEL_GRAM);
-    if (wide)
+    if (lds)
+      hipLaunchKernelGGL((k_gram_lds<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A,
+                         (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps,
+                         c->part);
+    else if (wide)
       hipLaunchKernelGGL((k_gram_wide<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A,
                          (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps,
                          c->part);

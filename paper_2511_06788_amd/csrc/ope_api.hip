@@ -913,7 +913,9 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
 
   const int64_t blk = n * N;
   const int64_t gtiles = ((N + 63) / 64) * ((N + 63) / 64);
-  const int64_t gram_parts = ((1024 + gtiles - 1) / gtiles) * N * N;
+  const int64_t ltiles = ((N + 127) / 128) * ((N + 127) / 128);   // 128 x 128 tiles of the LDS Gram
+  int64_t gram_parts = ((1024 + gtiles - 1) / gtiles) * N * N;
+  if (((512 + ltiles - 1) / ltiles) * N * N > gram_parts) gram_parts = ((512 + ltiles - 1) / ltiles) * N * N;
   const int64_t row_parts = ((n + 63) / 64) * N;
   int64_t pc = (int64_t)c->stream_wgs * 2 * N;
   if (march_rows(c) * N > pc) pc = march_rows(c) * N;

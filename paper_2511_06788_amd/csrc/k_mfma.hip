@@ -48,6 +48,10 @@ template <> struct Mk<MK_BF16> {
   __device__ static uint32_t drow(uint32_t kr, int r) { return 4u * kr + (uint32_t)r; }
 };
 
+// Contraction indices per LDS panel of the staged kernels: at least 16, and a
+// whole MFMA contraction step.
+template <int KIND> struct PanelRows { static constexpr int KC = Mk<KIND>::KSTEP < 16 ? 16 : Mk<KIND>::KSTEP; };
+
 // One MFMA with operands given as KPL values per lane (in the input type).
 template <int KIND, typename TI>
 __device__ __forceinline__ typename Mk<KIND>::acc_t mma(const TI (&a)[Mk<KIND>::KPL], const TI (&b)[Mk<KIND>::KPL],
@@ -289,6 +293,148 @@ __global__ __launch_bounds__(256) void k_rowmm(const TI* X0, const TI* __restric
   }
 }
 
+// Row-block products from LDS (N a multiple of the 16-byte chunk, aligned
+// blocks): work-group tile 128 rows x 128 columns, each wave 64 x 64 (4 x 4
+// MFMA blocks).  Panels of KC contraction indices are staged in LDS, double
+// buffered: X's rows (read as 16-byte chunks) are stored transposed, Xt[k][row],
+// so that the MFMA operand reads of both panels are contiguous across lanes,
+// and the KC rows of M beside them.  M is read once per work-group instead of
+// once per wave and 64-row tile.
+constexpr int RT2 = 128;    // rows per work-group tile
+
+template <typename TI, int KIND, int NSRC>
+__global__ __launch_bounds__(256, 2) void k_rowmm_lds(const TI* X0, const TI* __restrict__ M0, const TI* X1,
+                                                   const TI* __restrict__ M1, const TI* Cm, double cbeta,
+                                                   double ascale, TI* Out, uint32_t n, uint32_t N, int want_colsq,
+                                                   int predicated, const OpeScalars* __restrict__ sc,
+                                                   double* __restrict__ part) {
+  using MK = Mk<KIND>;
+  using acc_t = typename MK::acc_t;
+  constexpr int KC = PanelRows<KIND>::KC;
+  constexpr int VPC = 16 / (int)sizeof(TI);
+  constexpr int XC = KC / VPC;                        // chunks per X row and panel
+  constexpr int XCT = RT2 * XC / 256;                 // X chunks per thread
+  constexpr int MCR = CT / VPC;                       // chunks per M panel row
+  constexpr int MCT = KC * MCR / 256;                 // M chunks per thread
+  static_assert(XCT * 256 == RT2 * XC && MCT * 256 == KC * MCR, "panel chunks must divide the work-group");
+  typedef unsigned int Chunk __attribute__((ext_vector_type(4)));
+  union ChunkV {
+    Chunk c;
+    TI v[VPC];
+  };
+  __shared__ __align__(16) TI xt[2][KC][RT2];
+  __shared__ __align__(16) TI mp[2][KC][CT];
+  __shared__ double colsq[2][CT];
+  if (predicated && sc->err != 0) return;        // a failed small solve leaves the block untouched
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t wr = wave >> 1, wc = wave & 1u;
+  const uint32_t row0 = blockIdx.x * RT2, col0 = blockIdx.y * CT;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = zero_acc<acc_t>();
+  const uint32_t kpan = (N + KC - 1) / KC;          // panels per source
+  const uint32_t npan = NSRC * kpan;
+  ChunkV cx[XCT], cm[MCT];
+  const Chunk z = {0u, 0u, 0u, 0u};
+  auto load = [&](uint32_t t) {
+    const TI* X = t < kpan ? X0 : X1;
+    const TI* M = t < kpan ? M0 : M1;
+    const uint32_t k0 = (t < kpan ? t : t - kpan) * KC;
+#pragma unroll
+    for (int u = 0; u < XCT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t r = c / XC, kc = (c % XC) * VPC;
+      const uint32_t gr = row0 + r;
+      cx[u].c = (gr < n && k0 + kc < N) ? *reinterpret_cast<const Chunk*>(X + (uint64_t)gr * N + k0 + kc) : z;
+    }
+#pragma unroll
+    for (int u = 0; u < MCT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t kk = c / MCR, col = (c % MCR) * VPC;
+      cm[u].c = (k0 + kk < N && col0 + col < N) ? *reinterpret_cast<const Chunk*>(M + (uint64_t)(k0 + kk) * N + col0 + col)
+                                               : z;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < XCT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t r = c / XC, kc = (c % XC) * VPC;
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) xt[buf][kc + e][r] = cx[u].v[e];
+    }
+#pragma unroll
+    for (int u = 0; u < MCT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t kk = c / MCR, col = (c % MCR) * VPC;
+      *reinterpret_cast<Chunk*>(&mp[buf][kk][col]) = cm[u].c;
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  for (uint32_t t = 0; t < npan; ++t) {
+    const int buf = (int)(t & 1u);
+    if (t + 1 < npan) load(t + 1);
+#pragma unroll
+    for (int kk = 0; kk < KC / MK::KSTEP; ++kk) {
+      TI av[4][MK::KPL], bv[4][MK::KPL];
+#pragma unroll
+      for (int e = 0; e < MK::KPL; ++e) {
+        const uint32_t k = kk * MK::KSTEP + kr * MK::KPL + e;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          av[a][e] = xt[buf][k][wr * 64 + a * 16 + ci];
+          bv[a][e] = mp[buf][k][wc * 64 + a * 16 + ci];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mma<KIND, TI>(av[a], bv[b], acc[a][b]);
+    }
+    if (t + 1 < npan) store(buf ^ 1);
+    __syncthreads();
+  }
+  // every wave has read all of its rows (the last panel is in LDS) before any
+  // wave writes: Out may alias X0 (in-place Step 4)
+  double sq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t row = row0 + wr * 64 + a * 16 + MK::drow(kr, r);
+        const uint32_t col = col0 + wc * 64 + b * 16 + ci;
+        if (row < n && col < N) {
+          const uint64_t o = (uint64_t)row * N + col;
+          TI v = (TI)(ascale * (double)acc[a][b][r]);
+          if (cbeta != 0.0) v += (TI)cbeta * Cm[o];
+          Out[o] = v;
+          sq[b] += (double)v * (double)v;
+        }
+      }
+  if (!want_colsq) return;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    sq[b] += __shfl_xor(sq[b], 16);
+    sq[b] += __shfl_xor(sq[b], 32);
+  }
+  if (kr == 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) colsq[wr][wc * 64 + b * 16 + ci] = sq[b];
+  }
+  __syncthreads();
+  if (threadIdx.x < CT) {
+    const uint32_t col = col0 + threadIdx.x;
+    if (col < N) part[(uint64_t)blockIdx.x * N + col] = colsq[0][threadIdx.x] + colsq[1][threadIdx.x];
+  }
+}
+
 // Square FP64 products of N x N matrices (the small solves for large N):
 // D = alpha op(A) op(B) + beta C + gamma I, op = transpose when ta / tb is
 // set.  Work-group tile 64 x 64 (4 waves of 32 x 32), operands straight from
@@ -367,7 +513,6 @@ __global__ __launch_bounds__(256) void k_sqmm(const double* __restrict__ A, int 
 // is consumed), so each operand element crosses L2 once per work-group
 // instead of once per wave: at the MFMA rate the 64 x 64-tile Gram needs more
 // L1-to-L2 traffic than the chip sustains.
-template <int KIND> struct PanelRows { static constexpr int KC = Mk<KIND>::KSTEP < 16 ? 16 : Mk<KIND>::KSTEP; };
 
 template <typename TI, int KIND>
 __global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint64_t lda, uint32_t na,
@@ -510,11 +655,23 @@ template <typename TI, int KIND>
 hipError_t rowmm_t(ope_ctx* c, const TI* X0, const TI* M0, const TI* X1, const TI* M1, const TI* Cm, double cbeta,
                    double ascale, TI* Out, int want_colsq, int predicated, int64_t* nparts) {
   const uint32_t n = (uint32_t)c->n, N = (uint32_t)c->N;
-  const uint32_t gr = (n + RT - 1) / RT, gc = (N + CT - 1) / CT;
+  // LDS-staged panels when every operand row splits into whole, aligned 16-byte chunks
+  constexpr uint32_t VPC = 16 / (uint32_t)sizeof(TI);
+  auto al16 = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) % 16) == 0; };
+  const bool lds = N % VPC == 0 && al16(X0) && al16(M0) && al16(X1) && al16(M1);
+  const uint32_t rt = lds ? RT2 : RT;
+  const uint32_t gr = (n + rt - 1) / rt, gc = (N + CT - 1) / CT;
   if (gc != 1 && (Out == X0 || Out == X1)) return hipErrorInvalidValue;  // in place needs one column tile
   if (want_colsq && (int64_t)gr * N > c->part_cap) return hipErrorInvalidValue;
   ProfScope ps(c, OPE_KERNEL_ROWMM);
-  if (X1)
+  if (lds) {
+    if (X1)
+      hipLaunchKernelGGL((k_rowmm_lds<TI, KIND, 2>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
+                         ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
+    else
+      hipLaunchKernelGGL((k_rowmm_lds<TI, KIND, 1>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
+                         ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
+  } else if (X1)
     hipLaunchKernelGGL((k_rowmm<TI, KIND, 2>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
                        ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
   else

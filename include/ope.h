@@ -309,8 +309,8 @@ ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double 
 ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
 /* Autotuner: for every bucket of problems (grid edges and vector-column count
  * in steps of 8) time short CG runs of the first problem over the sweep shapes
- * (passes per plane 1/2 or the two-line tile, work-group order, non-temporal
- * stores, column chunking, march chunks)
+ * (passes per plane 1/2 or the two- and four-line tiles, work-group order,
+ * non-temporal stores, column chunking, march chunks)
  * and give every problem of the bucket the fastest; FP32 contexts keep the
  * default.  *tuned (nullable) = number of buckets.  Synchronises; uses a
  * temporary n x N block per tuned bucket. */
@@ -328,7 +328,7 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * plane mean fewer x segments but more registers), and the march axis is cut
  * into march_chunks ranges (0 = automatic: at least 512 work-groups).  The
  * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR, plus
- * OPE_SWEEP_LINES on 3D grids and OPE_SWEEP_NONTEMPORAL when five n x N
+ * OPE_SWEEP_LINES4 on 3D grids and OPE_SWEEP_NONTEMPORAL when five n x N
  * blocks of the storage type exceed 256 MiB.
  * q_max = 0 lets the library choose.  flags: OPE_SWEEP_CHUNK_MAJOR puts the
  * work-groups of one column chunk next to each other (so one XCD streams one
@@ -337,14 +337,17 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * OPE_SWEEP_NARROW keeps 8-vector column chunks for rows of at most 32
  * vector columns (which by default a work-group takes whole);
  * OPE_SWEEP_LINES (3D grids) gives a work-group two adjacent side lines, one
- * per pass over an x segment of 256/8 points (q is then 2), so that each line
- * takes its inner side neighbour from the other line's registers.
+ * per pass over an x segment of 256/8 points (q is then 2), OPE_SWEEP_LINES4
+ * four, two per pass over segments of half that; the lines take their inner
+ * side neighbours from the staged plane, and only the outer ones load side
+ * rows.
  * Results do not depend on the shape beyond the summation order of the CG dot
  * products.  Synchronises; on OPE_EINVAL the previous shape stays. */
 #define OPE_SWEEP_CHUNK_MAJOR 1
 #define OPE_SWEEP_NONTEMPORAL 2
 #define OPE_SWEEP_NARROW 4
 #define OPE_SWEEP_LINES 8
+#define OPE_SWEEP_LINES4 16
 ope_status ope_set_sweep_shape(ope_ctx* ctx, int32_t q_max, int32_t march_chunks, int32_t flags);
 
 /* The shape in use (outputs nullable, host). */

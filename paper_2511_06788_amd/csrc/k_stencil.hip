@@ -224,10 +224,11 @@ __device__ __forceinline__ void take_set(const MarchLoads<T, VW, Q>& a, MarchLoa
 
 // The march of work item t (0 <= t < lgroups * nxs * cc * mc) of one
 // problem; shared by the single-problem kernel and the batched kernel below.
-// HALO: the x line is split into several segments (nxs > 1).  LN: the Q passes
-// are Q adjacent side lines (each over one x segment of pp points) rather than
-// Q parts of one line's x segment; a pass then takes its inner side neighbours
-// from the other passes' registers and only the outer lines load side rows.
+// HALO: the x line is split into several segments (nxs > 1).  LN: the
+// work-group takes ly = Q lpp adjacent side lines, lpp per pass, each over one
+// x segment (xseg = pp / lpp points), rather than Q parts of one line's x
+// segment; the inner side neighbours come from the staged plane, and only the
+// tile's outer lines load side rows.
 // A plane of one array must be smaller than 2 GiB (checked when the context
 // is created).
 template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO, bool LN>
@@ -263,10 +264,14 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
     lg = t % ms.lgroups;
     cchunk = t / ms.lgroups;
   }
-  const uint32_t line0 = lg * (LN ? (uint32_t)Q : 1u);
+  const uint32_t lpp = LN ? ms.lpp : 1u;                 // side lines per pass
+  const uint32_t ly = LN ? (uint32_t)Q * lpp : 1u;       // side lines of the work-group
+  const uint32_t line0 = lg * ly;
   const uint32_t cv = threadIdx.x % ms.ncv, slot = threadIdx.x / ms.ncv;
+  const uint32_t used = LN ? lpp * ms.xseg : ms.pp;      // slots that hold points
+  const uint32_t lip = LN ? slot / ms.xseg : 0u;         // line within the pass
   const uint32_t colv = cchunk * ms.ncv + cv;
-  const bool lane_ok = slot < ms.pp && colv < NV;
+  const bool lane_ok = slot < used && colv < NV;
   const uint32_t z0 = mchunk_id * ms.mchunk;
   const uint32_t z1 = min(ms.mlen, z0 + ms.mchunk);
   // one plane of an array: march_stride rows of N values
@@ -285,19 +290,22 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   }
   const T cx = (T)g.cx, cs = (T)ms.cs, cm = (T)ms.cm;
   // per-pass byte offsets within a plane (NO_ROW where there is no row)
-  uint32_t xq[Q], xiq[Q], oc[Q], ol[Q], ou[Q], oh[Q], od[Q];
+  uint32_t xq[Q], xiq[Q], ltq[Q], liq[Q], oc[Q], ol[Q], ou[Q], oh[Q], od[Q];
   bool okq[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const uint32_t xi = LN ? slot : q * ms.pp + slot;      // position in the x segment
-    const uint32_t line = line0 + (LN ? (uint32_t)q : 0u);
+    const uint32_t lt = LN ? q * lpp + lip : 0u;               // line within the tile
+    const uint32_t xi = LN ? slot - lip * ms.xseg : q * ms.pp + slot;   // position in the x segment
+    const uint32_t line = line0 + lt;
     xiq[q] = xi;
+    ltq[q] = lt;
+    liq[q] = LN ? lt * ms.xseg + xi : q * ms.pp + slot;       // slot in the staged plane
     xq[q] = xs * ms.xseg + xi;
     okq[q] = lane_ok && xi < ms.xseg && xq[q] < g.m0 && line < ms.lines;
     const uint32_t p = xq[q] + line * ms.side_stride;     // point index within the plane
     oc[q] = okq[q] ? p * row_bytes + colv * VW * (uint32_t)sizeof(T) : NO_ROW;
-    // side rows from memory: every pass, or in LN only the outer lines
-    const bool own_lo = !LN || q == 0, own_hi = !LN || q == Q - 1;
+    // side rows from memory: every pass, or in LN only the tile's outer lines
+    const bool own_lo = !LN || lt == 0, own_hi = !LN || lt + 1 == ly;
     ol[q] = (okq[q] && own_lo && ms.has_side && line > 0) ? oc[q] - ms.side_stride * row_bytes : NO_ROW;
     ou[q] = (okq[q] && own_hi && ms.has_side && line + 1 < ms.lines) ? oc[q] + ms.side_stride * row_bytes : NO_ROW;
     oh[q] = NO_ROW;
@@ -413,20 +421,20 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
 
   // plane z: stage it for the x neighbours, apply H, use the result
   auto compute = [&](uint32_t z, T* __restrict__ buf) {
-    // lanes past the last whole slot (when ncv does not divide the work-group)
-    // hold no point, and their index would alias the next pass's first slot
-    if (slot < ms.pp) {
+    // lanes past the last used slot hold no point, and their index would
+    // alias another pass's slot
+    if (slot < used) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int v = 0; v < VW; ++v) buf[((q * ms.pp + slot) * ms.ncv + cv) * VW + v] = pz[q][v];
+        for (int v = 0; v < VW; ++v) buf[(liq[q] * ms.ncv + cv) * VW + v] = pz[q][v];
     }
     __syncthreads();
     const Rsrc o0 = prs(O0, z, MODE != SW_PAP);
     const Rsrc o1 = prs(O1, z, MODE == SW_PAP), yo = prs(Yv, z, YUP);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const uint32_t xi = xiq[q], li = q * ms.pp + slot;   // x position; slot in the staged plane
+      const uint32_t xi = xiq[q], li = liq[q];   // x position; slot in the staged plane
       // x neighbours: the staged plane, or the segment end's outer row (zero
       // where there is none: at the grid boundary, or a lane past the grid)
       const uint32_t im = xi > 0 ? li - 1 : li, ip = xi + 1 < ms.xseg ? li + 1 : li;
@@ -438,13 +446,16 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         xm[v] = xi > 0 ? lm : hm;
         xp[v] = xi + 1 < ms.xseg ? lp : hm;
       }
-      // side neighbours: loaded rows, or in LN the adjacent passes' lines
-      // (zero beyond the grid: such a pass loaded nothing)
+      // side neighbours: loaded rows, or in LN the staged plane's adjacent
+      // lines inside the tile (zero beyond the grid: such a line loaded nothing)
       T sm[VW], sp[VW];
+      const uint32_t lt = ltq[q];
+      const uint32_t ym = (LN && lt > 0) ? li - ms.xseg : li, yp = (LN && lt + 1 < ly) ? li + ms.xseg : li;
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
-        sm[v] = (LN && q > 0) ? pz[q > 0 ? q - 1 : 0][v] : smz[q][v];
-        sp[v] = (LN && q < Q - 1) ? pz[q < Q - 1 ? q + 1 : 0][v] : spz[q][v];
+        const T lm = buf[(ym * ms.ncv + cv) * VW + v], lp = buf[(yp * ms.ncv + cv) * VW + v];
+        sm[v] = (LN && lt > 0) ? lm : ((!LN || q == 0) ? smz[q][v] : T(0));
+        sp[v] = (LN && lt + 1 < ly) ? lp : ((!LN || q == Q - 1) ? spz[q][v] : T(0));
       }
       T hx[VW];
 #pragma unroll
@@ -835,12 +846,15 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
     }
   }
   ms.ly = 1;
-  if (lines && g.dim == 3 && g.m1 > 1) q = 2;   // two side lines per work-group, one per pass
+  ms.lpp = 1;
+  const bool tile = lines && g.dim == 3 && g.m1 > 1;
+  if (tile) q = 2;                 // side lines of the work-group: two (one per pass) or four (two per pass)
   ms.q = q;
   ms.xseg = q * ms.pp;
-  if (lines && g.dim == 3 && g.m1 > 1) {
-    ms.ly = 2;
-    ms.xseg = ms.pp;
+  if (tile) {
+    ms.lpp = (lines >= 2 && ms.pp >= 4) ? 2u : 1u;
+    ms.ly = q * ms.lpp;
+    ms.xseg = ms.pp / ms.lpp;
   }
   ms.nxs = (g.m0 + ms.xseg - 1) / ms.xseg;
   ms.cc = (NV + ms.ncv - 1) / ms.ncv;

@@ -39,7 +39,8 @@ struct MarchShape {
   uint32_t nxs;       // x segments
   uint32_t cc;        // column chunks
   uint32_t lines;     // side lines (m1 in 3D, 1 in 2D)
-  uint32_t ly;        // side lines per work-group: 1, or q (one line per pass, x segment = pp)
+  uint32_t ly;        // side lines per work-group: 1, or q lpp (lpp lines per pass, x segment = pp / lpp)
+  uint32_t lpp;       // side lines per pass of a line tile (1 or 2)
   uint32_t lgroups;   // groups of ly side lines
   uint32_t mlen;      // planes along the march axis (m2 in 3D, m1 in 2D)
   uint32_t mc;        // march chunks
@@ -173,7 +174,8 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 hipError_t launch_apply_h(ope_ctx* c, const void* X, void* Y);
 // fills c->ms (0 = automatic); narrow = 1 keeps 8-vector column chunks for short rows;
-// lines = 1 gives each work-group two side lines, one per pass (3D only)
+// lines = 1 gives each work-group two side lines, one per pass; lines = 2 four,
+// two per pass (3D only)
 void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int narrow, int lines = 0);
 int64_t march_rows(const ope_ctx* c);              // partial rows written by the CG sweeps
 

@@ -287,6 +287,7 @@ OPE_SWEEP_CHUNK_MAJOR = 1
 OPE_SWEEP_NONTEMPORAL = 2
 OPE_SWEEP_NARROW = 4
 OPE_SWEEP_LINES = 8
+OPE_SWEEP_LINES4 = 16
 
 
 def ope_set_graphs(ctx: int, enable: bool) -> None:

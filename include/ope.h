@@ -328,7 +328,7 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * plane mean fewer x segments but more registers), and the march axis is cut
  * into march_chunks ranges (0 = automatic: at least 512 work-groups).  The
  * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR, plus
- * OPE_SWEEP_LINES4 on 3D grids and OPE_SWEEP_NONTEMPORAL when five n x N
+ * OPE_SWEEP_LINES8 on 3D grids and OPE_SWEEP_NONTEMPORAL when five n x N
  * blocks of the storage type exceed 256 MiB.
  * q_max = 0 lets the library choose.  flags: OPE_SWEEP_CHUNK_MAJOR puts the
  * work-groups of one column chunk next to each other (so one XCD streams one
@@ -338,9 +338,10 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * vector columns (which by default a work-group takes whole);
  * OPE_SWEEP_LINES (3D grids) gives a work-group two adjacent side lines, one
  * per pass over an x segment of 256/8 points (q is then 2), OPE_SWEEP_LINES4
- * four, two per pass over segments of half that; the lines take their inner
- * side neighbours from the staged plane, and only the outer ones load side
- * rows.
+ * four, two per pass over segments of half that, OPE_SWEEP_LINES8 eight, four
+ * per pass over segments of a quarter (when a pass holds at least 16 points;
+ * else as OPE_SWEEP_LINES4); the lines take their inner side neighbours from
+ * the staged plane, and only the outer ones load side rows.
  * Results do not depend on the shape beyond the summation order of the CG dot
  * products.  Synchronises; on OPE_EINVAL the previous shape stays. */
 #define OPE_SWEEP_CHUNK_MAJOR 1
@@ -348,6 +349,7 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
 #define OPE_SWEEP_NARROW 4
 #define OPE_SWEEP_LINES 8
 #define OPE_SWEEP_LINES4 16
+#define OPE_SWEEP_LINES8 32
 ope_status ope_set_sweep_shape(ope_ctx* ctx, int32_t q_max, int32_t march_chunks, int32_t flags);
 
 /* The shape in use (outputs nullable, host). */

@@ -38,32 +38,48 @@ __device__ double wg_sum(double v, double* red) {
 
 // In-place Gauss-Jordan inversion of the register-resident matrix w.
 // Sets *bad when a pivot is not a finite number above 1e-300.
+// Pivot k: the pivot column is published in LDS in the owners' row order
+// (F[q * 16 + r] holds row q + 8 r, so a thread reads its 16 multipliers
+// contiguously) and the pivot row as R[j]; the column's own lanes then hold
+// zero, so every element takes the one update w - F_i r_j (r_j = R[j] / piv,
+// 1 / piv in column k), and the waves of row k write the scaled pivot row r_j.
 __device__ void gj_invert(double (&w)[RPT], uint32_t N, double* fcol, double* rowk, int* bad) {
   const Own o;
   for (uint32_t k = 0; k < N; ++k) {
     double* F = fcol + (k & 1u) * 128;
     double* R = rowk + (k & 1u) * 128;
+    const bool krow = o.q == (k & 7u);          // this wave holds row k (as w[k / 8])
+    const uint32_t kr = k >> 3;
+    if (krow && o.j < N) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if ((uint32_t)r == kr) R[o.j] = w[r];
+    }
     if (o.j == k) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (o.row(r) < N) F[o.row(r)] = w[r];
-    }
-    if (o.j < N) {
-#pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (o.row(r) == k) R[o.j] = w[r];
+      for (int r = 0; r < RPT; ++r) {
+        F[o.q * 16u + r] = w[r];
+        w[r] = 0.0;
+      }
     }
     __syncthreads();
-    const double piv = F[k];
+    const double piv = F[(k & 7u) * 16u + kr];
     const bool ok = isfinite(piv) && piv > 1e-300;
     if (!ok && threadIdx.x == 0) *bad = 1;
     const double pinv = ok ? 1.0 / piv : 0.0;
     const double rk = (o.j == k ? 1.0 : R[o.j & 127u]) * pinv;
     if (o.j < N) {
+      const double2* F2 = reinterpret_cast<const double2*>(F + o.q * 16u);
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const uint32_t i = o.row(r);
-        if (i < N) w[r] = (i == k) ? rk : ((o.j == k ? 0.0 : w[r]) - F[i] * rk);
+      for (int r = 0; r < RPT / 2; ++r) {
+        const double2 f = F2[r];
+        w[2 * r] = fma(-f.x, rk, w[2 * r]);
+        w[2 * r + 1] = fma(-f.y, rk, w[2 * r + 1]);
+      }
+      if (krow) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if ((uint32_t)r == kr) w[r] = rk;
       }
     }
   }
@@ -94,7 +110,8 @@ __global__ __launch_bounds__(SW) void k_prep_small(const double* __restrict__ C,
                                                    uint32_t N, OpeScalars* __restrict__ sc, float* __restrict__ Lam32,
                                                    float* __restrict__ Linv32) {
   __shared__ double red[SW];
-  __shared__ double fcol[256], rowk[256];
+  __shared__ __align__(16) double fcol[256];
+  __shared__ double rowk[256];
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
@@ -204,7 +221,8 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
                                                     double* __restrict__ Z, double* __restrict__ Aout,
                                                     OpeScalars* __restrict__ sc) {
   extern __shared__ double smat[];
-  __shared__ double fcol[256], rowk[256];
+  __shared__ __align__(16) double fcol[256];
+  __shared__ double rowk[256];
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
@@ -216,7 +234,7 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
   double P[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) P[r] = 0.0;
-#pragma unroll 4
+#pragma unroll 1
   for (uint32_t k = 0; k < N; ++k) {
     const double skj = smat[k * N + jj];
 #pragma unroll
@@ -240,13 +258,16 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
   gj_invert(w, N, fcol, rowk, &bad);
   store_own(Bws, N, w);           // B
   __syncthreads();
-  // A = 2/tau (I - B) + S_b B (B's columns from global memory, eight rows in flight)
+  // A = 2/tau (I - B) + S_b B (B's columns from global memory, the next
+  // row's load in flight; a deeper unroll spills at 1024 threads)
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
-#pragma unroll 8
+  double bnx = Bws[jj];
+#pragma unroll 1
   for (uint32_t k = 0; k < N; ++k) {
-    const double bkj = Bws[(uint64_t)k * N + jj];
+    const double bkj = bnx;
+    bnx = Bws[(uint64_t)(k + 1 < N ? k + 1 : k) * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t i = o.row(r);
@@ -283,7 +304,8 @@ __global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restri
                                                           double* __restrict__ Wsm, float* __restrict__ Z32,
                                                           OpeScalars* __restrict__ sc) {
   extern __shared__ double smat[];
-  __shared__ double fcol[256], rowk[256];
+  __shared__ __align__(16) double fcol[256];
+  __shared__ double rowk[256];
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
@@ -294,9 +316,11 @@ __global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restri
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
-#pragma unroll 8
+  double snx = Sb[jj];
+#pragma unroll 1
   for (uint32_t l = 0; l < N; ++l) {
-    const double slj = Sb[(uint64_t)l * N + jj];
+    const double slj = snx;
+    snx = Sb[(uint64_t)(l + 1 < N ? l + 1 : l) * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t k = o.row(r) < N ? o.row(r) : 0u;
@@ -311,9 +335,11 @@ __global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restri
   double qv[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) qv[r] = 0.0;
-#pragma unroll 8
+  double wnx = Wsm[jj];
+#pragma unroll 1
   for (uint32_t k = 0; k < N; ++k) {
-    const double wkj = Wsm[(uint64_t)k * N + jj];
+    const double wkj = wnx;
+    wnx = Wsm[(uint64_t)(k + 1 < N ? k + 1 : k) * N + jj];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const uint32_t i = o.row(r) < N ? o.row(r) : 0u;

@@ -637,48 +637,47 @@ __device__ __forceinline__ void cg_finalise(uint32_t col, double tot, double* __
   }
 }
 
-// Column sums of a [nrows][ncols] partial array in a fixed order, split over
-// gridDim.y work-groups per column group with a last-block second stage, and
-// an optional CG finalisation per column.
-template <int MODE>
-__global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict__ part, uint32_t nrows,
-                                                        uint32_t ncols, double* __restrict__ out,
-                                                        double* __restrict__ stage, uint32_t* __restrict__ counters,
-                                                        double* __restrict__ alpha, double* __restrict__ beta,
-                                                        double* __restrict__ rho, const double* __restrict__ target,
-                                                        int32_t* __restrict__ active, OpeScalars* __restrict__ sc) {
+// First stage of the column sums of a [nrows][ncols] partial array: work-group
+// (column group x, y) sums rows [y rps, (y + 1) rps) of its 64 columns into
+// stage[y][col], in a fixed order.
+__global__ __launch_bounds__(OPE_WG) void k_reduce_stage(const double* __restrict__ part, uint32_t nrows,
+                                                         uint32_t ncols, uint32_t rps, double* __restrict__ stage) {
   __shared__ double red[OPE_WG];
-  __shared__ uint32_t ticket;
-  // No early exit here even when every column has converged: the partials are
-  // then stale, but inactive columns only ever receive alpha = beta = 0, and a
-  // uniform exit keeps the last-block counters consistent.
-  const uint32_t S = gridDim.y, s = blockIdx.y;
   const uint32_t lc = threadIdx.x & 63u, grp = threadIdx.x >> 6;
   const uint32_t col = blockIdx.x * 64u + lc;
-  const uint32_t rps = (nrows + S - 1) / S;
-  const uint32_t w0 = s * rps, w1 = min(nrows, w0 + rps);
+  const uint32_t w0 = blockIdx.y * rps, w1 = min(nrows, w0 + rps);
   double acc = 0.0;
   if (col < ncols)
     for (uint32_t w = w0 + grp; w < w1; w += 4) acc += part[(uint64_t)w * ncols + col];
   red[threadIdx.x] = acc;
   __syncthreads();
+  if (grp == 0 && col < ncols)
+    stage[(uint64_t)blockIdx.y * ncols + col] = red[lc] + red[64 + lc] + red[128 + lc] + red[192 + lc];
+}
+
+// Column sums of a [nrows][ncols] partial array in a fixed order (one
+// work-group per 64 columns), with an optional CG finalisation per column.
+// Long partial arrays go through k_reduce_stage first.  (A last-block second
+// stage inside one launch needs a device-scope fence per work-group, which
+// writes back the XCD's dirty L2 lines; two launches need none.)
+template <int MODE>
+__global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict__ part, uint32_t nrows,
+                                                        uint32_t ncols, double* __restrict__ out,
+                                                        double* __restrict__ alpha, double* __restrict__ beta,
+                                                        double* __restrict__ rho, const double* __restrict__ target,
+                                                        int32_t* __restrict__ active, OpeScalars* __restrict__ sc) {
+  __shared__ double red[OPE_WG];
+  // No early exit here even when every column has converged: the partials are
+  // then stale, but inactive columns only ever receive alpha = beta = 0.
+  const uint32_t lc = threadIdx.x & 63u, grp = threadIdx.x >> 6;
+  const uint32_t col = blockIdx.x * 64u + lc;
+  double acc = 0.0;
+  if (col < ncols)
+    for (uint32_t w = grp; w < nrows; w += 4) acc += part[(uint64_t)w * ncols + col];
+  red[threadIdx.x] = acc;
+  __syncthreads();
   double tot = 0.0;
   if (grp == 0) tot = red[lc] + red[64 + lc] + red[128 + lc] + red[192 + lc];
-  if (S > 1) {
-    if (grp == 0 && col < ncols) stage[(uint64_t)s * ncols + col] = tot;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) ticket = atomicAdd(&counters[blockIdx.x], 1u);
-    __syncthreads();
-    if (ticket != S - 1) return;
-    __threadfence();
-    if (grp == 0) {
-      tot = 0.0;
-      if (col < ncols)
-        for (uint32_t k = 0; k < S; ++k) tot += stage[(uint64_t)k * ncols + col];
-    }
-    if (threadIdx.x == 0) counters[blockIdx.x] = 0u;
-  }
   if (grp != 0 || col >= ncols) return;
   if (MODE == RED_PLAIN) out[col] = tot;
   else cg_finalise<MODE>(col, tot, alpha, beta, rho, target, active, sc);
@@ -848,11 +847,11 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
   ms.ly = 1;
   ms.lpp = 1;
   const bool tile = lines && g.dim == 3 && g.m1 > 1;
-  if (tile) q = 2;                 // side lines of the work-group: two (one per pass) or four (two per pass)
+  if (tile) q = 2;                 // side lines of the work-group: 2, 4 or 8 (1, 2 or 4 per pass)
   ms.q = q;
   ms.xseg = q * ms.pp;
   if (tile) {
-    ms.lpp = (lines >= 2 && ms.pp >= 4) ? 2u : 1u;
+    ms.lpp = (lines >= 3 && ms.pp >= 16) ? 4u : ((lines >= 2 && ms.pp >= 4) ? 2u : 1u);
     ms.ly = q * ms.lpp;
     ms.xseg = ms.pp / ms.lpp;
   }
@@ -949,25 +948,32 @@ hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int
     return hipGetLastError();
   }
   const uint32_t ncg = (uint32_t)((ncols + 63) / 64);
-  // enough rows per work-group to amortise, enough work-groups to spread the read
-  uint32_t S = (uint32_t)((nrows + 255) / 256);
-  if (S < 1) S = 1;
+  // first stage: about 32 rows per work-group, at most 64 work-groups per
+  // column group (enough work-groups to keep HBM busy), within the stage buffer
+  uint32_t S = (uint32_t)((nrows + 31) / 32);
   if (S > 64) S = 64;
-  if ((int64_t)S * ncols > c->stage_cap) S = 1;
-  if (ncg > 4096) S = 1;
-  const dim3 grid(ncg, S), blk(OPE_WG);
+  if ((int64_t)S * ncols > c->stage_cap) S = (uint32_t)(c->stage_cap / ncols);
+  if (S > 1) {
+    const uint32_t rps = (uint32_t)((nrows + S - 1) / S);
+    S = (uint32_t)((nrows + rps - 1) / rps);
+    hipLaunchKernelGGL(k_reduce_stage, dim3(ncg, S), dim3(OPE_WG), 0, c->stream, part, (uint32_t)nrows,
+                       (uint32_t)ncols, rps, c->stage);
+    part = c->stage;
+    nrows = S;
+  }
+  const dim3 grid(ncg), blk(OPE_WG);
   switch (mode) {
     case RED_PLAIN:
       hipLaunchKernelGGL((k_reduce_cols<RED_PLAIN>), grid, blk, 0, c->stream, part, (uint32_t)nrows, (uint32_t)ncols,
-                         out, c->stage, c->counters, alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                         out, alpha, c->beta, c->rho, c->target, c->active, c->sc);
       break;
     case RED_CG_ALPHA:
       hipLaunchKernelGGL((k_reduce_cols<RED_CG_ALPHA>), grid, blk, 0, c->stream, part, (uint32_t)nrows, (uint32_t)ncols,
-                         out, c->stage, c->counters, alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                         out, alpha, c->beta, c->rho, c->target, c->active, c->sc);
       break;
     default:
       hipLaunchKernelGGL((k_reduce_cols<RED_CG_BETA>), grid, blk, 0, c->stream, part, (uint32_t)nrows, (uint32_t)ncols,
-                         out, c->stage, c->counters, alpha, c->beta, c->rho, c->target, c->active, c->sc);
+                         out, alpha, c->beta, c->rho, c->target, c->active, c->sc);
       break;
   }
   return hipGetLastError();

@@ -71,7 +71,7 @@ void free_ctx(ope_ctx* c) {
   if (!c) return;
   void* dptrs[] = {c->diag, c->diag32, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T,
                    c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
-                   c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->counters, c->sc,
+                   c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->sc,
                    c->Ubak, c->ns_x[0], c->ns_x[1], c->ns_g, c->ns_m, c->ns_p, c->ns_part, c->ns};
   for (void* p : dptrs)
     if (p) (void)hipFree(p);
@@ -818,16 +818,23 @@ ProfScope::~ProfScope() {
   c->prof_used += 2;
 }
 
-// Default sweep flags: chunk-major, four side lines per work-group on 3D grids
-// (measured 5-17% faster than two at 64^3 and at 96^3 N = 128, 1-3% slower at
-// 96^3 N = 17), and non-temporal stores when the CG's working set (about five
-// n x N blocks) exceeds the 256 MiB last-level cache.  Measured: streamed
-// stores help once the sweeps' arrays cannot stay in that cache and cost while
-// they can.
+// Line-tile level of sweep flags: 0 none, 1, 2, 3 for two, four, eight lines.
+static int sweep_lines(int flags) {
+  return (flags & OPE_SWEEP_LINES8) ? 3 : ((flags & OPE_SWEEP_LINES4) ? 2 : ((flags & OPE_SWEEP_LINES) ? 1 : 0));
+}
+
+// Default sweep flags: chunk-major, eight side lines per work-group on 3D
+// grids (four where a pass holds fewer than 16 points; measured: four lines
+// 5-17% faster than two at 64^3 and at 96^3 N = 128, 1-3% slower at 96^3
+// N = 17, eight lines another 0.7-0.9% at N = 128), and non-temporal stores
+// when the CG's working set (about five n x N blocks) exceeds the 256 MiB
+// last-level cache.  Measured: streamed stores help once the sweeps' arrays
+// cannot stay in that cache and cost while they can.
+
 static int default_sweep_flags(const ope_ctx* c) {
   const double esz = c->prec == OPE_FP64 ? 8.0 : 4.0;
   const bool big = 5.0 * (double)c->n * (double)c->N * esz > 256.0 * 1048576.0;
-  return OPE_SWEEP_CHUNK_MAJOR | (c->g.dim == 3 ? OPE_SWEEP_LINES4 : 0) | (big ? OPE_SWEEP_NONTEMPORAL : 0);
+  return OPE_SWEEP_CHUNK_MAJOR | (c->g.dim == 3 ? OPE_SWEEP_LINES8 : 0) | (big ? OPE_SWEEP_NONTEMPORAL : 0);
 }
 
 extern "C" {
@@ -910,8 +917,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   c->stream_wgs = (int)((n + pts - 1) / pts);
   {
     const int f = default_sweep_flags(c);
-    march_shape(c, 0, 0, 1, (f & OPE_SWEEP_NONTEMPORAL) ? 1 : 0, 0,
-                (f & OPE_SWEEP_LINES4) ? 2 : ((f & OPE_SWEEP_LINES) ? 1 : 0));
+    march_shape(c, 0, 0, 1, (f & OPE_SWEEP_NONTEMPORAL) ? 1 : 0, 0, sweep_lines(f));
   }
 
   const int64_t blk = n * N;
@@ -964,7 +970,6 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   ok &= dalloc(&c->active, N) == hipSuccess;
   ok &= dalloc(&c->part, c->part_cap) == hipSuccess;
   ok &= dalloc(&c->stage, c->stage_cap) == hipSuccess;
-  ok &= dalloc(&c->counters, 4096) == hipSuccess;
   ok &= dalloc(&c->sc, 1) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hsc, sizeof(OpeScalars), hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&c->hactive, sizeof(int32_t) * 2 * N, hipHostMallocDefault) == hipSuccess;
@@ -993,7 +998,6 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
     for (int64_t p = 0; p < n; ++p) hf[(size_t)p] = (float)hd[(size_t)p];
     hok &= hipMemcpy(c->diag32, hf.data(), sizeof(float) * n, hipMemcpyHostToDevice) == hipSuccess;
   }
-  hok &= hipMemset(c->counters, 0, sizeof(uint32_t) * 4096) == hipSuccess;
   hok &= hipMemset(c->sc, 0, sizeof(OpeScalars)) == hipSuccess;
   hok &= hipMemset(c->active, 0, sizeof(int32_t) * N) == hipSuccess;
   hok &= hipDeviceSynchronize() == hipSuccess;
@@ -1135,14 +1139,14 @@ ope_status ope_set_graphs(ope_ctx* c, int32_t enable) {
 }
 
 ope_status ope_set_sweep_shape(ope_ctx* c, int32_t q_max, int32_t march_chunks, int32_t flags) {
-  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~31))
+  if (!c || !(q_max == 0 || q_max == 1 || q_max == 2 || q_max == 4) || march_chunks < 0 || (flags & ~63))
     return OPE_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   const MarchShape keep = c->ms;
   march_shape(c, q_max, march_chunks, flags & OPE_SWEEP_CHUNK_MAJOR, flags & OPE_SWEEP_NONTEMPORAL,
               flags & OPE_SWEEP_NARROW,
-              (flags & OPE_SWEEP_LINES4) ? 2 : ((flags & OPE_SWEEP_LINES) ? 1 : 0));
+              sweep_lines(flags));
   if (march_rows(c) * c->N > c->part_cap) {
     c->ms = keep;
     return OPE_EINVAL;
@@ -1504,8 +1508,8 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
         Shape pick{2, 0, default_sweep_flags(c)};
         double tbest = 1e30;
         const int narrow_opts = NV <= 32 ? 2 : 1;
-        // qs = 3 and 4 stand for the two- and four-line tiles (q 2)
-        for (int qs : {1, 2, 3, 4})
+        // qs = 3, 4 and 5 stand for the two-, four- and eight-line tiles (q 2)
+        for (int qs : {1, 2, 3, 4, 5})
           for (int cm : {0, OPE_SWEEP_CHUNK_MAJOR})
             for (int nt : {0, OPE_SWEEP_NONTEMPORAL})
             for (int nr = 0; nr < narrow_opts; ++nr)
@@ -1513,7 +1517,7 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
                 if (qs >= 3 && c->g.dim != 3) continue;
                 const int q = qs >= 3 ? 2 : qs;
                 const int flags = cm | nt | (nr ? OPE_SWEEP_NARROW : 0) | (qs == 3 ? OPE_SWEEP_LINES : 0) |
-                                  (qs == 4 ? OPE_SWEEP_LINES4 : 0);
+                                  (qs == 4 ? OPE_SWEEP_LINES4 : 0) | (qs == 5 ? OPE_SWEEP_LINES8 : 0);
                 if (ope_set_sweep_shape(c, q, 0, flags) != OPE_OK) continue;
                 int mc = 0;
                 if (mcm == 2) {

@@ -107,7 +107,6 @@ struct ope_ctx {
   int64_t part_cap;
   double* stage;                // second-stage partial sums
   int64_t stage_cap;
-  uint32_t* counters;           // last-block counters of the split reductions
   // scalars
   OpeScalars* sc;               // device
   OpeScalars* hsc;              // pinned host mirror

@@ -288,6 +288,7 @@ OPE_SWEEP_NONTEMPORAL = 2
 OPE_SWEEP_NARROW = 4
 OPE_SWEEP_LINES = 8
 OPE_SWEEP_LINES4 = 16
+OPE_SWEEP_LINES8 = 32
 
 
 def ope_set_graphs(ctx: int, enable: bool) -> None:

@@ -204,14 +204,17 @@ def test_energy_residual_ritz_match_oracle():
 
 @pytest.mark.parametrize("q_max,chunks,flags", [(1, 1, 0), (2, 3, 1), (4, 0, 2), (4, 5, 3), (1, 0, 3),
                                                  (2, 0, 9), (2, 3, 8), (1, 2, 11), (2, 0, 13),
-                                                 (2, 0, 17), (2, 2, 19), (2, 0, 21)])
+                                                 (2, 0, 17), (2, 2, 19), (2, 0, 21),
+                                                 (2, 0, 33), (2, 0, 36), (2, 2, 39), (2, 0, 37)])
 def test_sweep_shapes_agree(q_max, chunks, flags):
     """Every launch shape of the marching sweeps computes the same H X, and the
     same CG solution up to the order of the dot-product sums (flags 8: two
     side lines per work-group; with 21 lines the last group is half empty, and
     its x segments of 15 points need segment-end neighbours; with 13 the
     8-vector chunks cover x whole; flags 16: four lines, segments of 7 points,
-    the last group three quarters empty)."""
+    the last group three quarters empty; flags 32 with 8-vector chunks: eight
+    lines, segments of 8 points, the last group and segment 5/8 full; flags 32
+    with whole rows (15 points per pass) falls back to four lines)."""
     from paper_2511_06788_amd import ope
     p = W.wells_3d(m=21, N=34, seed=6)
     op = _op(p)

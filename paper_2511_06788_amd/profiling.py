@@ -9,6 +9,12 @@ prints a per-kernel table (calls, total and average duration) as Markdown.
 ``regex`` per dispatch, scaled by the factor that makes a plain device copy of
 known size read its own size, and writes the JSON record ``bench.py`` uses for
 its ``traffic`` field.
+
+``python -m paper_2511_06788_amd.profiling mfma --pmc-db <db> --trace-db <db>
+--kernel LABEL=REGEX --flop LABEL=FLOP ...`` prints, per kernel, the matrix-core
+utilisation (``MfmaUtil``: MFMA-busy cycles over active cycles of every SIMD),
+the MFMA flops the counters saw per dispatch (``MfmaFlopsF64``/``BF16``) next to
+the algorithmic count, and the rate from the trace's average duration.
 """
 from __future__ import annotations
 
@@ -115,6 +121,42 @@ def cmd_pmc(args):
     ] + ([""] + [args.note] if args.note else [])))
 
 
+# Dense matrix-core peaks of the MI355X (TFLOP/s)
+MFMA_PEAK = {"F64": 78.6, "BF16": 2500.0}
+
+
+def trace_avg_us(db: str, pattern: str):
+    """Call-weighted average duration (us) of the kernels matching `pattern`."""
+    rx = re.compile(pattern)
+    st = [r for r in kernel_stats(db) if rx.search(r["name"])]
+    calls = sum(r["calls"] for r in st)
+    return (sum(r["total_ms"] for r in st) * 1e3 / calls, calls) if calls else (None, 0)
+
+
+def cmd_mfma(args):
+    flop = dict(kv.split("=", 1) for kv in args.flop)
+    out = [f"# Matrix-core use: {args.title}", "", "Commands:", "", "```", args.cmd, "```", "",
+           "| kernel | dispatches | MfmaUtil (%) | MFMA flop per dispatch (counters) | algorithmic flop | "
+           "average (us, trace) | algorithmic TFLOP/s | of peak |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for kv in args.kernel:
+        label, pat = kv.split("=", 1)
+        util, nu, _ = counter_per_dispatch(args.pmc_db, "MfmaUtil", pat)
+        kind = args.kind
+        fl, _, _ = counter_per_dispatch(args.pmc_db, "MfmaFlops" + kind, pat)
+        avg, _ = trace_avg_us(args.trace_db, pat)
+        algo = float(flop[label]) if label in flop else None
+        rate = algo / (avg * 1e-6) / 1e12 if (algo and avg) else None
+        out.append(f"| `{label}` | {nu} | {util:.1f} | {fl:.4g} | "
+                   f"{algo:.4g} | {avg:.1f} | {rate:.1f} | {rate / MFMA_PEAK[kind]:.2f} |"
+                   if None not in (util, fl, algo, avg) else f"| `{label}` | {nu} | n/a | n/a | n/a | n/a | n/a | n/a |")
+    out += ["", f"Peak: {MFMA_PEAK[args.kind]} TFLOP/s dense {args.kind} (MI355X). MfmaUtil is rocprofv3's derived "
+            "metric, SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs)."]
+    if args.note:
+        out += ["", args.note]
+    print("\n".join(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -141,8 +183,17 @@ def main(argv=None):
     p.add_argument("--json", default=None)
     p.add_argument("--min-frac", type=float, default=0.1)
     p.add_argument("--note", default="")
+    m = sub.add_parser("mfma")
+    m.add_argument("--pmc-db", required=True)
+    m.add_argument("--trace-db", required=True)
+    m.add_argument("--kernel", required=True, action="append", help="LABEL=REGEX")
+    m.add_argument("--flop", default=[], action="append", help="LABEL=algorithmic flop per dispatch")
+    m.add_argument("--kind", default="F64", choices=sorted(MFMA_PEAK))
+    m.add_argument("--cmd", required=True)
+    m.add_argument("--title", default="")
+    m.add_argument("--note", default="")
     args = ap.parse_args(argv)
-    {"trace": cmd_trace, "pmc": cmd_pmc}[args.what](args)
+    {"trace": cmd_trace, "pmc": cmd_pmc, "mfma": cmd_mfma}[args.what](args)
 
 
 if __name__ == "__main__":

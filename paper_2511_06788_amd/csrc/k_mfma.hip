@@ -202,6 +202,74 @@ __global__ __launch_bounds__(256) void k_gram_wide(const TI* __restrict__ A, uin
       }
 }
 
+// Narrow Grams (both sides at most 32 columns): one 32 x 32 output tile (2 x 2
+// MFMA blocks) per work-group, and the four waves split the work-group's rows
+// (wave w takes contraction steps w, w + 4, ...) instead of sharing a 64 x 64
+// tile that such a Gram would leave three quarters idle.  The waves' tiles are
+// summed in LDS in wave order.
+template <typename TI, int KIND>
+__global__ __launch_bounds__(256) void k_gram_narrow(const TI* __restrict__ A, uint64_t lda, uint32_t na,
+                                                     const TI* __restrict__ B, uint64_t ldb, uint32_t nb,
+                                                     uint32_t rows, uint32_t rows_per_split,
+                                                     double* __restrict__ part) {
+  using M = Mk<KIND>;
+  using acc_t = typename M::acc_t;
+  __shared__ double red[3][2][2][4][64];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t ks = blockIdx.x;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = zero_acc<acc_t>();
+  const uint32_t r0 = ks * rows_per_split;
+  const uint32_t r1 = min(rows, r0 + rows_per_split);
+  const bool ia0 = ci < na, ia1 = 16 + ci < na;
+  const bool jb0 = ci < nb, jb1 = 16 + ci < nb;
+#pragma unroll 4
+  for (uint32_t p = r0 + wave * M::KSTEP; p < r1; p += 4 * M::KSTEP) {
+    TI a0[M::KPL], a1[M::KPL], b0[M::KPL], b1[M::KPL];
+#pragma unroll
+    for (int e = 0; e < M::KPL; ++e) {
+      const uint32_t row = p + kr * M::KPL + e;
+      const bool rok = row < r1;
+      const TI* ar = A + (uint64_t)row * lda + ci;
+      const TI* br = B + (uint64_t)row * ldb + ci;
+      a0[e] = (rok && ia0) ? ar[0] : TI(0);
+      a1[e] = (rok && ia1) ? ar[16] : TI(0);
+      b0[e] = (rok && jb0) ? br[0] : TI(0);
+      b1[e] = (rok && jb1) ? br[16] : TI(0);
+    }
+    acc[0][0] = mma<KIND, TI>(a0, b0, acc[0][0]);
+    acc[0][1] = mma<KIND, TI>(a0, b1, acc[0][1]);
+    acc[1][0] = mma<KIND, TI>(a1, b0, acc[1][0]);
+    acc[1][1] = mma<KIND, TI>(a1, b1, acc[1][1]);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave - 1][a][b][r][lane] = (double)acc[a][b][r];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  double* out = part + (uint64_t)ks * na * nb;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = a * 16 + M::drow(kr, r);
+        const uint32_t j = b * 16 + ci;
+        const double v = (double)acc[a][b][r] + red[0][a][b][r][lane] + red[1][a][b][r][lane] + red[2][a][b][r][lane];
+        if (i < na && j < nb) out[(uint64_t)i * nb + j] = v;
+      }
+}
+
 // Row-block products Out = cbeta Cm + ascale (X0 M0 + X1 M1).  Work-group =
 // 4 waves, 2 (rows) x 2 (columns); a wave owns 32 rows x 64 columns (2 x 4
 // MFMA blocks), the work-group 64 x 128.  TI is the type of X, M, Cm and Out.
@@ -290,6 +358,104 @@ __global__ __launch_bounds__(256) void k_rowmm(const TI* X0, const TI* __restric
   if (threadIdx.x < CT) {
     const uint32_t col = blockIdx.y * CT + threadIdx.x;
     if (col < N) part[(uint64_t)blockIdx.x * N + col] = colsq[0][threadIdx.x] + colsq[1][threadIdx.x];
+  }
+}
+
+// Narrow row-block products (N <= 32): work-group tile 128 rows x N columns,
+// each wave 32 rows x 32 columns (2 x 2 MFMA blocks).  The tile's rows of X,
+// of Cm and of the result are contiguous in memory, so they pass through LDS
+// and every global access is a run of whole rows (the MFMA operand pattern
+// itself reads 16 rows x 4 values per instruction, 16 cache lines).  Sources
+// are staged one after the other; the LDS row stride is odd, so the 16 rows of
+// an operand read fall in distinct banks.
+constexpr int RTN = 128;    // rows per work-group tile
+constexpr int LDXN = 33;    // LDS row stride of the staged tile
+
+template <typename TI, int KIND, int NSRC>
+__global__ __launch_bounds__(256) void k_rowmm_narrow(const TI* X0, const TI* __restrict__ M0, const TI* X1,
+                                                      const TI* __restrict__ M1, const TI* Cm, double cbeta,
+                                                      double ascale, TI* Out, uint32_t n, uint32_t N, int want_colsq,
+                                                      int predicated, const OpeScalars* __restrict__ sc,
+                                                      double* __restrict__ part) {
+  using MK = Mk<KIND>;
+  using acc_t = typename MK::acc_t;
+  __shared__ TI xs[RTN * LDXN];
+  __shared__ TI ms[32 * 32];
+  __shared__ double colsq[8][32];
+  if (predicated && sc->err != 0) return;        // a failed small solve leaves the block untouched
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  const uint32_t row0 = blockIdx.x * RTN;
+  const uint32_t tc = threadIdx.x & 31u, tg = threadIdx.x >> 5;    // column and row group of the copies
+  const uint32_t wr = wave * 32u;                                  // the wave's first row in the tile
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = zero_acc<acc_t>();
+#pragma unroll
+  for (int s = 0; s < NSRC; ++s) {
+    const TI* X = s == 0 ? X0 : X1;
+    const TI* M = s == 0 ? M0 : M1;
+    if (s > 0) __syncthreads();                  // the previous source's operands are consumed
+#pragma unroll 4
+    for (uint32_t u = 0; u < RTN / 8; ++u) {
+      const uint32_t r = tg + 8u * u, gr = row0 + r;
+      xs[r * LDXN + tc] = (gr < n && tc < N) ? X[(uint64_t)gr * N + tc] : TI(0);
+    }
+    for (uint32_t e = threadIdx.x; e < 32u * 32u; e += 256u) {
+      const uint32_t kk = e >> 5, col = e & 31u;
+      ms[e] = (kk < N && col < N) ? M[(uint64_t)kk * N + col] : TI(0);
+    }
+    __syncthreads();
+    // contraction over the zero-padded 32 indices, in whole MFMA steps
+    for (uint32_t k = 0; k < N; k += MK::KSTEP) {
+      TI av[2][MK::KPL], bv[2][MK::KPL];
+#pragma unroll
+      for (int e = 0; e < MK::KPL; ++e) {
+        const uint32_t kk = k + kr * MK::KPL + e;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a][e] = xs[(wr + a * 16 + ci) * LDXN + kk];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b][e] = ms[kk * 32 + b * 16 + ci];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mma<KIND, TI>(av[a], bv[b], acc[a][b]);
+    }
+  }
+  // every operand read of the tile is done before the result replaces it
+  // (Out may alias X0: in-place Step 4)
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        xs[(wr + a * 16 + MK::drow(kr, r)) * LDXN + b * 16 + ci] = (TI)(ascale * (double)acc[a][b][r]);
+  __syncthreads();
+  double sq = 0.0;
+#pragma unroll 4
+  for (uint32_t u = 0; u < RTN / 8; ++u) {
+    const uint32_t r = tg + 8u * u, gr = row0 + r;
+    if (gr < n && tc < N) {
+      const uint64_t o = (uint64_t)gr * N + tc;
+      TI v = xs[r * LDXN + tc];
+      if (cbeta != 0.0) v += (TI)cbeta * Cm[o];
+      Out[o] = v;
+      sq += (double)v * (double)v;
+    }
+  }
+  if (!want_colsq) return;
+  colsq[tg][tc] = sq;
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) t += colsq[g][threadIdx.x];
+    part[(uint64_t)blockIdx.x * N + threadIdx.x] = t;
   }
 }
 
@@ -632,9 +798,13 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
   if (rps < kstep) rps = kstep;
   ks = (rows + rps - 1) / rps;
   if (ks < 1) ks = 1;
+  const bool narrow = na <= 32 && nb <= 32;    // one 32 x 32 tile; all four waves split the rows
   {
     ProfScope ps(c, OPE_KERNEL_GRAM);
-    if (lds)
+    if (narrow)
+      hipLaunchKernelGGL((k_gram_narrow<TI, KIND>), dim3((uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda,
+                         (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
+    else if (lds)
       hipLaunchKernelGGL((k_gram_lds<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A,
                          (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps,
                          c->part);
@@ -658,13 +828,21 @@ hipError_t rowmm_t(ope_ctx* c, const TI* X0, const TI* M0, const TI* X1, const T
   // LDS-staged panels when every operand row splits into whole, aligned 16-byte chunks
   constexpr uint32_t VPC = 16 / (uint32_t)sizeof(TI);
   auto al16 = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) % 16) == 0; };
-  const bool lds = N % VPC == 0 && al16(X0) && al16(M0) && al16(X1) && al16(M1);
-  const uint32_t rt = lds ? RT2 : RT;
+  const bool narrow = N <= 32;
+  const bool lds = !narrow && N % VPC == 0 && al16(X0) && al16(M0) && al16(X1) && al16(M1);
+  const uint32_t rt = narrow ? RTN : (lds ? RT2 : RT);
   const uint32_t gr = (n + rt - 1) / rt, gc = (N + CT - 1) / CT;
   if (gc != 1 && (Out == X0 || Out == X1)) return hipErrorInvalidValue;  // in place needs one column tile
   if (want_colsq && (int64_t)gr * N > c->part_cap) return hipErrorInvalidValue;
   ProfScope ps(c, OPE_KERNEL_ROWMM);
-  if (lds) {
+  if (narrow) {
+    if (X1)
+      hipLaunchKernelGGL((k_rowmm_narrow<TI, KIND, 2>), dim3(gr), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
+                         ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
+    else
+      hipLaunchKernelGGL((k_rowmm_narrow<TI, KIND, 1>), dim3(gr), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
+                         ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
+  } else if (lds) {
     if (X1)
       hipLaunchKernelGGL((k_rowmm_lds<TI, KIND, 2>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
                          ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);

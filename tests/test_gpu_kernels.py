@@ -51,7 +51,8 @@ def test_apply_h_matches_oracle(name, mk, N):
     assert np.max(np.abs(Y - ref)) <= stencil_bound(op, X)
 
 
-@pytest.mark.parametrize("n,na,nb", [(1000, 8, 8), (4099, 17, 33), (777, 1, 5), (5003, 128, 128), (2048, 64, 96)])
+@pytest.mark.parametrize("n,na,nb", [(1000, 8, 8), (4099, 17, 33), (777, 1, 5), (5003, 128, 128), (2048, 64, 96),
+                                     (4099, 17, 17), (3001, 32, 32), (130, 31, 2)])
 def test_gram_exact_on_integers(n, na, nb):
     from paper_2511_06788_amd import ope
     rng = np.random.default_rng(n + na)
@@ -66,10 +67,11 @@ def test_gram_exact_on_integers(n, na, nb):
     assert np.array_equal(G, A.T @ B)
 
 
-def test_gram_strided_and_random():
+@pytest.mark.parametrize("n,lda,na,ldb,nb", [(3001, 40, 33, 24, 20), (3001, 40, 17, 24, 20)])
+def test_gram_strided_and_random(n, lda, na, ldb, nb):
+    """Strided operands; the second shape takes the narrow (at most 32 columns) kernel."""
     from paper_2511_06788_amd import ope
     rng = np.random.default_rng(5)
-    n, lda, na, ldb, nb = 3001, 40, 33, 24, 20
     A = rng.standard_normal((n, lda))
     B = rng.standard_normal((n, ldb))
     p = W.harmonic_2d_32(m=8, N=8)
@@ -83,7 +85,8 @@ def test_gram_strided_and_random():
     assert np.all(np.abs(G - ref) <= bound)
 
 
-@pytest.mark.parametrize("m,N", [((40, 30), 8), ((17, 9, 7), 17), ((16, 16, 16), 128), ((5, 3), 1)])
+@pytest.mark.parametrize("m,N", [((40, 30), 8), ((17, 9, 7), 17), ((16, 16, 16), 128), ((5, 3), 1),
+                                 ((13, 11, 9), 32)])
 def test_update_exact_on_integers(m, N):
     """Step 4, U <- U Z1 + Y Z2 in place, with integer data (exact)."""
     from paper_2511_06788_amd import ope

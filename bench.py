@@ -224,8 +224,8 @@ def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
             torch.cuda.synchronize()
             return time.perf_counter() - t0, inner
 
-        # algorithmic bytes of the CG sweeps: 8 n x N block passes per iteration
-        blk = [8 * p.grid.n * p.N * 8 for p in probs]
+        # algorithmic bytes of the CG sweeps: 7.5 n x N block passes per iteration
+        blk = [7.5 * p.grid.n * p.N * 8 for p in probs]
 
         def batch_steps():
             inner, nbytes = 0, 0

@@ -304,8 +304,10 @@ ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double 
  * work-groups spread over (problem, tile) work items of every problem's own
  * sweep shape; same kernels and summation order as the per-problem launches,
  * so the results are identical.  shared = 0 (default): every problem's CG
- * runs on its own stream (measured: as fast as shared launches after the
- * autotuner, faster before it). */
+ * runs on its own stream.  Measured: on the 64-problem workload (grid edges
+ * 24..48, N 16..128) per-problem launches are 4-8% faster; on a batch of
+ * small problems alone shared launches are faster (2.2x for sixteen 24^3,
+ * N = 16 problems), on a batch of large ones slightly slower. */
 ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
 /* Autotuner: for every bucket of problems (grid edges and vector-column count
  * in steps of 8) time short CG runs of the first problem over the sweep shapes

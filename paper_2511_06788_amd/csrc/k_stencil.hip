@@ -540,22 +540,27 @@ __global__ __launch_bounds__(OPE_WG) void k_march(const T* __restrict__ F0, cons
 }
 
 // Batched form: one launch for the CG sweeps of many problems of the same
-// storage type and shape class.  The XCD-remapped work-group index is a work
-// item (problem, tile): problem j owns items [wg_begin, wg_begin + wg_count),
-// so each XCD streams a contiguous range of one problem's lines.
+// storage type and shape class.  Problem j owns work-groups [wg_begin,
+// wg_begin + wg_count rounded up to 8) (wg_begin a multiple of 8), remapped
+// within the problem so that each XCD streams one contiguous eighth of every
+// problem: a remap over the whole launch would give each XCD a range of
+// whole problems, and their work per item differs widely (the work of the
+// launch would not be spread evenly over the XCDs).
 template <typename T, int VW, int Q, int MODE, bool FIRST, bool HALO, bool LN>
 __global__ __launch_bounds__(OPE_WG) void k_march_batched(const MarchJob* __restrict__ jobs, uint32_t njobs) {
-  const uint32_t gt = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = blockIdx.x;
   uint32_t lo = 0, hi = njobs;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) / 2;
-    if (jobs[mid].wg_begin <= gt) lo = mid;
+    if (jobs[mid].wg_begin <= b) lo = mid;
     else hi = mid;
   }
   const MarchJob& jb = jobs[lo];
+  const uint32_t t = xcd_remap(b - jb.wg_begin, (jb.wg_count + 7u) & ~7u);
+  if (t >= jb.wg_count) return;      // padding of the problem's range
   const OpeGrid g = jb.g;
   const MarchShape ms = jb.ms;
-  march_body<T, VW, Q, MODE, FIRST, HALO, LN>(gt - jb.wg_begin, (const T*)jb.F0, (const T*)jb.F1, (T*)jb.O0, (T*)jb.O1,
+  march_body<T, VW, Q, MODE, FIRST, HALO, LN>(t, (const T*)jb.F0, (const T*)jb.F1, (T*)jb.O0, (T*)jb.O1,
                                     (T*)jb.Yv, jb.alpha, jb.beta, jb.active, (const T*)jb.diag, g, ms, jb.N, jb.NV,
                                     jb.part, jb.sc);
 }

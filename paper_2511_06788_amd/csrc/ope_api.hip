@@ -570,7 +570,7 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
         jb.sc = c->sc;
         jb.wg_begin = wg;
         jb.wg_count = jb.ms.lgroups * jb.ms.nxs * jb.ms.cc * jb.ms.mc;
-        wg += jb.wg_count;
+        wg += (jb.wg_count + 7u) & ~7u;          // whole groups of 8: one per XCD
       }
     }
     cls_total[k] = wg;
@@ -694,8 +694,13 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
   // CG phase and class (storage type, vector width, passes per plane, split x
   // lines) on the batch's CG stream; the others run their own chunks on their
   // own streams.
+  // Per-problem CG keeps two chunks in flight per problem, as run_cg does: a
+  // problem's next chunk is enqueued before the flags of its previous one are
+  // read, so the GPU does not drain while the host checks (a chunk enqueued
+  // after convergence does nothing).
   std::vector<char> pending(go), shared(P, 0);
   for (int i = 0; i < P; ++i) shared[i] = go[i] && b->shared && shared_fits(b->ctx[i]);
+  std::vector<int> head(P, 0), nout(P, 0), slot_next(P, 0), q0(P, 0), q1(P, 0);
   int32_t it_shared = 0;
   for (;;) {
     bool any = false, any_shared = false;
@@ -706,9 +711,16 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
         any_shared = true;
         continue;
       }
-      if (cg_chunk(b->ctx[i], &bs.it[i], b->ctx[i]->max_iter, 0) != hipSuccess) {
-        bs.st[i] = OPE_EHIP;
-        pending[i] = go[i] = 0;
+      ope_ctx* c = b->ctx[i];
+      while (bs.it[i] < c->max_iter && nout[i] < 2) {
+        if (cg_chunk(c, &bs.it[i], c->max_iter, slot_next[i]) != hipSuccess) {
+          bs.st[i] = OPE_EHIP;
+          pending[i] = go[i] = 0;
+          break;
+        }
+        (((head[i] + nout[i]) & 1) ? q1 : q0)[i] = slot_next[i];
+        ++nout[i];
+        slot_next[i] ^= 1;
       }
     }
     if (!any) break;
@@ -734,11 +746,18 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
         }
         continue;
       }
-      HIPCHK(hipEventSynchronize(c->chunk_ev[0]));
-      if (cg_all_done(c, 0)) {
+      if (nout[i] == 0) {            // max_iter reached and every chunk read
+        pending[i] = 0;
+        continue;
+      }
+      const int slot = (head[i] ? q1 : q0)[i];
+      head[i] ^= 1;
+      --nout[i];
+      HIPCHK(hipEventSynchronize(c->chunk_ev[slot]));
+      if (cg_all_done(c, slot)) {
         bs.cgdone[i] = 1;
         pending[i] = 0;
-      } else if (bs.it[i] >= c->max_iter) {
+      } else if (bs.it[i] >= c->max_iter && nout[i] == 0) {
         pending[i] = 0;
       }
     }

@@ -28,7 +28,7 @@ def _dev(a, prec):
 
 def _ragged():
     return [W.wells_3d(m=13, N=5, seed=1), W.wells_3d(m=20, N=17, seed=2), W.harmonic_2d_32(),
-            W.wells_3d(m=16, N=34, seed=3), W.wells_3d(m=11, N=3, seed=4)]
+            W.wells_3d(m=16, N=34, seed=3), W.wells_3d(m=11, N=3, seed=4), W.wells_3d(m=28, N=48, seed=5)]
 
 
 @pytest.mark.parametrize("shared", [True, False])

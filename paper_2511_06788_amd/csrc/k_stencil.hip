@@ -688,20 +688,19 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict
   else cg_finalise<MODE>(col, tot, alpha, beta, rho, target, active, sc);
 }
 
-// The same column sums for few columns (ncols <= 128) by one work-group with
-// no second stage: thread t sums column t % ncols over rows t / ncols,
-// t / ncols + G, ... (G = 256 / ncols row groups, eight loads in flight), then
-// the groups are added in order.  Avoids the cross-work-group fence of the
-// split form, which writes back the L2 lines the preceding sweep left dirty.
-template <int MODE>
-__global__ __launch_bounds__(OPE_WG) void k_reduce_few(const double* __restrict__ part, uint32_t nrows,
-                                                       uint32_t ncols, double* __restrict__ out,
-                                                       double* __restrict__ alpha, double* __restrict__ beta,
-                                                       double* __restrict__ rho, const double* __restrict__ target,
-                                                       int32_t* __restrict__ active, OpeScalars* __restrict__ sc) {
-  __shared__ double red[OPE_WG];
-  const uint32_t G = OPE_WG / ncols;
-  const uint32_t col = threadIdx.x % ncols, gi = threadIdx.x / ncols;
+// The same column sums for few columns (ncols <= 128) by one 1024-thread
+// work-group with no second stage: thread t sums column t % ncols over rows
+// t / ncols, t / ncols + G, ... (G = 1024 / ncols row groups, eight loads in
+// flight), then the groups are added in order (the single and the batched
+// kernel share this order).  Avoids the cross-work-group fence of the split
+// form, which writes back the L2 lines the preceding sweep left dirty.
+constexpr uint32_t RED_WG = 1024;
+
+__device__ __forceinline__ double few_cols_sum(const double* __restrict__ part, uint32_t nrows, uint32_t ncols,
+                                               double* red, uint32_t& col, bool& lead) {
+  const uint32_t G = RED_WG / ncols;
+  col = threadIdx.x % ncols;
+  const uint32_t gi = threadIdx.x / ncols;
   double a = 0.0;
   if (gi < G) {
     double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -715,9 +714,24 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_few(const double* __restrict_
   }
   red[threadIdx.x] = a;
   __syncthreads();
-  if (gi != 0) return;
+  lead = gi == 0;
   double tot = 0.0;
-  for (uint32_t k = 0; k < G; ++k) tot += red[k * ncols + col];
+  if (lead)
+    for (uint32_t k = 0; k < G; ++k) tot += red[k * ncols + col];
+  return tot;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(RED_WG) void k_reduce_few(const double* __restrict__ part, uint32_t nrows,
+                                                       uint32_t ncols, double* __restrict__ out,
+                                                       double* __restrict__ alpha, double* __restrict__ beta,
+                                                       double* __restrict__ rho, const double* __restrict__ target,
+                                                       int32_t* __restrict__ active, OpeScalars* __restrict__ sc) {
+  __shared__ double red[RED_WG];
+  uint32_t col;
+  bool lead;
+  const double tot = few_cols_sum(part, nrows, ncols, red, col, lead);
+  if (!lead) return;
   if (MODE == RED_PLAIN) out[col] = tot;
   else cg_finalise<MODE>(col, tot, alpha, beta, rho, target, active, sc);
 }
@@ -726,30 +740,14 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_few(const double* __restrict_
 // par: the CG iteration's parity, which selects the half of the problem's
 // alpha array (2 ncols entries) the alpha reduction writes.
 template <int MODE>
-__global__ __launch_bounds__(OPE_WG) void k_reduce_batched(const ReduceJob* __restrict__ jobs, uint32_t par) {
-  __shared__ double red[OPE_WG];
+__global__ __launch_bounds__(RED_WG) void k_reduce_batched(const ReduceJob* __restrict__ jobs, uint32_t par) {
+  __shared__ double red[RED_WG];
   const ReduceJob& jb = jobs[blockIdx.x];
-  const uint32_t nrows = jb.nrows, ncols = jb.ncols;
-  const double* part = jb.part;
-  const uint32_t G = OPE_WG / ncols;
-  const uint32_t col = threadIdx.x % ncols, gi = threadIdx.x / ncols;
-  double a = 0.0;
-  if (gi < G) {
-    double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    uint32_t w = gi;
-    for (; w + 7 * G < nrows; w += 8 * G) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] += part[(uint64_t)(w + u * G) * ncols + col];
-    }
-    for (; w < nrows; w += G) q[0] += part[(uint64_t)w * ncols + col];
-    a = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
-  }
-  red[threadIdx.x] = a;
-  __syncthreads();
-  if (gi != 0) return;
-  double tot = 0.0;
-  for (uint32_t k = 0; k < G; ++k) tot += red[k * ncols + col];
-  cg_finalise<MODE>(col, tot, jb.alpha + (uint64_t)par * ncols, jb.beta, jb.rho, jb.target, jb.active, jb.sc);
+  uint32_t col;
+  bool lead;
+  const double tot = few_cols_sum(jb.part, jb.nrows, jb.ncols, red, col, lead);
+  if (!lead) return;
+  cg_finalise<MODE>(col, tot, jb.alpha + (uint64_t)par * jb.ncols, jb.beta, jb.rho, jb.target, jb.active, jb.sc);
 }
 
 // y[i][j] += alpha[j] p[i][j] over n x N (a CG that stopped on an even
@@ -938,15 +936,15 @@ hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int
     const uint32_t nr = (uint32_t)nrows, nc = (uint32_t)ncols;
     switch (mode) {
       case RED_PLAIN:
-        hipLaunchKernelGGL((k_reduce_few<RED_PLAIN>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out, alpha,
+        hipLaunchKernelGGL((k_reduce_few<RED_PLAIN>), dim3(1), dim3(RED_WG), 0, c->stream, part, nr, nc, out, alpha,
                            c->beta, c->rho, c->target, c->active, c->sc);
         break;
       case RED_CG_ALPHA:
-        hipLaunchKernelGGL((k_reduce_few<RED_CG_ALPHA>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out,
+        hipLaunchKernelGGL((k_reduce_few<RED_CG_ALPHA>), dim3(1), dim3(RED_WG), 0, c->stream, part, nr, nc, out,
                            alpha, c->beta, c->rho, c->target, c->active, c->sc);
         break;
       default:
-        hipLaunchKernelGGL((k_reduce_few<RED_CG_BETA>), dim3(1), dim3(OPE_WG), 0, c->stream, part, nr, nc, out,
+        hipLaunchKernelGGL((k_reduce_few<RED_CG_BETA>), dim3(1), dim3(RED_WG), 0, c->stream, part, nr, nc, out,
                            alpha, c->beta, c->rho, c->target, c->active, c->sc);
         break;
     }
@@ -1053,9 +1051,9 @@ hipError_t launch_march_batched(hipStream_t s, int prec, int vw, int q, int halo
 hipError_t launch_reduce_batched(hipStream_t s, int mode, int par, const ReduceJob* jobs, uint32_t njobs) {
   if (njobs == 0) return hipSuccess;
   if (mode == RED_CG_ALPHA)
-    hipLaunchKernelGGL((k_reduce_batched<RED_CG_ALPHA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs, (uint32_t)par);
+    hipLaunchKernelGGL((k_reduce_batched<RED_CG_ALPHA>), dim3(njobs), dim3(RED_WG), 0, s, jobs, (uint32_t)par);
   else
-    hipLaunchKernelGGL((k_reduce_batched<RED_CG_BETA>), dim3(njobs), dim3(OPE_WG), 0, s, jobs, (uint32_t)par);
+    hipLaunchKernelGGL((k_reduce_batched<RED_CG_BETA>), dim3(njobs), dim3(RED_WG), 0, s, jobs, (uint32_t)par);
   return hipGetLastError();
 }
 

@@ -36,50 +36,105 @@ __device__ double wg_sum(double v, double* red) {
   return out;
 }
 
-// In-place Gauss-Jordan inversion of the register-resident matrix w.
-// Sets *bad when a pivot is not a finite number above 1e-300.
-// Pivot k: the pivot column is published in LDS in the owners' row order
-// (F[q * 16 + r] holds row q + 8 r, so a thread reads its 16 multipliers
-// contiguously) and the pivot row as R[j]; the column's own lanes then hold
-// zero, so every element takes the one update w - F_i r_j (r_j = R[j] / piv,
-// 1 / piv in column k), and the waves of row k write the scaled pivot row r_j.
-__device__ void gj_invert(double (&w)[RPT], uint32_t N, double* fcol, double* rowk, int* bad) {
+// In-place Gauss-Jordan inversion of the register-resident matrix w, four
+// pivots per block step (the arithmetic of four successive single pivots,
+// regrouped):  with K the block's pivot indices, P = W[K,K] and
+// X = P^{-1} [W[K,:] with W[K,K] replaced by I],
+//   rows not in K:  W[i,:] <- W'[i,:] - W[i,K] X   (W' = W with columns K zeroed)
+//   rows in K:      W[K,:] <- X.
+// LDS per block step (double-buffered by step parity): the pivot columns
+// F[c][q * 16 + r] (row q + 8 r, so a thread reads its rows contiguously), the
+// pivot rows R[c][j], and X[c][j], which the 128 threads of row group 0 solve
+// for their column from P by Gauss-Jordan (a 4 x 4 system per column, so one
+// barrier per step serves four pivots instead of one).  Sets *bad when a
+// pivot of the elimination is not a finite number above 1e-300.
+constexpr int GJB = 4;      // pivots per block step
+
+struct GjLds {
+  double F[2][GJB][128];
+  double R[2][GJB][128];
+  double X[2][GJB][128];
+};
+
+__device__ void gj_invert(double (&w)[RPT], uint32_t N, GjLds& L, int* bad) {
   const Own o;
-  for (uint32_t k = 0; k < N; ++k) {
-    double* F = fcol + (k & 1u) * 128;
-    double* R = rowk + (k & 1u) * 128;
-    const bool krow = o.q == (k & 7u);          // this wave holds row k (as w[k / 8])
-    const uint32_t kr = k >> 3;
+  for (uint32_t k0 = 0, st = 0; k0 < N; k0 += GJB, st ^= 1u) {
+    const uint32_t kb = min((uint32_t)GJB, N - k0);     // pivots of this step
+    double(&F)[GJB][128] = L.F[st];
+    double(&R)[GJB][128] = L.R[st];
+    double(&X)[GJB][128] = L.X[st];
+    const uint32_t kr = k0 >> 3;                         // register row of the pivot rows
+    const uint32_t q0 = k0 & 7u;                         // their row groups: q0 .. q0 + kb - 1
+    const bool krow = o.q >= q0 && o.q < q0 + kb;        // this wave holds a pivot row (as w[kr])
+    // pivot rows first (they include the block), then the pivot columns,
+    // which their lanes then zero
     if (krow && o.j < N) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if ((uint32_t)r == kr) R[o.j] = w[r];
+        if ((uint32_t)r == kr) R[o.q - q0][o.j] = w[r];
     }
-    if (o.j == k) {
+    if (o.j >= k0 && o.j < k0 + kb) {
+      const uint32_t c = o.j - k0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        F[o.q * 16u + r] = w[r];
+        F[c][o.q * 16u + r] = w[r];
         w[r] = 0.0;
       }
     }
     __syncthreads();
-    const double piv = F[(k & 7u) * 16u + kr];
-    const bool ok = isfinite(piv) && piv > 1e-300;
-    if (!ok && threadIdx.x == 0) *bad = 1;
-    const double pinv = ok ? 1.0 / piv : 0.0;
-    const double rk = (o.j == k ? 1.0 : R[o.j & 127u]) * pinv;
-    if (o.j < N) {
-      const double2* F2 = reinterpret_cast<const double2*>(F + o.q * 16u);
+    if (o.q == 0 && o.j < N) {
+      // solve P x = b for this column: b = R[:, j], or the unit vector of
+      // column j when j is a pivot column
+      double P[GJB][GJB], x[GJB];
 #pragma unroll
-      for (int r = 0; r < RPT / 2; ++r) {
-        const double2 f = F2[r];
-        w[2 * r] = fma(-f.x, rk, w[2 * r]);
-        w[2 * r + 1] = fma(-f.y, rk, w[2 * r + 1]);
+      for (int c = 0; c < GJB; ++c) {
+#pragma unroll
+        for (int d = 0; d < GJB; ++d)
+          P[c][d] = ((uint32_t)c < kb && (uint32_t)d < kb) ? R[c][k0 + d] : (c == d ? 1.0 : 0.0);
+        const bool inK = o.j >= k0 && o.j < k0 + kb;
+        x[c] = (uint32_t)c < kb ? (inK ? (o.j - k0 == (uint32_t)c ? 1.0 : 0.0) : R[c][o.j]) : 0.0;
+      }
+#pragma unroll
+      for (int p = 0; p < GJB; ++p) {
+        const double piv = P[p][p];
+        const bool ok = isfinite(piv) && piv > 1e-300;
+        if (!ok && (uint32_t)p < kb && o.j == 0) *bad = 1;
+        const double pinv = ok ? 1.0 / piv : 0.0;
+#pragma unroll
+        for (int d = 0; d < GJB; ++d) P[p][d] *= pinv;
+        x[p] *= pinv;
+#pragma unroll
+        for (int c = 0; c < GJB; ++c) {
+          if (c == p) continue;
+          const double f = P[c][p];
+#pragma unroll
+          for (int d = 0; d < GJB; ++d) P[c][d] = fma(-f, P[p][d], P[c][d]);
+          x[c] = fma(-f, x[p], x[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < GJB; ++c) X[c][o.j] = x[c];
+    }
+    __syncthreads();
+    if (o.j < N) {
+      double xj[GJB];
+#pragma unroll
+      for (int c = 0; c < GJB; ++c) xj[c] = X[c][o.j];
+#pragma unroll
+      for (int c = 0; c < GJB; ++c) {
+        if ((uint32_t)c >= kb) break;                    // slots past the last pivot hold no column
+        const double2* F2 = reinterpret_cast<const double2*>(&F[c][o.q * 16u]);
+#pragma unroll
+        for (int r = 0; r < RPT / 2; ++r) {
+          const double2 f = F2[r];
+          w[2 * r] = fma(-f.x, xj[c], w[2 * r]);
+          w[2 * r + 1] = fma(-f.y, xj[c], w[2 * r + 1]);
+        }
       }
       if (krow) {
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
-          if ((uint32_t)r == kr) w[r] = rk;
+          if ((uint32_t)r == kr) w[r] = xj[o.q - q0];
       }
     }
   }
@@ -110,8 +165,7 @@ __global__ __launch_bounds__(SW) void k_prep_small(const double* __restrict__ C,
                                                    uint32_t N, OpeScalars* __restrict__ sc, float* __restrict__ Lam32,
                                                    float* __restrict__ Linv32) {
   __shared__ double red[SW];
-  __shared__ __align__(16) double fcol[256];
-  __shared__ double rowk[256];
+  __shared__ __align__(16) GjLds gl;
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
@@ -138,7 +192,7 @@ __global__ __launch_bounds__(SW) void k_prep_small(const double* __restrict__ C,
   e = wg_sum(e, red);
   lf = wg_sum(lf, red);
   dr = wg_sum(dr, red);
-  gj_invert(w, N, fcol, rowk, &bad);
+  gj_invert(w, N, gl, &bad);
   store_own(Linv, N, w);
   if (Linv32) {
 #pragma unroll
@@ -221,8 +275,7 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
                                                     double* __restrict__ Z, double* __restrict__ Aout,
                                                     OpeScalars* __restrict__ sc) {
   extern __shared__ double smat[];
-  __shared__ __align__(16) double fcol[256];
-  __shared__ double rowk[256];
+  __shared__ __align__(16) GjLds gl;
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
@@ -255,7 +308,7 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
       w[r] = 0.0;
     }
   }
-  gj_invert(w, N, fcol, rowk, &bad);
+  gj_invert(w, N, gl, &bad);
   store_own(Bws, N, w);           // B
   __syncthreads();
   // A = 2/tau (I - B) + S_b B (B's columns from global memory, the next
@@ -304,8 +357,7 @@ __global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restri
                                                           double* __restrict__ Wsm, float* __restrict__ Z32,
                                                           OpeScalars* __restrict__ sc) {
   extern __shared__ double smat[];
-  __shared__ __align__(16) double fcol[256];
-  __shared__ double rowk[256];
+  __shared__ __align__(16) GjLds gl;
   __shared__ int bad;
   const Own o;
   if (threadIdx.x == 0) bad = 0;
@@ -358,7 +410,7 @@ __global__ __launch_bounds__(SW) void k_small_solve_delta(const double* __restri
       w[r] = 0.0;
     }
   }
-  gj_invert(w, N, fcol, rowk, &bad);
+  gj_invert(w, N, gl, &bad);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const uint32_t i = o.row(r);

@@ -166,19 +166,21 @@ def test_source_solve_residual_and_dense(name, mk, N):
     assert np.max(np.abs(Y - Yx)) <= 1e-8 * np.max(np.abs(Yx))
 
 
+@pytest.mark.parametrize("graphs", [False, True])
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 6])
-def test_capped_cg_equals_textbook_iterates(k):
+def test_capped_cg_equals_textbook_iterates(k, graphs):
     """After exactly k CG iterations (no column converged) the device solution
     equals the oracle's textbook CG iterate: y is updated in pairs of
     iterations on the device, and an odd count ends with the deferred term of
-    the last iteration added (k = 5, 6 also mix a captured 4-iteration chunk
-    with eager iterations)."""
+    the last iteration added (with graphs on, k = 5, 6 mix a captured
+    4-iteration chunk with eager iterations)."""
     from paper_2511_06788_amd import ope
     p = W.wells_3d(m=13, N=6, seed=11)
     op = _op(p)
     U = W.initial_block(p.grid.n, p.N, 5)
-    say(f"capped CG k={k}")
+    say(f"capped CG k={k} graphs={graphs}")
     with _ctx(p) as ctx:
+        ope.ope_set_graphs(ctx.handle, graphs)
         Yd = empty_dev(p.grid.n, p.N)
         its = ope.ope_source_solve(ctx.handle, to_dev(U), Yd, None, 1e-14, k, allow_maxit=True)
         Y = to_host(Yd)

@@ -311,7 +311,7 @@ ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double 
 ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
 /* Autotuner: for every bucket of problems (grid edges and vector-column count
  * in steps of 8) time short CG runs of the first problem over the sweep shapes
- * (passes per plane 1/2 or the two- and four-line tiles, work-group order,
+ * (passes per plane 1/2 or the two-, four- and eight-line tiles, work-group order,
  * non-temporal stores, column chunking, march chunks)
  * and give every problem of the bucket the fastest; FP32 contexts keep the
  * default.  *tuned (nullable) = number of buckets.  Synchronises; uses a

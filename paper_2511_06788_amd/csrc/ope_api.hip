@@ -1487,6 +1487,77 @@ ope_status ope_batch_solve(ope_batch* b, void* const* U, double tau, double res_
   return first;
 }
 
+namespace {
+
+struct TunedShape {
+  int q, mc, flags;
+};
+
+// The fastest sweep shape of an FP64 context for short CG runs on the scratch
+// right-hand side X (n x N): passes per plane 1/2 or the two-, four- and
+// eight-line tiles, work-group order, non-temporal stores, column chunking,
+// and the automatic march-chunk count times 1/2, 1, 3/2 or 2.  Leaves the
+// context on the last shape tried.
+TunedShape tune_shape(ope_ctx* c, const double* X, hipEvent_t e0, hipEvent_t e1) {
+  const uint32_t NV = (uint32_t)(c->N / c->vw);
+  TunedShape pick{2, 0, default_sweep_flags(c)};
+  double tbest = 1e30;
+  const int narrow_opts = NV <= 32 ? 2 : 1;
+  // qs = 3, 4 and 5 stand for the two-, four- and eight-line tiles (q 2)
+  for (int qs : {1, 2, 3, 4, 5})
+    for (int cm : {0, OPE_SWEEP_CHUNK_MAJOR})
+      for (int nt : {0, OPE_SWEEP_NONTEMPORAL})
+        for (int nr = 0; nr < narrow_opts; ++nr)
+          for (int mcm : {2, 4, 6, 8}) {     // the automatic count times mcm / 4
+            if (qs >= 3 && c->g.dim != 3) continue;
+            const int q = qs >= 3 ? 2 : qs;
+            const int flags = cm | nt | (nr ? OPE_SWEEP_NARROW : 0) | (qs == 3 ? OPE_SWEEP_LINES : 0) |
+                              (qs == 4 ? OPE_SWEEP_LINES4 : 0) | (qs == 5 ? OPE_SWEEP_LINES8 : 0);
+            if (ope_set_sweep_shape(c, q, 0, flags) != OPE_OK) continue;
+            int mc = 0;
+            if (mcm != 4) {
+              mc = ((int)c->ms.mc * mcm + 2) / 4;
+              if (mc < 1) mc = 1;
+              if (mc == (int)c->ms.mc) continue;       // the automatic count, timed with mcm = 4
+              if (ope_set_sweep_shape(c, q, mc, flags) != OPE_OK) continue;
+            }
+            const double t = time_cg(c, X, e0, e1);
+            if (t < tbest) {
+              tbest = t;
+              pick = TunedShape{q, mc, flags};
+            }
+          }
+  return pick;
+}
+
+}  // namespace
+
+ope_status ope_autotune(ope_ctx* c) {
+  if (!c) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_OK;          // FP32 contexts keep the default shape
+  HIPCHK(hipStreamSynchronize(c->stream));
+  void* X = nullptr;
+  const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
+  if (hipMalloc(&X, bytes) != hipSuccess) return OPE_ENOMEM;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(X);
+    return OPE_EHIP;
+  }
+  // any non-zero right-hand side (the sweeps' cost does not depend on it)
+  ope_status st = hipMemsetAsync(X, 0x3F, bytes, c->stream) == hipSuccess ? OPE_OK : OPE_EHIP;
+  if (st == OPE_OK) {
+    const TunedShape t = tune_shape(c, (const double*)X, e0, e1);
+    if (ope_set_sweep_shape(c, t.q, t.mc, t.flags) != OPE_OK) (void)ope_set_sweep_shape(c, 2, 0, default_sweep_flags(c));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) st = OPE_EHIP;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(X);
+  return st;
+}
+
 ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
   if (!b) return OPE_EINVAL;
   // bucket of a problem: grid edge and vector-column count, each in steps of 8
@@ -1497,10 +1568,7 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
       return std::tie(dim, prec, vw, mx, my, mz, nv) < std::tie(o.dim, o.prec, o.vw, o.mx, o.my, o.mz, o.nv);
     }
   };
-  struct Shape {
-    int q, mc, flags;
-  };
-  std::map<Key, Shape> best;
+  std::map<Key, TunedShape> best;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1514,7 +1582,7 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
     auto f = best.find(k);
     if (f == best.end()) {
       if (c->prec != OPE_FP64) {
-        best[k] = Shape{2, 0, default_sweep_flags(c)};   // FP32 contexts keep the default shape
+        best[k] = TunedShape{2, 0, default_sweep_flags(c)};   // FP32 contexts keep the default shape
       } else {
         void* X = nullptr;
         const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
@@ -1524,31 +1592,7 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
         }
         // any non-zero right-hand side (the sweeps' cost does not depend on it)
         (void)hipMemsetAsync(X, 0x3F, bytes, c->stream);
-        Shape pick{2, 0, default_sweep_flags(c)};
-        double tbest = 1e30;
-        const int narrow_opts = NV <= 32 ? 2 : 1;
-        // qs = 3, 4 and 5 stand for the two-, four- and eight-line tiles (q 2)
-        for (int qs : {1, 2, 3, 4, 5})
-          for (int cm : {0, OPE_SWEEP_CHUNK_MAJOR})
-            for (int nt : {0, OPE_SWEEP_NONTEMPORAL})
-            for (int nr = 0; nr < narrow_opts; ++nr)
-              for (int mcm : {0, 2}) {
-                if (qs >= 3 && c->g.dim != 3) continue;
-                const int q = qs >= 3 ? 2 : qs;
-                const int flags = cm | nt | (nr ? OPE_SWEEP_NARROW : 0) | (qs == 3 ? OPE_SWEEP_LINES : 0) |
-                                  (qs == 4 ? OPE_SWEEP_LINES4 : 0) | (qs == 5 ? OPE_SWEEP_LINES8 : 0);
-                if (ope_set_sweep_shape(c, q, 0, flags) != OPE_OK) continue;
-                int mc = 0;
-                if (mcm == 2) {
-                  mc = (int)c->ms.mc * 2;
-                  if (ope_set_sweep_shape(c, q, mc, flags) != OPE_OK) continue;
-                }
-                const double t = time_cg(c, (const double*)X, e0, e1);
-                if (t < tbest) {
-                  tbest = t;
-                  pick = Shape{q, mc, flags};
-                }
-              }
+        const TunedShape pick = tune_shape(c, (const double*)X, e0, e1);
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(X);
         best[k] = pick;

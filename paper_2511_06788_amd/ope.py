@@ -110,6 +110,7 @@ SIGNATURES = {
     "ope_solve": ([_P, _P, _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
     "ope_set_sweep_shape": ([_P, _I32, _I32, _I32], _I32),
     "ope_set_graphs": ([_P, _I32], _I32),
+    "ope_autotune": ([_P], _I32),
     "ope_batch_create": ([ctypes.POINTER(_P), ctypes.POINTER(ope_op_desc), ctypes.POINTER(_I64), _I32, _I32, _P],
                          _I32),
     "ope_batch_destroy": ([_P], _I32),
@@ -289,6 +290,10 @@ OPE_SWEEP_NARROW = 4
 OPE_SWEEP_LINES = 8
 OPE_SWEEP_LINES4 = 16
 OPE_SWEEP_LINES8 = 32
+
+
+def ope_autotune(ctx: int) -> None:
+    _check(lib().ope_autotune(ctx), "ope_autotune")
 
 
 def ope_set_graphs(ctx: int, enable: bool) -> None:

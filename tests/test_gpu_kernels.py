@@ -207,6 +207,30 @@ def test_energy_residual_ritz_match_oracle():
     assert abs(drift - O.ortho_error(U)) <= 1e-14 * p.N
 
 
+def test_autotune_single_context_keeps_results():
+    """ope_autotune picks the fastest sweep shape by timing; H X and the CG
+    solution then still match the oracle (a shape changes only the summation
+    order of the CG dot products)."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=21, N=17, seed=6)
+    op = _op(p)
+    X = np.random.default_rng(4).standard_normal((p.grid.n, p.N))
+    U = W.initial_block(p.grid.n, p.N, 9)
+    say("autotune single context")
+    with _ctx(p) as ctx:
+        ope.ope_autotune(ctx.handle)
+        q, mc, wgs = ope.ope_get_sweep_shape(ctx.handle)
+        assert q in (1, 2, 4) and mc >= 1 and wgs >= 1
+        Yd = empty_dev(p.grid.n, p.N)
+        ope.ope_apply_h(ctx.handle, to_dev(X), Yd)
+        Y = to_host(Yd)
+        Sd = empty_dev(p.grid.n, p.N)
+        ope.ope_source_solve(ctx.handle, to_dev(U), Sd, None, 1e-11, 20000)
+        S = to_host(Sd)
+    assert np.max(np.abs(Y - O.apply_H(op, X))) <= stencil_bound(op, X)
+    assert np.all(np.linalg.norm(U - O.apply_H(op, S), axis=0) <= 20 * 1e-11)
+
+
 @pytest.mark.parametrize("q_max,chunks,flags", [(1, 1, 0), (2, 3, 1), (4, 0, 2), (4, 5, 3), (1, 0, 3),
                                                  (2, 0, 9), (2, 3, 8), (1, 2, 11), (2, 0, 13),
                                                  (2, 0, 17), (2, 2, 19), (2, 0, 21),

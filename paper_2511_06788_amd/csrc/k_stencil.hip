@@ -137,14 +137,15 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
 typedef unsigned int BufU4 __attribute__((ext_vector_type(4)));
 typedef unsigned int BufU2 __attribute__((ext_vector_type(2)));
 
-// One row chunk (VW elements of T, 4, 8 or 16 bytes) through a descriptor.
-template <typename T, int VW>
+// One row chunk (VW elements of T, 4, 8 or 16 bytes) through a descriptor
+// (AUX: cache policy, AUX_NT for a stream read once).
+template <typename T, int VW, int AUX = 0>
 __device__ __forceinline__ void bld(Rsrc rs, uint32_t off, T (&v)[VW]) {
   constexpr int B = (int)sizeof(T) * VW;
   RowVec<T, VW> t;
-  if constexpr (B == 16) t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-  else if constexpr (B == 8) t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-  else t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+  if constexpr (B == 16) t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, AUX));
+  else if constexpr (B == 8) t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, AUX));
+  else t = __builtin_bit_cast(RowVec<T, VW>, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, AUX));
 #pragma unroll
   for (int k = 0; k < VW; ++k) v[k] = t.v[k];
 }
@@ -364,10 +365,20 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
         if constexpr (TWO) bld<T, VW>(s1, oh[q], L.hp[q]);
       }
       L.d[q] = bld1<T>(dr, od[q]);
-      if constexpr (UPD) bld<T, VW>(rr, oc[q], L.r[q]);
+      // single-use streams: non-temporal when the working set exceeds the
+      // last-level cache (with it, they would hit there; measured slower)
+      if constexpr (UPD) {
+        if (ms.nt) bld<T, VW, AUX_NT>(rr, oc[q], L.r[q]);
+        else bld<T, VW>(rr, oc[q], L.r[q]);
+      }
       if constexpr (YUP) {
-        bld<T, VW>(yr, oc[q], L.y[q]);
-        bld<T, VW>(qr, oc[q], L.pp[q]);
+        if (ms.nt) {
+          bld<T, VW, AUX_NT>(yr, oc[q], L.y[q]);
+          bld<T, VW, AUX_NT>(qr, oc[q], L.pp[q]);
+        } else {
+          bld<T, VW>(yr, oc[q], L.y[q]);
+          bld<T, VW>(qr, oc[q], L.pp[q]);
+        }
       }
     }
   };

@@ -214,3 +214,46 @@ def test_full_size_steps_invariants(full_size):
     assert abs(E2 - O.energy(op, U)) <= 1e-12 * abs(E2)
     assert O.ortho_error(U) <= 1e-11
     assert i1.drift <= 1e-11 and i2.drift <= 1e-11
+
+
+def test_full_size_step_building_blocks_match_oracle(full_size):
+    """64^3, N = 128 in the benchmark's launch shapes, Steps 1-4 from the ABI's
+    building blocks, each checked against the oracle: Step 1's CG on the true
+    residual of every column; the Grams <U,Y>, <Y,Y> against numpy; Steps 2-3
+    (the small solve, from the device Grams) element by element; Step 4 on
+    sampled rows."""
+    from paper_2511_06788_amd import ope
+    p, op = full_size
+    n, N, tau, tol = p.grid.n, p.N, 45.0, 1e-6
+    U = p.U0
+    say("full size building blocks")
+    with _ctx(p) as ctx:
+        Ud = to_dev(U)
+        Yd = empty_dev(n, N)
+        ope.ope_source_solve(ctx.handle, Ud, Yd, None, tol, 20000)
+        Sbd, Td = empty_dev(N, N), empty_dev(N, N)
+        ope.ope_gram(ctx.handle, Ud, N, N, Yd, N, N, n, Sbd)
+        ope.ope_gram(ctx.handle, Yd, N, N, Yd, N, N, n, Td)
+        Zd, Ad, Bd = empty_dev(2 * N, N), empty_dev(N, N), empty_dev(N, N)
+        ope.ope_small_solve(ctx.handle, Sbd, Td, tau, Zd, Ad, Bd)
+        Y, Sb, T, Z, A, B = (to_host(x) for x in (Yd, Sbd, Td, Zd, Ad, Bd))
+        ope.ope_update(ctx.handle, Ud, Yd, Zd)
+        Un = to_host(Ud)
+    # Step 1: every column meets the tolerance on its true residual
+    true_res = np.linalg.norm(U - O.apply_H(op, Y), axis=0)
+    assert np.all(true_res <= 20 * tol * np.linalg.norm(U, axis=0))
+    # Grams
+    assert np.max(np.abs(Sb - U.T @ Y)) <= 1e-12 * np.max(np.abs(Sb))
+    assert np.max(np.abs(T - Y.T @ Y)) <= 1e-12 * np.max(np.abs(T))
+    # Steps 2-3 from the same (device) Grams
+    A_ref, B_ref, _ = O.small_solve(Sb.T, T, tau, S_b=Sb)
+    assert np.max(np.abs(B - B_ref)) <= 1e-11 * max(1.0, np.max(np.abs(B_ref)))
+    assert np.max(np.abs(A - A_ref)) <= 1e-11 * max(1.0, np.max(np.abs(A_ref)))
+    assert np.max(np.abs(Z[:N] - (np.eye(N) - tau * A_ref))) <= 1e-11 * max(1.0, tau * np.max(np.abs(A_ref)))
+    assert np.max(np.abs(Z[N:] - tau * B_ref)) <= 1e-11 * tau * max(1.0, np.max(np.abs(B_ref)))
+    # Step 4 on sampled rows (with the device's Z)
+    rows = np.random.default_rng(12).choice(n, 4096, replace=False)
+    ref = U[rows] @ Z[:N] + Y[rows] @ Z[N:]
+    bound = 4 * N * np.finfo(np.float64).eps * (np.abs(U[rows]) @ np.abs(Z[:N]) + np.abs(Y[rows]) @ np.abs(Z[N:]))
+    assert np.all(np.abs(Un[rows] - ref) <= bound + 1e-300)
+

@@ -4,9 +4,10 @@
 //
 // A 1024-thread work-group holds an N x N matrix in registers: thread t owns
 // column j = t % 128 and rows i = t / 128 + 8 r, r = 0..15.  Gauss-Jordan
-// elimination without pivoting runs with one barrier per pivot (the pivot
-// column and pivot row are published through double-buffered LDS); this is
-// the path for N <= 128, larger N use the Newton-Schulz pieces below.  No
+// elimination without pivoting runs four pivots per block step, with two
+// barriers per step (the pivot columns and rows are published through
+// double-buffered LDS); this is the path for N <= 128, larger N use the
+// Newton-Schulz pieces below.  No
 // pivoting is needed: the Step-2 matrix has symmetric part >= I (Lemma 3.1 and
 // its generalisation to an inexact GU), and Lam = U^T H U is SPD, so every
 // pivot of either is positive.
@@ -45,8 +46,8 @@ __device__ double wg_sum(double v, double* red) {
 // LDS per block step (double-buffered by step parity): the pivot columns
 // F[c][q * 16 + r] (row q + 8 r, so a thread reads its rows contiguously), the
 // pivot rows R[c][j], and X[c][j], which the 128 threads of row group 0 solve
-// for their column from P by Gauss-Jordan (a 4 x 4 system per column, so one
-// barrier per step serves four pivots instead of one).  Sets *bad when a
+// for their column from P by Gauss-Jordan (a 4 x 4 system per column: two
+// barriers per step serve four pivots, instead of one barrier per pivot).  Sets *bad when a
 // pivot of the elimination is not a finite number above 1e-300.
 constexpr int GJB = 4;      // pivots per block step
 

@@ -17,9 +17,16 @@
 // D[4 (l / 16) + r][l % 16] for the FP32 and BF16 instructions.
 //
 // For the Gram the contraction index is the grid row, so a lane reads
-// X[row0 + k][i0 + l%16]: rows of 16 consecutive orbitals, straight from
-// global memory.  Split-K over rows writes one partial per split (in FP64);
-// a fixed-order column reduction follows, so results are bitwise reproducible.
+// X[row0 + k][i0 + l%16]: rows of 16 consecutive orbitals.  Split-K over rows
+// writes one partial per split (in FP64); a fixed-order column reduction
+// follows, so results are bitwise reproducible.
+//
+// Kernels by shape: wide operands (>= 128 columns, 16-byte rows) stage
+// panels in LDS with 128 x 128 work-group tiles (k_gram_lds, k_rowmm_lds);
+// narrow blocks (<= 32 columns) use k_gram_narrow (the four waves split the
+// rows of one 32 x 32 tile) and k_rowmm_narrow (128-row tiles through LDS);
+// the rest read their operands straight from global memory (k_gram,
+// k_gram_wide, k_rowmm).
 #include "ope_internal.h"
 
 namespace {

@@ -706,6 +706,10 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict
 // kernel share this order).  Avoids the cross-work-group fence of the split
 // form, which writes back the L2 lines the preceding sweep left dirty.
 constexpr uint32_t RED_WG = 1024;
+// Largest partial array (rows x columns) summed by one work-group; longer ones
+// take the two-launch split (measured: one work-group needs 10.5 us for the
+// 512 x 128 partials of the FP32 sweeps at 64^3, N = 128).
+constexpr int64_t FEW_MAX = (int64_t)1 << 15;
 
 __device__ __forceinline__ double few_cols_sum(const double* __restrict__ part, uint32_t nrows, uint32_t ncols,
                                                double* red, uint32_t& col, bool& lead) {
@@ -943,7 +947,7 @@ hipError_t launch_y_flush(ope_ctx* c, hipStream_t s, void* y, const void* p, con
 hipError_t launch_reduce_cols(ope_ctx* c, const double* part, int64_t nrows, int64_t ncols, double* out, int mode,
                               double* alpha) {
   if (!alpha) alpha = c->alpha;
-  if (ncols <= 128 && nrows * ncols <= (int64_t)1 << 17) {
+  if (ncols <= 128 && nrows * ncols <= FEW_MAX) {
     const uint32_t nr = (uint32_t)nrows, nc = (uint32_t)ncols;
     switch (mode) {
       case RED_PLAIN:
@@ -1005,7 +1009,7 @@ hipError_t launch_resid0(ope_ctx* c, const double* U, const double* HY, double* 
 }
 
 bool reduce_few_fits(const ope_ctx* c) {
-  return c->N <= 128 && march_rows(c) * c->N <= ((int64_t)1 << 17);
+  return c->N <= 128 && march_rows(c) * c->N <= FEW_MAX;
 }
 
 template <typename T, int VW, int Q, int MODE, bool FIRST, bool LN>

@@ -274,9 +274,10 @@ ope_status ope_step_learned(ope_ctx* ctx, void* U, double tau, ope_step_info* in
  * Many independent problems (each its own grid, potential and N) stepped
  * together.  Every problem gets its own context and a private stream (default
  * priority); a batch step enqueues the pre-phase of every problem, then rounds
- * of Step-1 CG chunks (graph replays) in which each problem drops out as soon
- * as its own columns have converged, then Steps 2-4 of every problem, so the
- * problems' kernels overlap on the GPU.  Each problem's result is exactly that
+ * of Step-1 CG chunks (two in flight per problem; graph replays when graphs
+ * are on) in which each problem drops out as soon as its own columns have
+ * converged, then Steps 2-4 of every problem, so the problems' kernels overlap
+ * on the GPU.  Each problem's result is exactly that
  * of ope_step on its own context.  The batch is ordered after earlier work on
  * `stream` (NULL: the default stream) and later work on it waits for the batch. */
 typedef struct ope_batch ope_batch;
@@ -298,11 +299,11 @@ ope_status ope_batch_step(ope_batch* batch, void* const* U, double tau, ope_step
 ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double res_tol, int32_t max_steps,
                            ope_solve_info* info);
 /* shared = 1: Step 1's CG sweeps and column reductions of all
- * problems whose column sums fit one work-group (at most 128 columns) run as
- * one launch per phase and class of problems (storage type, vector width,
- * passes per plane, split x lines, two-line tiles) on a batch stream, each launch's
- * work-groups spread over (problem, tile) work items of every problem's own
- * sweep shape; same kernels and summation order as the per-problem launches,
+ * problems whose column sums fit one work-group (at most 128 columns and
+ * 2^15 partial values) run as one launch per phase and class of problems
+ * (storage type, vector width, passes per plane, split x lines, line tiles)
+ * on a batch stream, each launch's work-groups spread over (problem, tile)
+ * work items of every problem's own sweep shape, each problem over all XCDs; same kernels and summation order as the per-problem launches,
  * so the results are identical.  shared = 0 (default): every problem's CG
  * runs on its own stream.  Measured: on the 64-problem workload (grid edges
  * 24..48, N 16..128) per-problem launches are 4-8% faster; on a batch of

@@ -8,7 +8,9 @@
   iteration cap is reported while the step stays orthogonal; runs repeat
   bit for bit.
 * At the 64^3, N = 128 size (the benchmark configuration): sampled stencil
-  rows and the full Gram against the oracle, and the step's invariants.
+  rows and the full Gram against the oracle, the step's invariants, and
+  Steps 1-4 from the ABI's building blocks (Step 1 on its true residual, the
+  Grams, the small solve element by element, Step 4 on sampled rows).
 """
 import numpy as np
 import pytest

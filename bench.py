@@ -107,9 +107,9 @@ def cpu_baseline(problem, tau, steps):
 def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
     """Wall time of Algorithm 1 from the start block to residual `tol` on an m^3
     wells problem whose block width N = 17 closes a level shell (it converges
-    in a few hundred steps): plain FP64 (default sweep shape, and autotuned);
-    the mixed form until `switch`, then FP64 steps; and the learned form
-    (shipped weights, plain-step judge and fallback)."""
+    in a few hundred steps): plain FP64; the mixed form until `switch`, then
+    FP64 steps (both with the default sweep shapes, and again autotuned); and
+    the learned form (shipped weights, plain-step judge and fallback)."""
     import numpy as np
     import workloads as W
     p = W.wells_3d(m=m, N=17, seed=0)
@@ -140,13 +140,17 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
                               "fp64_steps": int(sf.steps), "switch_residual": switch, "seconds": t_mixed,
                               "final_residual": sf.residual, "final_drift": sf.drift}
     out["speedup_mixed"] = t_plain / t_mixed
-    # the plain solve again with the sweep shape autotuned for this problem
-    # (the tuning itself is outside the timed region and reported beside it)
-    with ope.Context(p.grid, p.V, p.N) as ct:
+    # plain and mixed-then-FP64 again with the sweep shapes autotuned for this
+    # problem (the tuning itself is outside the timed regions, reported beside)
+    with ope.Context(p.grid, p.V, p.N) as ct, ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as cmt:
         t0 = time.perf_counter()
         ope.ope_autotune(ct.handle)
         t_tune = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ope.ope_autotune(cmt.handle)
+        t_tune_m = time.perf_counter() - t0
         ope.ope_solve(ct.handle, torch.from_numpy(p.U0).to("cuda"), tau, tol, 3)
+        ope.ope_solve(cmt.handle, torch.from_numpy(p.U0.astype(np.float32)).to("cuda"), tau, tol, 3)
         U = torch.from_numpy(p.U0).to("cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -154,9 +158,23 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
         torch.cuda.synchronize()
         t_tuned = time.perf_counter() - t0
         shape = list(ope.ope_get_sweep_shape(ct.handle))
+        U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
+        U64 = torch.empty_like(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smt = ope.ope_solve(cmt.handle, U32, tau, switch, 20000)
+        ope.ope_convert(cmt.handle, U32, U64, p.grid.n * p.N, True)
+        sft = ope.ope_solve(ct.handle, U64, tau, tol, 20000)
+        torch.cuda.synchronize()
+        t_mixed_tuned = time.perf_counter() - t0
+        shape_m = list(ope.ope_get_sweep_shape(cmt.handle))
     out["plain_fp64_autotuned"] = {"converged": bool(st.converged), "steps": int(st.steps), "seconds": t_tuned,
                                    "autotune_seconds": t_tune, "sweep_shape": shape,
                                    "final_residual": st.residual, "final_drift": st.drift}
+    out["mixed_then_fp64_autotuned"] = {"converged": bool(sft.converged), "mixed_steps": int(smt.steps),
+                                        "fp64_steps": int(sft.steps), "seconds": t_mixed_tuned,
+                                        "autotune_seconds": t_tune_m, "sweep_shape": shape_m,
+                                        "final_residual": sft.residual, "final_drift": sft.drift}
     with ope.Context(p.grid, p.V, p.N) as cl:
         net = ope.Net(cl, p.N, ope.load_net_weights())
         ope.ope_set_preconditioner(cl.handle, net.handle, judge=True)

@@ -314,13 +314,13 @@ ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
  * in steps of 8) time short CG runs of the first problem over the sweep shapes
  * (passes per plane 1/2 or the two-, four- and eight-line tiles, work-group order,
  * non-temporal stores, column chunking, and the automatic march-chunk count
- * times 1/2, 1, 3/2 or 2) and give every problem of the bucket the fastest;
- * FP32 contexts keep the default.  *tuned (nullable) = number of buckets.
+ * times 1/2, 1, 3/2 or 2) and give every problem of the bucket the fastest
+ * (FP64 and FP32 contexts alike).  *tuned (nullable) = number of buckets.
  * Synchronises; uses a temporary n x N block per tuned bucket. */
 ope_status ope_batch_autotune(ope_batch* batch, int32_t* tuned);
-/* The same search for one context (FP64; an FP32 context keeps its shape and
- * OPE_OK is returned).  The shape changes only the summation order of the CG
- * dot products.  Synchronises; uses a temporary n x N block. */
+/* The same search for one context.  The shape changes only the summation
+ * order of the CG dot products.  Synchronises; an FP64 context uses a
+ * temporary n x N block (an FP32 one its own CG buffers). */
 ope_status ope_autotune(ope_ctx* ctx);
 
 /* Step 1's CG runs in chunks of 4 iterations between host convergence checks;

@@ -791,18 +791,38 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
   return OPE_OK;
 }
 
-// Seconds per short CG run (8 iterations, 3 repetitions, best) for the
-// context's current sweep shape, on the scratch right-hand side X.
+// Seconds per short CG run (8 iterations, best of 3 after a warm-up run) for
+// the context's current sweep shape; the set-up is not timed.  FP64: r0 from
+// the scratch right-hand side X; FP32 (X unused): r0 is the block with every
+// word 0x3F3F3F3F, whose column norms are known on the host.  The inner
+// tolerance is 0, so no column converges within the run.
 double time_cg(ope_ctx* c, const double* X, hipEvent_t e0, hipEvent_t e1) {
+  const int N = (int)c->N;
+  std::vector<double> rho;
+  if (c->prec != OPE_FP64) {
+    const uint32_t bits = 0x3F3F3F3Fu;
+    float v;
+    memcpy(&v, &bits, sizeof v);
+    rho.assign(2 * (size_t)N, (double)c->n * (double)v * (double)v);
+  }
   double best = 1e30;
   for (int rep = 0; rep < 4; ++rep) {
-    if (hipEventRecord(e0, c->stream) != hipSuccess) return 1e30;
-    if (launch_resid0(c, X, nullptr, (double*)c->Rb[0], (double*)c->Y) != hipSuccess) return 1e30;
-    if (launch_reduce_cols(c, c->part, c->stream_wgs, 2 * c->N, c->rho0, RED_PLAIN) != hipSuccess) return 1e30;
+    if (c->prec == OPE_FP64) {
+      if (launch_resid0(c, X, nullptr, (double*)c->Rb[0], (double*)c->Y) != hipSuccess) return 1e30;
+      if (launch_reduce_cols(c, c->part, c->stream_wgs, 2 * c->N, c->rho0, RED_PLAIN) != hipSuccess) return 1e30;
+    } else {
+      const size_t bytes = sizeof(float) * (size_t)c->n * (size_t)N;
+      if (hipMemsetAsync(c->Rb[0], 0x3F, bytes, c->stream) != hipSuccess) return 1e30;
+      if (hipMemsetAsync(c->Y, 0, bytes, c->stream) != hipSuccess) return 1e30;
+      if (hipMemcpyAsync(c->rho0, rho.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess)
+        return 1e30;
+    }
     if (hipMemcpyAsync(c->cnorm2, c->rho0 + c->N, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream) !=
         hipSuccess)
       return 1e30;
     if (launch_solve_setup(c, c->rho0, 0.0) != hipSuccess) return 1e30;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return 1e30;
     for (int it = 0; it < 8; ++it)
       if (cg_iteration(c, it) != hipSuccess) return 1e30;
     if (hipEventRecord(e1, c->stream) != hipSuccess) return 1e30;
@@ -1493,8 +1513,8 @@ struct TunedShape {
   int q, mc, flags;
 };
 
-// The fastest sweep shape of an FP64 context for short CG runs on the scratch
-// right-hand side X (n x N): passes per plane 1/2 or the two-, four- and
+// The fastest sweep shape of a context for short CG runs (FP64: on the
+// scratch right-hand side X, n x N; FP32: X unused): passes per plane 1/2 or the two-, four- and
 // eight-line tiles, work-group order, non-temporal stores, column chunking,
 // and the automatic march-chunk count times 1/2, 1, 3/2 or 2.  Leaves the
 // context on the last shape tried.
@@ -1534,11 +1554,10 @@ TunedShape tune_shape(ope_ctx* c, const double* X, hipEvent_t e0, hipEvent_t e1)
 
 ope_status ope_autotune(ope_ctx* c) {
   if (!c) return OPE_EINVAL;
-  if (c->prec != OPE_FP64) return OPE_OK;          // FP32 contexts keep the default shape
   HIPCHK(hipStreamSynchronize(c->stream));
-  void* X = nullptr;
-  const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
-  if (hipMalloc(&X, bytes) != hipSuccess) return OPE_ENOMEM;
+  void* X = nullptr;                                // FP64: the scratch right-hand side
+  const size_t bytes = c->prec == OPE_FP64 ? sizeof(double) * (size_t)c->n * (size_t)c->N : 0;
+  if (bytes && hipMalloc(&X, bytes) != hipSuccess) return OPE_ENOMEM;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1546,7 +1565,7 @@ ope_status ope_autotune(ope_ctx* c) {
     return OPE_EHIP;
   }
   // any non-zero right-hand side (the sweeps' cost does not depend on it)
-  ope_status st = hipMemsetAsync(X, 0x3F, bytes, c->stream) == hipSuccess ? OPE_OK : OPE_EHIP;
+  ope_status st = (!X || hipMemsetAsync(X, 0x3F, bytes, c->stream) == hipSuccess) ? OPE_OK : OPE_EHIP;
   if (st == OPE_OK) {
     const TunedShape t = tune_shape(c, (const double*)X, e0, e1);
     if (ope_set_sweep_shape(c, t.q, t.mc, t.flags) != OPE_OK) (void)ope_set_sweep_shape(c, 2, 0, default_sweep_flags(c));
@@ -1554,7 +1573,7 @@ ope_status ope_autotune(ope_ctx* c) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(X);
+  if (X) (void)hipFree(X);
   return st;
 }
 
@@ -1581,22 +1600,18 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
     const Key k{c->g.dim, c->prec, c->vw, (c->g.m0 + 7) / 8, (c->g.m1 + 7) / 8, (c->g.m2 + 7) / 8, (NV + 7) / 8};
     auto f = best.find(k);
     if (f == best.end()) {
-      if (c->prec != OPE_FP64) {
-        best[k] = TunedShape{2, 0, default_sweep_flags(c)};   // FP32 contexts keep the default shape
-      } else {
-        void* X = nullptr;
-        const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
-        if (hipMalloc(&X, bytes) != hipSuccess) {
-          status = OPE_ENOMEM;
-          break;
-        }
-        // any non-zero right-hand side (the sweeps' cost does not depend on it)
-        (void)hipMemsetAsync(X, 0x3F, bytes, c->stream);
-        const TunedShape pick = tune_shape(c, (const double*)X, e0, e1);
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(X);
-        best[k] = pick;
+      void* X = nullptr;                          // FP64: the scratch right-hand side
+      const size_t bytes = c->prec == OPE_FP64 ? sizeof(double) * (size_t)c->n * (size_t)c->N : 0;
+      if (bytes && hipMalloc(&X, bytes) != hipSuccess) {
+        status = OPE_ENOMEM;
+        break;
       }
+      // any non-zero right-hand side (the sweeps' cost does not depend on it)
+      if (X) (void)hipMemsetAsync(X, 0x3F, bytes, c->stream);
+      const TunedShape pick = tune_shape(c, (const double*)X, e0, e1);
+      (void)hipStreamSynchronize(c->stream);
+      if (X) (void)hipFree(X);
+      best[k] = pick;
       f = best.find(k);
     }
     if (ope_set_sweep_shape(c, f->second.q, f->second.mc, f->second.flags) != OPE_OK) {

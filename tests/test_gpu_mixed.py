@@ -97,7 +97,10 @@ def test_apply_h_fp32_within_rounding(mk):
     assert np.max(np.abs(Y - ref)) <= bound
 
 
-def test_one_mixed_step_matches_oracle_delta_step():
+@pytest.mark.parametrize("autotune", [False, True])
+def test_one_mixed_step_matches_oracle_delta_step(autotune):
+    """One mixed step vs the oracle's delta-form step (also after ope_autotune
+    has picked the context's sweep shape by timing FP32 CG runs)."""
     from paper_2511_06788_amd import ope
     p = W.harmonic_2d_32()
     op = _op(p)
@@ -105,8 +108,10 @@ def test_one_mixed_step_matches_oracle_delta_step():
     U = U32.astype(np.float64)
     tau = 20.0
     ref = O.step_delta(U, O.GSolver(op, "dense")(U), tau)["U"]
-    say("one mixed step")
+    say(f"one mixed step autotune={autotune}")
     with _ctx(p) as ctx:
+        if autotune:
+            ope.ope_autotune(ctx.handle)
         ope.ope_set_inner(ctx.handle, 0.0, 1e-7, 20000)
         Ud = _dev32(U32)
         info = ope.ope_step(ctx.handle, Ud, tau)

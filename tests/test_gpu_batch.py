@@ -98,6 +98,26 @@ def test_autotuned_batch_converges_to_dense_eigenvalues():
         assert drift[i] <= 1e-12
 
 
+def test_autotuned_mixed_batch_steps():
+    """The autotuner on FP32 (mixed) problems: after it has picked their sweep
+    shapes, mixed batch steps lower the energy and keep the drift small, and
+    the first step's energy equals the oracle's energy of the start block."""
+    from paper_2511_06788_amd import ope
+    probs = [W.wells_3d(m=14, N=9, seed=21), W.wells_3d(m=19, N=32, seed=22), W.wells_3d(m=12, N=17, seed=23)]
+    say("autotuned mixed batch")
+    with ope.Batch(probs, precision=1) as b:
+        assert b.autotune() >= 1
+        Ub = [_dev(p.U0, 1) for p in probs]
+        i1 = b.step(Ub, 30.0)
+        i2 = b.step(Ub, 30.0)
+    for i, p in enumerate(probs):
+        op = O.Operator(p.grid.m, p.grid.h, p.V)
+        U32 = p.U0.astype(np.float32).astype(np.float64)
+        assert abs(i1[i].energy - O.energy(op, U32)) <= 1e-6 * abs(i1[i].energy), i
+        assert i2[i].energy < i1[i].energy, i
+        assert i2[i].drift <= 1e-5, i
+
+
 def test_full_batched_workload_one_step():
     from paper_2511_06788_amd import ope
     probs = W.batched_problems(64)

@@ -85,8 +85,8 @@ def cmd_pmc(args):
         nf, af, nw, aw = nf + n1, af + a1, nw + n2, aw + a2
     f = sum(fs_) / len(fs_)
     w = sum(ws_) / len(ws_)
-    blk = args.n * args.N * 8
-    algo_read = args.reads * blk + 8 * args.n
+    blk = args.n * args.N * args.esz
+    algo_read = args.reads * blk + args.esz * args.n
     algo_write = args.writes * blk
     per_kernel = [{"kernel_regex": k, "fetch_kib": a * fscale, "write_kib": b * wscale}
                   for k, a, b in zip(args.kernel, fs_, ws_)]
@@ -175,6 +175,7 @@ def main(argv=None):
     p.add_argument("--copy-bytes", type=int, default=1 << 30)
     p.add_argument("--n", type=int, required=True)
     p.add_argument("--N", type=int, required=True)
+    p.add_argument("--esz", type=int, default=8, help="bytes per element of the blocks (8 FP64, 4 FP32)")
     p.add_argument("--reads", type=float, default=3)
     p.add_argument("--writes", type=float, default=2)
     p.add_argument("--source", required=True)

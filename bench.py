@@ -213,9 +213,27 @@ def learned_steps_per_second(ope, torch, p, tau, steps, warmup):
             "residual_at_end": si.residual}
 
 
+def sweep_b_rate(ope, torch, ctx, U, tau, n, N, esz, steps=10):
+    """Sweep B's rate over `steps` further steps, timed per counted CG
+    iteration with the library's HIP events (as for the headline line), for
+    blocks of `esz`-byte elements."""
+    ope.ope_profile_begin(ctx.handle, ope.OPE_KERNEL_CG_SWEEP_B)
+    inner = 0
+    for _ in range(steps):
+        inner += ope.ope_step(ctx.handle, U, tau).inner_iterations
+    torch.cuda.synchronize()
+    launches, total_ms = ope.ope_profile_end(ctx.handle)
+    avg_ms = total_ms / max(inner, 1)
+    algo = 4.5 * n * N * esz + esz * n
+    achieved = algo / (avg_ms * 1e-3) / 1e9
+    return {"algorithmic_bytes": algo, "avg_ms_per_iteration": avg_ms, "achieved_GB_per_s": achieved,
+            "frac": achieved / HBM_PEAK_GBS, "counted_iterations": inner, "launches": launches, "steps": steps}
+
+
 def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
     import numpy as np
-    U = torch.from_numpy(p.U0.astype(np.float32 if precision == ope.OPE_MIXED else np.float64)).to("cuda")
+    mixed = precision == ope.OPE_MIXED
+    U = torch.from_numpy(p.U0.astype(np.float32 if mixed else np.float64)).to("cuda")
     with ope.Context(p.grid, p.V, p.N, precision=precision) as ctx:
         for _ in range(warmup):
             ope.ope_step(ctx.handle, U, tau)
@@ -226,8 +244,10 @@ def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
             inner += ope.ope_step(ctx.handle, U, tau).inner_iterations
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # after the timed steps, so that their events do not touch the rate above
+        sweep = sweep_b_rate(ope, torch, ctx, U, tau, p.grid.n, p.N, 4 if mixed else 8)
     return {"iter_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "inner_iterations_per_step": inner / steps,
-            "steps": steps, "warmup": warmup}
+            "steps": steps, "warmup": warmup, "cg_sweep_b": sweep}
 
 
 def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):

@@ -333,8 +333,9 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
 
 /* --- Launch shape of the stencil / CG sweeps (tuning) --------------------
  * The sweeps march along the slowest grid axis; a work-group covers q passes
- * of 256/8 grid points of one x segment (q in {1, 2, 4}; more passes per
- * plane mean fewer x segments but more registers), and the march axis is cut
+ * of 256/c grid points of one x segment, c the vector columns of its column
+ * chunk (q in {1, 2, 4}; more passes per plane mean fewer x segments but
+ * more registers), and the march axis is cut
  * into march_chunks ranges (0 = automatic: at least 512 work-groups).  The
  * default shape is q_max = 2, automatic chunks, OPE_SWEEP_CHUNK_MAJOR, plus
  * OPE_SWEEP_LINES8 on 3D grids and OPE_SWEEP_NONTEMPORAL when five n x N
@@ -343,10 +344,12 @@ ope_status ope_set_graphs(ope_ctx* ctx, int32_t enable);
  * work-groups of one column chunk next to each other (so one XCD streams one
  * chunk of every side line) instead of those of one side line;
  * OPE_SWEEP_NONTEMPORAL writes the swept outputs with non-temporal stores;
- * OPE_SWEEP_NARROW keeps 8-vector column chunks for rows of at most 32
- * vector columns (which by default a work-group takes whole);
+ * OPE_SWEEP_NARROW gives every work-group an 8-vector column chunk (by
+ * default a work-group takes rows of at most 32 vector columns whole, rows
+ * of up to 64 in chunks of the widest of 32, 16 and 8 vectors that divides
+ * them, and wider rows in chunks of 8);
  * OPE_SWEEP_LINES (3D grids) gives a work-group two adjacent side lines, one
- * per pass over an x segment of 256/8 points (q is then 2), OPE_SWEEP_LINES4
+ * per pass over an x segment of 256/c points (q is then 2), OPE_SWEEP_LINES4
  * four, two per pass over segments of half that, OPE_SWEEP_LINES8 eight, four
  * per pass over segments of a quarter (when a pass holds at least 16 points;
  * else as OPE_SWEEP_LINES4); the lines take their inner side neighbours from

@@ -843,9 +843,17 @@ void march_shape(ope_ctx* c, int q_max, int mc_override, int order, int nt, int 
   const OpeGrid& g = c->g;
   const uint32_t NV = (uint32_t)(c->N / c->vw);
   // Column chunk of a work-group: whole rows when they have at most 32 vector
-  // columns (one contiguous run of pp rows per pass, no partly idle chunk),
-  // else 8 vector columns (one 128-byte line per grid point and work-group).
-  ms.ncv = (NV <= 32u && !narrow) ? NV : (NV < 8u ? NV : 8u);
+  // columns (one contiguous run of pp rows per pass, no partly idle chunk);
+  // rows of up to 64 the widest of 32, 16 and 8 vector columns that divides
+  // them (no idle lanes; a wide chunk streams long runs per grid point: at
+  // N = 128 in FP64, 512-byte chunks sweep 1.17x faster than 128-byte ones);
+  // else 8 vector columns, one 128-byte line of FP64 or FP32 per grid point
+  // and work-group (at N = 512, 96^3, 32-vector chunks were 5% slower).
+  // `narrow` asks for 8 vector columns at any row width.
+  if (narrow) ms.ncv = NV < 8u ? NV : 8u;
+  else if (NV <= 32u) ms.ncv = NV;
+  else if (NV <= 64u) ms.ncv = NV % 32u == 0 ? 32u : (NV % 16u == 0 ? 16u : 8u);
+  else ms.ncv = 8u;
   ms.pp = OPE_WG / ms.ncv;
   // passes per plane (1, 2 or 4, at most q_max, default 2; a larger one only
   // while the smaller does not cover the x line): the one that leaves the

@@ -260,3 +260,30 @@ def test_sweep_shapes_agree(q_max, chunks, flags):
         S = to_host(Sd)
     assert np.max(np.abs(Y - O.apply_H(op, X))) <= stencil_bound(op, X)
     assert np.all(np.linalg.norm(U - O.apply_H(op, S), axis=0) <= 20 * 1e-11)
+
+
+@pytest.mark.parametrize("N", [80, 96, 128])
+@pytest.mark.parametrize("narrow", [False, True])
+def test_wide_row_chunks_agree(N, narrow):
+    """Rows wider than 32 vector columns: by default a work-group takes the
+    widest of 32, 16 and 8 vector columns that divides the row (N = 128 in
+    FP64: 32, two chunks; N = 96: 16, three; N = 80: 8, five), with the narrow
+    flag always 8; H X and the CG solution match the oracle either way."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=13, N=N, seed=7)
+    op = _op(p)
+    X = np.random.default_rng(5).standard_normal((p.grid.n, p.N))
+    U = W.initial_block(p.grid.n, p.N, 10)
+    say(f"wide row chunks N={N} narrow={narrow}")
+    with _ctx(p) as ctx:
+        if narrow:
+            ope.ope_set_sweep_shape(ctx.handle, 2, 0, ope.OPE_SWEEP_CHUNK_MAJOR | ope.OPE_SWEEP_LINES8
+                                    | ope.OPE_SWEEP_NARROW)
+        Yd = empty_dev(p.grid.n, p.N)
+        ope.ope_apply_h(ctx.handle, to_dev(X), Yd)
+        Y = to_host(Yd)
+        Sd = empty_dev(p.grid.n, p.N)
+        ope.ope_source_solve(ctx.handle, to_dev(U), Sd, None, 1e-11, 20000)
+        S = to_host(Sd)
+    assert np.max(np.abs(Y - O.apply_H(op, X))) <= stencil_bound(op, X)
+    assert np.all(np.linalg.norm(U - O.apply_H(op, S), axis=0) <= 20 * 1e-11)

@@ -701,8 +701,8 @@ __global__ __launch_bounds__(OPE_WG) void k_reduce_cols(const double* __restrict
 
 // The same column sums for few columns (ncols <= 128) by one 1024-thread
 // work-group with no second stage: thread t sums column t % ncols over rows
-// t / ncols, t / ncols + G, ... (G = 1024 / ncols row groups, eight loads in
-// flight), then the groups are added in order (the single and the batched
+// t / ncols, t / ncols + G, ... (G = 1024 / ncols row groups, 32 or eight
+// loads in flight, eight running sums), then the groups are added in order (the single and the batched
 // kernel share this order).  Avoids the cross-work-group fence of the split
 // form, which writes back the L2 lines the preceding sweep left dirty.
 constexpr uint32_t RED_WG = 1024;
@@ -720,6 +720,15 @@ __device__ __forceinline__ double few_cols_sum(const double* __restrict__ part, 
   if (gi < G) {
     double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     uint32_t w = gi;
+    // 32 loads in flight, added in the order of the 8-wide loop below (so the
+    // sums are the same bit for bit)
+    for (; w + 31 * G < nrows; w += 32 * G) {
+      double v[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) v[u] = part[(uint64_t)(w + u * G) * ncols + col];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) q[u & 7] += v[u];
+    }
     for (; w + 7 * G < nrows; w += 8 * G) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) q[u] += part[(uint64_t)(w + u * G) * ncols + col];

@@ -9,11 +9,14 @@ Algorithm 1) in float64 with numpy/scipy primitives, with no blocking or fusion,
 so that a reader can check each function against the paper by eye:
 
 * :mod:`oracle.operator` -- the finite-difference operator ``H = c(-Lap_h) + V``
-  (assembled and matrix-free) and the solution operator ``G = H^{-1}`` (dense
-  Cholesky, sparse LU, or textbook CG per column).
+  (assembled and matrix-free), the solution operator ``G = H^{-1}`` (dense
+  Cholesky, sparse LU, or textbook CG per column), a mass operator ``M`` for
+  the generalized problem ``H u = lambda M u``, and the lowest eigenpairs by a
+  library eigensolver (the converged result the scheme must reach).
 * :mod:`oracle.scheme`   -- the midpoint scheme (4.1): the paper's Steps 1-4,
   the same step as a dense Cayley solve and as the 2N x 2N Woodbury system,
-  the generator ``L_U``, energy, residual, Ritz values and the Algorithm 1 loop.
+  the generator ``L_U``, energy, residual, Ritz values, the Algorithm 1 loop
+  (fixed and adaptive step) and the scheme in the inner product of M.
 * :mod:`oracle.net`      -- the small 3D conv-net that stands in for ``H^{-1}``
   applied to residual columns in the learned form (forward, backward, loss);
   imported as ``oracle.net``.
@@ -29,6 +32,11 @@ from .operator import (  # noqa: F401
     apply_H,
     GSolver,
     cg_source,
+    Mass,
+    assemble_M,
+    apply_M,
+    sine_eigenvalues_1d,
+    lowest_eigenpairs,
 )
 from .scheme import (  # noqa: F401
     inner,
@@ -47,4 +55,13 @@ from .scheme import (  # noqa: F401
     ortho_error,
     subspace_distance,
     run_algorithm1,
+    run_algorithm1_adaptive,
+    inner_M,
+    steps_1_to_4_M,
+    step_general_M,
+    step_cayley_dense_M,
+    residual_M,
+    ortho_error_M,
+    ritz_values_M,
+    orthonormalize_M,
 )

@@ -33,10 +33,39 @@ Layout: a field of C channels on the grid is an array of shape
 ``(m2, m1, m0, C)`` (x fastest); taps are ordered ``(dz, dy, dx)`` with dx
 fastest, each in ``(-1, 0, 1)``.
 
+Two further pieces serve the element-wise comparison with the device kernels:
+
+* ``bf16``, ``storage_forward`` and ``storage_grad`` -- the same network and
+  losses evaluated with the storage precision of the device kernels made
+  explicit: inputs, weights, the activations after every ReLU, and the
+  back-propagated fields rounded to bfloat16 (round to nearest even, via
+  float32), everything else in float64.  The forward pass carries beside
+  every value an element-wise bound on the distance of a float32-accumulating
+  implementation with the same rounding points, by interval arithmetic: a sum
+  of K products is off by at most ``K u / (1 - K u)`` times the sum of absolute
+  products (u = 2^-24, the float32 unit roundoff); a rounding to bfloat16 is
+  monotone, so an input interval ``[z - e, z + e]`` maps to
+  ``[bf16(z - e), bf16(z + e)]`` and the bound after it is the width of that
+  image (zero whenever the whole interval rounds to one value).  The backward
+  pass returns the absolute-value contractions that scale its rounding
+  errors; with integer data and sparse +-1 weights every quantity is an
+  integer of at most 8 significant bits and the pass is exact.
+* ``adam_step`` -- Adam (Kingma & Ba, 2015, Algorithm 1): bias-corrected
+  first and second moment estimates and the step ``lr m_hat / (sqrt(v_hat) + eps)``.
+
 Parity: the backward pass is pinned by central finite differences of the loss,
 the forward pass by the special case where every ReLU passes and the network
 reduces to an explicit stencil, and the loss by its values for the zero and
-the exact network.
+the exact network; ``bf16`` by the bit patterns of exactly representable and
+halfway values; ``storage_forward`` by integer-valued cases where every rounding
+is exact (it must then equal ``forward`` with zero bounds), and both
+``storage_forward`` by a float32 re-evaluation with the same rounding points
+(a different accumulation order and precision) that must stay inside its
+bounds, ``storage_grad`` by ``backward`` on exact integer cases and by that
+float32 re-evaluation staying within 2^-5 of the absolute contractions; ``adam_step`` by hand-checked
+steps (the first step is ``-lr sign(g)`` up to eps, a constant gradient keeps
+that step size, two steps with different gradients match values worked out by
+hand) and by a planted swap of the moments.
 """
 from __future__ import annotations
 
@@ -223,3 +252,139 @@ def learned_step(op: Operator, U: np.ndarray, Ws: Sequence[np.ndarray], tau: flo
     out["Y"] = Y
     out["R"] = R
     return out
+
+
+# ---------------------------------------------------------------------------
+# optimiser
+# ---------------------------------------------------------------------------
+
+def adam_step(w: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, t: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) at step count ``t >= 1``:
+    ``m = b1 m + (1 - b1) g``, ``v = b2 v + (1 - b2) g^2``,
+    ``w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)``.
+    Returns the new ``(w, m, v)``."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# storage-precision evaluation with element-wise error bounds
+# ---------------------------------------------------------------------------
+
+U32 = 2.0 ** -24
+
+
+def bf16(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (float64 -> float32 round to nearest, then keep the
+    top 16 bits of the float32 word with round to nearest even); returns float64."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _gamma(k: int) -> float:
+    return k * U32 / (1.0 - k * U32)
+
+
+def _conv_abs(a, W):
+    return conv(np.abs(a), np.abs(W))
+
+
+def _round_interval(z, e, relu: bool):
+    """Image of ``[z - e, z + e]`` under (ReLU then) bf16 rounding: the rounded
+    centre and the bound on the distance of any image point from it."""
+    lo, hi = z - e, z + e
+    if relu:
+        z, lo, hi = np.maximum(z, 0.0), np.maximum(lo, 0.0), np.maximum(hi, 0.0)
+    c, rl, rh = bf16(z), bf16(lo), bf16(hi)
+    return c, np.maximum(np.abs(rh - c), np.abs(c - rl))
+
+
+def _stencil_abs(e: np.ndarray, v2: np.ndarray, kin: float) -> np.ndarray:
+    """``|A| e = kin (6 e + sum of neighbours of e) + |v2| e`` for e >= 0 (fields (m2, m1, m0))."""
+    nb = np.zeros_like(e)
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(1, None)
+        hi[ax] = slice(None, -1)
+        nb[tuple(lo)] += e[tuple(hi)]
+        nb[tuple(hi)] += e[tuple(lo)]
+    return kin * (6.0 * e + nb) + np.abs(v2) * e
+
+
+def _stencil(e: np.ndarray, v2: np.ndarray, kin: float) -> np.ndarray:
+    nb = np.zeros_like(e)
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(1, None)
+        hi[ax] = slice(None, -1)
+        nb[tuple(lo)] += e[tuple(hi)]
+        nb[tuple(hi)] += e[tuple(lo)]
+    return kin * (6.0 * e - nb) + v2 * e
+
+
+def storage_forward(x: np.ndarray, Ws: Sequence[np.ndarray]) -> Dict[str, np.ndarray]:
+    """Forward pass with bf16 storage of the input pair, the weights and the
+    activations a1..a3 (float32 accumulation assumed for the bounds).  ``x``
+    (m2, m1, m0, 2) holds the float32 input values.  Returns the values
+    (``xb``, ``Wb``, ``z*``, ``a*``, ``f``) and bounds ``e_a*``, ``e_z*``, ``e_f``."""
+    xb = bf16(x)
+    Wb = [bf16(W) for W in Ws]
+    out = {"xb": xb, "Wb": Wb}
+    a, ea = xb, np.zeros_like(xb)
+    for L in range(3):
+        K = 27 * Wb[L].shape[1]
+        z = conv(a, Wb[L])
+        ez = conv(ea, np.abs(Wb[L])) + (_gamma(K) + 1e-15) * _conv_abs(np.abs(a) + ea, Wb[L])
+        a_new, ea_new = _round_interval(z, ez, relu=True)
+        out[f"z{L + 1}"], out[f"e_z{L + 1}"] = z, ez
+        out[f"a{L + 1}"], out[f"e_a{L + 1}"] = a_new, ea_new
+        a, ea = a_new, ea_new
+    K = 27 * 16
+    f = conv(a, Wb[3])[..., 0]
+    ef = (conv(ea, np.abs(Wb[3])) + (_gamma(K) + 1e-15) * _conv_abs(np.abs(a) + ea, Wb[3]))[..., 0]
+    out["f"], out["e_f"] = f, ef
+    return out
+
+
+def storage_grad(x: np.ndarray, t: np.ndarray, v2: np.ndarray, Ws: Sequence[np.ndarray], kin: float,
+                 coef: float, kind: str = "energy", coef_r: float = 0.0):
+    """Weight gradients of one sample with bf16 storage of the forward
+    activations and of the back-propagated fields g4..g1, as the device
+    kernels store them.  ``coef`` multiplies ``A (f - t)`` (energy loss) and
+    ``coef_r`` multiplies ``A (A f - x0)`` (residual loss): ``kind`` "energy",
+    "residual" or "both".  ``v2`` (m2, m1, m0) is the float32 second input
+    channel, ``t`` the float32 target.  Returns ``(grads, mags, fields)``:
+    the float64 contractions of the stored fields, the contractions of their
+    absolute values (the scale of every weight's rounding errors, one bf16
+    rounding of a factor moving a term by at most 2^-8 of its size), and the
+    stored fields (forward values, g4..g1)."""
+    fw = storage_forward(x, Ws)
+    f = fw["f"]
+    Wb = fw["Wb"]
+    x0 = x[..., 0]
+    g = np.zeros_like(f)
+    if kind in ("energy", "both"):
+        g = g + coef * _stencil(f - t, v2, kin)
+    if kind in ("residual", "both"):
+        g = g + coef_r * _stencil(_stencil(f, v2, kin) - x0, v2, kin)
+    fields = dict(fw)
+    gcur = bf16(g)[..., None]
+    fields["g4"] = gcur
+    grads, mags = [None] * 4, [None] * 4
+    grads[3] = conv_weight_grad(fw["a3"], gcur)
+    mags[3] = conv_weight_grad(np.abs(fw["a3"]), np.abs(gcur))
+    for L in (3, 2, 1):          # weights of layer L + 1 transposed: data gradient at a_L
+        gcur = bf16(conv_transpose(gcur, Wb[L]) * (fw[f"a{L}"] > 0))
+        fields[f"g{L}"] = gcur
+        prev = fw["xb"] if L == 1 else fw[f"a{L - 1}"]
+        grads[L - 1] = conv_weight_grad(prev, gcur)
+        mags[L - 1] = conv_weight_grad(np.abs(prev), np.abs(gcur))
+    return grads, mags, fields

@@ -34,8 +34,21 @@ Functions and the passage each follows:
   ``|<U,U> - I|_F`` (Theorem 4.1).
 * ``run_algorithm1`` -- Algorithm 1 with a fixed step and either the paper's
   relative-energy-change stop or an eigen-residual stop.
+* ``run_algorithm1_adaptive`` -- Algorithm 1 with the step chosen in
+  ``[tau_min, tau_max]`` at every iteration.  The paper leaves the choice
+  open; the rule here rests on Theorem 4.2 (the energy decays for steps below
+  a threshold): a step whose energy rises is redone with the step shrunk
+  (never below tau_min), an accepted step lets the next one grow (never above
+  tau_max).  Stops on the relative energy change of Algorithm 1, on the
+  relative energy error against a reference energy (the stop of the
+  experiments, Section 5), or on the eigen-residual.
+* ``*_M`` -- the same scheme with the inner product ``<U, V> = U^T M V`` of a
+  mass operator M (Section 5: coefficient vectors of a finite-element space,
+  where Step 1 reads ``K (GU) = M U``).  ``G = K^{-1} M`` and every inner
+  matrix of Steps 2-4 is taken in the M product; Step 4 is unchanged.
 
-Parity: all functions are pinned (tests/test_oracle_scheme.py): the three step
+Parity: all functions are pinned (tests/test_oracle_scheme.py,
+tests/test_oracle_algorithm1.py, tests/test_oracle_mass.py): the three step
 forms agree with each other, orthogonality is preserved (Theorem 4.1), energy
 decreases (Theorem 4.2), eigenbases are fixed points (Remark after (3.1)),
 ``L_U`` is skew (Lemma 3.2), the Step-2 matrix is >= I (Lemma 3.1), and the
@@ -48,7 +61,7 @@ from typing import Callable, Dict, List, Optional
 import numpy as np
 import scipy.linalg as sla
 
-from .operator import Operator, apply_H
+from .operator import Mass, Operator, apply_H, apply_M
 
 
 def inner(U: np.ndarray, V: np.ndarray) -> np.ndarray:
@@ -212,3 +225,134 @@ def run_algorithm1(op: Operator, U0: np.ndarray, tau: float, G: Callable[[np.nda
         if energy_tol is not None and errE <= energy_tol:
             break
     return {"U": U, "steps": steps, "hist": hist}
+
+
+def run_algorithm1_adaptive(op: Operator, U0: np.ndarray, G: Callable[[np.ndarray], np.ndarray], tau0: float,
+                            tau_min: float, tau_max: float, max_steps: int, energy_tol: Optional[float] = None,
+                            energy_ref: Optional[float] = None, res_tol: Optional[float] = None,
+                            grow: float = 1.5, shrink: float = 0.5, slack: float = 1e-13,
+                            step: Optional[Callable] = None) -> Dict[str, object]:
+    """Algorithm 1 with ``tau_n`` chosen in ``[tau_min, tau_max]``.
+
+    Iteration n: with the current step tau, compute U' by Steps 1-4 (``step``,
+    default ``steps_1_to_4`` with ``G``).  If ``E(U') <= E(U^n) + slack |E(U^n)|``
+    (Theorem 4.2's energy decay) or tau is already tau_min, accept: U^{n+1} = U',
+    ``err_E^n = |E(U^{n+1}) - E(U^n)| / |E(U^n)|``, and the next step starts at
+    ``min(tau_max, grow tau)``.  Otherwise reject U', set
+    ``tau = max(tau_min, shrink tau)`` and recompute from U^n.
+
+    Stops (checked before every iteration, in this order): ``res_tol`` on the
+    eigen-residual of U^n; with ``energy_ref``, the experiments' relative energy
+    error ``(E(U^n) - E_ref) / |E_ref| <= energy_tol``; else Algorithm 1's
+    ``err_E <= energy_tol`` with ``err_E^0 = |E(U^0)|``; or ``max_steps``
+    accepted steps.  Returns U, the accepted step count, the rejected count,
+    and the per-step histories (energy, tau used, residual if ``res_tol``)."""
+    if not (0.0 < tau_min <= tau0 <= tau_max):
+        raise ValueError("need 0 < tau_min <= tau0 <= tau_max")
+    if step is None:
+        def step(U, tau):
+            return steps_1_to_4(U, G, tau)["U"]
+    U = np.array(U0, dtype=np.float64)
+    E = energy(op, U)
+    errE = abs(E)
+    tau = tau0
+    hist: Dict[str, List[float]] = {"E": [E], "tau": [], "errE": []}
+    if res_tol is not None:
+        hist["res"] = [residual(op, U)]
+    steps = 0
+    rejected = 0
+    while True:
+        if res_tol is not None and hist["res"][-1] <= res_tol:
+            break
+        if energy_tol is not None:
+            if energy_ref is not None:
+                if (E - energy_ref) / abs(energy_ref) <= energy_tol:
+                    break
+            elif errE <= energy_tol:
+                break
+        if steps >= max_steps:
+            break
+        while True:
+            U_new = step(U, tau)
+            E_new = energy(op, U_new)
+            if E_new <= E + slack * abs(E) or tau <= tau_min:
+                break
+            rejected += 1
+            tau = max(tau_min, shrink * tau)
+        errE = abs(E_new - E) / abs(E)
+        U, E = U_new, E_new
+        steps += 1
+        hist["E"].append(E)
+        hist["tau"].append(tau)
+        hist["errE"].append(errE)
+        if res_tol is not None:
+            hist["res"].append(residual(op, U))
+        tau = min(tau_max, grow * tau)
+    return {"U": U, "steps": steps, "rejected": rejected, "hist": hist}
+
+
+# ---------------------------------------------------------------------------
+# the scheme in the inner product of a mass operator M
+# ---------------------------------------------------------------------------
+
+def inner_M(op: Operator, mass: Mass, U: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """``<U, V> = U^T M V``."""
+    return U.T @ apply_M(op, mass, V)
+
+
+def steps_1_to_4_M(op: Operator, mass: Mass, U: np.ndarray, solve_K: Callable[[np.ndarray], np.ndarray],
+                   tau: float) -> Dict[str, np.ndarray]:
+    """Steps 1-4 of Section 4.1 in the M product: Step 1 solves ``K Y = M U``
+    (``solve_K`` applies K^{-1}); ``S = <Y, U>``, ``T = <Y, Y>``; Steps 2-3 as
+    ``small_solve``; Step 4 ``U' = U - tau U A + tau Y B``."""
+    Y = solve_K(apply_M(op, mass, U))
+    S = inner_M(op, mass, Y, U)
+    T = inner_M(op, mass, Y, Y)
+    A, B, Mb = small_solve(S, T, tau)
+    return {"U": U - tau * U @ A + tau * Y @ B, "Y": Y, "A": A, "B": B, "S": S, "T": T}
+
+
+def step_general_M(op: Operator, mass: Mass, U: np.ndarray, Y: np.ndarray, tau: float) -> Dict[str, np.ndarray]:
+    """Steps 2-4 for a given Y in the M product without assuming ``<Y,U> = <U,Y>``."""
+    S_a = inner_M(op, mass, Y, U)
+    S_b = inner_M(op, mass, U, Y)
+    T = inner_M(op, mass, Y, Y)
+    A, B, Mb = small_solve(S_a, T, tau, S_b=S_b)
+    return {"U": U - tau * U @ A + tau * Y @ B, "A": A, "B": B, "S_a": S_a, "S_b": S_b, "T": T}
+
+
+def step_cayley_dense_M(Mdense: np.ndarray, U: np.ndarray, Y: np.ndarray, tau: float) -> np.ndarray:
+    """(4.1) solved densely with ``L_U V = U <Y, V> - Y <U, V>`` in the M
+    product, i.e. ``L_U = (U Y^T - Y U^T) M`` as an n x n matrix."""
+    n = U.shape[0]
+    L = (U @ Y.T - Y @ U.T) @ Mdense
+    I = np.eye(n)
+    return np.linalg.solve(I + 0.5 * tau * L, (I - 0.5 * tau * L) @ U)
+
+
+def residual_M(op: Operator, mass: Mass, U: np.ndarray) -> float:
+    """``|K U - M U Lam|_F / |Lam|_F`` with ``Lam = U^T K U``."""
+    HU = apply_H(op, U)
+    Lam = U.T @ HU
+    return float(np.linalg.norm(HU - apply_M(op, mass, U) @ Lam) / np.linalg.norm(Lam))
+
+
+def ortho_error_M(op: Operator, mass: Mass, U: np.ndarray) -> float:
+    """``|<U, U> - I|_F`` in the M product (Theorem 4.1 keeps it at zero)."""
+    return float(np.linalg.norm(inner_M(op, mass, U, U) - np.eye(U.shape[1])))
+
+
+def ritz_values_M(op: Operator, mass: Mass, U: np.ndarray) -> np.ndarray:
+    """Eigenvalues of the pencil ``(U^T K U, U^T M U)`` (ascending)."""
+    Lam = U.T @ apply_H(op, U)
+    C = inner_M(op, mass, U, U)
+    return sla.eigh(0.5 * (Lam + Lam.T), 0.5 * (C + C.T), eigvals_only=True)
+
+
+def orthonormalize_M(op: Operator, mass: Mass, U: np.ndarray) -> np.ndarray:
+    """``U R^{-1}`` with ``R`` the upper Cholesky factor of ``U^T M U``
+    (``R^T R = U^T M U``, positive diagonal): the unique M-orthonormal block
+    with the same column span and an upper-triangular change of basis."""
+    C = inner_M(op, mass, U, U)
+    R = np.linalg.cholesky(0.5 * (C + C.T)).T
+    return sla.solve_triangular(R, U.T, trans="T", lower=False).T

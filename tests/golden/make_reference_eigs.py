@@ -1,0 +1,47 @@
+"""Writes ``reference_eigs.json``: the lowest eigenvalues of the Gaussian-well
+benchmark operators, computed by the oracle's library eigensolver
+(``oracle.lowest_eigenpairs``: preconditioned LOBPCG plus a Rayleigh-Ritz
+step), never by the scheme.  They are the converged result the GPU solves are
+compared with (1e-10 relative) and the spectral data of the step-count model
+for the 64^3, N = 128 workload.
+
+Run from the repository root:  python tests/golden/make_reference_eigs.py
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+CASES = [("wells3d_64^3_seed0", 64, 0, 17), ("wells3d_96^3_seed0", 96, 0, 17), ("wells3d_64^3_seed0", 64, 0, 136)]
+
+
+def main():
+    out = {"source": "oracle.lowest_eigenpairs (LOBPCG, sine-transform preconditioner, tol 1e-7)",
+           "operator": "-Lap_h + V on the m^3 interior grid of the unit cube, V = 8 seeded Gaussian wells",
+           "cases": []}
+    for name, m, seed, k in CASES:
+        p = W.wells_3d(m=m, N=k, seed=seed, with_u0=False)
+        op = O.Operator(p.grid.m, p.grid.h, p.V)
+        t0 = time.time()
+        vals, vecs, res = O.lowest_eigenpairs(op, k, extra=max(8, k // 8))
+        dt = time.time() - t0
+        hinv = 1.0 / p.grid.h[0] ** 2
+        gersh = float(np.max(p.V) + 12.0 * hinv)        # upper bound on lambda_max (Gershgorin)
+        out["cases"].append({"name": name, "m": m, "seed": seed, "k": k, "eigenvalues": vals.tolist(),
+                             "residual_norms": res.tolist(), "lambda_max_upper_bound": gersh,
+                             "seconds": dt})
+        print(name, k, f"{dt:.1f}s", "max residual", float(res.max()), flush=True)
+    with open(os.path.join(HERE, "reference_eigs.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,7 +46,8 @@ typedef enum {
   OPE_ENONFINITE = 4,  /* a NaN or Inf appeared in a reduction; U left unchanged */
   OPE_ECG_MAXIT = 5,   /* Step 1 hit its iteration cap before the tolerance (step still applied) */
   OPE_EPIVOT = 6,      /* non-positive or tiny pivot in a small FP64 solve; U left unchanged */
-  OPE_EUNSUPPORTED = 7 /* valid request the library does not implement */
+  OPE_EUNSUPPORTED = 7,/* valid request the library does not implement */
+  OPE_ENOTSPD = 8      /* the operator (or mass operator) is not symmetric positive definite */
 } ope_status;
 
 /* OPE_FP64: every block and every operation in FP64.
@@ -57,9 +58,12 @@ typedef enum {
  * cores, written in delta form U' = U + U Z1 + P Z2 (Z1 = -2(I - B),
  * Z2 = tau B) so that its rounding vanishes at convergence; the Step-2 matrix uses
  * T - S_a S_b = P^T P - S_b^T (C - I) S_b; the small solves and all checks in FP64.
- * FP32 rounding adds to the drift |U^T U - I|_F that the scheme itself keeps
- * constant, so a step whose predecessor saw a drift above 1e-6 first applies
- * U <- U (3I - C)/2 (one Newton-Schulz step, C = U^T U; drift E -> O(E^2)).
+ * FP32 rounding and the BF16 P^T P add to the drift |U^T U - I|_F that the
+ * scheme itself keeps constant, so after every update the drift of the new
+ * block is measured (C = U^T U accumulated in FP64) and, above 2.5e-7, the
+ * device applies U <- U (3I - C)/2 (one Newton-Schulz step; drift E -> O(E^2))
+ * before the block is handed back; a block entering a step with a drift
+ * above 1e-6 gets the same correction first.
  * Its accuracy is bounded by FP32 storage (residual floor about 1e-6); convert
  * U to FP64 and continue with an OPE_FP64 context to finish. */
 typedef enum { OPE_FP64 = 0, OPE_MIXED = 1 } ope_precision;
@@ -92,6 +96,9 @@ typedef struct {
   int64_t inner_iterations; /* total CG iterations */
   int32_t stalled;    /* OPE_MIXED only: 1 if the residual stopped improving (60 steps without a 10% gain) */
   int32_t learned_steps; /* steps taken by the learned form and kept by its judge */
+  int32_t rejected;   /* ope_solve_ex: steps redone with a smaller tau (energy rose) */
+  int32_t reserved;
+  double tau;         /* ope_solve_ex: the step the next iteration would take */
 } ope_solve_info;
 
 typedef struct ope_ctx ope_ctx;
@@ -100,8 +107,11 @@ typedef struct ope_ctx ope_ctx;
  * N <= n; larger N returns OPE_EUNSUPPORTED, and so does a plane of the
  * march axis holding 2 GiB or more of FP64 block rows, m0 m1 N 8 bytes in 3D,
  * m0 N 8 in 2D: the stencil addresses one plane through 32-bit offsets).  Copies V to the
- * device, allocates the workspace (five n x N blocks in the precision's storage
- * type plus O(N^2) matrices), and binds `stream` (a hipStream_t, or NULL).
+ * device, allocates O(N^2) matrices and per-column state (the five n x N
+ * workspace blocks in the precision's storage type follow on first use, or come
+ * from ope_set_workspace), binds `stream` (a hipStream_t, or NULL), and checks
+ * that H is SPD (Section 2.2's coercivity; OPE_ENOTSPD, see
+ * ope_spectrum_bounds).
  * Steps 2-3 run as one-work-group Gauss-Jordan kernels for N <= 128 and as
  * Newton-Schulz inversions on the FP64 matrix cores for larger N.
  * precision is an ope_precision.  On error *ctx is set to NULL. */
@@ -178,6 +188,42 @@ ope_status ope_step(ope_ctx* ctx, void* U, double tau, ope_step_info* info);
 ope_status ope_solve(ope_ctx* ctx, void* U, double tau, double res_tol, int32_t max_steps,
                      ope_solve_info* info);
 
+/* Options of ope_solve_ex: Algorithm 1 (Section 4.1) with the step tau_n
+ * chosen in [tau_min, tau_max] at every iteration.  The paper leaves the
+ * choice open; the rule here follows Theorem 4.2 (the energy decays for steps
+ * below a threshold): a step whose energy E(U') = 1/2 tr(U'^T H U') exceeds
+ * E(U) + 1e-13 |E(U)| is redone from U with tau <- max(tau_min, shrink tau)
+ * (a step at tau_min is always kept), and after an accepted step the next
+ * one starts at min(tau_max, grow tau).  tau_min = tau_max is a fixed step.
+ * Stops, checked before every iteration in this order: the residual
+ * |HU - U Lam|_F / |Lam|_F <= res_tol (negative: unused); the energy rule
+ * (energy_tol negative: unused): with energy_ref NaN, Algorithm 1's
+ * err_E = |E(U^{n+1}) - E(U^n)| / |E(U^n)| <= energy_tol (err_E^0 = |E(U^0)|),
+ * else the relative energy error of the experiments (Section 5)
+ * (E(U^n) - energy_ref) / |energy_ref| <= energy_tol; or max_steps accepted
+ * steps (OPE_MIXED also stops when the residual stalls, as ope_solve). */
+typedef struct {
+  double tau;         /* first step, tau_min <= tau <= tau_max */
+  double tau_min;     /* > 0 */
+  double tau_max;     /* finite */
+  double grow;        /* >= 1 */
+  double shrink;      /* in (0, 1) */
+  double res_tol;
+  double energy_tol;
+  double energy_ref;  /* NaN or non-zero */
+  int32_t max_steps;  /* >= 0 */
+  int32_t reserved;   /* 0 */
+} ope_solve_opts;
+
+/* Algorithm 1 with the options above, in place on U (device block in the
+ * context's storage type).  An adaptive run (tau_min < tau_max) keeps a copy
+ * of U in a library-owned n x N block (allocated on first use).  info
+ * (nullable) receives the counts, the final residual, energy and drift, the
+ * rejected steps and the next step.  EINVAL on inconsistent options;
+ * EUNSUPPORTED with a preconditioner set.  OPE_ECG_MAXIT of single steps is
+ * tolerated (the steps are kept). */
+ope_status ope_solve_ex(ope_ctx* ctx, void* U, const ope_solve_opts* opts, ope_solve_info* info);
+
 /* Elementwise precision change of `count` values on the context's stream:
  * to_double != 0 converts FP32 src to FP64 dst, else FP64 src to FP32 dst
  * (round to nearest).  Used to hand a mixed-precision iterate to an FP64
@@ -195,6 +241,74 @@ ope_status ope_gram_f32(ope_ctx* ctx, int32_t kind, const float* A, int64_t lda,
                         int64_t ldb, int64_t nb, int64_t rows, double* out);
 ope_status ope_rowmm_f32(ope_ctx* ctx, int32_t kind, const float* X0, const float* M0, const float* X1,
                          const float* M1, const float* Cm, double cbeta, double ascale, float* Out);
+
+/* --- Operator checks, the generalized problem, workspace, device scalars -- */
+
+/* Estimates of the extreme eigenvalues of H (host outputs, nullable): the
+ * extreme Ritz values of a Lanczos run on one seeded pseudo-random vector
+ * (FP64, on the device; run once per context, at ope_create when the closed-form
+ * bound lambda_min(c (-Lap_h)) + min(V + shift) does not already prove H SPD,
+ * else on the first call).  Ritz values lie inside the spectrum, so *lmin is
+ * an upper estimate of lambda_min and *lmax a lower estimate of lambda_max;
+ * with them the fixed-point stability limit of the step is about
+ * 2 / (1/lambda_min - 1/lambda_max).  ope_create returns OPE_ENOTSPD when this
+ * run finds a Ritz value <= 0 (then H certainly has an eigenvalue <= 0, and
+ * Section 2.2's coercivity fails); an eigenvalue <= 0 whose eigenvector is
+ * orthogonal to the Krylov space of the start vector would go unseen. */
+ope_status ope_spectrum_bounds(ope_ctx* ctx, double* lmin, double* lmax);
+
+/* The generalized problem H u = lambda M u of the paper's finite-element
+ * setting (Section 5: coefficient blocks with the inner product
+ * <U, V> = U^T M V and Step 1 solving H (GU) = M U), with the finite-difference
+ * mass operator M = diag(d) + sum_a mu_a (S_a + S_a^T), S_a the shift to the
+ * next grid node along axis a (zero past the boundary).  d: HOST array of n
+ * values, copied; mu: HOST array of dim coefficients.  From then on every
+ * inner matrix of Steps 2-4 and of the checks is taken in the M product:
+ * C = U^T M U (drift |C - I|_F), Lam = U^T H U (energy 1/2 tr Lam, Ritz values
+ * the eigenvalues of Lam, exact for C = I), residual |H U - M U Lam|_F / |Lam|_F,
+ * Step 1 solves H Y = M U (CG tolerance relative to |M u_j|), S_b = (MU)^T Y,
+ * T = Y^T (MY); Step 4 is unchanged.  U must be M-orthonormal
+ * (ope_orthonormalize).  OPE_ENOTSPD unless d_p > 2 sum_a |mu_a| for every p
+ * (strict diagonal dominance, a sufficient condition for SPD); EUNSUPPORTED for
+ * OPE_MIXED contexts, N > 256 or a preconditioner set.  d = NULL removes M. */
+ope_status ope_set_mass(ope_ctx* ctx, const double* d, const double* mu);
+/* Y = M X for n x N FP64 device blocks (the mass operator must be set). */
+ope_status ope_apply_mass(ope_ctx* ctx, const double* X, double* Y);
+
+/* U <- U R^{-1} in place (OPE_FP64), R the upper Cholesky factor of
+ * C = <U, U> (R^T R = C, positive diagonal; the M product when a mass operator
+ * is set): an orthonormal start block with the same column span.  OPE_ENOTSPD
+ * (U unchanged) when C is not numerically positive definite.  Synchronises. */
+ope_status ope_orthonormalize(ope_ctx* ctx, double* U);
+
+/* Size in bytes of the context's workspace of five n x N blocks in its storage
+ * type, each rounded up to 256 bytes. */
+ope_status ope_workspace_size(const ope_ctx* ctx, size_t* bytes);
+/* Give the context caller-owned device memory (>= ope_workspace_size bytes,
+ * 256-byte aligned; for instance a torch tensor) for those blocks; the library
+ * frees its own copy if it had one and never allocates them again until
+ * dptr = NULL hands the workspace back to the library (allocated on next use).
+ * The memory must stay valid, and unused by the caller, while the context uses
+ * it.  Synchronises the context's stream.  Without this call the library
+ * allocates the blocks on first use. */
+ope_status ope_set_workspace(ope_ctx* ctx, void* dptr, size_t bytes);
+
+/* Device-scalar forms of ope_energy / ope_residual: enqueue the same
+ * evaluation and write E(U), the residual and the drift to DEVICE addresses
+ * (each nullable except that one of residual/drift is needed), without
+ * synchronising the stream (N <= 128; larger N synchronise inside the
+ * Newton-Schulz inversion of Lam). */
+ope_status ope_energy_d(ope_ctx* ctx, const void* U, double* d_energy);
+ope_status ope_residual_d(ope_ctx* ctx, const void* U, double* d_residual, double* d_drift);
+
+/* ope_step / ope_energy / ope_residual for a block with leading dimension
+ * ldu >= N (row p at U + p ldu): ldu = N is the plain call; otherwise the block
+ * is copied into a packed library-owned staging block (allocated on first
+ * use), processed there, and for ope_step_ld copied back (two extra block
+ * copies; ope_step_ld synchronises). */
+ope_status ope_step_ld(ope_ctx* ctx, void* U, int64_t ldu, double tau, ope_step_info* info);
+ope_status ope_energy_ld(ope_ctx* ctx, const void* U, int64_t ldu, double* energy);
+ope_status ope_residual_ld(ope_ctx* ctx, const void* U, int64_t ldu, double* residual, double* ritz, double* drift);
 
 /* --- Learned preconditioner --------------------------------------------
  * Gradient form of Step 1: with R = HU - U Lam, G U = (U - H^{-1} R) Lam^{-1}.
@@ -249,6 +363,11 @@ ope_status ope_net_grad(ope_net* net, const float* X, const float* V2, const flo
  * learning rate lr > 0; *loss (host, nullable) receives the loss before the step. */
 ope_status ope_net_train_step(ope_net* net, const float* X, const float* V2, const float* T, int64_t B,
                               double lr, double* loss);
+/* One Adam step (as ope_net_train_step) with a caller-provided gradient
+ * (HOST array of OPE_NET_PARAMS values), for callers that form the gradient
+ * elsewhere, for instance summed over several processes' ope_net_grad
+ * results.  lr > 0. */
+ope_status ope_net_apply_grad(ope_net* net, const float* grad, double lr);
 /* Training samples from point-major FP64 device blocks R (residual columns)
  * and S = H^{-1} R (leading dimension ld, columns 0..B-1, B <= the context's
  * N): X[b] = r_b / |r_b|, T[b] = s_b / (|r_b| h^2); zero columns give zeros. */

@@ -365,7 +365,8 @@ def storage_grad(x: np.ndarray, t: np.ndarray, v2: np.ndarray, Ws: Sequence[np.n
     the float64 contractions of the stored fields, the contractions of their
     absolute values (the scale of every weight's rounding errors, one bf16
     rounding of a factor moving a term by at most 2^-8 of its size), and the
-    stored fields (forward values, g4..g1)."""
+    fields (forward values; g4..g1 as stored and, as ``g*_raw``, before their
+    rounding)."""
     fw = storage_forward(x, Ws)
     f = fw["f"]
     Wb = fw["Wb"]
@@ -376,14 +377,16 @@ def storage_grad(x: np.ndarray, t: np.ndarray, v2: np.ndarray, Ws: Sequence[np.n
     if kind in ("residual", "both"):
         g = g + coef_r * _stencil(_stencil(f, v2, kin) - x0, v2, kin)
     fields = dict(fw)
+    fields["g4_raw"] = g[..., None]
     gcur = bf16(g)[..., None]
     fields["g4"] = gcur
     grads, mags = [None] * 4, [None] * 4
     grads[3] = conv_weight_grad(fw["a3"], gcur)
     mags[3] = conv_weight_grad(np.abs(fw["a3"]), np.abs(gcur))
     for L in (3, 2, 1):          # weights of layer L + 1 transposed: data gradient at a_L
-        gcur = bf16(conv_transpose(gcur, Wb[L]) * (fw[f"a{L}"] > 0))
-        fields[f"g{L}"] = gcur
+        raw = conv_transpose(gcur, Wb[L]) * (fw[f"a{L}"] > 0)
+        gcur = bf16(raw)
+        fields[f"g{L}_raw"], fields[f"g{L}"] = raw, gcur
         prev = fw["xb"] if L == 1 else fw[f"a{L - 1}"]
         grads[L - 1] = conv_weight_grad(prev, gcur)
         mags[L - 1] = conv_weight_grad(np.abs(prev), np.abs(gcur))

@@ -280,6 +280,14 @@ __global__ __launch_bounds__(256) void k_gram_narrow(const TI* __restrict__ A, u
 // Row-block products Out = cbeta Cm + ascale (X0 M0 + X1 M1).  Work-group =
 // 4 waves, 2 (rows) x 2 (columns); a wave owns 32 rows x 64 columns (2 x 4
 // MFMA blocks), the work-group 64 x 128.  TI is the type of X, M, Cm and Out.
+// Predication of the row-block products (bits of `predicated`): ROWMM_IF_OK
+// skips the launch when the step's device error flag is set (a failed small
+// solve leaves the block untouched), ROWMM_IF_RENORM unless the drift check
+// asked for a re-normalisation.
+__device__ __forceinline__ bool rowmm_skip(int predicated, const OpeScalars* __restrict__ sc) {
+  return ((predicated & ROWMM_IF_OK) && sc->err != 0) || ((predicated & ROWMM_IF_RENORM) && sc->renorm == 0);
+}
+
 constexpr int RT = 64;      // rows per work-group tile
 constexpr int CT = 128;     // columns per work-group tile
 
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(256) void k_rowmm(const TI* X0, const TI* __restric
   using MK = Mk<KIND>;
   using acc_t = typename MK::acc_t;
   __shared__ double colsq[2][CT];
-  if (predicated && sc->err != 0) return;        // a failed small solve leaves the block untouched
+  if (rowmm_skip(predicated, sc)) return;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t wr = wave >> 1, wc = wave & 1u;
   const uint32_t row_base = blockIdx.x * RT + wr * 32;
@@ -389,7 +397,7 @@ __global__ __launch_bounds__(256) void k_rowmm_narrow(const TI* X0, const TI* __
   __shared__ TI xs[RTN * LDXN];
   __shared__ TI ms[32 * 32];
   __shared__ double colsq[8][32];
-  if (predicated && sc->err != 0) return;        // a failed small solve leaves the block untouched
+  if (rowmm_skip(predicated, sc)) return;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t kr = lane >> 4, ci = lane & 15u;
   const uint32_t row0 = blockIdx.x * RTN;
@@ -498,7 +506,7 @@ __global__ __launch_bounds__(256, 2) void k_rowmm_lds(const TI* X0, const TI* __
   __shared__ __align__(16) TI xt[2][KC][RT2];
   __shared__ __align__(16) TI mp[2][KC][CT];
   __shared__ double colsq[2][CT];
-  if (predicated && sc->err != 0) return;        // a failed small solve leaves the block untouched
+  if (rowmm_skip(predicated, sc)) return;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t wr = wave >> 1, wc = wave & 1u;
   const uint32_t row0 = blockIdx.x * RT2, col0 = blockIdx.y * CT;

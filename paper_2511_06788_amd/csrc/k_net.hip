@@ -758,6 +758,20 @@ hipError_t pack_weights(ope_net* t) {
   return hipGetLastError();
 }
 
+// One Adam step (Kingma & Ba 2015, Algorithm 1: beta1 0.9, beta2 0.999,
+// eps 1e-8, bias-corrected moments) on the FP32 masters from t->grad, then the
+// BF16 operand copies.
+hipError_t adam_update(ope_net* t, double lr) {
+  t->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.f - std::pow(b1, (float)t->adam_t), bc2 = 1.f - std::pow(b2, (float)t->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3((OPE_NET_PARAMS + 255) / 256), dim3(256), 0, t->ctx->stream, t->w, t->adam_m,
+                     t->adam_v, t->grad, (int)OPE_NET_PARAMS, (float)lr, b1, b2, 1e-8f, bc1, bc2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return pack_weights(t);
+}
+
 ope_status read_loss(ope_net* t, double* loss) {
   HIPCHK(hipMemcpyAsync(t->hloss, t->dloss, 2 * sizeof(double), hipMemcpyDeviceToHost, t->ctx->stream));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
@@ -925,14 +939,16 @@ ope_status ope_net_train_step(ope_net* t, const float* X, const float* V2, const
   if (st != OPE_OK) return st;
   st = grad_pass(t, X, V2 ? V2 : t->v2, T, (uint32_t)B);
   if (st != OPE_OK) return st;
-  t->adam_t += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float bc1 = 1.f - std::pow(b1, (float)t->adam_t), bc2 = 1.f - std::pow(b2, (float)t->adam_t);
-  hipLaunchKernelGGL(k_adam, dim3((OPE_NET_PARAMS + 255) / 256), dim3(256), 0, t->ctx->stream, t->w, t->adam_m,
-                     t->adam_v, t->grad, (int)OPE_NET_PARAMS, (float)lr, b1, b2, 1e-8f, bc1, bc2);
-  HIPCHK(hipGetLastError());
-  HIPCHK(pack_weights(t));
+  HIPCHK(adam_update(t, lr));
   return read_loss(t, loss);
+}
+
+ope_status ope_net_apply_grad(ope_net* t, const float* grad, double lr) {
+  if (!t || !grad || !(lr > 0.0)) return OPE_EINVAL;
+  HIPCHK(hipMemcpyAsync(t->grad, grad, sizeof(float) * OPE_NET_PARAMS, hipMemcpyHostToDevice, t->ctx->stream));
+  HIPCHK(adam_update(t, lr));
+  HIPCHK(hipStreamSynchronize(t->ctx->stream));
+  return OPE_OK;
 }
 
 ope_status ope_net_samples(ope_net* t, const double* R, const double* S, int64_t ld, int64_t B, float* X,

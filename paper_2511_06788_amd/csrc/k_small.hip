@@ -700,9 +700,35 @@ __global__ void k_renorm(const double* __restrict__ C, uint32_t N, float* __rest
   Z[q] = (float)((i == j ? 1.5 : 0.0) - 0.5 * C[q]);
 }
 
+// Drift check after a mixed-precision update: drift = |C - I|_F of the new
+// iterate (C = U^T U accumulated in FP64); above thr the next predicated
+// product applies U <- U (3 I - C) / 2, one Newton-Schulz step toward the
+// nearest orthonormal block (drift E -> O(E^2)).
+__global__ __launch_bounds__(SW) void k_drift_check(const double* __restrict__ C, uint32_t N, double thr,
+                                                    float* __restrict__ Z, OpeScalars* __restrict__ sc) {
+  __shared__ double red[SW];
+  double s = 0.0;
+  const uint64_t nn = (uint64_t)N * N;
+  for (uint64_t q = threadIdx.x; q < nn; q += SW) {
+    const uint32_t i = (uint32_t)(q / N), j = (uint32_t)(q % N);
+    const double d = C[q] - (i == j ? 1.0 : 0.0);
+    s += d * d;
+    Z[q] = (float)((i == j ? 1.5 : 0.0) - 0.5 * C[q]);
+  }
+  s = wg_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double drift = sqrt(s);
+    sc->drift_after = drift;
+    const int on = drift > thr && sc->err == 0 && isfinite(drift);
+    sc->renorm = on;
+    sc->renorms += on;
+  }
+}
+
 __global__ void k_copy_pred(const void* __restrict__ src, void* __restrict__ dst, uint64_t words,
-                            const OpeScalars* __restrict__ sc) {
-  if (sc->err != 0) return;
+                            const OpeScalars* __restrict__ sc, int pred) {
+  if ((pred & ROWMM_IF_OK) && sc->err != 0) return;
+  if ((pred & ROWMM_IF_RENORM) && sc->renorm == 0) return;
   const uint64_t* s = (const uint64_t*)src;
   uint64_t* d = (uint64_t*)dst;
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < words; e += (uint64_t)gridDim.x * blockDim.x)
@@ -799,12 +825,17 @@ hipError_t launch_renorm_matrix(ope_ctx* c, const double* C, float* Z32) {
   return hipGetLastError();
 }
 
-hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes) {
+hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes, int pred) {
   uint64_t words = bytes / 8;
   uint64_t grid = (words + 255) / 256;
   if (grid > 8192) grid = 8192;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_copy_pred, dim3((uint32_t)grid), dim3(256), 0, c->stream, src, dst, words, c->sc);
+  hipLaunchKernelGGL(k_copy_pred, dim3((uint32_t)grid), dim3(256), 0, c->stream, src, dst, words, c->sc, pred);
+  return hipGetLastError();
+}
+
+hipError_t launch_drift_check(ope_ctx* c, const double* C, float* Z32, double thr) {
+  hipLaunchKernelGGL(k_drift_check, dim3(1), dim3(SW), 0, c->stream, C, (uint32_t)c->N, thr, Z32, c->sc);
   return hipGetLastError();
 }
 

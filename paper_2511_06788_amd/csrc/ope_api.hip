@@ -69,10 +69,11 @@ void drop_graphs(ope_ctx* c);
 
 void free_ctx(ope_ctx* c) {
   if (!c) return;
-  void* dptrs[] = {c->diag, c->diag32, c->HU, c->Y, c->Rb[0], c->Rb[1], c->Pb, c->C, c->Lam, c->Linv, c->Sb, c->T,
+  void* dptrs[] = {c->diag, c->diag32, c->ws_own, c->C, c->Lam, c->Linv, c->Sb, c->T,
                    c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
                    c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->sc,
-                   c->Ubak, c->ns_x[0], c->ns_x[1], c->ns_g, c->ns_m, c->ns_p, c->ns_part, c->ns};
+                   c->Ubak, c->ns_x[0], c->ns_x[1], c->ns_g, c->ns_m, c->ns_p, c->ns_part, c->ns,
+                   c->mdiag, c->Upk};
   for (void* p : dptrs)
     if (p) (void)hipFree(p);
   if (c->hsc) (void)hipHostFree(c->hsc);
@@ -94,6 +95,63 @@ ope_status sync_and_read_scalars(ope_ctx* c) {
   return OPE_OK;
 }
 
+// Bytes of one n x N block in the workspace (rounded up to 256).
+size_t ws_block_bytes(const ope_ctx* c) {
+  const size_t esz = c->prec == OPE_FP64 ? sizeof(double) : sizeof(float);
+  return ((size_t)c->n * (size_t)c->N * esz + 255) & ~(size_t)255;
+}
+
+// The five n x N blocks (HU, Y, two CG residuals, a CG direction) carved from
+// one region: the caller's (ope_set_workspace) or one library allocation made
+// on first use.
+ope_status ensure_ws(ope_ctx* c) {
+  if (c->HU) return OPE_OK;
+  const size_t bb = ws_block_bytes(c);
+  char* base = (char*)c->ws_ext;
+  if (!base) {
+    if (hipMalloc(&c->ws_own, 5 * bb) != hipSuccess) {
+      c->ws_own = nullptr;
+      return OPE_ENOMEM;
+    }
+    base = (char*)c->ws_own;
+  }
+  c->HU = base;
+  c->Y = base + bb;
+  c->Rb[0] = base + 2 * bb;
+  c->Rb[1] = base + 3 * bb;
+  c->Pb = base + 4 * bb;
+  return OPE_OK;
+}
+
+#define WSCHK(c)                                \
+  do {                                          \
+    ope_status s_ = ensure_ws(c);               \
+    if (s_ != OPE_OK) return s_;                \
+  } while (0)
+
+// Y = M X for the mass operator: the stencil sweep with M's diagonal and the
+// negated off-diagonal coefficients (the sweep computes d x - sum c_a (x_- + x_+)).
+hipError_t apply_mass(ope_ctx* c, const void* X, void* Y) {
+  const OpeGrid g0 = c->g;
+  const MarchShape ms0 = c->ms;
+  double* d0 = c->diag;
+  c->g.cx = -c->mass_mu[0];
+  c->g.cy = -c->mass_mu[1];
+  c->g.cz = c->g.dim == 3 ? -c->mass_mu[2] : 0.0;
+  if (c->g.dim == 3) {
+    c->ms.cm = c->g.cz;
+    c->ms.cs = c->g.cy;
+  } else {
+    c->ms.cm = c->g.cy;
+  }
+  c->diag = c->mdiag;
+  const hipError_t e = launch_apply_h(c, X, Y);
+  c->g = g0;
+  c->ms = ms0;
+  c->diag = d0;
+  return e;
+}
+
 // HU, Grams C and Lam, the small prep kernel (energy, drift, Lam^{-1}) and the
 // residual R = HU - U Lam written over HU with its column norms in c->rcol.
 // FP64: everything in FP64.  Mixed: FP32 stencil, C and Lam accumulated in
@@ -102,7 +160,19 @@ ope_status phase_residual(ope_ctx* c, const void* Uv) {
   const int N = (int)c->N;
   int64_t np = 0;
   HIPCHK(launch_apply_h(c, Uv, c->HU));
-  if (c->prec == OPE_FP64) {
+  if (c->prec == OPE_FP64 && c->has_mass) {
+    // generalized problem: C = U^T M U, Lam = U^T H U, R = HU - MU Lam, and the
+    // Step-1 right-hand sides M u_j set the CG tolerances (their norms)
+    const double* U = (const double*)Uv;
+    double* HU = (double*)c->HU;
+    double* MU = (double*)c->Rb[1];
+    HIPCHK(apply_mass(c, U, MU));
+    HIPCHK(launch_gram(c, U, N, N, MU, N, N, c->n, c->C));
+    HIPCHK(launch_gram(c, U, N, N, HU, N, N, c->n, c->Lam));
+    HIPCHK(launch_prep_small(c));
+    HIPCHK(launch_colsq(c, MU, N, N, c->cnorm2));
+    HIPCHK(launch_rowmm(c, MU, c->Lam, nullptr, nullptr, HU, 1.0, -1.0, HU, 1, 0, &np));
+  } else if (c->prec == OPE_FP64) {
     const double* U = (const double*)Uv;
     double* HU = (double*)c->HU;
     HIPCHK(launch_gram(c, U, N, N, U, N, N, c->n, c->C));
@@ -299,8 +369,19 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
   if (c->prec == OPE_FP64) {
     double* U = (double*)Uv;
     const double* Y = (const double*)c->Y;
-    HIPCHK(launch_gram(c, U, N, N, Y, N, N, c->n, c->Sb));
-    HIPCHK(launch_gram(c, Y, N, N, Y, N, N, c->n, c->T));
+    if (c->has_mass) {
+      // inner matrices in the M product: S_b = (MU)^T Y, T = Y^T (MY); the CG
+      // residual blocks are free once Step 1 has finished
+      double* MU = (double*)c->Rb[0];
+      double* MY = (double*)c->Rb[1];
+      HIPCHK(apply_mass(c, U, MU));
+      HIPCHK(apply_mass(c, Y, MY));
+      HIPCHK(launch_gram(c, MU, N, N, Y, N, N, c->n, c->Sb));
+      HIPCHK(launch_gram(c, Y, N, N, MY, N, N, c->n, c->T));
+    } else {
+      HIPCHK(launch_gram(c, U, N, N, Y, N, N, c->n, c->Sb));
+      HIPCHK(launch_gram(c, Y, N, N, Y, N, N, c->n, c->T));
+    }
     HIPCHK(launch_small_solve(c, c->Sb, c->T, tau, c->Z, c->A, c->B));
     if (N <= 128) {
       HIPCHK(launch_rowmm(c, U, c->Z, Y, c->Z + NN, nullptr, 0.0, 1.0, U, 0, 1, &np));
@@ -324,11 +405,26 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
     HIPCHK(launch_gram_f32(c, MK_BF16, P, N, N, P, N, N, c->n, c->T));
     HIPCHK(launch_small_solve_delta(c, c->Sb, c->T, tau));
     if (N <= 128) {
-      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, 1, &np));
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, U, 0, ROWMM_IF_OK, &np));
     } else {
       float* tmp = (float*)c->Pb;
-      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, tmp, 0, 1, &np));
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, P, c->Z32 + NN, U, 1.0, 1.0, tmp, 0, ROWMM_IF_OK, &np));
       HIPCHK(launch_copy_pred(c, tmp, U, sizeof(float) * (uint64_t)c->n * N));
+    }
+    // Drift check of the updated iterate: the scheme keeps U^T U constant in
+    // exact arithmetic, but the BF16 P^T P perturbs the Step-2 matrix and the
+    // FP32 products round, so every mixed step may add drift.  C of the new
+    // block (FP64 accumulation) decides on the device whether one
+    // Newton-Schulz step U <- U (3I - C)/2 is applied, so that the block handed
+    // back stays below the drift target.
+    HIPCHK(launch_gram_f32(c, MK_F64, U, N, N, U, N, N, c->n, c->C));
+    HIPCHK(launch_drift_check(c, c->C, c->Z32, c->drift_tol));
+    if (N <= 128) {
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, U, 0, ROWMM_IF_RENORM, &np));
+    } else {
+      float* tmp = (float*)c->Pb;
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, tmp, 0, ROWMM_IF_RENORM, &np));
+      HIPCHK(launch_copy_pred(c, tmp, U, sizeof(float) * (uint64_t)c->n * N, ROWMM_IF_RENORM));
     }
   }
   return OPE_OK;
@@ -666,7 +762,8 @@ ope_status batch_round(ope_batch* b, void* const* U, double tau, double res_tol,
     if (!go[i]) continue;
     ope_ctx* c = b->ctx[i];
     HIPCHK(hipStreamWaitEvent(c->stream, b->start, 0));
-    ope_status st = mixed_renormalize(c, U[i]);
+    ope_status st = ensure_ws(c);
+    if (st == OPE_OK) st = mixed_renormalize(c, U[i]);
     if (st == OPE_OK) st = phase_residual(c, U[i]);
     if (st == OPE_OK) st = phase_warm_start(c, U[i]);
     if (st == OPE_OK && hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
@@ -888,6 +985,7 @@ const char* ope_status_string(ope_status s) {
     case OPE_ECG_MAXIT: return "inner CG reached its iteration cap";
     case OPE_EPIVOT: return "non-positive pivot in a small FP64 solve";
     case OPE_EUNSUPPORTED: return "not supported by the library";
+    case OPE_ENOTSPD: return "operator is not symmetric positive definite";
   }
   return "unknown status";
 }
@@ -945,6 +1043,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   c->max_iter = 2000;
   c->check_every = 4;
   c->use_graphs = 0;        // eager launches: measured about 2% faster than graph replays
+  c->drift_tol = 2.5e-7;
 
   // streaming launch shape: about 2048 work-groups, whole passes of points
   const int64_t NV = N / c->vw;
@@ -978,11 +1077,9 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
 
   bool ok = true;
   ok &= dalloc(&c->diag, n) == hipSuccess;
-  ok &= balloc(&c->HU, blk * esz) == hipSuccess;
-  ok &= balloc(&c->Y, blk * esz) == hipSuccess;
-  ok &= balloc(&c->Rb[0], blk * esz) == hipSuccess;
-  ok &= balloc(&c->Rb[1], blk * esz) == hipSuccess;
-  ok &= balloc(&c->Pb, blk * esz) == hipSuccess;
+  // the five n x N blocks are allocated on first use (ensure_ws), or come from the caller
+  (void)blk;
+  (void)esz;
   if (precision == OPE_MIXED) {
     ok &= dalloc(&c->diag32, n) == hipSuccess;
     ok &= dalloc(&c->Lam32, N * N) == hipSuccess;
@@ -1044,6 +1141,36 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
     free_ctx(c);
     return OPE_EHIP;
   }
+  // Coercivity (Section 2.2): H must be SPD for G = H^{-1} to exist.  The
+  // smallest eigenvalue is at least lambda_min(c (-Lap_h)) + min(V + shift)
+  // (Weyl), a closed form; when that bound is not positive a Lanczos run on
+  // the device decides: a Ritz value <= 0 proves an eigenvalue <= 0.
+  double lap_min = 0.0, vmin = 1e300;
+  for (int a = 0; a < op->dim; ++a) {
+    const double sn = std::sin(M_PI / (2.0 * (double)(op->m[a] + 1)));
+    lap_min += op->kinetic * 4.0 * sn * sn / (op->h[a] * op->h[a]);
+  }
+  for (int64_t p = 0; p < n; ++p) vmin = std::min(vmin, op->V[p] + op->shift);
+  if (!(std::isfinite(vmin))) {
+    free_ctx(c);
+    return OPE_EINVAL;
+  }
+  if (!(lap_min + vmin > 0.0)) {
+    double lo = 0.0, hi = 0.0;
+    int its = 0;
+    if (lanczos_extremes(c, 1000, &lo, &hi, &its) != hipSuccess) {
+      free_ctx(c);
+      return OPE_EHIP;
+    }
+    c->lz_done = 1;
+    c->lz_min = lo;
+    c->lz_max = hi;
+    c->lz_iters = its;
+    if (!(lo > 0.0)) {
+      free_ctx(c);
+      return OPE_ENOTSPD;
+    }
+  }
   *out = c;
   return OPE_OK;
 }
@@ -1074,6 +1201,7 @@ ope_status ope_source_solve(ope_ctx* c, const double* U, double* Y, const double
   if (!c || !U || !Y || !(tol >= 0.0) || max_iter < 0) return OPE_EINVAL;
   if (U == Y) return OPE_EINVAL;
   if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  WSCHK(c);
   const int N = (int)c->N;
   // r0 = U - H Y0, column norms of r0 and of U
   if (Y0) {
@@ -1132,6 +1260,7 @@ ope_status ope_small_solve(ope_ctx* c, const double* Sb, const double* T, double
 ope_status ope_update(ope_ctx* c, double* U, const double* Y, const double* Z) {
   if (!c || !U || !Y || !Z || U == Y) return OPE_EINVAL;
   if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  WSCHK(c);
   const size_t NN = (size_t)c->N * c->N;
   int64_t np = 0;
   if (c->N <= 128) {
@@ -1145,6 +1274,7 @@ ope_status ope_update(ope_ctx* c, double* U, const double* Y, const double* Z) {
 
 ope_status ope_energy(ope_ctx* c, const void* U, double* energy) {
   if (!c || !U || !energy) return OPE_EINVAL;
+  WSCHK(c);
   ope_status st = phase_residual(c, U);
   if (st != OPE_OK) return st;
   st = sync_and_read_scalars(c);
@@ -1155,6 +1285,7 @@ ope_status ope_energy(ope_ctx* c, const void* U, double* energy) {
 
 ope_status ope_residual(ope_ctx* c, const void* U, double* residual, double* ritz, double* drift) {
   if (!c || !U) return OPE_EINVAL;
+  WSCHK(c);
   const int N = (int)c->N;
   ope_status st = phase_residual(c, U);
   if (st != OPE_OK) return st;
@@ -1226,6 +1357,7 @@ ope_status ope_profile_end(ope_ctx* c, ope_kernel_time* out) {
 
 ope_status ope_step(ope_ctx* c, void* U, double tau, ope_step_info* info) {
   if (!c || !U || !(tau > 0.0)) return OPE_EINVAL;
+  WSCHK(c);
   return run_step(c, U, tau, info, -1.0, nullptr);
 }
 
@@ -1257,6 +1389,7 @@ ope_status ope_rowmm_f32(ope_ctx* c, int32_t kind, const float* X0, const float*
 
 ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t max_steps, ope_solve_info* info) {
   if (!c || !U || !(tau > 0.0) || !(res_tol >= 0.0) || max_steps < 0) return OPE_EINVAL;
+  WSCHK(c);
   ope_solve_info si;
   memset(&si, 0, sizeof(si));
   ope_status st = OPE_OK;
@@ -1296,6 +1429,115 @@ ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t ma
   return st;
 }
 
+// Residual phase and Step-1 warm start of the current iterate, scalars on the host.
+static ope_status prepare_iterate(ope_ctx* c, void* U) {
+  ope_status st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  st = phase_warm_start(c, U);
+  if (st != OPE_OK) return st;
+  st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  return (ope_status)c->hsc->err;
+}
+
+// Algorithm 1 with the step chosen in [tau_min, tau_max]: a step whose energy
+// rises above the current one (Theorem 4.2: below a threshold step the energy
+// decays) is redone from the saved iterate with the step shrunk, never below
+// tau_min; after an accepted step the next one grows, never above tau_max.
+static ope_status solve_adaptive(ope_ctx* c, void* U, const ope_solve_opts* o, ope_solve_info* si) {
+  const bool adaptive = o->tau_min < o->tau_max;
+  const size_t bytes = (c->prec == OPE_FP64 ? sizeof(double) : sizeof(float)) * (size_t)c->n * (size_t)c->N;
+  if (adaptive && !c->Ubak) {
+    if (balloc(&c->Ubak, sizeof(double) * (size_t)c->n * (size_t)c->N) != hipSuccess) return OPE_ENOMEM;
+  }
+  const double slack = 1e-13;
+  const bool use_ref = !std::isnan(o->energy_ref);
+  double tau = o->tau;
+  ope_status st = prepare_iterate(c, U);
+  if (st != OPE_OK) return st;
+  double E = c->hsc->energy, res = c->hsc->residual, drift = c->hsc->drift;
+  c->drift_seen = drift;
+  double errE = std::fabs(E);
+  double best = 1e300;
+  int32_t since_best = 0;
+  for (;;) {
+    si->residual = res;
+    si->energy = E;
+    si->drift = drift;
+    si->tau = tau;
+    if (o->res_tol >= 0.0 && res <= o->res_tol) {
+      si->converged = 1;
+      break;
+    }
+    if (o->energy_tol >= 0.0) {
+      const bool stop = use_ref ? (E - o->energy_ref) / std::fabs(o->energy_ref) <= o->energy_tol
+                                : errE <= o->energy_tol;
+      if (stop) {
+        si->converged = 1;
+        break;
+      }
+    }
+    if (si->steps >= o->max_steps || si->stalled) break;
+    double E_new = 0.0;
+    for (;;) {
+      if (adaptive) HIPCHK(hipMemcpyAsync(c->Ubak, U, bytes, hipMemcpyDeviceToDevice, c->stream));
+      int32_t iters = 0;
+      bool cg_done = false;
+      st = run_cg(c, c->max_iter, &iters, &cg_done);
+      if (st != OPE_OK) return st;
+      st = phase_update(c, U, tau);
+      if (st != OPE_OK) return st;
+      HIPCHK(hipMemcpyAsync(c->hsc2, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream));
+      st = phase_residual(c, U);
+      if (st == OPE_OK) st = phase_warm_start(c, U);
+      if (st == OPE_OK) st = sync_and_read_scalars(c);
+      if (st != OPE_OK) return st;
+      if (c->hsc2->err != 0) return (ope_status)c->hsc2->err;    // the step failed; U is unchanged
+      if (c->hsc->err != 0) return (ope_status)c->hsc->err;
+      E_new = c->hsc->energy;
+      if (adaptive && !(E_new <= E + slack * std::fabs(E)) && tau > o->tau_min) {
+        HIPCHK(hipMemcpyAsync(U, c->Ubak, bytes, hipMemcpyDeviceToDevice, c->stream));
+        si->rejected += 1;
+        tau = std::max(o->tau_min, o->shrink * tau);
+        st = prepare_iterate(c, U);
+        if (st != OPE_OK) return st;
+        continue;
+      }
+      si->inner_iterations += c->hsc2->cg_iters;
+      break;
+    }
+    errE = std::fabs(E_new - E) / std::fabs(E);
+    E = E_new;
+    res = c->hsc->residual;
+    drift = c->hsc->drift;
+    c->drift_seen = drift;
+    si->steps += 1;
+    tau = std::min(o->tau_max, o->grow * tau);
+    if (res < 0.9 * best) {
+      best = res;
+      since_best = 0;
+    } else if (c->prec == OPE_MIXED && ++since_best >= 60) {
+      si->stalled = 1;
+    }
+  }
+  return OPE_OK;
+}
+
+ope_status ope_solve_ex(ope_ctx* c, void* U, const ope_solve_opts* o, ope_solve_info* info) {
+  if (!c || !U || !o) return OPE_EINVAL;
+  if (!(o->tau_min > 0.0) || !(o->tau_min <= o->tau) || !(o->tau <= o->tau_max) || !(o->grow >= 1.0) ||
+      !(o->shrink > 0.0 && o->shrink < 1.0) || o->max_steps < 0 || std::isinf(o->tau_max))
+    return OPE_EINVAL;
+  if (!std::isnan(o->energy_ref) && !(std::fabs(o->energy_ref) > 0.0)) return OPE_EINVAL;
+  if (c->net) return OPE_EUNSUPPORTED;
+  WSCHK(c);
+  ope_solve_info si;
+  memset(&si, 0, sizeof(si));
+  const ope_status st = solve_adaptive(c, U, o, &si);
+  if (info) *info = si;
+  return st;
+}
+
 ope_status ope_set_preconditioner(ope_ctx* c, ope_net* net, int32_t judge) {
   if (!c) return OPE_EINVAL;
   if (!net) {
@@ -1303,7 +1545,7 @@ ope_status ope_set_preconditioner(ope_ctx* c, ope_net* net, int32_t judge) {
     return OPE_OK;
   }
   if (net->ctx != c || net->max_batch < c->N || (judge != 0 && judge != 1)) return OPE_EINVAL;
-  if (c->prec != OPE_FP64 || c->N > 128) return OPE_EUNSUPPORTED;
+  if (c->prec != OPE_FP64 || c->N > 128 || c->has_mass) return OPE_EUNSUPPORTED;
   c->net_judge = judge;
   if (judge && !c->Ubak) {
     if (balloc(&c->Ubak, sizeof(double) * (size_t)c->n * (size_t)c->N) != hipSuccess) return OPE_ENOMEM;
@@ -1314,6 +1556,7 @@ ope_status ope_set_preconditioner(ope_ctx* c, ope_net* net, int32_t judge) {
 
 ope_status ope_step_learned(ope_ctx* c, void* U, double tau, ope_step_info* info, int32_t* accepted) {
   if (!c || !U || !(tau > 0.0)) return OPE_EINVAL;
+  WSCHK(c);
   ope_status st = check_learned(c);
   if (st != OPE_OK) return st;
   if (accepted) *accepted = 0;
@@ -1554,6 +1797,7 @@ TunedShape tune_shape(ope_ctx* c, const double* X, hipEvent_t e0, hipEvent_t e1)
 
 ope_status ope_autotune(ope_ctx* c) {
   if (!c) return OPE_EINVAL;
+  WSCHK(c);
   HIPCHK(hipStreamSynchronize(c->stream));
   void* X = nullptr;                                // FP64: the scratch right-hand side
   const size_t bytes = c->prec == OPE_FP64 ? sizeof(double) * (size_t)c->n * (size_t)c->N : 0;
@@ -1598,6 +1842,8 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
     ope_ctx* c = b->ctx[i];
     const uint32_t NV = (uint32_t)(c->N / c->vw);
     const Key k{c->g.dim, c->prec, c->vw, (c->g.m0 + 7) / 8, (c->g.m1 + 7) / 8, (c->g.m2 + 7) / 8, (NV + 7) / 8};
+    status = ensure_ws(c);
+    if (status != OPE_OK) break;
     auto f = best.find(k);
     if (f == best.end()) {
       void* X = nullptr;                          // FP64: the scratch right-hand side
@@ -1623,6 +1869,171 @@ ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
   (void)hipEventDestroy(e1);
   if (tuned_keys) *tuned_keys = (int32_t)best.size();
   return status;
+}
+
+
+ope_status ope_spectrum_bounds(ope_ctx* c, double* lmin, double* lmax) {
+  if (!c) return OPE_EINVAL;
+  if (!c->lz_done) {
+    double lo = 0.0, hi = 0.0;
+    int its = 0;
+    HIPCHK(lanczos_extremes(c, 1000, &lo, &hi, &its));
+    c->lz_done = 1;
+    c->lz_min = lo;
+    c->lz_max = hi;
+    c->lz_iters = its;
+  }
+  if (lmin) *lmin = c->lz_min;
+  if (lmax) *lmax = c->lz_max;
+  return OPE_OK;
+}
+
+ope_status ope_workspace_size(const ope_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return OPE_EINVAL;
+  *bytes = 5 * ws_block_bytes(c);
+  return OPE_OK;
+}
+
+ope_status ope_set_workspace(ope_ctx* c, void* dptr, size_t bytes) {
+  if (!c) return OPE_EINVAL;
+  if (dptr && (bytes < 5 * ws_block_bytes(c) || (reinterpret_cast<uintptr_t>(dptr) % 256) != 0)) return OPE_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  if (c->ws_own) {
+    HIPCHK(hipFree(c->ws_own));
+    c->ws_own = nullptr;
+  }
+  c->HU = c->Y = c->Rb[0] = c->Rb[1] = c->Pb = nullptr;
+  c->ws_ext = dptr;
+  c->ws_ext_bytes = dptr ? bytes : 0;
+  if (dptr) return ensure_ws(c);
+  return OPE_OK;
+}
+
+ope_status ope_set_mass(ope_ctx* c, const double* d, const double* mu) {
+  if (!c) return OPE_EINVAL;
+  if (!d) {
+    c->has_mass = 0;
+    return OPE_OK;
+  }
+  if (!mu) return OPE_EINVAL;
+  if (c->prec != OPE_FP64 || c->net || c->N > 256) return OPE_EUNSUPPORTED;
+  const int dims = c->g.dim;
+  double off = 0.0;
+  for (int a = 0; a < dims; ++a) {
+    if (!std::isfinite(mu[a])) return OPE_EINVAL;
+    off += 2.0 * std::fabs(mu[a]);
+  }
+  // strict diagonal dominance with a positive diagonal: M is SPD (Gershgorin)
+  for (int64_t p = 0; p < c->n; ++p)
+    if (!std::isfinite(d[p])) return OPE_EINVAL;
+  for (int64_t p = 0; p < c->n; ++p)
+    if (!(d[p] > off)) return OPE_ENOTSPD;
+  if (!c->mdiag && dalloc(&c->mdiag, c->n) != hipSuccess) return OPE_ENOMEM;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->mdiag, d, sizeof(double) * c->n, hipMemcpyHostToDevice));
+  for (int a = 0; a < 3; ++a) c->mass_mu[a] = a < dims ? mu[a] : 0.0;
+  c->has_mass = 1;
+  drop_graphs(c);
+  return OPE_OK;
+}
+
+ope_status ope_apply_mass(ope_ctx* c, const double* X, double* Y) {
+  if (!c || !X || !Y || X == Y) return OPE_EINVAL;
+  if (!c->has_mass) return OPE_EINVAL;
+  HIPCHK(apply_mass(c, X, Y));
+  return OPE_OK;
+}
+
+ope_status ope_orthonormalize(ope_ctx* c, double* U) {
+  if (!c || !U) return OPE_EINVAL;
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  WSCHK(c);
+  const int N = (int)c->N;
+  int64_t np = 0;
+  if (c->has_mass) {
+    HIPCHK(apply_mass(c, U, c->Rb[1]));
+    HIPCHK(launch_gram(c, U, N, N, (const double*)c->Rb[1], N, N, c->n, c->Wsm));
+  } else {
+    HIPCHK(launch_gram(c, U, N, N, U, N, N, c->n, c->Wsm));
+  }
+  HIPCHK(hipMemsetAsync(&c->sc->err, 0, sizeof(int32_t), c->stream));
+  HIPCHK(launch_chol_rinv(c, c->Wsm, c->Z));
+  if (N <= 128) {
+    HIPCHK(launch_rowmm(c, U, c->Z, nullptr, nullptr, nullptr, 0.0, 1.0, U, 0, ROWMM_IF_OK, &np));
+  } else {
+    HIPCHK(launch_rowmm(c, U, c->Z, nullptr, nullptr, nullptr, 0.0, 1.0, (double*)c->Pb, 0, ROWMM_IF_OK, &np));
+    HIPCHK(launch_copy_pred(c, c->Pb, U, sizeof(double) * (uint64_t)c->n * N));
+  }
+  ope_status st = sync_and_read_scalars(c);
+  if (st != OPE_OK) return st;
+  return (ope_status)c->hsc->err;
+}
+
+ope_status ope_energy_d(ope_ctx* c, const void* U, double* d_energy) {
+  if (!c || !U || !d_energy) return OPE_EINVAL;
+  WSCHK(c);
+  ope_status st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  HIPCHK(launch_scalar_copy(c, 0, d_energy));
+  return OPE_OK;
+}
+
+ope_status ope_residual_d(ope_ctx* c, const void* U, double* d_residual, double* d_drift) {
+  if (!c || !U || (!d_residual && !d_drift)) return OPE_EINVAL;
+  WSCHK(c);
+  ope_status st = phase_residual(c, U);
+  if (st != OPE_OK) return st;
+  HIPCHK(launch_cg_setup(c, c->rcol));   // computes the residual scalar from the column norms
+  if (d_residual) HIPCHK(launch_scalar_copy(c, 1, d_residual));
+  if (d_drift) HIPCHK(launch_scalar_copy(c, 2, d_drift));
+  return OPE_OK;
+}
+
+// Blocks with a leading dimension other than N go through a packed staging
+// block: copy in, the packed entry point, copy out (steps only).
+static ope_status pack_in(ope_ctx* c, const void* U, int64_t ldu) {
+  const size_t esz = c->prec == OPE_FP64 ? sizeof(double) : sizeof(float);
+  if (!c->Upk && balloc(&c->Upk, esz * (size_t)c->n * (size_t)c->N) != hipSuccess) return OPE_ENOMEM;
+  HIPCHK(hipMemcpy2DAsync(c->Upk, esz * c->N, U, esz * (size_t)ldu, esz * c->N, (size_t)c->n,
+                          hipMemcpyDeviceToDevice, c->stream));
+  return OPE_OK;
+}
+
+static ope_status unpack_out(ope_ctx* c, void* U, int64_t ldu) {
+  const size_t esz = c->prec == OPE_FP64 ? sizeof(double) : sizeof(float);
+  HIPCHK(hipMemcpy2DAsync(U, esz * (size_t)ldu, c->Upk, esz * c->N, esz * c->N, (size_t)c->n,
+                          hipMemcpyDeviceToDevice, c->stream));
+  return OPE_OK;
+}
+
+ope_status ope_step_ld(ope_ctx* c, void* U, int64_t ldu, double tau, ope_step_info* info) {
+  if (!c || !U || !(tau > 0.0) || ldu < c->N) return OPE_EINVAL;
+  if (ldu == c->N) return ope_step(c, U, tau, info);
+  ope_status st = pack_in(c, U, ldu);
+  if (st != OPE_OK) return st;
+  st = ope_step(c, c->Upk, tau, info);
+  if (st != OPE_OK && st != OPE_ECG_MAXIT) return st;
+  const ope_status st2 = unpack_out(c, U, ldu);
+  if (st2 != OPE_OK) return st2;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+ope_status ope_energy_ld(ope_ctx* c, const void* U, int64_t ldu, double* energy) {
+  if (!c || !U || !energy || ldu < c->N) return OPE_EINVAL;
+  if (ldu == c->N) return ope_energy(c, U, energy);
+  ope_status st = pack_in(c, U, ldu);
+  if (st != OPE_OK) return st;
+  return ope_energy(c, c->Upk, energy);
+}
+
+ope_status ope_residual_ld(ope_ctx* c, const void* U, int64_t ldu, double* residual, double* ritz, double* drift) {
+  if (!c || !U || ldu < c->N) return OPE_EINVAL;
+  if (ldu == c->N) return ope_residual(c, U, residual, ritz, drift);
+  ope_status st = pack_in(c, U, ldu);
+  if (st != OPE_OK) return st;
+  return ope_residual(c, c->Upk, residual, ritz, drift);
 }
 
 }  // extern "C"

@@ -71,7 +71,13 @@ struct OpeScalars {
   double eta;         // inner tolerance of this step
   int32_t err;        // ope_status of the device side of the step (0 = ok)
   int32_t cg_iters;   // CG iterations that had at least one active column
+  int32_t renorm;     // mixed precision: 1 when the drift check after the update re-normalises U
+  int32_t renorms;    // re-normalisations since the context was created
+  double drift_after; // mixed precision: |U^T U - I|_F of the updated iterate before the check's correction
 };
+
+// predication bits of the row-block products and the predicated copy
+enum { ROWMM_IF_OK = 1, ROWMM_IF_RENORM = 2 };
 
 struct ope_ctx {
   int device;
@@ -118,6 +124,7 @@ struct ope_ctx {
   int32_t max_iter;
   int32_t check_every;          // CG iterations between host convergence checks (even: graph chunks)
   double drift_seen;            // drift of the last iterate whose scalars reached the host
+  double drift_tol;             // mixed precision: drift above which an updated block is re-normalised
   int64_t renorms;              // mixed precision: re-normalisations applied
   int use_graphs;               // replay CG chunks as captured graphs
   int graph_state;              // 0 not built, 1 built, -1 capture failed (eager launches)
@@ -127,6 +134,20 @@ struct ope_ctx {
   int stream_wgs;               // work-groups of the flat streaming kernels
   int stream_pts;               // grid points per flat streaming work-group
   MarchShape ms;                // plane-marching stencil sweeps
+  // workspace of the five n x N blocks: library-owned (ws_own) or the caller's (ws_ext)
+  void* ws_own;
+  void* ws_ext;
+  size_t ws_ext_bytes;
+  // generalized problem H u = lambda M u: M = diag(mdiag) + sum_a mu_a (S_a + S_a^T) (FP64 only)
+  int has_mass;
+  double* mdiag;
+  double mass_mu[3];
+  // staging block for callers' blocks with a leading dimension other than N
+  void* Upk;
+  // Lanczos estimates of the extreme eigenvalues of H (set-up check)
+  int lz_done;
+  int lz_iters;
+  double lz_min, lz_max;
   // learned form: network (not owned) and the saved iterate its judge restores
   ope_net* net;
   int net_judge;                // 1: the plain step judges each learned iterate and replaces it if rejected
@@ -235,7 +256,12 @@ hipError_t launch_sqmm(ope_ctx* c, const double* A, int ta, const double* B, int
 // Z32 (N x N, FP32) = (3 I - C) / 2
 hipError_t launch_renorm_matrix(ope_ctx* c, const double* C, float* Z32);
 // dst = src (bytes, a multiple of 8) unless the step's error flag is set
-hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes);
+// (pred = ROWMM_IF_OK), or only when the drift check asked for a
+// re-normalisation (pred = ROWMM_IF_RENORM)
+hipError_t launch_copy_pred(ope_ctx* c, const void* src, void* dst, uint64_t bytes, int pred = ROWMM_IF_OK);
+// drift check after a mixed-precision update: from C = U^T U, sets sc->renorm
+// (drift above thr) and writes Z32 = (3 I - C) / 2
+hipError_t launch_drift_check(ope_ctx* c, const double* C, float* Z32, double thr);
 hipError_t launch_solve_setup(ope_ctx* c, const double* rho0, double tol);
 
 // Batched CG sweeps (k_stencil.hip): one work item range per problem.  The
@@ -279,6 +305,14 @@ hipError_t launch_reduce_batched(hipStream_t s, int mode, int par, const ReduceJ
 hipError_t launch_gather_flags(hipStream_t s, const ReduceJob* jobs, uint32_t njobs);
 // whether a context's CG column sums fit the one-work-group reduction
 bool reduce_few_fits(const ope_ctx* c);
+
+// set-up kernels (k_check.hip): Lanczos extreme eigenvalues of H (FP64, one
+// vector, temporary device buffers), the Cholesky-based R^{-1} of an N x N SPD
+// matrix held in A (overwritten), and copies of a device scalar (0 energy,
+// 1 residual, 2 drift) to a caller's device address
+hipError_t lanczos_extremes(ope_ctx* c, int max_it, double* lmin, double* lmax, int* iters);
+hipError_t launch_chol_rinv(ope_ctx* c, double* A, double* Rinv);
+hipError_t launch_scalar_copy(ope_ctx* c, int which, double* out);
 
 // learned form (k_net.hip): column sums of squares of point-major FP64 rows
 // (B <= 256) into out, and E = U - P(R) for the context's N columns

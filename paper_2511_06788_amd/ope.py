@@ -24,6 +24,7 @@ OPE_ENONFINITE = 4
 OPE_ECG_MAXIT = 5
 OPE_EPIVOT = 6
 OPE_EUNSUPPORTED = 7
+OPE_ENOTSPD = 8
 OPE_FP64 = 0
 OPE_MIXED = 1
 MK_F64, MK_F32, MK_BF16 = 0, 1, 2
@@ -31,7 +32,7 @@ MK_F64, MK_F32, MK_BF16 = 0, 1, 2
 STATUS_NAMES = {
     OPE_OK: "OPE_OK", OPE_EINVAL: "OPE_EINVAL", OPE_ENOMEM: "OPE_ENOMEM", OPE_EHIP: "OPE_EHIP",
     OPE_ENONFINITE: "OPE_ENONFINITE", OPE_ECG_MAXIT: "OPE_ECG_MAXIT", OPE_EPIVOT: "OPE_EPIVOT",
-    OPE_EUNSUPPORTED: "OPE_EUNSUPPORTED",
+    OPE_EUNSUPPORTED: "OPE_EUNSUPPORTED", OPE_ENOTSPD: "OPE_ENOTSPD",
 }
 
 
@@ -72,6 +73,24 @@ class ope_solve_info(ctypes.Structure):
         ("inner_iterations", ctypes.c_int64),
         ("stalled", ctypes.c_int32),
         ("learned_steps", ctypes.c_int32),
+        ("rejected", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+    ]
+
+
+class ope_solve_opts(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double),
+        ("tau_min", ctypes.c_double),
+        ("tau_max", ctypes.c_double),
+        ("grow", ctypes.c_double),
+        ("shrink", ctypes.c_double),
+        ("res_tol", ctypes.c_double),
+        ("energy_tol", ctypes.c_double),
+        ("energy_ref", ctypes.c_double),
+        ("max_steps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -137,6 +156,19 @@ SIGNATURES = {
     "ope_net_samples": ([_P, _P, _P, _I64, _I64, _P, _P], _I32),
     "ope_set_preconditioner": ([_P, _P, _I32], _I32),
     "ope_step_learned": ([_P, _P, _D, ctypes.POINTER(ope_step_info), ctypes.POINTER(_I32)], _I32),
+    "ope_solve_ex": ([_P, _P, ctypes.POINTER(ope_solve_opts), ctypes.POINTER(ope_solve_info)], _I32),
+    "ope_net_apply_grad": ([_P, _P, _D], _I32),
+    "ope_spectrum_bounds": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_D)], _I32),
+    "ope_set_mass": ([_P, _P, _P], _I32),
+    "ope_apply_mass": ([_P, _P, _P], _I32),
+    "ope_orthonormalize": ([_P, _P], _I32),
+    "ope_workspace_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "ope_set_workspace": ([_P, _P, ctypes.c_size_t], _I32),
+    "ope_energy_d": ([_P, _P, _P], _I32),
+    "ope_residual_d": ([_P, _P, _P, _P], _I32),
+    "ope_step_ld": ([_P, _P, _I64, _D, ctypes.POINTER(ope_step_info)], _I32),
+    "ope_energy_ld": ([_P, _P, _I64, ctypes.POINTER(_D)], _I32),
+    "ope_residual_ld": ([_P, _P, _I64, ctypes.POINTER(_D), _P, ctypes.POINTER(_D)], _I32),
 }
 
 OPE_NET_PARAMS = 15120
@@ -284,6 +316,89 @@ def ope_solve(ctx: int, U, tau: float, res_tol: float, max_steps: int) -> ope_so
     return info
 
 
+def ope_solve_ex(ctx: int, U, tau: float, tau_min: Optional[float] = None, tau_max: Optional[float] = None,
+                 grow: float = 1.5, shrink: float = 0.5, res_tol: float = -1.0, energy_tol: float = -1.0,
+                 energy_ref: Optional[float] = None, max_steps: int = 10000) -> ope_solve_info:
+    """Algorithm 1 with the step chosen in [tau_min, tau_max] (fixed when equal)."""
+    o = ope_solve_opts()
+    o.tau = tau
+    o.tau_min = tau if tau_min is None else tau_min
+    o.tau_max = tau if tau_max is None else tau_max
+    o.grow, o.shrink = grow, shrink
+    o.res_tol, o.energy_tol = res_tol, energy_tol
+    o.energy_ref = float("nan") if energy_ref is None else energy_ref
+    o.max_steps = int(max_steps)
+    o.reserved = 0
+    info = ope_solve_info()
+    _check(lib().ope_solve_ex(ctx, _ptr(U), ctypes.byref(o), ctypes.byref(info)), "ope_solve_ex",
+           allow=(OPE_ECG_MAXIT,))
+    return info
+
+
+def ope_spectrum_bounds(ctx: int):
+    """Returns the Lanczos estimates ``(lambda_min, lambda_max)`` of H."""
+    lo, hi = _D(0.0), _D(0.0)
+    _check(lib().ope_spectrum_bounds(ctx, ctypes.byref(lo), ctypes.byref(hi)), "ope_spectrum_bounds")
+    return lo.value, hi.value
+
+
+def ope_set_mass(ctx: int, d: Optional[np.ndarray], mu: Sequence[float] = (0.0, 0.0, 0.0)) -> None:
+    if d is None:
+        _check(lib().ope_set_mass(ctx, None, None), "ope_set_mass")
+        return
+    dh = np.ascontiguousarray(d, dtype=np.float64)
+    muh = np.ascontiguousarray(list(mu) + [0.0] * (3 - len(mu)), dtype=np.float64)
+    _check(lib().ope_set_mass(ctx, dh.ctypes.data, muh.ctypes.data), "ope_set_mass")
+
+
+def ope_apply_mass(ctx: int, X, Y) -> None:
+    _check(lib().ope_apply_mass(ctx, _ptr(X), _ptr(Y)), "ope_apply_mass")
+
+
+def ope_orthonormalize(ctx: int, U) -> None:
+    _check(lib().ope_orthonormalize(ctx, _ptr(U)), "ope_orthonormalize")
+
+
+def ope_workspace_size(ctx: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().ope_workspace_size(ctx, ctypes.byref(b)), "ope_workspace_size")
+    return b.value
+
+
+def ope_set_workspace(ctx: int, buf, nbytes: int) -> None:
+    _check(lib().ope_set_workspace(ctx, _ptr(buf), int(nbytes)), "ope_set_workspace")
+
+
+def ope_energy_d(ctx: int, U, d_energy) -> None:
+    _check(lib().ope_energy_d(ctx, _ptr(U), _ptr(d_energy)), "ope_energy_d")
+
+
+def ope_residual_d(ctx: int, U, d_residual, d_drift) -> None:
+    _check(lib().ope_residual_d(ctx, _ptr(U), _ptr(d_residual), _ptr(d_drift)), "ope_residual_d")
+
+
+def ope_step_ld(ctx: int, U, ldu: int, tau: float, allow_maxit: bool = True) -> ope_step_info:
+    info = ope_step_info()
+    st = lib().ope_step_ld(ctx, _ptr(U), int(ldu), tau, ctypes.byref(info))
+    _check(st, "ope_step_ld", allow=(OPE_ECG_MAXIT,) if allow_maxit else ())
+    return info
+
+
+def ope_energy_ld(ctx: int, U, ldu: int) -> float:
+    e = _D(0.0)
+    _check(lib().ope_energy_ld(ctx, _ptr(U), int(ldu), ctypes.byref(e)), "ope_energy_ld")
+    return e.value
+
+
+def ope_residual_ld(ctx: int, U, ldu: int, N: int, want_ritz: bool = True):
+    res = _D(0.0)
+    drift = _D(0.0)
+    ritz = (ctypes.c_double * N)() if want_ritz else None
+    _check(lib().ope_residual_ld(ctx, _ptr(U), int(ldu), ctypes.byref(res), ritz, ctypes.byref(drift)),
+           "ope_residual_ld")
+    return res.value, (np.array(ritz[:], dtype=np.float64) if want_ritz else None), drift.value
+
+
 OPE_SWEEP_CHUNK_MAJOR = 1
 OPE_SWEEP_NONTEMPORAL = 2
 OPE_SWEEP_NARROW = 4
@@ -384,6 +499,13 @@ def ope_net_train_step(net: int, X, V2, T, B: int, lr: float) -> float:
     _check(lib().ope_net_train_step(net, _ptr(X), _ptr(V2), _ptr(T), int(B), float(lr), ctypes.byref(loss)),
            "ope_net_train_step")
     return loss.value
+
+
+def ope_net_apply_grad(net: int, grad: np.ndarray, lr: float) -> None:
+    g = np.ascontiguousarray(grad, dtype=np.float32).reshape(-1)
+    if g.size != OPE_NET_PARAMS:
+        raise ValueError(f"{OPE_NET_PARAMS} gradient values expected")
+    _check(lib().ope_net_apply_grad(net, g.ctypes.data, float(lr)), "ope_net_apply_grad")
 
 
 def ope_net_samples(net: int, R, S, ld: int, B: int, X, T) -> None:

@@ -115,7 +115,7 @@ def test_autotuned_mixed_batch_steps():
         U32 = p.U0.astype(np.float32).astype(np.float64)
         assert abs(i1[i].energy - O.energy(op, U32)) <= 1e-6 * abs(i1[i].energy), i
         assert i2[i].energy < i1[i].energy, i
-        assert i2[i].drift <= 1e-5, i
+        assert i2[i].drift <= 1e-6, i
 
 
 def test_full_batched_workload_one_step():

@@ -136,5 +136,6 @@ def test_mixed_96_cubed_n512_steps():
     E_ref = O.energy(op, U64)
     assert abs(i1.energy - E_ref) <= 1e-6 * abs(E_ref)
     assert i2.energy < i1.energy
-    assert i1.drift <= 1e-5 and drift <= 2e-5
+    # the device drift check after every update keeps the block below the 1e-6 target
+    assert i1.drift <= 1e-6 and i2.drift <= 1e-6 and drift <= 1e-6
     assert np.isfinite(res)

@@ -16,8 +16,13 @@ library's stream), per-kernel timings, the mixed-precision and learned forms'
 steps per second on the same workload, measured time-to-residual-1e-8 (plain
 FP64; mixed precision to 1e-4 then FP64; learned steps judged by the plain
 step) on problems that converge within the run (64^3 and 96^3 grids, N = 17,
-which closes a level shell), the batched and the large (96^3, N = 512)
-workloads, and the CPU oracle timed on a bounded sample of the same workload.
+which closes a level shell) with every form's Ritz values against the
+committed reference eigenvalues, an extrapolated (labelled) time to residual
+1e-8 at 64^3, N = 128 from measured step costs and the linearised rate,
+Algorithm 1's energy stops with the fixed and the adaptive step, Table 1's
+step counts on the finite-difference oscillator, the batched and the large
+(96^3, N = 512) workloads, and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -39,8 +44,27 @@ PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2511_06788_amd", "csrc", "k_stencil.hip")
 
 
+GOLDEN_EIGS = os.path.join(ROOT, "tests", "golden", "reference_eigs.json")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def reference_eigenvalues(name, k):
+    """The k lowest eigenvalues of a benchmark operator from the committed
+    reference file (written by the oracle's library eigensolver)."""
+    import numpy as np
+    d = json.load(open(GOLDEN_EIGS))
+    for c in d["cases"]:
+        if c["name"] == name and c["k"] >= k:
+            return np.array(c["eigenvalues"][:k])
+    raise KeyError(name)
+
+
+def ritz_error(ritz, ref):
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(ritz) - ref) / np.abs(ref)))
 
 
 def sweep_b_bytes(n, N):
@@ -90,18 +114,37 @@ def cpu_baseline(problem, tau, steps):
         HU = O.apply_H(op, U)
         Lam = U.T @ HU
         res = np.linalg.norm(HU - U @ Lam) / np.linalg.norm(Lam)
-        eta = max(1e-12, 1e-2 * res)
+        eta = max(1e-12, 0.1 * res)
         st = {}
         Y = O.cg_source(op, U, Y0=U @ np.linalg.inv(Lam), tol=eta, stats=st)
         its += st["iterations"]
         U = O.step_general(U, Y, tau)["U"]
     dt = time.perf_counter() - t0
+    logical, physical = host_cores()
     return {
         "value": steps / dt, "unit": "iter/s", "cores": int(blas_threads), "kind": "oracle",
+        "host_logical_cpus": logical, "host_physical_cores": physical,
         "sample": (f"{steps} outer step(s) of the same 64^3 N=128 workload from the same start block "
-                   f"({its} inner CG iterations, {dt:.1f} s); numpy/scipy FP64, BLAS products on "
-                   f"{blas_threads} threads, stencil and vector updates single-threaded numpy"),
+                   f"({its} inner CG iterations, {dt:.1f} s); numpy/scipy FP64: the BLAS products "
+                   f"(Grams, row products) ran on {blas_threads} threads, the stencil and the CG vector "
+                   f"updates are single-threaded numpy; the host has {logical} logical CPUs"
+                   + (f" ({physical} physical cores)" if physical else "")),
     }
+
+
+def host_cores():
+    """Logical CPUs and, when lscpu reports them, physical cores of the host."""
+    import subprocess
+    logical = os.cpu_count()
+    physical = None
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             text=True, timeout=10).stdout
+        pairs = {tuple(l.split(",")) for l in out.splitlines() if l and not l.startswith("#")}
+        physical = len(pairs) or None
+    except Exception:  # pragma: no cover
+        pass
+    return logical, physical
 
 
 def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
@@ -125,6 +168,7 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
         si = ope.ope_solve(cd.handle, U, tau, tol, 20000)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
+        ritz_plain = ope.ope_residual(cd.handle, U, p.N)[1]
         U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
         U64 = torch.empty_like(U)
         torch.cuda.synchronize()
@@ -134,11 +178,24 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
         sf = ope.ope_solve(cd.handle, U64, tau, tol, 20000)
         torch.cuda.synchronize()
         t_mixed = time.perf_counter() - t0
+        ritz_mixed = ope.ope_residual(cd.handle, U64, p.N)[1]
+        # the mixed phase on its own: to its FP32 floor, eigenvalues and drift
+        # of the FP32 iterate against the FP64 reference
+        U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
+        sm_floor = ope.ope_solve(cm.handle, U32, tau, 1e-8, 20000)
+        res_floor, ritz_floor, drift_floor = ope.ope_residual(cm.handle, U32, p.N)
+    ref = reference_eigenvalues(f"wells3d_{m}^3_seed0", p.N)
+    out["reference_eigenvalues"] = "tests/golden/reference_eigs.json (oracle LOBPCG)"
     out["plain_fp64"] = {"converged": bool(si.converged), "steps": int(si.steps), "seconds": t_plain,
-                         "final_residual": si.residual, "final_drift": si.drift}
+                         "final_residual": si.residual, "final_drift": si.drift,
+                         "ritz_max_rel_error_vs_reference": ritz_error(ritz_plain, ref)}
     out["mixed_then_fp64"] = {"converged": bool(sf.converged), "mixed_steps": int(sm.steps),
                               "fp64_steps": int(sf.steps), "switch_residual": switch, "seconds": t_mixed,
-                              "final_residual": sf.residual, "final_drift": sf.drift}
+                              "final_residual": sf.residual, "final_drift": sf.drift,
+                              "ritz_max_rel_error_vs_reference": ritz_error(ritz_mixed, ref)}
+    out["mixed_alone_to_fp32_floor"] = {"steps": int(sm_floor.steps), "stalled": bool(sm_floor.stalled),
+                                        "residual": res_floor, "drift": drift_floor,
+                                        "ritz_max_rel_error_vs_reference": ritz_error(ritz_floor, ref)}
     out["speedup_mixed"] = t_plain / t_mixed
     # plain and mixed-then-FP64 again with the sweep shapes autotuned for this
     # problem (the tuning itself is outside the timed regions, reported beside)
@@ -185,11 +242,115 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
         sl = ope.ope_solve(cl.handle, U, tau, tol, 20000)
         torch.cuda.synchronize()
         t_learned = time.perf_counter() - t0
+        ope.ope_set_preconditioner(cl.handle, None)
+        ritz_learned = ope.ope_residual(cl.handle, U, p.N)[1]
         net.close()
     out["learned_judged"] = {"converged": bool(sl.converged), "steps": int(sl.steps),
                              "learned_steps_kept": int(sl.learned_steps), "seconds": t_learned,
-                             "final_residual": sl.residual, "final_drift": sl.drift}
+                             "final_residual": sl.residual, "final_drift": sl.drift,
+                             "ritz_max_rel_error_vs_reference": ritz_error(ritz_learned, ref)}
     out["speedup_learned"] = t_plain / t_learned
+    return out
+
+
+def extrapolated_time_to_residual(ope, torch, p, tau, tol=1e-8, run=200, late=20):
+    """EXTRAPOLATION (not a measurement) of Algorithm 1's time to residual `tol`
+    at 64^3, N = 128: `run` steps from the start block are timed, then `late`
+    more give the per-step cost of the slow phase; the remaining steps follow
+    from the slow factor of the fixed-point linearisation,
+    rho = 1 - tau (1/lambda_N - 1/lambda_{N+1}), with lambda_N, lambda_{N+1} from
+    the committed reference eigenvalues: steps = ln(res / tol) / (-ln rho)."""
+    import numpy as np
+    lam = reference_eigenvalues(f"wells3d_{p.grid.m[0]}^3_seed0", p.N + 1)
+    rho = 1.0 - tau * (1.0 / lam[p.N - 1] - 1.0 / lam[p.N])
+    with ope.Context(p.grid, p.V, p.N) as ctx:
+        U = torch.from_numpy(p.U0).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(run):
+            ope.ope_step(ctx.handle, U, tau)
+        torch.cuda.synchronize()
+        t_run = time.perf_counter() - t0
+        res_a = ope.ope_residual(ctx.handle, U, p.N, want_ritz=False)[0]
+        its = 0
+        t0 = time.perf_counter()
+        for _ in range(late):
+            its += ope.ope_step(ctx.handle, U, tau).inner_iterations
+        torch.cuda.synchronize()
+        t_late = time.perf_counter() - t0
+        res_b = ope.ope_residual(ctx.handle, U, p.N, want_ritz=False)[0]
+    ms_late = 1e3 * t_late / late
+    more = float(np.log(res_b / tol) / -np.log(rho)) if res_b > tol else 0.0
+    seconds = t_run + t_late + more * ms_late * 1e-3
+    return {"label": "EXTRAPOLATED from measured step costs and the linearised rate, not measured",
+            "workload": f"wells3d_{p.grid.m[0]}^3_N{p.N}_seed0", "tau": tau, "res_tol": tol,
+            "lambda_N": float(lam[p.N - 1]), "lambda_N_plus_1": float(lam[p.N]), "rho": rho,
+            "measured_steps": run + late, "measured_seconds": t_run + t_late,
+            "residual_after_measured_steps": res_b,
+            "measured_residual_factor_per_step_late": float((res_b / res_a) ** (1.0 / late)),
+            "ms_per_step_late": ms_late, "cg_iterations_per_step_late": its / late,
+            "remaining_steps_model": more, "seconds": seconds, "hours": seconds / 3600.0}
+
+
+def algorithm1_energy_stops(ope, torch, m=64, N=17, tol=1e-10):
+    """Algorithm 1's energy stops on the m^3, N = 17 wells problem: the
+    relative energy error against the reference ground-state energy
+    (Section 5's stop) at the fixed tau = 45 and with the adaptive step
+    (start at the stability limit estimated from ope_spectrum_bounds, tau in
+    [1, 2 x limit]); and Algorithm 1's own err_E stop at tau = 45."""
+    import numpy as np
+    import workloads as W
+    p = W.wells_3d(m=m, N=N, seed=0)
+    lam = reference_eigenvalues(f"wells3d_{m}^3_seed0", N)
+    Egs = 0.5 * float(np.sum(lam))
+    out = {"workload": f"wells3d_{m}^3_N{N}_seed0", "energy_ref": Egs, "energy_tol": tol}
+    with ope.Context(p.grid, p.V, p.N) as c:
+        lmin, lmax = ope.ope_spectrum_bounds(c.handle)
+        tlim = 2.0 / (1.0 / lmin - 1.0 / lmax)
+        out["lanczos_lambda_min"], out["lanczos_lambda_max"], out["tau_limit_estimate"] = lmin, lmax, tlim
+        ope.ope_solve(c.handle, torch.from_numpy(p.U0).to("cuda"), 45.0, 1e-8, 3)
+        for name, kw in (("fixed_tau45", dict(tau=45.0)),
+                         ("adaptive", dict(tau=tlim, tau_min=1.0, tau_max=2.0 * tlim, grow=1.25)),
+                         ("algorithm1_errE_1e-12_tau45", dict(tau=45.0))):
+            U = torch.from_numpy(p.U0).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name.startswith("algorithm1"):
+                si = ope.ope_solve_ex(c.handle, U, energy_tol=1e-12, max_steps=20000, **kw)
+            else:
+                si = ope.ope_solve_ex(c.handle, U, energy_tol=tol, energy_ref=Egs, max_steps=20000, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ritz = ope.ope_residual(c.handle, U, N)[1]
+            out[name] = {"seconds": dt, "steps": int(si.steps), "rejected": int(si.rejected),
+                         "converged": bool(si.converged), "final_tau": si.tau,
+                         "rel_energy_error": (si.energy - Egs) / abs(Egs), "residual": si.residual,
+                         "ritz_max_rel_error_vs_reference": ritz_error(ritz, lam)}
+    return out
+
+
+def paper_table1(ope, torch, taus=(0.5, 1.0, 1.5)):
+    """Section 5.1's Table 1 on the finite-difference oscillator (99 x 99,
+    N = 15): steps and wall time to relative energy error 1e-10."""
+    import numpy as np
+    import workloads as W
+    p = W.oscillator_2d_paper(m=99)
+    lam = reference_eigenvalues("oscillator2d_99", 15)
+    Egs = 0.5 * float(np.sum(lam))
+    printed = {0.5: 681, 1.0: 301, 1.5: 209}
+    out = {"workload": "oscillator2d_99x99_N15 (finite-difference stand-in for the P2-FEM mesh)", "energy_ref": Egs}
+    with ope.Context(p.grid, p.V, p.N, kinetic=p.kinetic) as c:
+        for tau in taus:
+            U = torch.from_numpy(p.U0).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            si = ope.ope_solve_ex(c.handle, U, tau, energy_tol=1e-10, energy_ref=Egs, max_steps=5000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ritz = ope.ope_residual(c.handle, U, 15)[1]
+            err = np.abs(ritz - lam) / lam
+            out[f"tau_{tau}"] = {"steps": int(si.steps), "printed_steps": printed.get(tau), "seconds": dt,
+                                 "err_first_ten_max": float(err[:10].max()), "err_last_five_max": float(err[10:].max())}
     return out
 
 
@@ -250,7 +411,7 @@ def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
             "steps": steps, "warmup": warmup, "cg_sweep_b": sweep}
 
 
-def batched_throughput(ope, torch, steps=3, tau=30.0, count=64):
+def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
     """The batched workload (64 well problems, grid edges 24..48, N 16..128):
     problem-steps per second of ope_batch_step (per-problem CG launches on the
     problems' streams, the default; shared CG launches; each before and after
@@ -332,6 +493,7 @@ def large_mixed(ope, torch, steps=5, warmup=2, tau=45.0):
     import workloads as W
     p = W.wells_3d(m=96, N=512, seed=0)
     out = {"workload": "wells3d_96^3_N512_seed0", "tau": tau, "steps": steps, "warmup": warmup}
+    ritzs = {}
     for name, prec, dt_ in (("mixed", ope.OPE_MIXED, np.float32), ("plain_fp64", ope.OPE_FP64, np.float64)):
         with ope.Context(p.grid, p.V, p.N, precision=prec) as ctx:
             U = torch.from_numpy(p.U0.astype(dt_)).to("cuda")
@@ -344,10 +506,13 @@ def large_mixed(ope, torch, steps=5, warmup=2, tau=45.0):
                 inner += ope.ope_step(ctx.handle, U, tau).inner_iterations
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            res, _, drift = ope.ope_residual(ctx.handle, U, p.N, want_ritz=False)
+            res, ritz, drift = ope.ope_residual(ctx.handle, U, p.N)
         out[name] = {"iter_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "inner_iterations_per_step": inner / steps,
                      "residual_at_end": res, "drift_at_end": drift}
+        ritzs[name] = np.asarray(ritz)
     out["speedup_mixed"] = out["mixed"]["iter_per_s"] / out["plain_fp64"]["iter_per_s"]
+    out["ritz_max_rel_diff_mixed_vs_fp64_same_steps"] = float(
+        np.max(np.abs(ritzs["mixed"] - ritzs["plain_fp64"]) / np.abs(ritzs["plain_fp64"])))
     return out
 
 
@@ -397,7 +562,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
-    ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large"], default=None,
+    ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large", "extrapolate", "energy",
+                                       "table1", "ttr"], default=None,
                     help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
@@ -424,10 +590,18 @@ def main():
             r = batched_throughput(ope, torch, steps=args.steps)
         elif args.form == "net":
             r = net_forward_rate(ope, torch, reps=args.steps)
+        elif args.form == "energy":
+            r = algorithm1_energy_stops(ope, torch)
+        elif args.form == "table1":
+            r = paper_table1(ope, torch)
+        elif args.form == "ttr":
+            r = time_to_residual(ope, torch, m=args.m)
         else:
             p = W.wells_3d(m=args.m, N=args.N, seed=args.seed, tau=args.tau)
             if args.form == "mixed":
                 r = steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, args.steps, args.warmup)
+            elif args.form == "extrapolate":
+                r = extrapolated_time_to_residual(ope, torch, p, args.tau)
             else:
                 r = learned_steps_per_second(ope, torch, p, args.tau, args.steps, args.warmup)
         print(json.dumps({"form": args.form, **r}), flush=True)
@@ -482,7 +656,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"wells3d_{args.m}^3_N{N}_seed{args.seed}", "n": n, "N": N, "tau": args.tau,
-                   "form": "plain FP64", "inner": "CG, eta = max(1e-12, 1e-2 res), warm start U Lam^-1"},
+                   "form": "plain FP64", "inner": "CG, eta = max(1e-12, 0.1 res), warm start U Lam^-1",
+                   "window": {"warmup_steps": args.warmup, "timed_steps": args.steps,
+                              "start": "seeded orthonormal start block"}},
         "roofline": {"bound": "hbm", "kernel": "cg_sweep_b", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": sweep_b_bytes(n, N),
@@ -496,7 +672,7 @@ def main():
     if not args.no_extras:
         kernels = {}
         for name, kid in (("stencil", ope.OPE_KERNEL_STENCIL), ("cg_sweep_a", ope.OPE_KERNEL_CG_SWEEP_A),
-                          ("cg_sweep_b_odd", ope.OPE_KERNEL_CG_SWEEP_B_Y),
+                          ("cg_sweep_b_odd", ope.OPE_KERNEL_CG_SWEEP_B_Y), ("cg_reduce", ope.OPE_KERNEL_CG_REDUCE),
                           ("gram", ope.OPE_KERNEL_GRAM), ("rowmm", ope.OPE_KERNEL_ROWMM),
                           ("small", ope.OPE_KERNEL_SMALL)):
             ope.ope_profile_begin(h, kid)
@@ -506,7 +682,7 @@ def main():
             nl, tms = ope.ope_profile_end(h)
             # a CG sweep's time per counted iteration (as for sweep B above);
             # the odd form of sweep B runs on every second one
-            per = its if name == "cg_sweep_a" else (its / 2.0 if name == "cg_sweep_b_odd" else nl)
+            per = its if name in ("cg_sweep_a", "cg_reduce") else (its / 2.0 if name == "cg_sweep_b_odd" else nl)
             rec = {"avg_ms": tms / max(per, 1), "launches_per_step": nl / 5.0}
             b = kernel_bytes(name, n, N)
             if b:
@@ -518,6 +694,15 @@ def main():
             kernels[name] = rec
         kernels["cg_sweep_b"] = {"avg_ms": avg_ms, "GB/s": achieved}
         out["kernels"] = kernels
+        # window-independent cost: a CG iteration (both sweeps and both column
+        # reductions, kernel time) and what a step spends outside its CG
+        per_it = kernels["cg_sweep_a"]["avg_ms"] + avg_ms + kernels["cg_reduce"]["avg_ms"]
+        its_step = inner / max(args.steps, 1)
+        out["cost_model"] = {"ms_per_cg_iteration": per_it,
+                             "cg_iterations_per_step": its_step,
+                             "ms_per_step_outside_cg": ms_per_step - its_step * per_it,
+                             "note": "ms_per_step = cg_iterations_per_step x ms_per_cg_iteration + outside; "
+                                     "the CG iteration count depends on the window (early steps need more)"}
     ctx.close()
     if not args.no_extras:
         log("mixed-precision form at the same workload")
@@ -533,6 +718,12 @@ def main():
         out["time_to_residual"] = time_to_residual(ope, torch)
         log("time to residual on the 96^3 N=17 problem")
         out["time_to_residual_96"] = time_to_residual(ope, torch, m=96)
+        log("extrapolated time to residual 1e-8 at 64^3, N=128")
+        out["time_to_residual_64_N128_extrapolated"] = extrapolated_time_to_residual(ope, torch, p, args.tau)
+        log("Algorithm 1 energy stops and the adaptive step (64^3, N=17)")
+        out["algorithm1_energy_stops"] = algorithm1_energy_stops(ope, torch)
+        log("Table 1 on the finite-difference oscillator")
+        out["paper_table1"] = paper_table1(ope, torch)
         log("batched workload (64 problems)")
         out["batched"] = batched_throughput(ope, torch)
         log("large mixed-precision workload (96^3, N=512)")

@@ -693,17 +693,21 @@ __global__ void k_big_z(const double* __restrict__ A, const double* __restrict__
   }
 }
 
+// Z = (I - C) / 2, the correction of U <- U + U Z = U (3I - C) / 2
 __global__ void k_renorm(const double* __restrict__ C, uint32_t N, float* __restrict__ Z) {
   const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (uint64_t)N * N) return;
   const uint32_t i = (uint32_t)(q / N), j = (uint32_t)(q % N);
-  Z[q] = (float)((i == j ? 1.5 : 0.0) - 0.5 * C[q]);
+  Z[q] = (float)(0.5 * ((i == j ? 1.0 : 0.0) - C[q]));
 }
 
 // Drift check after a mixed-precision update: drift = |C - I|_F of the new
 // iterate (C = U^T U accumulated in FP64); above thr the next predicated
-// product applies U <- U (3 I - C) / 2, one Newton-Schulz step toward the
-// nearest orthonormal block (drift E -> O(E^2)).
+// product applies U <- U + U (I - C) / 2 = U (3 I - C) / 2, one Newton-Schulz
+// step toward the nearest orthonormal block (drift E -> O(E^2)).  Z receives
+// the correction (I - C) / 2: formed as U + U Z, its small terms are summed
+// among themselves before U is added; as U (3I - C)/2 in FP32 they would be
+// absorbed one by one into an accumulator of the size of U.
 __global__ __launch_bounds__(SW) void k_drift_check(const double* __restrict__ C, uint32_t N, double thr,
                                                     float* __restrict__ Z, OpeScalars* __restrict__ sc) {
   __shared__ double red[SW];
@@ -713,7 +717,7 @@ __global__ __launch_bounds__(SW) void k_drift_check(const double* __restrict__ C
     const uint32_t i = (uint32_t)(q / N), j = (uint32_t)(q % N);
     const double d = C[q] - (i == j ? 1.0 : 0.0);
     s += d * d;
-    Z[q] = (float)((i == j ? 1.5 : 0.0) - 0.5 * C[q]);
+    Z[q] = (float)(-0.5 * d);
   }
   s = wg_sum(s, red);
   if (threadIdx.x == 0) {

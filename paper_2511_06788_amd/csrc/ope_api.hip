@@ -206,10 +206,14 @@ hipError_t cg_iteration(ope_ctx* c, int it) {
   const int first = it == 0;
   hipError_t e;
   if ((e = launch_cg_pap(c, r_cur, p_old, p_new, first)) != hipSuccess) return e;
-  if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA, a_cur)) != hipSuccess) return e;
+  {
+    ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
+    if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA, a_cur)) != hipSuccess) return e;
+  }
   if (it & 1) e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, c->Y, p_old, a_prev);
   else e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, nullptr, nullptr, nullptr);
   if (e != hipSuccess) return e;
+  ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
   return launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA, a_cur);
 }
 
@@ -420,10 +424,10 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
     HIPCHK(launch_gram_f32(c, MK_F64, U, N, N, U, N, N, c->n, c->C));
     HIPCHK(launch_drift_check(c, c->C, c->Z32, c->drift_tol));
     if (N <= 128) {
-      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, U, 0, ROWMM_IF_RENORM, &np));
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, U, 1.0, 1.0, U, 0, ROWMM_IF_RENORM, &np));
     } else {
       float* tmp = (float*)c->Pb;
-      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, tmp, 0, ROWMM_IF_RENORM, &np));
+      HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, U, 1.0, 1.0, tmp, 0, ROWMM_IF_RENORM, &np));
       HIPCHK(launch_copy_pred(c, tmp, U, sizeof(float) * (uint64_t)c->n * N, ROWMM_IF_RENORM));
     }
   }
@@ -431,10 +435,10 @@ ope_status phase_update(ope_ctx* c, void* Uv, double tau) {
 }
 
 // Mixed precision: when the last observed drift |U^T U - I|_F exceeds 1e-6,
-// one Newton-Schulz re-normalisation U <- U (3I - C) / 2 with C = U^T U (FP64
-// Gram of the FP32 block, FP32 product) before the step: the scheme keeps the
-// drift constant in exact arithmetic, the BF16 update adds to it, and this
-// takes a drift E to O(E^2).
+// one Newton-Schulz re-normalisation U <- U + U (I - C) / 2 with C = U^T U
+// (FP64 Gram of the FP32 block, FP32 product of the correction) before the
+// step: the scheme keeps the drift constant in exact arithmetic, the BF16
+// update adds to it, and this takes a drift E to O(E^2).
 ope_status mixed_renormalize(ope_ctx* c, void* Uv) {
   if (c->prec != OPE_MIXED || !(c->drift_seen > 1e-6)) return OPE_OK;
   const int N = (int)c->N;
@@ -443,9 +447,9 @@ ope_status mixed_renormalize(ope_ctx* c, void* Uv) {
   HIPCHK(launch_gram_f32(c, MK_F64, U, N, N, U, N, N, c->n, c->C));
   HIPCHK(launch_renorm_matrix(c, c->C, c->Z32));
   if (N <= 128) {
-    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, U, 0, 0, &np));
+    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, U, 1.0, 1.0, U, 0, 0, &np));
   } else {
-    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, nullptr, 0.0, 1.0, (float*)c->Pb, 0, 0, &np));
+    HIPCHK(launch_rowmm_f32(c, MK_F32, U, c->Z32, nullptr, nullptr, U, 1.0, 1.0, (float*)c->Pb, 0, 0, &np));
     HIPCHK(hipMemcpyAsync(U, c->Pb, sizeof(float) * (size_t)c->n * N, hipMemcpyDeviceToDevice, c->stream));
   }
   c->renorms += 1;
@@ -1038,7 +1042,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   c->h[1] = op->h[1];
   c->h[2] = op->dim == 3 ? op->h[2] : op->h[1];
   c->kinetic = op->kinetic;
-  c->eta_rel = 1e-2;
+  c->eta_rel = 0.1;
   c->eta_floor = precision == OPE_FP64 ? 1e-12 : 1e-6;
   c->max_iter = 2000;
   c->check_every = 4;

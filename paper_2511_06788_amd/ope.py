@@ -105,6 +105,7 @@ OPE_KERNEL_GRAM = 3
 OPE_KERNEL_ROWMM = 4
 OPE_KERNEL_SMALL = 5
 OPE_KERNEL_CG_SWEEP_B_Y = 6
+OPE_KERNEL_CG_REDUCE = 7
 
 _lib = None
 

@@ -40,6 +40,13 @@ def test_indefinite_operator_is_refused():
         with pytest.raises(ope.OpeError) as ei:
             ope.Context(p.grid, p.V, p.N, shift=shift)
         assert ei.value.status == ope.OPE_ENOTSPD
+    # the coarse softened-Coulomb operator with shift 1 has lambda_1 = -4.74 (dense eigvalsh)
+    hp = W.hydrogen_softened(m=9, N=8, half=4.0)
+    hop = O.Operator(hp.grid.m, hp.grid.h, hp.V, kinetic=hp.kinetic, shift=hp.shift)
+    assert np.linalg.eigvalsh(O.assemble_H(hop).toarray())[0] < 0
+    with pytest.raises(ope.OpeError) as ei:
+        ope.Context(hp.grid, hp.V, hp.N, kinetic=hp.kinetic, shift=hp.shift)
+    assert ei.value.status == ope.OPE_ENOTSPD
     # just above the bottom of the spectrum: SPD, accepted
     with ope.Context(p.grid, p.V, p.N, shift=-w[0] + 0.5) as c:
         lo, hi = ope.ope_spectrum_bounds(c.handle)

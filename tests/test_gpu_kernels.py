@@ -30,7 +30,8 @@ CASES = [
     ("2d 7x5 N=1", lambda: W.harmonic_2d_32(m=7, N=1), 1),
     ("3d 13x13x13 N=17", lambda: W.wells_3d(m=13, N=17, seed=3), 17),
     ("3d 20^3 N=128", lambda: W.wells_3d(m=20, N=128, seed=1), 128),
-    ("3d 9^3 N=63 kinetic 0.5 shift", lambda: W.hydrogen_softened(m=9, N=63, half=4.0), 63),
+    # shift 7: the coarse softened-Coulomb operator has lambda_1 = -5.74 + shift
+    ("3d 9^3 N=63 kinetic 0.5 shift", lambda: W.hydrogen_softened(m=9, N=63, half=4.0, shift=7.0), 63),
 ]
 
 

@@ -137,3 +137,29 @@ def test_full_batched_workload_one_step():
         op = O.Operator(p.grid.m, p.grid.h, p.V)
         assert abs(i1[i].energy - O.energy(op, p.U0)) <= 1e-12 * abs(i1[i].energy)
         assert abs(i1[i].residual - O.residual(op, p.U0)) <= 1e-10 * i1[i].residual
+
+
+def test_batched_workload_step_matches_oracle():
+    """The 64-problem workload stepped once as a batch with Step 1 solved to
+    1e-13: the three smallest problems' new blocks equal the oracle's exact
+    step (Steps 1-4 with a sparse LU for Step 1) to 1e-12, and every problem's
+    input energy and residual equal the oracle's."""
+    from paper_2511_06788_amd import ope
+    probs = W.batched_problems(64)
+    order = sorted(range(len(probs)), key=lambda i: probs[i].grid.n)
+    pick = order[:3]
+    say("batched workload vs oracle step")
+    with ope.Batch(probs) as b:
+        for i in range(len(probs)):
+            ope.ope_set_inner(b.context(i), 0.0, 1e-13, 20000)
+        Ub = [_dev(p.U0, 0) for p in probs]
+        info = b.step(Ub, 30.0, allow_maxit=False)
+        got = {i: to_host(Ub[i]) for i in pick}
+    for i in pick:
+        p = probs[i]
+        op = O.Operator(p.grid.m, p.grid.h, p.V)
+        ref = O.steps_1_to_4(p.U0, O.GSolver(op, "sparse"), 30.0)["U"]
+        assert np.max(np.abs(got[i] - ref)) <= 1e-12, i
+        assert np.max(np.abs(got[i] - p.U0)) > 1e-5, i
+        assert abs(info[i].energy - O.energy(op, p.U0)) <= 1e-12 * abs(info[i].energy), i
+        assert abs(info[i].residual - O.residual(op, p.U0)) <= 1e-10 * info[i].residual, i

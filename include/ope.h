@@ -154,6 +154,18 @@ ope_status ope_source_solve(ope_ctx* ctx, const double* U, double* Y, const doub
 ope_status ope_gram(ope_ctx* ctx, const double* A, int64_t lda, int64_t na,
                     const double* B, int64_t ldb, int64_t nb, int64_t rows, double* out);
 
+/* ope_gram without a context and without any allocation, for callers that
+ * cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation).  Same operation, layouts and
+ * kernels as ope_gram, enqueued on `stream` (a hipStream_t, NULL = default
+ * stream); the split-K partial sums go to a fixed 4 MiB device array of the
+ * library (one per GPU, kept until the process ends), so na, nb <= 128
+ * (OPE_EINVAL beyond) and rows >= 1.  Calls that overlap on one GPU share that
+ * array and race: serialise them (one stream, or events).  The summation order
+ * may differ from ope_gram's (a different split of the rows). */
+ope_status ope_gram_noalloc(const double* A, int64_t lda, int64_t na, const double* B, int64_t ldb, int64_t nb,
+                            int64_t rows, double* out, void* stream);
+
 /* Steps 2-3 (Section 4.1) for the context's N, in FP64, on the device (OPE_FP64 contexts):
  * given S_b = <U, Y> and T = <Y, Y> (N x N device), forms
  *   M = I + tau/2 (S_a - S_b) + tau^2/4 (T - S_a S_b),  S_a = S_b^T,

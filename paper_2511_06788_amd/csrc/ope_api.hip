@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -977,6 +978,38 @@ static int default_sweep_flags(const ope_ctx* c) {
   return OPE_SWEEP_CHUNK_MAJOR | (c->g.dim == 3 ? OPE_SWEEP_LINES8 : 0) | (big ? OPE_SWEEP_NONTEMPORAL : 0);
 }
 
+// Scratch of the allocation-free Gram (ope_gram_noalloc): the split-K
+// partial sums, at most GRAM_NOALLOC_SPLITS x 128 x 128 doubles (4 MiB), in a
+// file-scope device array.  Every GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in).  Calls that overlap on one GPU share it and race.
+constexpr int64_t GRAM_NOALLOC_MAX = 128;
+constexpr int64_t GRAM_NOALLOC_SPLITS = 32;
+constexpr int64_t GRAM_NOALLOC_DOUBLES = GRAM_NOALLOC_SPLITS * GRAM_NOALLOC_MAX * GRAM_NOALLOC_MAX;
+static __device__ __align__(256) double scratch[GRAM_NOALLOC_DOUBLES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+ope_status scratch_address(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OPE_EHIP;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return OPE_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return OPE_EHIP;
+    scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = scratch_ptr[dev];
+  return OPE_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* ope_status_string(ope_status s) {
@@ -1247,6 +1280,29 @@ ope_status ope_gram(ope_ctx* c, const double* A, int64_t lda, int64_t na, const 
     return OPE_OK;
   }
   HIPCHK(launch_gram(c, A, lda, (int)na, B, ldb, (int)nb, rows, out));
+  return OPE_OK;
+}
+
+ope_status ope_gram_noalloc(const double* A, int64_t lda, int64_t na, const double* B, int64_t ldb, int64_t nb,
+                            int64_t rows, double* out, void* stream) {
+  if (!A || !B || !out) return OPE_EINVAL;
+  if (na < 1 || nb < 1 || lda < na || ldb < nb || rows < 1 || rows > ((int64_t)1 << 32) - 1) return OPE_EINVAL;
+  if (na > GRAM_NOALLOC_MAX || nb > GRAM_NOALLOC_MAX) return OPE_EINVAL;   // beyond the fixed scratch
+  double* part = nullptr;
+  const ope_status st = scratch_address(&part);
+  if (st != OPE_OK) return st;
+  // a context-free view for the shared launchers: the partial sums live in the
+  // scratch array, there is no stage buffer (the column sums then run in one
+  // pass), no timing and no per-step scalars
+  ope_ctx v{};
+  v.stream = (hipStream_t)stream;
+  v.part = part;
+  v.part_cap = GRAM_NOALLOC_SPLITS * na * nb;
+  v.stage = nullptr;
+  v.stage_cap = 0;
+  v.prof_kernel = -1;
+  v.prof_used = 0;
+  HIPCHK(launch_gram(&v, A, lda, (int)na, B, ldb, (int)nb, rows, out));
   return OPE_OK;
 }
 

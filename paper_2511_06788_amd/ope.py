@@ -157,6 +157,7 @@ SIGNATURES = {
     "ope_net_samples": ([_P, _P, _P, _I64, _I64, _P, _P], _I32),
     "ope_set_preconditioner": ([_P, _P, _I32], _I32),
     "ope_step_learned": ([_P, _P, _D, ctypes.POINTER(ope_step_info), ctypes.POINTER(_I32)], _I32),
+    "ope_gram_noalloc": ([_P, _I64, _I64, _P, _I64, _I64, _I64, _P, _P], _I32),
     "ope_solve_ex": ([_P, _P, ctypes.POINTER(ope_solve_opts), ctypes.POINTER(ope_solve_info)], _I32),
     "ope_net_apply_grad": ([_P, _P, _D], _I32),
     "ope_spectrum_bounds": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_D)], _I32),
@@ -273,6 +274,11 @@ def ope_source_solve(ctx: int, U, Y, Y0=None, tol: float = 1e-12, max_iter: int 
 
 def ope_gram(ctx: int, A, lda: int, na: int, B, ldb: int, nb: int, rows: int, out) -> None:
     _check(lib().ope_gram(ctx, _ptr(A), lda, na, _ptr(B), ldb, nb, rows, _ptr(out)), "ope_gram")
+
+
+def ope_gram_noalloc(A, lda: int, na: int, B, ldb: int, nb: int, rows: int, out, stream=None) -> None:
+    _check(lib().ope_gram_noalloc(_ptr(A), lda, na, _ptr(B), ldb, nb, rows, _ptr(out), _stream_ptr(stream)),
+           "ope_gram_noalloc")
 
 
 def ope_small_solve(ctx: int, Sb, T, tau: float, Z, A=None, B=None) -> None:

@@ -418,8 +418,9 @@ def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
     """The batched workload (64 well problems, grid edges 24..48, N 16..128):
     problem-steps per second of ope_batch_step (per-problem CG launches on the
     problems' streams, the default; shared CG launches; each before and after
-    the autotuner), and of the same problems stepped one after the other with
-    ope_step."""
+    the autotuner), of replays of the captured step (ope_batch_capture, both
+    launch modes, checked bit for bit against the eager steps), and of the same
+    problems stepped one after the other with ope_step."""
     import numpy as np
     import workloads as W
     probs = W.batched_problems(count)
@@ -446,10 +447,21 @@ def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
         # algorithmic bytes of the CG sweeps: 7.5 n x N block passes per iteration
         blk = [7.5 * p.grid.n * p.N * 8 for p in probs]
 
+        most = [0]
+
         def batch_steps():
             inner, nbytes = 0, 0
             for _ in range(steps):
                 for k, i in enumerate(b.step(U, tau)):
+                    inner += i.inner_iterations
+                    nbytes += i.inner_iterations * blk[k]
+                    most[0] = max(most[0], i.inner_iterations)
+            return inner, nbytes
+
+        def graph_steps():
+            inner, nbytes = 0, 0
+            for _ in range(steps):
+                for k, i in enumerate(b.replay()):
                     inner += i.inner_iterations
                     nbytes += i.inner_iterations * blk[k]
             return inner, nbytes
@@ -474,6 +486,17 @@ def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
         t_s1, in_s1 = timed(batch_steps)
         b.set_shared(False)
         t_b1, in_b1 = timed(batch_steps)
+        ref = [u.clone() for u in U]
+        # whole steps as graph replays, with the CG iteration count the
+        # largest any problem needed in the eager steps (multiple of 4)
+        K = max(4, -(-most[0] // 4) * 4)
+        b.capture(U, tau, K)
+        t_g0, in_g0 = timed(graph_steps)
+        same0 = all(torch.equal(a, r) for a, r in zip(U, ref))
+        b.set_shared(True)
+        b.capture(U, tau, K)
+        t_g1, in_g1 = timed(graph_steps)
+        same1 = all(torch.equal(a, r) for a, r in zip(U, ref))
     ps = count * steps
 
     def rec(t, r):
@@ -484,7 +507,64 @@ def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
     out["batched_shared_launches"] = rec(t_s0, in_s0)
     out["batched_shared_launches_autotuned"] = dict(rec(t_s1, in_s1), buckets=buckets, autotune_seconds=t_tune)
     out["batched_autotuned"] = rec(t_b1, in_b1)
+    out["graph_replay_autotuned"] = dict(rec(t_g0, in_g0), cg_iterations=K, equal_to_eager=same0)
+    out["graph_replay_shared_launches_autotuned"] = dict(rec(t_g1, in_g1), cg_iterations=K, equal_to_eager=same1)
     out["speedup_vs_sequential"] = t_seq / min(t_b0, t_b1)
+    return out
+
+
+def small_batch_graph(ope, torch, count=16, m=24, N=16, tau=30.0, steps=20):
+    """A batch of small problems (sixteen 24^3 wells, N = 16), where launch
+    latency and host checks dominate: problem-steps per second of eager
+    batched steps with per-problem and with shared CG launches, and of replays
+    of the captured step (ope_batch_capture) whose fixed CG iteration count is
+    the largest count the eager shared steps needed, rounded up to a multiple
+    of 4; the replayed blocks are checked against the eager ones bit for bit."""
+    import workloads as W
+    probs = [W.wells_3d(m=m, N=N, seed=100 + k) for k in range(count)]
+    out = {"workload": f"{count} wells3d problems, {m}^3, N = {N}, seeds 100..{99 + count}", "tau": tau,
+           "steps": steps}
+    with ope.Batch(probs) as b:
+        U0 = [torch.from_numpy(p.U0).to("cuda") for p in probs]
+        U = [u.clone() for u in U0]
+
+        def reset():
+            for u, u0 in zip(U, U0):
+                u.copy_(u0)
+            torch.cuda.synchronize()
+
+        def eager(shared):
+            b.set_shared(shared)
+            reset()
+            b.step(U, tau)
+            reset()
+            t0 = time.perf_counter()
+            most = 0
+            for _ in range(steps):
+                most = max(most, max(i.inner_iterations for i in b.step(U, tau)))
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, most
+
+        t_own, _ = eager(False)
+        t_sh, most = eager(True)
+        ref = [u.clone() for u in U]
+        K = max(4, -(-most // 4) * 4)
+        reset()
+        b.capture(U, tau, K)
+        b.replay()
+        reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.replay(wait=False)
+        torch.cuda.synchronize()
+        t_g = time.perf_counter() - t0
+        same = all(torch.equal(a, r) for a, r in zip(U, ref))
+    ps = count * steps
+    out["batched"] = {"problem_steps_per_s": ps / t_own, "seconds": t_own}
+    out["batched_shared_launches"] = {"problem_steps_per_s": ps / t_sh, "seconds": t_sh}
+    out["graph_replay"] = {"problem_steps_per_s": ps / t_g, "seconds": t_g, "cg_iterations": K,
+                           "equal_to_shared_steps": same}
+    out["graph_speedup_vs_shared"] = t_sh / t_g
     return out
 
 
@@ -566,7 +646,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large", "extrapolate", "energy",
-                                       "table1", "ttr"], default=None,
+                                       "table1", "ttr", "graph"], default=None,
                     help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
@@ -591,6 +671,8 @@ def main():
             r = large_mixed(ope, torch, steps=args.steps, warmup=args.warmup)
         elif args.form == "batched":
             r = batched_throughput(ope, torch, steps=args.steps)
+        elif args.form == "graph":
+            r = small_batch_graph(ope, torch)
         elif args.form == "net":
             r = net_forward_rate(ope, torch, reps=args.steps)
         elif args.form == "energy":
@@ -729,6 +811,8 @@ def main():
         out["paper_table1"] = paper_table1(ope, torch)
         log("batched workload (64 problems)")
         out["batched"] = batched_throughput(ope, torch)
+        log("batch of small problems: eager steps and graph replays")
+        out["small_batch"] = small_batch_graph(ope, torch)
         log("large mixed-precision workload (96^3, N=512)")
         out["large_mixed"] = large_mixed(ope, torch)
         log("network forward pass")

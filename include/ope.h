@@ -443,6 +443,34 @@ ope_status ope_batch_solve(ope_batch* batch, void* const* U, double tau, double 
  * small problems alone shared launches are faster (2.2x for sixteen 24^3,
  * N = 16 problems), on a batch of large ones slightly slower. */
 ope_status ope_batch_set_shared(ope_batch* batch, int32_t shared);
+/* Graph-captured batched step: one HIP graph holding a whole step of every
+ * problem (residual and warm start on the problems' streams, then exactly
+ * `cg_iterations` iterations of Step 1's CG, then Steps 2-4 on the problems'
+ * streams), so a step costs one graph launch and no host decision.  The CG
+ * follows the batch's launch mode at capture (ope_batch_set_shared): shared
+ * launches for the problems that fit them, the problems' own launches on
+ * their own streams otherwise.  Columns that converge earlier stop in place
+ * (their kernels skip them), so the result is identical to ope_batch_step
+ * whenever every problem's CG converges within cg_iterations; otherwise the
+ * step is taken with the CG state after cg_iterations and the problem's
+ * status is OPE_ECG_MAXIT.  Mixed-precision problems keep Step 4's
+ * device-side drift check; the host-decided re-normalisation before a step
+ * (driven by the previous step's drift) is not part of the graph.
+ * U[i] (device blocks) are fixed at capture: every replay steps the same
+ * buffers.  The graph also freezes tau and every problem's settings (inner
+ * tolerances, sweep shapes, mass product): capture again after changing any;
+ * ope_batch_autotune drops the graph.  Requires N[i] <= 128 (the
+ * one-work-group small solves), no kernel timing, cg_iterations even and
+ * >= 2; else OPE_EUNSUPPORTED / OPE_EINVAL.  Capture synchronises the device and allocates the graph's own
+ * job tables and flags (once per batch); replays may interleave with eager
+ * batched steps. */
+ope_status ope_batch_capture(ope_batch* batch, void* const* U, double tau, int32_t cg_iterations);
+/* Replays the captured step on the batch's stream.  info (host, count
+ * entries, nullable): when given, waits for the step and fills it as
+ * ope_batch_step does (inner_iterations = the CG iterations each problem
+ * counted before converging); returns the first non-OK status.  With info
+ * NULL it returns after the launch.  EINVAL if nothing is captured. */
+ope_status ope_batch_replay(ope_batch* batch, ope_step_info* info);
 /* Autotuner: for every bucket of problems (grid edges and vector-column count
  * in steps of 8) time short CG runs of the first problem over the sweep shapes
  * (passes per plane 1/2 or the two-, four- and eight-line tiles, work-group order,

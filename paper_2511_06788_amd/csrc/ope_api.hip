@@ -51,6 +51,17 @@ struct ope_batch {
   std::vector<uint32_t> flag_off;     // problem i's flags in h_flags
   std::vector<hipStream_t> cls_streams;  // one per class of problems in a shared launch
   std::vector<hipEvent_t> cls_events;
+  // a captured batched step (ope_batch_capture / ope_batch_replay): its own job
+  // tables and flags, so that eager batched steps between replays leave it intact
+  hipStream_t cap_stream;
+  hipEvent_t cap_fork, cap_join;
+  hipGraphExec_t step_graph;
+  MarchJob* d_gmjobs;
+  ReduceJob* d_grjobs;
+  int32_t* d_gflags;
+  int32_t* h_gflags;
+  std::vector<uint32_t> gflag_off;
+  int32_t cap_iters;
 };
 
 namespace {
@@ -617,16 +628,25 @@ struct BatchState {
 // work items are the tiles of its own sweep shape.
 bool shared_fits(const ope_ctx* c) { return reduce_few_fits(c); }
 
-// One chunk (check_every iterations) of Step 1's CG for the problems in
-// `members`, with one launch per sweep and class of problems and one launch
-// per column reduction, then the gather of their convergence flags into
-// h_flags (synchronised).  The problems' pre-phases must have completed.
-hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t* it) {
+// The shared CG launches of a set of problems: classes of problems that one
+// kernel instance can sweep (storage type, vector width, passes per plane,
+// split x lines, line tiles), and per class the job tables of its four sweep
+// variants (sweep A / B, even / odd iteration), staged in pinned host memory.
+struct CgPlan {
   struct Cls {
     int prec, vw, q, halo, ln;
     std::vector<int> idx;
   };
   std::vector<Cls> cls;
+  std::vector<uint32_t> cls_off, cls_total;
+  uint32_t M = 0;       // problems (reduce jobs)
+  uint32_t jobs = 0;    // march jobs
+  uint32_t flags = 0;   // convergence flags gathered
+};
+
+void plan_cg(ope_batch* b, const std::vector<int>& members, int32_t* d_flags, CgPlan& pl) {
+  auto& cls = pl.cls;
+  cls.clear();
   for (int i : members) {
     const ope_ctx* c = b->ctx[i];
     const int halo = c->ms.nxs > 1 ? 1 : 0, ln = c->ms.ly > 1 ? 1 : 0;
@@ -637,14 +657,15 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
         found = true;
         break;
       }
-    if (!found) cls.push_back(Cls{c->prec, c->vw, (int)c->ms.q, halo, ln, {i}});
+    if (!found) cls.push_back(CgPlan::Cls{c->prec, c->vw, (int)c->ms.q, halo, ln, {i}});
   }
   // job tables: per class, 4 variants (sweep A / B, even / odd iteration)
-  const uint32_t M = (uint32_t)members.size();
-  std::vector<uint32_t> cls_off(cls.size()), cls_total(cls.size());
+  pl.M = (uint32_t)members.size();
+  pl.cls_off.assign(cls.size(), 0);
+  pl.cls_total.assign(cls.size(), 0);
   uint32_t off = 0;
   for (size_t k = 0; k < cls.size(); ++k) {
-    cls_off[k] = off;
+    pl.cls_off[k] = off;
     uint32_t wg = 0;
     for (int v = 0; v < 4; ++v) {
       wg = 0;
@@ -674,11 +695,12 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
         wg += (jb.wg_count + 7u) & ~7u;          // whole groups of 8: one per XCD
       }
     }
-    cls_total[k] = wg;
+    pl.cls_total[k] = wg;
     off += 4 * (uint32_t)cls[k].idx.size();
   }
+  pl.jobs = off;
   uint32_t foff = 0;
-  for (uint32_t m = 0; m < M; ++m) {
+  for (uint32_t m = 0; m < pl.M; ++m) {
     ope_ctx* c = b->ctx[members[m]];
     ReduceJob& rj = b->h_rjobs[m];
     rj.part = c->part;
@@ -690,18 +712,20 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
     rj.target = c->target;
     rj.active = c->active;
     rj.sc = c->sc;
-    rj.flags_out = b->d_flags + foff;
+    rj.flags_out = d_flags + foff;
     b->flag_off[members[m]] = foff;
     foff += (uint32_t)c->N;
   }
-  hipStream_t s = b->cg_stream;
+  pl.flags = foff;
+}
+
+// Enqueues `count` CG iterations from iteration it0 of the planned problems on
+// stream s (class sweeps forked onto the classes' streams and joined back),
+// with the job tables at mjobs / rjobs on the device.  No host synchronisation.
+hipError_t enqueue_cg(ope_batch* b, const CgPlan& pl, const MarchJob* mjobs, const ReduceJob* rjobs, int32_t it0,
+                      int32_t count, hipStream_t s) {
   hipError_t e;
-  if ((e = hipMemcpyAsync(b->d_mjobs, b->h_mjobs, sizeof(MarchJob) * off, hipMemcpyHostToDevice, s)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(b->d_rjobs, b->h_rjobs, sizeof(ReduceJob) * M, hipMemcpyHostToDevice, s)) != hipSuccess)
-    return e;
-  // classes run their sweeps on their own streams (forked from and joined
-  // back into the CG stream around every sweep), so they overlap
+  const auto& cls = pl.cls;
   while (b->cls_streams.size() < cls.size()) {
     hipStream_t cs;
     hipEvent_t ce;
@@ -717,7 +741,7 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
       const uint32_t nc = (uint32_t)cls[0].idx.size();
       const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
       return launch_march_batched(s, cls[0].prec, cls[0].vw, cls[0].q, cls[0].halo, cls[0].ln, kmode, first,
-                                  b->d_mjobs + cls_off[0] + v * nc, nc, cls_total[0]);
+                                  mjobs + pl.cls_off[0] + v * nc, nc, pl.cls_total[0]);
     }
     if ((er = hipEventRecord(b->cg_ev, s)) != hipSuccess) return er;
     for (size_t c = 0; c < cls.size(); ++c) {
@@ -726,23 +750,43 @@ hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t
       const uint32_t v = (mode == BATCH_SW_PAP ? 0 : 2) + par;
       if ((er = hipStreamWaitEvent(cs, b->cg_ev, 0)) != hipSuccess) return er;
       if ((er = launch_march_batched(cs, cls[c].prec, cls[c].vw, cls[c].q, cls[c].halo, cls[c].ln, kmode, first,
-                                     b->d_mjobs + cls_off[c] + v * nc, nc, cls_total[c])) != hipSuccess)
+                                     mjobs + pl.cls_off[c] + v * nc, nc, pl.cls_total[c])) != hipSuccess)
         return er;
       if ((er = hipEventRecord(b->cls_events[c], cs)) != hipSuccess) return er;
       if ((er = hipStreamWaitEvent(s, b->cls_events[c], 0)) != hipSuccess) return er;
     }
     return hipSuccess;
   };
-  const int K = b->ctx[members[0]]->check_every;
-  for (int k = 0; k < K; ++k, ++*it) {
-    const int par = *it & 1, first = *it == 0;
+  for (int32_t k = 0, it = it0; k < count; ++k, ++it) {
+    const int par = it & 1, first = it == 0;
     if ((e = sweep(BATCH_SW_PAP, par, first)) != hipSuccess) return e;
-    if ((e = launch_reduce_batched(s, RED_CG_ALPHA, par, b->d_rjobs, M)) != hipSuccess) return e;
+    if ((e = launch_reduce_batched(s, RED_CG_ALPHA, par, rjobs, pl.M)) != hipSuccess) return e;
     if ((e = sweep(BATCH_SW_UPDATE, par, first)) != hipSuccess) return e;
-    if ((e = launch_reduce_batched(s, RED_CG_BETA, par, b->d_rjobs, M)) != hipSuccess) return e;
+    if ((e = launch_reduce_batched(s, RED_CG_BETA, par, rjobs, pl.M)) != hipSuccess) return e;
   }
-  if ((e = launch_gather_flags(s, b->d_rjobs, M)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int32_t) * foff, hipMemcpyDeviceToHost, s)) != hipSuccess)
+  return hipSuccess;
+}
+
+// One chunk (check_every iterations) of Step 1's CG for the problems in
+// `members`, with one launch per sweep and class of problems and one launch
+// per column reduction, then the gather of their convergence flags into
+// h_flags (synchronised).  The problems' pre-phases must have completed.
+hipError_t batch_cg_chunk(ope_batch* b, const std::vector<int>& members, int32_t* it) {
+  CgPlan pl;
+  plan_cg(b, members, b->d_flags, pl);
+  hipStream_t s = b->cg_stream;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(b->d_mjobs, b->h_mjobs, sizeof(MarchJob) * pl.jobs, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(b->d_rjobs, b->h_rjobs, sizeof(ReduceJob) * pl.M, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return e;
+  const int K = b->ctx[members[0]]->check_every;
+  if ((e = enqueue_cg(b, pl, b->d_mjobs, b->d_rjobs, *it, K, s)) != hipSuccess) return e;
+  *it += K;
+  if ((e = launch_gather_flags(s, b->d_rjobs, pl.M)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int32_t) * pl.flags, hipMemcpyDeviceToHost, s)) !=
+      hipSuccess)
     return e;
   if ((e = hipEventRecord(b->cg_ev, s)) != hipSuccess) return e;
   return hipEventSynchronize(b->cg_ev);
@@ -1717,6 +1761,14 @@ ope_status ope_batch_destroy(ope_batch* b) {
   if (b->h_mjobs) (void)hipHostFree(b->h_mjobs);
   if (b->h_rjobs) (void)hipHostFree(b->h_rjobs);
   if (b->h_flags) (void)hipHostFree(b->h_flags);
+  if (b->step_graph) (void)hipGraphExecDestroy(b->step_graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->cap_fork) (void)hipEventDestroy(b->cap_fork);
+  if (b->cap_join) (void)hipEventDestroy(b->cap_join);
+  if (b->d_gmjobs) (void)hipFree(b->d_gmjobs);
+  if (b->d_grjobs) (void)hipFree(b->d_grjobs);
+  if (b->d_gflags) (void)hipFree(b->d_gflags);
+  if (b->h_gflags) (void)hipHostFree(b->h_gflags);
   delete b;
   return OPE_OK;
 }
@@ -1810,6 +1862,147 @@ ope_status ope_batch_solve(ope_batch* b, void* const* U, double tau, double res_
   return first;
 }
 
+ope_status ope_batch_capture(ope_batch* b, void* const* U, double tau, int32_t cg_iterations) {
+  if (!b || !U || !(tau > 0.0) || cg_iterations < 2 || cg_iterations % 2 != 0) return OPE_EINVAL;
+  const int P = b->count;
+  int64_t nflags = 0;
+  for (int i = 0; i < P; ++i) {
+    if (!U[i]) return OPE_EINVAL;
+    ope_ctx* c = b->ctx[i];
+    // one-work-group small solves (no host check) and one-work-group column sums
+    if (c->N > OPE_MAX_N_ONE_WG || c->prof_kernel >= 0) return OPE_EUNSUPPORTED;
+    ope_status st = ensure_ws(c);
+    if (st != OPE_OK) return st;
+    nflags += c->N;
+  }
+  HIPCHK(hipDeviceSynchronize());
+  if (b->step_graph) {
+    HIPCHK(hipGraphExecDestroy(b->step_graph));
+    b->step_graph = nullptr;
+  }
+  if (!b->cap_stream) {
+    HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->cap_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->cap_join, hipEventDisableTiming));
+    if (hipMalloc((void**)&b->d_gmjobs, sizeof(MarchJob) * 4 * (size_t)P) != hipSuccess ||
+        hipMalloc((void**)&b->d_grjobs, sizeof(ReduceJob) * (size_t)P) != hipSuccess ||
+        hipMalloc((void**)&b->d_gflags, sizeof(int32_t) * (size_t)nflags) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_gflags, sizeof(int32_t) * (size_t)nflags, hipHostMallocDefault) != hipSuccess)
+      return OPE_ENOMEM;
+  }
+  // problems in the shared launches (the batch's launch mode), the others run
+  // their CG on their own streams; flags of both kinds land in h_gflags
+  std::vector<int> members;
+  std::vector<char> shared(P, 0);
+  for (int i = 0; i < P; ++i)
+    if (b->shared && shared_fits(b->ctx[i])) {
+      shared[i] = 1;
+      members.push_back(i);
+    }
+  CgPlan pl;
+  if (!members.empty()) {
+    plan_cg(b, members, b->d_gflags, pl);
+    HIPCHK(hipMemcpy(b->d_gmjobs, b->h_mjobs, sizeof(MarchJob) * pl.jobs, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_grjobs, b->h_rjobs, sizeof(ReduceJob) * pl.M, hipMemcpyHostToDevice));
+  }
+  b->gflag_off.assign(P, 0);
+  uint32_t foff = pl.flags;
+  for (int i = 0; i < P; ++i) {
+    if (shared[i]) {
+      b->gflag_off[i] = b->flag_off[i];
+    } else {
+      b->gflag_off[i] = foff;
+      foff += (uint32_t)b->ctx[i]->N;
+    }
+  }
+  hipStream_t cs = b->cap_stream;
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  auto finish = [&](int i) -> ope_status {    // Steps 2-4, scalars to the host, join
+    ope_ctx* c = b->ctx[i];
+    ope_status st = phase_update(c, U[i], tau);
+    if (st != OPE_OK) return st;
+    HIPCHK(hipMemcpyAsync(c->hsc, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipEventRecord(b->done[i], c->stream));
+    HIPCHK(hipStreamWaitEvent(cs, b->done[i], 0));
+    return OPE_OK;
+  };
+  auto body = [&]() -> ope_status {
+    HIPCHK(hipEventRecord(b->cap_fork, cs));
+    for (int i = 0; i < P; ++i) {
+      ope_ctx* c = b->ctx[i];
+      HIPCHK(hipStreamWaitEvent(c->stream, b->cap_fork, 0));
+      ope_status st = phase_residual(c, U[i]);
+      if (st == OPE_OK) st = phase_warm_start(c, U[i]);
+      if (st != OPE_OK) return st;
+      if (shared[i]) {
+        HIPCHK(hipEventRecord(b->done[i], c->stream));
+        HIPCHK(hipStreamWaitEvent(cs, b->done[i], 0));
+        continue;
+      }
+      // own launches, the whole step on the problem's stream
+      for (int32_t it = 0; it < cg_iterations; ++it) HIPCHK(cg_iteration(c, it));
+      HIPCHK(cg_flush(c, cg_iterations, c->stream));
+      HIPCHK(hipMemcpyAsync(b->h_gflags + b->gflag_off[i], c->active, sizeof(int32_t) * c->N,
+                            hipMemcpyDeviceToHost, c->stream));
+      if ((st = finish(i)) != OPE_OK) return st;
+    }
+    if (members.empty()) return OPE_OK;
+    HIPCHK(enqueue_cg(b, pl, b->d_gmjobs, b->d_grjobs, 0, cg_iterations, cs));
+    HIPCHK(launch_gather_flags(cs, b->d_grjobs, pl.M));
+    HIPCHK(hipMemcpyAsync(b->h_gflags, b->d_gflags, sizeof(int32_t) * pl.flags, hipMemcpyDeviceToHost, cs));
+    HIPCHK(hipEventRecord(b->cap_join, cs));
+    for (int i : members) {
+      HIPCHK(hipStreamWaitEvent(b->ctx[i]->stream, b->cap_join, 0));
+      ope_status st = finish(i);
+      if (st != OPE_OK) return st;
+    }
+    return OPE_OK;
+  };
+  const ope_status st = body();
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(cs, &g);
+  if (st != OPE_OK || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return st != OPE_OK ? st : OPE_EHIP;
+  }
+  const hipError_t ie = hipGraphInstantiate(&b->step_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    b->step_graph = nullptr;
+    return OPE_EHIP;
+  }
+  b->cap_iters = cg_iterations;
+  return OPE_OK;
+}
+
+ope_status ope_batch_replay(ope_batch* b, ope_step_info* info) {
+  if (!b) return OPE_EINVAL;
+  if (!b->step_graph) return OPE_EINVAL;
+  HIPCHK(hipGraphLaunch(b->step_graph, b->user));
+  if (!info) return OPE_OK;
+  HIPCHK(hipStreamSynchronize(b->user));
+  ope_status first = OPE_OK;
+  for (int i = 0; i < b->count; ++i) {
+    ope_ctx* c = b->ctx[i];
+    const OpeScalars& sc = *c->hsc;
+    ope_status st = (ope_status)sc.err;
+    if (st == OPE_OK) {
+      const int32_t* f = b->h_gflags + b->gflag_off[i];
+      for (int64_t j = 0; j < c->N; ++j)
+        if (f[j] != 0) st = OPE_ECG_MAXIT;
+    }
+    info[i].energy = sc.energy;
+    info[i].residual = sc.residual;
+    info[i].drift = sc.drift;
+    info[i].inner_iterations = sc.cg_iters;
+    info[i].status = st;
+    c->drift_seen = sc.drift;
+    if (first == OPE_OK && st != OPE_OK) first = st;
+  }
+  return first;
+}
+
 namespace {
 
 struct TunedShape {
@@ -1883,6 +2076,10 @@ ope_status ope_autotune(ope_ctx* c) {
 
 ope_status ope_batch_autotune(ope_batch* b, int32_t* tuned_keys) {
   if (!b) return OPE_EINVAL;
+  if (b->step_graph) {       // its job tables hold the old sweep shapes
+    (void)hipGraphExecDestroy(b->step_graph);
+    b->step_graph = nullptr;
+  }
   // bucket of a problem: grid edge and vector-column count, each in steps of 8
   struct Key {
     int dim, prec, vw;

@@ -139,6 +139,8 @@ SIGNATURES = {
     "ope_batch_solve": ([_P, ctypes.POINTER(_P), _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
     "ope_batch_autotune": ([_P, ctypes.POINTER(_I32)], _I32),
     "ope_batch_set_shared": ([_P, _I32], _I32),
+    "ope_batch_capture": ([_P, ctypes.POINTER(_P), ctypes.c_double, _I32], _I32),
+    "ope_batch_replay": ([_P, _P], _I32),
     "ope_get_sweep_shape": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], _I32),
     "ope_profile_begin": ([_P, _I32], _I32),
     "ope_convert": ([_P, _P, _P, _I64, _I32], _I32),
@@ -631,6 +633,21 @@ class Batch:
         infos = (ope_solve_info * self.count)()
         _check(lib().ope_batch_solve(self.handle, self._ptrs(Us), tau, res_tol, max_steps, infos), "ope_batch_solve",
                allow=(OPE_ECG_MAXIT,))
+        return list(infos)
+
+    def capture(self, Us, tau: float, cg_iterations: int) -> None:
+        """One batched step of the blocks Us as a HIP graph (ope_batch_capture)."""
+        self._captured = list(Us)          # the graph steps these buffers: keep them alive
+        _check(lib().ope_batch_capture(self.handle, self._ptrs(Us), tau, cg_iterations), "ope_batch_capture")
+
+    def replay(self, wait: bool = True, allow_maxit: bool = True):
+        """Replays the captured step; with wait, returns the per-problem infos."""
+        if not wait:
+            _check(lib().ope_batch_replay(self.handle, None), "ope_batch_replay")
+            return None
+        infos = (ope_step_info * self.count)()
+        _check(lib().ope_batch_replay(self.handle, ctypes.cast(infos, _P)), "ope_batch_replay",
+               allow=(OPE_ECG_MAXIT,) if allow_maxit else ())
         return list(infos)
 
     def set_shared(self, shared: bool) -> None:

@@ -17,6 +17,9 @@ so that a reader can check each function against the paper by eye:
   the same step as a dense Cayley solve and as the 2N x 2N Woodbury system,
   the generator ``L_U``, energy, residual, Ritz values, the Algorithm 1 loop
   (fixed and adaptive step) and the scheme in the inner product of M.
+* :mod:`oracle.multigrid` -- the symmetric multigrid V-cycle that preconditions
+  Step 1's CG in the library's optional preconditioned form, and that
+  preconditioned CG per column.
 * :mod:`oracle.net`      -- the small 3D conv-net that stands in for ``H^{-1}``
   applied to residual columns in the learned form (forward, backward, loss);
   imported as ``oracle.net``.
@@ -38,6 +41,7 @@ from .operator import (  # noqa: F401
     sine_eigenvalues_1d,
     lowest_eigenpairs,
 )
+from .multigrid import Hierarchy, pcg_source  # noqa: F401
 from .scheme import (  # noqa: F401
     inner,
     generator_apply,

@@ -357,6 +357,40 @@ def paper_table1(ope, torch, taus=(0.5, 1.0, 1.5)):
     return out
 
 
+def mg_steps_per_second(ope, torch, p, tau, steps, warmup):
+    """Steps per second with the multigrid-preconditioned Step 1
+    (ope_set_multigrid) from the seeded start over the given window, with the
+    V-cycle's share (HIP events around its launches) and the inner iterations."""
+    U = torch.from_numpy(p.U0).to("cuda")
+    with ope.Context(p.grid, p.V, p.N) as c:
+        ope.ope_set_multigrid(c.handle, True)
+        levels, coarsest = ope.ope_mg_info(c.handle)
+        for _ in range(warmup):
+            ope.ope_step(c.handle, U, tau)
+        torch.cuda.synchronize()
+        inner = 0
+        last = None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            last = ope.ope_step(c.handle, U, tau)
+            inner += last.inner_iterations
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        parts = {}
+        for name, kid in (("vcycle", ope.OPE_KERNEL_MG), ("cg_sweep_a", ope.OPE_KERNEL_CG_SWEEP_A),
+                          ("cg_sweep_b", ope.OPE_KERNEL_CG_SWEEP_B), ("cg_sweep_b_odd", ope.OPE_KERNEL_CG_SWEEP_B_Y),
+                          ("cg_reduce", ope.OPE_KERNEL_CG_REDUCE)):
+            ope.ope_profile_begin(c.handle, kid)
+            its = 0
+            for _ in range(3):
+                its += ope.ope_step(c.handle, U, tau).inner_iterations
+            nl, tms = ope.ope_profile_end(c.handle)
+            parts[name] = {"ms_per_step": tms / 3.0, "launches_per_step": nl / 3.0}
+    return {"iter_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "inner_iterations_per_step": inner / steps,
+            "levels": levels, "coarsest_nodes": coarsest, "residual_at_end": last.residual,
+            "drift_at_end": last.drift, "parts": parts}
+
+
 def learned_steps_per_second(ope, torch, p, tau, steps, warmup):
     """The learned form on the benchmark workload: Algorithm 1 with the shipped
     network, each learned step judged by the plain step (replaced when
@@ -646,7 +680,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large", "extrapolate", "energy",
-                                       "table1", "ttr", "graph"], default=None,
+                                       "table1", "ttr", "graph", "mg"], default=None,
                     help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
@@ -685,6 +719,8 @@ def main():
             p = W.wells_3d(m=args.m, N=args.N, seed=args.seed, tau=args.tau)
             if args.form == "mixed":
                 r = steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, args.steps, args.warmup)
+            elif args.form == "mg":
+                r = mg_steps_per_second(ope, torch, p, args.tau, args.steps, args.warmup)
             elif args.form == "extrapolate":
                 r = extrapolated_time_to_residual(ope, torch, p, args.tau)
             else:

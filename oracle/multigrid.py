@@ -15,8 +15,9 @@ Hierarchy (level 0 is the operator itself, ``W_0 = V + shift``):
   * ``W_{k+1}(I)`` is the mean of ``W_k`` over the existing children of ``I``;
   * ``H_k = kinetic (-Lap_{h_k}) + diag(W_k)`` (the same finite-difference
     form as the fine operator, on the coarse grid);
-  * coarsening stops at the first level with at most ``COARSEST_MAX`` nodes,
-    whose operator is inverted exactly (Cholesky).
+  * coarsening stops at the first level k >= 1 with at most ``COARSEST_MAX``
+    nodes (level 0 is always coarsened once, unless every axis has a single
+    node), whose operator is inverted exactly (Cholesky).
 
 Transfers, per coarsened axis (a tensor product over the axes):
   * prolongation P: fine node ``f`` with parent ``I = f // 2`` takes
@@ -187,9 +188,11 @@ class Hierarchy:
         self.omega = omega
         lv = [Level(tuple(int(x) for x in op.m), tuple(float(x) for x in op.h),
                     np.asarray(op.V, dtype=np.float64) + op.shift, float(op.kinetic))]
-        while lv[-1].n > coarsest_max:
+        while len(lv) == 1 or lv[-1].n > coarsest_max:
             f = lv[-1]
             mc = coarse_shape(f.m)
+            if mc == f.m:
+                break
             hc = tuple(2.0 * f.h[a] if f.m[a] > 1 else f.h[a] for a in range(len(f.m)))
             lv.append(Level(mc, hc, coarse_potential(f, mc), f.kinetic))
         self.levels = lv

@@ -81,6 +81,7 @@ void drop_graphs(ope_ctx* c);
 
 void free_ctx(ope_ctx* c) {
   if (!c) return;
+  mg_free(c);
   void* dptrs[] = {c->diag, c->diag32, c->ws_own, c->C, c->Lam, c->Linv, c->Sb, c->T,
                    c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
                    c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->sc,
@@ -217,7 +218,8 @@ hipError_t cg_iteration(ope_ctx* c, int it) {
   const int N = (int)c->N;
   const int first = it == 0;
   hipError_t e;
-  if ((e = launch_cg_pap(c, r_cur, p_old, p_new, first)) != hipSuccess) return e;
+  // preconditioned form: sweep A forms p from z = B r instead of r
+  if ((e = launch_cg_pap(c, c->mg_on ? (const void*)c->mg_Z : r_cur, p_old, p_new, first)) != hipSuccess) return e;
   {
     ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
     if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA, a_cur)) != hipSuccess) return e;
@@ -225,8 +227,26 @@ hipError_t cg_iteration(ope_ctx* c, int it) {
   if (it & 1) e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, c->Y, p_old, a_prev);
   else e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, nullptr, nullptr, nullptr);
   if (e != hipSuccess) return e;
+  if (c->mg_on) {
+    // z = B r', then beta = r'^T z / rho and the stop test on |r'|^2
+    if ((e = mg_vcycle(c, (const double*)r_nxt, c->mg_Z, c->active, true)) != hipSuccess) return e;
+    ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
+    if ((e = launch_reduce_cols(c, c->mg_part, c->mg_rows_used, 2 * N, c->mg_dots, RED_PLAIN)) != hipSuccess)
+      return e;
+    return launch_pcg_beta(c);
+  }
   ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
   return launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_BETA, a_cur);
+}
+
+// Preconditioned CG start, after the CG set-up (targets and flags from |r0|^2):
+// z0 = B r0 and rho = r0^T z0.
+hipError_t pcg_begin(ope_ctx* c) {
+  hipError_t e;
+  if ((e = mg_vcycle(c, (const double*)c->Rb[0], c->mg_Z, c->active, true)) != hipSuccess) return e;
+  if ((e = launch_reduce_cols(c, c->mg_part, c->mg_rows_used, 2 * c->N, c->mg_dots, RED_PLAIN)) != hipSuccess)
+    return e;
+  return launch_pcg_start(c);
 }
 
 // After `its` CG iterations: when the last one was even, add its deferred y
@@ -374,6 +394,7 @@ ope_status phase_warm_start(ope_ctx* c, const void* Uv) {
   }
   HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rho0, RED_PLAIN));
   HIPCHK(launch_cg_setup(c, c->rho0));
+  if (c->mg_on) HIPCHK(pcg_begin(c));
   return OPE_OK;
 }
 
@@ -626,7 +647,7 @@ struct BatchState {
 // work-group's reduction (the same fixed-order sum its own steps use, so that
 // its shared-launch iterates equal those of its own launches bit for bit); its
 // work items are the tiles of its own sweep shape.
-bool shared_fits(const ope_ctx* c) { return reduce_few_fits(c); }
+bool shared_fits(const ope_ctx* c) { return !c->mg_on && reduce_few_fits(c); }
 
 // The shared CG launches of a set of problems: classes of problems that one
 // kernel instance can sweep (storage type, vector width, passes per plane,
@@ -1294,6 +1315,7 @@ ope_status ope_source_solve(ope_ctx* c, const double* U, double* Y, const double
   HIPCHK(launch_reduce_cols(c, c->part, c->stream_wgs, 2 * N, c->rho0, RED_PLAIN));
   HIPCHK(hipMemcpyAsync(c->cnorm2, c->rho0 + N, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(launch_solve_setup(c, c->rho0, tol));
+  if (c->mg_on) HIPCHK(pcg_begin(c));
   if (Y0) HIPCHK(hipMemcpyAsync(c->Y, Y0, sizeof(double) * c->n * N, hipMemcpyDeviceToDevice, c->stream));
   int32_t iters = 0;
   bool done = false;
@@ -1409,6 +1431,38 @@ ope_status ope_residual(ope_ctx* c, const void* U, double* residual, double* rit
 ope_status ope_set_graphs(ope_ctx* c, int32_t enable) {
   if (!c || (enable != 0 && enable != 1)) return OPE_EINVAL;
   c->use_graphs = enable;
+  return OPE_OK;
+}
+
+ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
+  if (!c || (enable != 0 && enable != 1)) return OPE_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);               // the captured CG chunks hold the other iteration
+  if (!enable) {
+    mg_free(c);
+    return OPE_OK;
+  }
+  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
+  if (c->N % 2 != 0 && c->N > 256) return OPE_EUNSUPPORTED;     // one thread per row chunk of a point
+  const ope_status st = mg_build(c);
+  if (st != OPE_OK) return st;
+  c->mg_on = 1;
+  return OPE_OK;
+}
+
+ope_status ope_mg_info(const ope_ctx* c, int32_t* levels, int64_t* coarsest_nodes) {
+  if (!c) return OPE_EINVAL;
+  if (levels) *levels = c->mg_on ? c->mg_levels : 0;
+  if (coarsest_nodes) *coarsest_nodes = c->mg_on ? c->mg[c->mg_levels - 1].n : 0;
+  return OPE_OK;
+}
+
+ope_status ope_mg_vcycle(ope_ctx* c, const double* R, double* Zo) {
+  if (!c || !R || !Zo || (const void*)R == (const void*)Zo) return OPE_EINVAL;
+  if (!c->mg_on) return OPE_EINVAL;
+  if (c->N % 2 == 0 && ((((uintptr_t)R) | ((uintptr_t)Zo)) & 15u)) return OPE_EINVAL;
+  HIPCHK(mg_vcycle(c, R, Zo, nullptr, false));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return OPE_OK;
 }
 

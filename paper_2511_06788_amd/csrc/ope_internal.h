@@ -79,6 +79,17 @@ struct OpeScalars {
 // predication bits of the row-block products and the predicated copy
 enum { ROWMM_IF_OK = 1, ROWMM_IF_RENORM = 2 };
 
+// One level of the multigrid preconditioner (k_mg.hip).  Level 0 is the
+// operator itself (its B and E are the caller's residual and result).
+#define OPE_MG_MAX_LEVELS 16
+struct MgLevel {
+  uint32_t m0, m1, m2;          // nodes per axis (1 for absent axes)
+  double cx, cy, cz;            // kinetic / h_a^2 on this level (0 for absent axes)
+  int64_t n;
+  double* diag;                 // diagonal of H on this level (level 0: the context's)
+  double *B, *E, *T;            // right-hand side, correction, scratch (n x N each; level 0: T only)
+};
+
 struct ope_ctx {
   int device;
   hipStream_t stream;
@@ -153,6 +164,17 @@ struct ope_ctx {
   int net_judge;                // 1: the plain step judges each learned iterate and replaces it if rejected
   void* Ubak;
   OpeScalars* hsc2;             // pinned: scalars right after a learned update
+  // multigrid-preconditioned Step 1 (ope_set_multigrid; FP64)
+  int mg_on;
+  int mg_levels;
+  MgLevel mg[OPE_MG_MAX_LEVELS];
+  double* mg_inv;               // coarsest level: dense inverse, row-major nc x nc
+  double* mg_Z;                 // preconditioned residual z (n x N)
+  double* mg_part;              // partial rows of r^T z and r^T r (mg_rows x 2N)
+  int64_t mg_rows;
+  int64_t mg_rows_used;         // partial rows written by the last V-cycle with dots
+  double* mg_dots;              // 2N: r^T z, r^T r
+  void* mg_mem;                 // one allocation holding the level blocks
   // kernel timing (ope_profile_begin / ope_profile_end)
   int prof_kernel;              // kernel id being timed, -1 when off
   std::vector<hipEvent_t> prof_events;  // start/stop pairs, reused across sessions
@@ -210,6 +232,16 @@ hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew
 // stopped on an even iteration
 hipError_t launch_y_flush(ope_ctx* c, hipStream_t s, void* y, const void* p, const double* alpha);
 hipError_t launch_cg_setup_reduce(ope_ctx* c, int mode);
+
+// multigrid preconditioner (k_mg.hip)
+ope_status mg_build(ope_ctx* c);          // the hierarchy for the context's operator and N
+void mg_free(ope_ctx* c);
+// z = B r (one V-cycle) for the columns still active (all when active is
+// NULL); with dots, also the partial rows of r^T z and r^T r into c->mg_part
+hipError_t mg_vcycle(ope_ctx* c, const double* r, double* z, const int32_t* active, bool dots);
+// PCG scalars from the reduced dots: start (rho = r^T z) and the beta update
+hipError_t launch_pcg_start(ope_ctx* c);
+hipError_t launch_pcg_beta(ope_ctx* c);
 
 // column sums of partials: out[j] = sum_w part[w*ncols + j], fixed order
 // (the CG modes write alpha, default c->alpha)

@@ -106,6 +106,7 @@ OPE_KERNEL_ROWMM = 4
 OPE_KERNEL_SMALL = 5
 OPE_KERNEL_CG_SWEEP_B_Y = 6
 OPE_KERNEL_CG_REDUCE = 7
+OPE_KERNEL_MG = 8
 
 _lib = None
 
@@ -130,6 +131,9 @@ SIGNATURES = {
     "ope_solve": ([_P, _P, _D, _D, _I32, ctypes.POINTER(ope_solve_info)], _I32),
     "ope_set_sweep_shape": ([_P, _I32, _I32, _I32], _I32),
     "ope_set_graphs": ([_P, _I32], _I32),
+    "ope_set_multigrid": ([_P, _I32], _I32),
+    "ope_mg_info": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I64)], _I32),
+    "ope_mg_vcycle": ([_P, _P, _P], _I32),
     "ope_autotune": ([_P], _I32),
     "ope_batch_create": ([ctypes.POINTER(_P), ctypes.POINTER(ope_op_desc), ctypes.POINTER(_I64), _I32, _I32, _P],
                          _I32),
@@ -422,6 +426,21 @@ def ope_autotune(ctx: int) -> None:
 
 def ope_set_graphs(ctx: int, enable: bool) -> None:
     _check(lib().ope_set_graphs(ctx, 1 if enable else 0), "ope_set_graphs")
+
+
+def ope_set_multigrid(ctx: int, enable: bool) -> None:
+    _check(lib().ope_set_multigrid(ctx, 1 if enable else 0), "ope_set_multigrid")
+
+
+def ope_mg_info(ctx: int):
+    """(levels, nodes of the coarsest level); (0, 0) when the preconditioner is off."""
+    lv, nc = _I32(0), _I64(0)
+    _check(lib().ope_mg_info(ctx, ctypes.byref(lv), ctypes.byref(nc)), "ope_mg_info")
+    return lv.value, nc.value
+
+
+def ope_mg_vcycle(ctx: int, R, Z) -> None:
+    _check(lib().ope_mg_vcycle(ctx, _ptr(R), _ptr(Z)), "ope_mg_vcycle")
 
 
 def ope_set_sweep_shape(ctx: int, q_max: int, march_chunks: int, flags: int = 0) -> None:

@@ -85,13 +85,19 @@ def kernel_bytes(kind, n, N):
     }.get(kind)
 
 
-def traffic_from_pmc(n, N):
-    """HBM bytes per sweep-B launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def traffic_from_pmc(n, N, kernel="cg_sweep_b"):
+    """HBM bytes per working launch of a kernel from the committed rocprofv3
+    counter summary, or None when its source changed since the counters were
+    taken (or none were taken for it)."""
     if not os.path.exists(PMC_FILE):
         return None
-    rec = json.load(open(PMC_FILE))
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    recs = json.load(open(PMC_FILE))
+    rec = recs.get(kernel) if isinstance(recs, dict) and kernel in recs else (
+        recs if kernel == "cg_sweep_b" and "source_sha256" in recs else None)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2511_06788_amd", "csrc", rec.get("source", "k_stencil.hip"))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("source_sha256") != sha or rec.get("n") != n or rec.get("N") != N:
         return None
     return (rec["fetch_kib_per_dispatch"] + rec["write_kib_per_dispatch"]) * 1024.0 * rec["copy_scale"]
@@ -666,6 +672,119 @@ def copy_calibration(torch, gib=1.0, reps=5):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}))
 
 
+def mg_post_bytes(n, N):
+    """Algorithmic HBM bytes of the finest post-smoothing launch of a V-cycle:
+    read r and x1, write z (three n x N FP64 blocks), the diagonal and the
+    Jacobi factors (two n-entry arrays)."""
+    return 3 * n * N * 8 + 16 * n
+
+
+def step_rate(ope, torch, p, args, multigrid):
+    """Outer steps per second of the plain FP64 step on workload p over the
+    window (warm-up, then timed steps from the seeded start), with the live
+    roofline of the dominant kernel: the finest post-smoothing of the V-cycle
+    with the multigrid-preconditioned Step 1, CG sweep B without it (HIP events
+    the library records on its own stream, over the timed steps)."""
+    n, N = p.grid.n, p.N
+    U = torch.from_numpy(p.U0).to("cuda")
+    ctx = ope.Context(p.grid, p.V, N)
+    h = ctx.handle
+    levels = coarsest = 0
+    if multigrid:
+        ope.ope_set_multigrid(h, True)
+        levels, coarsest = ope.ope_mg_info(h)
+    for _ in range(args.warmup):
+        ope.ope_step(h, U, args.tau)
+    torch.cuda.synchronize()
+    kid = ope.OPE_KERNEL_MG_POST if multigrid else ope.OPE_KERNEL_CG_SWEEP_B
+    ope.ope_profile_begin(h, kid)
+    inner = 0
+    last = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        last = ope.ope_step(h, U, args.tau)
+        inner += last.inner_iterations
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, total_ms = ope.ope_profile_end(h)
+    dt = t1 - t0
+    ms_per_step = 1e3 * dt / max(args.steps, 1)
+    if multigrid:
+        # one finest post-smoothing per V-cycle: the start of every step's
+        # PCG and each counted iteration; the V-cycles of iterations past
+        # convergence find no active column and return at once
+        working = args.steps + inner
+        nbytes = mg_post_bytes(n, N)
+        traffic = traffic_from_pmc(n, N, "mg_post")
+        name = "mg_post"
+    else:
+        # every counted CG iteration runs one full sweep B (launches past the
+        # last converged column of a chunk return at once)
+        working = inner
+        nbytes = sweep_b_bytes(n, N)
+        traffic = traffic_from_pmc(n, N, "cg_sweep_b")
+        name = "cg_sweep_b"
+    avg_ms = total_ms / max(working, 1)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    res = {
+        "iter_per_s": args.steps / dt, "ms_per_step": ms_per_step,
+        "inner_iterations_per_step": inner / max(args.steps, 1),
+        "residual_at_end": last.residual if last else None, "drift_at_end": last.drift if last else None,
+        "levels": levels, "coarsest_nodes": coarsest,
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": nbytes,
+                     "avg_launch_ms": avg_ms, "working_launches": working, "launches": launches,
+                     "total_ms": total_ms, "avg_ms_all_launches": total_ms / max(launches, 1)},
+    }
+    if not args.no_extras:
+        kernels = {}
+        ids = [("stencil", ope.OPE_KERNEL_STENCIL), ("cg_sweep_a", ope.OPE_KERNEL_CG_SWEEP_A),
+               ("cg_sweep_b", ope.OPE_KERNEL_CG_SWEEP_B), ("cg_sweep_b_odd", ope.OPE_KERNEL_CG_SWEEP_B_Y),
+               ("cg_reduce", ope.OPE_KERNEL_CG_REDUCE), ("gram", ope.OPE_KERNEL_GRAM),
+               ("rowmm", ope.OPE_KERNEL_ROWMM), ("small", ope.OPE_KERNEL_SMALL)]
+        if multigrid:
+            ids += [("vcycle", ope.OPE_KERNEL_MG), ("mg_post", ope.OPE_KERNEL_MG_POST)]
+        for kname, k in ids:
+            ope.ope_profile_begin(h, k)
+            its = 0
+            for _ in range(5):
+                its += ope.ope_step(h, U, args.tau).inner_iterations
+            nl, tms = ope.ope_profile_end(h)
+            # a CG sweep's (or V-cycle's) time per working launch, as above
+            if kname in ("cg_sweep_a", "cg_sweep_b", "cg_reduce"):
+                per = its
+            elif kname == "cg_sweep_b_odd":
+                per = its / 2.0
+            elif kname in ("vcycle", "mg_post"):
+                per = its + 5
+            else:
+                per = nl
+            rec = {"avg_ms": tms / max(per, 1), "launches_per_step": nl / 5.0, "ms_per_step": tms / 5.0}
+            b = mg_post_bytes(n, N) if kname == "mg_post" else kernel_bytes(kname, n, N)
+            if b:
+                rec["GB/s"] = b / (rec["avg_ms"] * 1e-3) / 1e9
+            if kname == "gram":
+                rec["TFLOP/s_fp64"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
+            if kname == "rowmm":
+                rec["TFLOP/s_fp64_N_by_N"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
+            kernels[kname] = rec
+        res["kernels"] = kernels
+        # window-independent cost: an inner iteration (both sweeps, the column
+        # reductions and, preconditioned, the V-cycle) and what a step spends
+        # outside Step 1
+        per_it = kernels["cg_sweep_a"]["avg_ms"] + kernels["cg_sweep_b"]["avg_ms"] + kernels["cg_reduce"]["avg_ms"]
+        if multigrid:
+            per_it += kernels["vcycle"]["avg_ms"]
+        its_step = inner / max(args.steps, 1)
+        res["cost_model"] = {"ms_per_inner_iteration": per_it, "inner_iterations_per_step": its_step,
+                             "ms_per_step_outside_inner": ms_per_step - its_step * per_it,
+                             "note": "ms_per_step = inner_iterations_per_step x ms_per_inner_iteration + outside; "
+                                     "the iteration count depends on the window (early steps need more)"}
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -731,104 +850,54 @@ def main():
     log(f"building workload {args.m}^3 N={args.N} seed={args.seed}")
     p = W.wells_3d(m=args.m, N=args.N, seed=args.seed, tau=args.tau)
     n, N = p.grid.n, p.N
-    U = torch.from_numpy(p.U0).to("cuda")
-    ctx = ope.Context(p.grid, p.V, N)
-    h = ctx.handle
 
-    log(f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        ope.ope_step(h, U, args.tau)
-    torch.cuda.synchronize()
-
-    log(f"timed {args.steps} steps")
-    ope.ope_profile_begin(h, ope.OPE_KERNEL_CG_SWEEP_B)
-    inner = 0
-    last = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        last = ope.ope_step(h, U, args.tau)
-        inner += last.inner_iterations
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches, total_ms = ope.ope_profile_end(h)
-    dt = t1 - t0
-    ms_per_step = 1e3 * dt / max(args.steps, 1)
-    # Every counted CG iteration runs one full sweep B; the launches past the
-    # last converged column of a 4-iteration chunk find no active column and
-    # return at once.  The sweep's time is therefore taken per counted
-    # iteration (total sweep-B time / iterations), not per launch.
-    avg_ms = total_ms / max(inner, 1)
-    avg_all_ms = total_ms / max(launches, 1)
-    achieved = sweep_b_bytes(n, N) / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_pmc(n, N)
-
+    log("multigrid-preconditioned step (the headline)")
+    mg = step_rate(ope, torch, p, args, multigrid=True)
+    log("plain CG step")
+    plain = step_rate(ope, torch, p, args, multigrid=False)
     out = {
         "metric": METRIC,
-        "value": args.steps / dt,
+        "value": mg["iter_per_s"],
         "unit": "iter/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": mg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"wells3d_{args.m}^3_N{N}_seed{args.seed}", "n": n, "N": N, "tau": args.tau,
-                   "form": "plain FP64", "inner": "CG, eta = max(1e-12, 0.1 res), warm start U Lam^-1",
+                   "form": "plain FP64",
+                   "inner": "preconditioned CG, one symmetric multigrid V-cycle per iteration, "
+                            "eta = max(1e-12, 0.1 res), warm start U Lam^-1",
                    "window": {"warmup_steps": args.warmup, "timed_steps": args.steps,
                               "start": "seeded orthonormal start block"}},
-        "roofline": {"bound": "hbm", "kernel": "cg_sweep_b", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes": sweep_b_bytes(n, N),
-                     "avg_launch_ms": avg_ms, "sweeping_launches": inner, "launches": launches,
-                     "total_ms": total_ms, "avg_ms_all_launches": avg_all_ms},
-        "inner_iterations_per_step": inner / max(args.steps, 1),
-        "residual_at_end": last.residual if last else None,
-        "drift_at_end": last.drift if last else None,
+        "roofline": mg["roofline"],
+        "inner_iterations_per_step": mg["inner_iterations_per_step"],
+        "residual_at_end": mg["residual_at_end"],
+        "drift_at_end": mg["drift_at_end"],
+        "multigrid": {"levels": mg["levels"], "coarsest_nodes": mg["coarsest_nodes"]},
     }
-
-    if not args.no_extras:
-        kernels = {}
-        for name, kid in (("stencil", ope.OPE_KERNEL_STENCIL), ("cg_sweep_a", ope.OPE_KERNEL_CG_SWEEP_A),
-                          ("cg_sweep_b_odd", ope.OPE_KERNEL_CG_SWEEP_B_Y), ("cg_reduce", ope.OPE_KERNEL_CG_REDUCE),
-                          ("gram", ope.OPE_KERNEL_GRAM), ("rowmm", ope.OPE_KERNEL_ROWMM),
-                          ("small", ope.OPE_KERNEL_SMALL)):
-            ope.ope_profile_begin(h, kid)
-            its = 0
-            for _ in range(5):
-                its += ope.ope_step(h, U, args.tau).inner_iterations
-            nl, tms = ope.ope_profile_end(h)
-            # a CG sweep's time per counted iteration (as for sweep B above);
-            # the odd form of sweep B runs on every second one
-            per = its if name in ("cg_sweep_a", "cg_reduce") else (its / 2.0 if name == "cg_sweep_b_odd" else nl)
-            rec = {"avg_ms": tms / max(per, 1), "launches_per_step": nl / 5.0}
-            b = kernel_bytes(name, n, N)
-            if b:
-                rec["GB/s"] = b / (rec["avg_ms"] * 1e-3) / 1e9
-            if name == "gram":
-                rec["TFLOP/s_fp64"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
-            if name == "rowmm":
-                rec["TFLOP/s_fp64_N_by_N"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
-            kernels[name] = rec
-        kernels["cg_sweep_b"] = {"avg_ms": avg_ms, "GB/s": achieved}
-        out["kernels"] = kernels
-        # window-independent cost: a CG iteration (both sweeps and both column
-        # reductions, kernel time) and what a step spends outside its CG
-        per_it = kernels["cg_sweep_a"]["avg_ms"] + avg_ms + kernels["cg_reduce"]["avg_ms"]
-        its_step = inner / max(args.steps, 1)
-        out["cost_model"] = {"ms_per_cg_iteration": per_it,
-                             "cg_iterations_per_step": its_step,
-                             "ms_per_step_outside_cg": ms_per_step - its_step * per_it,
-                             "note": "ms_per_step = cg_iterations_per_step x ms_per_cg_iteration + outside; "
-                                     "the CG iteration count depends on the window (early steps need more)"}
-    ctx.close()
+    if "kernels" in mg:
+        out["kernels"] = mg["kernels"]
+        out["cost_model"] = mg["cost_model"]
+    out["plain_cg"] = {k: plain[k] for k in ("iter_per_s", "ms_per_step", "inner_iterations_per_step", "roofline",
+                                             "residual_at_end", "drift_at_end")}
+    if "kernels" in plain:
+        out["plain_cg"]["kernels"] = plain["kernels"]
+        out["plain_cg"]["cost_model"] = plain["cost_model"]
+    out["speedup_multigrid_vs_plain_cg"] = mg["iter_per_s"] / plain["iter_per_s"]
+    ms_per_step = plain["ms_per_step"]
+    dt = plain["ms_per_step"] * args.steps / 1e3
+    inner = plain["inner_iterations_per_step"] * args.steps
     if not args.no_extras:
         log("mixed-precision form at the same workload")
         ks = min(args.steps, 100)
         out["forms"] = {
+            "plain_fp64_multigrid": {"iter_per_s": mg["iter_per_s"], "ms_per_step": mg["ms_per_step"],
+                                     "inner_iterations_per_step": mg["inner_iterations_per_step"]},
             "plain_fp64": {"iter_per_s": args.steps / dt, "ms_per_step": ms_per_step,
                            "inner_iterations_per_step": inner / max(args.steps, 1)},
             "mixed": steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, ks, args.warmup),

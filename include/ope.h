@@ -140,10 +140,12 @@ ope_status ope_set_inner(ope_ctx* ctx, double eta_rel, double eta_floor, int32_t
  * potential V + shift averaged over the children), linear prolongation P
  * (weights 3/4, 1/4 per axis), restriction P^T / 2^d, damped Jacobi
  * (omega = 0.8) once before and once after the coarse correction, the first
- * level with at most 512 nodes solved exactly with a dense inverse.  Measured
+ * level with at most 64 nodes solved exactly with a dense inverse.  Measured
  * on 64^3 well problems: about 5 preconditioned iterations per step instead
  * of about 70.  Allocates two n x N blocks plus the coarse levels (about 3/7
- * of a block); synchronises; enable = 0 frees them.  OPE_EUNSUPPORTED for
+ * of a block); synchronises; enable = 0 frees them.  With the
+ * preconditioner on, the host checks the CG's convergence every 2 iterations
+ * (else every 4).  OPE_EUNSUPPORTED for
  * OPE_MIXED contexts and for odd N > 256; OPE_ENOTSPD if the coarsest
  * operator is not positive definite.  A problem with the preconditioner on
  * runs its CG on its own stream in batched steps (no shared launches). */
@@ -564,7 +566,8 @@ typedef enum {
   OPE_KERNEL_CG_SWEEP_B_Y = 6,/* CG sweep B of odd iterations only (with the paired y update) */
   OPE_KERNEL_CG_REDUCE = 7, /* the two fixed-order column reductions of every CG iteration */
   OPE_KERNEL_MG = 8,        /* one multigrid V-cycle of the preconditioned Step 1 (all its launches) */
-  OPE_KERNEL_COUNT = 9
+  OPE_KERNEL_MG_POST = 9,   /* its finest-level post-smoothing with the PCG dot products (one launch) */
+  OPE_KERNEL_COUNT = 10
 } ope_kernel_id;
 
 typedef struct {

@@ -61,7 +61,7 @@ import scipy.linalg as sla
 
 from .operator import Operator, apply_H, assemble_H
 
-COARSEST_MAX = 512          # nodes of the coarsest level (solved exactly)
+COARSEST_MAX = 64           # nodes of the coarsest level (solved exactly)
 OMEGA = 0.8                 # Jacobi damping
 
 

@@ -8,17 +8,19 @@
 // more than one node (m' = ceil(m / 2); coarse node I is the parent of fine
 // nodes 2I and 2I + 1), doubles its spacing (c_a' = c_a / 4), and takes as
 // potential the mean of V + shift over the existing children; the first level
-// k >= 1 with at most 512 nodes is solved exactly with a dense inverse
+// k >= 1 with at most 64 nodes is solved exactly with a dense inverse
 // (Cholesky on the host).  Transfers per coarsened axis: prolongation
 // 3/4 e_I + 1/4 e_J (J = I - 1 for even fine nodes, I + 1 for odd ones,
 // missing J = 0), restriction R = P^T / 2^d.  V-cycle, damped Jacobi
 // (omega = 0.8) once on each side of the coarse correction:
 //   x0 = omega b / d;  r1 = b - H x0;  e = B_{k+1}(R r1);  x1 = x0 + P e;
 //   z = x1 + omega (b - H x1) / d.
-// Kernels, per level: k_mg_res (r1, one stencil over x0 formed on the fly
-// from b), k_mg_restrict (R r1), k_mg_dense (coarsest), k_mg_prolong
-// (x1 = x0 + P e), k_mg_post (z, one stencil over x1; on level 0 also the
-// per-column partial sums of r^T z and r^T r that the PCG needs).
+// Kernels, per level: k_mg_zstencil<0> (r1, one stencil over x0 formed on the
+// fly from b), k_mg_zrestrict (R r1), k_mg_dense (coarsest), k_mg_zprolong
+// (x1 = x0 + P e), k_mg_zstencil<1> (z, one stencil over x1; on level 0 also
+// the per-column partial sums of r^T z and r^T r that the PCG needs).  The
+// stencil and transfer kernels march along z (see zmarch_shape); the
+// smoother's factors omega / d are precomputed per level.
 // Layout: every block is n x N row-major (a grid point's N values
 // contiguous), x fastest, as everywhere in the library; a thread owns one
 // 16-byte chunk (VW = 2 doubles) or one double of a point's row.  Columns
@@ -33,9 +35,8 @@
 namespace {
 
 constexpr double MG_OMEGA = 0.8;
-constexpr int64_t MG_COARSEST_MAX = 512;
+constexpr int64_t MG_COARSEST_MAX = 64;
 constexpr uint32_t MG_WG = 256;
-constexpr uint32_t MG_POST_WGS = 2048;      // work-groups of the level-0 post-smoothing (partial rows)
 
 struct MgGeom {
   uint32_t m0, m1, m2;
@@ -65,6 +66,12 @@ __device__ __forceinline__ void str(double* __restrict__ a, uint64_t row, uint32
 }
 
 template <int VW>
+__device__ __forceinline__ void zero(double (&a)[VW]) {
+#pragma unroll
+  for (int k = 0; k < VW; ++k) a[k] = 0.0;
+}
+
+template <int VW>
 __device__ __forceinline__ bool vec_active(const int32_t* __restrict__ active, uint32_t v) {
   if (!active) return true;
   bool a = false;
@@ -73,119 +80,39 @@ __device__ __forceinline__ bool vec_active(const int32_t* __restrict__ active, u
   return a;
 }
 
-// x0 = omega b / d at point q (zero outside the grid is the caller's job)
+// x0 = (omega / d) b at point q, with wd = omega / d (zero outside the grid is
+// the caller's job)
 template <int VW>
-__device__ __forceinline__ void jac0(const double* __restrict__ b, const double* __restrict__ diag, uint64_t q,
-                                     uint32_t N, uint32_t v, double omega, double (&o)[VW]) {
+__device__ __forceinline__ void jac0(const double* __restrict__ b, const double* __restrict__ wd, uint64_t q,
+                                     uint32_t N, uint32_t v, double (&o)[VW]) {
   ldr<VW>(b, q, N, v, o);
-  const double d = diag[q];
+  const double w = wd[q];
 #pragma unroll
-  for (int k = 0; k < VW; ++k) o[k] = (omega * o[k]) / d;
+  for (int k = 0; k < VW; ++k) o[k] = w * o[k];
 }
 
-// (H f)(p) for a field given point-wise by F(q, out): d f - sum_a c_a (f(p - e_a) + f(p + e_a))
-template <int VW, typename F>
-__device__ __forceinline__ void stencil(const MgGeom& g, const double* __restrict__ diag, uint32_t x, uint32_t y,
-                                        uint32_t z, uint64_t p, F&& field, double (&hx)[VW]) {
-  double c[VW], xm[VW], xp[VW], ym[VW], yp[VW], zm[VW], zp[VW];
-  field(p, c);
-  const uint64_t s1 = g.m0, s2 = (uint64_t)g.m0 * g.m1;
-#pragma unroll
-  for (int k = 0; k < VW; ++k) xm[k] = xp[k] = ym[k] = yp[k] = zm[k] = zp[k] = 0.0;
-  if (x > 0) field(p - 1, xm);
-  if (x + 1 < g.m0) field(p + 1, xp);
-  if (y > 0) field(p - s1, ym);
-  if (y + 1 < g.m1) field(p + s1, yp);
-  if (z > 0) field(p - s2, zm);
-  if (z + 1 < g.m2) field(p + s2, zp);
-  const double d = diag[p];
-#pragma unroll
-  for (int k = 0; k < VW; ++k)
-    hx[k] = d * c[k] - (g.cx * (xm[k] + xp[k]) + g.cy * (ym[k] + yp[k]) + g.cz * (zm[k] + zp[k]));
-}
-
-// r1 = b - H x0, x0 = omega b / d
-template <int VW>
-__global__ __launch_bounds__(MG_WG) void k_mg_res(const double* __restrict__ b, double* __restrict__ out, MgGeom g,
-                                                 const double* __restrict__ diag, double omega,
-                                                 const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                 uint64_t total) {
-  const uint64_t e = (uint64_t)xcd_remap(blockIdx.x, gridDim.x) * MG_WG + threadIdx.x;
-  if (e >= total) return;
-  const uint32_t v = (uint32_t)(e % NV);
-  const uint64_t p = e / NV;
-  if (!vec_active<VW>(active, v)) return;
-  const uint32_t x = (uint32_t)(p % g.m0), y = (uint32_t)((p / g.m0) % g.m1), z = (uint32_t)(p / ((uint64_t)g.m0 * g.m1));
-  double hx[VW], bc[VW], o[VW];
-  stencil<VW>(g, diag, x, y, z, p, [&](uint64_t q, double(&f)[VW]) { jac0<VW>(b, diag, q, N, v, omega, f); }, hx);
-  ldr<VW>(b, p, N, v, bc);
-#pragma unroll
-  for (int k = 0; k < VW; ++k) o[k] = bc[k] - hx[k];
-  str<VW>(out, p, N, v, o);
-}
-
-// Fine nodes and weights of coarse node I along one axis (4 at most); the
-// factor 1/2 of R = P^T / 2^d is applied per coarsened axis.
-__device__ __forceinline__ int restrict_taps(uint32_t I, uint32_t mf, uint32_t (&f)[4], double (&w)[4]) {
+// Fine nodes and weights of coarse node I along one axis: always four taps
+// (2I - 1, 2I, 2I + 1, 2I + 2 with weights 1/8, 3/8, 3/8, 1/8, the factor 1/2
+// of R = P^T / 2^d included), a missing node clamped into the grid with weight
+// zero; an axis that is not coarsened has the one tap I with weight 1.  The
+// fixed count lets every load of a gather be issued before the first is used.
+__device__ __forceinline__ void restrict_taps(uint32_t I, uint32_t mf, uint32_t (&f)[4], double (&w)[4]) {
   if (mf == 1) {
-    f[0] = I;
-    w[0] = 1.0;
-    return 1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f[t] = I;
+      w[t] = t == 1 ? 1.0 : 0.0;
+    }
+    return;
   }
-  int k = 0;
-  const int64_t c[4] = {2 * (int64_t)I - 1, 2 * (int64_t)I, 2 * (int64_t)I + 1, 2 * (int64_t)I + 2};
   const double cw[4] = {0.125, 0.375, 0.375, 0.125};
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-    if (c[t] >= 0 && c[t] < (int64_t)mf) {
-      f[k] = (uint32_t)c[t];
-      w[k] = cw[t];
-      ++k;
-    }
-  return k;
-}
-
-// coarse B = R T
-template <int VW>
-__global__ __launch_bounds__(MG_WG) void k_mg_restrict(const double* __restrict__ T, double* __restrict__ B,
-                                                      MgGeom fg, MgGeom cg, const int32_t* __restrict__ active,
-                                                      uint32_t N, uint32_t NV, uint64_t total) {
-  const uint64_t e = (uint64_t)xcd_remap(blockIdx.x, gridDim.x) * MG_WG + threadIdx.x;
-  if (e >= total) return;
-  const uint32_t v = (uint32_t)(e % NV);
-  const uint64_t P = e / NV;
-  if (!vec_active<VW>(active, v)) return;
-  const uint32_t I = (uint32_t)(P % cg.m0), J = (uint32_t)((P / cg.m0) % cg.m1),
-                 K = (uint32_t)(P / ((uint64_t)cg.m0 * cg.m1));
-  uint32_t fx[4], fy[4], fz[4];
-  double wx[4], wy[4], wz[4];
-  const int nx = restrict_taps(I, fg.m0, fx, wx), ny = restrict_taps(J, fg.m1, fy, wy),
-            nz = restrict_taps(K, fg.m2, fz, wz);
-  double acc[VW];
-#pragma unroll
-  for (int k = 0; k < VW; ++k) acc[k] = 0.0;
-  for (int c = 0; c < nz; ++c) {
-    double ay[VW];
-#pragma unroll
-    for (int k = 0; k < VW; ++k) ay[k] = 0.0;
-    for (int b = 0; b < ny; ++b) {
-      double ax[VW];
-#pragma unroll
-      for (int k = 0; k < VW; ++k) ax[k] = 0.0;
-      const uint64_t row = ((uint64_t)fz[c] * fg.m1 + fy[b]) * fg.m0;
-      for (int a = 0; a < nx; ++a) {
-        double t[VW];
-        ldr<VW>(T, row + fx[a], N, v, t);
-#pragma unroll
-        for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
-      }
-#pragma unroll
-      for (int k = 0; k < VW; ++k) ay[k] += wy[b] * ax[k];
-    }
-#pragma unroll
-    for (int k = 0; k < VW; ++k) acc[k] += wz[c] * ay[k];
+  for (int t = 0; t < 4; ++t) {
+    const int64_t c = 2 * (int64_t)I - 1 + t;
+    const bool in = c >= 0 && c < (int64_t)mf;
+    f[t] = in ? (uint32_t)c : (uint32_t)(2 * I);
+    w[t] = in ? cw[t] : 0.0;
   }
-  str<VW>(B, P, N, v, acc);
 }
 
 // coarsest level: E = A^{-1} B with the dense inverse (row-major nc x nc)
@@ -203,115 +130,127 @@ __global__ __launch_bounds__(MG_WG) void k_mg_dense(const double* __restrict__ A
 #pragma unroll
   for (int k = 0; k < VW; ++k) acc[k] = 0.0;
   const double* a = Ainv + (uint64_t)i * nc;
-  for (uint32_t j = 0; j < nc; ++j) {
+  // four running sums over j = 4 u + s (their loads are issued together), added in order
+  double part[4][VW];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) zero(part[s]);
+  uint32_t j = 0;
+  for (; j + 4 <= nc; j += 4) {
+    double t[4][VW];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ldr<VW>(B, j + s, N, v, t[s]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double w = a[j + s];
+#pragma unroll
+      for (int k = 0; k < VW; ++k) part[s][k] += w * t[s][k];
+    }
+  }
+  for (; j < nc; ++j) {
     double t[VW];
     ldr<VW>(B, j, N, v, t);
     const double w = a[j];
 #pragma unroll
-    for (int k = 0; k < VW; ++k) acc[k] += w * t[k];
+    for (int k = 0; k < VW; ++k) part[0][k] += w * t[k];
   }
+#pragma unroll
+  for (int k = 0; k < VW; ++k) acc[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
   str<VW>(E, i, N, v, acc);
 }
 
-// Coarse nodes and weights of fine node f along one axis (2 at most).
-__device__ __forceinline__ int prolong_taps(uint32_t f, uint32_t mf, uint32_t mc, uint32_t (&I)[2], double (&w)[2]) {
-  if (mf == 1) {
-    I[0] = f;
-    w[0] = 1.0;
-    return 1;
-  }
-  I[0] = f / 2;
-  w[0] = 0.75;
-  const int64_t J = (f % 2 == 0) ? (int64_t)(f / 2) - 1 : (int64_t)(f / 2) + 1;
-  if (J >= 0 && J < (int64_t)mc) {
-    I[1] = (uint32_t)J;
-    w[1] = 0.25;
-    return 2;
-  }
-  return 1;
+// z-march decomposition of a level: a work-group owns PL = 256 / NV
+// consecutive x nodes (thread t: vector t % NV of node t / NV) of one y row
+// over ZC consecutive z planes, keeping the field of the planes below, at and
+// above the current one in registers; work-groups are numbered x segment
+// fastest, then y, then z range, and spread XCD-contiguously, so one XCD
+// streams neighbouring rows of the same planes (their y neighbours hit L2).
+struct ZMarch {
+  uint32_t PL, nxs, nzc, ZC;
+};
+
+ZMarch zmarch_shape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV) {
+  ZMarch s;
+  s.PL = MG_WG / NV;
+  s.nxs = (m0 + s.PL - 1) / s.PL;
+  const uint64_t cols = (uint64_t)s.nxs * m1;
+  uint64_t nzc = (2048 + cols - 1) / cols;          // at least 2048 work-groups when the grid allows
+  if (nzc > m2) nzc = m2;
+  if (nzc < 1) nzc = 1;
+  s.ZC = (uint32_t)((m2 + nzc - 1) / nzc);
+  s.nzc = (m2 + s.ZC - 1) / s.ZC;
+  return s;
 }
 
-// T = x0 + P E (x0 = omega b / d), on the fine level of the pair
+struct ZPos {
+  uint32_t x, y, z0, z1, v;
+  bool ok;
+};
+
 template <int VW>
-__global__ __launch_bounds__(MG_WG) void k_mg_prolong(const double* __restrict__ b, const double* __restrict__ E,
-                                                     double* __restrict__ T, MgGeom fg, MgGeom cg,
-                                                     const double* __restrict__ diag, double omega,
-                                                     const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                     uint64_t total) {
-  const uint64_t e = (uint64_t)xcd_remap(blockIdx.x, gridDim.x) * MG_WG + threadIdx.x;
-  if (e >= total) return;
-  const uint32_t v = (uint32_t)(e % NV);
-  const uint64_t p = e / NV;
-  if (!vec_active<VW>(active, v)) return;
-  const uint32_t x = (uint32_t)(p % fg.m0), y = (uint32_t)((p / fg.m0) % fg.m1),
-                 z = (uint32_t)(p / ((uint64_t)fg.m0 * fg.m1));
-  uint32_t Ix[2], Iy[2], Iz[2];
-  double wx[2], wy[2], wz[2];
-  const int nx = prolong_taps(x, fg.m0, cg.m0, Ix, wx), ny = prolong_taps(y, fg.m1, cg.m1, Iy, wy),
-            nz = prolong_taps(z, fg.m2, cg.m2, Iz, wz);
-  double pe[VW];
-#pragma unroll
-  for (int k = 0; k < VW; ++k) pe[k] = 0.0;
-  for (int c = 0; c < nz; ++c) {
-    double ay[VW];
-#pragma unroll
-    for (int k = 0; k < VW; ++k) ay[k] = 0.0;
-    for (int bb = 0; bb < ny; ++bb) {
-      double ax[VW];
-#pragma unroll
-      for (int k = 0; k < VW; ++k) ax[k] = 0.0;
-      const uint64_t row = ((uint64_t)Iz[c] * cg.m1 + Iy[bb]) * cg.m0;
-      for (int a = 0; a < nx; ++a) {
-        double t[VW];
-        ldr<VW>(E, row + Ix[a], N, v, t);
-#pragma unroll
-        for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
-      }
-#pragma unroll
-      for (int k = 0; k < VW; ++k) ay[k] += wy[bb] * ax[k];
-    }
-#pragma unroll
-    for (int k = 0; k < VW; ++k) pe[k] += wz[c] * ay[k];
-  }
-  double x0[VW], o[VW];
-  jac0<VW>(b, diag, p, N, v, omega, x0);
-#pragma unroll
-  for (int k = 0; k < VW; ++k) o[k] = x0[k] + pe[k];
-  str<VW>(T, p, N, v, o);
+__device__ __forceinline__ ZPos zpos(const MgGeom& g, const ZMarch& zs, const int32_t* __restrict__ active,
+                                     uint32_t NV) {
+  ZPos q;
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t xs = L % zs.nxs, r = L / zs.nxs;
+  q.y = r % g.m1;
+  const uint32_t zc = r / g.m1;
+  const uint32_t t = threadIdx.x;
+  const bool lane_ok = t < zs.PL * NV;
+  q.v = lane_ok ? t % NV : 0;
+  q.x = xs * zs.PL + (lane_ok ? t / NV : 0);
+  q.z0 = zc * zs.ZC;
+  q.z1 = q.z0 + zs.ZC < g.m2 ? q.z0 + zs.ZC : g.m2;
+  q.ok = lane_ok && q.x < g.m0 && vec_active<VW>(active, q.v);
+  return q;
 }
 
-// z = x1 + omega (b - H x1) / d with x1 in T.  A work-group owns a contiguous
-// range of `ppw` points; thread t < PL NV (PL = 256 / NV point lanes) owns
-// vector t % NV of every PL-th point.  With DOTS, the work-group's sums of
-// b z and b b per column (point lanes added in order) form row blockIdx.x of
-// part (2N columns: r^T z, then r^T r).
-template <int VW, bool DOTS>
-__global__ __launch_bounds__(MG_WG) void k_mg_post(const double* __restrict__ b, const double* __restrict__ T,
-                                                  double* __restrict__ out, MgGeom g,
-                                                  const double* __restrict__ diag, double omega,
-                                                  const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                  uint64_t n, uint64_t ppw, double* __restrict__ part) {
-  const uint32_t PL = MG_WG / NV;
-  const uint32_t t = threadIdx.x;
-  const bool lane_ok = t < PL * NV;
-  const uint32_t v = lane_ok ? t % NV : 0, pl = lane_ok ? t / NV : 0;
-  const bool act = lane_ok && vec_active<VW>(active, v);
-  const uint64_t p0 = (uint64_t)blockIdx.x * ppw;
-  const uint64_t p1 = p0 + ppw < n ? p0 + ppw : n;
+// KIND 0 (pre-smoothing residual): field x0 = omega b / d, out = b - H x0.
+// KIND 1 (post-smoothing): field x1 = T, out = x1 + omega (b - H x1) / d; with
+// DOTS the work-group's per-column sums of b out and b b (point lanes added in
+// order) form row blockIdx.x of part (2N columns: r^T z, then r^T r).
+template <int VW, int KIND, bool DOTS>
+__global__ __launch_bounds__(MG_WG) void k_mg_zstencil(const double* __restrict__ b, const double* __restrict__ T,
+                                                      double* __restrict__ out, MgGeom g,
+                                                      const double* __restrict__ diag, const double* __restrict__ wd,
+                                                      const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
+                                                      ZMarch zs, double* __restrict__ part) {
+  const ZPos q = zpos<VW>(g, zs, active, NV);
   double srz[VW], srr[VW];
-#pragma unroll
-  for (int k = 0; k < VW; ++k) srz[k] = srr[k] = 0.0;
-  if (act) {
-    for (uint64_t p = p0 + pl; p < p1; p += PL) {
-      const uint32_t x = (uint32_t)(p % g.m0), y = (uint32_t)((p / g.m0) % g.m1),
-                     z = (uint32_t)(p / ((uint64_t)g.m0 * g.m1));
-      double hx[VW], bc[VW], xc[VW], o[VW];
-      stencil<VW>(g, diag, x, y, z, p, [&](uint64_t q, double(&f)[VW]) { ldr<VW>(T, q, N, v, f); }, hx);
+  zero(srz);
+  zero(srr);
+  if (q.ok) {
+    const uint32_t v = q.v;
+    const uint64_t s1 = g.m0, s2 = (uint64_t)g.m0 * g.m1;
+    auto field = [&](uint64_t at, double(&f)[VW]) {
+      if constexpr (KIND == 0) jac0<VW>(b, wd, at, N, v, f);
+      else ldr<VW>(T, at, N, v, f);
+    };
+    double fm[VW], fc[VW], fp[VW];
+    uint64_t p = ((uint64_t)q.z0 * g.m1 + q.y) * g.m0 + q.x;
+    zero(fm);
+    if (q.z0 > 0) field(p - s2, fm);
+    field(p, fc);
+    for (uint32_t z = q.z0; z < q.z1; ++z, p += s2) {
+      double xm[VW], xp[VW], ym[VW], yp[VW], bc[VW], o[VW];
+      zero(fp);
+      zero(xm);
+      zero(xp);
+      zero(ym);
+      zero(yp);
+      if (z + 1 < g.m2) field(p + s2, fp);
+      if (q.x > 0) field(p - 1, xm);
+      if (q.x + 1 < g.m0) field(p + 1, xp);
+      if (q.y > 0) field(p - s1, ym);
+      if (q.y + 1 < g.m1) field(p + s1, yp);
       ldr<VW>(b, p, N, v, bc);
-      ldr<VW>(T, p, N, v, xc);
       const double d = diag[p];
+      const double w = KIND == 0 ? 0.0 : wd[p];
 #pragma unroll
-      for (int k = 0; k < VW; ++k) o[k] = xc[k] + (omega * (bc[k] - hx[k])) / d;
+      for (int k = 0; k < VW; ++k) {
+        const double hx = d * fc[k] - (g.cx * (xm[k] + xp[k]) + g.cy * (ym[k] + yp[k]) + g.cz * (fm[k] + fp[k]));
+        if constexpr (KIND == 0) o[k] = bc[k] - hx;
+        else o[k] = fc[k] + w * (bc[k] - hx);
+      }
       str<VW>(out, p, N, v, o);
       if constexpr (DOTS) {
 #pragma unroll
@@ -320,10 +259,16 @@ __global__ __launch_bounds__(MG_WG) void k_mg_post(const double* __restrict__ b,
           srr[k] += bc[k] * bc[k];
         }
       }
+#pragma unroll
+      for (int k = 0; k < VW; ++k) {
+        fm[k] = fc[k];
+        fc[k] = fp[k];
+      }
     }
   }
   if constexpr (DOTS) {
-    __shared__ double red[2 * MG_WG * 2];
+    __shared__ double red[MG_WG * 2 * 2];
+    const uint32_t t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       red[(t * VW + k) * 2 + 0] = srz[k];
@@ -333,15 +278,172 @@ __global__ __launch_bounds__(MG_WG) void k_mg_post(const double* __restrict__ b,
     // thread c < N sums column c over the point lanes in order
     for (uint32_t c = t; c < N; c += MG_WG) {
       const uint32_t cv = c / VW, ck = c % VW;
-      double a = 0.0, bsum = 0.0;
-      for (uint32_t l = 0; l < PL; ++l) {
+      double a = 0.0, bs = 0.0;
+      for (uint32_t l = 0; l < zs.PL; ++l) {
         const uint32_t th = l * NV + cv;
         a += red[(th * VW + ck) * 2 + 0];
-        bsum += red[(th * VW + ck) * 2 + 1];
+        bs += red[(th * VW + ck) * 2 + 1];
       }
       part[(uint64_t)blockIdx.x * 2 * N + c] = a;
-      part[(uint64_t)blockIdx.x * 2 * N + N + c] = bsum;
+      part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
     }
+  }
+}
+
+// Coarse nodes and weights of fine node f along one axis: always two taps,
+// the parent f / 2 with 3/4 and the other neighbour (f / 2 - 1 for even f,
+// f / 2 + 1 for odd f) with 1/4, or weight zero (clamped to the parent) when
+// it is missing; an axis that is not coarsened has the tap f with weight 1.
+__device__ __forceinline__ void prolong_taps(uint32_t f, uint32_t mf, uint32_t mc, uint32_t (&I)[2], double (&w)[2]) {
+  if (mf == 1) {
+    I[0] = I[1] = f;
+    w[0] = 1.0;
+    w[1] = 0.0;
+    return;
+  }
+  I[0] = f / 2;
+  w[0] = 0.75;
+  const int64_t J = (f % 2 == 0) ? (int64_t)(f / 2) - 1 : (int64_t)(f / 2) + 1;
+  const bool in = J >= 0 && J < (int64_t)mc;
+  I[1] = in ? (uint32_t)J : f / 2;
+  w[1] = in ? 0.25 : 0.0;
+}
+
+// T = x0 + P E (x0 = omega b / d) on the fine level of the pair, z-marched:
+// the x-y interpolation of the coarse planes K0 - 1, K0, K0 + 1 around the
+// current fine plane's parent K0 stays in registers, so each coarse plane is
+// read once per fine column.
+template <int VW>
+__global__ __launch_bounds__(MG_WG) void k_mg_zprolong(const double* __restrict__ b, const double* __restrict__ E,
+                                                      double* __restrict__ T, MgGeom fg, MgGeom cg,
+                                                      const double* __restrict__ wd,
+                                                      const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
+                                                      ZMarch zs) {
+  const ZPos q = zpos<VW>(fg, zs, active, NV);
+  if (!q.ok) return;
+  const uint32_t v = q.v;
+  uint32_t Ix[2], Iy[2];
+  double wx[2], wy[2];
+  prolong_taps(q.x, fg.m0, cg.m0, Ix, wx);
+  prolong_taps(q.y, fg.m1, cg.m1, Iy, wy);
+  auto cxy = [&](uint32_t K, double(&o)[VW]) {
+    zero(o);
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      double ax[VW];
+      zero(ax);
+      const uint64_t row = ((uint64_t)K * cg.m1 + Iy[bb]) * cg.m0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        double t[VW];
+        ldr<VW>(E, row + Ix[a], N, v, t);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
+      }
+#pragma unroll
+      for (int k = 0; k < VW; ++k) o[k] += wy[bb] * ax[k];
+    }
+  };
+  const uint64_t s2 = (uint64_t)fg.m0 * fg.m1;
+  uint64_t p = ((uint64_t)q.z0 * fg.m1 + q.y) * fg.m0 + q.x;
+  if (fg.m2 == 1) {                 // no z axis: one plane, coarse plane 0
+    double pe[VW], x0[VW], o[VW];
+    cxy(0, pe);
+    jac0<VW>(b, wd, p, N, v, x0);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) o[k] = x0[k] + pe[k];
+    str<VW>(T, p, N, v, o);
+    return;
+  }
+  uint32_t K0 = q.z0 / 2;
+  double lo[VW], mid[VW], hi[VW];
+  zero(lo);
+  zero(hi);
+  cxy(K0, mid);
+  if (K0 >= 1) cxy(K0 - 1, lo);
+  if (K0 + 1 < cg.m2) cxy(K0 + 1, hi);
+  for (uint32_t z = q.z0; z < q.z1; ++z, p += s2) {
+    if (z > q.z0 && z % 2 == 0) {   // next parent plane
+      K0 = z / 2;
+#pragma unroll
+      for (int k = 0; k < VW; ++k) {
+        lo[k] = mid[k];
+        mid[k] = hi[k];
+      }
+      zero(hi);
+      if (K0 + 1 < cg.m2) cxy(K0 + 1, hi);
+    }
+    double x0[VW], o[VW];
+    jac0<VW>(b, wd, p, N, v, x0);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      const double pe = 0.75 * mid[k] + 0.25 * (z % 2 == 0 ? lo[k] : hi[k]);
+      o[k] = x0[k] + pe;
+    }
+    str<VW>(T, p, N, v, o);
+  }
+}
+
+// coarse B = R T, z-marched over the coarse planes of a coarse (I, J) column:
+// the x-y restriction of each fine plane is formed once and added to the two
+// coarse planes it feeds.
+template <int VW>
+__global__ __launch_bounds__(MG_WG) void k_mg_zrestrict(const double* __restrict__ T, double* __restrict__ B,
+                                                       MgGeom fg, MgGeom cg, const int32_t* __restrict__ active,
+                                                       uint32_t N, uint32_t NV, ZMarch zs) {
+  const ZPos q = zpos<VW>(cg, zs, active, NV);
+  if (!q.ok) return;
+  const uint32_t v = q.v;
+  uint32_t fx[4], fy[4];
+  double wx[4], wy[4];
+  restrict_taps(q.x, fg.m0, fx, wx);
+  restrict_taps(q.y, fg.m1, fy, wy);
+  auto rxy = [&](uint32_t z, double(&o)[VW]) {
+    zero(o);
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      double ax[VW];
+      zero(ax);
+      const uint64_t row = ((uint64_t)z * fg.m1 + fy[bb]) * fg.m0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double t[VW];
+        ldr<VW>(T, row + fx[a], N, v, t);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
+      }
+#pragma unroll
+      for (int k = 0; k < VW; ++k) o[k] += wy[bb] * ax[k];
+    }
+  };
+  const uint64_t cs2 = (uint64_t)cg.m0 * cg.m1;
+  uint64_t P = ((uint64_t)q.z0 * cg.m1 + q.y) * cg.m0 + q.x;
+  if (fg.m2 == 1) {                 // no z axis
+    double o[VW];
+    rxy(0, o);
+    str<VW>(B, P, N, v, o);
+    return;
+  }
+  // fine planes 2K - 1, 2K, 2K + 1, 2K + 2 with weights 1/8, 3/8, 3/8, 1/8;
+  // the last two are the first two of coarse plane K + 1
+  double ra[VW], rb[VW];
+  zero(ra);
+  zero(rb);
+  if (q.z0 >= 1) rxy(2 * q.z0 - 1, ra);
+  rxy(2 * q.z0, rb);
+  for (uint32_t K = q.z0; K < q.z1; ++K, P += cs2) {
+    double rc[VW], rd[VW], o[VW];
+    zero(rc);
+    zero(rd);
+    if (2 * K + 1 < fg.m2) rxy(2 * K + 1, rc);
+    if (2 * K + 2 < fg.m2) rxy(2 * K + 2, rd);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      o[k] = 0.125 * ra[k] + 0.375 * rb[k] + 0.375 * rc[k] + 0.125 * rd[k];
+      ra[k] = rc[k];
+      rb[k] = rd[k];
+    }
+    str<VW>(B, P, N, v, o);
   }
 }
 
@@ -420,8 +522,10 @@ bool spd_inverse(std::vector<double>& A, int n) {
 }  // namespace
 
 void mg_free(ope_ctx* c) {
-  for (int k = 1; k < c->mg_levels; ++k)
-    if (c->mg[k].diag) (void)hipFree(c->mg[k].diag);
+  for (int k = 0; k < c->mg_levels; ++k) {
+    if (k > 0 && c->mg[k].diag) (void)hipFree(c->mg[k].diag);
+    if (c->mg[k].wd) (void)hipFree(c->mg[k].wd);
+  }
   if (c->mg_mem) (void)hipFree(c->mg_mem);
   if (c->mg_inv) (void)hipFree(c->mg_inv);
   if (c->mg_part) (void)hipFree(c->mg_part);
@@ -442,9 +546,10 @@ ope_status mg_build(ope_ctx* c) {
   // level 0: the operator; its potential W = diag - 2 (cx + cy + cz)
   std::vector<double> W((size_t)c->n);
   if (hipMemcpy(W.data(), c->diag, sizeof(double) * c->n, hipMemcpyDeviceToHost) != hipSuccess) return OPE_EHIP;
+  std::vector<std::vector<double>> diags;       // the diagonal of every level (level 0: the context's)
+  diags.push_back(W);
   const double dsum0 = 2.0 * (c->g.cx + c->g.cy + c->g.cz);
   for (auto& w : W) w -= dsum0;
-  std::vector<std::vector<double>> diags;
   MgLevel L0{};
   L0.m0 = c->g.m0;
   L0.m1 = c->g.m1;
@@ -500,7 +605,7 @@ ope_status mg_build(ope_ctx* c) {
   const MgLevel& cl = lv[nl - 1];
   const int nc = (int)cl.n;
   std::vector<double> A((size_t)nc * nc, 0.0);
-  const std::vector<double>& dc = diags.back();
+  const std::vector<double>& dc = diags[(size_t)nl - 1];
   for (uint32_t z = 0; z < cl.m2; ++z)
     for (uint32_t y = 0; y < cl.m1; ++y)
       for (uint32_t x = 0; x < cl.m0; ++x) {
@@ -517,12 +622,17 @@ ope_status mg_build(ope_ctx* c) {
   // device memory: level diagonals, blocks (level 0: T and Z; others: B, E, T)
   int64_t elems = 2 * c->n * N;
   for (int k = 1; k < nl; ++k) elems += 3 * lv[k].n * N;
-  c->mg_rows = std::min<int64_t>(MG_POST_WGS, (c->n + 3) / 4);
+  {
+    const uint32_t NV = (uint32_t)(N % 2 == 0 ? N / 2 : N);
+    const ZMarch zs = zmarch_shape(lv[0].m0, lv[0].m1, lv[0].m2, NV);
+    c->mg_rows = (int64_t)zs.nxs * lv[0].m1 * zs.nzc;      // partial rows of the level-0 post-smoothing
+  }
   bool ok = hipMalloc(&c->mg_mem, sizeof(double) * (size_t)elems) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_inv, sizeof(double) * (size_t)nc * nc) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_part, sizeof(double) * (size_t)c->mg_rows * 2 * N) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_dots, sizeof(double) * 2 * (size_t)N) == hipSuccess;
   for (int k = 1; k < nl && ok; ++k) ok = hipMalloc((void**)&lv[k].diag, sizeof(double) * lv[k].n) == hipSuccess;
+  for (int k = 0; k < nl && ok; ++k) ok = hipMalloc((void**)&lv[k].wd, sizeof(double) * lv[k].n) == hipSuccess;
   c->mg_levels = nl;
   for (int k = 0; k < nl; ++k) c->mg[k] = lv[k];
   if (!ok) {
@@ -544,8 +654,13 @@ ope_status mg_build(ope_ctx* c) {
   }
   ok = hipMemcpy(c->mg_inv, A.data(), sizeof(double) * (size_t)nc * nc, hipMemcpyHostToDevice) == hipSuccess;
   for (int k = 1; k < nl && ok; ++k)
-    ok = hipMemcpy(c->mg[k].diag, diags[(size_t)k - 1].data(), sizeof(double) * c->mg[k].n,
-                   hipMemcpyHostToDevice) == hipSuccess;
+    ok = hipMemcpy(c->mg[k].diag, diags[(size_t)k].data(), sizeof(double) * c->mg[k].n, hipMemcpyHostToDevice) ==
+         hipSuccess;
+  for (int k = 0; k < nl && ok; ++k) {
+    std::vector<double> w(diags[(size_t)k].size());
+    for (size_t p = 0; p < w.size(); ++p) w[p] = MG_OMEGA / diags[(size_t)k][p];
+    ok = hipMemcpy(c->mg[k].wd, w.data(), sizeof(double) * c->mg[k].n, hipMemcpyHostToDevice) == hipSuccess;
+  }
   if (!ok) {
     mg_free(c);
     return OPE_EHIP;
@@ -562,11 +677,12 @@ static hipError_t vcycle_t(ope_ctx* c, const double* r, double* z, const int32_t
     const MgLevel& f = c->mg[k];
     const MgLevel& q = c->mg[k + 1];
     const double* in = k == 0 ? r : f.B;
-    const uint64_t tf = (uint64_t)f.n * NV, tc = (uint64_t)q.n * NV;
-    hipLaunchKernelGGL(k_mg_res<VW>, dim3(grid_of(tf)), dim3(MG_WG), 0, s, in, f.T, geom(f), f.diag, MG_OMEGA, active,
-                       N, NV, tf);
-    hipLaunchKernelGGL(k_mg_restrict<VW>, dim3(grid_of(tc)), dim3(MG_WG), 0, s, f.T, q.B, geom(f), geom(q), active, N,
-                       NV, tc);
+    const ZMarch zs = zmarch_shape(f.m0, f.m1, f.m2, NV);
+    const ZMarch zq = zmarch_shape(q.m0, q.m1, q.m2, NV);
+    hipLaunchKernelGGL((k_mg_zstencil<VW, 0, false>), dim3(zs.nxs * f.m1 * zs.nzc), dim3(MG_WG), 0, s, in,
+                       (const double*)nullptr, f.T, geom(f), f.diag, f.wd, active, N, NV, zs, (double*)nullptr);
+    hipLaunchKernelGGL(k_mg_zrestrict<VW>, dim3(zq.nxs * q.m1 * zq.nzc), dim3(MG_WG), 0, s, f.T, q.B, geom(f),
+                       geom(q), active, N, NV, zq);
   }
   const MgLevel& cl = c->mg[L - 1];
   const uint64_t tcl = (uint64_t)cl.n * NV;
@@ -577,22 +693,18 @@ static hipError_t vcycle_t(ope_ctx* c, const double* r, double* z, const int32_t
     const MgLevel& q = c->mg[k + 1];
     const double* in = k == 0 ? r : f.B;
     double* out = k == 0 ? z : f.E;
-    const uint64_t tf = (uint64_t)f.n * NV;
-    hipLaunchKernelGGL(k_mg_prolong<VW>, dim3(grid_of(tf)), dim3(MG_WG), 0, s, in, q.E, f.T, geom(f), geom(q), f.diag,
-                       MG_OMEGA, active, N, NV, tf);
-    const uint32_t PL = MG_WG / NV;
-    const uint64_t wgs = k == 0 ? (uint64_t)c->mg_rows : std::min<uint64_t>(4096, (f.n + PL - 1) / PL);
-    uint64_t ppw = (f.n + wgs - 1) / wgs;
-    ppw = (ppw + PL - 1) / PL * PL;
-    const uint32_t grid = (uint32_t)((f.n + ppw - 1) / ppw);
+    const ZMarch zs = zmarch_shape(f.m0, f.m1, f.m2, NV);
+    const uint32_t grid = zs.nxs * f.m1 * zs.nzc;
+    hipLaunchKernelGGL(k_mg_zprolong<VW>, dim3(grid), dim3(MG_WG), 0, s, in, q.E, f.T, geom(f), geom(q), f.wd,
+                       active, N, NV, zs);
     if (k == 0 && dots) {
-      // rows past the last used work-group stay zero
-      hipLaunchKernelGGL((k_mg_post<VW, true>), dim3(grid), dim3(MG_WG), 0, s, in, f.T, out, geom(f), f.diag, MG_OMEGA,
-                         active, N, NV, (uint64_t)f.n, ppw, c->mg_part);
+      ProfScope ps(c, OPE_KERNEL_MG_POST);
+      hipLaunchKernelGGL((k_mg_zstencil<VW, 1, true>), dim3(grid), dim3(MG_WG), 0, s, in, (const double*)f.T, out,
+                         geom(f), f.diag, f.wd, active, N, NV, zs, c->mg_part);
       c->mg_rows_used = grid;
     } else {
-      hipLaunchKernelGGL((k_mg_post<VW, false>), dim3(grid), dim3(MG_WG), 0, s, in, f.T, out, geom(f), f.diag,
-                         MG_OMEGA, active, N, NV, (uint64_t)f.n, ppw, nullptr);
+      hipLaunchKernelGGL((k_mg_zstencil<VW, 1, false>), dim3(grid), dim3(MG_WG), 0, s, in, (const double*)f.T, out,
+                         geom(f), f.diag, f.wd, active, N, NV, zs, (double*)nullptr);
     }
   }
   return hipGetLastError();

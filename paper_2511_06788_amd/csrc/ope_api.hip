@@ -1440,6 +1440,7 @@ ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
   drop_graphs(c);               // the captured CG chunks hold the other iteration
   if (!enable) {
     mg_free(c);
+    c->check_every = 4;
     return OPE_OK;
   }
   if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
@@ -1447,6 +1448,9 @@ ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
   const ope_status st = mg_build(c);
   if (st != OPE_OK) return st;
   c->mg_on = 1;
+  // a preconditioned Step 1 converges in a few iterations: check every two,
+  // so that fewer iterations run past convergence
+  c->check_every = 2;
   return OPE_OK;
 }
 

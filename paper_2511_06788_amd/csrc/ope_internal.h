@@ -87,6 +87,7 @@ struct MgLevel {
   double cx, cy, cz;            // kinetic / h_a^2 on this level (0 for absent axes)
   int64_t n;
   double* diag;                 // diagonal of H on this level (level 0: the context's)
+  double* wd;                   // omega / diag (the damped Jacobi factor)
   double *B, *E, *T;            // right-hand side, correction, scratch (n x N each; level 0: T only)
 };
 

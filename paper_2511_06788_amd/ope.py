@@ -107,6 +107,7 @@ OPE_KERNEL_SMALL = 5
 OPE_KERNEL_CG_SWEEP_B_Y = 6
 OPE_KERNEL_CG_REDUCE = 7
 OPE_KERNEL_MG = 8
+OPE_KERNEL_MG_POST = 9
 
 _lib = None
 

@@ -6,13 +6,15 @@ cube plus 8 seeded Gaussian wells (seed 0), N = 128 lowest pairs, plain FP64,
 fixed tau = 45 (0.9 of the stability limit 2 / (1/lambda_1 - 1/lambda_max)),
 start block a seeded Gaussian orthonormalised by QR.  One benchmark step is one
 full step of scheme (4.1) (Section 4.1, Steps 1-4) with every row of the hot
-path: stencil, Grams, energy/residual reductions, warm-started CG for Step 1,
-the FP64 small solve and the in-place update.  Inputs are resident in HBM
-before the timed region starts.
+path: stencil, Grams, energy/residual reductions, warm-started CG for Step 1
+(in the headline preconditioned by one multigrid V-cycle per iteration; the
+plain CG step is measured beside it), the FP64 small solve and the in-place
+update.  Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line: outer steps per second (whole job, one GPU), the live
-roofline of the dominant kernel (CG sweep B, timed with HIP events on the
-library's stream), per-kernel timings, the mixed-precision and learned forms'
+roofline of the dominant kernel (the finest post-smoothing of the V-cycle;
+CG sweep B for the plain CG step; timed with HIP events on the library's
+stream), per-kernel timings, the mixed-precision and learned forms'
 steps per second on the same workload, measured time-to-residual-1e-8 (plain
 FP64; mixed precision to 1e-4 then FP64; learned steps judged by the plain
 step) on problems that converge within the run (64^3 and 96^3 grids, N = 17,
@@ -256,10 +258,26 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
                              "final_residual": sl.residual, "final_drift": sl.drift,
                              "ritz_max_rel_error_vs_reference": ritz_error(ritz_learned, ref)}
     out["speedup_learned"] = t_plain / t_learned
+    # the plain FP64 form with the multigrid-preconditioned Step 1
+    with ope.Context(p.grid, p.V, p.N) as cg:
+        ope.ope_set_multigrid(cg.handle, True)
+        ope.ope_solve(cg.handle, torch.from_numpy(p.U0).to("cuda"), tau, tol, 3)
+        U = torch.from_numpy(p.U0).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sg = ope.ope_solve(cg.handle, U, tau, tol, 20000)
+        torch.cuda.synchronize()
+        t_mg = time.perf_counter() - t0
+        ritz_mg = ope.ope_residual(cg.handle, U, p.N)[1]
+    out["plain_fp64_multigrid"] = {"converged": bool(sg.converged), "steps": int(sg.steps), "seconds": t_mg,
+                                   "inner_iterations": int(sg.inner_iterations),
+                                   "final_residual": sg.residual, "final_drift": sg.drift,
+                                   "ritz_max_rel_error_vs_reference": ritz_error(ritz_mg, ref)}
+    out["speedup_multigrid"] = t_plain / t_mg
     return out
 
 
-def extrapolated_time_to_residual(ope, torch, p, tau, tol=1e-8, run=200, late=20):
+def extrapolated_time_to_residual(ope, torch, p, tau, tol=1e-8, run=200, late=20, multigrid=True):
     """EXTRAPOLATION (not a measurement) of Algorithm 1's time to residual `tol`
     at 64^3, N = 128: `run` steps from the start block are timed, then `late`
     more give the per-step cost of the slow phase; the remaining steps follow
@@ -270,6 +288,8 @@ def extrapolated_time_to_residual(ope, torch, p, tau, tol=1e-8, run=200, late=20
     lam = reference_eigenvalues(f"wells3d_{p.grid.m[0]}^3_seed0", p.N + 1)
     rho = 1.0 - tau * (1.0 / lam[p.N - 1] - 1.0 / lam[p.N])
     with ope.Context(p.grid, p.V, p.N) as ctx:
+        if multigrid:
+            ope.ope_set_multigrid(ctx.handle, True)
         U = torch.from_numpy(p.U0).to("cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -290,6 +310,7 @@ def extrapolated_time_to_residual(ope, torch, p, tau, tol=1e-8, run=200, late=20
     seconds = t_run + t_late + more * ms_late * 1e-3
     return {"label": "EXTRAPOLATED from measured step costs and the linearised rate, not measured",
             "workload": f"wells3d_{p.grid.m[0]}^3_N{p.N}_seed0", "tau": tau, "res_tol": tol,
+            "inner": "multigrid-preconditioned CG" if multigrid else "CG",
             "lambda_N": float(lam[p.N - 1]), "lambda_N_plus_1": float(lam[p.N]), "rho": rho,
             "measured_steps": run + late, "measured_seconds": t_run + t_late,
             "residual_after_measured_steps": res_b,
@@ -910,6 +931,8 @@ def main():
         out["time_to_residual_96"] = time_to_residual(ope, torch, m=96)
         log("extrapolated time to residual 1e-8 at 64^3, N=128")
         out["time_to_residual_64_N128_extrapolated"] = extrapolated_time_to_residual(ope, torch, p, args.tau)
+        out["time_to_residual_64_N128_extrapolated_plain_cg"] = extrapolated_time_to_residual(
+            ope, torch, p, args.tau, run=60, multigrid=False)
         log("Algorithm 1 energy stops and the adaptive step (64^3, N=17)")
         out["algorithm1_energy_stops"] = algorithm1_energy_stops(ope, torch)
         log("Table 1 on the finite-difference oscillator")

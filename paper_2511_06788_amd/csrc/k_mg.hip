@@ -15,11 +15,11 @@
 // (omega = 0.8) once on each side of the coarse correction:
 //   x0 = omega b / d;  r1 = b - H x0;  e = B_{k+1}(R r1);  x1 = x0 + P e;
 //   z = x1 + omega (b - H x1) / d.
-// Kernels, per level: k_mg_zstencil<0> (r1, one stencil over x0 formed on the
+// Kernels, per level: k_mg_tstencil<0> (r1, one stencil over x0 formed on the
 // fly from b), k_mg_zrestrict (R r1), k_mg_dense (coarsest), k_mg_zprolong
-// (x1 = x0 + P e), k_mg_zstencil<1> (z, one stencil over x1; on level 0 also
+// (x1 = x0 + P e), k_mg_tstencil<1> (z, one stencil over x1; on level 0 also
 // the per-column partial sums of r^T z and r^T r that the PCG needs).  The
-// stencil and transfer kernels march along z (see zmarch_shape); the
+// stencil and transfer kernels march along z (see zmarch_shape, tshape); the
 // smoother's factors omega / d are precomputed per level.
 // Layout: every block is n x N row-major (a grid point's N values
 // contiguous), x fastest, as everywhere in the library; a thread owns one
@@ -206,50 +206,126 @@ __device__ __forceinline__ ZPos zpos(const MgGeom& g, const ZMarch& zs, const in
 
 // KIND 0 (pre-smoothing residual): field x0 = omega b / d, out = b - H x0.
 // KIND 1 (post-smoothing): field x1 = T, out = x1 + omega (b - H x1) / d; with
-// DOTS the work-group's per-column sums of b out and b b (point lanes added in
-// order) form row blockIdx.x of part (2N columns: r^T z, then r^T r).
+// DOTS the work-group's per-column sums of b out and b b (the tile's columns
+// added in order) form row blockIdx.x of part (2N columns: r^T z, then r^T r).
+// x-y tiled form of the stencil sweeps: a work-group of TX TY NV threads owns
+// a TX x TY tile of grid columns (thread t: vector t % NV of column t / NV)
+// over ZC planes.  At each plane the tile's field values and those of the
+// one-column ring around it go to LDS, so the x and y neighbours come from
+// LDS (each ring value is loaded once per work-group instead of by every
+// neighbouring thread), and the z neighbours stay in registers.
+struct TShape {
+  uint32_t TX, TY, nxt, nyt, nzc, ZC;
+};
+
+constexpr uint32_t MG_TWG = 1024;                 // threads of a tiled work-group (at most)
+constexpr uint32_t MG_TLDS = 8192;                // LDS tile capacity in doubles (64 KiB)
+
+TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N) {
+  TShape s;
+  const uint32_t P = MG_TWG / NV;                 // columns per work-group
+  uint32_t tx = 1;
+  while ((tx * 2) * (tx * 2) <= P) tx *= 2;       // a square tile of powers of two, x side first
+  if (tx * tx * 2 <= P) tx *= 2;
+  s.TX = std::min(tx, m0);
+  s.TY = std::max(1u, std::min(P / s.TX, m1));
+  while ((s.TX + 2) * (s.TY + 2) * N > MG_TLDS && s.TY > 1) --s.TY;
+  s.nxt = (m0 + s.TX - 1) / s.TX;
+  s.nyt = (m1 + s.TY - 1) / s.TY;
+  const uint64_t tiles = (uint64_t)s.nxt * s.nyt;
+  uint64_t nzc = (512 + tiles - 1) / tiles;       // at least 512 work-groups when the grid allows
+  if (nzc > m2) nzc = m2;
+  if (nzc < 1) nzc = 1;
+  s.ZC = (uint32_t)((m2 + nzc - 1) / nzc);
+  s.nzc = (m2 + s.ZC - 1) / s.ZC;
+  return s;
+}
+
 template <int VW, int KIND, bool DOTS>
-__global__ __launch_bounds__(MG_WG) void k_mg_zstencil(const double* __restrict__ b, const double* __restrict__ T,
-                                                      double* __restrict__ out, MgGeom g,
-                                                      const double* __restrict__ diag, const double* __restrict__ wd,
-                                                      const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                      ZMarch zs, double* __restrict__ part) {
-  const ZPos q = zpos<VW>(g, zs, active, NV);
+__global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict__ b, const double* __restrict__ T,
+                                                       double* __restrict__ out, MgGeom g,
+                                                       const double* __restrict__ diag, const double* __restrict__ wd,
+                                                       const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
+                                                       TShape ts, double* __restrict__ part) {
+  __shared__ __align__(16) double tile[MG_TLDS];
+  const uint32_t t = threadIdx.x;
+  const uint32_t v = t % NV, pt = t / NV;
+  const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t xt = L % ts.nxt, r = L / ts.nxt;
+  const uint32_t yt = r % ts.nyt, zc = r / ts.nyt;
+  const uint32_t x0 = xt * ts.TX, y0 = yt * ts.TY;
+  const uint32_t x = x0 + tx, y = y0 + ty;
+  const bool inb = x < g.m0 && y < g.m1;
+  const bool act = vec_active<VW>(active, v);
+  const bool own = inb && act;
+  const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
+  const uint64_t s2 = (uint64_t)g.m0 * g.m1;
+  const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
+  auto field = [&](uint64_t at, double(&f)[VW]) {
+    if constexpr (KIND == 0) jac0<VW>(b, wd, at, N, v, f);
+    else ldr<VW>(T, at, N, v, f);
+  };
+  // LDS slot of tile-local column (cx, cy) (ring included: cx, cy in [0, W) x [0, TY + 2))
+  auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NV + v) * VW; };
+  double fm[VW], fc[VW], fp[VW];
+  zero(fm);
+  zero(fc);
+  uint64_t p = ((uint64_t)z0 * g.m1 + (inb ? y : 0)) * g.m0 + (inb ? x : 0);
+  if (own) {
+    if (z0 > 0) field(p - s2, fm);
+    field(p, fc);
+  }
   double srz[VW], srr[VW];
   zero(srz);
   zero(srr);
-  if (q.ok) {
-    const uint32_t v = q.v;
-    const uint64_t s1 = g.m0, s2 = (uint64_t)g.m0 * g.m1;
-    auto field = [&](uint64_t at, double(&f)[VW]) {
-      if constexpr (KIND == 0) jac0<VW>(b, wd, at, N, v, f);
-      else ldr<VW>(T, at, N, v, f);
-    };
-    double fm[VW], fc[VW], fp[VW];
-    uint64_t p = ((uint64_t)q.z0 * g.m1 + q.y) * g.m0 + q.x;
-    zero(fm);
-    if (q.z0 > 0) field(p - s2, fm);
-    field(p, fc);
-    for (uint32_t z = q.z0; z < q.z1; ++z, p += s2) {
-      double xm[VW], xp[VW], ym[VW], yp[VW], bc[VW], o[VW];
-      zero(fp);
-      zero(xm);
-      zero(xp);
-      zero(ym);
-      zero(yp);
+  for (uint32_t z = z0; z < z1; ++z, p += s2) {
+    // the tile's own values, then the ring (column k of the ring: bottom row,
+    // top row, left column, right column), zero outside the grid
+#pragma unroll
+    for (int k = 0; k < VW; ++k) tile[slot(tx + 1, ty + 1) + k] = fc[k];
+    for (uint32_t k = pt; k < RING; k += P) {
+      int64_t hx, hy;
+      uint32_t cx, cy;
+      if (k < ts.TX) {
+        hx = (int64_t)x0 + k; hy = (int64_t)y0 - 1; cx = k + 1; cy = 0;
+      } else if (k < 2 * ts.TX) {
+        hx = (int64_t)x0 + (k - ts.TX); hy = (int64_t)y0 + ts.TY; cx = k - ts.TX + 1; cy = ts.TY + 1;
+      } else if (k < 2 * ts.TX + ts.TY) {
+        hx = (int64_t)x0 - 1; hy = (int64_t)y0 + (k - 2 * ts.TX); cx = 0; cy = k - 2 * ts.TX + 1;
+      } else {
+        hx = (int64_t)x0 + ts.TX; hy = (int64_t)y0 + (k - 2 * ts.TX - ts.TY); cx = ts.TX + 1;
+        cy = k - 2 * ts.TX - ts.TY + 1;
+      }
+      double hv[VW];
+      zero(hv);
+      if (act && hx >= 0 && hx < (int64_t)g.m0 && hy >= 0 && hy < (int64_t)g.m1)
+        field(((uint64_t)z * g.m1 + (uint64_t)hy) * g.m0 + (uint64_t)hx, hv);
+#pragma unroll
+      for (int kk = 0; kk < VW; ++kk) tile[slot(cx, cy) + kk] = hv[kk];
+    }
+    // the next plane's own value and the centre data, loaded before the wait
+    zero(fp);
+    double bc[VW];
+    zero(bc);
+    double d = 0.0, w = 0.0;
+    if (own) {
       if (z + 1 < g.m2) field(p + s2, fp);
-      if (q.x > 0) field(p - 1, xm);
-      if (q.x + 1 < g.m0) field(p + 1, xp);
-      if (q.y > 0) field(p - s1, ym);
-      if (q.y + 1 < g.m1) field(p + s1, yp);
       ldr<VW>(b, p, N, v, bc);
-      const double d = diag[p];
-      const double w = KIND == 0 ? 0.0 : wd[p];
+      d = diag[p];
+      if constexpr (KIND == 1) w = wd[p];
+    }
+    __syncthreads();
+    if (own) {
+      double o[VW];
+      const uint32_t sxm = slot(tx, ty + 1), sxp = slot(tx + 2, ty + 1), sym = slot(tx + 1, ty),
+                     syp = slot(tx + 1, ty + 2);
 #pragma unroll
       for (int k = 0; k < VW; ++k) {
-        const double hx = d * fc[k] - (g.cx * (xm[k] + xp[k]) + g.cy * (ym[k] + yp[k]) + g.cz * (fm[k] + fp[k]));
-        if constexpr (KIND == 0) o[k] = bc[k] - hx;
-        else o[k] = fc[k] + w * (bc[k] - hx);
+        const double hxv = d * fc[k] - (g.cx * (tile[sxm + k] + tile[sxp + k]) + g.cy * (tile[sym + k] + tile[syp + k]) +
+                                        g.cz * (fm[k] + fp[k]));
+        if constexpr (KIND == 0) o[k] = bc[k] - hxv;
+        else o[k] = fc[k] + w * (bc[k] - hxv);
       }
       str<VW>(out, p, N, v, o);
       if constexpr (DOTS) {
@@ -259,30 +335,29 @@ __global__ __launch_bounds__(MG_WG) void k_mg_zstencil(const double* __restrict_
           srr[k] += bc[k] * bc[k];
         }
       }
+    }
+    __syncthreads();
 #pragma unroll
-      for (int k = 0; k < VW; ++k) {
-        fm[k] = fc[k];
-        fc[k] = fp[k];
-      }
+    for (int k = 0; k < VW; ++k) {
+      fm[k] = fc[k];
+      fc[k] = fp[k];
     }
   }
   if constexpr (DOTS) {
-    __shared__ double red[MG_WG * 2 * 2];
-    const uint32_t t = threadIdx.x;
+    // per-column sums over the tile's columns in order (LDS reused)
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
-      red[(t * VW + k) * 2 + 0] = srz[k];
-      red[(t * VW + k) * 2 + 1] = srr[k];
+      tile[(t * VW + k) * 2 + 0] = srz[k];
+      tile[(t * VW + k) * 2 + 1] = srr[k];
     }
     __syncthreads();
-    // thread c < N sums column c over the point lanes in order
-    for (uint32_t c = t; c < N; c += MG_WG) {
+    for (uint32_t c = t; c < N; c += blockDim.x) {
       const uint32_t cv = c / VW, ck = c % VW;
       double a = 0.0, bs = 0.0;
-      for (uint32_t l = 0; l < zs.PL; ++l) {
+      for (uint32_t l = 0; l < P; ++l) {
         const uint32_t th = l * NV + cv;
-        a += red[(th * VW + ck) * 2 + 0];
-        bs += red[(th * VW + ck) * 2 + 1];
+        a += tile[(th * VW + ck) * 2 + 0];
+        bs += tile[(th * VW + ck) * 2 + 1];
       }
       part[(uint64_t)blockIdx.x * 2 * N + c] = a;
       part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
@@ -624,8 +699,8 @@ ope_status mg_build(ope_ctx* c) {
   for (int k = 1; k < nl; ++k) elems += 3 * lv[k].n * N;
   {
     const uint32_t NV = (uint32_t)(N % 2 == 0 ? N / 2 : N);
-    const ZMarch zs = zmarch_shape(lv[0].m0, lv[0].m1, lv[0].m2, NV);
-    c->mg_rows = (int64_t)zs.nxs * lv[0].m1 * zs.nzc;      // partial rows of the level-0 post-smoothing
+    const TShape ts = tshape(lv[0].m0, lv[0].m1, lv[0].m2, NV, (uint32_t)N);
+    c->mg_rows = (int64_t)ts.nxt * ts.nyt * ts.nzc;        // partial rows of the level-0 post-smoothing
   }
   bool ok = hipMalloc(&c->mg_mem, sizeof(double) * (size_t)elems) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_inv, sizeof(double) * (size_t)nc * nc) == hipSuccess;
@@ -677,10 +752,10 @@ static hipError_t vcycle_t(ope_ctx* c, const double* r, double* z, const int32_t
     const MgLevel& f = c->mg[k];
     const MgLevel& q = c->mg[k + 1];
     const double* in = k == 0 ? r : f.B;
-    const ZMarch zs = zmarch_shape(f.m0, f.m1, f.m2, NV);
+    const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N);
     const ZMarch zq = zmarch_shape(q.m0, q.m1, q.m2, NV);
-    hipLaunchKernelGGL((k_mg_zstencil<VW, 0, false>), dim3(zs.nxs * f.m1 * zs.nzc), dim3(MG_WG), 0, s, in,
-                       (const double*)nullptr, f.T, geom(f), f.diag, f.wd, active, N, NV, zs, (double*)nullptr);
+    hipLaunchKernelGGL((k_mg_tstencil<VW, 0, false>), dim3(ts.nxt * ts.nyt * ts.nzc), dim3(ts.TX * ts.TY * NV), 0, s,
+                       in, (const double*)nullptr, f.T, geom(f), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
     hipLaunchKernelGGL(k_mg_zrestrict<VW>, dim3(zq.nxs * q.m1 * zq.nzc), dim3(MG_WG), 0, s, f.T, q.B, geom(f),
                        geom(q), active, N, NV, zq);
   }
@@ -697,14 +772,16 @@ static hipError_t vcycle_t(ope_ctx* c, const double* r, double* z, const int32_t
     const uint32_t grid = zs.nxs * f.m1 * zs.nzc;
     hipLaunchKernelGGL(k_mg_zprolong<VW>, dim3(grid), dim3(MG_WG), 0, s, in, q.E, f.T, geom(f), geom(q), f.wd,
                        active, N, NV, zs);
+    const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N);
+    const uint32_t tgrid = ts.nxt * ts.nyt * ts.nzc;
     if (k == 0 && dots) {
       ProfScope ps(c, OPE_KERNEL_MG_POST);
-      hipLaunchKernelGGL((k_mg_zstencil<VW, 1, true>), dim3(grid), dim3(MG_WG), 0, s, in, (const double*)f.T, out,
-                         geom(f), f.diag, f.wd, active, N, NV, zs, c->mg_part);
-      c->mg_rows_used = grid;
+      hipLaunchKernelGGL((k_mg_tstencil<VW, 1, true>), dim3(tgrid), dim3(ts.TX * ts.TY * NV), 0, s, in,
+                         (const double*)f.T, out, geom(f), f.diag, f.wd, active, N, NV, ts, c->mg_part);
+      c->mg_rows_used = tgrid;
     } else {
-      hipLaunchKernelGGL((k_mg_zstencil<VW, 1, false>), dim3(grid), dim3(MG_WG), 0, s, in, (const double*)f.T, out,
-                         geom(f), f.diag, f.wd, active, N, NV, zs, (double*)nullptr);
+      hipLaunchKernelGGL((k_mg_tstencil<VW, 1, false>), dim3(tgrid), dim3(ts.TX * ts.TY * NV), 0, s, in,
+                         (const double*)f.T, out, geom(f), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
     }
   }
   return hipGetLastError();

@@ -459,6 +459,231 @@ __global__ __launch_bounds__(MG_WG) void k_mg_zprolong(const double* __restrict_
   }
 }
 
+// Coarse x-y interpolation of coarse plane K at a fine column (fixed taps).
+template <int VW>
+__device__ __forceinline__ void coarse_xy(const double* __restrict__ E, const MgGeom& cg, const uint32_t (&Ix)[2],
+                                          const double (&wx)[2], const uint32_t (&Iy)[2], const double (&wy)[2],
+                                          uint32_t K, uint32_t N, uint32_t v, double (&o)[VW]) {
+  zero(o);
+#pragma unroll
+  for (int bb = 0; bb < 2; ++bb) {
+    double ax[VW];
+    zero(ax);
+    const uint64_t row = ((uint64_t)K * cg.m1 + Iy[bb]) * cg.m0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double t[VW];
+      ldr<VW>(E, row + Ix[a], N, v, t);
+#pragma unroll
+      for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
+    }
+#pragma unroll
+    for (int k = 0; k < VW; ++k) o[k] += wy[bb] * ax[k];
+  }
+}
+
+// The prolongation P e along one fine column, marched plane by plane: the
+// x-y interpolations of the coarse planes K0 - 1, K0, K0 + 1 around the
+// current plane's parent K0 stay in registers (each coarse plane read once).
+template <int VW>
+struct PeMarch {
+  uint32_t Ix[2], Iy[2];
+  double wx[2], wy[2];
+  double lo[VW], mid[VW], hi[VW];
+  uint32_t K0;
+  bool flat;                                      // no z axis: the one coarse plane 0
+
+  __device__ __forceinline__ void init(const double* __restrict__ E, const MgGeom& fg, const MgGeom& cg,
+                                       uint32_t fx, uint32_t fy, uint32_t z, uint32_t N, uint32_t v) {
+    prolong_taps(fx, fg.m0, cg.m0, Ix, wx);
+    prolong_taps(fy, fg.m1, cg.m1, Iy, wy);
+    flat = fg.m2 == 1;
+    zero(lo);
+    zero(hi);
+    K0 = flat ? 0 : z / 2;
+    coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0, N, v, mid);
+    if (!flat) {
+      if (K0 >= 1) coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0 - 1, N, v, lo);
+      if (K0 + 1 < cg.m2) coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0 + 1, N, v, hi);
+    }
+  }
+  // move to plane z (the plane after the current one)
+  __device__ __forceinline__ void step(const double* __restrict__ E, const MgGeom& cg, uint32_t z, uint32_t N,
+                                       uint32_t v) {
+    if (flat || z % 2 != 0) return;
+    K0 = z / 2;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      lo[k] = mid[k];
+      mid[k] = hi[k];
+    }
+    zero(hi);
+    if (K0 + 1 < cg.m2) coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0 + 1, N, v, hi);
+  }
+  __device__ __forceinline__ void value(uint32_t z, double (&pe)[VW]) const {
+#pragma unroll
+    for (int k = 0; k < VW; ++k) pe[k] = flat ? mid[k] : 0.75 * mid[k] + 0.25 * (z % 2 == 0 ? lo[k] : hi[k]);
+  }
+};
+
+// Prolongation and post-smoothing in one x-y tiled sweep (as k_mg_tstencil):
+// x1 = omega b / d + P e is formed on the fly for the tile's columns and its
+// ring, then z = x1 + omega (b - H x1) / d; with DOTS also the per-column
+// sums of b z and b b (row blockIdx.x of part).  The ring columns are spread
+// over the threads (at most two per thread), each with its own P e march.
+template <int VW, bool DOTS, int R>
+__global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ b, const double* __restrict__ E,
+                                                    double* __restrict__ out, MgGeom g, MgGeom cg,
+                                                    const double* __restrict__ diag, const double* __restrict__ wd,
+                                                    const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
+                                                    TShape ts, double* __restrict__ part) {
+  __shared__ __align__(16) double tile[MG_TLDS];
+  const uint32_t t = threadIdx.x;
+  const uint32_t v = t % NV, pt = t / NV;
+  const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t xt = L % ts.nxt, r = L / ts.nxt;
+  const uint32_t yt = r % ts.nyt, zc = r / ts.nyt;
+  const uint32_t x0 = xt * ts.TX, y0 = yt * ts.TY;
+  const uint32_t x = x0 + tx, y = y0 + ty;
+  const bool inb = x < g.m0 && y < g.m1;
+  const bool act = vec_active<VW>(active, v);
+  const bool own = inb && act;
+  const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
+  const uint64_t s2 = (uint64_t)g.m0 * g.m1;
+  const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
+  auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NV + v) * VW; };
+  // x1 at fine point `at` with the column's P e value pe
+  auto x1 = [&](uint64_t at, const double(&pe)[VW], double(&f)[VW]) {
+    jac0<VW>(b, wd, at, N, v, f);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) f[k] = f[k] + pe[k];
+  };
+  // ring columns of this thread: k = pt + j P, j < R (R = 2 when the ring is
+  // longer than the tile has columns)
+  uint32_t rk[R], rcx[R], rcy[R];
+  int64_t rhx[R], rhy[R];
+  bool rin[R];
+  PeMarch<VW> rm[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const uint32_t k = pt + j * P;
+    rk[j] = k;
+    rin[j] = false;
+    if (k >= RING) continue;
+    if (k < ts.TX) {
+      rhx[j] = (int64_t)x0 + k; rhy[j] = (int64_t)y0 - 1; rcx[j] = k + 1; rcy[j] = 0;
+    } else if (k < 2 * ts.TX) {
+      rhx[j] = (int64_t)x0 + (k - ts.TX); rhy[j] = (int64_t)y0 + ts.TY; rcx[j] = k - ts.TX + 1; rcy[j] = ts.TY + 1;
+    } else if (k < 2 * ts.TX + ts.TY) {
+      rhx[j] = (int64_t)x0 - 1; rhy[j] = (int64_t)y0 + (k - 2 * ts.TX); rcx[j] = 0; rcy[j] = k - 2 * ts.TX + 1;
+    } else {
+      rhx[j] = (int64_t)x0 + ts.TX; rhy[j] = (int64_t)y0 + (k - 2 * ts.TX - ts.TY); rcx[j] = ts.TX + 1;
+      rcy[j] = k - 2 * ts.TX - ts.TY + 1;
+    }
+    rin[j] = act && rhx[j] >= 0 && rhx[j] < (int64_t)g.m0 && rhy[j] >= 0 && rhy[j] < (int64_t)g.m1;
+    if (rin[j]) rm[j].init(E, g, cg, (uint32_t)rhx[j], (uint32_t)rhy[j], z0, N, v);
+  }
+  // own column: the march starts one plane below z0 when there is one
+  PeMarch<VW> om;
+  double fm[VW], fc[VW], fp[VW], pe[VW];
+  zero(fm);
+  zero(fc);
+  uint64_t p = ((uint64_t)z0 * g.m1 + (inb ? y : 0)) * g.m0 + (inb ? x : 0);
+  if (own) {
+    if (z0 > 0) {
+      om.init(E, g, cg, x, y, z0 - 1, N, v);
+      om.value(z0 - 1, pe);
+      x1(p - s2, pe, fm);
+      om.step(E, cg, z0, N, v);
+    } else {
+      om.init(E, g, cg, x, y, z0, N, v);
+    }
+    om.value(z0, pe);
+    x1(p, pe, fc);
+  }
+  double srz[VW], srr[VW];
+  zero(srz);
+  zero(srr);
+  for (uint32_t z = z0; z < z1; ++z, p += s2) {
+#pragma unroll
+    for (int k = 0; k < VW; ++k) tile[slot(tx + 1, ty + 1) + k] = fc[k];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (rk[j] >= RING) continue;
+      double hv[VW];
+      zero(hv);
+      if (rin[j]) {
+        double rp[VW];
+        rm[j].value(z, rp);
+        x1(((uint64_t)z * g.m1 + (uint64_t)rhy[j]) * g.m0 + (uint64_t)rhx[j], rp, hv);
+        if (z + 1 < z1) rm[j].step(E, cg, z + 1, N, v);
+      }
+#pragma unroll
+      for (int kk = 0; kk < VW; ++kk) tile[slot(rcx[j], rcy[j]) + kk] = hv[kk];
+    }
+    zero(fp);
+    double bc[VW];
+    zero(bc);
+    double d = 0.0, w = 0.0;
+    if (own) {
+      if (z + 1 < g.m2) {
+        om.step(E, cg, z + 1, N, v);
+        om.value(z + 1, pe);
+        x1(p + s2, pe, fp);
+      }
+      ldr<VW>(b, p, N, v, bc);
+      d = diag[p];
+      w = wd[p];
+    }
+    __syncthreads();
+    if (own) {
+      double o[VW];
+      const uint32_t sxm = slot(tx, ty + 1), sxp = slot(tx + 2, ty + 1), sym = slot(tx + 1, ty),
+                     syp = slot(tx + 1, ty + 2);
+#pragma unroll
+      for (int k = 0; k < VW; ++k) {
+        const double hxv = d * fc[k] - (g.cx * (tile[sxm + k] + tile[sxp + k]) + g.cy * (tile[sym + k] + tile[syp + k]) +
+                                        g.cz * (fm[k] + fp[k]));
+        o[k] = fc[k] + w * (bc[k] - hxv);
+      }
+      str<VW>(out, p, N, v, o);
+      if constexpr (DOTS) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+          srz[k] += bc[k] * o[k];
+          srr[k] += bc[k] * bc[k];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      fm[k] = fc[k];
+      fc[k] = fp[k];
+    }
+  }
+  if constexpr (DOTS) {
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      tile[(t * VW + k) * 2 + 0] = srz[k];
+      tile[(t * VW + k) * 2 + 1] = srr[k];
+    }
+    __syncthreads();
+    for (uint32_t c = t; c < N; c += blockDim.x) {
+      const uint32_t cv = c / VW, ck = c % VW;
+      double a = 0.0, bs = 0.0;
+      for (uint32_t l = 0; l < P; ++l) {
+        const uint32_t th = l * NV + cv;
+        a += tile[(th * VW + ck) * 2 + 0];
+        bs += tile[(th * VW + ck) * 2 + 1];
+      }
+      part[(uint64_t)blockIdx.x * 2 * N + c] = a;
+      part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
+    }
+  }
+}
+
 // coarse B = R T, z-marched over the coarse planes of a coarse (I, J) column:
 // the x-y restriction of each fine plane is formed once and added to the two
 // coarse planes it feeds.
@@ -768,20 +993,25 @@ static hipError_t vcycle_t(ope_ctx* c, const double* r, double* z, const int32_t
     const MgLevel& q = c->mg[k + 1];
     const double* in = k == 0 ? r : f.B;
     double* out = k == 0 ? z : f.E;
-    const ZMarch zs = zmarch_shape(f.m0, f.m1, f.m2, NV);
-    const uint32_t grid = zs.nxs * f.m1 * zs.nzc;
-    hipLaunchKernelGGL(k_mg_zprolong<VW>, dim3(grid), dim3(MG_WG), 0, s, in, q.E, f.T, geom(f), geom(q), f.wd,
-                       active, N, NV, zs);
     const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N);
     const uint32_t tgrid = ts.nxt * ts.nyt * ts.nzc;
+    const bool two = 2 * (ts.TX + ts.TY) > ts.TX * ts.TY;     // ring longer than the tile: two per thread
+    const dim3 grid(tgrid), block(ts.TX * ts.TY * NV);
     if (k == 0 && dots) {
       ProfScope ps(c, OPE_KERNEL_MG_POST);
-      hipLaunchKernelGGL((k_mg_tstencil<VW, 1, true>), dim3(tgrid), dim3(ts.TX * ts.TY * NV), 0, s, in,
-                         (const double*)f.T, out, geom(f), f.diag, f.wd, active, N, NV, ts, c->mg_part);
+      if (two)
+        hipLaunchKernelGGL((k_mg_tpost<VW, true, 2>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
+                           geom(q), f.diag, f.wd, active, N, NV, ts, c->mg_part);
+      else
+        hipLaunchKernelGGL((k_mg_tpost<VW, true, 1>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
+                           geom(q), f.diag, f.wd, active, N, NV, ts, c->mg_part);
       c->mg_rows_used = tgrid;
+    } else if (two) {
+      hipLaunchKernelGGL((k_mg_tpost<VW, false, 2>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
+                         geom(q), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
     } else {
-      hipLaunchKernelGGL((k_mg_tstencil<VW, 1, false>), dim3(tgrid), dim3(ts.TX * ts.TY * NV), 0, s, in,
-                         (const double*)f.T, out, geom(f), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
+      hipLaunchKernelGGL((k_mg_tpost<VW, false, 1>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
+                         geom(q), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
     }
   }
   return hipGetLastError();

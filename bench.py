@@ -43,7 +43,6 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-residual-1e-8 and iter/s at 64³,N=128: plain FP64 vs mixed vs learned"
 HBM_PEAK_GBS = 8000.0
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2511_06788_amd", "csrc", "k_stencil.hip")
 
 
 GOLDEN_EIGS = os.path.join(ROOT, "tests", "golden", "reference_eigs.json")
@@ -87,18 +86,21 @@ def kernel_bytes(kind, n, N):
     }.get(kind)
 
 
+PMC_SOURCES = {"cg_sweep_b": "k_stencil.hip", "mg_post": "k_mg.hip"}
+
+
 def traffic_from_pmc(n, N, kernel="cg_sweep_b"):
     """HBM bytes per working launch of a kernel from the committed rocprofv3
-    counter summary, or None when its source changed since the counters were
-    taken (or none were taken for it)."""
-    if not os.path.exists(PMC_FILE):
+    counter summary (profiles/pmc_traffic_<kernel>.json; for CG sweep B also
+    profiles/pmc_traffic.json), or None when its source changed since the
+    counters were taken, or none were taken for this workload."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{kernel}.json")
+    if not os.path.exists(path):
+        path = PMC_FILE if kernel == "cg_sweep_b" else None
+    if path is None or not os.path.exists(path):
         return None
-    recs = json.load(open(PMC_FILE))
-    rec = recs.get(kernel) if isinstance(recs, dict) and kernel in recs else (
-        recs if kernel == "cg_sweep_b" and "source_sha256" in recs else None)
-    if rec is None:
-        return None
-    src = os.path.join(ROOT, "paper_2511_06788_amd", "csrc", rec.get("source", "k_stencil.hip"))
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2511_06788_amd", "csrc", PMC_SOURCES[kernel])
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("source_sha256") != sha or rec.get("n") != n or rec.get("N") != N:
         return None

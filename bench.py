@@ -157,7 +157,7 @@ def host_cores():
     return logical, physical
 
 
-def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
+def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4, switch_mg=1e-3):
     """Wall time of Algorithm 1 from the start block to residual `tol` on an m^3
     wells problem whose block width N = 17 closes a level shell (it converges
     in a few hundred steps): plain FP64; the mixed form until `switch`, then
@@ -271,6 +271,26 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4):
         torch.cuda.synchronize()
         t_mg = time.perf_counter() - t0
         ritz_mg = ope.ope_residual(cg.handle, U, p.N)[1]
+        # the mixed form with its own preconditioned Step 1, then FP64 (also preconditioned)
+        with ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as cmg:
+            ope.ope_set_multigrid(cmg.handle, True)
+            ope.ope_solve(cmg.handle, torch.from_numpy(p.U0.astype(np.float32)).to("cuda"), tau, tol, 3)
+            U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
+            U64 = torch.empty_like(U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            smg = ope.ope_solve(cmg.handle, U32, tau, switch_mg, 20000)
+            ope.ope_convert(cmg.handle, U32, U64, p.grid.n * p.N, True)
+            sfg = ope.ope_solve(cg.handle, U64, tau, tol, 20000)
+            torch.cuda.synchronize()
+            t_mixed_mg = time.perf_counter() - t0
+            ritz_mixed_mg = ope.ope_residual(cg.handle, U64, p.N)[1]
+    out["mixed_then_fp64_multigrid"] = {"converged": bool(sfg.converged), "mixed_steps": int(smg.steps),
+                                        "fp64_steps": int(sfg.steps), "switch_residual": switch_mg,
+                                        "seconds": t_mixed_mg, "final_residual": sfg.residual,
+                                        "final_drift": sfg.drift,
+                                        "ritz_max_rel_error_vs_reference": ritz_error(ritz_mixed_mg, ref)}
+    out["speedup_mixed_multigrid"] = t_plain / t_mixed_mg
     out["plain_fp64_multigrid"] = {"converged": bool(sg.converged), "steps": int(sg.steps), "seconds": t_mg,
                                    "inner_iterations": int(sg.inner_iterations),
                                    "final_residual": sg.residual, "final_drift": sg.drift,
@@ -457,11 +477,13 @@ def sweep_b_rate(ope, torch, ctx, U, tau, n, N, esz, steps=10):
             "frac": achieved / HBM_PEAK_GBS, "counted_iterations": inner, "launches": launches, "steps": steps}
 
 
-def steps_per_second(ope, torch, p, tau, precision, steps, warmup):
+def steps_per_second(ope, torch, p, tau, precision, steps, warmup, multigrid=False):
     import numpy as np
     mixed = precision == ope.OPE_MIXED
     U = torch.from_numpy(p.U0.astype(np.float32 if mixed else np.float64)).to("cuda")
     with ope.Context(p.grid, p.V, p.N, precision=precision) as ctx:
+        if multigrid:
+            ope.ope_set_multigrid(ctx.handle, True)
         for _ in range(warmup):
             ope.ope_step(ctx.handle, U, tau)
         torch.cuda.synchronize()
@@ -560,6 +582,17 @@ def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
         b.capture(U, tau, K)
         t_g1, in_g1 = timed(graph_steps)
         same1 = all(torch.equal(a, r) for a, r in zip(U, ref))
+        # every problem with the multigrid-preconditioned Step 1 (own launches)
+        b.set_shared(False)
+        for i in range(count):
+            ope.ope_set_multigrid(b.context(i), True)
+        most[0] = 0
+        t_m, in_m = timed(batch_steps)
+        Km = max(4, -(-most[0] // 4) * 4)
+        ref_m = [u.clone() for u in U]
+        b.capture(U, tau, Km)
+        t_gm, in_gm = timed(graph_steps)
+        same_m = all(torch.equal(a, r) for a, r in zip(U, ref_m))
     ps = count * steps
 
     def rec(t, r):
@@ -572,6 +605,9 @@ def batched_throughput(ope, torch, steps=5, tau=30.0, count=64):
     out["batched_autotuned"] = rec(t_b1, in_b1)
     out["graph_replay_autotuned"] = dict(rec(t_g0, in_g0), cg_iterations=K, equal_to_eager=same0)
     out["graph_replay_shared_launches_autotuned"] = dict(rec(t_g1, in_g1), cg_iterations=K, equal_to_eager=same1)
+    out["batched_multigrid_autotuned"] = rec(t_m, in_m)
+    out["graph_replay_multigrid_autotuned"] = dict(rec(t_gm, in_gm), cg_iterations=Km, equal_to_eager=same_m)
+    out["speedup_multigrid_vs_batched"] = min(t_b0, t_b1) / min(t_m, t_gm)
     out["speedup_vs_sequential"] = t_seq / min(t_b0, t_b1)
     return out
 
@@ -822,7 +858,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large", "extrapolate", "energy",
-                                       "table1", "ttr", "graph", "mg"], default=None,
+                                       "table1", "ttr", "graph", "mg", "mgmixed"], default=None,
                     help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
@@ -863,6 +899,8 @@ def main():
                 r = steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, args.steps, args.warmup)
             elif args.form == "mg":
                 r = mg_steps_per_second(ope, torch, p, args.tau, args.steps, args.warmup)
+            elif args.form == "mgmixed":
+                r = steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, args.steps, args.warmup, multigrid=True)
             elif args.form == "extrapolate":
                 r = extrapolated_time_to_residual(ope, torch, p, args.tau)
             else:
@@ -924,6 +962,8 @@ def main():
             "plain_fp64": {"iter_per_s": args.steps / dt, "ms_per_step": ms_per_step,
                            "inner_iterations_per_step": inner / max(args.steps, 1)},
             "mixed": steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, ks, args.warmup),
+            "mixed_multigrid": steps_per_second(ope, torch, p, args.tau, ope.OPE_MIXED, ks, args.warmup,
+                                                multigrid=True),
         }
         log("learned form at the same workload")
         out["forms"]["learned"] = learned_steps_per_second(ope, torch, p, args.tau, min(ks, 40), 5)

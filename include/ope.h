@@ -104,7 +104,7 @@ typedef struct {
 typedef struct ope_ctx ope_ctx;
 
 /* Create a context for one operator and block width N (1 <= N <= 512,
- * N <= n; larger N returns OPE_EUNSUPPORTED, and so does a plane of the
+ * N <= n, odd N at most 256; other N return OPE_EUNSUPPORTED, and so does a plane of the
  * march axis holding 2 GiB or more of FP64 block rows, m0 m1 N 8 bytes in 3D,
  * m0 N 8 in 2D: the stencil addresses one plane through 32-bit offsets).  Copies V to the
  * device, allocates O(N^2) matrices and per-column state (the five n x N
@@ -132,31 +132,32 @@ const char* ope_status_string(ope_status s);
  * N = 17 takes 1.5-1.7x less time than with eta_rel = 1e-2, at a few more steps). */
 ope_status ope_set_inner(ope_ctx* ctx, double eta_rel, double eta_floor, int32_t max_iter);
 
-/* Multigrid-preconditioned Step 1 (OPE_FP64 contexts; Step 1 of Section 4.1
- * leaves the solver open).  enable = 1: the CG of every later step, solve and
- * ope_source_solve is preconditioned by one symmetric multigrid V-cycle per
- * iteration (same stopping rule on |u_j - H y_j|, same warm start):
- * hierarchy by halving every axis (m' = ceil(m/2), spacing doubled,
- * potential V + shift averaged over the children), linear prolongation P
- * (weights 3/4, 1/4 per axis), restriction P^T / 2^d, damped Jacobi
- * (omega = 0.8) once before and once after the coarse correction, the first
- * level with at most 64 nodes solved exactly with a dense inverse.  Measured
- * on 64^3 well problems: about 5 preconditioned iterations per step instead
- * of about 70.  Allocates two n x N blocks plus the coarse levels (about 3/7
- * of a block); synchronises; enable = 0 frees them.  With the
+/* Multigrid-preconditioned Step 1 (Step 1 of Section 4.1 leaves the solver
+ * open).  enable = 1: the CG of every later step, solve and ope_source_solve
+ * is preconditioned by one symmetric multigrid V-cycle per iteration (same
+ * stopping rule on |u_j - H y_j|, same warm start): hierarchy by halving
+ * every axis (m' = ceil(m/2), spacing doubled, potential V + shift averaged
+ * over the children), linear prolongation P (weights 3/4, 1/4 per axis),
+ * restriction P^T / 2^d, damped Jacobi (omega = 0.8) once before and once
+ * after the coarse correction, the first level with at most 64 nodes solved
+ * exactly with a dense inverse.  The V-cycle runs in the context's storage
+ * type (FP64, or FP32 for OPE_MIXED, its dot products accumulated in FP64).
+ * Measured on 64^3 well problems: about 4 preconditioned iterations per step
+ * instead of about 66.  Allocates two n x N blocks plus the coarse levels
+ * (about 3/7 of a block); synchronises; enable = 0 frees them.  With the
  * preconditioner on, the host checks the CG's convergence every 2 iterations
- * (else every 4).  OPE_EUNSUPPORTED for
- * OPE_MIXED contexts and for odd N > 256; OPE_ENOTSPD if the coarsest
- * operator is not positive definite.  A problem with the preconditioner on
- * runs its CG on its own stream in batched steps (no shared launches). */
+ * (else every 4).  OPE_EUNSUPPORTED when a point's row has more than 256
+ * 16-byte chunks (odd N > 256 in FP64); OPE_ENOTSPD if the coarsest operator
+ * is not positive definite.  A problem with the preconditioner on runs its
+ * CG on its own stream in batched steps (no shared launches). */
 ope_status ope_set_multigrid(ope_ctx* ctx, int32_t enable);
 /* Levels of the hierarchy (0 when off) and nodes of its coarsest level
  * (host outputs, nullable). */
 ope_status ope_mg_info(const ope_ctx* ctx, int32_t* levels, int64_t* coarsest_nodes);
-/* One V-cycle Z = B R on n x N device blocks (the preconditioner alone;
- * R and Z distinct, 16-byte aligned when N is even).  Synchronises.
- * OPE_EINVAL when the preconditioner is off. */
-ope_status ope_mg_vcycle(ope_ctx* ctx, const double* R, double* Z);
+/* One V-cycle Z = B R on n x N device blocks in the context's storage type
+ * (the preconditioner alone; R and Z distinct and 16-byte aligned).
+ * Synchronises.  OPE_EINVAL when the preconditioner is off. */
+ope_status ope_mg_vcycle(ope_ctx* ctx, const void* R, void* Z);
 
 /* --- Hot-path building blocks (each is one row of the step) -------------- */
 

@@ -23,7 +23,8 @@
 // smoother's factors omega / d are precomputed per level.
 // Layout: every block is n x N row-major (a grid point's N values
 // contiguous), x fastest, as everywhere in the library; a thread owns one
-// 16-byte chunk (VW = 2 doubles) or one double of a point's row.  Columns
+// 16-byte chunk (VW elements) or one element of a point's row, FP64, or
+// FP32 for mixed-precision contexts (dot products accumulated in FP64).  Columns
 // whose CG has converged are skipped.
 #include <algorithm>
 #include <cmath>
@@ -43,32 +44,32 @@ struct MgGeom {
   double cx, cy, cz;
 };
 
-template <int VW>
-__device__ __forceinline__ void ldr(const double* __restrict__ a, uint64_t row, uint32_t N, uint32_t v,
-                                    double (&o)[VW]) {
-  if constexpr (VW == 2) {
-    const double2 t = *reinterpret_cast<const double2*>(a + row * N + 2u * v);
-    o[0] = t.x;
-    o[1] = t.y;
-  } else {
-    o[0] = a[row * N + v];
-  }
-}
+// VW consecutive elements of a point's row (16 bytes or less), loaded and
+// stored as one access.
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) Chunk {
+  T v[VW];
+};
 
-template <int VW>
-__device__ __forceinline__ void str(double* __restrict__ a, uint64_t row, uint32_t N, uint32_t v,
-                                    const double (&o)[VW]) {
-  if constexpr (VW == 2) {
-    *reinterpret_cast<double2*>(a + row * N + 2u * v) = make_double2(o[0], o[1]);
-  } else {
-    a[row * N + v] = o[0];
-  }
-}
-
-template <int VW>
-__device__ __forceinline__ void zero(double (&a)[VW]) {
+template <typename T, int VW>
+__device__ __forceinline__ void ldr(const T* __restrict__ a, uint64_t row, uint32_t N, uint32_t v, T (&o)[VW]) {
+  const Chunk<T, VW> t = *reinterpret_cast<const Chunk<T, VW>*>(a + row * N + (uint64_t)VW * v);
 #pragma unroll
-  for (int k = 0; k < VW; ++k) a[k] = 0.0;
+  for (int k = 0; k < VW; ++k) o[k] = t.v[k];
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void str(T* __restrict__ a, uint64_t row, uint32_t N, uint32_t v, const T (&o)[VW]) {
+  Chunk<T, VW> t;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) t.v[k] = o[k];
+  *reinterpret_cast<Chunk<T, VW>*>(a + row * N + (uint64_t)VW * v) = t;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void zero(T (&a)[VW]) {
+#pragma unroll
+  for (int k = 0; k < VW; ++k) a[k] = T(0);
 }
 
 template <int VW>
@@ -82,11 +83,11 @@ __device__ __forceinline__ bool vec_active(const int32_t* __restrict__ active, u
 
 // x0 = (omega / d) b at point q, with wd = omega / d (zero outside the grid is
 // the caller's job)
-template <int VW>
-__device__ __forceinline__ void jac0(const double* __restrict__ b, const double* __restrict__ wd, uint64_t q,
-                                     uint32_t N, uint32_t v, double (&o)[VW]) {
-  ldr<VW>(b, q, N, v, o);
-  const double w = wd[q];
+template <typename T, int VW>
+__device__ __forceinline__ void jac0(const T* __restrict__ b, const double* __restrict__ wd, uint64_t q, uint32_t N,
+                                     uint32_t v, T (&o)[VW]) {
+  ldr<T, VW>(b, q, N, v, o);
+  const T w = (T)wd[q];
 #pragma unroll
   for (int k = 0; k < VW; ++k) o[k] = w * o[k];
 }
@@ -116,9 +117,9 @@ __device__ __forceinline__ void restrict_taps(uint32_t I, uint32_t mf, uint32_t 
 }
 
 // coarsest level: E = A^{-1} B with the dense inverse (row-major nc x nc)
-template <int VW>
-__global__ __launch_bounds__(MG_WG) void k_mg_dense(const double* __restrict__ Ainv, const double* __restrict__ B,
-                                                   double* __restrict__ E, uint32_t nc,
+template <typename T, int VW>
+__global__ __launch_bounds__(MG_WG) void k_mg_dense(const double* __restrict__ Ainv, const T* __restrict__ B,
+                                                   T* __restrict__ E, uint32_t nc,
                                                    const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
                                                    uint64_t total) {
   const uint64_t e = (uint64_t)blockIdx.x * MG_WG + threadIdx.x;
@@ -126,36 +127,36 @@ __global__ __launch_bounds__(MG_WG) void k_mg_dense(const double* __restrict__ A
   const uint32_t v = (uint32_t)(e % NV);
   const uint32_t i = (uint32_t)(e / NV);
   if (!vec_active<VW>(active, v)) return;
-  double acc[VW];
+  T acc[VW];
 #pragma unroll
   for (int k = 0; k < VW; ++k) acc[k] = 0.0;
   const double* a = Ainv + (uint64_t)i * nc;
   // four running sums over j = 4 u + s (their loads are issued together), added in order
-  double part[4][VW];
+  T part[4][VW];
 #pragma unroll
   for (int s = 0; s < 4; ++s) zero(part[s]);
   uint32_t j = 0;
   for (; j + 4 <= nc; j += 4) {
-    double t[4][VW];
+    T t[4][VW];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) ldr<VW>(B, j + s, N, v, t[s]);
+    for (int s = 0; s < 4; ++s) ldr<T, VW>(B, j + s, N, v, t[s]);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const double w = a[j + s];
+      const T w = (T)a[j + s];
 #pragma unroll
       for (int k = 0; k < VW; ++k) part[s][k] += w * t[s][k];
     }
   }
   for (; j < nc; ++j) {
-    double t[VW];
-    ldr<VW>(B, j, N, v, t);
-    const double w = a[j];
+    T t[VW];
+    ldr<T, VW>(B, j, N, v, t);
+    const T w = (T)a[j];
 #pragma unroll
     for (int k = 0; k < VW; ++k) part[0][k] += w * t[k];
   }
 #pragma unroll
   for (int k = 0; k < VW; ++k) acc[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
-  str<VW>(E, i, N, v, acc);
+  str<T, VW>(E, i, N, v, acc);
 }
 
 // z-march decomposition of a level: a work-group owns PL = 256 / NV
@@ -219,9 +220,9 @@ struct TShape {
 };
 
 constexpr uint32_t MG_TWG = 1024;                 // threads of a tiled work-group (at most)
-constexpr uint32_t MG_TLDS = 8192;                // LDS tile capacity in doubles (64 KiB)
+constexpr uint32_t MG_TLDS_BYTES = 65536;         // LDS of a tiled work-group
 
-TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N) {
+TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N, uint32_t esz) {
   TShape s;
   const uint32_t P = MG_TWG / NV;                 // columns per work-group
   uint32_t tx = 1;
@@ -229,7 +230,7 @@ TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N) {
   if (tx * tx * 2 <= P) tx *= 2;
   s.TX = std::min(tx, m0);
   s.TY = std::max(1u, std::min(P / s.TX, m1));
-  while ((s.TX + 2) * (s.TY + 2) * N > MG_TLDS && s.TY > 1) --s.TY;
+  while ((s.TX + 2) * (s.TY + 2) * N * esz > MG_TLDS_BYTES && s.TY > 1) --s.TY;
   s.nxt = (m0 + s.TX - 1) / s.TX;
   s.nyt = (m1 + s.TY - 1) / s.TY;
   const uint64_t tiles = (uint64_t)s.nxt * s.nyt;
@@ -241,13 +242,13 @@ TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N) {
   return s;
 }
 
-template <int VW, int KIND, bool DOTS>
-__global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict__ b, const double* __restrict__ T,
-                                                       double* __restrict__ out, MgGeom g,
+template <typename T, int VW, int KIND, bool DOTS>
+__global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b, const T* __restrict__ X1,
+                                                       T* __restrict__ out, MgGeom g,
                                                        const double* __restrict__ diag, const double* __restrict__ wd,
                                                        const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
                                                        TShape ts, double* __restrict__ part) {
-  __shared__ __align__(16) double tile[MG_TLDS];
+  __shared__ __align__(16) T tile[MG_TLDS_BYTES / sizeof(T)];
   const uint32_t t = threadIdx.x;
   const uint32_t v = t % NV, pt = t / NV;
   const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
@@ -262,13 +263,13 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict
   const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
   const uint64_t s2 = (uint64_t)g.m0 * g.m1;
   const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
-  auto field = [&](uint64_t at, double(&f)[VW]) {
-    if constexpr (KIND == 0) jac0<VW>(b, wd, at, N, v, f);
-    else ldr<VW>(T, at, N, v, f);
+  auto field = [&](uint64_t at, T(&f)[VW]) {
+    if constexpr (KIND == 0) jac0<T, VW>(b, wd, at, N, v, f);
+    else ldr<T, VW>(X1, at, N, v, f);
   };
   // LDS slot of tile-local column (cx, cy) (ring included: cx, cy in [0, W) x [0, TY + 2))
   auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NV + v) * VW; };
-  double fm[VW], fc[VW], fp[VW];
+  T fm[VW], fc[VW], fp[VW];
   zero(fm);
   zero(fc);
   uint64_t p = ((uint64_t)z0 * g.m1 + (inb ? y : 0)) * g.m0 + (inb ? x : 0);
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict
         hx = (int64_t)x0 + ts.TX; hy = (int64_t)y0 + (k - 2 * ts.TX - ts.TY); cx = ts.TX + 1;
         cy = k - 2 * ts.TX - ts.TY + 1;
       }
-      double hv[VW];
+      T hv[VW];
       zero(hv);
       if (act && hx >= 0 && hx < (int64_t)g.m0 && hy >= 0 && hy < (int64_t)g.m1)
         field(((uint64_t)z * g.m1 + (uint64_t)hy) * g.m0 + (uint64_t)hx, hv);
@@ -306,33 +307,33 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict
     }
     // the next plane's own value and the centre data, loaded before the wait
     zero(fp);
-    double bc[VW];
+    T bc[VW];
     zero(bc);
-    double d = 0.0, w = 0.0;
+    T d = T(0), w = T(0);
     if (own) {
       if (z + 1 < g.m2) field(p + s2, fp);
-      ldr<VW>(b, p, N, v, bc);
-      d = diag[p];
-      if constexpr (KIND == 1) w = wd[p];
+      ldr<T, VW>(b, p, N, v, bc);
+      d = (T)diag[p];
+      if constexpr (KIND == 1) w = (T)wd[p];
     }
     __syncthreads();
     if (own) {
-      double o[VW];
+      T o[VW];
       const uint32_t sxm = slot(tx, ty + 1), sxp = slot(tx + 2, ty + 1), sym = slot(tx + 1, ty),
                      syp = slot(tx + 1, ty + 2);
 #pragma unroll
       for (int k = 0; k < VW; ++k) {
-        const double hxv = d * fc[k] - (g.cx * (tile[sxm + k] + tile[sxp + k]) + g.cy * (tile[sym + k] + tile[syp + k]) +
-                                        g.cz * (fm[k] + fp[k]));
+        const T hxv = d * fc[k] - ((T)g.cx * (tile[sxm + k] + tile[sxp + k]) +
+                                   (T)g.cy * (tile[sym + k] + tile[syp + k]) + (T)g.cz * (fm[k] + fp[k]));
         if constexpr (KIND == 0) o[k] = bc[k] - hxv;
         else o[k] = fc[k] + w * (bc[k] - hxv);
       }
-      str<VW>(out, p, N, v, o);
+      str<T, VW>(out, p, N, v, o);
       if constexpr (DOTS) {
 #pragma unroll
         for (int k = 0; k < VW; ++k) {
-          srz[k] += bc[k] * o[k];
-          srr[k] += bc[k] * bc[k];
+          srz[k] += (double)bc[k] * (double)o[k];
+          srr[k] += (double)bc[k] * (double)bc[k];
         }
       }
     }
@@ -345,10 +346,11 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict
   }
   if constexpr (DOTS) {
     // per-column sums over the tile's columns in order (LDS reused)
+    double* red = reinterpret_cast<double*>(tile);
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
-      tile[(t * VW + k) * 2 + 0] = srz[k];
-      tile[(t * VW + k) * 2 + 1] = srr[k];
+      red[(t * VW + k) * 2 + 0] = srz[k];
+      red[(t * VW + k) * 2 + 1] = srr[k];
     }
     __syncthreads();
     for (uint32_t c = t; c < N; c += blockDim.x) {
@@ -356,8 +358,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const double* __restrict
       double a = 0.0, bs = 0.0;
       for (uint32_t l = 0; l < P; ++l) {
         const uint32_t th = l * NV + cv;
-        a += tile[(th * VW + ck) * 2 + 0];
-        bs += tile[(th * VW + ck) * 2 + 1];
+        a += red[(th * VW + ck) * 2 + 0];
+        bs += red[(th * VW + ck) * 2 + 1];
       }
       part[(uint64_t)blockIdx.x * 2 * N + c] = a;
       part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
@@ -384,116 +386,42 @@ __device__ __forceinline__ void prolong_taps(uint32_t f, uint32_t mf, uint32_t m
   w[1] = in ? 0.25 : 0.0;
 }
 
-// T = x0 + P E (x0 = omega b / d) on the fine level of the pair, z-marched:
-// the x-y interpolation of the coarse planes K0 - 1, K0, K0 + 1 around the
-// current fine plane's parent K0 stays in registers, so each coarse plane is
-// read once per fine column.
-template <int VW>
-__global__ __launch_bounds__(MG_WG) void k_mg_zprolong(const double* __restrict__ b, const double* __restrict__ E,
-                                                      double* __restrict__ T, MgGeom fg, MgGeom cg,
-                                                      const double* __restrict__ wd,
-                                                      const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                      ZMarch zs) {
-  const ZPos q = zpos<VW>(fg, zs, active, NV);
-  if (!q.ok) return;
-  const uint32_t v = q.v;
-  uint32_t Ix[2], Iy[2];
-  double wx[2], wy[2];
-  prolong_taps(q.x, fg.m0, cg.m0, Ix, wx);
-  prolong_taps(q.y, fg.m1, cg.m1, Iy, wy);
-  auto cxy = [&](uint32_t K, double(&o)[VW]) {
-    zero(o);
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
-      double ax[VW];
-      zero(ax);
-      const uint64_t row = ((uint64_t)K * cg.m1 + Iy[bb]) * cg.m0;
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        double t[VW];
-        ldr<VW>(E, row + Ix[a], N, v, t);
-#pragma unroll
-        for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
-      }
-#pragma unroll
-      for (int k = 0; k < VW; ++k) o[k] += wy[bb] * ax[k];
-    }
-  };
-  const uint64_t s2 = (uint64_t)fg.m0 * fg.m1;
-  uint64_t p = ((uint64_t)q.z0 * fg.m1 + q.y) * fg.m0 + q.x;
-  if (fg.m2 == 1) {                 // no z axis: one plane, coarse plane 0
-    double pe[VW], x0[VW], o[VW];
-    cxy(0, pe);
-    jac0<VW>(b, wd, p, N, v, x0);
-#pragma unroll
-    for (int k = 0; k < VW; ++k) o[k] = x0[k] + pe[k];
-    str<VW>(T, p, N, v, o);
-    return;
-  }
-  uint32_t K0 = q.z0 / 2;
-  double lo[VW], mid[VW], hi[VW];
-  zero(lo);
-  zero(hi);
-  cxy(K0, mid);
-  if (K0 >= 1) cxy(K0 - 1, lo);
-  if (K0 + 1 < cg.m2) cxy(K0 + 1, hi);
-  for (uint32_t z = q.z0; z < q.z1; ++z, p += s2) {
-    if (z > q.z0 && z % 2 == 0) {   // next parent plane
-      K0 = z / 2;
-#pragma unroll
-      for (int k = 0; k < VW; ++k) {
-        lo[k] = mid[k];
-        mid[k] = hi[k];
-      }
-      zero(hi);
-      if (K0 + 1 < cg.m2) cxy(K0 + 1, hi);
-    }
-    double x0[VW], o[VW];
-    jac0<VW>(b, wd, p, N, v, x0);
-#pragma unroll
-    for (int k = 0; k < VW; ++k) {
-      const double pe = 0.75 * mid[k] + 0.25 * (z % 2 == 0 ? lo[k] : hi[k]);
-      o[k] = x0[k] + pe;
-    }
-    str<VW>(T, p, N, v, o);
-  }
-}
 
 // Coarse x-y interpolation of coarse plane K at a fine column (fixed taps).
-template <int VW>
-__device__ __forceinline__ void coarse_xy(const double* __restrict__ E, const MgGeom& cg, const uint32_t (&Ix)[2],
+template <typename T, int VW>
+__device__ __forceinline__ void coarse_xy(const T* __restrict__ E, const MgGeom& cg, const uint32_t (&Ix)[2],
                                           const double (&wx)[2], const uint32_t (&Iy)[2], const double (&wy)[2],
-                                          uint32_t K, uint32_t N, uint32_t v, double (&o)[VW]) {
+                                          uint32_t K, uint32_t N, uint32_t v, T (&o)[VW]) {
   zero(o);
 #pragma unroll
   for (int bb = 0; bb < 2; ++bb) {
-    double ax[VW];
+    T ax[VW];
     zero(ax);
     const uint64_t row = ((uint64_t)K * cg.m1 + Iy[bb]) * cg.m0;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      double t[VW];
-      ldr<VW>(E, row + Ix[a], N, v, t);
+      T t[VW];
+      ldr<T, VW>(E, row + Ix[a], N, v, t);
 #pragma unroll
-      for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
+      for (int k = 0; k < VW; ++k) ax[k] += (T)wx[a] * t[k];
     }
 #pragma unroll
-    for (int k = 0; k < VW; ++k) o[k] += wy[bb] * ax[k];
+    for (int k = 0; k < VW; ++k) o[k] += (T)wy[bb] * ax[k];
   }
 }
 
 // The prolongation P e along one fine column, marched plane by plane: the
 // x-y interpolations of the coarse planes K0 - 1, K0, K0 + 1 around the
 // current plane's parent K0 stay in registers (each coarse plane read once).
-template <int VW>
+template <typename T, int VW>
 struct PeMarch {
   uint32_t Ix[2], Iy[2];
   double wx[2], wy[2];
-  double lo[VW], mid[VW], hi[VW];
+  T lo[VW], mid[VW], hi[VW];
   uint32_t K0;
   bool flat;                                      // no z axis: the one coarse plane 0
 
-  __device__ __forceinline__ void init(const double* __restrict__ E, const MgGeom& fg, const MgGeom& cg,
+  __device__ __forceinline__ void init(const T* __restrict__ E, const MgGeom& fg, const MgGeom& cg,
                                        uint32_t fx, uint32_t fy, uint32_t z, uint32_t N, uint32_t v) {
     prolong_taps(fx, fg.m0, cg.m0, Ix, wx);
     prolong_taps(fy, fg.m1, cg.m1, Iy, wy);
@@ -501,14 +429,14 @@ struct PeMarch {
     zero(lo);
     zero(hi);
     K0 = flat ? 0 : z / 2;
-    coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0, N, v, mid);
+    coarse_xy<T, VW>(E, cg, Ix, wx, Iy, wy, K0, N, v, mid);
     if (!flat) {
-      if (K0 >= 1) coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0 - 1, N, v, lo);
-      if (K0 + 1 < cg.m2) coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0 + 1, N, v, hi);
+      if (K0 >= 1) coarse_xy<T, VW>(E, cg, Ix, wx, Iy, wy, K0 - 1, N, v, lo);
+      if (K0 + 1 < cg.m2) coarse_xy<T, VW>(E, cg, Ix, wx, Iy, wy, K0 + 1, N, v, hi);
     }
   }
   // move to plane z (the plane after the current one)
-  __device__ __forceinline__ void step(const double* __restrict__ E, const MgGeom& cg, uint32_t z, uint32_t N,
+  __device__ __forceinline__ void step(const T* __restrict__ E, const MgGeom& cg, uint32_t z, uint32_t N,
                                        uint32_t v) {
     if (flat || z % 2 != 0) return;
     K0 = z / 2;
@@ -518,11 +446,11 @@ struct PeMarch {
       mid[k] = hi[k];
     }
     zero(hi);
-    if (K0 + 1 < cg.m2) coarse_xy<VW>(E, cg, Ix, wx, Iy, wy, K0 + 1, N, v, hi);
+    if (K0 + 1 < cg.m2) coarse_xy<T, VW>(E, cg, Ix, wx, Iy, wy, K0 + 1, N, v, hi);
   }
-  __device__ __forceinline__ void value(uint32_t z, double (&pe)[VW]) const {
+  __device__ __forceinline__ void value(uint32_t z, T (&pe)[VW]) const {
 #pragma unroll
-    for (int k = 0; k < VW; ++k) pe[k] = flat ? mid[k] : 0.75 * mid[k] + 0.25 * (z % 2 == 0 ? lo[k] : hi[k]);
+    for (int k = 0; k < VW; ++k) pe[k] = flat ? mid[k] : T(0.75) * mid[k] + T(0.25) * (z % 2 == 0 ? lo[k] : hi[k]);
   }
 };
 
@@ -531,13 +459,13 @@ struct PeMarch {
 // ring, then z = x1 + omega (b - H x1) / d; with DOTS also the per-column
 // sums of b z and b b (row blockIdx.x of part).  The ring columns are spread
 // over the threads (at most two per thread), each with its own P e march.
-template <int VW, bool DOTS, int R>
-__global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ b, const double* __restrict__ E,
-                                                    double* __restrict__ out, MgGeom g, MgGeom cg,
+template <typename T, int VW, bool DOTS, int R>
+__global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, const T* __restrict__ E,
+                                                    T* __restrict__ out, MgGeom g, MgGeom cg,
                                                     const double* __restrict__ diag, const double* __restrict__ wd,
                                                     const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
                                                     TShape ts, double* __restrict__ part) {
-  __shared__ __align__(16) double tile[MG_TLDS];
+  __shared__ __align__(16) T tile[MG_TLDS_BYTES / sizeof(T)];
   const uint32_t t = threadIdx.x;
   const uint32_t v = t % NV, pt = t / NV;
   const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
@@ -554,8 +482,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
   const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
   auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NV + v) * VW; };
   // x1 at fine point `at` with the column's P e value pe
-  auto x1 = [&](uint64_t at, const double(&pe)[VW], double(&f)[VW]) {
-    jac0<VW>(b, wd, at, N, v, f);
+  auto x1 = [&](uint64_t at, const T(&pe)[VW], T(&f)[VW]) {
+    jac0<T, VW>(b, wd, at, N, v, f);
 #pragma unroll
     for (int k = 0; k < VW; ++k) f[k] = f[k] + pe[k];
   };
@@ -564,7 +492,7 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
   uint32_t rk[R], rcx[R], rcy[R];
   int64_t rhx[R], rhy[R];
   bool rin[R];
-  PeMarch<VW> rm[R];
+  PeMarch<T, VW> rm[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const uint32_t k = pt + j * P;
@@ -585,8 +513,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
     if (rin[j]) rm[j].init(E, g, cg, (uint32_t)rhx[j], (uint32_t)rhy[j], z0, N, v);
   }
   // own column: the march starts one plane below z0 when there is one
-  PeMarch<VW> om;
-  double fm[VW], fc[VW], fp[VW], pe[VW];
+  PeMarch<T, VW> om;
+  T fm[VW], fc[VW], fp[VW], pe[VW];
   zero(fm);
   zero(fc);
   uint64_t p = ((uint64_t)z0 * g.m1 + (inb ? y : 0)) * g.m0 + (inb ? x : 0);
@@ -611,10 +539,10 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       if (rk[j] >= RING) continue;
-      double hv[VW];
+      T hv[VW];
       zero(hv);
       if (rin[j]) {
-        double rp[VW];
+        T rp[VW];
         rm[j].value(z, rp);
         x1(((uint64_t)z * g.m1 + (uint64_t)rhy[j]) * g.m0 + (uint64_t)rhx[j], rp, hv);
         if (z + 1 < z1) rm[j].step(E, cg, z + 1, N, v);
@@ -623,36 +551,36 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
       for (int kk = 0; kk < VW; ++kk) tile[slot(rcx[j], rcy[j]) + kk] = hv[kk];
     }
     zero(fp);
-    double bc[VW];
+    T bc[VW];
     zero(bc);
-    double d = 0.0, w = 0.0;
+    T d = T(0), w = T(0);
     if (own) {
       if (z + 1 < g.m2) {
         om.step(E, cg, z + 1, N, v);
         om.value(z + 1, pe);
         x1(p + s2, pe, fp);
       }
-      ldr<VW>(b, p, N, v, bc);
-      d = diag[p];
-      w = wd[p];
+      ldr<T, VW>(b, p, N, v, bc);
+      d = (T)diag[p];
+      w = (T)wd[p];
     }
     __syncthreads();
     if (own) {
-      double o[VW];
+      T o[VW];
       const uint32_t sxm = slot(tx, ty + 1), sxp = slot(tx + 2, ty + 1), sym = slot(tx + 1, ty),
                      syp = slot(tx + 1, ty + 2);
 #pragma unroll
       for (int k = 0; k < VW; ++k) {
-        const double hxv = d * fc[k] - (g.cx * (tile[sxm + k] + tile[sxp + k]) + g.cy * (tile[sym + k] + tile[syp + k]) +
-                                        g.cz * (fm[k] + fp[k]));
+        const T hxv = d * fc[k] - ((T)g.cx * (tile[sxm + k] + tile[sxp + k]) +
+                                   (T)g.cy * (tile[sym + k] + tile[syp + k]) + (T)g.cz * (fm[k] + fp[k]));
         o[k] = fc[k] + w * (bc[k] - hxv);
       }
-      str<VW>(out, p, N, v, o);
+      str<T, VW>(out, p, N, v, o);
       if constexpr (DOTS) {
 #pragma unroll
         for (int k = 0; k < VW; ++k) {
-          srz[k] += bc[k] * o[k];
-          srr[k] += bc[k] * bc[k];
+          srz[k] += (double)bc[k] * (double)o[k];
+          srr[k] += (double)bc[k] * (double)bc[k];
         }
       }
     }
@@ -664,10 +592,11 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
     }
   }
   if constexpr (DOTS) {
+    double* red = reinterpret_cast<double*>(tile);
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
-      tile[(t * VW + k) * 2 + 0] = srz[k];
-      tile[(t * VW + k) * 2 + 1] = srr[k];
+      red[(t * VW + k) * 2 + 0] = srz[k];
+      red[(t * VW + k) * 2 + 1] = srr[k];
     }
     __syncthreads();
     for (uint32_t c = t; c < N; c += blockDim.x) {
@@ -675,8 +604,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
       double a = 0.0, bs = 0.0;
       for (uint32_t l = 0; l < P; ++l) {
         const uint32_t th = l * NV + cv;
-        a += tile[(th * VW + ck) * 2 + 0];
-        bs += tile[(th * VW + ck) * 2 + 1];
+        a += red[(th * VW + ck) * 2 + 0];
+        bs += red[(th * VW + ck) * 2 + 1];
       }
       part[(uint64_t)blockIdx.x * 2 * N + c] = a;
       part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
@@ -687,8 +616,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const double* __restrict__ 
 // coarse B = R T, z-marched over the coarse planes of a coarse (I, J) column:
 // the x-y restriction of each fine plane is formed once and added to the two
 // coarse planes it feeds.
-template <int VW>
-__global__ __launch_bounds__(MG_WG) void k_mg_zrestrict(const double* __restrict__ T, double* __restrict__ B,
+template <typename T, int VW>
+__global__ __launch_bounds__(MG_WG) void k_mg_zrestrict(const T* __restrict__ R1, T* __restrict__ B,
                                                        MgGeom fg, MgGeom cg, const int32_t* __restrict__ active,
                                                        uint32_t N, uint32_t NV, ZMarch zs) {
   const ZPos q = zpos<VW>(cg, zs, active, NV);
@@ -698,52 +627,52 @@ __global__ __launch_bounds__(MG_WG) void k_mg_zrestrict(const double* __restrict
   double wx[4], wy[4];
   restrict_taps(q.x, fg.m0, fx, wx);
   restrict_taps(q.y, fg.m1, fy, wy);
-  auto rxy = [&](uint32_t z, double(&o)[VW]) {
+  auto rxy = [&](uint32_t z, T(&o)[VW]) {
     zero(o);
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-      double ax[VW];
+      T ax[VW];
       zero(ax);
       const uint64_t row = ((uint64_t)z * fg.m1 + fy[bb]) * fg.m0;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        double t[VW];
-        ldr<VW>(T, row + fx[a], N, v, t);
+        T t[VW];
+        ldr<T, VW>(R1, row + fx[a], N, v, t);
 #pragma unroll
-        for (int k = 0; k < VW; ++k) ax[k] += wx[a] * t[k];
+        for (int k = 0; k < VW; ++k) ax[k] += (T)wx[a] * t[k];
       }
 #pragma unroll
-      for (int k = 0; k < VW; ++k) o[k] += wy[bb] * ax[k];
+      for (int k = 0; k < VW; ++k) o[k] += (T)wy[bb] * ax[k];
     }
   };
   const uint64_t cs2 = (uint64_t)cg.m0 * cg.m1;
   uint64_t P = ((uint64_t)q.z0 * cg.m1 + q.y) * cg.m0 + q.x;
   if (fg.m2 == 1) {                 // no z axis
-    double o[VW];
+    T o[VW];
     rxy(0, o);
-    str<VW>(B, P, N, v, o);
+    str<T, VW>(B, P, N, v, o);
     return;
   }
   // fine planes 2K - 1, 2K, 2K + 1, 2K + 2 with weights 1/8, 3/8, 3/8, 1/8;
   // the last two are the first two of coarse plane K + 1
-  double ra[VW], rb[VW];
+  T ra[VW], rb[VW];
   zero(ra);
   zero(rb);
   if (q.z0 >= 1) rxy(2 * q.z0 - 1, ra);
   rxy(2 * q.z0, rb);
   for (uint32_t K = q.z0; K < q.z1; ++K, P += cs2) {
-    double rc[VW], rd[VW], o[VW];
+    T rc[VW], rd[VW], o[VW];
     zero(rc);
     zero(rd);
     if (2 * K + 1 < fg.m2) rxy(2 * K + 1, rc);
     if (2 * K + 2 < fg.m2) rxy(2 * K + 2, rd);
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
-      o[k] = 0.125 * ra[k] + 0.375 * rb[k] + 0.375 * rc[k] + 0.125 * rd[k];
+      o[k] = T(0.125) * ra[k] + T(0.375) * rb[k] + T(0.375) * rc[k] + T(0.125) * rd[k];
       ra[k] = rc[k];
       rb[k] = rd[k];
     }
-    str<VW>(B, P, N, v, o);
+    str<T, VW>(B, P, N, v, o);
   }
 }
 
@@ -782,6 +711,14 @@ __global__ __launch_bounds__(MG_WG) void k_pcg_beta(const double* __restrict__ d
 inline MgGeom geom(const MgLevel& L) { return MgGeom{L.m0, L.m1, L.m2, L.cx, L.cy, L.cz}; }
 
 inline uint32_t grid_of(uint64_t total) { return (uint32_t)((total + MG_WG - 1) / MG_WG); }
+
+// Storage type of the blocks (the context's: FP64, or FP32 for OPE_MIXED) and
+// elements per thread (16 bytes when N allows).
+inline uint32_t mg_esz(const ope_ctx* c) { return c->prec == OPE_FP64 ? 8u : 4u; }
+inline uint32_t mg_vw(const ope_ctx* c) {
+  if (c->prec == OPE_FP64) return c->N % 2 == 0 ? 2u : 1u;
+  return c->N % 4 == 0 ? 4u : (c->N % 2 == 0 ? 2u : 1u);
+}
 
 // Dense inverse of an SPD matrix (row-major, n x n) by Cholesky: A = L L^T,
 // A^{-1} = L^{-T} L^{-1}.  False if A is not positive definite.
@@ -922,12 +859,13 @@ ope_status mg_build(ope_ctx* c) {
   // device memory: level diagonals, blocks (level 0: T and Z; others: B, E, T)
   int64_t elems = 2 * c->n * N;
   for (int k = 1; k < nl; ++k) elems += 3 * lv[k].n * N;
+  const uint32_t esz = mg_esz(c);
   {
-    const uint32_t NV = (uint32_t)(N % 2 == 0 ? N / 2 : N);
-    const TShape ts = tshape(lv[0].m0, lv[0].m1, lv[0].m2, NV, (uint32_t)N);
+    const uint32_t NV = (uint32_t)N / mg_vw(c);
+    const TShape ts = tshape(lv[0].m0, lv[0].m1, lv[0].m2, NV, (uint32_t)N, esz);
     c->mg_rows = (int64_t)ts.nxt * ts.nyt * ts.nzc;        // partial rows of the level-0 post-smoothing
   }
-  bool ok = hipMalloc(&c->mg_mem, sizeof(double) * (size_t)elems) == hipSuccess;
+  bool ok = hipMalloc(&c->mg_mem, (size_t)esz * (size_t)elems) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_inv, sizeof(double) * (size_t)nc * nc) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_part, sizeof(double) * (size_t)c->mg_rows * 2 * N) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->mg_dots, sizeof(double) * 2 * (size_t)N) == hipSuccess;
@@ -939,18 +877,18 @@ ope_status mg_build(ope_ctx* c) {
     mg_free(c);
     return OPE_ENOMEM;
   }
-  double* mem = (double*)c->mg_mem;
+  char* mem = (char*)c->mg_mem;
   c->mg[0].T = mem;
-  mem += c->n * N;
+  mem += (size_t)esz * c->n * N;
   c->mg_Z = mem;
-  mem += c->n * N;
+  mem += (size_t)esz * c->n * N;
   for (int k = 1; k < nl; ++k) {
     c->mg[k].B = mem;
-    mem += c->mg[k].n * N;
+    mem += (size_t)esz * c->mg[k].n * N;
     c->mg[k].E = mem;
-    mem += c->mg[k].n * N;
+    mem += (size_t)esz * c->mg[k].n * N;
     c->mg[k].T = mem;
-    mem += c->mg[k].n * N;
+    mem += (size_t)esz * c->mg[k].n * N;
   }
   ok = hipMemcpy(c->mg_inv, A.data(), sizeof(double) * (size_t)nc * nc, hipMemcpyHostToDevice) == hipSuccess;
   for (int k = 1; k < nl && ok; ++k)
@@ -968,59 +906,68 @@ ope_status mg_build(ope_ctx* c) {
   return OPE_OK;
 }
 
-template <int VW>
-static hipError_t vcycle_t(ope_ctx* c, const double* r, double* z, const int32_t* active, bool dots) {
+template <typename T, int VW>
+static hipError_t vcycle_t(ope_ctx* c, const T* r, T* z, const int32_t* active, bool dots) {
   const uint32_t N = (uint32_t)c->N, NV = N / VW;
   const int L = c->mg_levels;
   hipStream_t s = c->stream;
   for (int k = 0; k + 1 < L; ++k) {
     const MgLevel& f = c->mg[k];
     const MgLevel& q = c->mg[k + 1];
-    const double* in = k == 0 ? r : f.B;
-    const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N);
+    const T* in = k == 0 ? r : (const T*)f.B;
+    const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N, sizeof(T));
     const ZMarch zq = zmarch_shape(q.m0, q.m1, q.m2, NV);
-    hipLaunchKernelGGL((k_mg_tstencil<VW, 0, false>), dim3(ts.nxt * ts.nyt * ts.nzc), dim3(ts.TX * ts.TY * NV), 0, s,
-                       in, (const double*)nullptr, f.T, geom(f), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
-    hipLaunchKernelGGL(k_mg_zrestrict<VW>, dim3(zq.nxs * q.m1 * zq.nzc), dim3(MG_WG), 0, s, f.T, q.B, geom(f),
-                       geom(q), active, N, NV, zq);
+    hipLaunchKernelGGL((k_mg_tstencil<T, VW, 0, false>), dim3(ts.nxt * ts.nyt * ts.nzc), dim3(ts.TX * ts.TY * NV), 0,
+                       s, in, (const T*)nullptr, (T*)f.T, geom(f), f.diag, f.wd, active, N, NV, ts,
+                       (double*)nullptr);
+    hipLaunchKernelGGL((k_mg_zrestrict<T, VW>), dim3(zq.nxs * q.m1 * zq.nzc), dim3(MG_WG), 0, s, (const T*)f.T,
+                       (T*)q.B, geom(f), geom(q), active, N, NV, zq);
   }
   const MgLevel& cl = c->mg[L - 1];
   const uint64_t tcl = (uint64_t)cl.n * NV;
-  hipLaunchKernelGGL(k_mg_dense<VW>, dim3(grid_of(tcl)), dim3(MG_WG), 0, s, c->mg_inv, cl.B, cl.E, (uint32_t)cl.n,
-                     active, N, NV, tcl);
+  hipLaunchKernelGGL((k_mg_dense<T, VW>), dim3(grid_of(tcl)), dim3(MG_WG), 0, s, c->mg_inv, (const T*)cl.B, (T*)cl.E,
+                     (uint32_t)cl.n, active, N, NV, tcl);
   for (int k = L - 2; k >= 0; --k) {
     const MgLevel& f = c->mg[k];
     const MgLevel& q = c->mg[k + 1];
-    const double* in = k == 0 ? r : f.B;
-    double* out = k == 0 ? z : f.E;
-    const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N);
+    const T* in = k == 0 ? r : (const T*)f.B;
+    T* out = k == 0 ? z : (T*)f.E;
+    const T* qe = (const T*)q.E;
+    const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N, sizeof(T));
     const uint32_t tgrid = ts.nxt * ts.nyt * ts.nzc;
     const bool two = 2 * (ts.TX + ts.TY) > ts.TX * ts.TY;     // ring longer than the tile: two per thread
     const dim3 grid(tgrid), block(ts.TX * ts.TY * NV);
     if (k == 0 && dots) {
       ProfScope ps(c, OPE_KERNEL_MG_POST);
       if (two)
-        hipLaunchKernelGGL((k_mg_tpost<VW, true, 2>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
-                           geom(q), f.diag, f.wd, active, N, NV, ts, c->mg_part);
+        hipLaunchKernelGGL((k_mg_tpost<T, VW, true, 2>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
+                           f.wd, active, N, NV, ts, c->mg_part);
       else
-        hipLaunchKernelGGL((k_mg_tpost<VW, true, 1>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
-                           geom(q), f.diag, f.wd, active, N, NV, ts, c->mg_part);
+        hipLaunchKernelGGL((k_mg_tpost<T, VW, true, 1>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
+                           f.wd, active, N, NV, ts, c->mg_part);
       c->mg_rows_used = tgrid;
     } else if (two) {
-      hipLaunchKernelGGL((k_mg_tpost<VW, false, 2>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
-                         geom(q), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
+      hipLaunchKernelGGL((k_mg_tpost<T, VW, false, 2>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
+                         f.wd, active, N, NV, ts, (double*)nullptr);
     } else {
-      hipLaunchKernelGGL((k_mg_tpost<VW, false, 1>), grid, block, 0, s, in, (const double*)q.E, out, geom(f),
-                         geom(q), f.diag, f.wd, active, N, NV, ts, (double*)nullptr);
+      hipLaunchKernelGGL((k_mg_tpost<T, VW, false, 1>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
+                         f.wd, active, N, NV, ts, (double*)nullptr);
     }
   }
   return hipGetLastError();
 }
 
-hipError_t mg_vcycle(ope_ctx* c, const double* r, double* z, const int32_t* active, bool dots) {
+hipError_t mg_vcycle(ope_ctx* c, const void* r, void* z, const int32_t* active, bool dots) {
   ProfScope ps(c, OPE_KERNEL_MG);
-  if (c->N % 2 == 0) return vcycle_t<2>(c, r, z, active, dots);
-  return vcycle_t<1>(c, r, z, active, dots);
+  if (c->prec == OPE_FP64) {
+    if (mg_vw(c) == 2) return vcycle_t<double, 2>(c, (const double*)r, (double*)z, active, dots);
+    return vcycle_t<double, 1>(c, (const double*)r, (double*)z, active, dots);
+  }
+  switch (mg_vw(c)) {
+    case 4: return vcycle_t<float, 4>(c, (const float*)r, (float*)z, active, dots);
+    case 2: return vcycle_t<float, 2>(c, (const float*)r, (float*)z, active, dots);
+    default: return vcycle_t<float, 1>(c, (const float*)r, (float*)z, active, dots);
+  }
 }
 
 hipError_t launch_pcg_start(ope_ctx* c) {

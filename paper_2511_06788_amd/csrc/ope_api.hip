@@ -229,7 +229,7 @@ hipError_t cg_iteration(ope_ctx* c, int it) {
   if (e != hipSuccess) return e;
   if (c->mg_on) {
     // z = B r', then beta = r'^T z / rho and the stop test on |r'|^2
-    if ((e = mg_vcycle(c, (const double*)r_nxt, c->mg_Z, c->active, true)) != hipSuccess) return e;
+    if ((e = mg_vcycle(c, r_nxt, c->mg_Z, c->active, true)) != hipSuccess) return e;
     ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
     if ((e = launch_reduce_cols(c, c->mg_part, c->mg_rows_used, 2 * N, c->mg_dots, RED_PLAIN)) != hipSuccess)
       return e;
@@ -243,7 +243,7 @@ hipError_t cg_iteration(ope_ctx* c, int it) {
 // z0 = B r0 and rho = r0^T z0.
 hipError_t pcg_begin(ope_ctx* c) {
   hipError_t e;
-  if ((e = mg_vcycle(c, (const double*)c->Rb[0], c->mg_Z, c->active, true)) != hipSuccess) return e;
+  if ((e = mg_vcycle(c, c->Rb[0], c->mg_Z, c->active, true)) != hipSuccess) return e;
   if ((e = launch_reduce_cols(c, c->mg_part, c->mg_rows_used, 2 * c->N, c->mg_dots, RED_PLAIN)) != hipSuccess)
     return e;
   return launch_pcg_start(c);
@@ -1107,6 +1107,9 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (!(op->kinetic > 0.0)) return OPE_EINVAL;
   if (N < 1 || N > n) return OPE_EINVAL;
   if (N > OPE_MAX_N_SMALL) return OPE_EUNSUPPORTED;
+  // a point's row is split into 16-byte chunks (one element when N is odd),
+  // at most one work-group's width of them
+  if (N % 2 != 0 && N > OPE_WG) return OPE_EUNSUPPORTED;
   // the stencil sweeps address one plane of the march axis with 32-bit offsets
   const int64_t plane_pts = op->dim == 3 ? op->m[0] * op->m[1] : op->m[0];
   if (plane_pts * N * (int64_t)sizeof(double) >= ((int64_t)1 << 31)) return OPE_EUNSUPPORTED;
@@ -1443,8 +1446,9 @@ ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
     c->check_every = 4;
     return OPE_OK;
   }
-  if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
-  if (c->N % 2 != 0 && c->N > 256) return OPE_EUNSUPPORTED;     // one thread per row chunk of a point
+  // one thread per row chunk of a point: at most 256 chunks per row
+  const int64_t vw = c->prec == OPE_FP64 ? (c->N % 2 == 0 ? 2 : 1) : (c->N % 4 == 0 ? 4 : (c->N % 2 == 0 ? 2 : 1));
+  if (c->N / vw > 256) return OPE_EUNSUPPORTED;
   const ope_status st = mg_build(c);
   if (st != OPE_OK) return st;
   c->mg_on = 1;
@@ -1461,10 +1465,10 @@ ope_status ope_mg_info(const ope_ctx* c, int32_t* levels, int64_t* coarsest_node
   return OPE_OK;
 }
 
-ope_status ope_mg_vcycle(ope_ctx* c, const double* R, double* Zo) {
-  if (!c || !R || !Zo || (const void*)R == (const void*)Zo) return OPE_EINVAL;
+ope_status ope_mg_vcycle(ope_ctx* c, const void* R, void* Zo) {
+  if (!c || !R || !Zo || R == (const void*)Zo) return OPE_EINVAL;
   if (!c->mg_on) return OPE_EINVAL;
-  if (c->N % 2 == 0 && ((((uintptr_t)R) | ((uintptr_t)Zo)) & 15u)) return OPE_EINVAL;
+  if (((((uintptr_t)R) | ((uintptr_t)Zo)) & 15u) != 0) return OPE_EINVAL;
   HIPCHK(mg_vcycle(c, R, Zo, nullptr, false));
   HIPCHK(hipStreamSynchronize(c->stream));
   return OPE_OK;

@@ -88,7 +88,8 @@ struct MgLevel {
   int64_t n;
   double* diag;                 // diagonal of H on this level (level 0: the context's)
   double* wd;                   // omega / diag (the damped Jacobi factor)
-  double *B, *E, *T;            // right-hand side, correction, scratch (n x N each; level 0: T only)
+  void *B, *E, *T;              // right-hand side, correction, scratch (n x N each, the context's
+                                // storage type; level 0: T only)
 };
 
 struct ope_ctx {
@@ -170,7 +171,7 @@ struct ope_ctx {
   int mg_levels;
   MgLevel mg[OPE_MG_MAX_LEVELS];
   double* mg_inv;               // coarsest level: dense inverse, row-major nc x nc
-  double* mg_Z;                 // preconditioned residual z (n x N)
+  void* mg_Z;                   // preconditioned residual z (n x N, the context's storage type)
   double* mg_part;              // partial rows of r^T z and r^T r (mg_rows x 2N)
   int64_t mg_rows;
   int64_t mg_rows_used;         // partial rows written by the last V-cycle with dots
@@ -239,7 +240,7 @@ ope_status mg_build(ope_ctx* c);          // the hierarchy for the context's ope
 void mg_free(ope_ctx* c);
 // z = B r (one V-cycle) for the columns still active (all when active is
 // NULL); with dots, also the partial rows of r^T z and r^T r into c->mg_part
-hipError_t mg_vcycle(ope_ctx* c, const double* r, double* z, const int32_t* active, bool dots);
+hipError_t mg_vcycle(ope_ctx* c, const void* r, void* z, const int32_t* active, bool dots);
 // PCG scalars from the reduced dots: start (rho = r^T z) and the beta update
 hipError_t launch_pcg_start(ope_ctx* c);
 hipError_t launch_pcg_beta(ope_ctx* c);

@@ -13,6 +13,9 @@ against the oracle's V-cycle and preconditioned CG (oracle/multigrid.py).
   1-4; at 64^3 with N = 128 a step needs far fewer inner iterations than the
   plain CG, keeps the block orthonormal and lowers the energy.
 * Batched steps of problems with the preconditioner equal their single steps.
+* Mixed precision: the FP32 V-cycle equals the oracle's to FP32 rounding, and
+  a mixed solve with the preconditioner followed by an FP64 one reaches the
+  dense eigenvalues.
 """
 import numpy as np
 import pytest
@@ -180,11 +183,11 @@ def test_batched_steps_with_multigrid_equal_single_steps():
 
 def test_multigrid_refusals():
     from paper_2511_06788_amd import ope
+    q = W.wells_3d(m=8, N=257, seed=0)
+    with pytest.raises(ope.OpeError) as ei:                  # 257 single-element chunks per row
+        ope.Context(q.grid, q.V, q.N)
+    assert ei.value.status == ope.OPE_EUNSUPPORTED
     p = W.wells_3d(m=12, N=4, seed=0)
-    with ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as c:
-        with pytest.raises(ope.OpeError) as ei:
-            ope.ope_set_multigrid(c.handle, True)
-        assert ei.value.status == ope.OPE_EUNSUPPORTED
     with ope.Context(p.grid, p.V, p.N) as c:
         R = to_dev(p.U0)
         Z = empty_dev(p.grid.n, p.N)
@@ -195,3 +198,44 @@ def test_multigrid_refusals():
         assert ope.ope_mg_info(c.handle) == (len(hier.levels), hier.levels[-1].n)
         ope.ope_set_multigrid(c.handle, False)
         assert ope.ope_mg_info(c.handle) == (0, 0)
+
+
+@pytest.mark.parametrize("name", ["wells20_N8", "aniso13x11x9_N7", "2d_33x27_N6"])
+def test_fp32_vcycle_matches_oracle(name):
+    import torch
+    from paper_2511_06788_amd import ope
+    p = _case(name)
+    hier = O.Hierarchy(_op(p))
+    R = np.random.default_rng(8).standard_normal((p.grid.n, p.N)).astype(np.float32)
+    ref = hier.vcycle(R.astype(np.float64))
+    say(f"mg vcycle fp32 {name}")
+    with ope.Context(p.grid, p.V, p.N, kinetic=p.kinetic, shift=p.shift, precision=ope.OPE_MIXED) as c:
+        ope.ope_set_multigrid(c.handle, True)
+        Z = torch.empty((p.grid.n, p.N), dtype=torch.float32, device="cuda")
+        ope.ope_mg_vcycle(c.handle, torch.from_numpy(R).to("cuda"), Z)
+        got = Z.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+
+
+def test_mixed_solve_with_multigrid_reaches_dense_eigenvalues():
+    import torch
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=16, N=8, seed=1)
+    op = _op(p)
+    w = np.linalg.eigvalsh(O.assemble_H(op).toarray())
+    tau = 0.8 * 2.0 / (1.0 / w[0] - 1.0 / w[-1])
+    say("mixed + multigrid solve, then FP64 + multigrid")
+    with ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as cm, _ctx(p) as cd:
+        ope.ope_set_multigrid(cm.handle, True)
+        U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
+        # the FP32 preconditioned CG floors the mixed phase near 1e-3 (the plain
+        # FP32 CG near 1e-4): switch to FP64 there
+        sm = ope.ope_solve(cm.handle, U32, tau, 1e-3, 5000)
+        assert sm.converged == 1 and sm.inner_iterations < 8 * sm.steps
+        U = torch.empty((p.grid.n, p.N), dtype=torch.float64, device="cuda")
+        ope.ope_convert(cm.handle, U32, U, p.grid.n * p.N, True)
+        sf = ope.ope_solve(cd.handle, U, tau, 1e-10, 20000)
+        res, ritz, drift = ope.ope_residual(cd.handle, U, p.N)
+    assert sf.converged == 1
+    assert np.max(np.abs(ritz - w[:p.N]) / w[:p.N]) <= 1e-10
+    assert drift <= 1e-12

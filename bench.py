@@ -732,10 +732,11 @@ def copy_calibration(torch, gib=1.0, reps=5):
 
 
 def mg_post_bytes(n, N):
-    """Algorithmic HBM bytes of the finest post-smoothing launch of a V-cycle:
-    read r and x1, write z (three n x N FP64 blocks), the diagonal and the
-    Jacobi factors (two n-entry arrays)."""
-    return 3 * n * N * 8 + 16 * n
+    """Algorithmic HBM bytes of the finest prolongation + post-smoothing launch
+    of a V-cycle: read r and write z (two n x N FP64 blocks), read the coarse
+    correction (an eighth of a block), the diagonal and the Jacobi factors
+    (two n-entry arrays)."""
+    return 2.125 * n * N * 8 + 16 * n
 
 
 def step_rate(ope, torch, p, args, multigrid):

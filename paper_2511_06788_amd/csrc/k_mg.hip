@@ -465,7 +465,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
                                                     const double* __restrict__ diag, const double* __restrict__ wd,
                                                     const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
                                                     TShape ts, double* __restrict__ part) {
-  __shared__ __align__(16) T tile[MG_TLDS_BYTES / sizeof(T)];
+  // two tile buffers (planes alternate), so one barrier per plane suffices
+  __shared__ __align__(16) T tiles[2][MG_TLDS_BYTES / sizeof(T)];
   const uint32_t t = threadIdx.x;
   const uint32_t v = t % NV, pt = t / NV;
   const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
@@ -534,6 +535,7 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
   zero(srz);
   zero(srr);
   for (uint32_t z = z0; z < z1; ++z, p += s2) {
+    T* tile = tiles[z & 1];
 #pragma unroll
     for (int k = 0; k < VW; ++k) tile[slot(tx + 1, ty + 1) + k] = fc[k];
 #pragma unroll
@@ -584,7 +586,6 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
         }
       }
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       fm[k] = fc[k];
@@ -592,7 +593,8 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
     }
   }
   if constexpr (DOTS) {
-    double* red = reinterpret_cast<double*>(tile);
+    __syncthreads();              // the last plane's reads are done
+    double* red = reinterpret_cast<double*>(tiles[0]);
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       red[(t * VW + k) * 2 + 0] = srz[k];

@@ -12,9 +12,10 @@ plain CG step is measured beside it), the FP64 small solve and the in-place
 update.  Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line: outer steps per second (whole job, one GPU), the live
-roofline of the dominant kernel (the finest post-smoothing of the V-cycle;
-CG sweep B for the plain CG step; timed with HIP events on the library's
-stream), per-kernel timings, the mixed-precision and learned forms'
+roofline of the dominant kernel (CG sweep B in both the preconditioned and the
+plain CG step, timed with HIP events on the library's stream), per-kernel
+timings (the V-cycle's fused post-smoothing with its counter traffic among
+them), the mixed-precision and learned forms'
 steps per second on the same workload, measured time-to-residual-1e-8 (plain
 FP64; mixed precision to 1e-4 then FP64; learned steps judged by the plain
 step) on problems that converge within the run (64^3 and 96^3 grids, N = 17,
@@ -741,10 +742,10 @@ def mg_post_bytes(n, N):
 
 def step_rate(ope, torch, p, args, multigrid):
     """Outer steps per second of the plain FP64 step on workload p over the
-    window (warm-up, then timed steps from the seeded start), with the live
-    roofline of the dominant kernel: the finest post-smoothing of the V-cycle
-    with the multigrid-preconditioned Step 1, CG sweep B without it (HIP events
-    the library records on its own stream, over the timed steps)."""
+    window (warm-up, then timed steps from the seeded start), with or without
+    the multigrid-preconditioned Step 1, with the live roofline of the dominant
+    kernel, CG sweep B (HIP events the library records on its own stream, over
+    the timed steps)."""
     n, N = p.grid.n, p.N
     U = torch.from_numpy(p.U0).to("cuda")
     ctx = ope.Context(p.grid, p.V, N)
@@ -756,8 +757,11 @@ def step_rate(ope, torch, p, args, multigrid):
     for _ in range(args.warmup):
         ope.ope_step(h, U, args.tau)
     torch.cuda.synchronize()
-    kid = ope.OPE_KERNEL_MG_POST if multigrid else ope.OPE_KERNEL_CG_SWEEP_B
-    ope.ope_profile_begin(h, kid)
+    # the dominant kernel of both steps is CG sweep B (at 64^3, N = 128 with the
+    # V-cycle: its two forms 1.5 ms of a 6.9 ms step, then the four row
+    # products 1.1 ms and the fused post-smoothing 0.7 ms; without the V-cycle
+    # 8.2 ms of 28.6)
+    ope.ope_profile_begin(h, ope.OPE_KERNEL_CG_SWEEP_B)
     inner = 0
     last = None
     torch.cuda.synchronize()
@@ -770,21 +774,12 @@ def step_rate(ope, torch, p, args, multigrid):
     launches, total_ms = ope.ope_profile_end(h)
     dt = t1 - t0
     ms_per_step = 1e3 * dt / max(args.steps, 1)
-    if multigrid:
-        # one finest post-smoothing per V-cycle: the start of every step's
-        # PCG and each counted iteration; the V-cycles of iterations past
-        # convergence find no active column and return at once
-        working = args.steps + inner
-        nbytes = mg_post_bytes(n, N)
-        traffic = traffic_from_pmc(n, N, "mg_post")
-        name = "mg_post"
-    else:
-        # every counted CG iteration runs one full sweep B (launches past the
-        # last converged column of a chunk return at once)
-        working = inner
-        nbytes = sweep_b_bytes(n, N)
-        traffic = traffic_from_pmc(n, N, "cg_sweep_b")
-        name = "cg_sweep_b"
+    # every counted CG iteration runs one full sweep B (launches past the last
+    # converged column of a chunk return at once)
+    working = inner
+    nbytes = sweep_b_bytes(n, N)
+    traffic = traffic_from_pmc(n, N, "cg_sweep_b")
+    name = "cg_sweep_b"
     avg_ms = total_ms / max(working, 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     res = {
@@ -824,6 +819,10 @@ def step_rate(ope, torch, p, args, multigrid):
             b = mg_post_bytes(n, N) if kname == "mg_post" else kernel_bytes(kname, n, N)
             if b:
                 rec["GB/s"] = b / (rec["avg_ms"] * 1e-3) / 1e9
+                rec["frac"] = rec["GB/s"] / HBM_PEAK_GBS
+            if kname == "mg_post":
+                rec["algorithmic_bytes"] = b
+                rec["traffic"] = traffic_from_pmc(n, N, "mg_post")
             if kname == "gram":
                 rec["TFLOP/s_fp64"] = 2.0 * n * N * N / (rec["avg_ms"] * 1e-3) / 1e12
             if kname == "rowmm":

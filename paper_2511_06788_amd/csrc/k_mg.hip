@@ -205,35 +205,53 @@ __device__ __forceinline__ ZPos zpos(const MgGeom& g, const ZMarch& zs, const in
   return q;
 }
 
-// KIND 0 (pre-smoothing residual): field x0 = omega b / d, out = b - H x0.
-// KIND 1 (post-smoothing): field x1 = T, out = x1 + omega (b - H x1) / d; with
-// DOTS the work-group's per-column sums of b out and b b (the tile's columns
-// added in order) form row blockIdx.x of part (2N columns: r^T z, then r^T r).
-// x-y tiled form of the stencil sweeps: a work-group of TX TY NV threads owns
-// a TX x TY tile of grid columns (thread t: vector t % NV of column t / NV)
-// over ZC planes.  At each plane the tile's field values and those of the
-// one-column ring around it go to LDS, so the x and y neighbours come from
-// LDS (each ring value is loaded once per work-group instead of by every
-// neighbouring thread), and the z neighbours stay in registers.
+// x-y tiled form of the stencil sweeps: a work-group of TX TY NVS threads
+// owns a TX x TY tile of grid columns over ZC planes, for one slice of NVS
+// consecutive vector groups (of the NV = N / VW of a row; thread t: group
+// t % NVS of the slice, column t / NVS).  At each plane the tile's field
+// values and those of the one-column ring around it go to LDS, so the x and y
+// neighbours come from LDS (each ring value is loaded once per work-group
+// instead of by every neighbouring thread), and the z neighbours stay in
+// registers.  Slicing the row lets the tile grow (the ring costs 2(TX + TY) + 4
+// extra columns per TX TY) within the same threads and LDS.
 struct TShape {
-  uint32_t TX, TY, nxt, nyt, nzc, ZC;
+  uint32_t TX, TY, nxt, nyt, nzc, ZC, NS, NVS;
 };
 
 constexpr uint32_t MG_TWG = 1024;                 // threads of a tiled work-group (at most)
-constexpr uint32_t MG_TLDS_BYTES = 65536;         // LDS of a tiled work-group
+constexpr uint32_t MG_TLDS_BYTES = 36864;         // LDS of one plane's tile and ring
+
+// Slices of a row: as many as keep a slice at least 8 vector groups wide (a
+// 128-byte run of FP64 pairs), dividing NV.
+uint32_t tslices(uint32_t NV) {
+  uint32_t ns = 1;
+  while (NV % (2 * ns) == 0 && NV / (2 * ns) >= 8) ns *= 2;
+  return ns;
+}
 
 TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N, uint32_t esz) {
   TShape s;
-  const uint32_t P = MG_TWG / NV;                 // columns per work-group
+  s.NS = tslices(NV);
+  s.NVS = NV / s.NS;
+  // columns per work-group: as many as MG_TWG threads hold (measured at 64^3,
+  // N = 128: 1024 threads on 16 x 8 tiles beat 512 on 8 x 8 and 256 on 8 x 4,
+  // whose rings cost more than the extra work-groups per compute unit gain)
+  const uint32_t P = std::max(1u, MG_TWG / s.NVS);
+  const uint64_t rowb = (uint64_t)(N / s.NS) * esz;      // LDS bytes of one column's slice
   uint32_t tx = 1;
   while ((tx * 2) * (tx * 2) <= P) tx *= 2;       // a square tile of powers of two, x side first
   if (tx * tx * 2 <= P) tx *= 2;
   s.TX = std::min(tx, m0);
   s.TY = std::max(1u, std::min(P / s.TX, m1));
-  while ((s.TX + 2) * (s.TY + 2) * N * esz > MG_TLDS_BYTES && s.TY > 1) --s.TY;
+  // fit the tile and its ring in the LDS array (a 1 x 1 tile always fits:
+  // 9 columns of at most 4 KB)
+  while ((uint64_t)(s.TX + 2) * (s.TY + 2) * rowb > MG_TLDS_BYTES && s.TX * s.TY > 1) {
+    if (s.TY > 1) --s.TY;
+    else --s.TX;
+  }
   s.nxt = (m0 + s.TX - 1) / s.TX;
   s.nyt = (m1 + s.TY - 1) / s.TY;
-  const uint64_t tiles = (uint64_t)s.nxt * s.nyt;
+  const uint64_t tiles = (uint64_t)s.nxt * s.nyt * s.NS;
   uint64_t nzc = (512 + tiles - 1) / tiles;       // at least 512 work-groups when the grid allows
   if (nzc > m2) nzc = m2;
   if (nzc < 1) nzc = 1;
@@ -242,20 +260,38 @@ TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N, ui
   return s;
 }
 
-template <typename T, int VW, int KIND, bool DOTS>
-__global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b, const T* __restrict__ X1,
-                                                       T* __restrict__ out, MgGeom g,
+// Work-group L of a tiled sweep: tile (xt, yt), z chunk zc, slice sl; `row` is
+// its partial-sum row (the tile and chunk; the slices of one tile share it).
+struct TPos {
+  uint32_t xt, yt, zc, sl, row;
+};
+
+__device__ __forceinline__ TPos tpos(const TShape& ts, uint32_t L) {
+  TPos q;
+  q.xt = L % ts.nxt;
+  uint32_t r = L / ts.nxt;
+  q.yt = r % ts.nyt;
+  r /= ts.nyt;
+  q.zc = r % ts.nzc;
+  q.sl = r / ts.nzc;
+  q.row = (q.zc * ts.nyt + q.yt) * ts.nxt + q.xt;
+  return q;
+}
+
+// Pre-smoothing residual r1 = b - H x0 with x0 = omega b / d formed on the fly,
+// as an x-y tiled sweep (see TShape).
+template <typename T, int VW>
+__global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b, T* __restrict__ out, MgGeom g,
                                                        const double* __restrict__ diag, const double* __restrict__ wd,
-                                                       const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                       TShape ts, double* __restrict__ part) {
+                                                       const int32_t* __restrict__ active, uint32_t N, TShape ts) {
   __shared__ __align__(16) T tile[MG_TLDS_BYTES / sizeof(T)];
   const uint32_t t = threadIdx.x;
-  const uint32_t v = t % NV, pt = t / NV;
+  const uint32_t NVS = ts.NVS;
+  const uint32_t vl = t % NVS, pt = t / NVS;
   const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
-  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t xt = L % ts.nxt, r = L / ts.nxt;
-  const uint32_t yt = r % ts.nyt, zc = r / ts.nyt;
-  const uint32_t x0 = xt * ts.TX, y0 = yt * ts.TY;
+  const TPos wp = tpos(ts, xcd_remap(blockIdx.x, gridDim.x));
+  const uint32_t v = wp.sl * NVS + vl, zc = wp.zc;
+  const uint32_t x0 = wp.xt * ts.TX, y0 = wp.yt * ts.TY;
   const uint32_t x = x0 + tx, y = y0 + ty;
   const bool inb = x < g.m0 && y < g.m1;
   const bool act = vec_active<VW>(active, v);
@@ -263,12 +299,9 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b,
   const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
   const uint64_t s2 = (uint64_t)g.m0 * g.m1;
   const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
-  auto field = [&](uint64_t at, T(&f)[VW]) {
-    if constexpr (KIND == 0) jac0<T, VW>(b, wd, at, N, v, f);
-    else ldr<T, VW>(X1, at, N, v, f);
-  };
+  auto field = [&](uint64_t at, T(&f)[VW]) { jac0<T, VW>(b, wd, at, N, v, f); };
   // LDS slot of tile-local column (cx, cy) (ring included: cx, cy in [0, W) x [0, TY + 2))
-  auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NV + v) * VW; };
+  auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NVS + vl) * VW; };
   T fm[VW], fc[VW], fp[VW];
   zero(fm);
   zero(fc);
@@ -277,9 +310,6 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b,
     if (z0 > 0) field(p - s2, fm);
     field(p, fc);
   }
-  double srz[VW], srr[VW];
-  zero(srz);
-  zero(srr);
   for (uint32_t z = z0; z < z1; ++z, p += s2) {
     // the tile's own values, then the ring (column k of the ring: bottom row,
     // top row, left column, right column), zero outside the grid
@@ -309,12 +339,11 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b,
     zero(fp);
     T bc[VW];
     zero(bc);
-    T d = T(0), w = T(0);
+    T d = T(0);
     if (own) {
       if (z + 1 < g.m2) field(p + s2, fp);
       ldr<T, VW>(b, p, N, v, bc);
       d = (T)diag[p];
-      if constexpr (KIND == 1) w = (T)wd[p];
     }
     __syncthreads();
     if (own) {
@@ -325,44 +354,15 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b,
       for (int k = 0; k < VW; ++k) {
         const T hxv = d * fc[k] - ((T)g.cx * (tile[sxm + k] + tile[sxp + k]) +
                                    (T)g.cy * (tile[sym + k] + tile[syp + k]) + (T)g.cz * (fm[k] + fp[k]));
-        if constexpr (KIND == 0) o[k] = bc[k] - hxv;
-        else o[k] = fc[k] + w * (bc[k] - hxv);
+        o[k] = bc[k] - hxv;
       }
       str<T, VW>(out, p, N, v, o);
-      if constexpr (DOTS) {
-#pragma unroll
-        for (int k = 0; k < VW; ++k) {
-          srz[k] += (double)bc[k] * (double)o[k];
-          srr[k] += (double)bc[k] * (double)bc[k];
-        }
-      }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       fm[k] = fc[k];
       fc[k] = fp[k];
-    }
-  }
-  if constexpr (DOTS) {
-    // per-column sums over the tile's columns in order (LDS reused)
-    double* red = reinterpret_cast<double*>(tile);
-#pragma unroll
-    for (int k = 0; k < VW; ++k) {
-      red[(t * VW + k) * 2 + 0] = srz[k];
-      red[(t * VW + k) * 2 + 1] = srr[k];
-    }
-    __syncthreads();
-    for (uint32_t c = t; c < N; c += blockDim.x) {
-      const uint32_t cv = c / VW, ck = c % VW;
-      double a = 0.0, bs = 0.0;
-      for (uint32_t l = 0; l < P; ++l) {
-        const uint32_t th = l * NV + cv;
-        a += red[(th * VW + ck) * 2 + 0];
-        bs += red[(th * VW + ck) * 2 + 1];
-      }
-      part[(uint64_t)blockIdx.x * 2 * N + c] = a;
-      part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
     }
   }
 }
@@ -463,17 +463,17 @@ template <typename T, int VW, bool DOTS, int R>
 __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, const T* __restrict__ E,
                                                     T* __restrict__ out, MgGeom g, MgGeom cg,
                                                     const double* __restrict__ diag, const double* __restrict__ wd,
-                                                    const int32_t* __restrict__ active, uint32_t N, uint32_t NV,
-                                                    TShape ts, double* __restrict__ part) {
+                                                    const int32_t* __restrict__ active, uint32_t N, TShape ts,
+                                                    double* __restrict__ part) {
   // two tile buffers (planes alternate), so one barrier per plane suffices
   __shared__ __align__(16) T tiles[2][MG_TLDS_BYTES / sizeof(T)];
   const uint32_t t = threadIdx.x;
-  const uint32_t v = t % NV, pt = t / NV;
+  const uint32_t NVS = ts.NVS;
+  const uint32_t vl = t % NVS, pt = t / NVS;
   const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
-  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t xt = L % ts.nxt, r = L / ts.nxt;
-  const uint32_t yt = r % ts.nyt, zc = r / ts.nyt;
-  const uint32_t x0 = xt * ts.TX, y0 = yt * ts.TY;
+  const TPos wp = tpos(ts, xcd_remap(blockIdx.x, gridDim.x));
+  const uint32_t v = wp.sl * NVS + vl, zc = wp.zc;
+  const uint32_t x0 = wp.xt * ts.TX, y0 = wp.yt * ts.TY;
   const uint32_t x = x0 + tx, y = y0 + ty;
   const bool inb = x < g.m0 && y < g.m1;
   const bool act = vec_active<VW>(active, v);
@@ -481,15 +481,15 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
   const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
   const uint64_t s2 = (uint64_t)g.m0 * g.m1;
   const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
-  auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NV + v) * VW; };
+  auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NVS + vl) * VW; };
   // x1 at fine point `at` with the column's P e value pe
   auto x1 = [&](uint64_t at, const T(&pe)[VW], T(&f)[VW]) {
     jac0<T, VW>(b, wd, at, N, v, f);
 #pragma unroll
     for (int k = 0; k < VW; ++k) f[k] = f[k] + pe[k];
   };
-  // ring columns of this thread: k = pt + j P, j < R (R = 2 when the ring is
-  // longer than the tile has columns)
+  // ring columns of this thread: k = pt + j P, j < R (R P at least the ring's
+  // 2 (TX + TY) columns)
   uint32_t rk[R], rcx[R], rcy[R];
   int64_t rhx[R], rhy[R];
   bool rin[R];
@@ -593,24 +593,22 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
     }
   }
   if constexpr (DOTS) {
-    __syncthreads();              // the last plane's reads are done
-    double* red = reinterpret_cast<double*>(tiles[0]);
+    // per-column sums over the tile's columns in order, b z then b b (LDS
+    // reused, one quantity at a time)
+    double* red = reinterpret_cast<double*>(&tiles[0][0]);
+    const uint32_t SC = NVS * VW, c0 = wp.sl * SC;
 #pragma unroll
-    for (int k = 0; k < VW; ++k) {
-      red[(t * VW + k) * 2 + 0] = srz[k];
-      red[(t * VW + k) * 2 + 1] = srr[k];
-    }
-    __syncthreads();
-    for (uint32_t c = t; c < N; c += blockDim.x) {
-      const uint32_t cv = c / VW, ck = c % VW;
-      double a = 0.0, bs = 0.0;
-      for (uint32_t l = 0; l < P; ++l) {
-        const uint32_t th = l * NV + cv;
-        a += red[(th * VW + ck) * 2 + 0];
-        bs += red[(th * VW + ck) * 2 + 1];
+    for (int q = 0; q < 2; ++q) {
+      __syncthreads();            // the last plane's (or the previous pass's) reads are done
+#pragma unroll
+      for (int k = 0; k < VW; ++k) red[t * VW + k] = q == 0 ? srz[k] : srr[k];
+      __syncthreads();
+      for (uint32_t c = t; c < SC; c += blockDim.x) {
+        const uint32_t cv = c / VW, ck = c % VW;
+        double a = 0.0;
+        for (uint32_t l = 0; l < P; ++l) a += red[(l * NVS + cv) * VW + ck];
+        part[(uint64_t)wp.row * 2 * N + (uint64_t)q * N + c0 + c] = a;
       }
-      part[(uint64_t)blockIdx.x * 2 * N + c] = a;
-      part[(uint64_t)blockIdx.x * 2 * N + N + c] = bs;
     }
   }
 }
@@ -919,9 +917,8 @@ static hipError_t vcycle_t(ope_ctx* c, const T* r, T* z, const int32_t* active, 
     const T* in = k == 0 ? r : (const T*)f.B;
     const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N, sizeof(T));
     const ZMarch zq = zmarch_shape(q.m0, q.m1, q.m2, NV);
-    hipLaunchKernelGGL((k_mg_tstencil<T, VW, 0, false>), dim3(ts.nxt * ts.nyt * ts.nzc), dim3(ts.TX * ts.TY * NV), 0,
-                       s, in, (const T*)nullptr, (T*)f.T, geom(f), f.diag, f.wd, active, N, NV, ts,
-                       (double*)nullptr);
+    hipLaunchKernelGGL((k_mg_tstencil<T, VW>), dim3(ts.nxt * ts.nyt * ts.nzc * ts.NS), dim3(ts.TX * ts.TY * ts.NVS),
+                       0, s, in, (T*)f.T, geom(f), f.diag, f.wd, active, N, ts);
     hipLaunchKernelGGL((k_mg_zrestrict<T, VW>), dim3(zq.nxs * q.m1 * zq.nzc), dim3(MG_WG), 0, s, (const T*)f.T,
                        (T*)q.B, geom(f), geom(q), active, N, NV, zq);
   }
@@ -936,24 +933,28 @@ static hipError_t vcycle_t(ope_ctx* c, const T* r, T* z, const int32_t* active, 
     T* out = k == 0 ? z : (T*)f.E;
     const T* qe = (const T*)q.E;
     const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N, sizeof(T));
-    const uint32_t tgrid = ts.nxt * ts.nyt * ts.nzc;
-    const bool two = 2 * (ts.TX + ts.TY) > ts.TX * ts.TY;     // ring longer than the tile: two per thread
-    const dim3 grid(tgrid), block(ts.TX * ts.TY * NV);
-    if (k == 0 && dots) {
-      ProfScope ps(c, OPE_KERNEL_MG_POST);
-      if (two)
-        hipLaunchKernelGGL((k_mg_tpost<T, VW, true, 2>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
-                           f.wd, active, N, NV, ts, c->mg_part);
-      else
-        hipLaunchKernelGGL((k_mg_tpost<T, VW, true, 1>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
-                           f.wd, active, N, NV, ts, c->mg_part);
-      c->mg_rows_used = tgrid;
-    } else if (two) {
-      hipLaunchKernelGGL((k_mg_tpost<T, VW, false, 2>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
-                         f.wd, active, N, NV, ts, (double*)nullptr);
-    } else {
-      hipLaunchKernelGGL((k_mg_tpost<T, VW, false, 1>), grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag,
-                         f.wd, active, N, NV, ts, (double*)nullptr);
+    const uint32_t rows = ts.nxt * ts.nyt * ts.nzc;
+    // ring columns per thread: ceil(2 (TX + TY) / (TX TY)) <= 4, as 1, 2 or 4
+    const uint32_t P = ts.TX * ts.TY, need = (2 * (ts.TX + ts.TY) + P - 1) / P;
+    const int R = need <= 1 ? 1 : need <= 2 ? 2 : 4;
+    const dim3 grid(rows * ts.NS), block(P * ts.NVS);
+    const bool d = k == 0 && dots;
+    double* part = d ? c->mg_part : nullptr;
+    auto post = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, block, 0, s, in, qe, out, geom(f), geom(q), f.diag, f.wd, active, N, ts, part);
+    };
+    {
+      ProfScope ps(c, d ? OPE_KERNEL_MG_POST : OPE_KERNEL_COUNT);   // only the finest level is timed
+      if (d) {
+        if (R == 1) post(k_mg_tpost<T, VW, true, 1>);
+        else if (R == 2) post(k_mg_tpost<T, VW, true, 2>);
+        else post(k_mg_tpost<T, VW, true, 4>);
+        c->mg_rows_used = rows;
+      } else {
+        if (R == 1) post(k_mg_tpost<T, VW, false, 1>);
+        else if (R == 2) post(k_mg_tpost<T, VW, false, 2>);
+        else post(k_mg_tpost<T, VW, false, 4>);
+      }
     }
   }
   return hipGetLastError();

@@ -3,11 +3,13 @@ against the oracle's V-cycle and preconditioned CG (oracle/multigrid.py).
 
 * One V-cycle (ope_mg_vcycle) equals the oracle's ``Hierarchy.vcycle`` to
   1e-12 relative on 3D and 2D grids with odd and even sizes, a kinetic
-  factor and a shift, even and odd N, and at 64^3 with N = 128 (columns
+  factor and a shift, a grid two nodes thick (levels one node thick), even
+  and odd N, rows split into slices, and at 64^3 with N = 128 (columns
   compared against the oracle on eight of them); the hierarchy has the
   oracle's number of levels and coarsest size.
 * The preconditioned CG capped at k = 1, 2, 3, 5, 6 iterations (eager and
-  graph-replayed chunks) equals the oracle's ``pcg_source`` iterate.
+  graph-replayed chunks; N = 40 and 17 at k = 3) equals the oracle's
+  ``pcg_source`` iterate.
 * Stand-alone Step 1 converges to the sparse direct solution in a few
   iterations; steps with a tight inner solve equal the oracle's exact Steps
   1-4; at 64^3 with N = 128 a step needs far fewer inner iterations than the
@@ -49,10 +51,23 @@ def _case(name):
         g = W.Grid(m=(33, 27), h=(1.0 / 34, 1.0 / 28), lo=(0.0, 0.0))
         V = W.harmonic_potential(g, 80.0, (0.5, 0.5))
         return W.Problem("2d", g, V, 6, 1.0, U0=W.initial_block(g.n, 6, 2))
+    if name == "thin40x2x30_N6":
+        # y has two nodes, one on the coarse levels: tiles one column high,
+        # whose ring is longer than two columns per thread
+        g = W.Grid(m=(40, 2, 30), h=(0.05, 0.05, 0.05), lo=(0.0, 0.0, 0.0))
+        V = W.harmonic_potential(g, 30.0, (0.5, 0.5, 0.5))
+        return W.Problem("thin", g, V, 6, 1.0, U0=W.initial_block(g.n, 6, 4))
+    if name == "wells16_N40":
+        return W.wells_3d(m=16, N=40, seed=6)         # rows in two slices of 10 vector pairs
+    if name == "wells12_N17":
+        return W.wells_3d(m=12, N=17, seed=8)         # odd N: one element per vector group
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["wells20_N8", "aniso13x11x9_N7", "2d_33x27_N6"])
+VCYCLE_CASES = ["wells20_N8", "aniso13x11x9_N7", "2d_33x27_N6", "thin40x2x30_N6", "wells16_N40", "wells12_N17"]
+
+
+@pytest.mark.parametrize("name", VCYCLE_CASES)
 def test_vcycle_matches_oracle(name):
     from paper_2511_06788_amd import ope
     p = _case(name)
@@ -101,6 +116,24 @@ def test_capped_pcg_equals_oracle_iterates(k, graphs):
     st = {}
     Y_ref = O.pcg_source(op, U, None, tol=1e-15, max_iter=k, stats=st)
     assert its == k and st["iterations"] == k
+    assert np.max(np.abs(Y - Y_ref)) <= 1e-12 * np.max(np.abs(Y_ref))
+
+
+@pytest.mark.parametrize("N", [40, 17])
+def test_capped_pcg_equals_oracle_iterates_wide_rows(N):
+    """The PCG dot products of the finest post-smoothing with rows split into
+    slices (N = 40) and with odd N."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=13, N=N, seed=12)
+    op = _op(p)
+    U = W.initial_block(p.grid.n, p.N, 6)
+    say(f"capped PCG N={N}")
+    with _ctx(p) as c:
+        Yd = empty_dev(p.grid.n, p.N)
+        its = ope.ope_source_solve(c.handle, to_dev(U), Yd, None, 1e-15, 3, allow_maxit=True)
+        Y = to_host(Yd)
+    Y_ref = O.pcg_source(op, U, None, tol=1e-15, max_iter=3)
+    assert its == 3
     assert np.max(np.abs(Y - Y_ref)) <= 1e-12 * np.max(np.abs(Y_ref))
 
 
@@ -200,7 +233,7 @@ def test_multigrid_refusals():
         assert ope.ope_mg_info(c.handle) == (0, 0)
 
 
-@pytest.mark.parametrize("name", ["wells20_N8", "aniso13x11x9_N7", "2d_33x27_N6"])
+@pytest.mark.parametrize("name", VCYCLE_CASES)
 def test_fp32_vcycle_matches_oracle(name):
     import torch
     from paper_2511_06788_amd import ope

@@ -260,6 +260,13 @@ TShape tshape(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t NV, uint32_t N, ui
   return s;
 }
 
+// Ring columns per thread of a tiled sweep: ceil(2 (TX + TY) / (TX TY)) <= 4,
+// as 1, 2 or 4.
+int ring_per_thread(const TShape& ts) {
+  const uint32_t P = ts.TX * ts.TY, need = (2 * (ts.TX + ts.TY) + P - 1) / P;
+  return need <= 1 ? 1 : need <= 2 ? 2 : 4;
+}
+
 // Work-group L of a tiled sweep: tile (xt, yt), z chunk zc, slice sl; `row` is
 // its partial-sum row (the tile and chunk; the slices of one tile share it).
 struct TPos {
@@ -278,72 +285,128 @@ __device__ __forceinline__ TPos tpos(const TShape& ts, uint32_t L) {
   return q;
 }
 
+// Ring column j of a tiled work-group (k = pt + j P, k < 2 (TX + TY): bottom
+// row, top row, left column, right column): its grid x-y index (when inside
+// the grid) and its LDS slot.
+struct RingCol {
+  uint64_t col;
+  uint32_t slot;
+  bool ok, in;
+};
+
+__device__ __forceinline__ RingCol ring_col(const MgGeom& g, const TShape& ts, uint32_t x0, uint32_t y0, uint32_t k,
+                                            uint32_t NVS, uint32_t vl, uint32_t VW, bool act) {
+  RingCol rc;
+  const uint32_t RING = 2 * (ts.TX + ts.TY), W = ts.TX + 2;
+  rc.ok = k < RING;
+  rc.in = false;
+  rc.col = 0;
+  rc.slot = 0;
+  if (!rc.ok) return rc;
+  int64_t hx, hy;
+  uint32_t cx, cy;
+  if (k < ts.TX) {
+    hx = (int64_t)x0 + k; hy = (int64_t)y0 - 1; cx = k + 1; cy = 0;
+  } else if (k < 2 * ts.TX) {
+    hx = (int64_t)x0 + (k - ts.TX); hy = (int64_t)y0 + ts.TY; cx = k - ts.TX + 1; cy = ts.TY + 1;
+  } else if (k < 2 * ts.TX + ts.TY) {
+    hx = (int64_t)x0 - 1; hy = (int64_t)y0 + (k - 2 * ts.TX); cx = 0; cy = k - 2 * ts.TX + 1;
+  } else {
+    hx = (int64_t)x0 + ts.TX; hy = (int64_t)y0 + (k - 2 * ts.TX - ts.TY); cx = ts.TX + 1;
+    cy = k - 2 * ts.TX - ts.TY + 1;
+  }
+  rc.slot = ((cy * W + cx) * NVS + vl) * VW;
+  rc.in = act && hx >= 0 && hx < (int64_t)g.m0 && hy >= 0 && hy < (int64_t)g.m1;
+  if (rc.in) rc.col = (uint64_t)hy * g.m0 + (uint64_t)hx;
+  return rc;
+}
+
 // Pre-smoothing residual r1 = b - H x0 with x0 = omega b / d formed on the fly,
-// as an x-y tiled sweep (see TShape).
-template <typename T, int VW>
+// as an x-y tiled sweep (see TShape).  The loads are issued one plane ahead
+// (the ring's b and omega/d of the next plane, the own column's two planes
+// ahead), so a plane's wait finds them arrived; the two tile buffers
+// alternate, one barrier per plane.
+template <typename T, int VW, int R>
 __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b, T* __restrict__ out, MgGeom g,
                                                        const double* __restrict__ diag, const double* __restrict__ wd,
                                                        const int32_t* __restrict__ active, uint32_t N, TShape ts) {
-  __shared__ __align__(16) T tile[MG_TLDS_BYTES / sizeof(T)];
+  __shared__ __align__(16) T tiles[2][MG_TLDS_BYTES / sizeof(T)];
   const uint32_t t = threadIdx.x;
   const uint32_t NVS = ts.NVS;
   const uint32_t vl = t % NVS, pt = t / NVS;
   const uint32_t tx = pt % ts.TX, ty = pt / ts.TX;
   const TPos wp = tpos(ts, xcd_remap(blockIdx.x, gridDim.x));
-  const uint32_t v = wp.sl * NVS + vl, zc = wp.zc;
+  const uint32_t v = wp.sl * NVS + vl;
   const uint32_t x0 = wp.xt * ts.TX, y0 = wp.yt * ts.TY;
   const uint32_t x = x0 + tx, y = y0 + ty;
   const bool inb = x < g.m0 && y < g.m1;
   const bool act = vec_active<VW>(active, v);
+  if (!__syncthreads_or(act ? 1 : 0)) return;     // every column of the slice has stopped
   const bool own = inb && act;
-  const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
+  const uint32_t z0 = wp.zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
   const uint64_t s2 = (uint64_t)g.m0 * g.m1;
-  const uint32_t W = ts.TX + 2, RING = 2 * (ts.TX + ts.TY), P = ts.TX * ts.TY;
-  auto field = [&](uint64_t at, T(&f)[VW]) { jac0<T, VW>(b, wd, at, N, v, f); };
-  // LDS slot of tile-local column (cx, cy) (ring included: cx, cy in [0, W) x [0, TY + 2))
+  const uint32_t W = ts.TX + 2, P = ts.TX * ts.TY;
   auto slot = [&](uint32_t cx, uint32_t cy) -> uint32_t { return ((cy * W + cx) * NVS + vl) * VW; };
-  T fm[VW], fc[VW], fp[VW];
+  RingCol rc[R];
+  T rb[R][VW], rw[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) rc[j] = ring_col(g, ts, x0, y0, pt + (uint32_t)j * P, NVS, vl, VW, act);
+  auto ring_load = [&](uint32_t z) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      zero(rb[j]);
+      rw[j] = T(0);
+      if (rc[j].in) {
+        const uint64_t q = (uint64_t)z * s2 + rc[j].col;
+        ldr<T, VW>(b, q, N, v, rb[j]);
+        rw[j] = (T)wd[q];
+      }
+    }
+  };
+  // own column: x0 at z - 1 and z, b and d at z, the raw b and omega/d of z + 1
+  T fm[VW], fc[VW], bc[VW], bn[VW];
+  T wn = T(0), dc = T(0);
   zero(fm);
   zero(fc);
+  zero(bc);
+  zero(bn);
   uint64_t p = ((uint64_t)z0 * g.m1 + (inb ? y : 0)) * g.m0 + (inb ? x : 0);
   if (own) {
-    if (z0 > 0) field(p - s2, fm);
-    field(p, fc);
+    if (z0 > 0) jac0<T, VW>(b, wd, p - s2, N, v, fm);
+    ldr<T, VW>(b, p, N, v, bc);
+    const T w0 = (T)wd[p];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) fc[k] = w0 * bc[k];
+    dc = (T)diag[p];
+    if (z0 + 1 < g.m2) {
+      ldr<T, VW>(b, p + s2, N, v, bn);
+      wn = (T)wd[p + s2];
+    }
   }
+  ring_load(z0);
   for (uint32_t z = z0; z < z1; ++z, p += s2) {
-    // the tile's own values, then the ring (column k of the ring: bottom row,
-    // top row, left column, right column), zero outside the grid
+    T* tile = tiles[z & 1];
 #pragma unroll
     for (int k = 0; k < VW; ++k) tile[slot(tx + 1, ty + 1) + k] = fc[k];
-    for (uint32_t k = pt; k < RING; k += P) {
-      int64_t hx, hy;
-      uint32_t cx, cy;
-      if (k < ts.TX) {
-        hx = (int64_t)x0 + k; hy = (int64_t)y0 - 1; cx = k + 1; cy = 0;
-      } else if (k < 2 * ts.TX) {
-        hx = (int64_t)x0 + (k - ts.TX); hy = (int64_t)y0 + ts.TY; cx = k - ts.TX + 1; cy = ts.TY + 1;
-      } else if (k < 2 * ts.TX + ts.TY) {
-        hx = (int64_t)x0 - 1; hy = (int64_t)y0 + (k - 2 * ts.TX); cx = 0; cy = k - 2 * ts.TX + 1;
-      } else {
-        hx = (int64_t)x0 + ts.TX; hy = (int64_t)y0 + (k - 2 * ts.TX - ts.TY); cx = ts.TX + 1;
-        cy = k - 2 * ts.TX - ts.TY + 1;
-      }
-      T hv[VW];
-      zero(hv);
-      if (act && hx >= 0 && hx < (int64_t)g.m0 && hy >= 0 && hy < (int64_t)g.m1)
-        field(((uint64_t)z * g.m1 + (uint64_t)hy) * g.m0 + (uint64_t)hx, hv);
 #pragma unroll
-      for (int kk = 0; kk < VW; ++kk) tile[slot(cx, cy) + kk] = hv[kk];
-    }
-    // the next plane's own value and the centre data, loaded before the wait
-    zero(fp);
-    T bc[VW];
-    zero(bc);
-    T d = T(0);
-    if (own) {
-      if (z + 1 < g.m2) field(p + s2, fp);
-      ldr<T, VW>(b, p, N, v, bc);
-      d = (T)diag[p];
+    for (int j = 0; j < R; ++j)
+      if (rc[j].ok) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) tile[rc[j].slot + k] = rw[j] * rb[j][k];
+      }
+    // the next plane's ring and the own column two planes ahead
+    if (z + 1 < z1) ring_load(z + 1);
+    T fp[VW], b2[VW];
+    T w2 = T(0), d2 = T(0);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) fp[k] = wn * bn[k];
+    zero(b2);
+    if (own && z + 1 < z1) {
+      if (z + 2 < g.m2) {
+        ldr<T, VW>(b, p + 2 * s2, N, v, b2);
+        w2 = (T)wd[p + 2 * s2];
+      }
+      d2 = (T)diag[p + s2];
     }
     __syncthreads();
     if (own) {
@@ -352,18 +415,21 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tstencil(const T* __restrict__ b,
                      syp = slot(tx + 1, ty + 2);
 #pragma unroll
       for (int k = 0; k < VW; ++k) {
-        const T hxv = d * fc[k] - ((T)g.cx * (tile[sxm + k] + tile[sxp + k]) +
-                                   (T)g.cy * (tile[sym + k] + tile[syp + k]) + (T)g.cz * (fm[k] + fp[k]));
+        const T hxv = dc * fc[k] - ((T)g.cx * (tile[sxm + k] + tile[sxp + k]) +
+                                    (T)g.cy * (tile[sym + k] + tile[syp + k]) + (T)g.cz * (fm[k] + fp[k]));
         o[k] = bc[k] - hxv;
       }
       str<T, VW>(out, p, N, v, o);
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       fm[k] = fc[k];
       fc[k] = fp[k];
+      bc[k] = bn[k];
+      bn[k] = b2[k];
     }
+    wn = w2;
+    dc = d2;
   }
 }
 
@@ -477,6 +543,16 @@ __global__ __launch_bounds__(MG_TWG) void k_mg_tpost(const T* __restrict__ b, co
   const uint32_t x = x0 + tx, y = y0 + ty;
   const bool inb = x < g.m0 && y < g.m1;
   const bool act = vec_active<VW>(active, v);
+  if (!__syncthreads_or(act ? 1 : 0)) {          // every column of the slice has stopped
+    if constexpr (DOTS) {
+      const uint32_t SC = ts.NVS * VW, c0 = wp.sl * SC;
+      for (uint32_t c = t; c < SC; c += blockDim.x) {
+        part[(uint64_t)wp.row * 2 * N + c0 + c] = 0.0;
+        part[(uint64_t)wp.row * 2 * N + N + c0 + c] = 0.0;
+      }
+    }
+    return;
+  }
   const bool own = inb && act;
   const uint32_t z0 = zc * ts.ZC, z1 = z0 + ts.ZC < g.m2 ? z0 + ts.ZC : g.m2;
   const uint64_t s2 = (uint64_t)g.m0 * g.m1;
@@ -917,8 +993,20 @@ static hipError_t vcycle_t(ope_ctx* c, const T* r, T* z, const int32_t* active, 
     const T* in = k == 0 ? r : (const T*)f.B;
     const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N, sizeof(T));
     const ZMarch zq = zmarch_shape(q.m0, q.m1, q.m2, NV);
-    hipLaunchKernelGGL((k_mg_tstencil<T, VW>), dim3(ts.nxt * ts.nyt * ts.nzc * ts.NS), dim3(ts.TX * ts.TY * ts.NVS),
-                       0, s, in, (T*)f.T, geom(f), f.diag, f.wd, active, N, ts);
+    const dim3 sgrid(ts.nxt * ts.nyt * ts.nzc * ts.NS), sblock(ts.TX * ts.TY * ts.NVS);
+    switch (ring_per_thread(ts)) {
+      case 1:
+        hipLaunchKernelGGL((k_mg_tstencil<T, VW, 1>), sgrid, sblock, 0, s, in, (T*)f.T, geom(f), f.diag, f.wd, active,
+                           N, ts);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_mg_tstencil<T, VW, 2>), sgrid, sblock, 0, s, in, (T*)f.T, geom(f), f.diag, f.wd, active,
+                           N, ts);
+        break;
+      default:
+        hipLaunchKernelGGL((k_mg_tstencil<T, VW, 4>), sgrid, sblock, 0, s, in, (T*)f.T, geom(f), f.diag, f.wd, active,
+                           N, ts);
+    }
     hipLaunchKernelGGL((k_mg_zrestrict<T, VW>), dim3(zq.nxs * q.m1 * zq.nzc), dim3(MG_WG), 0, s, (const T*)f.T,
                        (T*)q.B, geom(f), geom(q), active, N, NV, zq);
   }
@@ -934,9 +1022,8 @@ static hipError_t vcycle_t(ope_ctx* c, const T* r, T* z, const int32_t* active, 
     const T* qe = (const T*)q.E;
     const TShape ts = tshape(f.m0, f.m1, f.m2, NV, N, sizeof(T));
     const uint32_t rows = ts.nxt * ts.nyt * ts.nzc;
-    // ring columns per thread: ceil(2 (TX + TY) / (TX TY)) <= 4, as 1, 2 or 4
-    const uint32_t P = ts.TX * ts.TY, need = (2 * (ts.TX + ts.TY) + P - 1) / P;
-    const int R = need <= 1 ? 1 : need <= 2 ? 2 : 4;
+    const uint32_t P = ts.TX * ts.TY;
+    const int R = ring_per_thread(ts);
     const dim3 grid(rows * ts.NS), block(P * ts.NVS);
     const bool d = k == 0 && dots;
     double* part = d ? c->mg_part : nullptr;

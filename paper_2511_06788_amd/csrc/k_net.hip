@@ -21,6 +21,8 @@
 // accumulator gives each lane four consecutive output channels of one voxel
 // and a wave stores 16 voxels x 32 bytes contiguously.  A work-group computes
 // a 16 x 4 x 4 voxel tile from an LDS copy of the 18 x 6 x 6 input tile.
+// The last forward layer (one output channel) is a dot product per voxel on
+// the vector ALUs instead, z-marched through a ring of LDS planes (k_conv_out1).
 // Backward: the data gradient of a layer is the same convolution with the
 // weights transposed in the channels and flipped in the taps, masked by the
 // ReLU pattern of the forward activation; weight gradients are contractions
@@ -41,7 +43,7 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 constexpr int TX = 16, TY = 4, TZ = 4;          // output tile of a work-group
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HV = HX * HY * HZ;                // staged input voxels (with halo)
-enum { EPI_RELU = 0, EPI_MASK = 1, EPI_F32 = 2 };
+enum { EPI_RELU = 0, EPI_MASK = 1 };
 
 // weight block offsets (FP32 masters) and packed BF16 operand offsets
 constexpr int W1_OFF = 0, W2_OFF = 864, W3_OFF = 7776, W4_OFF = 14688;
@@ -168,30 +170,108 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     const int gy = y0 + yb;
     if (gy >= (int)m1) break;
     const uint64_t v = ((uint64_t)gz * m1 + gy) * m0 + gx;
-    if constexpr (EPI == EPI_F32) {
-      if (kq == 0) reinterpret_cast<float*>(out)[(uint64_t)b * n + v] = acc[yb][0];
+    const uint64_t o = ((uint64_t)b * n + v) * 16 + 4 * kq;
+    float r[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = acc[yb][e];
+    if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) r[e] = r[e] > 0.f ? r[e] : 0.f;
     } else {
-      const uint64_t o = ((uint64_t)b * n + v) * 16 + 4 * kq;
-      float r[4];
+      const uint2 mk = *reinterpret_cast<const uint2*>(mask + o);
+      const uint32_t mw[2] = {mk.x, mk.y};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) r[e] = acc[yb][e];
-      if constexpr (EPI == EPI_RELU) {
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t mb = (uint16_t)(mw[e >> 1] >> (16 * (e & 1)));
+        if (!(from_bf16(mb) > 0.f)) r[e] = 0.f;
+      }
+    }
+    uint2 w;
+    w.x = (uint32_t)to_bf16(r[0]) | ((uint32_t)to_bf16(r[1]) << 16);
+    w.y = (uint32_t)to_bf16(r[2]) | ((uint32_t)to_bf16(r[3]) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + o) = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last forward layer (16 channels -> 1, FP32 output): per voxel a dot product
+// of length 27 x 16 with one weight vector shared by every voxel, so it runs
+// on the vector ALUs (an MFMA tile would compute 16 output channels for the
+// one that exists).  A work-group owns a 16 x 16 x-y tile of one sample and
+// marches along z over OZ planes: the input planes pass through a ring of
+// three 18 x 18 LDS planes (each staged once, halo 1.27x), and each thread
+// adds, for its voxel, tap by tap and channel by channel in FP32 (fused
+// multiply-adds), the BF16 weights of the packed row (k = 16 tap + channel)
+// times the inputs.  (The BF16 dot2 instruction would take a quarter of the
+// instructions but does not keep the FP32 accuracy of these sums.)
+// ---------------------------------------------------------------------------
+constexpr int OX = 16, OY = 16, OZ = 16;        // x-y tile and z run of a work-group
+constexpr int OHX = OX + 2, OHY = OY + 2, OPL = OHX * OHY;
+
+__global__ __launch_bounds__(256) void k_conv_out1(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wrow,
+                                                   float* __restrict__ out, uint32_t m0, uint32_t m1, uint32_t m2,
+                                                   uint32_t ntx, uint32_t nty, uint32_t ntz) {
+  __shared__ __align__(16) v4u ring[3][2][OPL];   // [plane slot][channel half][voxel of the 18 x 18 plane]
+  __shared__ __align__(16) float wsh[27 * 16];
+  const uint32_t tiles = ntx * nty * ntz;
+  const uint32_t b = blockIdx.x / tiles;
+  uint32_t t = blockIdx.x - b * tiles;
+  const uint32_t tx = t % ntx;
+  t /= ntx;
+  const uint32_t ty = t % nty;
+  const uint32_t tz = t / nty;
+  const int x0 = (int)(tx * OX), y0 = (int)(ty * OY), z0 = (int)(tz * OZ);
+  const int z1 = z0 + OZ < (int)m2 ? z0 + OZ : (int)m2;
+  const uint64_t n = (uint64_t)m0 * m1 * m2;
+  const uint16_t* src = in + (uint64_t)b * n * 16;
+  // input plane z (zeros outside the grid) into ring slot (z + 1) mod 3
+  auto stage = [&](int z) {
+    v4u* dst = &ring[(z + 3 + 1) % 3][0][0];
+    for (int idx = threadIdx.x; idx < 2 * OPL; idx += 256) {
+      const int h = idx & 1, v = idx >> 1;
+      const int gx = x0 + v % OHX - 1, gy = y0 + v / OHX - 1;
+      v4u val = {0u, 0u, 0u, 0u};
+      if (z >= 0 && z < (int)m2 && gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1)
+        val = *reinterpret_cast<const v4u*>(src + (((uint64_t)z * m1 + gy) * m0 + gx) * 16 + 8 * h);
+      dst[h * OPL + v] = val;
+    }
+  };
+  for (int k = threadIdx.x; k < 27 * 16; k += 256) wsh[k] = from_bf16(wrow[k]);
+  stage(z0 - 1);
+  stage(z0);
+  const int lx = threadIdx.x % OX, ly = threadIdx.x / OX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool mine = gx < (int)m0 && gy < (int)m1;
+  const float4* w4 = reinterpret_cast<const float4*>(wsh);
+  for (int z = z0; z < z1; ++z) {
+    stage(z + 1);
+    __syncthreads();
+    float acc = 0.f;
+#pragma unroll 1
+    for (int dz = 0; dz < 3; ++dz) {
+      const v4u* pl = &ring[(z + dz) % 3][0][0];      // plane z - 1 + dz
+#pragma unroll 3
+      for (int q9 = 0; q9 < 9; ++q9) {
+        const int tap = 9 * dz + q9;
+        const int v = (ly + q9 / 3) * OHX + lx + q9 % 3;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) r[e] = r[e] > 0.f ? r[e] : 0.f;
-      } else {
-        const uint2 mk = *reinterpret_cast<const uint2*>(mask + o);
-        const uint32_t mw[2] = {mk.x, mk.y};
+        for (int h = 0; h < 2; ++h) {
+          const v4u a = pl[h * OPL + v];              // channels 8 h .. 8 h + 7, two per word
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint16_t mb = (uint16_t)(mw[e >> 1] >> (16 * (e & 1)));
-          if (!(from_bf16(mb) > 0.f)) r[e] = 0.f;
+          for (int c = 0; c < 2; ++c) {
+            const float4 w = w4[4 * tap + 2 * h + c];  // channels 8 h + 4 c .. + 3 (the same for every lane)
+            const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const uint32_t word = a[2 * c + (e >> 1)];
+              acc = fmaf(wv[e], from_bf16((uint16_t)(word >> (16 * (e & 1)))), acc);
+            }
+          }
         }
       }
-      uint2 w;
-      w.x = (uint32_t)to_bf16(r[0]) | ((uint32_t)to_bf16(r[1]) << 16);
-      w.y = (uint32_t)to_bf16(r[2]) | ((uint32_t)to_bf16(r[3]) << 16);
-      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + o) = w;
     }
+    if (mine) out[(uint64_t)b * n + ((uint64_t)z * m1 + gy) * m0 + gx] = acc;
+    __syncthreads();                              // the slot of plane z - 1 is staged next
   }
 }
 
@@ -667,7 +747,13 @@ hipError_t forward(ope_net* t, uint32_t B, float* f) {
   if ((e = conv<2, 16, EPI_RELU>(t, t->x, PK_F1, nullptr, t->a1, B)) != hipSuccess) return e;
   if ((e = conv<16, 16, EPI_RELU>(t, t->a1, PK_F2, nullptr, t->a2, B)) != hipSuccess) return e;
   if ((e = conv<16, 16, EPI_RELU>(t, t->a2, PK_F3, nullptr, t->a3, B)) != hipSuccess) return e;
-  return conv<16, 1, EPI_F32>(t, t->a3, PK_F4, nullptr, f, B);
+  const uint32_t ntx = (t->m0 + OX - 1) / OX, nty = (t->m1 + OY - 1) / OY, ntz = (t->m2 + OZ - 1) / OZ;
+  const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_conv_out1, dim3((uint32_t)blocks), dim3(256), 0, t->ctx->stream, t->a3, t->wpk + PK_F4, f, t->m0,
+                     t->m1, t->m2, ntx, nty, ntz);
+  return hipGetLastError();
 }
 
 hipError_t pack_x(ope_net* t, const float* X, const float* v2, uint32_t B) {

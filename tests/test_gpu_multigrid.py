@@ -137,6 +137,27 @@ def test_capped_pcg_equals_oracle_iterates_wide_rows(N):
     assert np.max(np.abs(Y - Y_ref)) <= 1e-12 * np.max(np.abs(Y_ref))
 
 
+def test_capped_pcg_with_a_stopped_slice():
+    """Right-hand-side columns that are zero stop before the first iteration;
+    with N = 40 the first 20 columns are a whole slice of the row, whose
+    V-cycle work-groups return at once (writing zero partial sums) while the
+    other slice iterates."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=13, N=40, seed=13)
+    op = _op(p)
+    U = W.initial_block(p.grid.n, p.N, 7)
+    U[:, :20] = 0.0
+    say("capped PCG N=40 with a stopped slice")
+    with _ctx(p) as c:
+        Yd = empty_dev(p.grid.n, p.N)
+        its = ope.ope_source_solve(c.handle, to_dev(U), Yd, None, 1e-15, 3, allow_maxit=True)
+        Y = to_host(Yd)
+    Y_ref = O.pcg_source(op, U, None, tol=1e-15, max_iter=3)
+    assert its == 3
+    assert np.all(Y[:, :20] == 0.0)
+    assert np.max(np.abs(Y - Y_ref)) <= 1e-12 * np.max(np.abs(Y_ref))
+
+
 def test_source_solve_reaches_direct_solution():
     from paper_2511_06788_amd import ope
     p = W.wells_3d(m=24, N=5, seed=1)

@@ -475,16 +475,17 @@ __global__ __launch_bounds__(256) void k_rowmm_narrow(const TI* X0, const TI* __
 }
 
 // Row-block products from LDS (N a multiple of the 16-byte chunk, aligned
-// blocks): work-group tile 128 rows x 128 columns, each wave 64 x 64 (4 x 4
-// MFMA blocks).  Panels of KC contraction indices are staged in LDS, double
+// blocks): work-group tile RTW rows x 128 columns, each wave RTW/2 x 64
+// (RTW/32 x 4 MFMA blocks; RTW = 128, or 64 for the FP64 kind).  Panels of KC contraction indices are staged in LDS, double
 // buffered: X's rows (read as 16-byte chunks) are stored transposed, Xt[k][row],
 // so that the MFMA operand reads of both panels are contiguous across lanes,
 // and the KC rows of M beside them.  M is read once per work-group instead of
 // once per wave and 64-row tile.
 constexpr int RT2 = 128;    // rows per work-group tile
+constexpr int RT2H = 64;    // rows per work-group tile of the FP64 kind
 
-template <typename TI, int KIND, int NSRC>
-__global__ __launch_bounds__(256, 2) void k_rowmm_lds(const TI* X0, const TI* __restrict__ M0, const TI* X1,
+template <typename TI, int KIND, int NSRC, int RTW>
+__global__ __launch_bounds__(256, RTW == RT2H ? 3 : 2) void k_rowmm_lds(const TI* X0, const TI* __restrict__ M0, const TI* X1,
                                                    const TI* __restrict__ M1, const TI* Cm, double cbeta,
                                                    double ascale, TI* Out, uint32_t n, uint32_t N, int want_colsq,
                                                    int predicated, const OpeScalars* __restrict__ sc,
@@ -494,26 +495,27 @@ __global__ __launch_bounds__(256, 2) void k_rowmm_lds(const TI* X0, const TI* __
   constexpr int KC = PanelRows<KIND>::KC;
   constexpr int VPC = 16 / (int)sizeof(TI);
   constexpr int XC = KC / VPC;                        // chunks per X row and panel
-  constexpr int XCT = RT2 * XC / 256;                 // X chunks per thread
+  constexpr int XCT = RTW * XC / 256;                 // X chunks per thread
+  constexpr int AR = RTW / 32;                        // 16-row MFMA blocks per wave (a wave spans RTW / 2 rows)
   constexpr int MCR = CT / VPC;                       // chunks per M panel row
   constexpr int MCT = KC * MCR / 256;                 // M chunks per thread
-  static_assert(XCT * 256 == RT2 * XC && MCT * 256 == KC * MCR, "panel chunks must divide the work-group");
+  static_assert(XCT * 256 == RTW * XC && MCT * 256 == KC * MCR, "panel chunks must divide the work-group");
   typedef unsigned int Chunk __attribute__((ext_vector_type(4)));
   union ChunkV {
     Chunk c;
     TI v[VPC];
   };
-  __shared__ __align__(16) TI xt[2][KC][RT2];
+  __shared__ __align__(16) TI xt[2][KC][RTW];
   __shared__ __align__(16) TI mp[2][KC][CT];
   __shared__ double colsq[2][CT];
   if (rowmm_skip(predicated, sc)) return;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t wr = wave >> 1, wc = wave & 1u;
-  const uint32_t row0 = blockIdx.x * RT2, col0 = blockIdx.y * CT;
+  const uint32_t row0 = blockIdx.x * RTW, col0 = blockIdx.y * CT;
   const uint32_t kr = lane >> 4, ci = lane & 15u;
-  acc_t acc[4][4];
+  acc_t acc[AR][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < AR; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = zero_acc<acc_t>();
   const uint32_t kpan = (N + KC - 1) / KC;          // panels per source
@@ -562,18 +564,17 @@ __global__ __launch_bounds__(256, 2) void k_rowmm_lds(const TI* X0, const TI* __
     if (t + 1 < npan) load(t + 1);
 #pragma unroll
     for (int kk = 0; kk < KC / MK::KSTEP; ++kk) {
-      TI av[4][MK::KPL], bv[4][MK::KPL];
+      TI av[AR][MK::KPL], bv[4][MK::KPL];
 #pragma unroll
       for (int e = 0; e < MK::KPL; ++e) {
         const uint32_t k = kk * MK::KSTEP + kr * MK::KPL + e;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          av[a][e] = xt[buf][k][wr * 64 + a * 16 + ci];
-          bv[a][e] = mp[buf][k][wc * 64 + a * 16 + ci];
-        }
+        for (int a = 0; a < AR; ++a) av[a][e] = xt[buf][k][wr * (RTW / 2) + a * 16 + ci];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b][e] = mp[buf][k][wc * 64 + b * 16 + ci];
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < AR; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = mma<KIND, TI>(av[a], bv[b], acc[a][b]);
     }
@@ -584,12 +585,12 @@ __global__ __launch_bounds__(256, 2) void k_rowmm_lds(const TI* X0, const TI* __
   // wave writes: Out may alias X0 (in-place Step 4)
   double sq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < AR; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const uint32_t row = row0 + wr * 64 + a * 16 + MK::drow(kr, r);
+        const uint32_t row = row0 + wr * (RTW / 2) + a * 16 + MK::drow(kr, r);
         const uint32_t col = col0 + wc * 64 + b * 16 + ci;
         if (row < n && col < N) {
           const uint64_t o = (uint64_t)row * N + col;
@@ -845,7 +846,11 @@ hipError_t rowmm_t(ope_ctx* c, const TI* X0, const TI* M0, const TI* X1, const T
   auto al16 = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) % 16) == 0; };
   const bool narrow = N <= 32;
   const bool lds = !narrow && N % VPC == 0 && al16(X0) && al16(M0) && al16(X1) && al16(M1);
-  const uint32_t rt = narrow ? RTN : (lds ? RT2 : RT);
+  // FP64: 64-row tiles (132 VGPRs, three work-groups per compute unit, whose
+  // output stores overlap the others' matrix-core work) measured 4% faster than
+  // 128-row tiles (219 VGPRs, two) at 64^3, N = 128
+  const bool half = lds && KIND == MK_F64;
+  const uint32_t rt = narrow ? RTN : (lds ? (half ? RT2H : RT2) : RT);
   const uint32_t gr = (n + rt - 1) / rt, gc = (N + CT - 1) / CT;
   if (gc != 1 && (Out == X0 || Out == X1)) return hipErrorInvalidValue;  // in place needs one column tile
   if (want_colsq && (int64_t)gr * N > c->part_cap) return hipErrorInvalidValue;
@@ -858,12 +863,17 @@ hipError_t rowmm_t(ope_ctx* c, const TI* X0, const TI* M0, const TI* X1, const T
       hipLaunchKernelGGL((k_rowmm_narrow<TI, KIND, 1>), dim3(gr), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
                          ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
   } else if (lds) {
-    if (X1)
-      hipLaunchKernelGGL((k_rowmm_lds<TI, KIND, 2>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
-                         ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
-    else
-      hipLaunchKernelGGL((k_rowmm_lds<TI, KIND, 1>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
-                         ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta, ascale, Out, n, N,
+                         want_colsq, predicated, c->sc, c->part);
+    };
+    if (half) {
+      if (X1) go(k_rowmm_lds<TI, KIND, 2, RT2H>);
+      else go(k_rowmm_lds<TI, KIND, 1, RT2H>);
+    } else {
+      if (X1) go(k_rowmm_lds<TI, KIND, 2, RT2>);
+      else go(k_rowmm_lds<TI, KIND, 1, RT2>);
+    }
   } else if (X1)
     hipLaunchKernelGGL((k_rowmm<TI, KIND, 2>), dim3(gr, gc), dim3(256), 0, c->stream, X0, M0, X1, M1, Cm, cbeta,
                        ascale, Out, n, N, want_colsq, predicated, c->sc, c->part);

@@ -194,6 +194,108 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 }
 
 // ---------------------------------------------------------------------------
+// 16 -> 16 channel convolution (layers 2-3 forward, and their data gradients)
+// z-marched: a work-group owns a 16 x 16 x-y tile of one sample and OZ planes;
+// the input planes pass through a ring of three 18 x 18 LDS planes (each
+// staged once, halo 1.27x instead of the 2.5x of a 16 x 4 x 4 tile), and wave
+// w computes output rows 4 w .. 4 w + 3 of the current plane with the MFMA
+// mapping of k_conv (weights in the A operand, 16 voxels along x in B).
+// ---------------------------------------------------------------------------
+constexpr int OX = 16, OY = 16, OZ = 16;        // x-y tile and z run of a work-group
+constexpr int OHX = OX + 2, OHY = OY + 2, OPL = OHX * OHY;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv16z(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+                                                 const uint16_t* __restrict__ mask, uint16_t* __restrict__ out,
+                                                 uint32_t m0, uint32_t m1, uint32_t m2, uint32_t ntx, uint32_t nty,
+                                                 uint32_t ntz) {
+  __shared__ __align__(16) v4u ring[3][2][OPL];   // [plane slot][channel half][voxel of the 18 x 18 plane]
+  const uint32_t tiles = ntx * nty * ntz;
+  const uint32_t b = blockIdx.x / tiles;
+  uint32_t t = blockIdx.x - b * tiles;
+  const uint32_t tx = t % ntx;
+  t /= ntx;
+  const uint32_t ty = t % nty;
+  const uint32_t tz = t / nty;
+  const int x0 = (int)(tx * OX), y0 = (int)(ty * OY), z0 = (int)(tz * OZ);
+  const int z1 = z0 + OZ < (int)m2 ? z0 + OZ : (int)m2;
+  const uint64_t n = (uint64_t)m0 * m1 * m2;
+  const uint16_t* src = in + (uint64_t)b * n * 16;
+  // input plane z (zeros outside the grid) into ring slot (z + 1) mod 3
+  auto stage = [&](int z) {
+    v4u* dst = &ring[(z + 3 + 1) % 3][0][0];
+    for (int idx = threadIdx.x; idx < 2 * OPL; idx += 256) {
+      const int h = idx & 1, v = idx >> 1;
+      const int gx = x0 + v % OHX - 1, gy = y0 + v / OHX - 1;
+      v4u val = {0u, 0u, 0u, 0u};
+      if (z >= 0 && z < (int)m2 && gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1)
+        val = *reinterpret_cast<const v4u*>(src + (((uint64_t)z * m1 + gy) * m0 + gx) * 16 + 8 * h);
+      dst[h * OPL + v] = val;
+    }
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, kq = lane >> 4;
+  // A operand: packed weights, row = output channel j, k = 32 s + 8 kq + e
+  v8bf wa[KS16];
+#pragma unroll
+  for (int s = 0; s < KS16; ++s)
+    wa[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(wpk + j * (KS16 * 32) + 32 * s + 8 * kq));
+  stage(z0 - 1);
+  stage(z0);
+  const int gx = x0 + j;
+  for (int z = z0; z < z1; ++z) {
+    stage(z + 1);
+    __syncthreads();
+    v4f acc[4];
+#pragma unroll
+    for (int yb = 0; yb < 4; ++yb) acc[yb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS16; ++s) {
+      // k = 32 s + 8 kq + e: tap 2 s + kq / 2, channels 8 (kq % 2) .. + 7
+      const int tap = 2 * s + (kq >> 1);
+      const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+      const v4u* pl = &ring[(z + dz) % 3][kq & 1][0];            // plane z - 1 + dz
+#pragma unroll
+      for (int yb = 0; yb < 4; ++yb) {
+        v4u bw = {0u, 0u, 0u, 0u};
+        if (tap < 27) bw = pl[(4 * wave + yb + dy) * OHX + j + dx];
+        acc[yb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], __builtin_bit_cast(v8bf, bw), acc[yb], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds output channels 4 kq + r of voxel (x0 + j, y0 + 4 wave + yb, z)
+    if (gx < (int)m0) {
+#pragma unroll
+      for (int yb = 0; yb < 4; ++yb) {
+        const int gy = y0 + 4 * wave + yb;
+        if (gy >= (int)m1) break;
+        const uint64_t v = ((uint64_t)z * m1 + gy) * m0 + gx;
+        const uint64_t o = ((uint64_t)b * n + v) * 16 + 4 * kq;
+        float r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = acc[yb][e];
+        if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) r[e] = r[e] > 0.f ? r[e] : 0.f;
+        } else {
+          const uint2 mk = *reinterpret_cast<const uint2*>(mask + o);
+          const uint32_t mw[2] = {mk.x, mk.y};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint16_t mb = (uint16_t)(mw[e >> 1] >> (16 * (e & 1)));
+            if (!(from_bf16(mb) > 0.f)) r[e] = 0.f;
+          }
+        }
+        uint2 w;
+        w.x = (uint32_t)to_bf16(r[0]) | ((uint32_t)to_bf16(r[1]) << 16);
+        w.y = (uint32_t)to_bf16(r[2]) | ((uint32_t)to_bf16(r[3]) << 16);
+        *reinterpret_cast<uint2*>(out + o) = w;
+      }
+    }
+    __syncthreads();                              // the slot of plane z - 1 is staged next
+  }
+}
+
+// ---------------------------------------------------------------------------
 // last forward layer (16 channels -> 1, FP32 output): per voxel a dot product
 // of length 27 x 16 with one weight vector shared by every voxel, so it runs
 // on the vector ALUs (an MFMA tile would compute 16 output channels for the
@@ -205,8 +307,6 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 // times the inputs.  (The BF16 dot2 instruction would take a quarter of the
 // instructions but does not keep the FP32 accuracy of these sums.)
 // ---------------------------------------------------------------------------
-constexpr int OX = 16, OY = 16, OZ = 16;        // x-y tile and z run of a work-group
-constexpr int OHX = OX + 2, OHY = OY + 2, OPL = OHX * OHY;
 
 __global__ __launch_bounds__(256) void k_conv_out1(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wrow,
                                                    float* __restrict__ out, uint32_t m0, uint32_t m1, uint32_t m2,
@@ -732,6 +832,15 @@ void free_net(ope_net* t) {
 
 template <int CIN, int COUT, int EPI>
 hipError_t conv(ope_net* t, const uint16_t* in, int pk_off, const uint16_t* mask, void* out, uint32_t B) {
+  if constexpr (CIN == 16 && COUT == 16) {
+    const uint32_t ntx = (t->m0 + OX - 1) / OX, nty = (t->m1 + OY - 1) / OY, ntz = (t->m2 + OZ - 1) / OZ;
+    const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_conv16z<EPI>), dim3((uint32_t)blocks), dim3(256), 0, t->ctx->stream, in, t->wpk + pk_off,
+                       mask, (uint16_t*)out, t->m0, t->m1, t->m2, ntx, nty, ntz);
+    return hipGetLastError();
+  }
   const uint32_t ntx = (t->m0 + TX - 1) / TX, nty = (t->m1 + TY - 1) / TY, ntz = (t->m2 + TZ - 1) / TZ;
   const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
   if (blocks == 0) return hipSuccess;

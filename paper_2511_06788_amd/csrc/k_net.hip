@@ -48,14 +48,15 @@ enum { EPI_RELU = 0, EPI_MASK = 1 };
 // weight block offsets (FP32 masters) and packed BF16 operand offsets
 constexpr int W1_OFF = 0, W2_OFF = 864, W3_OFF = 7776, W4_OFF = 14688;
 constexpr int KS16 = 14, KS2 = 2, KS1 = 1;      // 32-wide k-steps for 16, 2, 1 input channels
+constexpr int KSZ = 18;                         // 16 -> 16 layers: 9 (dz, dy) x 2 x-offset pairs
 constexpr int PK_F1 = 0;                        // forward layer 1: 16 x 64
-constexpr int PK_F2 = PK_F1 + 16 * 32 * KS2;    // forward layers 2-4: 16 x 448
-constexpr int PK_F3 = PK_F2 + 16 * 32 * KS16;
-constexpr int PK_F4 = PK_F3 + 16 * 32 * KS16;
+constexpr int PK_F2 = PK_F1 + 16 * 32 * KS2;    // forward layers 2, 3: 16 x 576 (see packed_value)
+constexpr int PK_F3 = PK_F2 + 16 * 32 * KSZ;
+constexpr int PK_F4 = PK_F3 + 16 * 32 * KSZ;    // forward layer 4: 16 x 448 (row 0 used)
 constexpr int PK_B4 = PK_F4 + 16 * 32 * KS16;   // transposed layer 4: 16 x 32
-constexpr int PK_B3 = PK_B4 + 16 * 32 * KS1;    // transposed layers 3, 2: 16 x 448
-constexpr int PK_B2 = PK_B3 + 16 * 32 * KS16;
-constexpr int PK_TOTAL = PK_B2 + 16 * 32 * KS16;
+constexpr int PK_B3 = PK_B4 + 16 * 32 * KS1;    // transposed layers 3, 2: 16 x 576
+constexpr int PK_B2 = PK_B3 + 16 * 32 * KSZ;
+constexpr int PK_TOTAL = PK_B2 + 16 * 32 * KSZ;
 static_assert(W4_OFF + 432 == OPE_NET_PARAMS, "parameter count");
 
 __device__ __forceinline__ uint16_t to_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
@@ -75,7 +76,8 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
                                               uint32_t m0, uint32_t m1, uint32_t m2, uint32_t ntx, uint32_t nty,
                                               uint32_t ntz) {
   constexpr int KS = (27 * CIN + 31) / 32;
-  constexpr int LDS_WORDS = CIN == 16 ? 2 * HV * 4 : (CIN == 2 ? HV : (HV + 1) / 2);
+  static_assert(CIN == 2 || CIN == 1, "16-channel inputs take k_conv16z");
+  constexpr int LDS_WORDS = CIN == 2 ? HV : (HV + 1) / 2;
   __shared__ __align__(16) uint32_t tile[LDS_WORDS];
   const uint32_t tiles = ntx * nty * ntz;
   const uint32_t b = blockIdx.x / tiles;
@@ -89,18 +91,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
   const uint16_t* src = in + (uint64_t)b * n * CIN;
 
   // stage the input tile with a one-voxel halo (zeros outside the grid)
-  if constexpr (CIN == 16) {
-    v4u* t4 = reinterpret_cast<v4u*>(tile);
-    for (int idx = threadIdx.x; idx < 2 * HV; idx += 256) {
-      const int h = idx & 1, v = idx >> 1;
-      const int lx = v % HX, ly = (v / HX) % HY, lz = v / (HX * HY);
-      const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
-      v4u val = {0u, 0u, 0u, 0u};
-      if (gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1 && gz >= 0 && gz < (int)m2)
-        val = *reinterpret_cast<const v4u*>(src + (((uint64_t)gz * m1 + gy) * m0 + gx) * 16 + 8 * h);
-      t4[h * HV + v] = val;
-    }
-  } else {
+  {
     uint16_t* t16 = reinterpret_cast<uint16_t*>(tile);
     for (int v = threadIdx.x; v < HV; v += 256) {
       const int lx = v % HX, ly = (v / HX) % HY, lz = v / (HX * HY);
@@ -134,13 +125,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     for (int yb = 0; yb < TY; ++yb) {
       const int base = (zc * HY + yb + 1) * HX + j + 1;
       v4u bw = {0u, 0u, 0u, 0u};
-      if constexpr (CIN == 16) {
-        // k = 32 s + 8 kq + e: tap 2 s + kq / 2, channels 8 (kq % 2) .. + 7
-        const int ta = 2 * s, tb = 2 * s + 1;
-        const int tap = (kq >> 1) ? tb : ta;
-        const int d = (kq >> 1) ? tap_delta(tb) : tap_delta(ta);
-        if (tap < 27) bw = reinterpret_cast<const v4u*>(tile)[(kq & 1) * HV + base + d];
-      } else if constexpr (CIN == 2) {
+      if constexpr (CIN == 2) {
         // k = 32 s + 8 kq + e: taps 16 s + 4 kq + i, both channels in one word
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -198,8 +183,12 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
 // z-marched: a work-group owns a 16 x 16 x-y tile of one sample and OZ planes;
 // the input planes pass through a ring of three 18 x 18 LDS planes (each
 // staged once, halo 1.27x instead of the 2.5x of a 16 x 4 x 4 tile), and wave
-// w computes output rows 4 w .. 4 w + 3 of the current plane with the MFMA
-// mapping of k_conv (weights in the A operand, 16 voxels along x in B).
+// w computes output rows 4 w .. 4 w + 3 of the current plane (weights in the
+// A operand, 16 voxels along x in B).  The contraction is packed per (dz, dy)
+// in two 32-wide steps of x-offset pairs (dx 0, 1; dx 2 and zeros), so that
+// one LDS read of an input row serves the up to three output rows that use
+// it with different dy (36 reads and 72 MFMAs per wave and plane instead of
+// 56 and 56).
 // ---------------------------------------------------------------------------
 constexpr int OX = 16, OY = 16, OZ = 16;        // x-y tile and z run of a work-group
 constexpr int OHX = OX + 2, OHY = OY + 2, OPL = OHX * OHY;
@@ -236,10 +225,10 @@ __global__ __launch_bounds__(256) void k_conv16z(const uint16_t* __restrict__ in
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
   // A operand: packed weights, row = output channel j, k = 32 s + 8 kq + e
-  v8bf wa[KS16];
+  v8bf wa[KSZ];
 #pragma unroll
-  for (int s = 0; s < KS16; ++s)
-    wa[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(wpk + j * (KS16 * 32) + 32 * s + 8 * kq));
+  for (int s = 0; s < KSZ; ++s)
+    wa[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(wpk + j * (KSZ * 32) + 32 * s + 8 * kq));
   stage(z0 - 1);
   stage(z0);
   const int gx = x0 + j;
@@ -249,17 +238,28 @@ __global__ __launch_bounds__(256) void k_conv16z(const uint16_t* __restrict__ in
     v4f acc[4];
 #pragma unroll
     for (int yb = 0; yb < 4; ++yb) acc[yb] = v4f{0.f, 0.f, 0.f, 0.f};
+    // k-step 2 (3 dz + dy) + pair: lanes kq / 2 take x offset dx = 2 pair + kq / 2
+    // (dx = 3: zero), kq % 2 the channel half.  Input row Y (frame row
+    // 4 wave + Y) of plane z - 1 + dz feeds output rows yb = Y - dy, so each
+    // LDS read serves up to three MFMAs.
 #pragma unroll
-    for (int s = 0; s < KS16; ++s) {
-      // k = 32 s + 8 kq + e: tap 2 s + kq / 2, channels 8 (kq % 2) .. + 7
-      const int tap = 2 * s + (kq >> 1);
-      const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
-      const v4u* pl = &ring[(z + dz) % 3][kq & 1][0];            // plane z - 1 + dz
+    for (int dz = 0; dz < 3; ++dz) {
+      const v4u* pl = &ring[(z + dz) % 3][kq & 1][0];             // plane z - 1 + dz
 #pragma unroll
-      for (int yb = 0; yb < 4; ++yb) {
-        v4u bw = {0u, 0u, 0u, 0u};
-        if (tap < 27) bw = pl[(4 * wave + yb + dy) * OHX + j + dx];
-        acc[yb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], __builtin_bit_cast(v8bf, bw), acc[yb], 0, 0, 0);
+      for (int pr = 0; pr < 2; ++pr) {
+        const int dx = 2 * pr + (kq >> 1);
+#pragma unroll
+        for (int Y = 0; Y < 6; ++Y) {
+          v4u bw = {0u, 0u, 0u, 0u};
+          if (dx <= 2) bw = pl[(4 * wave + Y) * OHX + j + dx];
+          const v8bf bv = __builtin_bit_cast(v8bf, bw);
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            const int yb = Y - dy;
+            if (yb >= 0 && yb < 4)
+              acc[yb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[2 * (3 * dz + dy) + pr], bv, acc[yb], 0, 0, 0);
+          }
+        }
       }
     }
     // epilogue: lane holds output channels 4 kq + r of voxel (x0 + j, y0 + 4 wave + yb, z)
@@ -769,13 +769,22 @@ __device__ float packed_value(const float* __restrict__ w, int q) {
   int off, ks, cin, cout, wo;
   bool tr;
   if (q < PK_F2) { off = PK_F1; ks = KS2; cin = 2; cout = 16; wo = W1_OFF; tr = false; }
-  else if (q < PK_F3) { off = PK_F2; ks = KS16; cin = 16; cout = 16; wo = W2_OFF; tr = false; }
-  else if (q < PK_F4) { off = PK_F3; ks = KS16; cin = 16; cout = 16; wo = W3_OFF; tr = false; }
+  else if (q < PK_F3) { off = PK_F2; ks = KSZ; cin = 16; cout = 16; wo = W2_OFF; tr = false; }
+  else if (q < PK_F4) { off = PK_F3; ks = KSZ; cin = 16; cout = 16; wo = W3_OFF; tr = false; }
   else if (q < PK_B4) { off = PK_F4; ks = KS16; cin = 16; cout = 1; wo = W4_OFF; tr = false; }
   else if (q < PK_B3) { off = PK_B4; ks = KS1; cin = 16; cout = 1; wo = W4_OFF; tr = true; }
-  else if (q < PK_B2) { off = PK_B3; ks = KS16; cin = 16; cout = 16; wo = W3_OFF; tr = true; }
-  else { off = PK_B2; ks = KS16; cin = 16; cout = 16; wo = W2_OFF; tr = true; }
-  const int r = (q - off) / (32 * ks), k = (q - off) % (32 * ks);
+  else if (q < PK_B2) { off = PK_B3; ks = KSZ; cin = 16; cout = 16; wo = W3_OFF; tr = true; }
+  else { off = PK_B2; ks = KSZ; cin = 16; cout = 16; wo = W2_OFF; tr = true; }
+  int r = (q - off) / (32 * ks), k = (q - off) % (32 * ks);
+  if (ks == KSZ) {
+    // 16 -> 16 layers: k-step s = 2 (3 dz + dy) + pair covers taps (dz, dy,
+    // dx = 2 pair + half) for half 0, 1 (dx = 3 is zero), 16 channels each;
+    // rewritten to the tap-major index k = 16 tap + channel used below
+    const int st = k / 32, kk = k % 32;
+    const int g = st / 2, dx = 2 * (st % 2) + kk / 16;
+    if (dx > 2) return 0.f;
+    k = 16 * (3 * g + dx) + kk % 16;
+  }
   if (!tr) {
     const int tap = k / cin, ci = k % cin;
     if (r >= cout || tap >= 27) return 0.f;
@@ -840,14 +849,16 @@ hipError_t conv(ope_net* t, const uint16_t* in, int pk_off, const uint16_t* mask
     hipLaunchKernelGGL((k_conv16z<EPI>), dim3((uint32_t)blocks), dim3(256), 0, t->ctx->stream, in, t->wpk + pk_off,
                        mask, (uint16_t*)out, t->m0, t->m1, t->m2, ntx, nty, ntz);
     return hipGetLastError();
+  } else {
+    static_assert(CIN != 16, "16-channel inputs take the z-marched kernel");
+    const uint32_t ntx = (t->m0 + TX - 1) / TX, nty = (t->m1 + TY - 1) / TY, ntz = (t->m2 + TZ - 1) / TZ;
+    const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), dim3((uint32_t)blocks), dim3(256), 0, t->ctx->stream, in,
+                       t->wpk + pk_off, mask, out, t->m0, t->m1, t->m2, ntx, nty, ntz);
+    return hipGetLastError();
   }
-  const uint32_t ntx = (t->m0 + TX - 1) / TX, nty = (t->m1 + TY - 1) / TY, ntz = (t->m2 + TZ - 1) / TZ;
-  const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
-  if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), dim3((uint32_t)blocks), dim3(256), 0, t->ctx->stream, in,
-                     t->wpk + pk_off, mask, out, t->m0, t->m1, t->m2, ntx, nty, ntz);
-  return hipGetLastError();
 }
 
 // layer 1..4 forward from the packed input pair in t->x; output f (FP32 [b][v])

@@ -21,8 +21,9 @@
 // accumulator gives each lane four consecutive output channels of one voxel
 // and a wave stores 16 voxels x 32 bytes contiguously.  A work-group computes
 // a 16 x 4 x 4 voxel tile from an LDS copy of the 18 x 6 x 6 input tile.
-// The last forward layer (one output channel) is a dot product per voxel on
-// the vector ALUs instead, z-marched through a ring of LDS planes (k_conv_out1).
+// The 16-channel layers march along z through a ring of LDS planes
+// (k_conv16z, k_conv_out1: the last layer's one output channel puts the z
+// and y offsets on the MFMA rows).
 // Backward: the data gradient of a layer is the same convolution with the
 // weights transposed in the channels and flipped in the taps, masked by the
 // ReLU pattern of the forward activation; weight gradients are contractions
@@ -296,23 +297,22 @@ __global__ __launch_bounds__(256) void k_conv16z(const uint16_t* __restrict__ in
 }
 
 // ---------------------------------------------------------------------------
-// last forward layer (16 channels -> 1, FP32 output): per voxel a dot product
-// of length 27 x 16 with one weight vector shared by every voxel, so it runs
-// on the vector ALUs (an MFMA tile would compute 16 output channels for the
-// one that exists).  A work-group owns a 16 x 16 x-y tile of one sample and
-// marches along z over OZ planes: the input planes pass through a ring of
-// three 18 x 18 LDS planes (each staged once, halo 1.27x), and each thread
-// adds, for its voxel, tap by tap and channel by channel in FP32 (fused
-// multiply-adds), the BF16 weights of the packed row (k = 16 tap + channel)
-// times the inputs.  (The BF16 dot2 instruction would take a quarter of the
-// instructions but does not keep the FP32 accuracy of these sums.)
+// last forward layer (16 channels -> 1, FP32 output).  One output channel
+// leaves no output-channel dimension for the matrix cores, so the MFMA rows
+// carry the z and y offsets instead (row 4 dz + dy; 9 of 16 rows used, the
+// matrix cores do 1.8x the algorithmic flops at 32x the FP32 vector rate):
+// for input row Y of input plane P, a pair of MFMAs (x offsets 0, 1 and 2 in
+// the contraction with the 16 channels, as in k_conv16z) gives in row
+// 4 dz + dy the contribution of that row to output row Y - dy of output plane
+// P + 1 - dz.  Each input plane is staged and multiplied once, right after it
+// arrives; lane group dz (lanes 16 dz .. 16 dz + 15 hold rows 4 dz .. + 3)
+// adds its rows into the three output planes in flight, and an output plane,
+// complete once plane P = z + 1 is in, is summed over the lane groups.
 // ---------------------------------------------------------------------------
-
 __global__ __launch_bounds__(256) void k_conv_out1(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wrow,
                                                    float* __restrict__ out, uint32_t m0, uint32_t m1, uint32_t m2,
                                                    uint32_t ntx, uint32_t nty, uint32_t ntz) {
-  __shared__ __align__(16) v4u ring[3][2][OPL];   // [plane slot][channel half][voxel of the 18 x 18 plane]
-  __shared__ __align__(16) float wsh[27 * 16];
+  __shared__ __align__(16) v4u ring[2][2][OPL];   // [plane slot][channel half][voxel of the 18 x 18 plane]
   const uint32_t tiles = ntx * nty * ntz;
   const uint32_t b = blockIdx.x / tiles;
   uint32_t t = blockIdx.x - b * tiles;
@@ -324,54 +324,89 @@ __global__ __launch_bounds__(256) void k_conv_out1(const uint16_t* __restrict__ 
   const int z1 = z0 + OZ < (int)m2 ? z0 + OZ : (int)m2;
   const uint64_t n = (uint64_t)m0 * m1 * m2;
   const uint16_t* src = in + (uint64_t)b * n * 16;
-  // input plane z (zeros outside the grid) into ring slot (z + 1) mod 3
-  auto stage = [&](int z) {
-    v4u* dst = &ring[(z + 3 + 1) % 3][0][0];
+  // input plane P (zeros outside the grid) into ring slot (P + 2) mod 2
+  auto stage = [&](int P) {
+    v4u* dst = &ring[(P + 2) & 1][0][0];
     for (int idx = threadIdx.x; idx < 2 * OPL; idx += 256) {
       const int h = idx & 1, v = idx >> 1;
       const int gx = x0 + v % OHX - 1, gy = y0 + v / OHX - 1;
       v4u val = {0u, 0u, 0u, 0u};
-      if (z >= 0 && z < (int)m2 && gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1)
-        val = *reinterpret_cast<const v4u*>(src + (((uint64_t)z * m1 + gy) * m0 + gx) * 16 + 8 * h);
+      if (P >= 0 && P < (int)m2 && gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1)
+        val = *reinterpret_cast<const v4u*>(src + (((uint64_t)P * m1 + gy) * m0 + gx) * 16 + 8 * h);
       dst[h * OPL + v] = val;
     }
   };
-  for (int k = threadIdx.x; k < 27 * 16; k += 256) wsh[k] = from_bf16(wrow[k]);
-  stage(z0 - 1);
-  stage(z0);
-  const int lx = threadIdx.x % OX, ly = threadIdx.x / OX;
-  const int gx = x0 + lx, gy = y0 + ly;
-  const bool mine = gx < (int)m0 && gy < (int)m1;
-  const float4* w4 = reinterpret_cast<const float4*>(wsh);
-  for (int z = z0; z < z1; ++z) {
-    stage(z + 1);
-    __syncthreads();
-    float acc = 0.f;
-#pragma unroll 1
-    for (int dz = 0; dz < 3; ++dz) {
-      const v4u* pl = &ring[(z + dz) % 3][0][0];      // plane z - 1 + dz
-#pragma unroll 3
-      for (int q9 = 0; q9 < 9; ++q9) {
-        const int tap = 9 * dz + q9;
-        const int v = (ly + q9 / 3) * OHX + lx + q9 % 3;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, kq = lane >> 4;
+  // A operand of x-offset pair pr: row j = 4 dz + dy (dz, dy < 3, else zero),
+  // k = 8 kq + e: dx = 2 pr + kq / 2 (dx = 3: zero), channel 8 (kq % 2) + e;
+  // the packed row holds tap (dz, dy, dx) (dx fastest) at k = 16 tap + channel
+  v8bf wa[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const v4u a = pl[h * OPL + v];              // channels 8 h .. 8 h + 7, two per word
+  for (int pr = 0; pr < 2; ++pr) {
+    const int dz = j >> 2, dy = j & 3, dx = 2 * pr + (kq >> 1);
+    v4u w = {0u, 0u, 0u, 0u};
+    if (dz < 3 && dy < 3 && dx < 3) w = *reinterpret_cast<const v4u*>(wrow + 16 * (9 * dz + 3 * dy + dx) + 8 * (kq & 1));
+    wa[pr] = __builtin_bit_cast(v8bf, w);
+  }
+  // output planes z, z + 1, z + 2 in flight: this lane's part (its dz = kq) of rows 4 wave + yb
+  float acc[3][4];
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const float4 w = w4[4 * tap + 2 * h + c];  // channels 8 h + 4 c .. + 3 (the same for every lane)
-            const float wv[4] = {w.x, w.y, w.z, w.w};
+  for (int q = 0; q < 3; ++q)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const uint32_t word = a[2 * c + (e >> 1)];
-              acc = fmaf(wv[e], from_bf16((uint16_t)(word >> (16 * (e & 1)))), acc);
-            }
-          }
+    for (int yb = 0; yb < 4; ++yb) acc[q][yb] = 0.f;
+  // multiply input plane P (staged) into the planes in flight; z is the
+  // output plane of acc[0], so lane group kq adds into plane offset P + 1 - kq - z
+  auto process = [&](int P, int z) {
+    const v4u* pl = &ring[(P + 2) & 1][kq & 1][0];
+    const int qq = P + 1 - kq - z;
+#pragma unroll
+    for (int Y = 0; Y < 6; ++Y) {
+      v4f d = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr) {
+        const int dx = 2 * pr + (kq >> 1);
+        v4u bw = {0u, 0u, 0u, 0u};
+        if (dx <= 2) bw = pl[(4 * wave + Y) * OHX + j + dx];
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[pr], __builtin_bit_cast(v8bf, bw), d, 0, 0, 0);
+      }
+      // row 4 kq + r of column j: dz = kq, dy = r -> output row Y - r
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int yb = Y - r;
+        if (yb >= 0 && yb < 4) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) acc[q][yb] += qq == q ? d[r] : 0.f;
         }
       }
     }
-    if (mine) out[(uint64_t)b * n + ((uint64_t)z * m1 + gy) * m0 + gx] = acc;
-    __syncthreads();                              // the slot of plane z - 1 is staged next
+  };
+  stage(z0 - 1);
+  __syncthreads();
+  process(z0 - 1, z0);
+  stage(z0);
+  __syncthreads();
+  process(z0, z0);
+  const int gx = x0 + j;
+  for (int z = z0; z < z1; ++z) {
+    stage(z + 1);                                 // the slot of plane z - 1 (its reads ended before the last wait)
+    __syncthreads();
+    process(z + 1, z);
+    // output plane z is complete: sum the lane groups (kq = 3 holds zeros)
+#pragma unroll
+    for (int yb = 0; yb < 4; ++yb) {
+      float v = acc[0][yb];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      const int gy = y0 + 4 * wave + yb;
+      if (kq == 0 && gx < (int)m0 && gy < (int)m1) out[(uint64_t)b * n + ((uint64_t)z * m1 + gy) * m0 + gx] = v;
+    }
+#pragma unroll
+    for (int yb = 0; yb < 4; ++yb) {
+      acc[0][yb] = acc[1][yb];
+      acc[1][yb] = acc[2][yb];
+      acc[2][yb] = 0.f;
+    }
   }
 }
 

@@ -69,7 +69,8 @@ __host__ __device__ constexpr int tap_delta(int t) {
 }
 
 // ---------------------------------------------------------------------------
-// convolution (forward, or backward data with transposed weights)
+// convolution of a one-channel input (the data gradient of the last layer:
+// its transposed weights, 1 -> 16 channels) on 16 x 4 x 4 voxel tiles
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
                                               uint32_t m0, uint32_t m1, uint32_t m2, uint32_t ntx, uint32_t nty,
                                               uint32_t ntz) {
   constexpr int KS = (27 * CIN + 31) / 32;
-  static_assert(CIN == 2 || CIN == 1, "16-channel inputs take k_conv16z");
-  constexpr int LDS_WORDS = CIN == 2 ? HV : (HV + 1) / 2;
+  static_assert(CIN == 1, "2- and 16-channel inputs take k_conv2z and k_conv16z");
+  constexpr int LDS_WORDS = (HV + 1) / 2;
   __shared__ __align__(16) uint32_t tile[LDS_WORDS];
   const uint32_t tiles = ntx * nty * ntz;
   const uint32_t b = blockIdx.x / tiles;
@@ -99,11 +100,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
       const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
       const bool inside = gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1 && gz >= 0 && gz < (int)m2;
       const uint64_t gv = ((uint64_t)gz * m1 + gy) * m0 + gx;
-      if constexpr (CIN == 2) {
-        tile[v] = inside ? *reinterpret_cast<const uint32_t*>(src + gv * 2) : 0u;
-      } else {
-        t16[v] = inside ? src[gv] : (uint16_t)0;
-      }
+      t16[v] = inside ? src[gv] : (uint16_t)0;
     }
   }
 
@@ -126,14 +123,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, c
     for (int yb = 0; yb < TY; ++yb) {
       const int base = (zc * HY + yb + 1) * HX + j + 1;
       v4u bw = {0u, 0u, 0u, 0u};
-      if constexpr (CIN == 2) {
-        // k = 32 s + 8 kq + e: taps 16 s + 4 kq + i, both channels in one word
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int tap = 16 * s + 4 * kq + i;
-          if (tap < 27) bw[i] = tile[base + tap_delta(tap)];
-        }
-      } else {
+      {
         // k = 8 kq + e = tap
         const uint16_t* t16 = reinterpret_cast<const uint16_t*>(tile);
 #pragma unroll
@@ -286,6 +276,89 @@ __global__ __launch_bounds__(256) void k_conv16z(const uint16_t* __restrict__ in
             if (!(from_bf16(mb) > 0.f)) r[e] = 0.f;
           }
         }
+        uint2 w;
+        w.x = (uint32_t)to_bf16(r[0]) | ((uint32_t)to_bf16(r[1]) << 16);
+        w.y = (uint32_t)to_bf16(r[2]) | ((uint32_t)to_bf16(r[3]) << 16);
+        *reinterpret_cast<uint2*>(out + o) = w;
+      }
+    }
+    __syncthreads();                              // the slot of plane z - 1 is staged next
+  }
+}
+
+// ---------------------------------------------------------------------------
+// first layer (2 input channels -> 16) on the same z-march and 16 x 16 x-y
+// tiles as k_conv16z, a plane ring of one 32-bit word (the two BF16 input
+// channels) per voxel; the MFMA mapping is that of k_conv (k = 2 tap + ci:
+// lane kq reads taps 16 s + 4 kq + i, i < 4).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_conv2z(const uint32_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+                                                uint16_t* __restrict__ out, uint32_t m0, uint32_t m1, uint32_t m2,
+                                                uint32_t ntx, uint32_t nty, uint32_t ntz) {
+  __shared__ uint32_t ring[3][OPL];               // [plane slot][voxel of the 18 x 18 plane]
+  const uint32_t tiles = ntx * nty * ntz;
+  const uint32_t b = blockIdx.x / tiles;
+  uint32_t t = blockIdx.x - b * tiles;
+  const uint32_t tx = t % ntx;
+  t /= ntx;
+  const uint32_t ty = t % nty;
+  const uint32_t tz = t / nty;
+  const int x0 = (int)(tx * OX), y0 = (int)(ty * OY), z0 = (int)(tz * OZ);
+  const int z1 = z0 + OZ < (int)m2 ? z0 + OZ : (int)m2;
+  const uint64_t n = (uint64_t)m0 * m1 * m2;
+  const uint32_t* src = in + (uint64_t)b * n;
+  // input plane z (zeros outside the grid) into ring slot (z + 1) mod 3
+  auto stage = [&](int z) {
+    uint32_t* dst = &ring[(z + 3 + 1) % 3][0];
+    for (int v = threadIdx.x; v < OPL; v += 256) {
+      const int gx = x0 + v % OHX - 1, gy = y0 + v / OHX - 1;
+      uint32_t val = 0u;
+      if (z >= 0 && z < (int)m2 && gx >= 0 && gx < (int)m0 && gy >= 0 && gy < (int)m1)
+        val = src[((uint64_t)z * m1 + gy) * m0 + gx];
+      dst[v] = val;
+    }
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, kq = lane >> 4;
+  v8bf wa[KS2];
+#pragma unroll
+  for (int s = 0; s < KS2; ++s)
+    wa[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(wpk + j * (KS2 * 32) + 32 * s + 8 * kq));
+  stage(z0 - 1);
+  stage(z0);
+  const int gx = x0 + j;
+  for (int z = z0; z < z1; ++z) {
+    stage(z + 1);
+    __syncthreads();
+    v4f acc[4];
+#pragma unroll
+    for (int yb = 0; yb < 4; ++yb) acc[yb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS2; ++s) {
+#pragma unroll
+      for (int yb = 0; yb < 4; ++yb) {
+        v4u bw = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int tap = 16 * s + 4 * kq + i;
+          if (tap < 27) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+            bw[i] = ring[(z + dz) % 3][(4 * wave + yb + dy) * OHX + j + dx];
+          }
+        }
+        acc[yb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], __builtin_bit_cast(v8bf, bw), acc[yb], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds output channels 4 kq + r of voxel (x0 + j, y0 + 4 wave + yb, z), ReLU
+    if (gx < (int)m0) {
+#pragma unroll
+      for (int yb = 0; yb < 4; ++yb) {
+        const int gy = y0 + 4 * wave + yb;
+        if (gy >= (int)m1) break;
+        const uint64_t o = ((uint64_t)b * n + ((uint64_t)z * m1 + gy) * m0 + gx) * 16 + 4 * kq;
+        float r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = acc[yb][e] > 0.f ? acc[yb][e] : 0.f;
         uint2 w;
         w.x = (uint32_t)to_bf16(r[0]) | ((uint32_t)to_bf16(r[1]) << 16);
         w.y = (uint32_t)to_bf16(r[2]) | ((uint32_t)to_bf16(r[3]) << 16);
@@ -885,7 +958,7 @@ hipError_t conv(ope_net* t, const uint16_t* in, int pk_off, const uint16_t* mask
                        mask, (uint16_t*)out, t->m0, t->m1, t->m2, ntx, nty, ntz);
     return hipGetLastError();
   } else {
-    static_assert(CIN != 16, "16-channel inputs take the z-marched kernel");
+    static_assert(CIN == 1, "2- and 16-channel inputs take the z-marched kernels");
     const uint32_t ntx = (t->m0 + TX - 1) / TX, nty = (t->m1 + TY - 1) / TY, ntz = (t->m2 + TZ - 1) / TZ;
     const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
     if (blocks == 0) return hipSuccess;
@@ -899,7 +972,16 @@ hipError_t conv(ope_net* t, const uint16_t* in, int pk_off, const uint16_t* mask
 // layer 1..4 forward from the packed input pair in t->x; output f (FP32 [b][v])
 hipError_t forward(ope_net* t, uint32_t B, float* f) {
   hipError_t e;
-  if ((e = conv<2, 16, EPI_RELU>(t, t->x, PK_F1, nullptr, t->a1, B)) != hipSuccess) return e;
+  {
+    const uint32_t ntx = (t->m0 + OX - 1) / OX, nty = (t->m1 + OY - 1) / OY, ntz = (t->m2 + OZ - 1) / OZ;
+    const uint64_t blocks = (uint64_t)ntx * nty * ntz * B;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    if (blocks > 0) {
+      hipLaunchKernelGGL(k_conv2z, dim3((uint32_t)blocks), dim3(256), 0, t->ctx->stream, (const uint32_t*)t->x,
+                         t->wpk + PK_F1, (uint16_t*)t->a1, t->m0, t->m1, t->m2, ntx, nty, ntz);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
   if ((e = conv<16, 16, EPI_RELU>(t, t->a1, PK_F2, nullptr, t->a2, B)) != hipSuccess) return e;
   if ((e = conv<16, 16, EPI_RELU>(t, t->a2, PK_F3, nullptr, t->a3, B)) != hipSuccess) return e;
   const uint32_t ntx = (t->m0 + OX - 1) / OX, nty = (t->m1 + OY - 1) / OY, ntz = (t->m2 + OZ - 1) / OZ;

@@ -380,6 +380,44 @@ def algorithm1_energy_stops(ope, torch, m=64, N=17, tol=1e-10):
     return out
 
 
+def paper_hydrogen(ope, torch):
+    """Section 5.2's hydrogen atom in its finite-difference form (48^3 on
+    (-10, 10)^3, -1/2 Lap - 1/sqrt(|x|^2 + 0.1^2), shifted by 1, N = 5):
+    Algorithm 1 at 0.9 of the step limit from the Lanczos estimates to
+    residual 1e-8, plain and multigrid-preconditioned Step 1; Ritz values
+    against the oracle eigensolver's, and (context) the unshifted energies
+    against the exact hydrogen ones, -1/2 and -1/8 (the grid's error)."""
+    import numpy as np
+    import workloads as W
+    ref_case = [c for c in json.load(open(GOLDEN_EIGS))["cases"] if c["name"] == "hydrogen_soft_48"][0]
+    ref = np.array(ref_case["eigenvalues"][:5])
+    p = W.hydrogen_softened(m=48, N=5, half=10.0, shift=1.0)
+    exact = np.array([-0.5, -0.125, -0.125, -0.125, -0.125])
+    out = {"workload": "hydrogen_soft_48^3_N5 (finite-difference stand-in for the P2-FEM hydrogen of Section 5.2)",
+           "shift": 1.0, "res_tol": 1e-8}
+    for mg in (False, True):
+        with ope.Context(p.grid, p.V, p.N, kinetic=p.kinetic, shift=p.shift) as c:
+            ope.ope_set_multigrid(c.handle, mg)
+            lo, hi = ope.ope_spectrum_bounds(c.handle)
+            tau = 0.9 * 2.0 / (1.0 / lo - 1.0 / hi)
+            ope.ope_solve(c.handle, torch.from_numpy(p.U0).to("cuda"), tau, 1e-8, 3)
+            U = torch.from_numpy(p.U0).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            si = ope.ope_solve(c.handle, U, tau, 1e-8, 4000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res, ritz, drift = ope.ope_residual(c.handle, U, p.N)
+        ritz = np.sort(ritz)
+        out["multigrid" if mg else "plain"] = {
+            "tau": tau, "converged": bool(si.converged), "steps": int(si.steps), "seconds": dt,
+            "inner_iterations": int(si.inner_iterations), "final_residual": res, "drift": drift,
+            "ritz_max_rel_error_vs_reference": float(np.max(np.abs(ritz - ref) / ref)),
+            "energies": (ritz - 1.0).tolist(),
+            "grid_error_vs_exact_hydrogen": (ritz - 1.0 - exact).tolist()}
+    return out
+
+
 def paper_table1(ope, torch, taus=(0.5, 1.0, 1.5)):
     """Section 5.1's Table 1 on the finite-difference oscillator (99 x 99,
     N = 15): steps and wall time to relative energy error 1e-10, Step 1
@@ -859,7 +897,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large", "extrapolate", "energy",
-                                       "table1", "ttr", "graph", "mg", "mgmixed"], default=None,
+                                       "table1", "hydrogen", "ttr", "graph", "mg", "mgmixed"], default=None,
                     help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
@@ -890,6 +928,8 @@ def main():
             r = net_forward_rate(ope, torch, reps=args.steps)
         elif args.form == "energy":
             r = algorithm1_energy_stops(ope, torch)
+        elif args.form == "hydrogen":
+            r = paper_hydrogen(ope, torch)
         elif args.form == "table1":
             r = paper_table1(ope, torch)
         elif args.form == "ttr":
@@ -980,6 +1020,7 @@ def main():
         out["algorithm1_energy_stops"] = algorithm1_energy_stops(ope, torch)
         log("Table 1 on the finite-difference oscillator")
         out["paper_table1"] = paper_table1(ope, torch)
+        out["paper_hydrogen"] = paper_hydrogen(ope, torch)
         log("batched workload (64 problems)")
         out["batched"] = batched_throughput(ope, torch)
         log("batch of small problems: eager steps and graph replays")

@@ -301,6 +301,61 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4, switch_mg=1e-4):
     return out
 
 
+def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, multigrid=True):
+    """Algorithm 1 at 64^3, N = 128, tau = 45 (plain FP64, multigrid-
+    preconditioned Step 1) MEASURED from the start block for up to `minutes`
+    of wall time, in chunks of `chunk` steps (a progress line per chunk on
+    stderr).  If the residual has not reached `tol` by then, the remainder is
+    EXTRAPOLATED from the measured rate: the slope of ln(residual) over the
+    last quarter of the measured steps (at least the last two chunks) and
+    their measured cost per step."""
+    import numpy as np
+    import workloads as W
+    p = W.wells_3d(m=64, N=128, seed=0)
+    tau = 45.0
+    traj = []
+    with ope.Context(p.grid, p.V, p.N) as ctx:
+        ope.ope_set_multigrid(ctx.handle, multigrid)
+        U = torch.from_numpy(p.U0).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        converged = False
+        while time.perf_counter() - t0 < 60.0 * minutes:
+            si = ope.ope_solve(ctx.handle, U, tau, tol, chunk)
+            torch.cuda.synchronize()
+            steps += int(si.steps)
+            traj.append((time.perf_counter() - t0, steps, float(si.residual)))
+            print(f"long run: {traj[-1][0]:.1f} s, {steps} steps, residual {si.residual:.3e}", file=sys.stderr,
+                  flush=True)
+            if si.converged:
+                converged = True
+                break
+        res, ritz, drift = ope.ope_residual(ctx.handle, U, p.N)
+    out = {"workload": "wells3d_64^3_N128_seed0", "tau": tau, "res_tol": tol,
+           "inner": "multigrid-preconditioned CG" if multigrid else "CG", "measured_seconds": traj[-1][0],
+           "measured_steps": steps, "residual_reached": res, "drift": drift, "converged": converged,
+           "trajectory": [{"seconds": a, "steps": b, "residual": c} for a, b, c in traj]}
+    if converged:
+        out["seconds"] = traj[-1][0]
+        out["label"] = "MEASURED"
+        lam = reference_eigenvalues("wells3d_64^3_seed0", p.N)
+        out["ritz_max_rel_error_vs_reference"] = ritz_error(ritz, lam)
+        return out
+    q = [t for t in traj if t[1] >= 0.75 * steps]
+    if len(q) < 2:
+        q = traj[-2:]
+    if len(q) >= 2 and q[-1][2] < q[0][2]:
+        slope = (np.log(q[-1][2]) - np.log(q[0][2])) / (q[-1][1] - q[0][1])
+        sec_per_step = (q[-1][0] - q[0][0]) / (q[-1][1] - q[0][1])
+        more = float(np.log(tol / res) / slope)
+        out.update({"label": "MEASURED for the first part, the remainder EXTRAPOLATED from the measured rate",
+                    "measured_residual_factor_per_step": float(np.exp(slope)), "ms_per_step_late": 1e3 * sec_per_step,
+                    "remaining_steps": more, "seconds": traj[-1][0] + more * sec_per_step})
+        out["hours"] = out["seconds"] / 3600.0
+    return out
+
+
 def extrapolated_time_to_residual(ope, torch, p, tau, tol=1e-8, run=200, late=20, multigrid=True):
     """EXTRAPOLATION (not a measurement) of Algorithm 1's time to residual `tol`
     at 64^3, N = 128: `run` steps from the start block are timed, then `late`
@@ -889,6 +944,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--minutes", type=float, default=16.0, help="wall-time budget of --form longrun")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tau", type=float, default=45.0)
@@ -897,7 +953,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
     ap.add_argument("--form", choices=["mixed", "learned", "net", "batched", "large", "extrapolate", "energy",
-                                       "table1", "hydrogen", "ttr", "graph", "mg", "mgmixed"], default=None,
+                                       "table1", "hydrogen", "ttr", "graph", "mg", "mgmixed", "longrun"],
+                    default=None,
                     help="only run the measurement of one form (short; for profiling)")
     args = ap.parse_args()
 
@@ -928,6 +985,8 @@ def main():
             r = net_forward_rate(ope, torch, reps=args.steps)
         elif args.form == "energy":
             r = algorithm1_energy_stops(ope, torch)
+        elif args.form == "longrun":
+            r = long_run_time_to_residual(ope, torch, minutes=args.minutes)
         elif args.form == "hydrogen":
             r = paper_hydrogen(ope, torch)
         elif args.form == "table1":

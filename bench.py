@@ -90,11 +90,13 @@ def kernel_bytes(kind, n, N):
 PMC_SOURCES = {"cg_sweep_b": "k_stencil.hip", "mg_post": "k_mg.hip"}
 
 
-def traffic_from_pmc(n, N, kernel="cg_sweep_b"):
+def traffic_from_pmc(n, N, kernel="cg_sweep_b", mix=None):
     """HBM bytes per working launch of a kernel from the committed rocprofv3
     counter summary (profiles/pmc_traffic_<kernel>.json; for CG sweep B also
     profiles/pmc_traffic.json), or None when its source changed since the
-    counters were taken, or none were taken for this workload."""
+    counters were taken, or none were taken for this workload.  `mix` gives
+    per-kernel launch counts for a record of several kernels (CG sweep B: even
+    and odd form) to weight their per-dispatch bytes with; else their mean."""
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{kernel}.json")
     if not os.path.exists(path):
         path = PMC_FILE if kernel == "cg_sweep_b" else None
@@ -105,6 +107,10 @@ def traffic_from_pmc(n, N, kernel="cg_sweep_b"):
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("source_sha256") != sha or rec.get("n") != n or rec.get("N") != N:
         return None
+    pk = rec.get("per_kernel", [])
+    if mix is not None and len(pk) == len(mix) and sum(mix) > 0:
+        kib = sum(w * (k["fetch_kib"] + k["write_kib"]) for w, k in zip(mix, pk)) / sum(mix)
+        return kib * 1024.0 * rec["copy_scale"]
     return (rec["fetch_kib_per_dispatch"] + rec["write_kib_per_dispatch"]) * 1024.0 * rec["copy_scale"]
 
 
@@ -301,26 +307,48 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4, switch_mg=1e-4):
     return out
 
 
-def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, multigrid=True):
+def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, multigrid=True, mixed=False,
+                              switch=1e-4):
     """Algorithm 1 at 64^3, N = 128, tau = 45 (plain FP64, multigrid-
     preconditioned Step 1) MEASURED from the start block for up to `minutes`
     of wall time, in chunks of `chunk` steps (a progress line per chunk on
     stderr).  If the residual has not reached `tol` by then, the remainder is
     EXTRAPOLATED from the measured rate: the slope of ln(residual) over the
     last quarter of the measured steps (at least the last two chunks) and
-    their measured cost per step."""
+    their measured cost per step.  With `mixed`, the mixed-precision form
+    (FP32 V-cycle) runs first, to residual `switch` (or its FP32 floor), and
+    the FP64 step takes over from the converted block."""
     import numpy as np
     import workloads as W
     p = W.wells_3d(m=64, N=128, seed=0)
     tau = 45.0
     traj = []
+    mixed_steps = 0
     with ope.Context(p.grid, p.V, p.N) as ctx:
         ope.ope_set_multigrid(ctx.handle, multigrid)
         U = torch.from_numpy(p.U0).to("cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         steps = 0
         converged = False
+        if mixed:
+            with ope.Context(p.grid, p.V, p.N, precision=ope.OPE_MIXED) as cm:
+                ope.ope_set_multigrid(cm.handle, multigrid)
+                U32 = torch.from_numpy(p.U0.astype(np.float32)).to("cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                while time.perf_counter() - t0 < 60.0 * minutes:
+                    sm = ope.ope_solve(cm.handle, U32, tau, switch, chunk)
+                    torch.cuda.synchronize()
+                    steps += int(sm.steps)
+                    traj.append((time.perf_counter() - t0, steps, float(sm.residual)))
+                    print(f"long run (mixed): {traj[-1][0]:.1f} s, {steps} steps, residual {sm.residual:.3e}",
+                          file=sys.stderr, flush=True)
+                    if sm.converged or sm.stalled:
+                        break
+                mixed_steps = steps
+                ope.ope_convert(cm.handle, U32, U, p.grid.n * p.N, True)
+        else:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
         while time.perf_counter() - t0 < 60.0 * minutes:
             si = ope.ope_solve(ctx.handle, U, tau, tol, chunk)
             torch.cuda.synchronize()
@@ -333,6 +361,7 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
                 break
         res, ritz, drift = ope.ope_residual(ctx.handle, U, p.N)
     out = {"workload": "wells3d_64^3_N128_seed0", "tau": tau, "res_tol": tol,
+           "form": "mixed to %g, then plain FP64" % switch if mixed else "plain FP64", "mixed_steps": mixed_steps,
            "inner": "multigrid-preconditioned CG" if multigrid else "CG", "measured_seconds": traj[-1][0],
            "measured_steps": steps, "residual_reached": res, "drift": drift, "converged": converged,
            "trajectory": [{"seconds": a, "steps": b, "residual": c} for a, b, c in traj]}
@@ -857,24 +886,50 @@ def step_rate(ope, torch, p, args, multigrid):
     # 8.2 ms of 28.6)
     ope.ope_profile_begin(h, ope.OPE_KERNEL_CG_SWEEP_B)
     inner = 0
+    its = []
     last = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         last = ope.ope_step(h, U, args.tau)
         inner += last.inner_iterations
+        its.append(last.inner_iterations)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, total_ms = ope.ope_profile_end(h)
+    launches, total_ms, tags, lms = ope.ope_profile_end_launches(h, 1 << 20)
     dt = t1 - t0
     ms_per_step = 1e3 * dt / max(args.steps, 1)
-    # every counted CG iteration runs one full sweep B (launches past the last
-    # converged column of a chunk return at once)
-    working = inner
-    nbytes = sweep_b_bytes(n, N)
-    traffic = traffic_from_pmc(n, N, "cg_sweep_b")
     name = "cg_sweep_b"
-    avg_ms = total_ms / max(working, 1)
+    # Every step's CG starts at iteration tag 0; the iterations with a tag
+    # below the step's inner_iterations ran a full sweep B (even: 3 blocks,
+    # odd: 6 blocks, plus the diagonal), the ones enqueued past the
+    # convergence of every column return at once or, in an odd iteration, add
+    # only the pending y term.  The roofline is taken over the full sweeps.
+    steps_tags = []
+    for tg, t_ms in zip(tags, lms):
+        if tg == 0 or not steps_tags:
+            steps_tags.append([])
+        steps_tags[-1].append((tg, t_ms))
+    full_ms = full_bytes = 0.0
+    full = 0
+    parity = [0, 0]                  # full even (SW_UPDATE) and odd (SW_UPDATE_Y) sweeps
+    if len(steps_tags) == len(its) and len(tags) == launches:
+        blk = n * N * 8
+        for st_tags, k in zip(steps_tags, its):
+            for tg, t_ms in st_tags:
+                if 0 <= tg < k:
+                    full += 1
+                    full_ms += t_ms
+                    full_bytes += (6 if tg % 2 else 3) * blk + 8 * n
+                    parity[tg % 2] += 1
+    # the counter record lists the even form first, then the odd one
+    traffic = traffic_from_pmc(n, N, "cg_sweep_b", mix=parity if full else None)
+    if full:
+        nbytes = full_bytes / full
+        avg_ms = full_ms / full
+    else:
+        # no per-launch tags: every counted CG iteration taken as one full sweep
+        full, nbytes, avg_ms, full_ms = inner, sweep_b_bytes(n, N), total_ms / max(inner, 1), total_ms
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     res = {
         "iter_per_s": args.steps / dt, "ms_per_step": ms_per_step,
@@ -883,8 +938,9 @@ def step_rate(ope, torch, p, args, multigrid):
         "levels": levels, "coarsest_nodes": coarsest,
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes": nbytes,
-                     "avg_launch_ms": avg_ms, "working_launches": working, "launches": launches,
-                     "total_ms": total_ms, "avg_ms_all_launches": total_ms / max(launches, 1)},
+                     "avg_launch_ms": avg_ms, "working_launches": full, "launches": launches,
+                     "working_ms": full_ms, "total_ms": total_ms,
+                     "avg_ms_all_launches": total_ms / max(launches, 1)},
     }
     if not args.no_extras:
         kernels = {}
@@ -945,6 +1001,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--m", type=int, default=64)
     ap.add_argument("--minutes", type=float, default=16.0, help="wall-time budget of --form longrun")
+    ap.add_argument("--mixed", action="store_true", help="--form longrun: the mixed form first, then FP64")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tau", type=float, default=45.0)
@@ -986,7 +1043,7 @@ def main():
         elif args.form == "energy":
             r = algorithm1_energy_stops(ope, torch)
         elif args.form == "longrun":
-            r = long_run_time_to_residual(ope, torch, minutes=args.minutes)
+            r = long_run_time_to_residual(ope, torch, minutes=args.minutes, mixed=args.mixed)
         elif args.form == "hydrogen":
             r = paper_hydrogen(ope, torch)
         elif args.form == "table1":
@@ -1032,7 +1089,7 @@ def main():
         "config": {"workload": f"wells3d_{args.m}^3_N{N}_seed{args.seed}", "n": n, "N": N, "tau": args.tau,
                    "form": "plain FP64",
                    "inner": "preconditioned CG, one symmetric multigrid V-cycle per iteration, "
-                            "eta = max(1e-12, 0.1 res), warm start U Lam^-1",
+                            "eta = max(1e-12, 0.25 res), warm start U Lam^-1",
                    "window": {"warmup_steps": args.warmup, "timed_steps": args.steps,
                               "start": "seeded orthonormal start block"}},
         "roofline": mg["roofline"],

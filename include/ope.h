@@ -127,9 +127,12 @@ const char* ope_status_string(ope_status s);
  * H Y = U is solved by conjugate gradients warm-started at U Lam^{-1} until
  * |u_j - H y_j| <= eta |u_j|, with eta = max(eta_floor, eta_rel * res) and
  * res the outer residual of the current iterate; at most max_iter iterations.
- * Defaults: eta_rel = 0.1, eta_floor = 1e-12 (1e-6 for OPE_MIXED), max_iter = 2000
- * (measured: Algorithm 1 to residual 1e-8 on 64^3 and 96^3 well problems with
- * N = 17 takes 1.5-1.7x less time than with eta_rel = 1e-2, at a few more steps). */
+ * Defaults: eta_rel = 0.1, or 0.25 while the multigrid preconditioner is on,
+ * eta_floor = 1e-12 (1e-6 for OPE_MIXED), max_iter = 2000 (measured: Algorithm
+ * 1 to residual 1e-8 on 64^3 and 96^3 well problems with N = 17 takes 1.5-1.7x
+ * less time than with eta_rel = 1e-2, at a few more steps; with the
+ * preconditioner 0.25 takes 1.15-1.45x less time than 0.1).  Once this has
+ * been called, ope_set_multigrid no longer changes eta_rel. */
 ope_status ope_set_inner(ope_ctx* ctx, double eta_rel, double eta_floor, int32_t max_iter);
 
 /* Multigrid-preconditioned Step 1 (Step 1 of Section 4.1 leaves the solver
@@ -143,10 +146,11 @@ ope_status ope_set_inner(ope_ctx* ctx, double eta_rel, double eta_floor, int32_t
  * exactly with a dense inverse.  The V-cycle runs in the context's storage
  * type (FP64, or FP32 for OPE_MIXED, its dot products accumulated in FP64).
  * Measured on 64^3 well problems: about 4 preconditioned iterations per step
- * instead of about 66.  Allocates two n x N blocks plus the coarse levels
+ * instead of about 66.  Unless ope_set_inner has been called, enabling sets
+ * the inner factor eta_rel to 0.25 and disabling to 0.1.  Allocates two n x N blocks plus the coarse levels
  * (about 3/7 of a block); synchronises; enable = 0 frees them.  With the
- * preconditioner on, the host checks the CG's convergence every 2 iterations
- * (else every 4).  OPE_EUNSUPPORTED when a point's row has more than 256
+ * preconditioner on, the host checks the CG's convergence after every
+ * iteration (every 2 with graphs on; without the preconditioner every 4).  OPE_EUNSUPPORTED when a point's row has more than 256
  * 16-byte chunks (odd N > 256 in FP64); OPE_ENOTSPD if the coarsest operator
  * is not positive definite.  A problem with the preconditioner on runs its
  * CG on its own stream in batched steps (no shared launches). */
@@ -511,7 +515,8 @@ ope_status ope_batch_autotune(ope_batch* batch, int32_t* tuned);
  * temporary n x N block (an FP32 one its own CG buffers). */
 ope_status ope_autotune(ope_ctx* ctx);
 
-/* Step 1's CG runs in chunks of 4 iterations between host convergence checks;
+/* Step 1's CG runs in chunks of 4 iterations between host convergence checks
+ * (preconditioned: 1, or 2 with graphs on);
  * with graphs on each chunk is one replay of a HIP graph captured once per
  * context (on a private stream, replayed on the context's stream), with the
  * same kernels and results as eager launches.  Off by default: eager launches
@@ -582,6 +587,16 @@ ope_status ope_profile_begin(ope_ctx* ctx, int32_t kernel);
 
 /* Stop timing; synchronises the stream and writes the totals to *out (host). */
 ope_status ope_profile_end(ope_ctx* ctx, ope_kernel_time* out);
+
+/* ope_profile_end that also writes, for the first `cap` timed launches in
+ * order, the launch's tag (the index of the CG iteration it belongs to, 0 at
+ * the start of every Step 1; -1 for launches outside a CG iteration) and its
+ * device time in ms (host arrays of `cap` entries; nullable when cap = 0).  A
+ * CG iteration past the convergence of every column does no sweep work (or,
+ * for sweep B of an odd iteration, only the pending y term), so the tags let
+ * a caller average over the iterations that ran (ope_step_info's
+ * inner_iterations of the step). */
+ope_status ope_profile_end_launches(ope_ctx* ctx, ope_kernel_time* out, int32_t* tags, double* ms, int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -695,6 +695,43 @@ __global__ __launch_bounds__(256) void k_sqmm(const double* __restrict__ A, int 
 // is consumed), so each operand element crosses L2 once per work-group
 // instead of once per wave: at the MFMA rate the 64 x 64-tile Gram needs more
 // L1-to-L2 traffic than the chip sustains.
+//
+// A Gram of one block with itself (X^T X) that fits one tile (at most 128
+// columns) runs as k_gram_lds_diag, which stages one panel and computes only
+// the 36 MFMA blocks on or above the block diagonal (nine per wave, each
+// block off the diagonal also written mirrored) instead of 64: the matrix
+// cores do 36/64 of the work.
+
+// Panel staging shared by the two kernels: the 16-byte chunks of KC rows
+// starting at row p of columns c0 .. c0 + 127 of X (zero outside the rows
+// [.., r1) and the columns [.., nc)).
+template <typename TI, int KC>
+struct PanelChunks {
+  static constexpr int VPC = 16 / (int)sizeof(TI);      // values per 16-byte chunk
+  static constexpr int CPR = GT2 / VPC;                  // chunks per panel row
+  static constexpr int CPT = KC * CPR / 256;             // chunks per thread
+  static_assert(CPT * 256 == KC * CPR, "panel chunks must divide the work-group");
+  typedef unsigned int Chunk __attribute__((ext_vector_type(4)));
+  Chunk ch[CPT];
+  __device__ void load(const TI* __restrict__ X, uint64_t ld, uint32_t nc, uint32_t c0, uint32_t p, uint32_t r1) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t row = c / CPR, col = (c % CPR) * VPC;
+      const uint32_t gr = p + row;
+      const Chunk z = {0u, 0u, 0u, 0u};
+      ch[u] = (gr < r1 && c0 + col < nc) ? *reinterpret_cast<const Chunk*>(X + (uint64_t)gr * ld + c0 + col) : z;
+    }
+  }
+  __device__ void store(TI (*panel)[GT2]) const {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const uint32_t c = threadIdx.x + 256u * u;
+      const uint32_t row = c / CPR, col = (c % CPR) * VPC;
+      *reinterpret_cast<Chunk*>(&panel[row][col]) = ch[u];
+    }
+  }
+};
 
 template <typename TI, int KIND>
 __global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint64_t lda, uint32_t na,
@@ -703,10 +740,6 @@ __global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint
   using M = Mk<KIND>;
   using acc_t = typename M::acc_t;
   constexpr int KC = PanelRows<KIND>::KC;
-  constexpr int VPC = 16 / (int)sizeof(TI);            // values per 16-byte chunk
-  constexpr int CPR = GT2 / VPC;                        // chunks per panel row
-  constexpr int CPT = KC * CPR / 256;                   // chunks per thread and operand
-  static_assert(CPT * 256 == KC * CPR, "panel chunks must divide the work-group");
   __shared__ __align__(16) TI pa[2][KC][GT2];
   __shared__ __align__(16) TI pb[2][KC][GT2];
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
@@ -721,40 +754,21 @@ __global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = zero_acc<acc_t>();
-  // 16-byte chunks of the panel starting at row p (zero outside the rows and
-  // columns), as raw 4 x 32-bit vectors
-  typedef unsigned int Chunk __attribute__((ext_vector_type(4)));
-  Chunk ca[CPT], cb[CPT];
-  auto load = [&](uint32_t p) {
-#pragma unroll
-    for (int u = 0; u < CPT; ++u) {
-      const uint32_t c = threadIdx.x + 256u * u;
-      const uint32_t row = c / CPR, col = (c % CPR) * VPC;
-      const uint32_t gr = p + row;
-      const bool rok = gr < r1;
-      const Chunk z = {0u, 0u, 0u, 0u};
-      ca[u] = (rok && i0 + col < na) ? *reinterpret_cast<const Chunk*>(A + (uint64_t)gr * lda + i0 + col) : z;
-      cb[u] = (rok && j0 + col < nb) ? *reinterpret_cast<const Chunk*>(B + (uint64_t)gr * ldb + j0 + col) : z;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < CPT; ++u) {
-      const uint32_t c = threadIdx.x + 256u * u;
-      const uint32_t row = c / CPR, col = (c % CPR) * VPC;
-      *reinterpret_cast<Chunk*>(&pa[buf][row][col]) = ca[u];
-      *reinterpret_cast<Chunk*>(&pb[buf][row][col]) = cb[u];
-    }
-  };
+  PanelChunks<TI, KC> ca, cb;
   const uint32_t npan = (r1 > r0) ? (r1 - r0 + KC - 1) / KC : 0;
   if (npan > 0) {
-    load(r0);
-    store(0);
+    ca.load(A, lda, na, i0, r0, r1);
+    cb.load(B, ldb, nb, j0, r0, r1);
+    ca.store(pa[0]);
+    cb.store(pb[0]);
   }
   __syncthreads();
   for (uint32_t t = 0; t < npan; ++t) {
     const int buf = (int)(t & 1u);
-    if (t + 1 < npan) load(r0 + (t + 1) * KC);
+    if (t + 1 < npan) {
+      ca.load(A, lda, na, i0, r0 + (t + 1) * KC, r1);
+      cb.load(B, ldb, nb, j0, r0 + (t + 1) * KC, r1);
+    }
 #pragma unroll
     for (int kk = 0; kk < KC / M::KSTEP; ++kk) {
       TI av[4][M::KPL], bv[4][M::KPL];
@@ -772,7 +786,10 @@ __global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = mma<KIND, TI>(av[a], bv[b], acc[a][b]);
     }
-    if (t + 1 < npan) store(buf ^ 1);
+    if (t + 1 < npan) {
+      ca.store(pa[buf ^ 1]);
+      cb.store(pb[buf ^ 1]);
+    }
     __syncthreads();
   }
   double* out = part + (uint64_t)ks * na * nb;
@@ -788,6 +805,86 @@ __global__ __launch_bounds__(256) void k_gram_lds(const TI* __restrict__ A, uint
       }
 }
 
+// The nine 16 x 16 blocks (a, b), a <= b, of a diagonal tile that wave w
+// computes: together the 36 blocks of the upper block triangle of 8 x 8.
+__device__ __forceinline__ void sym_blocks(uint32_t w, uint32_t (&oa)[9], uint32_t (&ob)[9]) {
+  constexpr unsigned char T[4][9][2] = {
+      {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4}, {0, 5}, {0, 6}, {0, 7}, {1, 1}},
+      {{1, 2}, {1, 3}, {1, 4}, {1, 5}, {1, 6}, {1, 7}, {2, 2}, {2, 3}, {2, 4}},
+      {{2, 5}, {2, 6}, {2, 7}, {3, 3}, {3, 4}, {3, 5}, {3, 6}, {3, 7}, {4, 4}},
+      {{4, 5}, {4, 6}, {4, 7}, {5, 5}, {5, 6}, {5, 7}, {6, 6}, {6, 7}, {7, 7}}};
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    uint32_t a = T[0][p][0], b = T[0][p][1];
+    if (w == 1u) a = T[1][p][0], b = T[1][p][1];
+    if (w == 2u) a = T[2][p][0], b = T[2][p][1];
+    if (w == 3u) a = T[3][p][0], b = T[3][p][1];
+    oa[p] = 16u * a;
+    ob[p] = 16u * b;
+  }
+}
+
+// X^T X for at most 128 columns: the one tile, split blockIdx.z.
+template <typename TI, int KIND>
+__global__ __launch_bounds__(256) void k_gram_lds_diag(const TI* __restrict__ A, uint64_t lda, uint32_t na,
+                                                       uint32_t rows, uint32_t rows_per_split,
+                                                       double* __restrict__ part) {
+  using M = Mk<KIND>;
+  using acc_t = typename M::acc_t;
+  constexpr int KC = PanelRows<KIND>::KC;
+  __shared__ __align__(16) TI pa[2][KC][GT2];
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+  const uint32_t i0 = blockIdx.x * GT2;
+  const uint32_t ks = blockIdx.z;
+  const uint32_t kr = lane >> 4, ci = lane & 15u;
+  const uint32_t r0 = ks * rows_per_split;
+  const uint32_t r1 = min(rows, r0 + rows_per_split);
+  uint32_t oa[9], ob[9];
+  sym_blocks(wave, oa, ob);
+  acc_t acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = zero_acc<acc_t>();
+  PanelChunks<TI, KC> ca;
+  const uint32_t npan = (r1 > r0) ? (r1 - r0 + KC - 1) / KC : 0;
+  if (npan > 0) {
+    ca.load(A, lda, na, i0, r0, r1);
+    ca.store(pa[0]);
+  }
+  __syncthreads();
+  for (uint32_t t = 0; t < npan; ++t) {
+    const int buf = (int)(t & 1u);
+    if (t + 1 < npan) ca.load(A, lda, na, i0, r0 + (t + 1) * KC, r1);
+#pragma unroll
+    for (int kk = 0; kk < KC / M::KSTEP; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        TI av[M::KPL], bv[M::KPL];
+#pragma unroll
+        for (int e = 0; e < M::KPL; ++e) {
+          const uint32_t row = kk * M::KSTEP + kr * M::KPL + e;
+          av[e] = pa[buf][row][oa[q] + ci];
+          bv[e] = pa[buf][row][ob[q] + ci];
+        }
+        acc[q] = mma<KIND, TI>(av, bv, acc[q]);
+      }
+    }
+    if (t + 1 < npan) ca.store(pa[buf ^ 1]);
+    __syncthreads();
+  }
+  double* out = part + (uint64_t)ks * na * na;
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = i0 + oa[q] + M::drow(kr, r);
+      const uint32_t j = i0 + ob[q] + ci;
+      if (i < na && j < na) {
+        out[(uint64_t)i * na + j] = (double)acc[q][r];
+        if (oa[q] != ob[q]) out[(uint64_t)j * na + i] = (double)acc[q][r];
+      }
+    }
+}
+
 template <typename TI, int KIND>
 hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int64_t ldb, int nb, int64_t rows,
                   double* out) {
@@ -799,9 +896,13 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
                    (reinterpret_cast<uintptr_t>(B) % 16) == 0 && lda % VPC == 0 && ldb % VPC == 0 &&
                    na % VPC == 0 && nb % VPC == 0;
   const bool wide = lds || (KIND != MK_F64 && na >= GT2 && nb >= GT2);
+  // a Gram of one block with itself in one tile: the MFMA blocks on and
+  // above the block diagonal (with several tiles the two launches of fewer
+  // work-groups each were measured slower than the full product)
+  const bool sym = lds && A == B && lda == ldb && na == nb && na <= GT2;
   const int tile = wide ? GT2 : GT;
   const uint32_t ti = (uint32_t)((na + tile - 1) / tile), tj = (uint32_t)((nb + tile - 1) / tile);
-  // about 1024 work-groups in total (512, two per CU, for the LDS kernel),
+  // about 1024 work-groups in total (512, two per CU, for the LDS kernels),
   // within the partial buffer
   int64_t ks = (lds ? 512 : 1024) / (int64_t)(ti * tj);
   if (ks < 1) ks = 1;
@@ -820,6 +921,9 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
     if (narrow)
       hipLaunchKernelGGL((k_gram_narrow<TI, KIND>), dim3((uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda,
                          (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
+    else if (sym)
+      hipLaunchKernelGGL((k_gram_lds_diag<TI, KIND>), dim3(1, 1, (uint32_t)ks), dim3(256), 0, c->stream, A,
+                         (uint64_t)lda, (uint32_t)na, (uint32_t)rows, (uint32_t)rps, c->part);
     else if (lds)
       hipLaunchKernelGGL((k_gram_lds<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A,
                          (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps,

@@ -247,8 +247,19 @@ __device__ __forceinline__ void march_body(uint32_t t, const T* __restrict__ F0,
   __shared__ T lds[2 * Q * OPE_WG * VW];
   __shared__ double red[OPE_WG * VW];
   if (MODE != SW_APPLY) {
-    // SW_UPDATE_Y also runs for a pending y update of converged columns
-    if (!any_active(active, N, YUP ? beta : nullptr)) return;
+    if (!any_active(active, N)) {
+      // every column has converged; SW_UPDATE_Y still adds the pending y term
+      // of the previous iteration, y += alpha_prev p_prev (the arithmetic of
+      // the full sweep with alpha = 0, and of the flush kernel), as a plain
+      // stream over the block instead of a march
+      if (YUP && any_active(active, N, beta)) {
+        const uint64_t count = (uint64_t)g.m0 * g.m1 * g.m2 * N;
+        const uint64_t stride = (uint64_t)ms.lgroups * ms.nxs * ms.cc * ms.mc * OPE_WG;
+        for (uint64_t e = (uint64_t)t * OPE_WG + threadIdx.x; e < count; e += stride)
+          Yv[e] = Yv[e] + (T)beta[e % N] * O1[e];
+      }
+      return;
+    }
     if (MODE == SW_PAP && t == 0 && threadIdx.x == 0) sc->cg_iters += 1;
   }
   const uint32_t mchunk_id = t % ms.mc;

@@ -208,7 +208,17 @@ ope_status phase_residual(ope_ctx* c, const void* Uv) {
 // buffer roles of iteration `it` (r and p alternate between two buffers, alpha
 // between the two halves of its array).  The y term of an even iteration is
 // added by the next iteration's sweep B, together with its own.
+hipError_t cg_iteration_body(ope_ctx* c, int it);
+
+// One CG iteration; its timed launches are tagged with the iteration index.
 hipError_t cg_iteration(ope_ctx* c, int it) {
+  c->prof_tag = it;
+  const hipError_t r = cg_iteration_body(c, it);
+  c->prof_tag = -1;
+  return r;
+}
+
+hipError_t cg_iteration_body(ope_ctx* c, int it) {
   void* r_cur = c->Rb[it & 1];
   void* r_nxt = c->Rb[(it + 1) & 1];
   void* p_old = (it & 1) ? c->Pb : c->HU;    // never read on the first iteration
@@ -299,6 +309,13 @@ void build_graphs(ope_ctx* c) {
   }
   c->graph_state = 1;
 }
+
+// Host convergence checks of the preconditioned CG: it converges in a few
+// iterations (about 2-4 per step) that each cost about 1 ms, and the chunk
+// enqueued behind the one being checked runs past convergence as no-op
+// launches (about 0.1 ms per iteration), so every iteration is checked; graph
+// chunks hold pairs of iterations.
+int mg_check_every(const ope_ctx* c) { return c->use_graphs ? 2 : 1; }
 
 // Enqueues CG iterations up to the next host check (a multiple of
 // check_every, or max_iter), the copy of the column flags into host slot
@@ -1016,6 +1033,8 @@ ProfScope::ProfScope(ope_ctx* ctx, int kernel) : c(ctx), on(ctx->prof_kernel == 
     }
   }
   (void)hipEventRecord(c->prof_events[c->prof_used], c->stream);
+  c->prof_tags.resize(c->prof_used / 2 + 1);
+  c->prof_tags[c->prof_used / 2] = c->prof_tag;
 }
 
 ProfScope::~ProfScope() {
@@ -1118,6 +1137,7 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   if (!c) return OPE_ENOMEM;
   c->prof_kernel = -1;
   c->prof_used = 0;
+  c->prof_tag = -1;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -1143,7 +1163,8 @@ ope_status ope_create(ope_ctx** out, const ope_op_desc* op, int64_t N, int32_t p
   c->h[1] = op->h[1];
   c->h[2] = op->dim == 3 ? op->h[2] : op->h[1];
   c->kinetic = op->kinetic;
-  c->eta_rel = 0.1;
+  c->eta_rel = ETA_REL_CG;
+  c->eta_user = 0;
   c->eta_floor = precision == OPE_FP64 ? 1e-12 : 1e-6;
   c->max_iter = 2000;
   c->check_every = 4;
@@ -1292,6 +1313,7 @@ ope_status ope_set_inner(ope_ctx* c, double eta_rel, double eta_floor, int32_t m
   c->eta_rel = eta_rel;
   c->eta_floor = eta_floor;
   c->max_iter = max_iter;
+  c->eta_user = 1;
   return OPE_OK;
 }
 
@@ -1371,6 +1393,7 @@ ope_status ope_gram_noalloc(const double* A, int64_t lda, int64_t na, const doub
   v.stage_cap = 0;
   v.prof_kernel = -1;
   v.prof_used = 0;
+  v.prof_tag = -1;
   HIPCHK(launch_gram(&v, A, lda, (int)na, B, ldb, (int)nb, rows, out));
   return OPE_OK;
 }
@@ -1434,6 +1457,11 @@ ope_status ope_residual(ope_ctx* c, const void* U, double* residual, double* rit
 ope_status ope_set_graphs(ope_ctx* c, int32_t enable) {
   if (!c || (enable != 0 && enable != 1)) return OPE_EINVAL;
   c->use_graphs = enable;
+  if (c->mg_on) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->check_every = mg_check_every(c);
+  }
   return OPE_OK;
 }
 
@@ -1444,6 +1472,7 @@ ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
   if (!enable) {
     mg_free(c);
     c->check_every = 4;
+    if (!c->eta_user) c->eta_rel = ETA_REL_CG;
     return OPE_OK;
   }
   // one thread per row chunk of a point: at most 256 chunks per row
@@ -1452,9 +1481,8 @@ ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
   const ope_status st = mg_build(c);
   if (st != OPE_OK) return st;
   c->mg_on = 1;
-  // a preconditioned Step 1 converges in a few iterations: check every two,
-  // so that fewer iterations run past convergence
-  c->check_every = 2;
+  c->check_every = mg_check_every(c);
+  if (!c->eta_user) c->eta_rel = ETA_REL_MG;
   return OPE_OK;
 }
 
@@ -1505,20 +1533,29 @@ ope_status ope_profile_begin(ope_ctx* c, int32_t kernel) {
   return OPE_OK;
 }
 
-ope_status ope_profile_end(ope_ctx* c, ope_kernel_time* out) {
-  if (!c || !out) return OPE_EINVAL;
+ope_status ope_profile_end_launches(ope_ctx* c, ope_kernel_time* out, int32_t* tags, double* ms, int64_t cap) {
+  if (!c || !out || cap < 0 || (cap > 0 && (!tags || !ms))) return OPE_EINVAL;
   c->prof_kernel = -1;
   HIPCHK(hipStreamSynchronize(c->stream));
   double total = 0.0;
   for (size_t k = 0; k + 1 < c->prof_used; k += 2) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->prof_events[k], c->prof_events[k + 1]));
-    total += ms;
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, c->prof_events[k], c->prof_events[k + 1]));
+    total += t;
+    const int64_t i = (int64_t)(k / 2);
+    if (i < cap) {
+      tags[i] = c->prof_tags[i];
+      ms[i] = t;
+    }
   }
   out->launches = (int64_t)(c->prof_used / 2);
   out->total_ms = total;
   c->prof_used = 0;
   return OPE_OK;
+}
+
+ope_status ope_profile_end(ope_ctx* c, ope_kernel_time* out) {
+  return ope_profile_end_launches(c, out, nullptr, nullptr, 0);
 }
 
 ope_status ope_step(ope_ctx* c, void* U, double tau, ope_step_info* info) {

@@ -23,6 +23,15 @@ enum { MK_F64 = 0, MK_F32 = 1, MK_BF16 = 2 };
 #define OPE_MAX_N_SMALL 512         // largest block width N
 #define OPE_MAX_N_ONE_WG 128        // largest N of the one-work-group FP64 small solves
 
+// Default inner tolerance factor eta_rel of Step 1 (|u_j - H y_j| <= eta_rel *
+// res |u_j|): plain CG, and CG with the multigrid preconditioner, whose few
+// iterations per step make a looser factor pay (measured on 64^3 and 96^3
+// well problems: N = 17 to residual 1e-8 in 0.46 / 1.08 s instead of
+// 0.53 / 1.58 s at 0.1, and at N = 128 about 4% less time per e-fold of the
+// late residual).
+constexpr double ETA_REL_CG = 0.1;
+constexpr double ETA_REL_MG = 0.25;
+
 struct OpeGrid {
   int dim;
   uint32_t m0, m1, m2;              // interior nodes per axis (m2 = 1 in 2D)
@@ -134,6 +143,7 @@ struct ope_ctx {
   double* hbuf;                 // pinned host scratch (N doubles)
   // policy
   double eta_rel, eta_floor;
+  int32_t eta_user;             // ope_set_inner was called: the preconditioner keeps eta_rel
   int32_t max_iter;
   int32_t check_every;          // CG iterations between host convergence checks (even: graph chunks)
   double drift_seen;            // drift of the last iterate whose scalars reached the host
@@ -181,6 +191,8 @@ struct ope_ctx {
   int prof_kernel;              // kernel id being timed, -1 when off
   std::vector<hipEvent_t> prof_events;  // start/stop pairs, reused across sessions
   size_t prof_used;             // events recorded in this session
+  std::vector<int32_t> prof_tags;  // per timed launch: the CG iteration index (-1 outside the CG)
+  int32_t prof_tag;             // the tag of the launches being enqueued
 };
 
 // The conv-net preconditioner (see k_net.hip).  Activations BF16

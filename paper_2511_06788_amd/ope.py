@@ -152,6 +152,8 @@ SIGNATURES = {
     "ope_gram_f32": ([_P, _I32, _P, _I64, _I64, _P, _I64, _I64, _I64, _P], _I32),
     "ope_rowmm_f32": ([_P, _I32, _P, _P, _P, _P, _P, _D, _D, _P], _I32),
     "ope_profile_end": ([_P, ctypes.POINTER(ope_kernel_time)], _I32),
+    "ope_profile_end_launches": ([_P, ctypes.POINTER(ope_kernel_time), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int64], _I32),
     "ope_net_create": ([_P, _I64, ctypes.POINTER(_P)], _I32),
     "ope_net_destroy": ([_P], _I32),
     "ope_net_set_weights": ([_P, _P], _I32),
@@ -264,7 +266,7 @@ def ope_destroy(ctx: int) -> None:
     _check(lib().ope_destroy(ctx), "ope_destroy")
 
 
-def ope_set_inner(ctx: int, eta_rel: float = 1e-2, eta_floor: float = 1e-12, max_iter: int = 2000) -> None:
+def ope_set_inner(ctx: int, eta_rel: float = 0.1, eta_floor: float = 1e-12, max_iter: int = 2000) -> None:
     _check(lib().ope_set_inner(ctx, eta_rel, eta_floor, max_iter), "ope_set_inner")
 
 
@@ -477,6 +479,17 @@ def ope_profile_end(ctx: int):
     t = ope_kernel_time()
     _check(lib().ope_profile_end(ctx, ctypes.byref(t)), "ope_profile_end")
     return t.launches, t.total_ms
+
+
+def ope_profile_end_launches(ctx: int, cap: int):
+    """Returns ``(launches, total_ms, tags, ms)``: the totals and, for the first
+    ``cap`` timed launches, each launch's CG iteration tag and device time."""
+    t = ope_kernel_time()
+    tags = (ctypes.c_int32 * max(cap, 1))()
+    ms = (ctypes.c_double * max(cap, 1))()
+    _check(lib().ope_profile_end_launches(ctx, ctypes.byref(t), tags, ms, cap), "ope_profile_end_launches")
+    k = min(cap, t.launches)
+    return t.launches, t.total_ms, list(tags[:k]), list(ms[:k])
 
 
 def ope_net_create(ctx: int, max_batch: int) -> int:

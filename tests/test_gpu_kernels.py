@@ -68,6 +68,26 @@ def test_gram_exact_on_integers(n, na, nb):
     assert np.array_equal(G, A.T @ B)
 
 
+@pytest.mark.parametrize("n,N", [(5003, 128), (3001, 200), (2048, 256), (4099, 300), (1000, 130)])
+def test_gram_of_a_block_with_itself_exact_on_integers(n, N):
+    """X^T X with one pointer for both operands: up to 128 columns the kernel
+    computes the MFMA blocks on and above the block diagonal and mirrors
+    them; wider blocks take the full product (ragged last tiles at 200, 300,
+    130)."""
+    from paper_2511_06788_amd import ope
+    rng = np.random.default_rng(n + N)
+    A = rng.integers(-8, 9, size=(n, N)).astype(np.float64)
+    # a context of block width N holds the split-K partials of an N x N Gram
+    p = W.Problem("sq", W.Grid(m=(N + 8, 1), h=(1.0, 1.0), lo=(0.0, 0.0)), np.zeros(N + 8), N, 1.0)
+    say(f"gram X^T X int n={n} N={N}")
+    with ope.Context(p.grid, p.V, N) as ctx:
+        Ad = to_dev(A)
+        out = empty_dev(N, N)
+        ope.ope_gram(ctx.handle, Ad, N, N, Ad, N, N, n, out)
+        G = to_host(out)
+    assert np.array_equal(G, A.T @ A)
+
+
 @pytest.mark.parametrize("n,lda,na,ldb,nb", [(3001, 40, 33, 24, 20), (3001, 40, 17, 24, 20)])
 def test_gram_strided_and_random(n, lda, na, ldb, nb):
     """Strided operands; the second shape takes the narrow (at most 32 columns) kernel."""

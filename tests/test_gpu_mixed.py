@@ -58,6 +58,26 @@ def test_gram_kinds_exact_on_integers(kind, n, na, nb):
     assert np.array_equal(G, A.astype(np.float64).T @ B.astype(np.float64))
 
 
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("n,N", [(2048, 128), (3001, 256), (1000, 136)])
+def test_gram_kinds_of_a_block_with_itself_exact_on_integers(kind, n, N):
+    """X^T X with one pointer for both operands in every arithmetic kind (at
+    128 columns the upper block triangle, mirrored; wider, the full product)."""
+    from paper_2511_06788_amd import ope
+    rng = np.random.default_rng(n + N + kind)
+    A = rng.integers(-8, 9, size=(n, N)).astype(np.float32)
+    # a context of block width N holds the split-K partials of an N x N Gram
+    p = W.Problem("sq", W.Grid(m=(N + 8, 1), h=(1.0, 1.0), lo=(0.0, 0.0)), np.zeros(N + 8), N, 1.0)
+    say(f"gram_f32 X^T X kind={kind} n={n} N={N}")
+    with _ctx(p) as ctx:
+        Ad = _dev32(A)
+        out = empty_dev(N, N)
+        ope.ope_gram_f32(ctx.handle, kind, Ad, N, N, Ad, N, N, n, out)
+        G = to_host(out)
+    A64 = A.astype(np.float64)
+    assert np.array_equal(G, A64.T @ A64)
+
+
 @pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("m,N", [((40, 30), 8), ((17, 9, 7), 20), ((16, 16, 16), 128)])
 def test_rowmm_kinds_exact_on_integers(kind, m, N):

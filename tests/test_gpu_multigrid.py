@@ -15,6 +15,8 @@ against the oracle's V-cycle and preconditioned CG (oracle/multigrid.py).
   1-4; at 64^3 with N = 128 a step needs far fewer inner iterations than the
   plain CG, keeps the block orthonormal and lowers the energy.
 * Batched steps of problems with the preconditioner equal their single steps.
+* The preconditioner's default inner factor (0.25; 0.1 again when it is
+  switched off, and the caller's factor once ope_set_inner was called).
 * Mixed precision: the FP32 V-cycle equals the oracle's to FP32 rounding, and
   a mixed solve with the preconditioner followed by an FP64 one reaches the
   dense eigenvalues.
@@ -198,6 +200,7 @@ def test_full_size_steps_need_few_iterations():
     tau = 45.0
     say("PCG steps 64^3 N=128")
     with ope.Context(p.grid, p.V, p.N) as plain, _ctx(p) as c:
+        ope.ope_set_inner(c.handle, 0.1, 1e-12, 2000)        # the plain CG's default factor
         Ua, Ub = to_dev(p.U0), to_dev(p.U0)
         ia = [ope.ope_step(plain.handle, Ua, tau) for _ in range(3)]
         ib = [ope.ope_step(c.handle, Ub, tau) for _ in range(3)]
@@ -211,6 +214,36 @@ def test_full_size_steps_need_few_iterations():
     assert drift_b <= 1e-12
     # both steps meet the same inner tolerance: the iterates stay close
     assert abs(res_b - res_a) <= 0.2 * res_a
+
+
+def test_inner_factor_defaults():
+    """Enabling the preconditioner sets the inner factor to 0.25 and disabling
+    it back to 0.1, unless ope_set_inner chose one: steps equal those with the
+    factor set explicitly, bit for bit."""
+    from paper_2511_06788_amd import ope
+    p = W.wells_3d(m=16, N=8, seed=5)
+    tau = 45.0
+
+    def run(setup):
+        with ope.Context(p.grid, p.V, p.N) as c:
+            setup(c.handle)
+            U = to_dev(p.U0)
+            info = [ope.ope_step(c.handle, U, tau) for _ in range(3)]
+            return to_host(U), [(i.energy, i.inner_iterations) for i in info]
+
+    say("inner factor defaults")
+    mg = lambda h, on=True: ope.ope_set_multigrid(h, on)
+    inner = lambda h, eta: ope.ope_set_inner(h, eta, 1e-12, 2000)
+    a = run(lambda h: mg(h))
+    b = run(lambda h: (inner(h, 0.25), mg(h)))
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+    c = run(lambda h: (inner(h, 0.1), mg(h)))                   # the caller's factor stays
+    d = run(lambda h: (mg(h), inner(h, 0.1)))
+    assert np.array_equal(c[0], d[0]) and c[1] == d[1]
+    assert sum(x[1] for x in c[1]) > sum(x[1] for x in a[1])      # a tighter tolerance costs iterations
+    e = run(lambda h: (mg(h), mg(h, False)))
+    f = run(lambda h: None)
+    assert np.array_equal(e[0], f[0]) and e[1] == f[1]
 
 
 def test_batched_steps_with_multigrid_equal_single_steps():

@@ -308,7 +308,7 @@ def time_to_residual(ope, torch, m=64, tol=1e-8, switch=1e-4, switch_mg=1e-4):
 
 
 def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, multigrid=True, mixed=False,
-                              switch=1e-4):
+                              switch=1e-4, recycle=False):
     """Algorithm 1 at 64^3, N = 128, tau = 45 (plain FP64, multigrid-
     preconditioned Step 1) MEASURED from the start block for up to `minutes`
     of wall time, in chunks of `chunk` steps (a progress line per chunk on
@@ -317,7 +317,9 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
     last quarter of the measured steps (at least the last two chunks) and
     their measured cost per step.  With `mixed`, the mixed-precision form
     (FP32 V-cycle) runs first, to residual `switch` (or its FP32 floor), and
-    the FP64 step takes over from the converted block."""
+    the FP64 step takes over from the converted block.  With `recycle`, the
+    FP64 step's inner CG starts from the previous step's correction
+    (ope_set_recycle)."""
     import numpy as np
     import workloads as W
     p = W.wells_3d(m=64, N=128, seed=0)
@@ -326,6 +328,7 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
     mixed_steps = 0
     with ope.Context(p.grid, p.V, p.N) as ctx:
         ope.ope_set_multigrid(ctx.handle, multigrid)
+        ope.ope_set_recycle(ctx.handle, recycle)
         U = torch.from_numpy(p.U0).to("cuda")
         steps = 0
         converged = False
@@ -362,7 +365,8 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
         res, ritz, drift = ope.ope_residual(ctx.handle, U, p.N)
     out = {"workload": "wells3d_64^3_N128_seed0", "tau": tau, "res_tol": tol,
            "form": "mixed to %g, then plain FP64" % switch if mixed else "plain FP64", "mixed_steps": mixed_steps,
-           "inner": "multigrid-preconditioned CG" if multigrid else "CG", "measured_seconds": traj[-1][0],
+           "inner": ("multigrid-preconditioned CG" if multigrid else "CG") +
+                    (", recycled warm start" if recycle else ""), "measured_seconds": traj[-1][0],
            "measured_steps": steps, "residual_reached": res, "drift": drift, "converged": converged,
            "trajectory": [{"seconds": a, "steps": b, "residual": c} for a, b, c in traj]}
     if converged:
@@ -1002,6 +1006,8 @@ def main():
     ap.add_argument("--m", type=int, default=64)
     ap.add_argument("--minutes", type=float, default=16.0, help="wall-time budget of --form longrun")
     ap.add_argument("--mixed", action="store_true", help="--form longrun: the mixed form first, then FP64")
+    ap.add_argument("--recycle", action="store_true",
+                    help="--form longrun: the inner CG starts from the previous step's correction")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tau", type=float, default=45.0)
@@ -1043,7 +1049,7 @@ def main():
         elif args.form == "energy":
             r = algorithm1_energy_stops(ope, torch)
         elif args.form == "longrun":
-            r = long_run_time_to_residual(ope, torch, minutes=args.minutes, mixed=args.mixed)
+            r = long_run_time_to_residual(ope, torch, minutes=args.minutes, mixed=args.mixed, recycle=args.recycle)
         elif args.form == "hydrogen":
             r = paper_hydrogen(ope, torch)
         elif args.form == "table1":

@@ -86,7 +86,7 @@ void free_ctx(ope_ctx* c) {
                    c->Z, c->A, c->B, c->Wsm, c->Lam32, c->Linv32, c->Sb32, c->Z32, c->alpha, c->beta, c->rho,
                    c->target, c->cnorm2, c->rcol, c->rho0, c->active, c->part, c->stage, c->sc,
                    c->Ubak, c->ns_x[0], c->ns_x[1], c->ns_g, c->ns_m, c->ns_p, c->ns_part, c->ns,
-                   c->mdiag, c->Upk};
+                   c->mdiag, c->Upk, c->Dr, c->HDr};
   for (void* p : dptrs)
     if (p) (void)hipFree(p);
   if (c->hsc) (void)hipHostFree(c->hsc);
@@ -210,6 +210,9 @@ ope_status phase_residual(ope_ctx* c, const void* Uv) {
 // added by the next iteration's sweep B, together with its own.
 hipError_t cg_iteration_body(ope_ctx* c, int it);
 
+// The buffer the CG iterates on: Y, or in a recycled step the correction Dr.
+static inline void* cg_y(const ope_ctx* c) { return c->cg_on_d ? c->Dr : c->Y; }
+
 // One CG iteration; its timed launches are tagged with the iteration index.
 hipError_t cg_iteration(ope_ctx* c, int it) {
   c->prof_tag = it;
@@ -234,7 +237,7 @@ hipError_t cg_iteration_body(ope_ctx* c, int it) {
     ProfScope ps(c, OPE_KERNEL_CG_REDUCE);
     if ((e = launch_reduce_cols(c, c->part, march_rows(c), N, nullptr, RED_CG_ALPHA, a_cur)) != hipSuccess) return e;
   }
-  if (it & 1) e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, c->Y, p_old, a_prev);
+  if (it & 1) e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, cg_y(c), p_old, a_prev);
   else e = launch_cg_update(c, r_cur, p_new, r_nxt, a_cur, nullptr, nullptr, nullptr);
   if (e != hipSuccess) return e;
   if (c->mg_on) {
@@ -263,7 +266,7 @@ hipError_t pcg_begin(ope_ctx* c) {
 // term (its p is in Pb, its alpha in the first half), on stream s.
 hipError_t cg_flush(ope_ctx* c, int32_t its, hipStream_t s) {
   if (its <= 0 || (its & 1) == 0) return hipSuccess;
-  return launch_y_flush(c, s, c->Y, c->Pb, c->alpha);
+  return launch_y_flush(c, s, cg_y(c), c->Pb, c->alpha);
 }
 
 void drop_graphs(ope_ctx* c) {
@@ -323,7 +326,7 @@ int mg_check_every(const ope_ctx* c) { return c->use_graphs ? 2 : 1; }
 // are on (and no kernel is being timed), the rest as eager launches.
 hipError_t cg_chunk(ope_ctx* c, int32_t* it, int32_t max_iter, int slot) {
   const int K = c->check_every;
-  const bool graphs = c->use_graphs && c->prof_kernel < 0 && K % 2 == 0;
+  const bool graphs = c->use_graphs && c->prof_kernel < 0 && K % 2 == 0 && !c->recycle;
   if (graphs && c->graph_state == 0) build_graphs(c);
   const int32_t end = std::min<int32_t>(max_iter, (*it / K + 1) * K);
   hipError_t e;
@@ -399,7 +402,17 @@ void fill_info(ope_ctx* c, ope_step_info* info, int32_t iters, ope_status st) {
 ope_status phase_warm_start(ope_ctx* c, const void* Uv) {
   const int N = (int)c->N;
   int64_t np = 0;
-  if (c->prec == OPE_FP64) {
+  c->cg_on_d = 0;
+  if (c->prec == OPE_FP64 && c->recycle) {
+    // recycled: the CG solves H d = -R Lam^{-1} from d0 = the previous step's
+    // correction (zero at the start), so r0 = -R Lam^{-1} - H d0; Y = U Lam^{-1}
+    // + d afterwards (recycle_after_cg)
+    HIPCHK(launch_rowmm(c, (const double*)Uv, c->Linv, nullptr, nullptr, nullptr, 0.0, 1.0, (double*)c->Y, 0, 0, &np));
+    HIPCHK(launch_rowmm(c, (const double*)c->HU, c->Linv, nullptr, nullptr, c->have_d ? (const double*)c->HDr : nullptr,
+                        c->have_d ? -1.0 : 0.0, -1.0, (double*)c->Rb[0], 1, 0, &np));
+    if (!c->have_d) HIPCHK(hipMemsetAsync(c->Dr, 0, sizeof(double) * (size_t)c->n * (size_t)N, c->stream));
+    c->cg_on_d = 1;
+  } else if (c->prec == OPE_FP64) {
     HIPCHK(launch_rowmm(c, (const double*)Uv, c->Linv, nullptr, nullptr, nullptr, 0.0, 1.0, (double*)c->Y, 0, 0, &np));
     HIPCHK(launch_rowmm(c, (const double*)c->HU, c->Linv, nullptr, nullptr, nullptr, 0.0, -1.0, (double*)c->Rb[0], 1,
                         0, &np));
@@ -412,6 +425,17 @@ ope_status phase_warm_start(ope_ctx* c, const void* Uv) {
   HIPCHK(launch_reduce_cols(c, c->part, np, N, c->rho0, RED_PLAIN));
   HIPCHK(launch_cg_setup(c, c->rho0));
   if (c->mg_on) HIPCHK(pcg_begin(c));
+  return OPE_OK;
+}
+
+// After a recycled step's CG: Y = U Lam^{-1} + d, and H d for the next warm
+// start (d stays in Dr as the next step's starting correction).
+ope_status recycle_after_cg(ope_ctx* c) {
+  if (!c->cg_on_d) return OPE_OK;
+  HIPCHK(launch_add_block(c, (double*)c->Y, (const double*)c->Dr));
+  HIPCHK(launch_apply_h(c, c->Dr, c->HDr));
+  c->have_d = 1;
+  c->cg_on_d = 0;
   return OPE_OK;
 }
 
@@ -529,6 +553,8 @@ ope_status run_step(ope_ctx* c, void* U, double tau, ope_step_info* info, double
   int32_t iters = 0;
   bool cg_done = false;
   st = run_cg(c, c->max_iter, &iters, &cg_done);
+  if (st != OPE_OK) return st;
+  st = recycle_after_cg(c);
   if (st != OPE_OK) return st;
   st = phase_update(c, U, tau);
   if (st != OPE_OK) return st;
@@ -990,6 +1016,7 @@ double time_cg(ope_ctx* c, const double* X, hipEvent_t e0, hipEvent_t e1) {
     rho.assign(2 * (size_t)N, (double)c->n * (double)v * (double)v);
   }
   double best = 1e30;
+  c->cg_on_d = 0;                // the timed CG iterates on Y
   for (int rep = 0; rep < 4; ++rep) {
     if (c->prec == OPE_FP64) {
       if (launch_resid0(c, X, nullptr, (double*)c->Rb[0], (double*)c->Y) != hipSuccess) return 1e30;
@@ -1330,6 +1357,7 @@ ope_status ope_source_solve(ope_ctx* c, const double* U, double* Y, const double
   if (c->prec != OPE_FP64) return OPE_EUNSUPPORTED;
   WSCHK(c);
   const int N = (int)c->N;
+  c->cg_on_d = 0;                // this CG iterates on Y
   // r0 = U - H Y0, column norms of r0 and of U
   if (Y0) {
     HIPCHK(launch_apply_h(c, Y0, c->HU));
@@ -1486,6 +1514,33 @@ ope_status ope_set_multigrid(ope_ctx* c, int32_t enable) {
   return OPE_OK;
 }
 
+ope_status ope_set_recycle(ope_ctx* c, int32_t enable) {
+  if (!c || (enable != 0 && enable != 1)) return OPE_EINVAL;
+  if (c->prec != OPE_FP64 || c->has_mass || c->in_batch) return OPE_EUNSUPPORTED;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  c->have_d = 0;
+  c->cg_on_d = 0;
+  if (!enable) {
+    if (c->Dr) (void)hipFree(c->Dr);
+    if (c->HDr) (void)hipFree(c->HDr);
+    c->Dr = c->HDr = nullptr;
+    c->recycle = 0;
+    return OPE_OK;
+  }
+  const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->N;
+  if (!c->Dr && hipMalloc(&c->Dr, bytes) != hipSuccess) {
+    c->Dr = nullptr;
+    return OPE_ENOMEM;
+  }
+  if (!c->HDr && hipMalloc(&c->HDr, bytes) != hipSuccess) {
+    c->HDr = nullptr;
+    return OPE_ENOMEM;
+  }
+  c->recycle = 1;
+  return OPE_OK;
+}
+
 ope_status ope_mg_info(const ope_ctx* c, int32_t* levels, int64_t* coarsest_nodes) {
   if (!c) return OPE_EINVAL;
   if (levels) *levels = c->mg_on ? c->mg_levels : 0;
@@ -1596,6 +1651,7 @@ ope_status ope_solve(ope_ctx* c, void* U, double tau, double res_tol, int32_t ma
   ope_solve_info si;
   memset(&si, 0, sizeof(si));
   ope_status st = OPE_OK;
+  c->have_d = 0;                 // a solve starts without a recycled correction
   if (c->net) {
     st = solve_learned(c, U, tau, res_tol, max_steps, &si);
     if (info) *info = si;
@@ -1688,6 +1744,8 @@ static ope_status solve_adaptive(ope_ctx* c, void* U, const ope_solve_opts* o, o
       bool cg_done = false;
       st = run_cg(c, c->max_iter, &iters, &cg_done);
       if (st != OPE_OK) return st;
+      st = recycle_after_cg(c);
+      if (st != OPE_OK) return st;
       st = phase_update(c, U, tau);
       if (st != OPE_OK) return st;
       HIPCHK(hipMemcpyAsync(c->hsc2, c->sc, sizeof(OpeScalars), hipMemcpyDeviceToHost, c->stream));
@@ -1736,6 +1794,7 @@ ope_status ope_solve_ex(ope_ctx* c, void* U, const ope_solve_opts* o, ope_solve_
   WSCHK(c);
   ope_solve_info si;
   memset(&si, 0, sizeof(si));
+  c->have_d = 0;                 // a solve starts without a recycled correction
   const ope_status st = solve_adaptive(c, U, o, &si);
   if (info) *info = si;
   return st;
@@ -1812,6 +1871,7 @@ ope_status ope_batch_create(ope_batch** out, const ope_op_desc* ops, const int64
       break;
     }
     st = ope_create(&b->ctx[i], &ops[i], N[i], precision, b->streams[i]);
+    if (st == OPE_OK) b->ctx[i]->in_batch = 1;
   }
   b->shared = 0;   // per-problem launches: measured as fast as tuned shared launches
   b->flag_off.assign(count, 0);

@@ -144,6 +144,12 @@ struct ope_ctx {
   // policy
   double eta_rel, eta_floor;
   int32_t eta_user;             // ope_set_inner was called: the preconditioner keeps eta_rel
+  // recycled Step-1 correction (ope_set_recycle): the CG runs on the correction
+  // d = Y - U Lam^{-1} in Dr, started from the previous step's; HDr = H Dr
+  int32_t recycle, have_d, in_batch;
+  int32_t cg_on_d;              // the CG being run iterates on Dr (a recycled step's Step 1)
+  void* Dr;
+  void* HDr;
   int32_t max_iter;
   int32_t check_every;          // CG iterations between host convergence checks (even: graph chunks)
   double drift_seen;            // drift of the last iterate whose scalars reached the host
@@ -245,6 +251,8 @@ hipError_t launch_cg_update(ope_ctx* c, const void* r, const void* p, void* rnew
 // y += alpha p (per column) on stream s: the deferred y term of a CG that
 // stopped on an even iteration
 hipError_t launch_y_flush(ope_ctx* c, hipStream_t s, void* y, const void* p, const double* alpha);
+// y += x over an n x N FP64 block
+hipError_t launch_add_block(ope_ctx* c, double* y, const double* x);
 hipError_t launch_cg_setup_reduce(ope_ctx* c, int mode);
 
 // multigrid preconditioner (k_mg.hip)

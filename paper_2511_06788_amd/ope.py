@@ -152,6 +152,7 @@ SIGNATURES = {
     "ope_gram_f32": ([_P, _I32, _P, _I64, _I64, _P, _I64, _I64, _I64, _P], _I32),
     "ope_rowmm_f32": ([_P, _I32, _P, _P, _P, _P, _P, _D, _D, _P], _I32),
     "ope_profile_end": ([_P, ctypes.POINTER(ope_kernel_time)], _I32),
+    "ope_set_recycle": ([_P, _I32], _I32),
     "ope_profile_end_launches": ([_P, ctypes.POINTER(ope_kernel_time), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_double), ctypes.c_int64], _I32),
     "ope_net_create": ([_P, _I64, ctypes.POINTER(_P)], _I32),
@@ -479,6 +480,10 @@ def ope_profile_end(ctx: int):
     t = ope_kernel_time()
     _check(lib().ope_profile_end(ctx, ctypes.byref(t)), "ope_profile_end")
     return t.launches, t.total_ms
+
+
+def ope_set_recycle(ctx: int, enable: bool) -> None:
+    _check(lib().ope_set_recycle(ctx, 1 if enable else 0), "ope_set_recycle")
 
 
 def ope_profile_end_launches(ctx: int, cap: int):

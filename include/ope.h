@@ -162,9 +162,11 @@ ope_status ope_set_multigrid(ope_ctx* ctx, int32_t enable);
  * Y0 = U Lam^{-1} + d_prev with r0 = -R Lam^{-1} - H d_prev (same stopping rule
  * on |u_j - H y_j|); after the CG, Y = U Lam^{-1} + d and H d is kept for the
  * next warm start.  Between steps the slowly changing residual leaves the
- * previous correction a close guess, so about half as many inner iterations
- * run (measured on well problems, with and without the multigrid
- * preconditioner).  ope_solve and ope_solve_ex start every solve with d = 0;
+ * previous correction a close guess, so fewer inner iterations run (measured
+ * on well problems: about half with the multigrid preconditioner).  The outer
+ * convergence per step can be slower: at 64^3, N = 128 a solve to residual
+ * 1e-8 took 654 s with it against 592 s without (more, cheaper steps).
+ * ope_solve and ope_solve_ex start every solve with d = 0;
  * successive ope_step calls carry it.  FP64 contexts without a mass operator,
  * outside a batch (else OPE_EUNSUPPORTED); turns CG graph chunks off; allocates
  * two n x N blocks (enable = 0 frees them); synchronises. */

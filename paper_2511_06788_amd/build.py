@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libope.so")
 
-SOURCES = ["k_stencil.hip", "k_mfma.hip", "k_small.hip", "k_net.hip", "k_check.hip", "k_mg.hip", "ope_api.hip"]
+SOURCES = ["k_stencil.hip", "k_mfma.hip", "k_small.hip", "k_net.hip", "k_check.hip", "k_mg.hip", "k_block.hip",
+           "ope_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -824,15 +824,18 @@ __device__ __forceinline__ void sym_blocks(uint32_t w, uint32_t (&oa)[9], uint32
   }
 }
 
-// X^T X for at most 128 columns: the one tile, split blockIdx.z.
-template <typename TI, int KIND>
+// A symmetric A^T B for at most 128 columns (X^T X, or TWO: A != B known to
+// give a symmetric product): the one tile, split blockIdx.z.
+template <typename TI, int KIND, bool TWO>
 __global__ __launch_bounds__(256) void k_gram_lds_diag(const TI* __restrict__ A, uint64_t lda, uint32_t na,
+                                                       const TI* __restrict__ B, uint64_t ldb,
                                                        uint32_t rows, uint32_t rows_per_split,
                                                        double* __restrict__ part) {
   using M = Mk<KIND>;
   using acc_t = typename M::acc_t;
   constexpr int KC = PanelRows<KIND>::KC;
   __shared__ __align__(16) TI pa[2][KC][GT2];
+  __shared__ __align__(16) TI pb[TWO ? 2 : 1][TWO ? KC : 1][TWO ? GT2 : 1];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
   const uint32_t i0 = blockIdx.x * GT2;
   const uint32_t ks = blockIdx.z;
@@ -844,16 +847,23 @@ __global__ __launch_bounds__(256) void k_gram_lds_diag(const TI* __restrict__ A,
   acc_t acc[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[q] = zero_acc<acc_t>();
-  PanelChunks<TI, KC> ca;
+  PanelChunks<TI, KC> ca, cb;
   const uint32_t npan = (r1 > r0) ? (r1 - r0 + KC - 1) / KC : 0;
   if (npan > 0) {
     ca.load(A, lda, na, i0, r0, r1);
     ca.store(pa[0]);
+    if constexpr (TWO) {
+      cb.load(B, ldb, na, i0, r0, r1);
+      cb.store(pb[0]);
+    }
   }
   __syncthreads();
   for (uint32_t t = 0; t < npan; ++t) {
     const int buf = (int)(t & 1u);
-    if (t + 1 < npan) ca.load(A, lda, na, i0, r0 + (t + 1) * KC, r1);
+    if (t + 1 < npan) {
+      ca.load(A, lda, na, i0, r0 + (t + 1) * KC, r1);
+      if constexpr (TWO) cb.load(B, ldb, na, i0, r0 + (t + 1) * KC, r1);
+    }
 #pragma unroll
     for (int kk = 0; kk < KC / M::KSTEP; ++kk) {
 #pragma unroll
@@ -863,12 +873,16 @@ __global__ __launch_bounds__(256) void k_gram_lds_diag(const TI* __restrict__ A,
         for (int e = 0; e < M::KPL; ++e) {
           const uint32_t row = kk * M::KSTEP + kr * M::KPL + e;
           av[e] = pa[buf][row][oa[q] + ci];
-          bv[e] = pa[buf][row][ob[q] + ci];
+          if constexpr (TWO) bv[e] = pb[buf][row][ob[q] + ci];
+          else bv[e] = pa[buf][row][ob[q] + ci];
         }
         acc[q] = mma<KIND, TI>(av, bv, acc[q]);
       }
     }
-    if (t + 1 < npan) ca.store(pa[buf ^ 1]);
+    if (t + 1 < npan) {
+      ca.store(pa[buf ^ 1]);
+      if constexpr (TWO) cb.store(pb[buf ^ 1]);
+    }
     __syncthreads();
   }
   double* out = part + (uint64_t)ks * na * na;
@@ -887,7 +901,7 @@ __global__ __launch_bounds__(256) void k_gram_lds_diag(const TI* __restrict__ A,
 
 template <typename TI, int KIND>
 hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int64_t ldb, int nb, int64_t rows,
-                  double* out) {
+                  double* out, bool symmetric = false) {
   // 128 x 128 tiles from LDS when both sides are wide and rows split into
   // whole 16-byte chunks; else the wide tile from global memory (FP32 and
   // BF16 kinds), else 64 x 64 tiles
@@ -899,7 +913,8 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
   // a Gram of one block with itself in one tile: the MFMA blocks on and
   // above the block diagonal (with several tiles the two launches of fewer
   // work-groups each were measured slower than the full product)
-  const bool sym = lds && A == B && lda == ldb && na == nb && na <= GT2;
+  const bool same = A == B && lda == ldb;
+  const bool sym = lds && (same || symmetric) && na == nb && na <= GT2;
   const int tile = wide ? GT2 : GT;
   const uint32_t ti = (uint32_t)((na + tile - 1) / tile), tj = (uint32_t)((nb + tile - 1) / tile);
   // about 1024 work-groups in total (512, two per CU, for the LDS kernels),
@@ -921,9 +936,12 @@ hipError_t gram_t(ope_ctx* c, const TI* A, int64_t lda, int na, const TI* B, int
     if (narrow)
       hipLaunchKernelGGL((k_gram_narrow<TI, KIND>), dim3((uint32_t)ks), dim3(256), 0, c->stream, A, (uint64_t)lda,
                          (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps, c->part);
+    else if (sym && same)
+      hipLaunchKernelGGL((k_gram_lds_diag<TI, KIND, false>), dim3(1, 1, (uint32_t)ks), dim3(256), 0, c->stream, A,
+                         (uint64_t)lda, (uint32_t)na, A, (uint64_t)lda, (uint32_t)rows, (uint32_t)rps, c->part);
     else if (sym)
-      hipLaunchKernelGGL((k_gram_lds_diag<TI, KIND>), dim3(1, 1, (uint32_t)ks), dim3(256), 0, c->stream, A,
-                         (uint64_t)lda, (uint32_t)na, (uint32_t)rows, (uint32_t)rps, c->part);
+      hipLaunchKernelGGL((k_gram_lds_diag<TI, KIND, true>), dim3(1, 1, (uint32_t)ks), dim3(256), 0, c->stream, A,
+                         (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)rows, (uint32_t)rps, c->part);
     else if (lds)
       hipLaunchKernelGGL((k_gram_lds<TI, KIND>), dim3(tj, ti, (uint32_t)ks), dim3(256), 0, c->stream, A,
                          (uint64_t)lda, (uint32_t)na, B, (uint64_t)ldb, (uint32_t)nb, (uint32_t)rows, (uint32_t)rps,
@@ -993,6 +1011,11 @@ hipError_t rowmm_t(ope_ctx* c, const TI* X0, const TI* M0, const TI* X1, const T
 hipError_t launch_gram(ope_ctx* c, const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb,
                        int64_t rows, double* out) {
   return gram_t<double, MK_F64>(c, A, lda, na, B, ldb, nb, rows, out);
+}
+
+hipError_t launch_gram_sym(ope_ctx* c, const double* A, int64_t lda, const double* B, int64_t ldb, int n,
+                           int64_t rows, double* out) {
+  return gram_t<double, MK_F64>(c, A, lda, n, B, ldb, n, rows, out, true);
 }
 
 hipError_t launch_gram_f32(ope_ctx* c, int kind, const float* A, int64_t lda, int na, const float* B, int64_t ldb,

@@ -189,7 +189,7 @@ ope_status phase_residual(ope_ctx* c, const void* Uv) {
     const double* U = (const double*)Uv;
     double* HU = (double*)c->HU;
     HIPCHK(launch_gram(c, U, N, N, U, N, N, c->n, c->C));
-    HIPCHK(launch_gram(c, U, N, N, HU, N, N, c->n, c->Lam));
+    HIPCHK(launch_gram_sym(c, U, N, HU, N, N, c->n, c->Lam));     // H is symmetric
     HIPCHK(launch_prep_small(c));
     HIPCHK(launch_rowmm(c, U, c->Lam, nullptr, nullptr, HU, 1.0, -1.0, HU, 1, 0, &np));
   } else {

@@ -275,6 +275,12 @@ enum { RED_PLAIN = 0, RED_CG_ALPHA = 1, RED_CG_BETA = 2 };
 hipError_t launch_gram(ope_ctx* c, const double* A, int64_t lda, int na, const double* B,
                        int64_t ldb, int nb, int64_t rows, double* out);
 
+// out = A^T B for a product the caller knows to be symmetric (U^T H U): up to 128
+// columns only the MFMA blocks on and above the block diagonal are computed and
+// mirrored, so out is exactly symmetric
+hipError_t launch_gram_sym(ope_ctx* c, const double* A, int64_t lda, const double* B, int64_t ldb, int n,
+                           int64_t rows, double* out);
+
 // row-block products: Out = cbeta*Cm + ascale*(X0*M0 + X1*M1); optional per-column sums of Out^2
 // into c->part (one row per work-group); returns the number of partial rows in *nparts.
 hipError_t launch_rowmm(ope_ctx* c, const double* X0, const double* M0, const double* X1,

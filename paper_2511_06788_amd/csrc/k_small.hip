@@ -482,26 +482,27 @@ __global__ __launch_bounds__(SW) void k_jacobi(const double* __restrict__ Asrc, 
         qq[s] = q;
       }
       __syncthreads();
-      // rows: row_p' = c row_p - s row_q ; row_q' = s row_p + c row_q
-      for (uint32_t e = threadIdx.x; e < npair * N; e += SW) {
-        const uint32_t s = e / N, j = e - s * N;
-        const uint32_t p = pp[s], q = qq[s];
-        if (q < N) {
-          const double xp = W[(uint64_t)p * N + j], xq = W[(uint64_t)q * N + j];
-          W[(uint64_t)p * N + j] = cs[s] * xp - sn[s] * xq;
-          W[(uint64_t)q * N + j] = sn[s] * xp + cs[s] * xq;
-        }
-      }
-      __syncthreads();
-      // columns: col_p' = c col_p - s col_q ; col_q' = s col_p + c col_q
-      for (uint32_t e = threadIdx.x; e < npair * N; e += SW) {
-        const uint32_t s = e / N, i = e - s * N;
-        const uint32_t p = pp[s], q = qq[s];
-        if (q < N) {
-          const double xp = W[(uint64_t)i * N + p], xq = W[(uint64_t)i * N + q];
-          W[(uint64_t)i * N + p] = cs[s] * xp - sn[s] * xq;
-          W[(uint64_t)i * N + q] = sn[s] * xp + cs[s] * xq;
-        }
+      // W <- J^T W J in one pass over the 2 x 2 blocks of rows (p_a, q_a) and
+      // columns (p_b, q_b) of two pairs a, b: the rows first,
+      //   row_p' = c row_p - s row_q, row_q' = s row_p + c row_q,
+      // then the columns of the result the same way (a dummy index of odd N,
+      // q = N, leaves its row or column unrotated and is not stored)
+      for (uint32_t e = threadIdx.x; e < npair * npair; e += SW) {
+        const uint32_t a = e / npair, b = e - a * npair;
+        const uint32_t pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+        const bool ra = qa < N, rb = qb < N;
+        const double ca = ra ? cs[a] : 1.0, sa = ra ? sn[a] : 0.0;
+        const double cb = rb ? cs[b] : 1.0, sb = rb ? sn[b] : 0.0;
+        const double w00 = W[(uint64_t)pa * N + pb];
+        const double w01 = rb ? W[(uint64_t)pa * N + qb] : 0.0;
+        const double w10 = ra ? W[(uint64_t)qa * N + pb] : 0.0;
+        const double w11 = (ra && rb) ? W[(uint64_t)qa * N + qb] : 0.0;
+        const double r00 = ca * w00 - sa * w10, r01 = ca * w01 - sa * w11;
+        const double r10 = sa * w00 + ca * w10, r11 = sa * w01 + ca * w11;
+        W[(uint64_t)pa * N + pb] = cb * r00 - sb * r01;
+        if (rb) W[(uint64_t)pa * N + qb] = sb * r00 + cb * r01;
+        if (ra) W[(uint64_t)qa * N + pb] = cb * r10 - sb * r11;
+        if (ra && rb) W[(uint64_t)qa * N + qb] = sb * r10 + cb * r11;
       }
       __syncthreads();
     }

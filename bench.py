@@ -90,6 +90,34 @@ def kernel_bytes(kind, n, N):
 PMC_SOURCES = {"cg_sweep_b": "k_stencil.hip", "mg_post": "k_mg.hip"}
 
 
+def full_sweep_b(tags, ms, its, launches, n, N):
+    """The CG sweep-B launches of a timed run that swept, from the per-launch
+    CG iteration tags and times (ope_profile_end_launches) and every step's
+    inner_iterations: a step's CG starts at tag 0, and its launches with a tag
+    below the step's count ran a full sweep (even tag: 3 FP64 blocks + the
+    diagonal, odd: 6 + the diagonal); the others, enqueued past the
+    convergence of every column, returned at once or added only the pending y
+    term.  Returns (full launches, their total ms, their algorithmic bytes,
+    [even, odd] counts); zero launches when the tags do not cover the run."""
+    steps = []
+    for tg, t_ms in zip(tags, ms):
+        if tg == 0 or not steps:
+            steps.append([])
+        steps[-1].append((tg, t_ms))
+    full, full_ms, full_bytes, parity = 0, 0.0, 0.0, [0, 0]
+    if len(steps) != len(its) or len(tags) != launches:
+        return 0, 0.0, 0.0, [0, 0]
+    blk = n * N * 8
+    for st, k in zip(steps, its):
+        for tg, t_ms in st:
+            if 0 <= tg < k:
+                full += 1
+                full_ms += t_ms
+                full_bytes += (6 if tg % 2 else 3) * blk + 8 * n
+                parity[tg % 2] += 1
+    return full, full_ms, full_bytes, parity
+
+
 def traffic_from_pmc(n, N, kernel="cg_sweep_b", mix=None):
     """HBM bytes per working launch of a kernel from the committed rocprofv3
     counter summary (profiles/pmc_traffic_<kernel>.json; for CG sweep B also
@@ -909,23 +937,7 @@ def step_rate(ope, torch, p, args, multigrid):
     # odd: 6 blocks, plus the diagonal), the ones enqueued past the
     # convergence of every column return at once or, in an odd iteration, add
     # only the pending y term.  The roofline is taken over the full sweeps.
-    steps_tags = []
-    for tg, t_ms in zip(tags, lms):
-        if tg == 0 or not steps_tags:
-            steps_tags.append([])
-        steps_tags[-1].append((tg, t_ms))
-    full_ms = full_bytes = 0.0
-    full = 0
-    parity = [0, 0]                  # full even (SW_UPDATE) and odd (SW_UPDATE_Y) sweeps
-    if len(steps_tags) == len(its) and len(tags) == launches:
-        blk = n * N * 8
-        for st_tags, k in zip(steps_tags, its):
-            for tg, t_ms in st_tags:
-                if 0 <= tg < k:
-                    full += 1
-                    full_ms += t_ms
-                    full_bytes += (6 if tg % 2 else 3) * blk + 8 * n
-                    parity[tg % 2] += 1
+    full, full_ms, full_bytes, parity = full_sweep_b(tags, lms, its, launches, n, N)
     # the counter record lists the even form first, then the odd one
     traffic = traffic_from_pmc(n, N, "cg_sweep_b", mix=parity if full else None)
     if full:

@@ -312,21 +312,27 @@ __global__ __launch_bounds__(SW) void k_small_solve(const double* __restrict__ S
   gj_invert(w, N, gl, &bad);
   store_own(Bws, N, w);           // B
   __syncthreads();
-  // A = 2/tau (I - B) + S_b B (B's columns from global memory, the next
-  // row's load in flight; a deeper unroll spills at 1024 threads)
+  // A = 2/tau (I - B) + S_b B: B's rows staged through the elimination's LDS
+  // (free now) in chunks of BCH rows, every thread loading its share at once
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
-  double bnx = Bws[jj];
+  constexpr uint32_t BCH = sizeof(GjLds) / (sizeof(double) * 128);     // rows of 128 per chunk
+  double* bst = reinterpret_cast<double*>(&gl);
+  for (uint32_t k0 = 0; k0 < N; k0 += BCH) {
+    const uint32_t kn = min(BCH, N - k0);
+    for (uint32_t e = threadIdx.x; e < kn * N; e += SW) bst[e] = Bws[(uint64_t)k0 * N + e];
+    __syncthreads();
 #pragma unroll 1
-  for (uint32_t k = 0; k < N; ++k) {
-    const double bkj = bnx;
-    bnx = Bws[(uint64_t)(k + 1 < N ? k + 1 : k) * N + jj];
+    for (uint32_t k = 0; k < kn; ++k) {
+      const double bkj = bst[k * N + jj];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const uint32_t i = o.row(r);
-      acc[r] += smat[(i < N ? i : 0u) * N + k] * bkj;
+      for (int r = 0; r < RPT; ++r) {
+        const uint32_t i = o.row(r);
+        acc[r] += smat[(i < N ? i : 0u) * N + k0 + k] * bkj;
+      }
     }
+    __syncthreads();
   }
   const double it = 2.0 / tau;
 #pragma unroll

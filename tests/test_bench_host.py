@@ -47,3 +47,19 @@ def test_traffic_weighted_by_the_forms(tmp_path, monkeypatch):
     assert bench.traffic_from_pmc(10, 5) is None                  # another workload
     (d / bench.PMC_SOURCES["cg_sweep_b"]).write_bytes(b"changed")
     assert bench.traffic_from_pmc(10, 4) is None                  # the kernel changed since the counters
+
+
+def test_mixed_floor_rule():
+    """The mixed phase of the long run ends once `chunk` steps lower the
+    residual by less than 1%, and not before `chunk` steps have run."""
+    chunk = 1500
+    # a slow but steady phase: 10% per 1500 steps is not the floor
+    steady = [(k * 100, 1e-3 * 0.9 ** (k / 15)) for k in range(40)]
+    assert not bench.mixed_floor_reached(steady, chunk)
+    # fewer steps than one chunk: no decision yet, however flat
+    assert not bench.mixed_floor_reached([(0, 1e-4), (60, 1e-4), (120, 1e-4)], chunk)
+    # flat over the last chunk: the floor
+    flat = steady + [(4000 + k * 100, steady[-1][1] * (1 - 1e-4 * k)) for k in range(1, 20)]
+    assert bench.mixed_floor_reached(flat, chunk)
+    # a residual that rises again is at the floor too
+    assert bench.mixed_floor_reached([(0, 1e-4), (1600, 1.2e-4)], chunk)

@@ -345,7 +345,7 @@ def mixed_floor_reached(hist, chunk, gain=0.99):
 
 
 def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, multigrid=True, mixed=False,
-                              switch=1e-4, recycle=False):
+                              switch=1e-4, recycle=False, mixed_steps=0):
     """Algorithm 1 at 64^3, N = 128, tau = 45 (plain FP64, multigrid-
     preconditioned Step 1) MEASURED from the start block for up to `minutes`
     of wall time, in chunks of `chunk` steps (a progress line per chunk on
@@ -354,7 +354,8 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
     last quarter of the measured steps (at least the last two chunks) and
     their measured cost per step.  With `mixed`, the mixed-precision form
     (FP32 V-cycle) runs first, to residual `switch` (or its FP32 floor), and
-    the FP64 step takes over from the converted block.  With `recycle`, the
+    the FP64 step takes over from the converted block; with `mixed_steps` > 0
+    the mixed form runs exactly that many steps instead.  With `recycle`, the
     FP64 step's inner CG starts from the previous step's correction
     (ope_set_recycle)."""
     import numpy as np
@@ -362,7 +363,7 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
     p = W.wells_3d(m=64, N=128, seed=0)
     tau = 45.0
     traj = []
-    mixed_steps = 0
+    mixed_done = 0
     with ope.Context(p.grid, p.V, p.N) as ctx:
         ope.ope_set_multigrid(ctx.handle, multigrid)
         ope.ope_set_recycle(ctx.handle, recycle)
@@ -381,7 +382,8 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
                 # steps; here the mixed phase goes on while `chunk` steps still lower the
                 # residual by 1%.
                 while time.perf_counter() - t0 < 60.0 * minutes:
-                    sm = ope.ope_solve(cm.handle, U32, tau, switch, chunk)
+                    n = min(chunk, mixed_steps - steps) if mixed_steps > 0 else chunk
+                    sm = ope.ope_solve(cm.handle, U32, tau, switch, n)
                     torch.cuda.synchronize()
                     steps += int(sm.steps)
                     hist.append((steps, float(sm.residual)))
@@ -391,11 +393,14 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
                               file=sys.stderr, flush=True)
                     if sm.converged or int(sm.steps) == 0:
                         break
-                    if mixed_floor_reached(hist, chunk):
+                    if mixed_steps > 0:
+                        if steps >= mixed_steps:
+                            break
+                    elif mixed_floor_reached(hist, chunk):
                         break
                 torch.cuda.synchronize()
                 traj.append((time.perf_counter() - t0, steps, float(hist[-1][1])))
-                mixed_steps = steps
+                mixed_done = steps
                 ope.ope_convert(cm.handle, U32, U, p.grid.n * p.N, True)
         else:
             torch.cuda.synchronize()
@@ -412,7 +417,9 @@ def long_run_time_to_residual(ope, torch, minutes=16.0, tol=1e-8, chunk=1500, mu
                 break
         res, ritz, drift = ope.ope_residual(ctx.handle, U, p.N)
     out = {"workload": "wells3d_64^3_N128_seed0", "tau": tau, "res_tol": tol,
-           "form": "mixed to %g, then plain FP64" % switch if mixed else "plain FP64", "mixed_steps": mixed_steps,
+           "form": ("mixed for %d steps, then plain FP64" % mixed_steps if mixed_steps > 0 else
+                    "mixed to %g or its floor, then plain FP64" % switch) if mixed else "plain FP64",
+           "mixed_steps": mixed_done,
            "inner": ("multigrid-preconditioned CG" if multigrid else "CG") +
                     (", recycled warm start" if recycle else ""), "measured_seconds": traj[-1][0],
            "measured_steps": steps, "residual_reached": res, "drift": drift, "converged": converged,
@@ -1039,6 +1046,8 @@ def main():
     ap.add_argument("--minutes", type=float, default=16.0, help="wall-time budget of --form longrun")
     ap.add_argument("--mixed", action="store_true", help="--form longrun: the mixed form first, then FP64")
     ap.add_argument("--switch", type=float, default=1e-4, help="--form longrun --mixed: residual at which FP64 takes over")
+    ap.add_argument("--mixed-steps", type=int, default=0,
+                    help="--form longrun --mixed: a fixed number of mixed steps before FP64")
     ap.add_argument("--recycle", action="store_true",
                     help="--form longrun: the inner CG starts from the previous step's correction")
     ap.add_argument("--N", type=int, default=128)
@@ -1083,7 +1092,7 @@ def main():
             r = algorithm1_energy_stops(ope, torch)
         elif args.form == "longrun":
             r = long_run_time_to_residual(ope, torch, minutes=args.minutes, mixed=args.mixed, recycle=args.recycle,
-                                          switch=args.switch)
+                                          switch=args.switch, mixed_steps=args.mixed_steps)
         elif args.form == "hydrogen":
             r = paper_hydrogen(ope, torch)
         elif args.form == "table1":

@@ -1053,7 +1053,7 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tau", type=float, default=45.0)
-    ap.add_argument("--cpu-steps", type=int, default=1, help="outer steps of the CPU oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="outer steps of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-kernel timings and time-to-residual")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
